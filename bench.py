@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the mini-batch landmark kernel k-means hot path on one MI355X.
+
+One step = the whole path on one synthetic dataset, inputs already in HBM:
+  kkm_fit   -- per mini-batch: landmark block + landmark loop (one cooperative
+               kernel), the batch-wide distance pass with FP64 re-decisions,
+               member counts, batch medoids (Eq. 10) and the merge (Eq. 11-13);
+  kkm_assign -- every sample of the dataset against the fitted medoids (Eq. 2).
+
+Default workload: N = 100 000 samples, d = 16, a 20-component isotropic Gaussian
+mixture (means uniform in [-10, 10]^16, std 1, float32), RBF sigma = 4,
+C = 20, B = 10 mini-batches, s = 0.1 (1000 landmarks per batch), T = 20.
+
+Metric: algorithmic kernel evaluations per second (Eq. 18's n|L| per batch plus
+the n x C medoid blocks, plus N x C for the assign pass).  Printed as one JSON
+line with a roofline entry for the dominant kernel (timed with HIP events on the
+library's stream inside the timed steps) and the FP64 oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+WORKLOADS = {
+    # name: (config index, description)
+    "mixture16": (1, "gaussian-mixture N=100000 d=16 K=20 rbf(sigma=4) C=20 B=10 s=0.1 T=20"),
+    "mixture64": (3, "gaussian-mixture N=1000000 d=64 K=100 aniso rbf(sigma=8) C=100 B=50 s=0.02 T=20"),
+    "rings": (0, "two-rings N=2000 d=2 float64 rbf(sigma=1) C=2 B=1 s=1 T=30 random-init"),
+    "md": (2, "md-frames N=200000 A=50 templates=10 rmsd(sigma=1.5) C=50 B=20 s=0.05 T=20"),
+}
+
+PEAK_FP32_VECTOR = 157.3e12   # published MI355X vector FP32 FLOP/s
+PEAK_FP64_VECTOR = 78.6e12    # published MI355X vector FP64 FLOP/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def dist_flops_per_eval(kind: str, d: int) -> float:
+    """Algorithmic FP work of one kernel evaluation in the batch-wide pass:
+    dot product 2d, squared distance 3, scaling + exponential 2, coefficient FMA 2."""
+    if kind == "linear":
+        return 2 * d + 2
+    if kind == "rbf":
+        return 2 * d + 7
+    # RMSD: 9 correlation sums over A atoms (18 A), key-matrix polynomial and Newton (~150)
+    A = d // 3
+    return 18 * A + 150
+
+
+def landmark_flops_per_launch(kind: str, d: int, ell: int, updates: int, C: int) -> float:
+    """FP64 work of one landmark-phase launch: l^2 kernel evaluations (3d + 20 each),
+    l^2 adds per centroid evaluation, l C distance updates per label update."""
+    ev = 3 * d + 20 if kind != "rmsd" else 18 * (d // 3) + 300
+    return ell * ell * ev + (updates + 1) * (ell * ell + 3 * ell * C)
+
+
+def cpu_baseline(X, cfg, landmarks, uniforms, init_labels):
+    """The FP64 oracle, as it stands, on the same workload (one whole fit + one assign pass)."""
+    from oracle import kkm as okkm
+    from oracle.kernels import Kernel
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    kern = Kernel(cfg["kernel"], cfg.get("sigma", 1.0), cfg.get("n_atoms", 0))
+    t0 = time.perf_counter()
+    ref = okkm.fit(X, cfg["C"], kern, cfg["B"], cfg["T"], landmarks, init=cfg["init"],
+                   kmpp_uniforms=uniforms, init_labels=init_labels)
+    t1 = time.perf_counter()
+    okkm.assign(kern, X, okkm.medoid_model(ref))
+    t2 = time.perf_counter()
+    evals = ref.evals + X.shape[0] * cfg["C"]
+    return {"value": evals / (t2 - t0), "unit": "kernel evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one full fit ({t1 - t0:.1f} s) and one assign pass ({t2 - t1:.1f} s) of the same workload; "
+                      f"BLAS threads={threads}, numpy elementwise single-threaded"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mixture16", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-requests", type=int, default=200)
+    ap.add_argument("--latency-size", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import kkm_inputs as ki
+    import paper_1710_03013_amd as kk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    k_idx, desc = WORKLOADS[args.workload]
+    cfg = dict(ki.datasets.CONFIGS[k_idx])
+    prec = args.precision or ("fp64" if cfg["dtype"] == "f64" else "fp32")
+    seed = 2000 + k_idx
+    log(f"[bench] generating {desc}")
+    X, _ = ki.datasets.config_data(k_idx)
+    N, d = X.shape
+    C, B, s, T = cfg["C"], cfg["B"], cfg["s"], cfg["T"]
+    landmarks = ki.draw_all_landmarks(seed, N, B, s)
+    uniforms = ki.draw_kmpp_uniforms(seed, C) if cfg["init"] == "kmeans++" else None
+    n0 = len(ki.batch_index_sets(N, B)[0])
+    init_labels = ki.draw_init_labels(seed, n0, C) if cfg["init"] == "random" else None
+    dev = torch.device("cuda:0")
+    Xd = torch.from_numpy(X).to(dev)
+    fit_kw = dict(kernel=cfg["kernel"], sigma=cfg.get("sigma", 1.0), n_atoms=cfg.get("n_atoms", 0), C=C, B=B, s=s,
+                  max_iter=T, init=cfg["init"], precision=prec, seed=seed, landmarks=landmarks,
+                  kmpp_uniforms=uniforms, init_labels=init_labels)
+    model = kk.kkm_model_create(cfg["kernel"], d=d, C=C, dtype=cfg["dtype"], sigma=cfg.get("sigma", 1.0),
+                                n_atoms=cfg.get("n_atoms", 0))
+    wbytes = kk.kkm_fit(Xd, model=model, **fit_kw)[2]["workspace_bytes"]
+    ws = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+    labels = torch.empty(N, dtype=torch.int32, device=dev)
+    aws = torch.empty(max(256, kk.kkm_assign_workspace_bytes(model, N, prec)), dtype=torch.uint8, device=dev)
+
+    def step(time_phases=False):
+        _, _, info = kk.kkm_fit(Xd, model=model, workspace=ws, want_labels=True, time_phases=time_phases,
+                                **fit_kw)
+        kk.kkm_assign(model, Xd, precision=prec, workspace=aws, labels=labels)
+        return info
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        infos.append(step(time_phases=True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"[bench] {args.steps} timed steps in {t1 - t0:.3f} s")
+    elapsed = t1 - t0
+    info = infos[-1]
+    evals_step = info["evals_algorithmic"] + N * C
+    value = evals_step * args.steps / elapsed
+    batch_n = [len(ix) for ix in ki.batch_index_sets(N, B)]
+    assigned_step = int(np.dot(batch_n, info["updates_per_batch"])) + N
+    ms = {k_: float(np.mean([i["ms"][k_] for i in infos])) for k_ in infos[0]["ms"]}
+
+    # dominant kernel: the per-phase time summed over the step
+    ells = [len(l) for l in landmarks]
+    if ms["landmark"] >= ms["dist"]:
+        dom = "landmark_phase_kernel"
+        per_launch = np.mean([landmark_flops_per_launch(cfg["kernel"], d, ells[i], int(info["updates_per_batch"][i]), C)
+                              for i in range(B)])
+        dur = ms["landmark"] / B * 1e-3
+        peak, bound = PEAK_FP64_VECTOR, "alu"
+    else:
+        dom = "dist_kernel"
+        per_launch = np.mean([batch_n[i] * ells[i] for i in range(B)]) * dist_flops_per_eval(cfg["kernel"], d)
+        dur = ms["dist"] / B * 1e-3
+        peak, bound = (PEAK_FP32_VECTOR if prec != "fp64" else PEAK_FP64_VECTOR), "alu"
+    achieved = per_launch / dur
+    roofline = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": dom,
+                "avg_launch_us": dur * 1e6, "phase_ms_per_step": ms}
+
+    # assign latency at a fixed request size
+    lat = []
+    q = Xd[: min(args.latency_size, N)]
+    qlab = torch.empty(q.shape[0], dtype=torch.int32, device=dev)
+    qws = torch.empty(max(256, kk.kkm_assign_workspace_bytes(model, q.shape[0], prec)), dtype=torch.uint8, device=dev)
+    for r in range(args.latency_requests):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        kk.kkm_assign(model, q, precision=prec, workspace=qws, labels=qlab)
+        e1.record()
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.asarray(lat)
+
+    out = {
+        "metric": "kernel evals/s (fit + assign, algorithmic count)",
+        "value": value,
+        "unit": "kernel evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32"}[prec] + " (landmark loop, medoids, merge: f64)",
+        "data": "synthetic",
+        "config": {"workload": desc, "N": N, "d": d, "C": C, "B": B, "s": s, "T": T, "precision": prec},
+        "samples_assigned_per_s": assigned_step * args.steps / elapsed,
+        "assign_latency_ms": {"request_size": int(q.shape[0]), "p50": float(np.percentile(lat, 50)),
+                              "p99": float(np.percentile(lat, 99))},
+        "refined_rows_per_step": int(info["rows_refined"]),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host (one fit + one assign pass)")
+        out["cpu_baseline"] = cpu_baseline(X, cfg, landmarks, uniforms, init_labels)
+        log("[bench] oracle done")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

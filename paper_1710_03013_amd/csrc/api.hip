@@ -1,0 +1,662 @@
+// C ABI entry points kkm_fit / kkm_assign / kkm_cost: argument checks, workspace layout and the
+// per-batch launch sequence.  All arithmetic runs in the kernels of k_landmark / k_dist / k_select.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kkm_internal.hpp"
+#include "kkm_launch.hpp"
+
+namespace kkm {
+namespace {
+
+// Pairs of HIP events recorded on the caller's stream around phases of a fit (optional).
+struct PhaseTimer {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+    hipEvent_t open = nullptr;
+    kkm_status begin() {
+        if (!on) return KKM_OK;
+        KKM_HIP(hipEventCreate(&open));
+        return hipEventRecord(open, s) == hipSuccess ? KKM_OK : fail(KKM_ERR_DEVICE, "hipEventRecord");
+    }
+    kkm_status end(int phase) {
+        if (!on) return KKM_OK;
+        hipEvent_t e;
+        KKM_HIP(hipEventCreate(&e));
+        KKM_HIP(hipEventRecord(e, s));
+        ev[phase].push_back({open, e});
+        open = nullptr;
+        return KKM_OK;
+    }
+    // after the stream has been synchronised
+    void collect(double out[5]) {
+        for (int p = 0; p < 5; ++p) {
+            out[p] = 0.0;
+            for (auto& pr : ev[p]) {
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) out[p] += ms;
+            }
+        }
+    }
+    ~PhaseTimer() {
+        for (auto& v : ev)
+            for (auto& pr : v) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+        if (open) (void)hipEventDestroy(open);
+    }
+};
+enum { kPhInit = 0, kPhLandmark = 1, kPhDist = 2, kPhRefine = 3, kPhSelect = 4 };
+
+// ----------------------------------------------------------------------------- fit plan
+struct FitPlan {
+    int64_t N = 0, d = 0;
+    int dtype = KKM_F32;
+    kkm_kernel kernel{};
+    kkm_params p{};
+    int B = 0, C = 0, T = 0;
+    int dpad = 0;
+    std::vector<int64_t> n, base, stride, ell, lm_off;
+    int64_t nmax = 0, ellmax = 0, ell_total = 0;
+    int gmax = 1;
+    int nchunk = 1;
+    bool tile_f64 = false;
+    std::vector<int32_t> lm_host;      // concatenated batch positions
+    std::vector<double> uniforms;      // k-means++
+    std::vector<int32_t> lab0;         // landmark labels of batch 0 (random init)
+    std::vector<int32_t> med0;         // batch-0 medoid positions (explicit init)
+};
+
+struct FitWs {
+    void* Xc;
+    int32_t* lm;
+    int32_t* lab_init;
+    double* uniforms;
+    int32_t* chosen;
+    double* D2;
+    void* M;
+    double* Mself;
+    int64_t* Midx;
+    int64_t* wcount;
+    double* Kbuf;
+    int32_t* lab;
+    double* partial;
+    int32_t* changed;
+    int32_t* lab_final;
+    int32_t* offsets;
+    double* ghat;
+    double* segabs;
+    void* support;
+    float* snorm32;
+    double* snorm64;
+    float* coef32;
+    double* coef64;
+    int32_t* src_index;
+    float* snorm_max;
+    int32_t* counts_b;     // [C]   cleared by the landmark phase of each batch
+    float* Dt;
+    float* Erow;
+    int32_t* labels_b;
+    int32_t* refine_list;
+    int32_t* refine_counts; // [B]
+    int32_t* flags;        // [2] nonfinite, medoid candidates
+    int32_t* bmed;
+    double* mpart_v;
+    int32_t* mpart_i;
+    int32_t* updates;      // [B]
+    int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
+};
+
+size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
+    const size_t es = P.dtype == KKM_F64 ? 8 : 4;
+    const int C = P.C;
+    w.Xc = P.kernel.type == KKM_KERNEL_RMSD ? c.take<char>((size_t)P.N * P.d * es) : nullptr;
+    w.lm = c.take<int32_t>(std::max<int64_t>(1, P.ell_total));
+    w.lab_init = c.take<int32_t>(P.ellmax);
+    w.uniforms = c.take<double>(C);
+    w.chosen = c.take<int32_t>(C);
+    w.D2 = c.take<double>(P.nmax);
+    w.M = c.take<char>((size_t)C * P.dpad * es);
+    w.Mself = c.take<double>(C);
+    w.Midx = c.take<int64_t>(C);
+    w.wcount = c.take<int64_t>(C);
+    w.Kbuf = c.take<double>((size_t)P.ellmax * P.ellmax);
+    w.lab = c.take<int32_t>(2 * P.ellmax);
+    w.partial = c.take<double>((size_t)P.gmax * C);
+    w.changed = c.take<int32_t>(P.T + 1);
+    w.lab_final = c.take<int32_t>(P.ellmax);
+    w.offsets = c.take<int32_t>(C + 1);
+    w.ghat = c.take<double>(C);
+    w.segabs = c.take<double>(C);
+    w.support = c.take<char>((size_t)P.ellmax * P.dpad * es);
+    w.snorm32 = c.take<float>(P.ellmax);
+    w.snorm64 = c.take<double>(P.ellmax);
+    w.coef32 = c.take<float>(P.ellmax);
+    w.coef64 = c.take<double>(P.ellmax);
+    w.src_index = c.take<int32_t>(P.ellmax);
+    w.snorm_max = c.take<float>(1);
+    w.counts_b = c.take<int32_t>(C);
+    w.Dt = c.take<float>((size_t)C * P.nmax * (P.tile_f64 ? 2 : 1));
+    w.Erow = c.take<float>(P.nmax);
+    w.labels_b = c.take<int32_t>(P.nmax);
+    w.refine_list = c.take<int32_t>(P.nmax);
+    w.refine_counts = c.take<int32_t>(P.B);
+    w.flags = c.take<int32_t>(2);
+    w.bmed = c.take<int32_t>(C);
+    w.mpart_v = c.take<double>((size_t)C * P.nchunk);
+    w.mpart_i = c.take<int32_t>((size_t)C * P.nchunk);
+    w.updates = c.take<int32_t>(P.B);
+    w.info = c.take<int64_t>((size_t)3 * P.B * C);
+    return c.off;
+}
+
+kkm_status check_kernel_args(const kkm_kernel* k, int64_t d) {
+    if (!k) return fail(KKM_ERR_INVALID_ARG, "kernel is NULL");
+    if (k->type != KKM_KERNEL_LINEAR && k->type != KKM_KERNEL_RBF && k->type != KKM_KERNEL_RMSD)
+        return fail(KKM_ERR_INVALID_ARG, "unknown kernel type");
+    if (k->type != KKM_KERNEL_LINEAR && !(k->sigma > 0.0 && std::isfinite(k->sigma)))
+        return fail(KKM_ERR_INVALID_ARG, "sigma must be finite and > 0");
+    if (k->type == KKM_KERNEL_RMSD && (k->n_atoms < 1 || d != 3 * (int64_t)k->n_atoms))
+        return fail(KKM_ERR_INVALID_ARG, "RMSD kernel needs d == 3 * n_atoms");
+    if (k->type != KKM_KERNEL_RMSD && d > kMaxRegDim) return fail(KKM_ERR_UNSUPPORTED, "linear / RBF support d <= 128");
+    return KKM_OK;
+}
+
+double inv2s2_of(const kkm_kernel& k) { return k.type == KKM_KERNEL_LINEAR ? 0.0 : 1.0 / (2.0 * k.sigma * k.sigma); }
+
+// Validate everything and build the plan (host draws included); no device work.
+kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel, const kkm_params* params,
+                     const DeviceInfo* dev, FitPlan& P) {
+    if (N < 1) return fail(KKM_ERR_INVALID_ARG, "N must be >= 1");
+    if (d < 1) return fail(KKM_ERR_INVALID_ARG, "d must be >= 1");
+    if (dtype != KKM_F32 && dtype != KKM_F64) return fail(KKM_ERR_INVALID_ARG, "bad dtype");
+    KKM_TRY(check_kernel_args(kernel, d));
+    if (!params) return fail(KKM_ERR_INVALID_ARG, "params is NULL");
+    const kkm_params& p = *params;
+    if (p.B < 1 || p.B > N) return fail(KKM_ERR_INVALID_ARG, "B must be in [1, N]");
+    if (!(p.s > 0.0 && p.s <= 1.0)) return fail(KKM_ERR_INVALID_ARG, "s must be in (0, 1]");
+    if (p.max_iter < 1 || p.max_iter > 100000) return fail(KKM_ERR_INVALID_ARG, "max_iter must be in [1, 100000]");
+    if (p.sampling != KKM_SAMPLE_STRIDE && p.sampling != KKM_SAMPLE_BLOCK) return fail(KKM_ERR_INVALID_ARG, "bad sampling");
+    if (p.init != KKM_INIT_KMEANSPP && p.init != KKM_INIT_RANDOM_LABELS && p.init != KKM_INIT_MEDOIDS)
+        return fail(KKM_ERR_INVALID_ARG, "bad init");
+    if (p.precision != KKM_PREC_FP64 && p.precision != KKM_PREC_FP32 && p.precision != KKM_PREC_BF16X3)
+        return fail(KKM_ERR_INVALID_ARG, "bad precision");
+    P.N = N;
+    P.d = d;
+    P.dtype = dtype;
+    P.kernel = *kernel;
+    P.p = p;
+    P.B = p.B;
+    P.C = p.C;
+    P.T = p.max_iter;
+    P.dpad = kernel->type == KKM_KERNEL_RMSD ? (int)d : padded_dim(d);
+    P.n.resize(P.B);
+    P.base.resize(P.B);
+    P.stride.resize(P.B);
+    for (int i = 0; i < P.B; ++i) {
+        if (p.sampling == KKM_SAMPLE_STRIDE) {
+            P.base[i] = i;
+            P.stride[i] = P.B;
+            P.n[i] = (N - i + P.B - 1) / P.B;
+        } else {
+            const int64_t q = N / P.B, r = N % P.B;
+            P.n[i] = q + (i < r ? 1 : 0);
+            P.base[i] = i * q + std::min<int64_t>(i, r);
+            P.stride[i] = 1;
+        }
+    }
+    if (p.C < 1 || p.C > kMaxClusters) return fail(KKM_ERR_INVALID_ARG, "C must be in [1, 1024]");
+    if (p.C > P.n[0]) return fail(KKM_ERR_INVALID_ARG, "C exceeds the size of the first batch");
+    P.ell.resize(P.B);
+    P.lm_off.resize(P.B + 1);
+    P.lm_off[0] = 0;
+    for (int i = 0; i < P.B; ++i) {
+        P.ell[i] = kkm_landmark_count(P.n[i], p.s);
+        P.lm_off[i + 1] = P.lm_off[i] + P.ell[i];
+        P.nmax = std::max(P.nmax, P.n[i]);
+        P.ellmax = std::max(P.ellmax, P.ell[i]);
+    }
+    P.ell_total = P.lm_off[P.B];
+    if (P.ellmax > 65535) return fail(KKM_ERR_UNSUPPORTED, "at most 65535 landmarks per batch; use more mini-batches");
+    P.lm_host.resize(P.ell_total);
+    std::vector<int64_t> tmp(P.ellmax);
+    for (int i = 0; i < P.B; ++i) {
+        const int64_t* src;
+        if (p.landmarks) {
+            src = p.landmarks + P.lm_off[i];
+        } else {
+            KKM_TRY(kkm_draw_landmarks(p.seed, i, P.n[i], p.s, tmp.data()));
+            src = tmp.data();
+        }
+        for (int64_t k = 0; k < P.ell[i]; ++k) {
+            if (src[k] < 0 || src[k] >= P.n[i] || (k > 0 && src[k] <= src[k - 1]))
+                return fail(KKM_ERR_INVALID_ARG, "landmarks of batch " + std::to_string(i) +
+                                                     " must be strictly ascending positions inside the batch");
+            P.lm_host[P.lm_off[i] + k] = (int32_t)src[k];
+        }
+    }
+    if (p.init == KKM_INIT_KMEANSPP) {
+        P.uniforms.resize(P.C);
+        if (p.kmpp_uniforms) std::copy(p.kmpp_uniforms, p.kmpp_uniforms + P.C, P.uniforms.begin());
+        else KKM_TRY(kkm_draw_kmpp_uniforms(p.seed, P.C, P.uniforms.data()));
+        for (double u : P.uniforms)
+            if (!(u >= 0.0 && u < 1.0)) return fail(KKM_ERR_INVALID_ARG, "k-means++ uniforms must lie in [0, 1)");
+    } else if (p.init == KKM_INIT_RANDOM_LABELS) {
+        std::vector<int32_t> labs(P.n[0]);
+        if (p.init_labels) std::copy(p.init_labels, p.init_labels + P.n[0], labs.begin());
+        else KKM_TRY(kkm_draw_init_labels(p.seed, P.n[0], P.C, labs.data()));
+        P.lab0.resize(P.ell[0]);
+        for (int64_t k = 0; k < P.ell[0]; ++k) {
+            const int32_t v = labs[P.lm_host[k]];
+            if (v < 0 || v >= P.C) return fail(KKM_ERR_INVALID_ARG, "init labels must lie in [0, C)");
+            P.lab0[k] = v;
+        }
+    } else {
+        if (!p.init_medoids) return fail(KKM_ERR_INVALID_ARG, "MEDOIDS init needs init_medoids");
+        P.med0.resize(P.C);
+        for (int j = 0; j < P.C; ++j) {
+            if (p.init_medoids[j] < 0 || p.init_medoids[j] >= P.n[0])
+                return fail(KKM_ERR_INVALID_ARG, "init medoids must be positions of the first batch");
+            P.med0[j] = (int32_t)p.init_medoids[j];
+        }
+    }
+    P.tile_f64 = p.precision == KKM_PREC_FP64 || kernel->type == KKM_KERNEL_RMSD;
+    P.nchunk = (int)std::max<int64_t>(1, (P.nmax + 2047) / 2048);
+    if (dev) {
+        for (int i = 0; i < P.B; ++i) {
+            const int G = landmark_grid(*dev, (int)P.ell[i]);
+            P.gmax = std::max(P.gmax, G);
+            if (landmark_lds_bytes_host((int)P.ell[i], P.C, G) > dev->max_lds_per_block)
+                return fail(KKM_ERR_UNSUPPORTED, "landmark set of batch " + std::to_string(i) +
+                                                     " too large for one workgroup's LDS; use more mini-batches");
+        }
+        if ((P.tile_f64 ? 8u : 4u) * (size_t)P.C * 64 > dev->max_lds_per_block)
+            return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
+    } else {
+        P.gmax = 256;
+    }
+    return KKM_OK;
+}
+
+KSpec kspec_of(const kkm_kernel& k, int64_t d) { return KSpec{k.type, k.n_atoms, d, inv2s2_of(k)}; }
+
+kkm_status check_workspace(void* ws, size_t have, size_t need) {
+    if (!ws) return fail(KKM_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(KKM_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (have < need)
+        return fail(KKM_ERR_WORKSPACE, "workspace too small: " + std::to_string(have) + " < " + std::to_string(need));
+    return KKM_OK;
+}
+
+kkm_status check_device_of(const kkm_model* m) {
+    int cur = -1;
+    KKM_HIP(hipGetDevice(&cur));
+    if (cur != m->device) return fail(KKM_ERR_INVALID_ARG, "the model lives on another device than the current one");
+    return KKM_OK;
+}
+
+// ----------------------------------------------------------------------------- assign workspace
+struct AssignWs {
+    void* Qc;
+    int32_t* refine_list;
+    int32_t* refine_count;
+    int32_t* nonfinite;
+    double* best;
+    double* partials;
+    double* cost;
+    int32_t* labels_tmp;   // labels when the caller wants only the cost
+};
+
+size_t carve_assign(Carver& c, const kkm_model* m, int64_t n, AssignWs& w) {
+    const size_t es = m->dtype == KKM_F64 ? 8 : 4;
+    const int64_t nn = std::max<int64_t>(1, n);
+    w.Qc = m->kernel.type == KKM_KERNEL_RMSD ? c.take<char>((size_t)nn * m->d * es) : nullptr;
+    w.refine_list = c.take<int32_t>(nn);
+    w.refine_count = c.take<int32_t>(2);
+    w.nonfinite = w.refine_count + 1;
+    w.best = c.take<double>(nn);
+    w.partials = c.take<double>(1024);
+    w.cost = c.take<double>(1);
+    w.labels_tmp = c.take<int32_t>(nn);
+    return c.off;
+}
+
+SupportView model_support(const kkm_model* m) {
+    SupportView s;
+    s.rows = m->support;
+    s.dpad = m->dpad;
+    s.snorm32 = m->snorm32;
+    s.snorm64 = m->snorm64;
+    s.coef32 = m->coef32;
+    s.coef64 = m->coef64;
+    s.offsets = m->offsets;
+    s.self = m->self;
+    s.segabs = m->segabs;
+    s.snorm_max = m->snorm_max;
+    s.C = m->C;
+    return s;
+}
+
+kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
+                         size_t ws_bytes, hipStream_t s, int32_t* labels, float* gap, bool want_best, AssignWs& w) {
+    if (!m) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
+    if (n < 0) return fail(KKM_ERR_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && !X) return fail(KKM_ERR_INVALID_ARG, "X is NULL");
+    if (dtype != m->dtype) return fail(KKM_ERR_INVALID_ARG, "X dtype differs from the model dtype");
+    if (precision != KKM_PREC_FP64 && precision != KKM_PREC_FP32 && precision != KKM_PREC_BF16X3)
+        return fail(KKM_ERR_INVALID_ARG, "bad precision");
+    if (n >= (int64_t)1 << 31) return fail(KKM_ERR_UNSUPPORTED, "at most 2^31 - 1 rows per call");
+    KKM_TRY(check_device_of(m));
+    Carver probe(nullptr);
+    const size_t need = carve_assign(probe, m, n, w);
+    KKM_TRY(check_workspace(ws, ws_bytes, need));
+    Carver c(ws);
+    carve_assign(c, m, n, w);
+    DeviceInfo dev;
+    KKM_TRY(device_info(&dev));
+    KKM_TRY(launch_zero_i32(w.refine_count, 2, s));
+    if (n == 0) return KKM_OK;
+    const void* Q = X;
+    if (m->kernel.type == KKM_KERNEL_RMSD) {
+        KKM_TRY(launch_centre(X, w.Qc, n, m->kernel.n_atoms, dtype, s));
+        Q = w.Qc;
+    }
+    DistArgs da{};
+    da.q = BatchView{Q, m->d, 0, 1, n};
+    da.dtype = dtype;
+    da.precision = precision;
+    da.ks = kspec_of(m->kernel, m->d);
+    da.sup = model_support(m);
+    da.Dt = nullptr;
+    da.ldD = 0;
+    da.Erow = nullptr;
+    da.labels = labels;
+    da.gap = gap;
+    da.best = want_best ? w.best : nullptr;
+    da.refine_list = w.refine_list;
+    da.refine_count = w.refine_count;
+    da.nonfinite = w.nonfinite;
+    if (da.sup.C * 64 * (dist_is_fp64(da) ? 8u : 4u) > dev.max_lds_per_block)
+        return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
+    KKM_TRY(launch_dist(da, dev, s));
+    if (!dist_is_fp64(da)) KKM_TRY(launch_refine(da, dev, s));
+    return KKM_OK;
+}
+
+}  // namespace
+}  // namespace kkm
+
+using namespace kkm;
+
+extern "C" {
+
+size_t kkm_fit_workspace_bytes(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel, const kkm_params* params) {
+    FitPlan P;
+    DeviceInfo dev;
+    const bool have_dev = device_info(&dev) == KKM_OK;
+    if (make_plan(N, d, dtype, kernel, params, have_dev ? &dev : nullptr, P) != KKM_OK) return 0;
+    FitWs w;
+    Carver c(nullptr);
+    return carve_fit(c, P, w);
+}
+
+kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
+                   const kkm_params* params, void* workspace, size_t workspace_bytes, void* stream, kkm_model* model,
+                   int32_t* labels_out, kkm_fit_info* info) {
+    if (!X) return fail(KKM_ERR_INVALID_ARG, "X is NULL");
+    if (!model) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
+    DeviceInfo dev;
+    KKM_TRY(device_info(&dev));
+    if (!dev.coop) return fail(KKM_ERR_DEVICE, "device lacks cooperative launch");
+    FitPlan P;
+    KKM_TRY(make_plan(N, d, dtype, kernel, params, &dev, P));
+    if (model->d != d || model->C != P.C || model->dtype != dtype || model->cap < P.C ||
+        model->kernel.type != kernel->type || model->kernel.sigma != kernel->sigma ||
+        model->kernel.n_atoms != kernel->n_atoms || model->dpad != P.dpad)
+        return fail(KKM_ERR_INVALID_ARG, "model was created for another kernel, d, C, dtype or capacity");
+    KKM_TRY(check_device_of(model));
+    FitWs w;
+    Carver probe(nullptr);
+    const size_t need = carve_fit(probe, P, w);
+    KKM_TRY(check_workspace(workspace, workspace_bytes, need));
+    Carver c(workspace);
+    carve_fit(c, P, w);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const KSpec ks = kspec_of(*kernel, d);
+    const int C = P.C;
+    const size_t es = dtype == KKM_F64 ? 8 : 4;
+    PhaseTimer tm;
+    tm.on = info && info->time_phases;
+    tm.s = s;
+
+    KKM_TRY(launch_zero_i32(w.refine_counts, P.B, s));
+    KKM_TRY(launch_zero_i32(w.flags, 2, s));
+    KKM_HIP(hipMemcpyAsync(w.lm, P.lm_host.data(), sizeof(int32_t) * P.ell_total, hipMemcpyHostToDevice, s));
+    const void* Xs = X;
+    if (kernel->type == KKM_KERNEL_RMSD) {
+        KKM_TRY(launch_centre(X, w.Xc, N, kernel->n_atoms, dtype, s));
+        Xs = w.Xc;
+    }
+    auto view = [&](int i) { return BatchView{Xs, d, P.base[i], P.stride[i], P.n[i]}; };
+
+    // batch-0 initialisation of the global medoids
+    KKM_TRY(tm.begin());
+    if (P.p.init == KKM_INIT_KMEANSPP) {
+        KKM_HIP(hipMemcpyAsync(w.uniforms, P.uniforms.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
+        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, s));
+        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+    } else if (P.p.init == KKM_INIT_MEDOIDS) {
+        KKM_HIP(hipMemcpyAsync(w.chosen, P.med0.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+    } else {
+        KKM_HIP(hipMemcpyAsync(w.lab_init, P.lab0.data(), sizeof(int32_t) * P.ell[0], hipMemcpyHostToDevice, s));
+        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, nullptr, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+    }
+    KKM_TRY(tm.end(kPhInit));
+
+    for (int i = 0; i < P.B; ++i) {
+        const BatchView bv = view(i);
+        const int ell = (int)P.ell[i];
+        LandmarkArgs la{};
+        la.X = Xs;
+        la.d = d;
+        la.base = bv.base;
+        la.stride = bv.stride;
+        la.lm = w.lm + P.lm_off[i];
+        la.ell = ell;
+        la.C = C;
+        la.max_updates = P.T - 1;
+        la.grid = landmark_grid(dev, ell);
+        la.ktype = kernel->type;
+        la.n_atoms = kernel->n_atoms;
+        la.inv2s2 = ks.inv2s2;
+        la.init_mode = (i == 0 && P.p.init == KKM_INIT_RANDOM_LABELS) ? 0 : 1;
+        la.lab_init = w.lab_init;
+        la.M = w.M;
+        la.Mpad = P.dpad;
+        la.Mself = w.Mself;
+        la.Kbuf = w.Kbuf;
+        la.lab = w.lab;
+        la.partial = w.partial;
+        la.changed = w.changed;
+        la.zero_ints = w.counts_b;
+        la.n_zero_ints = C;
+        la.lab_final = w.lab_final;
+        la.offsets = w.offsets;
+        la.ghat = w.ghat;
+        la.segabs = w.segabs;
+        la.updates_out = w.updates + i;
+        la.support = w.support;
+        la.dpad = P.dpad;
+        la.snorm32 = w.snorm32;
+        la.snorm64 = w.snorm64;
+        la.coef32 = w.coef32;
+        la.coef64 = w.coef64;
+        la.src_index = w.src_index;
+        la.snorm_max = w.snorm_max;
+        KKM_TRY(tm.begin());
+        KKM_TRY(launch_landmark_phase(la, dtype, dev, s));
+        KKM_TRY(tm.end(kPhLandmark));
+
+        SupportView sv;
+        sv.rows = w.support;
+        sv.dpad = P.dpad;
+        sv.snorm32 = w.snorm32;
+        sv.snorm64 = w.snorm64;
+        sv.coef32 = w.coef32;
+        sv.coef64 = w.coef64;
+        sv.offsets = w.offsets;
+        sv.self = w.ghat;
+        sv.segabs = w.segabs;
+        sv.snorm_max = w.snorm_max;
+        sv.C = C;
+
+        DistArgs da{};
+        da.q = bv;
+        da.dtype = dtype;
+        da.precision = P.p.precision;
+        da.ks = ks;
+        da.sup = sv;
+        da.Dt = w.Dt;
+        da.ldD = P.nmax;
+        da.Erow = w.Erow;
+        da.labels = w.labels_b;
+        da.gap = nullptr;
+        da.best = nullptr;
+        da.refine_list = w.refine_list;
+        da.refine_count = w.refine_counts + i;
+        da.nonfinite = w.flags;
+        KKM_TRY(tm.begin());
+        KKM_TRY(launch_dist(da, dev, s));
+        KKM_TRY(tm.end(kPhDist));
+        if (!dist_is_fp64(da)) {
+            KKM_TRY(tm.begin());
+            KKM_TRY(launch_refine(da, dev, s));
+            KKM_TRY(tm.end(kPhRefine));
+        }
+
+        SelectArgs sa{};
+        sa.b = bv;
+        sa.dtype = dtype;
+        sa.ks = ks;
+        sa.C = C;
+        sa.M = w.M;
+        sa.Mpad = P.dpad;
+        sa.Mself = w.Mself;
+        sa.Midx = w.Midx;
+        sa.wcount = w.wcount;
+        sa.labels = w.labels_b;
+        sa.counts = w.counts_b;
+        sa.bmed = w.bmed;
+        sa.label_out = labels_out;
+        sa.Dt = w.Dt;
+        sa.ldD = P.nmax;
+        sa.Erow = w.Erow;
+        sa.sup = sv;
+        sa.mpart_v = w.mpart_v;
+        sa.mpart_i = w.mpart_i;
+        sa.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(P.nchunk, (bv.n + 2047) / 2048));
+        sa.cand_total = w.flags + 1;
+        sa.info_bmed = w.info + (size_t)i * C;
+        sa.info_bcnt = w.info + (size_t)(P.B + i) * C;
+        sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
+        KKM_TRY(tm.begin());
+        KKM_TRY(launch_members(sa, s));
+        KKM_TRY(launch_batch_medoids(sa, dist_is_fp64(da), s));
+        KKM_TRY(launch_merge(sa, s));
+        KKM_TRY(tm.end(kPhSelect));
+    }
+    KKM_TRY(launch_model_from_medoids(model, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+
+    std::vector<int32_t> updates(P.B), refined(P.B), flags(2);
+    std::vector<int64_t> infos((size_t)3 * P.B * C);
+    KKM_HIP(hipMemcpyAsync(updates.data(), w.updates, sizeof(int32_t) * P.B, hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipMemcpyAsync(refined.data(), w.refine_counts, sizeof(int32_t) * P.B, hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipMemcpyAsync(flags.data(), w.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipMemcpyAsync(infos.data(), w.info, sizeof(int64_t) * infos.size(), hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipStreamSynchronize(s));
+    model->used = C;
+    (void)es;
+
+    if (info) {
+        int64_t alg = 0, perf = 0, rows_ref = 0;
+        for (int i = 0; i < P.B; ++i) {
+            const int64_t n = P.n[i], ell = P.ell[i];
+            int64_t nonempty = 0;
+            for (int j = 0; j < C; ++j) nonempty += infos[(size_t)(P.B + i) * C + j] > 0;
+            alg += n * ell + n * nonempty;
+            const bool eq8 = i > 0 || P.p.init != KKM_INIT_RANDOM_LABELS;
+            if (i > 0 || P.p.init == KKM_INIT_KMEANSPP) alg += n * C;
+            perf += ell * ell + (eq8 ? ell * C : 0) + n * ell + (int64_t)refined[i] * ell + 2 * n * nonempty;
+            if (i == 0 && P.p.init == KKM_INIT_KMEANSPP) perf += n * (C - 1);
+            rows_ref += refined[i];
+            if (info->updates_per_batch) info->updates_per_batch[i] = updates[i] + 1;
+            for (int j = 0; j < C; ++j) {
+                if (info->batch_medoids) info->batch_medoids[(size_t)i * C + j] = infos[(size_t)i * C + j];
+                if (info->batch_counts) info->batch_counts[(size_t)i * C + j] = infos[(size_t)(P.B + i) * C + j];
+                if (info->global_medoids) info->global_medoids[(size_t)i * C + j] = infos[(size_t)(2 * P.B + i) * C + j];
+            }
+        }
+        info->evals_algorithmic = alg;
+        info->evals_performed = perf;
+        info->rows_refined = rows_ref;
+        info->medoid_candidates = flags[1];
+        double ms[5];
+        tm.collect(ms);
+        info->ms_init = ms[kPhInit];
+        info->ms_landmark = ms[kPhLandmark];
+        info->ms_dist = ms[kPhDist];
+        info->ms_refine = ms[kPhRefine];
+        info->ms_select = ms[kPhSelect];
+    }
+    if (flags[0]) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
+    return KKM_OK;
+}
+
+size_t kkm_assign_workspace_bytes(const kkm_model* m, int64_t n, int32_t precision) {
+    if (!m || n < 0) return 0;
+    (void)precision;
+    AssignWs w;
+    Carver c(nullptr);
+    return carve_assign(c, m, n, w);
+}
+
+kkm_status kkm_assign(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
+                      size_t ws_bytes, void* stream, int32_t* labels_out, float* gap_out) {
+    if (!labels_out && n > 0) return fail(KKM_ERR_INVALID_ARG, "labels_out is NULL");
+    AssignWs w;
+    return assign_common(m, X, n, dtype, precision, ws, ws_bytes, static_cast<hipStream_t>(stream), labels_out, gap_out,
+                         false, w);
+}
+
+kkm_status kkm_cost(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
+                    size_t ws_bytes, void* stream, double* cost_out) {
+    if (!cost_out) return fail(KKM_ERR_INVALID_ARG, "cost_out is NULL");
+    AssignWs w;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!m) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
+    if (ws && ws_bytes >= kkm_assign_workspace_bytes(m, n, precision) && !(reinterpret_cast<uintptr_t>(ws) & 255)) {
+        Carver c(ws);
+        carve_assign(c, m, n, w);
+    }
+    int32_t* labels = w.labels_tmp;
+    KKM_TRY(assign_common(m, X, n, dtype, precision, ws, ws_bytes, s, labels, nullptr, true, w));
+    if (n == 0) {
+        *cost_out = 0.0;
+        return KKM_OK;
+    }
+    KKM_TRY(launch_sum(w.best, n, w.partials, w.cost, s));
+    double cost = 0.0;
+    int32_t nf = 0;
+    KKM_HIP(hipMemcpyAsync(&cost, w.cost, sizeof(double), hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipMemcpyAsync(&nf, w.nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipStreamSynchronize(s));
+    if (nf) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
+    *cost_out = cost;
+    return KKM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// Distances from a tile of samples to sparse centroids, and the label decision (Eq. 2, 15, 17):
+//
+//   d(x, j) = K(x,x) - 2 sum_{l in segment j} a_l K(x, s_l) + a^T K_SS a
+//
+// Used for the batch-wide pass of a fit (support = the landmarks of the final centroids,
+// a_l = 1/c_j, self = g^) and for assigning new samples to a model (support = medoids or any
+// sparse centroids).  Work split: a workgroup of four wavefronts owns 64 samples, one per lane;
+// each wavefront takes a contiguous run of clusters holding about a quarter of the support rows;
+// support rows are read with wave-uniform addresses (scalar loads, broadcast to every lane).
+//
+// FP32 evaluation carries a per-row bound E on the error of every d(x, j).  A row whose best and
+// second-best distances are within 2E is listed and decided again in FP64 (launch_refine), so the
+// label equals the exact-arithmetic label wherever the FP64 margin is non-zero.
+#include "kkm_internal.hpp"
+#include "kkm_launch.hpp"
+
+namespace kkm {
+
+namespace {
+
+constexpr float kU32 = 5.9604645e-8f;  // unit roundoff of float
+
+// ----------------------------------------------------------------------------- evaluators
+// linear / RBF with the sample row held in registers (DP = padded length)
+template <typename TI, typename TC, int DP>
+struct EvalDot {
+    TC x[DP];
+    TC qn, kqq;
+    const TI* rows;
+    int64_t dpad;
+    const float* sn32;
+    const double* sn64;
+    int type;
+    TC inv2s2;
+    int64_t d;
+    float snmax;
+
+    __device__ bool load(const DistArgs& a, int64_t q) {
+        const TI* r = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+            TI v = k < a.q.d ? r[k] : TI(0);
+            ok = ok && isfinite((double)v);
+            x[k] = (TC)v;
+        }
+        qn = TC(0);
+#pragma unroll
+        for (int k = 0; k < DP; ++k) qn = fma(x[k], x[k], qn);
+        type = a.ks.type;
+        kqq = type == KKM_KERNEL_LINEAR ? qn : TC(1);
+        rows = static_cast<const TI*>(a.sup.rows);
+        dpad = a.sup.dpad;
+        sn32 = a.sup.snorm32;
+        sn64 = a.sup.snorm64;
+        inv2s2 = (TC)a.ks.inv2s2;
+        d = a.q.d;
+        snmax = *a.sup.snorm_max;
+        return ok;
+    }
+    __device__ __forceinline__ TC eval(int l) const {
+        const TI* s = rows + (int64_t)l * dpad;
+        TC dot = TC(0);
+#pragma unroll
+        for (int k = 0; k < DP; ++k) dot = fma(x[k], (TC)s[k], dot);
+        const TC sn = sizeof(TC) == 8 ? (TC)sn64[l] : (TC)sn32[l];
+        return kfun_from_dot(type, dot, qn, sn, inv2s2);
+    }
+    // bound on |computed - exact| of d(x, j) for a segment of `len` rows (FP32 only)
+    __device__ __forceinline__ float bound(int len, float acc, float g, float segabs) const {
+        if (sizeof(TC) == 8) return 0.0f;
+        const float u = kU32;
+        const float q = (float)qn;
+        float ef;
+        float extra = 0.0f;
+        if (type == KKM_KERNEL_LINEAR) {
+            const float kmax = sqrtf(q * snmax) * 1.0001f;
+            ef = ((float)(d + 2) * u * kmax + (float)(len + 2) * u * kmax) * segabs;
+            extra = (float)(d + 2) * u * q;
+        } else {
+            const float rho = (float)(2 * d + 6) * u * (q + snmax) * (float)inv2s2;
+            ef = (rho + (float)(len + 8) * u) * segabs;
+        }
+        const float e = 2.0f * ef + 3.0f * u * (fabsf((float)kqq) + 2.0f * fabsf(acc) + fabsf(g)) + extra;
+        return 2.0f * e;
+    }
+};
+
+// any kernel type in FP64, rows read from memory (RMSD rows centred)
+template <typename TI>
+struct EvalGeneric64 {
+    const TI* xr;
+    const TI* rows;
+    int64_t dpad;
+    KSpec ks;
+    double kqq;
+
+    __device__ bool load(const DistArgs& a, int64_t q) {
+        xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        bool ok = true;
+        for (int64_t k = 0; k < a.q.d; ++k) ok = ok && isfinite((double)xr[k]);
+        ks = a.ks;
+        rows = static_cast<const TI*>(a.sup.rows);
+        dpad = a.sup.dpad;
+        kqq = kself64(ks, xr);
+        return ok;
+    }
+    __device__ __forceinline__ double eval(int l) const { return k64(ks, xr, rows + (int64_t)l * dpad); }
+    __device__ __forceinline__ float bound(int, float, float, float) const { return 0.0f; }
+};
+
+template <typename T> struct TcOf;
+template <typename TI, typename TC, int DP> struct TcOf<EvalDot<TI, TC, DP>> { using type = TC; };
+template <typename TI> struct TcOf<EvalGeneric64<TI>> { using type = double; };
+
+// ----------------------------------------------------------------------------- tile kernel
+template <class Ev>
+__global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
+    using TC = typename TcOf<Ev>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    TC* Dl = reinterpret_cast<TC*>(smem_raw);      // [C][64]
+    __shared__ float Ew[4][64];
+    __shared__ int jb[5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+    const bool active = q < a.q.n;
+    const int C = a.sup.C;
+    const int32_t* off = a.sup.offsets;
+
+    if (threadIdx.x < 5) {
+        const int t = threadIdx.x;
+        const int64_t ns = off[C];
+        int j = 0;
+        if (t == 4) {
+            j = C;
+        } else if (t > 0) {
+            const int64_t target = (ns * t + 3) / 4;
+            while (j < C && off[j] < target) ++j;
+        }
+        jb[t] = j;
+    }
+    Ev ev;
+    const bool ok = ev.load(a, active ? q : 0);
+    if (active && !ok) atomicOr(a.nonfinite, 1);
+    __syncthreads();
+
+    float emax = 0.0f;
+    const int j0 = jb[wave], j1 = jb[wave + 1];
+    for (int j = j0; j < j1; ++j) {
+        const int lo = off[j], hi = off[j + 1];
+        TC acc = TC(0);
+        for (int l = lo; l < hi; ++l) {
+            const TC coef = sizeof(TC) == 8 ? (TC)a.sup.coef64[l] : (TC)a.sup.coef32[l];
+            acc = fma(coef, ev.eval(l), acc);
+        }
+        const double g = a.sup.self[j];
+        TC D;
+        if (hi > lo && g < kInf) {
+            D = ev.kqq - TC(2) * acc + (TC)g;
+            emax = fmaxf(emax, ev.bound(hi - lo, (float)acc, (float)g, (float)a.sup.segabs[j]));
+        } else {
+            D = (TC)kInf;
+        }
+        Dl[j * 64 + lane] = D;
+    }
+    Ew[wave][lane] = emax;
+    __syncthreads();
+
+    if (wave == 0 && active) {
+        const float E = fmaxf(fmaxf(Ew[0][lane], Ew[1][lane]), fmaxf(Ew[2][lane], Ew[3][lane]));
+        TC best = (TC)kInf, second = (TC)kInf;
+        int bj = 0;
+        for (int j = 0; j < C; ++j) {
+            const TC D = Dl[j * 64 + lane];
+            if (D < best) { second = best; best = D; bj = j; }
+            else if (D < second) { second = D; }
+        }
+        a.labels[q] = bj;
+        if (a.best) a.best[q] = (double)best;
+        if (a.Erow) a.Erow[q] = E;
+        if (a.gap) {
+            const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)ev.kqq));
+            a.gap[q] = second < (TC)kInf ? (float)(((double)second - (double)best) / (scale > 0 ? scale : 1.0))
+                                         : __builtin_huge_valf();
+        }
+        if (E > 0.0f && (double)second - (double)best <= 2.0 * (double)E) {
+            const int pos = atomicAdd(a.refine_count, 1);
+            a.refine_list[pos] = (int32_t)q;
+        }
+    }
+    if (a.Dt && active) {
+        TC* Dt = static_cast<TC*>(static_cast<void*>(a.Dt));
+        for (int j = wave; j < C; j += 4) Dt[(int64_t)j * a.ldD + q] = Dl[j * 64 + lane];
+    }
+}
+
+// ----------------------------------------------------------------------------- FP64 re-decision
+template <typename TI>
+__global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
+    __shared__ double Kv[1024];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* facc = reinterpret_cast<double*>(smem_raw);   // [C]
+    const int C = a.sup.C;
+    const int32_t* off = a.sup.offsets;
+    const int64_t ns = off[C];
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    const int count = *a.refine_count;
+    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+        const int64_t q = a.refine_list[i];
+        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        for (int j = threadIdx.x; j < C; j += blockDim.x) facc[j] = 0.0;
+        for (int64_t base = 0; base < ns; base += 1024) {
+            const int64_t lim = min<int64_t>(1024, ns - base);
+            __syncthreads();
+            for (int t = threadIdx.x; t < lim; t += blockDim.x)
+                Kv[t] = a.sup.coef64[base + t] * k64(a.ks, xr, rows + (base + t) * a.sup.dpad);
+            __syncthreads();
+            for (int j = threadIdx.x; j < C; j += blockDim.x) {
+                const int64_t lo = max<int64_t>(off[j], base), hi = min<int64_t>(off[j + 1], base + lim);
+                double s = facc[j];
+                for (int64_t l = lo; l < hi; ++l) s += Kv[l - base];
+                facc[j] = s;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double kqq = kself64(a.ks, xr);
+            double best = kInf, second = kInf;
+            int bj = 0;
+            for (int j = 0; j < C; ++j) {
+                const double g = a.sup.self[j];
+                const double D = (off[j + 1] > off[j] && g < kInf) ? kqq - 2.0 * facc[j] + g : kInf;
+                if (D < best) { second = best; best = D; bj = j; }
+                else if (D < second) { second = D; }
+            }
+            a.labels[q] = bj;
+            if (a.best) a.best[q] = best;
+            if (a.gap) {
+                const double scale = fmax(fmax(fabs(best), fabs(second)), fabs(kqq));
+                a.gap[q] = second < kInf ? (float)((second - best) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------- deterministic sum
+__global__ __launch_bounds__(256) void sum_partial_kernel(const double* __restrict__ v, int64_t n, int64_t chunk,
+                                                          double* __restrict__ out) {
+    __shared__ double red[256];
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min<int64_t>(n, lo + chunk);
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+template <class Ev>
+kkm_status launch_dist_ev(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    using TC = typename TcOf<Ev>::type;
+    const size_t lds = sizeof(TC) * (size_t)a.sup.C * 64;
+    if (lds > dev.max_lds_per_block)
+        return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile (C=" + std::to_string(a.sup.C) + ")");
+    const void* fn = reinterpret_cast<const void*>(&dist_kernel<Ev>);
+    if (lds > 48 * 1024) KKM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const unsigned blocks = (unsigned)((a.q.n + 63) / 64);
+    hipLaunchKernelGGL(dist_kernel<Ev>, dim3(blocks), dim3(256), lds, s, a);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+template <typename TI, typename TC>
+kkm_status launch_dist_dot(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    switch (a.sup.dpad) {
+        case 4: return launch_dist_ev<EvalDot<TI, TC, 4>>(a, dev, s);
+        case 8: return launch_dist_ev<EvalDot<TI, TC, 8>>(a, dev, s);
+        case 16: return launch_dist_ev<EvalDot<TI, TC, 16>>(a, dev, s);
+        case 32: return launch_dist_ev<EvalDot<TI, TC, 32>>(a, dev, s);
+        case 64: return launch_dist_ev<EvalDot<TI, TC, 64>>(a, dev, s);
+        case 128: return launch_dist_ev<EvalDot<TI, TC, 128>>(a, dev, s);
+        default: return fail(KKM_ERR_INTERNAL, "unexpected padded dimension");
+    }
+}
+
+}  // namespace
+
+bool dist_is_fp64(const DistArgs& a) { return a.precision == KKM_PREC_FP64 || a.ks.type == KKM_KERNEL_RMSD; }
+
+size_t dist_lds_bytes(const DistArgs& a) { return (dist_is_fp64(a) ? 8 : 4) * (size_t)a.sup.C * 64; }
+
+kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    if (a.q.n <= 0) return KKM_OK;
+    const bool f64 = a.dtype == KKM_F64;
+    if (dist_is_fp64(a)) {
+        return f64 ? launch_dist_ev<EvalGeneric64<double>>(a, dev, s) : launch_dist_ev<EvalGeneric64<float>>(a, dev, s);
+    }
+    if (a.q.d > kMaxRegDim) return fail(KKM_ERR_UNSUPPORTED, "FP32 path supports d <= 128");
+    return f64 ? launch_dist_dot<double, float>(a, dev, s) : launch_dist_dot<float, float>(a, dev, s);
+}
+
+kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    if (a.q.n <= 0) return KKM_OK;
+    const size_t lds = sizeof(double) * (size_t)a.sup.C;
+    const unsigned blocks = (unsigned)std::min<int64_t>(a.q.n, 2 * (int64_t)dev.num_cus);
+    if (a.dtype == KKM_F64)
+        hipLaunchKernelGGL(refine_kernel<double>, dim3(blocks), dim3(256), lds, s, a);
+    else
+        hipLaunchKernelGGL(refine_kernel<float>, dim3(blocks), dim3(256), lds, s, a);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s) {
+    const int64_t P = 1024;
+    const int64_t chunk = std::max<int64_t>(1, (n + P - 1) / P);
+    const int64_t blocks = std::max<int64_t>(1, (n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(sum_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, best, n, chunk, partials);
+    KKM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sum_partial_kernel, dim3(1), dim3(256), 0, s, partials, blocks, blocks, out);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+}  // namespace kkm

@@ -1,0 +1,459 @@
+// Selection steps of a mini-batch, all in FP64:
+//
+//   kernel k-means++ seeding of the first batch (D^2 sampling in feature space);
+//   batch member counts |w_j^i| and the scatter of batch labels to caller order;
+//   batch medoids m_j^i = argmin_x d_last(x, j) over the batch (Eq. 10);
+//   the merge m_j <- argmin_x K(x,x) - 2(1-alpha) K(x, m_j) - 2 alpha K(x, m_j^i)
+//   with alpha = |w_j^i| / (|w_j^i| + |w_j|) (Eq. 11-13; alpha = 0 leaves m_j alone);
+//   building model arrays from medoids or from general sparse centroids;
+//   centring of RMSD frames.
+//
+// Every argmin keeps the lowest index on ties; minima are order-independent, so the chunked
+// reductions give the same result as a sequential scan.
+#include "kkm_internal.hpp"
+#include "kkm_launch.hpp"
+
+namespace kkm {
+
+namespace {
+
+template <typename TI>
+__device__ __forceinline__ const TI* brow(const BatchView& b, int64_t pos) {
+    return static_cast<const TI*>(b.X) + (b.base + pos * b.stride) * b.d;
+}
+
+// (value, index) minimum with the lowest index on equal values
+__device__ __forceinline__ void vmin(double& v, int64_t& i, double v2, int64_t i2) {
+    if (v2 < v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+__device__ void block_vmin(double& v, int64_t& i) {
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    sv[threadIdx.x] = v;
+    si[threadIdx.x] = i;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) {
+            double a = sv[threadIdx.x];
+            int64_t ia = si[threadIdx.x];
+            vmin(a, ia, sv[threadIdx.x + w], si[threadIdx.x + w]);
+            sv[threadIdx.x] = a;
+            si[threadIdx.x] = ia;
+        }
+        __syncthreads();
+    }
+    v = sv[0];
+    i = si[0];
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------------- k-means++
+__global__ __launch_bounds__(1024) void kpp_pick_kernel(const double* __restrict__ D2, int64_t n, int k,
+                                                        const double* __restrict__ uniforms, int32_t* chosen) {
+    __shared__ double incl[1024];
+    const int t = threadIdx.x;
+    const double u = uniforms[k];
+    const int64_t fallback = min<int64_t>((int64_t)floor(u * (double)n), n - 1);
+    if (k == 0) {
+        if (t == 0) chosen[0] = (int32_t)fallback;
+        return;
+    }
+    const int64_t w = (n + 1023) / 1024;
+    const int64_t lo = min<int64_t>(n, t * w), hi = min<int64_t>(n, lo + w);
+    double cs = 0.0;
+    for (int64_t q = lo; q < hi; ++q) cs += D2[q];
+    incl[t] = cs;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan, fixed order
+        const double add = t >= o ? incl[t - o] : 0.0;
+        __syncthreads();
+        incl[t] += add;
+        __syncthreads();
+    }
+    const double total = incl[1023];
+    if (t == 0) chosen[k] = (int32_t)fallback;   // overwritten below when D^2 has mass
+    __syncthreads();
+    if (!(total > 0.0)) return;
+    const double thr = u * total;
+    const double excl = t > 0 ? incl[t - 1] : 0.0;
+    if (incl[t] > thr && excl <= thr) {
+        double loc = 0.0;
+        int64_t pick = hi - 1;
+        for (int64_t q = lo; q < hi; ++q) {
+            loc += D2[q];
+            if (excl + loc > thr) { pick = q; break; }
+        }
+        chosen[k] = (int32_t)pick;
+    }
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void kpp_dist_kernel(BatchView b, KSpec ks, int k, const int32_t* chosen,
+                                                       double* D2) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= b.n) return;
+    const TI* x = brow<TI>(b, q);
+    const TI* m = brow<TI>(b, chosen[k]);
+    double v = (kself64(ks, x) - 2.0 * k64(ks, x, m)) + kself64(ks, m);
+    v = v > 0.0 ? v : 0.0;
+    D2[q] = k == 0 ? v : fmin(D2[q], v);
+}
+
+template <typename TI>
+__global__ void set_medoids_kernel(BatchView b, KSpec ks, int C, const int32_t* chosen, TI* M, int64_t Mpad,
+                                   double* Mself, int64_t* Midx, int64_t* wcount) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < C; j += gridDim.x * blockDim.x) {
+        wcount[j] = 0;
+        if (!chosen) {
+            Mself[j] = kInf;
+            Midx[j] = -1;
+            for (int64_t c = 0; c < Mpad; ++c) M[j * Mpad + c] = TI(0);
+            continue;
+        }
+        const TI* x = brow<TI>(b, chosen[j]);
+        for (int64_t c = 0; c < Mpad; ++c) M[j * Mpad + c] = c < b.d ? x[c] : TI(0);
+        Mself[j] = kself64(ks, x);
+        Midx[j] = b.base + (int64_t)chosen[j] * b.stride;
+    }
+}
+
+// ----------------------------------------------------------------------------- members / medoids / merge
+__global__ __launch_bounds__(256) void members_kernel(SelectArgs a) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.b.n) return;
+    const int j = a.labels[q];
+    atomicAdd(a.counts + j, 1);
+    if (a.label_out) a.label_out[a.b.base + q * a.b.stride] = j;
+}
+
+// Eq. 10 with FP32 distances: candidates are the rows whose interval [D - E, D + E] can hold the
+// minimum; their distance is recomputed in FP64 and the lowest (value, position) wins.
+template <typename TI, typename TD>
+__global__ __launch_bounds__(256) void batch_medoid_kernel(SelectArgs a) {
+    const int j = blockIdx.x;
+    if (a.counts[j] == 0) {
+        if (threadIdx.x == 0) a.bmed[j] = -1;
+        return;
+    }
+    const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
+    const int64_t n = a.b.n;
+    double up = kInf;
+    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) up = fmin(up, (double)Dt[q] + (double)a.Erow[q]);
+    int64_t dummy = 0;
+    block_vmin(up, dummy);
+    const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    const double g = a.sup.self[j];
+    double bv = kInf;
+    int64_t bi = INT64_MAX;
+    int cands = 0;
+    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) {
+        if ((double)Dt[q] - (double)a.Erow[q] <= up) {
+            const TI* x = brow<TI>(a.b, q);
+            double f = 0.0;
+            for (int l = lo; l < hi; ++l) f += a.sup.coef64[l] * k64(a.ks, x, rows + (int64_t)l * a.sup.dpad);
+            const double v = kself64(a.ks, x) - 2.0 * f + g;
+            vmin(bv, bi, v, q);
+            ++cands;
+        }
+    }
+    block_vmin(bv, bi);
+    if (cands) atomicAdd(a.cand_total, cands);
+    // no candidate only when every distance is +inf or NaN (non-finite input, reported by the caller)
+    if (threadIdx.x == 0) a.bmed[j] = bi == INT64_MAX ? 0 : (int32_t)bi;
+}
+
+__device__ __forceinline__ double merge_alpha(int32_t members, int64_t w) {
+    const double den = (double)members + (double)w;
+    return den > 0.0 ? (double)members / den : 0.0;
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void merge_partial_kernel(SelectArgs a, int64_t chunk) {
+    const int j = blockIdx.y;
+    const double alpha = merge_alpha(a.counts[j], a.wcount[j]);
+    if (!(alpha > 0.0) || a.bmed[j] < 0) return;
+    const TI* xm = brow<TI>(a.b, a.bmed[j]);
+    const TI* mj = static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min<int64_t>(a.b.n, lo + chunk);
+    double bv = kInf;
+    int64_t bi = INT64_MAX;
+    for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
+        const TI* x = brow<TI>(a.b, q);
+        double sc = kself64(a.ks, x) - 2.0 * alpha * k64(a.ks, x, xm);
+        if (alpha < 1.0) sc = sc - 2.0 * (1.0 - alpha) * k64(a.ks, x, mj);
+        vmin(bv, bi, sc, q);
+    }
+    block_vmin(bv, bi);
+    if (threadIdx.x == 0) {
+        a.mpart_v[(int64_t)j * a.nchunk + blockIdx.x] = bv;
+        a.mpart_i[(int64_t)j * a.nchunk + blockIdx.x] = (int32_t)(bi == INT64_MAX ? -1 : bi);
+    }
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void merge_final_kernel(SelectArgs a) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.C; j += gridDim.x * blockDim.x) {
+        const int32_t mem = a.counts[j];
+        const double alpha = merge_alpha(mem, a.wcount[j]);
+        if (alpha > 0.0) {
+            double bv = kInf;
+            int64_t bi = INT64_MAX;
+            for (int c = 0; c < a.nchunk; ++c) {
+                const int32_t i = a.mpart_i[(int64_t)j * a.nchunk + c];
+                if (i >= 0) vmin(bv, bi, a.mpart_v[(int64_t)j * a.nchunk + c], i);
+            }
+            if (bi == INT64_MAX) bi = a.bmed[j];
+            const TI* x = brow<TI>(a.b, bi);
+            TI* M = static_cast<TI*>(a.M) + (int64_t)j * a.Mpad;
+            for (int64_t c = 0; c < a.Mpad; ++c) M[c] = c < a.b.d ? x[c] : TI(0);
+            a.Mself[j] = kself64(a.ks, x);
+            a.Midx[j] = a.b.base + bi * a.b.stride;
+        }
+        a.wcount[j] += mem;
+        if (a.info_bmed) a.info_bmed[j] = mem > 0 ? a.b.base + (int64_t)a.bmed[j] * a.b.stride : -1;
+        if (a.info_bcnt) a.info_bcnt[j] = mem;
+        if (a.info_gmed) a.info_gmed[j] = a.Mself[j] < kInf ? a.Midx[j] : -1;
+    }
+}
+
+// ----------------------------------------------------------------------------- models
+template <typename TI>
+__global__ __launch_bounds__(1024) void model_from_medoids_kernel(kkm_model m, const TI* M, int64_t Mpad,
+                                                                  const double* Mself, const int64_t* Midx,
+                                                                  const int64_t* wcount, KSpec ks) {
+    __shared__ float red[1024];
+    float mx = 0.0f;
+    TI* S = static_cast<TI*>(m.support);
+    for (int j = threadIdx.x; j < m.C; j += blockDim.x) {
+        const TI* src = M + (int64_t)j * Mpad;
+        TI* dst = S + (int64_t)j * m.dpad;
+        double n64 = 0.0;
+        float n32 = 0.0f;
+        for (int64_t c = 0; c < m.dpad; ++c) {
+            const TI v = c < Mpad ? src[c] : TI(0);
+            dst[c] = v;
+            n64 = fma((double)v, (double)v, n64);
+            n32 = fmaf((float)v, (float)v, n32);
+        }
+        m.snorm64[j] = n64;
+        m.snorm32[j] = n32;
+        m.coef64[j] = 1.0;
+        m.coef32[j] = 1.0f;
+        m.offsets[j] = j;
+        m.self[j] = Mself[j];
+        m.segabs[j] = 1.0;
+        m.counts[j] = wcount[j];
+        m.medoid_index[j] = Mself[j] < kInf ? Midx[j] : -1;
+        mx = fmaxf(mx, n32);
+    }
+    if (threadIdx.x == 0) m.offsets[m.C] = m.C;
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *m.snorm_max = red[0];
+    (void)ks;
+}
+
+// norms of every support row and the maximum (single block)
+template <typename TI>
+__global__ __launch_bounds__(1024) void model_norms_kernel(kkm_model m) {
+    __shared__ float red[1024];
+    float mx = 0.0f;
+    const TI* S = static_cast<const TI*>(m.support);
+    for (int64_t l = threadIdx.x; l < m.used; l += blockDim.x) {
+        double n64 = 0.0;
+        float n32 = 0.0f;
+        for (int64_t c = 0; c < m.d; ++c) {
+            const TI v = S[l * m.dpad + c];
+            n64 = fma((double)v, (double)v, n64);
+            n32 = fmaf((float)v, (float)v, n32);
+        }
+        m.snorm64[l] = n64;
+        m.snorm32[l] = n32;
+        m.coef32[l] = (float)m.coef64[l];
+        mx = fmaxf(mx, n32);
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 512; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *m.snorm_max = red[0];
+}
+
+// self term a^T K_SS a of segment j (one block per cluster), fixed summation order
+template <typename TI>
+__global__ __launch_bounds__(256) void model_self_kernel(kkm_model m, KSpec ks) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    const int lo = m.offsets[j], hi = m.offsets[j + 1];
+    const int64_t len = hi - lo;
+    const TI* S = static_cast<const TI*>(m.support);
+    double s = 0.0, sa = 0.0;
+    for (int64_t p = threadIdx.x; p < len * len; p += blockDim.x) {
+        const int64_t r = lo + p / len, c = lo + p % len;
+        s += m.coef64[r] * m.coef64[c] * k64(ks, S + r * m.dpad, S + c * m.dpad);
+    }
+    for (int64_t p = threadIdx.x; p < len; p += blockDim.x) sa += fabs(m.coef64[lo + p]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) m.self[j] = len > 0 ? red[0] : kInf;
+    __syncthreads();
+    red[threadIdx.x] = sa;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) m.segabs[j] = red[0];
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void centre_kernel(const TI* __restrict__ X, TI* __restrict__ Y, int64_t n, int A) {
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n) return;
+    const TI* x = X + f * 3 * A;
+    TI* y = Y + f * 3 * A;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int a = 0; a < A; ++a) {
+        cx += (double)x[3 * a];
+        cy += (double)x[3 * a + 1];
+        cz += (double)x[3 * a + 2];
+    }
+    cx /= A;
+    cy /= A;
+    cz /= A;
+    for (int a = 0; a < A; ++a) {
+        y[3 * a] = (TI)((double)x[3 * a] - cx);
+        y[3 * a + 1] = (TI)((double)x[3 * a + 1] - cy);
+        y[3 * a + 2] = (TI)((double)x[3 * a + 2] - cz);
+    }
+}
+
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+}  // namespace
+
+kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
+                           int32_t* chosen, double* D2, hipStream_t s) {
+    for (int k = 0; k < C; ++k) {
+        hipLaunchKernelGGL(kpp_pick_kernel, dim3(1), dim3(1024), 0, s, D2, b.n, k, uniforms, chosen);
+        KKM_HIP(hipGetLastError());
+        if (k == C - 1) break;
+        if (dtype == KKM_F64)
+            hipLaunchKernelGGL(kpp_dist_kernel<double>, dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
+        else
+            hipLaunchKernelGGL(kpp_dist_kernel<float>, dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
+        KKM_HIP(hipGetLastError());
+    }
+    return KKM_OK;
+}
+
+kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, int C, const int32_t* chosen, void* M,
+                              int64_t Mpad, double* Mself, int64_t* Midx, int64_t* wcount, hipStream_t s) {
+    if (dtype == KKM_F64)
+        hipLaunchKernelGGL(set_medoids_kernel<double>, dim3(nblocks(C, 256)), dim3(256), 0, s, b, ks, C, chosen,
+                           static_cast<double*>(M), Mpad, Mself, Midx, wcount);
+    else
+        hipLaunchKernelGGL(set_medoids_kernel<float>, dim3(nblocks(C, 256)), dim3(256), 0, s, b, ks, C, chosen,
+                           static_cast<float*>(M), Mpad, Mself, Midx, wcount);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_members(const SelectArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(members_kernel, dim3(nblocks(a.b.n, 256)), dim3(256), 0, s, a);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_batch_medoids(const SelectArgs& a, bool tile_f64, hipStream_t s) {
+    if (a.dtype == KKM_F64) {
+        if (tile_f64) hipLaunchKernelGGL((batch_medoid_kernel<double, double>), dim3(a.C), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((batch_medoid_kernel<double, float>), dim3(a.C), dim3(256), 0, s, a);
+    } else {
+        if (tile_f64) hipLaunchKernelGGL((batch_medoid_kernel<float, double>), dim3(a.C), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((batch_medoid_kernel<float, float>), dim3(a.C), dim3(256), 0, s, a);
+    }
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_merge(const SelectArgs& a, hipStream_t s) {
+    const int64_t chunk = (a.b.n + a.nchunk - 1) / a.nchunk;
+    if (a.dtype == KKM_F64) {
+        hipLaunchKernelGGL(merge_partial_kernel<double>, dim3(a.nchunk, a.C), dim3(256), 0, s, a, chunk);
+        KKM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(merge_final_kernel<double>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(merge_partial_kernel<float>, dim3(a.nchunk, a.C), dim3(256), 0, s, a, chunk);
+        KKM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(merge_final_kernel<float>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
+    }
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_model_from_medoids(kkm_model* m, const void* M, int64_t Mpad, const double* Mself,
+                                     const int64_t* Midx, const int64_t* wcount, hipStream_t s) {
+    const KSpec ks{m->kernel.type, m->kernel.n_atoms, m->d, 0.0};
+    if (m->dtype == KKM_F64)
+        hipLaunchKernelGGL(model_from_medoids_kernel<double>, dim3(1), dim3(1024), 0, s, *m,
+                           static_cast<const double*>(M), Mpad, Mself, Midx, wcount, ks);
+    else
+        hipLaunchKernelGGL(model_from_medoids_kernel<float>, dim3(1), dim3(1024), 0, s, *m,
+                           static_cast<const float*>(M), Mpad, Mself, Midx, wcount, ks);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_model_prepare(kkm_model* m, hipStream_t s) {
+    const double sg = m->kernel.sigma;
+    const KSpec ks{m->kernel.type, m->kernel.n_atoms, m->d, m->kernel.type == KKM_KERNEL_LINEAR ? 0.0 : 1.0 / (2.0 * sg * sg)};
+    if (m->dtype == KKM_F64) {
+        hipLaunchKernelGGL(model_norms_kernel<double>, dim3(1), dim3(1024), 0, s, *m);
+        KKM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(model_self_kernel<double>, dim3(m->C), dim3(256), 0, s, *m, ks);
+    } else {
+        hipLaunchKernelGGL(model_norms_kernel<float>, dim3(1), dim3(1024), 0, s, *m);
+        KKM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(model_self_kernel<float>, dim3(m->C), dim3(256), 0, s, *m, ks);
+    }
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_centre(const void* X, void* Y, int64_t n, int A, int dtype, hipStream_t s) {
+    if (n <= 0) return KKM_OK;
+    if (dtype == KKM_F64)
+        hipLaunchKernelGGL(centre_kernel<double>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                           static_cast<const double*>(X), static_cast<double*>(Y), n, A);
+    else
+        hipLaunchKernelGGL(centre_kernel<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                           static_cast<const float*>(X), static_cast<float*>(Y), n, A);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return KKM_OK;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)std::min<int64_t>(1024, nblocks(n, 256))), dim3(256), 0, s, p, n);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+}  // namespace kkm

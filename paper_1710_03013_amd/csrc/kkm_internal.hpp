@@ -1,0 +1,252 @@
+// Internal declarations of libkkm: status plumbing, the model layout, launch helpers and the device
+// building blocks shared by the kernels (kernel functions, wavefront reductions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "../../include/kkm.h"
+
+namespace kkm {
+
+// ----------------------------------------------------------------------------- host status
+void set_error(const std::string& msg);
+kkm_status fail(kkm_status code, const std::string& msg);
+
+#define KKM_HIP(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::kkm::fail(KKM_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define KKM_TRY(expr)                          \
+    do {                                       \
+        kkm_status s_ = (expr);                \
+        if (s_ != KKM_OK) return s_;           \
+    } while (0)
+
+// ----------------------------------------------------------------------------- constants
+constexpr int kWave = 64;
+constexpr int kMaxClusters = 1024;        // C limit of the device kernels
+constexpr int kMaxRegDim = 128;           // register-resident query rows (linear / RBF)
+constexpr double kInf = __builtin_huge_val();
+
+// Padded dimension of stored support rows: the register-resident row length the distance
+// kernels are instantiated for.
+inline int padded_dim(int64_t d) {
+    if (d <= 4) return 4;
+    if (d <= 8) return 8;
+    if (d <= 16) return 16;
+    if (d <= 32) return 32;
+    if (d <= 64) return 64;
+    return 128;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bump allocator over the caller's workspace (or a size probe when base == nullptr).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count) {
+        size_t at = off;
+        off = align256(off + count * sizeof(T));
+        return base ? reinterpret_cast<T*>(base + at) : nullptr;
+    }
+};
+
+// Per-device facts queried once.
+struct DeviceInfo {
+    int device = -1;
+    int num_cus = 0;
+    size_t max_lds_per_block = 0;
+    bool coop = false;
+};
+kkm_status device_info(DeviceInfo* out);
+
+}  // namespace kkm
+
+// ----------------------------------------------------------------------------- the model
+// Device-resident sparse centroids.  Support rows are stored padded to `dpad` columns with zeros
+// (RMSD: centred frames, also padded), in the model dtype.
+struct kkm_model {
+    kkm_kernel kernel;
+    int64_t d = 0;
+    int32_t dpad = 0;
+    int32_t C = 0;
+    int64_t cap = 0;          // support rows allocated
+    int64_t used = 0;         // support rows in use
+    int32_t dtype = KKM_F32;
+    int device = 0;
+    void* block = nullptr;    // one allocation holding everything below
+    void* support = nullptr;  // [cap][dpad] (dtype)
+    float* snorm32 = nullptr; // [cap] ||s||^2 (RBF / linear) or G (RMSD), FP32
+    double* snorm64 = nullptr;// [cap] same in FP64
+    float* coef32 = nullptr;  // [cap]
+    double* coef64 = nullptr; // [cap]
+    int32_t* offsets = nullptr; // [C+1]
+    double* self = nullptr;   // [C] a^T K a (FP64); +inf disables the cluster
+    double* segabs = nullptr; // [C] sum_l |a_l| over segment j
+    float* snorm_max = nullptr; // [1] max ||s||^2 over the support (error bounds)
+    int64_t* counts = nullptr;  // [C] |w_j| of a fitted model
+    int64_t* medoid_index = nullptr; // [C]
+};
+
+namespace kkm {
+
+// ----------------------------------------------------------------------------- device helpers
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    // fixed butterfly: the result depends only on the 64 inputs, not on timing
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float exp_neg(float a) {     // exp(-a), a >= 0
+    return __builtin_amdgcn_exp2f(-a * 1.4426950408889634f);
+}
+__device__ __forceinline__ double exp_neg(double a) { return ::exp(-a); }
+
+// Kernel-function evaluation from a dot product and the two squared norms (linear / RBF).
+template <typename T>
+__device__ __forceinline__ T kfun_from_dot(int type, T dot, T qn, T sn, T inv2s2) {
+    if (type == KKM_KERNEL_LINEAR) return dot;
+    T d2 = qn + sn - T(2) * dot;
+    d2 = d2 > T(0) ? d2 : T(0);
+    return exp_neg(d2 * inv2s2);
+}
+
+// FP64 kernel evaluation between two rows of length d (linear / RBF), RBF from explicit
+// differences.  Rows may be float or double.
+template <typename TA, typename TB>
+__device__ inline double kfun64_rows(int type, const TA* __restrict__ a, const TB* __restrict__ b, int64_t d,
+                                     double inv2s2) {
+    double acc = 0.0;
+    if (type == KKM_KERNEL_LINEAR) {
+        for (int64_t k = 0; k < d; ++k) acc = fma((double)a[k], (double)b[k], acc);
+        return acc;
+    }
+    for (int64_t k = 0; k < d; ++k) {
+        double t = (double)a[k] - (double)b[k];
+        acc = fma(t, t, acc);
+    }
+    return ::exp(-acc * inv2s2);
+}
+
+// Kernel specification as the device sees it.
+struct KSpec {
+    int type;        // enum kkm_kernel_type
+    int n_atoms;     // RMSD
+    int64_t d;       // row length
+    double inv2s2;   // 1 / (2 sigma^2)
+};
+
+// Determinant of a 4x4 matrix by the Laplace expansion over 2x2 minors of rows (0,1) and (2,3).
+template <typename T>
+__device__ __forceinline__ T det4(const T m[4][4]) {
+    T s0 = m[0][0] * m[1][1] - m[1][0] * m[0][1];
+    T s1 = m[0][0] * m[1][2] - m[1][0] * m[0][2];
+    T s2 = m[0][0] * m[1][3] - m[1][0] * m[0][3];
+    T s3 = m[0][1] * m[1][2] - m[1][1] * m[0][2];
+    T s4 = m[0][1] * m[1][3] - m[1][1] * m[0][3];
+    T s5 = m[0][2] * m[1][3] - m[1][2] * m[0][3];
+    T c5 = m[2][2] * m[3][3] - m[3][2] * m[2][3];
+    T c4 = m[2][1] * m[3][3] - m[3][1] * m[2][3];
+    T c3 = m[2][1] * m[3][2] - m[3][1] * m[2][2];
+    T c2 = m[2][0] * m[3][3] - m[3][0] * m[2][3];
+    T c1 = m[2][0] * m[3][2] - m[3][0] * m[2][2];
+    T c0 = m[2][0] * m[3][1] - m[3][0] * m[2][1];
+    return s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0;
+}
+
+// Horn's symmetric, traceless 4x4 key matrix of the correlation R[p][q] = sum_a x_ap y_aq
+// (row-major R[3p+q]); its largest eigenvalue is the best superposition overlap.
+template <typename T>
+__device__ __forceinline__ void horn_key(const T R[9], T N[4][4]) {
+    const T Sxx = R[0], Sxy = R[1], Sxz = R[2], Syx = R[3], Syy = R[4], Syz = R[5];
+    const T Szx = R[6], Szy = R[7], Szz = R[8];
+    N[0][0] = Sxx + Syy + Szz; N[0][1] = Syz - Szy;        N[0][2] = Szx - Sxz;         N[0][3] = Sxy - Syx;
+    N[1][1] = Sxx - Syy - Szz; N[1][2] = Sxy + Syx;        N[1][3] = Szx + Sxz;
+    N[2][2] = -Sxx + Syy - Szz; N[2][3] = Syz + Szy;
+    N[3][3] = -Sxx - Syy + Szz;
+    N[1][0] = N[0][1]; N[2][0] = N[0][2]; N[3][0] = N[0][3];
+    N[2][1] = N[1][2]; N[3][1] = N[1][3]; N[3][2] = N[2][3];
+}
+
+// Largest eigenvalue of the key matrix by Newton's method on its characteristic polynomial
+// lambda^4 + c2 lambda^2 + c1 lambda + c0 (c2 = -tr(N^2)/2, c1 = -tr(N^3)/3, c0 = det N),
+// started from the upper bound (Ga + Gb)/2; the polynomial is convex above its largest root, so
+// the iterates decrease monotonically onto it.  Returns RMSD^2 = max(0, (Ga + Gb - 2 lambda) / A).
+__device__ inline double rmsd2_from_corr64(const double R[9], double Ga, double Gb, int A) {
+    double N[4][4];
+    horn_key(R, N);
+    double N2[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double t = 0.0;
+            for (int k = 0; k < 4; ++k) t = fma(N[i][k], N[k][j], t);
+            N2[i][j] = t;
+        }
+    double tr2 = 0.0, tr3 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        tr2 += N2[i][i];
+        for (int k = 0; k < 4; ++k) tr3 = fma(N2[i][k], N[k][i], tr3);
+    }
+    const double c2 = -0.5 * tr2, c1 = -tr3 / 3.0, c0 = det4(N);
+    const double E0 = 0.5 * (Ga + Gb);
+    double lam = E0;
+    for (int it = 0; it < 60; ++it) {
+        const double l2 = lam * lam;
+        const double p = (l2 + c2) * l2 + c1 * lam + c0;
+        const double dp = (4.0 * l2 + 2.0 * c2) * lam + c1;
+        if (!(dp > 0.0)) break;
+        const double step = p / dp;
+        lam -= step;
+        if (fabs(step) <= 1e-15 * E0) break;
+    }
+    const double r2 = (Ga + Gb - 2.0 * lam) / A;
+    return r2 > 0.0 ? r2 : 0.0;
+}
+
+// FP64 RMSD kernel between two centred frames (AoS rows x0 y0 z0 x1 ...).
+template <typename TA, typename TB>
+__device__ inline double rmsd_kfun64(const TA* __restrict__ a, const TB* __restrict__ b, int A, double inv2s2) {
+    double R[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double Ga = 0.0, Gb = 0.0;
+    for (int t = 0; t < A; ++t) {
+        const double ax = a[3 * t], ay = a[3 * t + 1], az = a[3 * t + 2];
+        const double bx = b[3 * t], by = b[3 * t + 1], bz = b[3 * t + 2];
+        R[0] = fma(ax, bx, R[0]); R[1] = fma(ax, by, R[1]); R[2] = fma(ax, bz, R[2]);
+        R[3] = fma(ay, bx, R[3]); R[4] = fma(ay, by, R[4]); R[5] = fma(ay, bz, R[5]);
+        R[6] = fma(az, bx, R[6]); R[7] = fma(az, by, R[7]); R[8] = fma(az, bz, R[8]);
+        Ga = fma(ax, ax, fma(ay, ay, fma(az, az, Ga)));
+        Gb = fma(bx, bx, fma(by, by, fma(bz, bz, Gb)));
+    }
+    return ::exp(-rmsd2_from_corr64(R, Ga, Gb, A) * inv2s2);
+}
+
+// K(a, b) in FP64 for any kernel type (RMSD rows must be centred).
+template <typename TA, typename TB>
+__device__ inline double k64(const KSpec& ks, const TA* __restrict__ a, const TB* __restrict__ b) {
+    if (ks.type == KKM_KERNEL_RMSD) return rmsd_kfun64(a, b, ks.n_atoms, ks.inv2s2);
+    return kfun64_rows(ks.type, a, b, ks.d, ks.inv2s2);
+}
+
+// K(a, a) in FP64.
+template <typename TA>
+__device__ inline double kself64(const KSpec& ks, const TA* __restrict__ a) {
+    if (ks.type != KKM_KERNEL_LINEAR) return 1.0;
+    double acc = 0.0;
+    for (int64_t k = 0; k < ks.d; ++k) acc = fma((double)a[k], (double)a[k], acc);
+    return acc;
+}
+
+}  // namespace kkm

@@ -1,0 +1,149 @@
+// Argument blocks and host launchers of the device kernels (one struct per kernel family).
+#pragma once
+
+#include "kkm_internal.hpp"
+
+namespace kkm {
+
+// A view of one mini-batch: row j of the batch is row (base + j * stride) of X.
+struct BatchView {
+    const void* X;
+    int64_t d;
+    int64_t base;
+    int64_t stride;
+    int64_t n;
+};
+
+// ---------------------------------------------------------------- landmark phase (k_landmark.hip)
+struct LandmarkArgs {
+    const void* X;          // samples (dtype of the fit), RMSD: centred frames
+    int64_t d, base, stride;
+    const int32_t* lm;      // [ell] batch positions of the landmarks, ascending
+    int32_t ell, C, max_updates, grid;
+    int32_t ktype, n_atoms;
+    double inv2s2;
+    int32_t init_mode;      // 0: lab_init, 1: nearest valid global medoid (Eq. 8)
+    const int32_t* lab_init;// [ell]
+    const void* M;          // [C][Mpad] global medoid rows (dtype of the fit)
+    int64_t Mpad;
+    const double* Mself;    // [C] K(m,m), +inf where the medoid is unset
+    double* Kbuf;           // [ell][ell] scratch
+    int32_t* lab;           // [2][ell] scratch
+    double* partial;        // [grid][C] scratch
+    int32_t* changed;       // [max_updates+1] scratch
+    int32_t* zero_ints;     // ints to clear for the later kernels of the batch
+    int32_t n_zero_ints;
+    // outputs
+    int32_t* lab_final;     // [ell]
+    int32_t* offsets;       // [C+1]
+    double* ghat;           // [C] (+inf for clusters without landmarks)
+    double* segabs;         // [C]
+    int32_t* updates_out;   // [1] landmark label updates performed
+    void* support;          // [ell][dpad]
+    int64_t dpad;
+    float* snorm32;
+    double* snorm64;
+    float* coef32;
+    double* coef64;
+    int32_t* src_index;     // [ell] batch position of each support row
+    float* snorm_max;       // [1]
+};
+int landmark_grid(const DeviceInfo& dev, int ell);
+size_t landmark_lds_bytes_host(int ell, int C, int G);
+kkm_status launch_landmark_phase(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
+
+// ---------------------------------------------------------------- sparse-centroid distances (k_dist.hip)
+// Support of the centroids being assigned to: rows in CSR order, coefficients, self terms.
+struct SupportView {
+    const void* rows;       // [ns][dpad] (dtype)
+    int64_t dpad;
+    const float* snorm32;
+    const double* snorm64;
+    const float* coef32;
+    const double* coef64;
+    const int32_t* offsets; // [C+1]
+    const double* self;     // [C]
+    const double* segabs;   // [C]
+    const float* snorm_max; // [1]
+    int32_t C;
+};
+
+struct DistArgs {
+    BatchView q;            // query rows (RMSD: centred)
+    int32_t dtype;          // dtype of both query rows and support rows
+    int32_t precision;      // KKM_PREC_*
+    KSpec ks;
+    SupportView sup;
+    // outputs
+    float* Dt;              // [C][ldD] distances (transposed), or null
+    int64_t ldD;
+    float* Erow;            // [n] per-row error bound of every D entry, or null
+    int32_t* labels;        // [n]
+    float* gap;             // [n] or null
+    double* best;           // [n] best distance, or null
+    int32_t* refine_list;   // [n]
+    int32_t* refine_count;  // [1]
+    int32_t* nonfinite;     // [1]
+};
+kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
+// True when launch_dist evaluates (and stores Dt) in FP64 for these arguments.
+bool dist_is_fp64(const DistArgs& a);
+// LDS bytes the distance tile needs for C clusters.
+size_t dist_lds_bytes(const DistArgs& a);
+// FP64 re-decision of the rows listed by launch_dist.
+kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
+// Deterministic FP64 sum of best[0..n) into out[0] (partials: >= 1024 doubles of scratch).
+kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------- selection steps (k_select.hip)
+struct SelectArgs {
+    BatchView b;            // the batch
+    int32_t dtype;
+    KSpec ks;
+    int32_t C;
+    // global medoid state
+    void* M;                // [C][Mpad]
+    int64_t Mpad;
+    double* Mself;          // [C]
+    int64_t* Midx;          // [C] sample index
+    int64_t* wcount;        // [C]
+    // batch state
+    const int32_t* labels;  // [n] batch labels
+    int32_t* counts;        // [C] |w_j^i|
+    int32_t* bmed;          // [C] batch medoid positions
+    int32_t* label_out;     // [N] caller labels (scatter), or null
+    const float* Dt;        // [C][ldD]
+    int64_t ldD;
+    const float* Erow;      // [n]
+    SupportView sup;        // support of the batch centroids (FP64 re-evaluation of candidates)
+    double* mpart_v;        // [C][nchunk] merge partial minima
+    int32_t* mpart_i;
+    int32_t nchunk;
+    int32_t* cand_total;    // [1] medoid candidates evaluated (accumulates)
+    // per-batch info rows (device, length C) or null
+    int64_t* info_bmed;
+    int64_t* info_bcnt;
+    int64_t* info_gmed;
+};
+kkm_status launch_members(const SelectArgs& a, hipStream_t s);
+// tile_f64: the distance tile Dt holds doubles (FP64 precision) rather than floats.
+kkm_status launch_batch_medoids(const SelectArgs& a, bool tile_f64, hipStream_t s);
+kkm_status launch_merge(const SelectArgs& a, hipStream_t s);
+
+// k-means++ on a batch: uniforms[C] device, chosen[C] device out, D2 [n] scratch.
+kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
+                           int32_t* chosen, double* D2, hipStream_t s);
+// Global medoids <- batch rows `chosen` (valid, counts 0), or all unset when chosen == null.
+kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, int C, const int32_t* chosen,
+                              void* M, int64_t Mpad, double* Mself, int64_t* Midx, int64_t* wcount, hipStream_t s);
+// Write a fitted model (support = the C medoid rows, coefficient 1) from the global medoid state.
+kkm_status launch_model_from_medoids(kkm_model* m, const void* M, int64_t Mpad, const double* Mself,
+                                     const int64_t* Midx, const int64_t* wcount, hipStream_t s);
+// Self terms a^T K_SS a of a model's segments (FP64) and its norm / coefficient arrays from rows.
+kkm_status launch_model_prepare(kkm_model* m, hipStream_t s);
+// RMSD: centre each frame of X (n rows, 3A values) into Y.
+kkm_status launch_centre(const void* X, void* Y, int64_t n, int A, int dtype, hipStream_t s);
+// Set n ints to zero (a kernel, so that the call can sit inside a captured graph).
+kkm_status launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+
+}  // namespace kkm

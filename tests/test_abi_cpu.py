@@ -1,0 +1,88 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry point,
+reproduces the random-draw specification, and fails cleanly where a device is needed."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import kkm_inputs as ki
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _kk():
+    import paper_1710_03013_amd as kk
+    return kk
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "kkm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(kkm_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    kk = _kk()
+    out = subprocess.run(["nm", "-D", "--defined-only", kk.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (kkm_\w+)", out))
+    declared = _declared()
+    assert len(declared) >= 16
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    assert set(declared) == set(kk.EXPORTED_SYMBOLS)
+
+
+def test_landmark_count_matches_spec():
+    kk = _kk()
+    for n, s in [(10000, 0.1), (20000, 0.02), (7, 0.5), (5, 0.01), (100, 1.0), (3, 0.5), (10001, 0.05)]:
+        assert kk.kkm_landmark_count(n, s) == ki.landmark_count(n, s)
+
+
+def test_library_draws_equal_python_spec():
+    kk = _kk()
+    for seed, batch, n, s in [(2001, 0, 10000, 0.1), (7, 3, 999, 0.05), (0, 1, 50, 0.5), (5, 0, 40, 1.0)]:
+        np.testing.assert_array_equal(kk.kkm_draw_landmarks(seed, batch, n, s), ki.draw_landmarks(seed, batch, n, s))
+    np.testing.assert_array_equal(kk.kkm_draw_kmpp_uniforms(2003, 100), ki.draw_kmpp_uniforms(2003, 100))
+    np.testing.assert_array_equal(kk.kkm_draw_init_labels(2000, 2000, 2), ki.draw_init_labels(2000, 2000, 2))
+    np.testing.assert_array_equal(kk.kkm_draw_init_labels(9, 777, 13), ki.draw_init_labels(9, 777, 13))
+
+
+def test_invalid_arguments_are_rejected():
+    kk = _kk()
+    with pytest.raises(kk.KkmError) as e:
+        kk.kkm_draw_landmarks(1, 0, 10, 0.0)
+    assert e.value.status == -1
+    k = kk._kernel("rbf", 1.0)
+    for bad in [dict(C=0), dict(B=0), dict(s=1.5), dict(max_iter=0), dict(precision=7), dict(C=5000)]:
+        args = dict(C=2, B=1, s=1.0, max_iter=5, sampling="stride", init="kmeans++", precision="fp32", seed=0,
+                    landmarks=None, kmpp_uniforms=None, init_labels=None, init_medoids=None)
+        args.update(bad)
+        assert kk.kkm_fit_workspace_bytes(100, 2, kk.KKM_F32, k, **args) == 0
+    rmsd = kk._kernel("rmsd", 1.0, 50)
+    args = dict(C=2, B=1, s=1.0, max_iter=5, sampling="stride", init="kmeans++", precision="fp32", seed=0,
+                landmarks=None, kmpp_uniforms=None, init_labels=None, init_medoids=None)
+    assert kk.kkm_fit_workspace_bytes(100, 149, kk.KKM_F32, rmsd, **args) == 0
+    assert kk.kkm_fit_workspace_bytes(100, 150, kk.KKM_F32, rmsd, **args) > 0
+
+
+def test_workspace_estimate_grows_with_problem_size():
+    kk = _kk()
+    k = kk._kernel("rbf", 4.0)
+    base = dict(C=20, B=10, s=0.1, max_iter=20, sampling="stride", init="kmeans++", precision="fp32", seed=1,
+                landmarks=None, kmpp_uniforms=None, init_labels=None, init_medoids=None)
+    a = kk.kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, k, **base)
+    b = kk.kkm_fit_workspace_bytes(200_000, 16, kk.KKM_F32, k, **base)
+    assert 0 < a < b
+    # the landmark block (l^2 FP64) and the n x C distance tile dominate
+    n, ell = 10_000, 1000
+    assert a >= ell * ell * 8 + 20 * n * 4
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU is present: the no-device path is not reachable")
+def test_model_create_without_device_fails_cleanly():
+    kk = _kk()
+    with pytest.raises(kk.KkmError) as e:
+        kk.kkm_model_create("rbf", d=4, C=3)
+    assert e.value.status == -3

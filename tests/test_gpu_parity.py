@@ -1,0 +1,244 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Labels must match the oracle exactly wherever the oracle's relative margin
+(d2 - d1) / max(|d1|, |d2|, |K(x,x)|) exceeds 1e-6; costs within 1e-9 (FP64) or
+1e-5 (FP32) relative.  Inputs are seeded synthetic sets shaped like the
+workloads, at sizes the oracle finishes in seconds, spanning several 64-row
+tiles with a ragged tail."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import kkm_inputs as ki  # noqa: E402
+from oracle import kkm as okkm  # noqa: E402
+from oracle.kernels import Kernel  # noqa: E402
+
+GAP = 1e-6
+
+
+def _kk():
+    import paper_1710_03013_amd as kk
+    return kk
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _labels_match(got, want, gaps, what):
+    bad = (got != want) & (gaps > GAP)
+    assert not bad.any(), f"{what}: {int(bad.sum())} labels differ with margin > {GAP} (first at {np.flatnonzero(bad)[:5]})"
+
+
+def _medoid_model_from_rows(kk, kern, rows, dtype):
+    C, d = rows.shape
+    m = kk.kkm_model_create(kern.kind, d=d, C=C, dtype=dtype, sigma=kern.sigma, n_atoms=kern.n_atoms)
+    kk.kkm_model_load(m, rows, np.arange(C + 1), np.ones(C))
+    return m
+
+
+# ------------------------------------------------------------------------------------------ assign
+@pytest.mark.parametrize("kind,sigma,d,C,n,prec,dtype", [
+    ("rbf", 4.0, 16, 20, 1000 + 17, "fp32", "f32"),
+    ("rbf", 8.0, 64, 100, 4096 + 63, "fp32", "f32"),
+    ("rbf", 1.0, 2, 2, 2000, "fp64", "f64"),
+    ("linear", 1.0, 16, 7, 777, "fp32", "f32"),
+    ("linear", 1.0, 5, 3, 65, "fp64", "f64"),
+    ("rbf", 2.0, 3, 5, 1, "fp32", "f32"),
+    ("rbf", 3.0, 33, 9, 130, "fp32", "f64"),
+])
+def test_assign_medoid_model(kind, sigma, d, C, n, prec, dtype):
+    kk = _kk()
+    _say(f"assign {kind} d={d} C={C} n={n} {prec} {dtype}")
+    npdt = np.float64 if dtype == "f64" else np.float32
+    X, _ = ki.datasets.gaussian_mixture(n + C, d, max(C, 2), seed=100 + d, sigma=1.0, dtype=npdt)
+    rows, Y = X[:C], X[C:] if n > 0 else X[:0]
+    kern = Kernel(kind, sigma)
+    m = _medoid_model_from_rows(kk, kern, rows, dtype)
+    Yd = torch.from_numpy(np.ascontiguousarray(Y)).cuda()
+    lab, gap = kk.kkm_assign(m, Yd, precision=prec, want_gap=True)
+    torch.cuda.synchronize()
+    model = okkm.SparseModel(rows.astype(np.float64), np.arange(C + 1), np.ones(C))
+    rl, rg, rd = okkm.assign(kern, Y, model)
+    _labels_match(lab.cpu().numpy(), rl, rg, "assign")
+    g = gap.cpu().numpy()
+    fin = np.isfinite(rg) & (rg > 1e-3)
+    np.testing.assert_allclose(g[fin], rg[fin], rtol=1e-3 if prec == "fp32" else 2e-7, atol=2e-4 if prec == "fp32" else 1e-12)
+    cost = kk.kkm_cost(m, Yd, precision=prec)
+    want = okkm.cost(kern, Y, model)
+    assert abs(cost - want) <= (1e-5 if prec == "fp32" else 1e-9) * max(1.0, abs(want))
+
+
+def test_assign_sparse_centroids():
+    """General sparse centroids: several support rows per cluster, unequal coefficients, an empty cluster."""
+    kk = _kk()
+    _say("assign sparse centroids")
+    X, _ = ki.datasets.gaussian_mixture(3000, 16, 6, seed=5, sigma=1.5, box=5.0)
+    rng = np.random.default_rng(0)
+    S = X[:40]
+    offsets = np.array([0, 10, 10, 17, 30, 31, 40])
+    coef = rng.uniform(0.2, 1.0, size=40)
+    for j in range(6):
+        a, b = offsets[j], offsets[j + 1]
+        if b > a:
+            coef[a:b] /= coef[a:b].sum()
+    kern = Kernel("rbf", 3.0)
+    m = kk.kkm_model_create("rbf", d=16, C=6, max_support=40, dtype="f32", sigma=3.0)
+    kk.kkm_model_load(m, S, offsets, coef)
+    exp = kk.kkm_model_export(m)
+    model = okkm.SparseModel(S.astype(np.float64), offsets, coef)
+    K_ss = kern(S, S)
+    for j in range(6):
+        a, b = offsets[j], offsets[j + 1]
+        if b > a:
+            w = coef[a:b]
+            assert abs(exp["self"][j] - w @ K_ss[a:b, a:b] @ w) < 1e-12
+        else:
+            assert np.isinf(exp["self"][j])
+    Y = X[40:]
+    for prec in ("fp32", "fp64"):
+        lab, gap = kk.kkm_assign(m, torch.from_numpy(Y).cuda(), precision=prec, want_gap=True)
+        rl, rg, _ = okkm.assign(kern, Y, model)
+        got = lab.cpu().numpy()
+        _labels_match(got, rl, rg, f"sparse {prec}")
+        assert not np.any(got == 1)
+
+
+# ------------------------------------------------------------------------------------------ fit
+def _fit_both(kk, X, kern, C, B, s, T, init, seed, prec, sampling="stride", dtype=None, **kw):
+    N = X.shape[0]
+    L = ki.draw_all_landmarks(seed, N, B, s, sampling)
+    u = ki.draw_kmpp_uniforms(seed, C) if init == "kmeans++" else None
+    n0 = len(ki.batch_index_sets(N, B, sampling)[0])
+    lab0 = ki.draw_init_labels(seed, n0, C) if init == "random" else None
+    med0 = kw.get("init_medoids")
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    model, labels, info = kk.kkm_fit(Xd, kern.kind, sigma=kern.sigma, n_atoms=kern.n_atoms, C=C, B=B, s=s,
+                                     max_iter=T, sampling=sampling, init=init, precision=prec, seed=seed,
+                                     landmarks=L, kmpp_uniforms=u, init_labels=lab0, init_medoids=med0)
+    torch.cuda.synchronize()
+    ref = okkm.fit(X, C, kern, B, T, L, sampling=sampling, init=init, kmpp_uniforms=u, init_labels=lab0,
+                   init_medoids=med0)
+    return model, labels.cpu().numpy(), info, ref
+
+
+def _device_updates(ref, T):
+    """Label updates the device makes per batch: landmark-only updates until the landmark labels
+    first repeat (at most T-1), plus the one batch-wide pass.  Read off the oracle's trajectory of
+    landmark labels, which the landmark-only loop follows step for step."""
+    out = []
+    for lp in ref.loops:
+        tr = lp.trajectory
+        k = T - 1
+        for t in range(1, min(len(tr), T)):
+            if np.array_equal(tr[t], tr[t - 1]):
+                k = t
+                break
+        out.append(k + 1)
+    return np.asarray(out)
+
+
+def _check_fit(kk, model, labels, info, ref, kern, X, T, strict=True):
+    if strict and ref.min_gap > GAP:
+        np.testing.assert_array_equal(labels, ref.labels)
+        np.testing.assert_array_equal(info["batch_medoids"], ref.batch_medoids)
+        np.testing.assert_array_equal(info["global_medoids"], ref.global_medoids)
+        np.testing.assert_array_equal(info["batch_counts"], ref.batch_counts)
+        np.testing.assert_array_equal(info["updates_per_batch"], _device_updates(ref, T))
+        exp = kk.kkm_model_export(model)
+        np.testing.assert_array_equal(exp["medoid_index"], ref.medoid_index)
+        np.testing.assert_array_equal(exp["counts"], ref.counts)
+    else:
+        _labels_match(labels, ref.labels, ref.label_gaps, "fit labels")
+
+
+def test_fit_two_rings_fp64():
+    """Two-ring workload at full size: exact kernel k-means (B = 1, s = 1), FP64, random labels."""
+    kk = _kk()
+    _say("fit rings fp64")
+    X, y = ki.datasets.config_data(0)
+    kern = Kernel("rbf", 1.0)
+    T = 30
+    model, labels, info, ref = _fit_both(kk, X, kern, 2, 1, 1.0, T, "random", 2000, "fp64")
+    assert ref.min_gap > GAP
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+
+
+@pytest.mark.parametrize("N,prec", [(20_000, "fp32"), (20_000, "fp64"), (100_000, "fp32")])
+def test_fit_gaussian_mixture(N, prec):
+    """Mini-batch landmark form on the 16-d, 20-component mixture (B = 10, s = 0.1, T = 20)."""
+    kk = _kk()
+    _say(f"fit mixture N={N} {prec}")
+    X, y = ki.datasets.gaussian_mixture(N, 16, 20, seed=1001, sigma=1.0)
+    kern = Kernel("rbf", 4.0)
+    T = 20
+    model, labels, info, ref = _fit_both(kk, X, kern, 20, 10, 0.1, T, "kmeans++", 2001, prec)
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+    assert info["evals_algorithmic"] == ref.evals
+
+
+def test_fit_linear_block_ragged_explicit_medoids():
+    """Linear kernel, block sampling, N not a multiple of B, explicit initial medoids."""
+    kk = _kk()
+    _say("fit linear block ragged")
+    X, _ = ki.datasets.gaussian_mixture(5003, 8, 6, seed=3, sigma=1.0, box=6.0)
+    kern = Kernel("linear")
+    T = 15
+    model, labels, info, ref = _fit_both(kk, X, kern, 6, 7, 0.3, T, "medoids", 9, "fp32", sampling="block",
+                                         init_medoids=np.array([0, 100, 200, 300, 400, 500]))
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+
+
+@pytest.mark.parametrize("C,B,s,T", [(1, 3, 0.5, 5), (4, 2, 0.001, 3), (3, 5, 1.0, 1), (5, 4, 0.25, 2)])
+def test_fit_edge_cases(C, B, s, T):
+    """One cluster, a single landmark per batch, one update, tiny batches."""
+    kk = _kk()
+    _say(f"fit edge C={C} B={B} s={s} T={T}")
+    X, _ = ki.datasets.gaussian_mixture(641, 4, 4, seed=C * 10 + B, sigma=1.0, box=3.0)
+    kern = Kernel("rbf", 2.0)
+    model, labels, info, ref = _fit_both(kk, X, kern, C, B, s, T, "kmeans++", 5, "fp32")
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+
+
+def test_fit_is_deterministic():
+    kk = _kk()
+    _say("fit determinism")
+    X, _ = ki.datasets.gaussian_mixture(30_000, 16, 20, seed=4, sigma=1.0)
+    Xd = torch.from_numpy(X).cuda()
+    outs = []
+    for _ in range(2):
+        m, lab, info = kk.kkm_fit(Xd, "rbf", sigma=4.0, C=20, B=10, s=0.1, max_iter=20, seed=77)
+        outs.append((lab.cpu().numpy(), kk.kkm_model_export(m)["support"], info["global_medoids"]))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    np.testing.assert_array_equal(outs[0][2], outs[1][2])
+
+
+def test_fit_rejects_nonfinite_input():
+    kk = _kk()
+    X, _ = ki.datasets.gaussian_mixture(500, 4, 3, seed=1, sigma=1.0)
+    X[123, 2] = np.nan
+    with pytest.raises(kk.KkmError) as e:
+        kk.kkm_fit(torch.from_numpy(X).cuda(), "rbf", sigma=1.0, C=3, B=2, s=0.5, max_iter=5, seed=1)
+    assert e.value.status == -4
+
+
+# ------------------------------------------------------------------------------------------ RMSD
+def test_rmsd_assign_and_fit_small():
+    kk = _kk()
+    _say("rmsd small")
+    X, y = ki.datasets.md_frames(600, A=12, n_templates=4, seed=8)
+    kern = Kernel("rmsd", 1.5, 12)
+    T = 10
+    model, labels, info, ref = _fit_both(kk, X, kern, 4, 3, 0.2, T, "kmeans++", 3, "fp32")
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+    Y, _ = ki.datasets.md_frames(257, A=12, n_templates=4, seed=9)
+    lab = kk.kkm_assign(model, torch.from_numpy(Y).cuda()).cpu().numpy()
+    rl, rg, _ = okkm.assign(kern, Y, okkm.medoid_model(ref))
+    _labels_match(lab, rl, rg, "rmsd assign")
