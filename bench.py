@@ -97,6 +97,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-requests", type=int, default=200)
     ap.add_argument("--latency-size", type=int, default=4096)
+    ap.add_argument("--no-phase-timing", action="store_true",
+                    help="do not record HIP events around the fit phases (no roofline entry)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -123,6 +125,9 @@ def main() -> int:
     n0 = len(ki.batch_index_sets(N, B)[0])
     init_labels = ki.draw_init_labels(seed, n0, C) if cfg["init"] == "random" else None
     dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    log(f"[bench] device {props.name} CUs={props.multi_processor_count} "
+        f"lds/block={getattr(props, 'shared_memory_per_block', '?')}")
     Xd = torch.from_numpy(X).to(dev)
     fit_kw = dict(kernel=cfg["kernel"], sigma=cfg.get("sigma", 1.0), n_atoms=cfg.get("n_atoms", 0), C=C, B=B, s=s,
                   max_iter=T, init=cfg["init"], precision=prec, seed=seed, landmarks=landmarks,
@@ -147,7 +152,7 @@ def main() -> int:
     infos = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        infos.append(step(time_phases=True))
+        infos.append(step(time_phases=not args.no_phase_timing))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"[bench] {args.steps} timed steps in {t1 - t0:.3f} s")
@@ -157,25 +162,28 @@ def main() -> int:
     value = evals_step * args.steps / elapsed
     batch_n = [len(ix) for ix in ki.batch_index_sets(N, B)]
     assigned_step = int(np.dot(batch_n, info["updates_per_batch"])) + N
-    ms = {k_: float(np.mean([i["ms"][k_] for i in infos])) for k_ in infos[0]["ms"]}
+    ms = ({k_: float(np.mean([i["ms"][k_] for i in infos])) for k_ in infos[0]["ms"]}
+          if not args.no_phase_timing else None)
 
     # dominant kernel: the per-phase time summed over the step
     ells = [len(l) for l in landmarks]
-    if ms["landmark"] >= ms["dist"]:
-        dom = "landmark_phase_kernel"
-        per_launch = np.mean([landmark_flops_per_launch(cfg["kernel"], d, ells[i], int(info["updates_per_batch"][i]), C)
-                              for i in range(B)])
-        dur = ms["landmark"] / B * 1e-3
-        peak, bound = PEAK_FP64_VECTOR, "alu"
-    else:
-        dom = "dist_kernel"
-        per_launch = np.mean([batch_n[i] * ells[i] for i in range(B)]) * dist_flops_per_eval(cfg["kernel"], d)
-        dur = ms["dist"] / B * 1e-3
-        peak, bound = (PEAK_FP32_VECTOR if prec != "fp64" else PEAK_FP64_VECTOR), "alu"
-    achieved = per_launch / dur
-    roofline = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": dom,
-                "avg_launch_us": dur * 1e6, "phase_ms_per_step": ms}
+    roofline = None
+    if ms is not None:
+        if ms["landmark"] >= ms["dist"]:
+            dom = "landmark_phase_kernel"
+            per_launch = np.mean([landmark_flops_per_launch(cfg["kernel"], d, ells[i],
+                                                            int(info["updates_per_batch"][i]), C) for i in range(B)])
+            dur = ms["landmark"] / B * 1e-3
+            peak, bound = PEAK_FP64_VECTOR, "alu"
+        else:
+            dom = "dist_kernel"
+            per_launch = np.mean([batch_n[i] * ells[i] for i in range(B)]) * dist_flops_per_eval(cfg["kernel"], d)
+            dur = ms["dist"] / B * 1e-3
+            peak, bound = (PEAK_FP32_VECTOR if prec != "fp64" else PEAK_FP64_VECTOR), "alu"
+        achieved = per_launch / dur
+        roofline = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None, "kernel": dom,
+                    "avg_launch_us": dur * 1e6, "phase_ms_per_step": ms}
 
     # assign latency at a fixed request size
     lat = []
@@ -189,7 +197,7 @@ def main() -> int:
         e1.record()
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
-    lat = np.asarray(lat)
+    lat = np.asarray(lat) if lat else np.zeros(1)
 
     out = {
         "metric": "kernel evals/s (fit + assign, algorithmic count)",
@@ -209,6 +217,7 @@ def main() -> int:
         "assign_latency_ms": {"request_size": int(q.shape[0]), "p50": float(np.percentile(lat, 50)),
                               "p99": float(np.percentile(lat, 99))},
         "refined_rows_per_step": int(info["rows_refined"]),
+        "medoid_candidates_per_step": int(info["medoid_candidates"]),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
@@ -216,8 +225,15 @@ def main() -> int:
         out["cpu_baseline"] = cpu_baseline(X, cfg, landmarks, uniforms, init_labels)
         log("[bench] oracle done")
     print(json.dumps(out), flush=True)
+    # release device objects before the interpreter exits (profilers finalise after this point)
+    del model, ws, labels, aws, qws, qlab, q, Xd
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
     return 0
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    _rc = main()
+    if _rc:
+        sys.exit(_rc)

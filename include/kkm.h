@@ -122,6 +122,10 @@ typedef struct kkm_fit_info {
     double ms_dist;             /* out: batch-wide distance pass (Eq. 15-17 over every batch sample) */
     double ms_refine;           /* out: FP64 re-decision of near-tie rows */
     double ms_select;           /* out: member counts, batch medoids (Eq. 10), merge (Eq. 11-13) */
+    int64_t* landmark_trace;    /* host [64] or NULL: device wall-clock stamps (100 MHz) taken by the first
+                                   workgroup at the steps of batch 0's landmark phase: [0] count, then
+                                   start, block done, init done, and per update: sort, sums, barrier,
+                                   g^, barrier (profiling aid) */
 } kkm_fit_info;
 
 /* A clustering model: C sparse centroids w_j = sum_{l in segment j} a_l phi(s_l), kept resident in

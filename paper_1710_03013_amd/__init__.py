@@ -63,7 +63,7 @@ class _FitInfo(ct.Structure):
                 ("rows_refined", ct.c_int64), ("medoid_candidates", ct.c_int64),
                 ("time_phases", ct.c_int32), ("reserved", ct.c_int32), ("ms_init", ct.c_double),
                 ("ms_landmark", ct.c_double), ("ms_dist", ct.c_double), ("ms_refine", ct.c_double),
-                ("ms_select", ct.c_double)]
+                ("ms_select", ct.c_double), ("landmark_trace", ct.POINTER(ct.c_int64))]
 
 
 # name -> (restype, argtypes): every symbol include/kkm.h declares
@@ -248,7 +248,8 @@ def kkm_fit_workspace_bytes(N, d, dtype, kernel, **params) -> int:
 
 def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20, sampling="stride",
             init="kmeans++", precision="fp32", seed=0, landmarks=None, kmpp_uniforms=None, init_labels=None,
-            init_medoids=None, model=None, workspace=None, stream=None, want_labels=True, time_phases=False):
+            init_medoids=None, model=None, workspace=None, stream=None, want_labels=True, time_phases=False,
+            landmark_trace=False):
     """Fit on X (a CUDA tensor, N x d).  Returns (model, labels tensor or None, info dict)."""
     import torch
     if not X.is_cuda:
@@ -271,7 +272,10 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     bmed = np.zeros(B * C, dtype=np.int64)
     bcnt = np.zeros(B * C, dtype=np.int64)
     gmed = np.zeros(B * C, dtype=np.int64)
+    trace = np.zeros(64, dtype=np.int64) if landmark_trace else None
     info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, int(bool(time_phases)))
+    if trace is not None:
+        info.landmark_trace = _i64p(trace)
     _check(lib().kkm_fit(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p),
                          ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(stream)), model.ptr,
                          ct.c_void_p(labels.data_ptr()) if labels is not None else None, ct.byref(info)))
@@ -280,7 +284,8 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
                evals_performed=info.evals_performed, rows_refined=info.rows_refined,
                medoid_candidates=info.medoid_candidates, workspace_bytes=need,
                ms=dict(init=info.ms_init, landmark=info.ms_landmark, dist=info.ms_dist, refine=info.ms_refine,
-                       select=info.ms_select) if time_phases else None)
+                       select=info.ms_select) if time_phases else None,
+               landmark_trace=trace[1:1 + int(trace[0])] if trace is not None else None)
     return model, labels, out
 
 

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libkkm.so")
 ARCH = os.environ.get("KKM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
 ]

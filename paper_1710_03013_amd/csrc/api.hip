@@ -2,6 +2,7 @@
 // per-batch launch sequence.  All arithmetic runs in the kernels of k_landmark / k_dist / k_select.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <vector>
 
 #include "kkm_internal.hpp"
@@ -10,43 +11,51 @@
 namespace kkm {
 namespace {
 
-// Pairs of HIP events recorded on the caller's stream around phases of a fit (optional).
+// Pairs of HIP events recorded on the caller's stream around phases of a fit (optional).  The
+// events live for one call only.
 struct PhaseTimer {
     bool on = false;
     hipStream_t s = nullptr;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
-    hipEvent_t open = nullptr;
-    kkm_status begin() {
-        if (!on) return KKM_OK;
-        KKM_HIP(hipEventCreate(&open));
-        return hipEventRecord(open, s) == hipSuccess ? KKM_OK : fail(KKM_ERR_DEVICE, "hipEventRecord");
+    int device = 0;
+    size_t used = 0;
+    std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;   // (phase, (begin, end) pool slots)
+    size_t open = 0;
+    static std::vector<hipEvent_t>& pool(int device) {
+        static thread_local std::map<int, std::vector<hipEvent_t>> pools;
+        return pools[device];
     }
+    kkm_status record(size_t* slot) {
+        auto& p = pool(device);
+        if (used == p.size()) {
+            hipEvent_t e;
+            KKM_HIP(hipEventCreate(&e));
+            p.push_back(e);
+        }
+        *slot = used++;
+        KKM_HIP(hipEventRecord(p[*slot], s));
+        return KKM_OK;
+    }
+    kkm_status begin() { return on ? record(&open) : KKM_OK; }
     kkm_status end(int phase) {
         if (!on) return KKM_OK;
-        hipEvent_t e;
-        KKM_HIP(hipEventCreate(&e));
-        KKM_HIP(hipEventRecord(e, s));
-        ev[phase].push_back({open, e});
-        open = nullptr;
+        size_t e;
+        KKM_TRY(record(&e));
+        spans.push_back({phase, {open, e}});
         return KKM_OK;
+    }
+    ~PhaseTimer() {
+        auto& p = pool(device);
+        for (hipEvent_t e : p) (void)hipEventDestroy(e);
+        p.clear();
     }
     // after the stream has been synchronised
     void collect(double out[5]) {
-        for (int p = 0; p < 5; ++p) {
-            out[p] = 0.0;
-            for (auto& pr : ev[p]) {
-                float ms = 0.0f;
-                if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) out[p] += ms;
-            }
+        for (int p = 0; p < 5; ++p) out[p] = 0.0;
+        auto& pl = pool(device);
+        for (auto& sp : spans) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, pl[sp.second.first], pl[sp.second.second]) == hipSuccess) out[sp.first] += ms;
         }
-    }
-    ~PhaseTimer() {
-        for (auto& v : ev)
-            for (auto& pr : v) {
-                (void)hipEventDestroy(pr.first);
-                (void)hipEventDestroy(pr.second);
-            }
-        if (open) (void)hipEventDestroy(open);
     }
 };
 enum { kPhInit = 0, kPhLandmark = 1, kPhDist = 2, kPhRefine = 3, kPhSelect = 4 };
@@ -63,6 +72,7 @@ struct FitPlan {
     int64_t nmax = 0, ellmax = 0, ell_total = 0;
     int gmax = 1;
     int nchunk = 1;
+    int64_t cand_cap = 1;
     bool tile_f64 = false;
     std::vector<int32_t> lm_host;      // concatenated batch positions
     std::vector<double> uniforms;      // k-means++
@@ -83,6 +93,7 @@ struct FitWs {
     int64_t* wcount;
     double* Kbuf;
     int32_t* lab;
+    double* Sall;
     double* partial;
     int32_t* changed;
     int32_t* lab_final;
@@ -96,7 +107,12 @@ struct FitWs {
     double* coef64;
     int32_t* src_index;
     float* snorm_max;
-    int32_t* counts_b;     // [C]   cleared by the landmark phase of each batch
+    int32_t* split;        // [5]
+    int32_t* counts_b;     // [C+1] cleared by the landmark phase of each batch; [C] = candidate count
+    unsigned long long* colmin;   // [C]
+    int32_t* cand_q;
+    int32_t* cand_j;
+    double* cand_v;
     float* Dt;
     float* Erow;
     int32_t* labels_b;
@@ -104,10 +120,14 @@ struct FitWs {
     int32_t* refine_counts; // [B]
     int32_t* flags;        // [2] nonfinite, medoid candidates
     int32_t* bmed;
-    double* mpart_v;
-    int32_t* mpart_i;
+    int32_t* mpart_c;
+    double* gpart_v;
+    int32_t* gpart_i;
     int32_t* updates;      // [B]
     int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
+    int64_t* trace;        // [64]
+    unsigned* barrier;     // [1]
+    int32_t* lm_error;     // [1]
 };
 
 size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
@@ -125,7 +145,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.wcount = c.take<int64_t>(C);
     w.Kbuf = c.take<double>((size_t)P.ellmax * P.ellmax);
     w.lab = c.take<int32_t>(2 * P.ellmax);
-    w.partial = c.take<double>((size_t)P.gmax * C);
+    w.Sall = c.take<double>((size_t)2 * P.ellmax * C);
+    w.partial = c.take<double>((size_t)2 * P.gmax * C);
     w.changed = c.take<int32_t>(P.T + 1);
     w.lab_final = c.take<int32_t>(P.ellmax);
     w.offsets = c.take<int32_t>(C + 1);
@@ -138,7 +159,12 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.coef64 = c.take<double>(P.ellmax);
     w.src_index = c.take<int32_t>(P.ellmax);
     w.snorm_max = c.take<float>(1);
-    w.counts_b = c.take<int32_t>(C);
+    w.split = c.take<int32_t>(5);
+    w.counts_b = c.take<int32_t>(C + 1);
+    w.colmin = c.take<unsigned long long>(C);
+    w.cand_q = c.take<int32_t>((size_t)P.cand_cap);
+    w.cand_j = c.take<int32_t>((size_t)P.cand_cap);
+    w.cand_v = c.take<double>((size_t)P.cand_cap);
     w.Dt = c.take<float>((size_t)C * P.nmax * (P.tile_f64 ? 2 : 1));
     w.Erow = c.take<float>(P.nmax);
     w.labels_b = c.take<int32_t>(P.nmax);
@@ -146,10 +172,14 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.refine_counts = c.take<int32_t>(P.B);
     w.flags = c.take<int32_t>(2);
     w.bmed = c.take<int32_t>(C);
-    w.mpart_v = c.take<double>((size_t)C * P.nchunk);
-    w.mpart_i = c.take<int32_t>((size_t)C * P.nchunk);
+    w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
+    w.gpart_v = c.take<double>((size_t)C * P.nchunk);
+    w.gpart_i = c.take<int32_t>((size_t)C * P.nchunk);
     w.updates = c.take<int32_t>(P.B);
     w.info = c.take<int64_t>((size_t)3 * P.B * C);
+    w.trace = c.take<int64_t>(64);
+    w.barrier = c.take<unsigned>(1);
+    w.lm_error = c.take<int32_t>(1);
     return c.off;
 }
 
@@ -264,12 +294,13 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
         }
     }
     P.tile_f64 = p.precision == KKM_PREC_FP64 || kernel->type == KKM_KERNEL_RMSD;
-    P.nchunk = (int)std::max<int64_t>(1, (P.nmax + 2047) / 2048);
+    P.nchunk = select_chunks(P.nmax);
+    P.cand_cap = std::min<int64_t>((int64_t)P.nmax * P.C, (int64_t)1 << 30);
     if (dev) {
         for (int i = 0; i < P.B; ++i) {
             const int G = landmark_grid(*dev, (int)P.ell[i]);
             P.gmax = std::max(P.gmax, G);
-            if (landmark_lds_bytes_host((int)P.ell[i], P.C, G) > dev->max_lds_per_block)
+            if (landmark_lds_bytes_host((int)P.ell[i], P.C, G, false) > dev->max_lds_per_block)
                 return fail(KKM_ERR_UNSUPPORTED, "landmark set of batch " + std::to_string(i) +
                                                      " too large for one workgroup's LDS; use more mini-batches");
         }
@@ -336,6 +367,7 @@ SupportView model_support(const kkm_model* m) {
     s.self = m->self;
     s.segabs = m->segabs;
     s.snorm_max = m->snorm_max;
+    s.split = m->split;
     s.C = m->C;
     return s;
 }
@@ -379,10 +411,11 @@ kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t d
     da.refine_list = w.refine_list;
     da.refine_count = w.refine_count;
     da.nonfinite = w.nonfinite;
+    da.n_support = m->used;
     if (da.sup.C * 64 * (dist_is_fp64(da) ? 8u : 4u) > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
     KKM_TRY(launch_dist(da, dev, s));
-    if (!dist_is_fp64(da)) KKM_TRY(launch_refine(da, dev, s));
+    if (!dist_is_fp64(da)) KKM_TRY(launch_refine(da, dev, s, m->used));
     return KKM_OK;
 }
 
@@ -431,6 +464,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     PhaseTimer tm;
     tm.on = info && info->time_phases;
     tm.s = s;
+    tm.device = dev.device;
 
     KKM_TRY(launch_zero_i32(w.refine_counts, P.B, s));
     KKM_TRY(launch_zero_i32(w.flags, 2, s));
@@ -480,10 +514,11 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.Mself = w.Mself;
         la.Kbuf = w.Kbuf;
         la.lab = w.lab;
+        la.Sall = w.Sall;
         la.partial = w.partial;
         la.changed = w.changed;
         la.zero_ints = w.counts_b;
-        la.n_zero_ints = C;
+        la.n_zero_ints = C + 1;
         la.lab_final = w.lab_final;
         la.offsets = w.offsets;
         la.ghat = w.ghat;
@@ -497,6 +532,13 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.coef64 = w.coef64;
         la.src_index = w.src_index;
         la.snorm_max = w.snorm_max;
+        la.split = w.split;
+        la.k_in_lds = landmark_k_in_lds(dev, ell, C, la.grid) ? 1 : 0;
+        la.trace = (i == 0 && info && info->landmark_trace) ? w.trace : nullptr;
+        la.barrier = w.barrier;
+        la.colmin = w.colmin;
+        la.error = w.lm_error;
+        if (la.trace) KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
         KKM_TRY(tm.begin());
         KKM_TRY(launch_landmark_phase(la, dtype, dev, s));
         KKM_TRY(tm.end(kPhLandmark));
@@ -512,6 +554,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sv.self = w.ghat;
         sv.segabs = w.segabs;
         sv.snorm_max = w.snorm_max;
+        sv.split = w.split;
         sv.C = C;
 
         DistArgs da{};
@@ -529,12 +572,14 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         da.refine_list = w.refine_list;
         da.refine_count = w.refine_counts + i;
         da.nonfinite = w.flags;
+        da.colmin = w.colmin;
+        da.n_support = ell;
         KKM_TRY(tm.begin());
         KKM_TRY(launch_dist(da, dev, s));
         KKM_TRY(tm.end(kPhDist));
         if (!dist_is_fp64(da)) {
             KKM_TRY(tm.begin());
-            KKM_TRY(launch_refine(da, dev, s));
+            KKM_TRY(launch_refine(da, dev, s, ell));
             KKM_TRY(tm.end(kPhRefine));
         }
 
@@ -556,27 +601,37 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.ldD = P.nmax;
         sa.Erow = w.Erow;
         sa.sup = sv;
-        sa.mpart_v = w.mpart_v;
-        sa.mpart_i = w.mpart_i;
-        sa.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(P.nchunk, (bv.n + 2047) / 2048));
-        sa.cand_total = w.flags + 1;
+        sa.nchunk = select_chunks(bv.n);
+        sa.mpart_c = w.mpart_c;
+        sa.colmin = w.colmin;
+        sa.cand_q = w.cand_q;
+        sa.cand_j = w.cand_j;
+        sa.cand_v = w.cand_v;
+        sa.cand_count = w.counts_b + C;
+        sa.cand_cap = (int32_t)P.cand_cap;
+        sa.gpart_v = w.gpart_v;
+        sa.gpart_i = w.gpart_i;
+
         sa.info_bmed = w.info + (size_t)i * C;
         sa.info_bcnt = w.info + (size_t)(P.B + i) * C;
         sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
         KKM_TRY(tm.begin());
-        KKM_TRY(launch_members(sa, s));
-        KKM_TRY(launch_batch_medoids(sa, dist_is_fp64(da), s));
-        KKM_TRY(launch_merge(sa, s));
+        sa.cand_total = w.flags + 1;
+        KKM_TRY(launch_select(sa, dist_is_fp64(da), dev, s));
         KKM_TRY(tm.end(kPhSelect));
     }
     KKM_TRY(launch_model_from_medoids(model, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
 
     std::vector<int32_t> updates(P.B), refined(P.B), flags(2);
+    int32_t lm_err = 0;
+    KKM_HIP(hipMemcpyAsync(&lm_err, w.lm_error, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     std::vector<int64_t> infos((size_t)3 * P.B * C);
     KKM_HIP(hipMemcpyAsync(updates.data(), w.updates, sizeof(int32_t) * P.B, hipMemcpyDeviceToHost, s));
     KKM_HIP(hipMemcpyAsync(refined.data(), w.refine_counts, sizeof(int32_t) * P.B, hipMemcpyDeviceToHost, s));
     KKM_HIP(hipMemcpyAsync(flags.data(), w.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
     KKM_HIP(hipMemcpyAsync(infos.data(), w.info, sizeof(int64_t) * infos.size(), hipMemcpyDeviceToHost, s));
+    if (info && info->landmark_trace)
+        KKM_HIP(hipMemcpyAsync(info->landmark_trace, w.trace, sizeof(int64_t) * 64, hipMemcpyDeviceToHost, s));
     KKM_HIP(hipStreamSynchronize(s));
     model->used = C;
     (void)es;
@@ -612,6 +667,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         info->ms_refine = ms[kPhRefine];
         info->ms_select = ms[kPhSelect];
     }
+    if (lm_err) return fail(KKM_ERR_INTERNAL, "a landmark-loop barrier wait exceeded its cap");
     if (flags[0]) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
     return KKM_OK;
 }

@@ -2,6 +2,7 @@
 // and the model lifecycle (create / load / export / free).
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -44,6 +45,21 @@ kkm_status device_info(DeviceInfo* out) {
         cache[dev] = di;
     }
     *out = cache[dev];
+    return KKM_OK;
+}
+
+kkm_status allow_dynamic_lds(const void* fn, size_t bytes) {
+    if (bytes <= 65536) return KKM_OK;
+    // raise a kernel's dynamic-LDS limit once per device and kernel, to the largest size asked for
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> raised;
+    int dev = 0;
+    KKM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& have = raised[{dev, fn}];
+    if (bytes <= have) return KKM_OK;
+    KKM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    have = bytes;
     return KKM_OK;
 }
 
@@ -182,6 +198,7 @@ kkm_status kkm_model_create(const kkm_kernel* kernel, int64_t d, int32_t C, int6
         m->self = c.take<double>(C);
         m->segabs = c.take<double>(C);
         m->snorm_max = c.take<float>(1);
+        m->split = c.take<int32_t>(5);
         m->counts = c.take<int64_t>(C);
         m->medoid_index = c.take<int64_t>(C);
     };

@@ -24,6 +24,7 @@ constexpr float kU32 = 5.9604645e-8f;  // unit roundoff of float
 // linear / RBF with the sample row held in registers (DP = padded length)
 template <typename TI, typename TC, int DP>
 struct EvalDot {
+    static constexpr bool kPerLaneRows = false;
     TC x[DP];
     TC qn, kqq;
     const TI* rows;
@@ -89,6 +90,7 @@ struct EvalDot {
 // any kernel type in FP64, rows read from memory (RMSD rows centred)
 template <typename TI>
 struct EvalGeneric64 {
+    static constexpr bool kPerLaneRows = true;
     const TI* xr;
     const TI* rows;
     int64_t dpad;
@@ -114,34 +116,28 @@ template <typename TI, typename TC, int DP> struct TcOf<EvalDot<TI, TC, DP>> { u
 template <typename TI> struct TcOf<EvalGeneric64<TI>> { using type = double; };
 
 // ----------------------------------------------------------------------------- tile kernel
-template <class Ev>
+// LPQ lanes per sample: a workgroup owns QT = 64 / LPQ samples; lane (ql, part) takes the support
+// rows l = lo + part, lo + part + LPQ, ... of every segment, and the LPQ partial sums are combined
+// by a fixed xor-butterfly, so the result does not depend on timing.
+template <class Ev, int LPQ>
 __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
     using TC = typename TcOf<Ev>::type;
+    constexpr int QT = 64 / LPQ;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    TC* Dl = reinterpret_cast<TC*>(smem_raw);      // [C][64]
-    __shared__ float Ew[4][64];
+    TC* Dl = reinterpret_cast<TC*>(smem_raw);      // [C][QT]
+    __shared__ float Ew[4][QT];
     __shared__ int jb[5];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+    const int ql = lane % QT, part = lane / QT;
+    const int64_t q = (int64_t)blockIdx.x * QT + ql;
     const bool active = q < a.q.n;
     const int C = a.sup.C;
     const int32_t* off = a.sup.offsets;
 
-    if (threadIdx.x < 5) {
-        const int t = threadIdx.x;
-        const int64_t ns = off[C];
-        int j = 0;
-        if (t == 4) {
-            j = C;
-        } else if (t > 0) {
-            const int64_t target = (ns * t + 3) / 4;
-            while (j < C && off[j] < target) ++j;
-        }
-        jb[t] = j;
-    }
+    if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
     Ev ev;
     const bool ok = ev.load(a, active ? q : 0);
-    if (active && !ok) atomicOr(a.nonfinite, 1);
+    if (active && part == 0 && !ok) atomicOr(a.nonfinite, 1);
     __syncthreads();
 
     float emax = 0.0f;
@@ -149,10 +145,12 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
     for (int j = j0; j < j1; ++j) {
         const int lo = off[j], hi = off[j + 1];
         TC acc = TC(0);
-        for (int l = lo; l < hi; ++l) {
+        for (int l = lo + part; l < hi; l += LPQ) {
             const TC coef = sizeof(TC) == 8 ? (TC)a.sup.coef64[l] : (TC)a.sup.coef32[l];
             acc = fma(coef, ev.eval(l), acc);
         }
+        if constexpr (LPQ >= 2) acc += __shfl_xor(acc, QT, 64);
+        if constexpr (LPQ >= 4) acc += __shfl_xor(acc, 2 * QT, 64);
         const double g = a.sup.self[j];
         TC D;
         if (hi > lo && g < kInf) {
@@ -161,17 +159,17 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
         } else {
             D = (TC)kInf;
         }
-        Dl[j * 64 + lane] = D;
+        if (part == 0) Dl[j * QT + ql] = D;
     }
-    Ew[wave][lane] = emax;
+    if (part == 0) Ew[wave][ql] = emax;
     __syncthreads();
 
-    if (wave == 0 && active) {
-        const float E = fmaxf(fmaxf(Ew[0][lane], Ew[1][lane]), fmaxf(Ew[2][lane], Ew[3][lane]));
+    const float E = fmaxf(fmaxf(Ew[0][ql], Ew[1][ql]), fmaxf(Ew[2][ql], Ew[3][ql]));
+    if (wave == 0 && part == 0 && active) {
         TC best = (TC)kInf, second = (TC)kInf;
         int bj = 0;
         for (int j = 0; j < C; ++j) {
-            const TC D = Dl[j * 64 + lane];
+            const TC D = Dl[j * QT + ql];
             if (D < best) { second = best; best = D; bj = j; }
             else if (D < second) { second = D; }
         }
@@ -188,19 +186,102 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
             a.refine_list[pos] = (int32_t)q;
         }
     }
-    if (a.Dt && active) {
+    if (a.Dt) {
+        // store the tile and lower each column's running minimum of D + E (order-independent)
         TC* Dt = static_cast<TC*>(static_cast<void*>(a.Dt));
-        for (int j = wave; j < C; j += 4) Dt[(int64_t)j * a.ldD + q] = Dl[j * 64 + lane];
+        for (int j = wave; j < C; j += 4) {
+            const TC D = Dl[j * QT + ql];
+            if (active && part == 0) Dt[(int64_t)j * a.ldD + q] = D;
+            if (a.colmin) {
+                double v = (active && part == 0) ? (double)D + (double)E : kInf;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+                if (lane == 0 && v < kInf) atomicMin(a.colmin + j, ord_enc(v));
+            }
+        }
     }
 }
 
 // ----------------------------------------------------------------------------- FP64 re-decision
-template <typename TI>
+// One wavefront per listed row: lanes evaluate a_l K(x, s_l) in FP64 for 256 support rows at a
+// time into LDS, each lane then adds the part of its clusters' segments (in row order), and the
+// best / second-best cluster is found by a wave reduction (lowest index on ties).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename TI, int DP>
 __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
-    __shared__ double Kv[1024];
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    double* facc = reinterpret_cast<double*>(smem_raw);   // [C]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int C = a.sup.C;
+    double* Kv = reinterpret_cast<double*>(smem_raw) + (size_t)wave * (256 + C);   // [256]
+    double* facc = Kv + 256;                                                       // [C]
+    const int32_t* off = a.sup.offsets;
+    const int64_t ns = off[C];
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    const int count = *a.refine_count;
+    for (int i = blockIdx.x * 4 + wave; i < count; i += gridDim.x * 4) {
+        const int64_t q = a.refine_list[i];
+        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        for (int j = lane; j < C; j += 64) facc[j] = 0.0;
+        for (int64_t base = 0; base < ns; base += 256) {
+            const int lim = (int)min<int64_t>(256, ns - base);
+            for (int t = lane; t < lim; t += 64)
+                Kv[t] = a.sup.coef64[base + t] * k64p<DP>(a.ks, xr, rows + (base + t) * a.sup.dpad);
+            wave_sync_lds();
+            for (int j = lane; j < C; j += 64) {
+                const int64_t lo = max<int64_t>(off[j], base), hi = min<int64_t>(off[j + 1], base + lim);
+                double s = facc[j];
+                for (int64_t l = lo; l < hi; ++l) s += Kv[l - base];
+                facc[j] = s;
+            }
+            wave_sync_lds();
+        }
+        const double kqq = kself64(a.ks, xr);
+        double b1 = kInf, b2 = kInf;
+        int i1 = C;
+        for (int j = lane; j < C; j += 64) {
+            const double g = a.sup.self[j];
+            const double D = (off[j + 1] > off[j] && g < kInf) ? kqq - 2.0 * facc[j] + g : kInf;
+            if (D < b1) { b2 = b1; b1 = D; i1 = j; }
+            else if (D < b2) { b2 = D; }
+        }
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double c1 = __shfl_xor(b1, o, 64), c2 = __shfl_xor(b2, o, 64);
+            const int j1 = __shfl_xor(i1, o, 64);
+            if (c1 < b1 || (c1 == b1 && j1 < i1)) {
+                b2 = fmin(b1, c2);
+                b1 = c1;
+                i1 = j1;
+            } else {
+                b2 = fmin(b2, c1);
+            }
+        }
+        if (lane == 0) {
+            a.labels[q] = i1 < C ? i1 : 0;
+            if (a.best) a.best[q] = b1;
+            if (a.gap) {
+                const double scale = fmax(fmax(fabs(b1), fabs(b2)), fabs(kqq));
+                a.gap[q] = b2 < kInf ? (float)((b2 - b1) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
+            }
+        }
+        wave_sync_lds();
+    }
+}
+
+// A whole block per listed row (supports of hundreds of rows and more): 256 support rows per step,
+// one per thread, then per-cluster sums in row order and a block reduction of best / second best.
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void refine_block_kernel(DistArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int C = a.sup.C;
+    double* Kv = reinterpret_cast<double*>(smem_raw);   // [256]
+    double* facc = Kv + 256;                              // [C]
+    __shared__ double rb1[256], rb2[256];
+    __shared__ int ri1[256];
     const int32_t* off = a.sup.offsets;
     const int64_t ns = off[C];
     const TI* rows = static_cast<const TI*>(a.sup.rows);
@@ -209,11 +290,12 @@ __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
         const int64_t q = a.refine_list[i];
         const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
         for (int j = threadIdx.x; j < C; j += blockDim.x) facc[j] = 0.0;
-        for (int64_t base = 0; base < ns; base += 1024) {
-            const int64_t lim = min<int64_t>(1024, ns - base);
+        for (int64_t base = 0; base < ns; base += 256) {
+            const int lim = (int)min<int64_t>(256, ns - base);
             __syncthreads();
-            for (int t = threadIdx.x; t < lim; t += blockDim.x)
-                Kv[t] = a.sup.coef64[base + t] * k64(a.ks, xr, rows + (base + t) * a.sup.dpad);
+            if ((int)threadIdx.x < lim)
+                Kv[threadIdx.x] = a.sup.coef64[base + threadIdx.x] *
+                                  k64p<DP>(a.ks, xr, rows + (base + threadIdx.x) * a.sup.dpad);
             __syncthreads();
             for (int j = threadIdx.x; j < C; j += blockDim.x) {
                 const int64_t lo = max<int64_t>(off[j], base), hi = min<int64_t>(off[j + 1], base + lim);
@@ -223,21 +305,45 @@ __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const double kqq = kself64(a.ks, xr);
-            double best = kInf, second = kInf;
-            int bj = 0;
-            for (int j = 0; j < C; ++j) {
-                const double g = a.sup.self[j];
-                const double D = (off[j + 1] > off[j] && g < kInf) ? kqq - 2.0 * facc[j] + g : kInf;
-                if (D < best) { second = best; best = D; bj = j; }
-                else if (D < second) { second = D; }
+        const double kqq = kself64(a.ks, xr);
+        double b1 = kInf, b2 = kInf;
+        int i1 = C;
+        for (int j = threadIdx.x; j < C; j += blockDim.x) {
+            const double g = a.sup.self[j];
+            const double D = (off[j + 1] > off[j] && g < kInf) ? kqq - 2.0 * facc[j] + g : kInf;
+            if (D < b1) { b2 = b1; b1 = D; i1 = j; }
+            else if (D < b2) { b2 = D; }
+        }
+        rb1[threadIdx.x] = b1;
+        rb2[threadIdx.x] = b2;
+        ri1[threadIdx.x] = i1;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                const double c1 = rb1[threadIdx.x + w], c2 = rb2[threadIdx.x + w];
+                const int j1 = ri1[threadIdx.x + w];
+                double x1 = rb1[threadIdx.x], x2 = rb2[threadIdx.x];
+                int y1 = ri1[threadIdx.x];
+                if (c1 < x1 || (c1 == x1 && j1 < y1)) {
+                    x2 = fmin(x1, c2);
+                    x1 = c1;
+                    y1 = j1;
+                } else {
+                    x2 = fmin(x2, c1);
+                }
+                rb1[threadIdx.x] = x1;
+                rb2[threadIdx.x] = x2;
+                ri1[threadIdx.x] = y1;
             }
-            a.labels[q] = bj;
-            if (a.best) a.best[q] = best;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double v1 = rb1[0], v2 = rb2[0];
+            a.labels[q] = ri1[0] < C ? ri1[0] : 0;
+            if (a.best) a.best[q] = v1;
             if (a.gap) {
-                const double scale = fmax(fmax(fabs(best), fabs(second)), fabs(kqq));
-                a.gap[q] = second < kInf ? (float)((second - best) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
+                const double scale = fmax(fmax(fabs(v1), fabs(v2)), fabs(kqq));
+                a.gap[q] = v2 < kInf ? (float)((v2 - v1) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
             }
         }
         __syncthreads();
@@ -260,18 +366,34 @@ __global__ __launch_bounds__(256) void sum_partial_kernel(const double* __restri
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
-template <class Ev>
-kkm_status launch_dist_ev(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+template <class Ev, int LPQ>
+kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     using TC = typename TcOf<Ev>::type;
-    const size_t lds = sizeof(TC) * (size_t)a.sup.C * 64;
+    constexpr int QT = 64 / LPQ;
+    const size_t lds = sizeof(TC) * (size_t)a.sup.C * QT;
     if (lds > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile (C=" + std::to_string(a.sup.C) + ")");
-    const void* fn = reinterpret_cast<const void*>(&dist_kernel<Ev>);
-    if (lds > 48 * 1024) KKM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const unsigned blocks = (unsigned)((a.q.n + 63) / 64);
-    hipLaunchKernelGGL(dist_kernel<Ev>, dim3(blocks), dim3(256), lds, s, a);
+    const void* fn = reinterpret_cast<const void*>(&dist_kernel<Ev, LPQ>);
+    KKM_TRY(allow_dynamic_lds(fn, lds));
+    const unsigned blocks = (unsigned)((a.q.n + QT - 1) / QT);
+    hipLaunchKernelGGL((dist_kernel<Ev, LPQ>), dim3(blocks), dim3(256), lds, s, a);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
+}
+
+// Lanes per sample: more when there are few 64-sample tiles for the device and the segments are
+// long enough to split.
+template <class Ev>
+kkm_status launch_dist_ev(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    const int64_t tiles = (a.q.n + 63) / 64;
+    const double seg = (double)a.n_support / std::max(1, a.sup.C);
+    int lpq = 1;
+    // only the evaluator that reads support rows per lane gains: the register-row evaluator streams
+    // wave-uniform support rows through the scalar cache, which split lanes would turn into gathers
+    if (Ev::kPerLaneRows && tiles < 2 * (int64_t)dev.num_cus && seg >= 2.0) lpq = seg >= 6.0 ? 4 : 2;
+    if (lpq == 4) return launch_dist_lpq<Ev, 4>(a, dev, s);
+    if (lpq == 2) return launch_dist_lpq<Ev, 2>(a, dev, s);
+    return launch_dist_lpq<Ev, 1>(a, dev, s);
 }
 
 template <typename TI, typename TC>
@@ -291,7 +413,7 @@ kkm_status launch_dist_dot(const DistArgs& a, const DeviceInfo& dev, hipStream_t
 
 bool dist_is_fp64(const DistArgs& a) { return a.precision == KKM_PREC_FP64 || a.ks.type == KKM_KERNEL_RMSD; }
 
-size_t dist_lds_bytes(const DistArgs& a) { return (dist_is_fp64(a) ? 8 : 4) * (size_t)a.sup.C * 64; }
+size_t dist_lds_bytes(const DistArgs& a) { return (dist_is_fp64(a) ? 8 : 4) * (size_t)a.sup.C * 64; }  // LPQ = 1
 
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     if (a.q.n <= 0) return KKM_OK;
@@ -303,16 +425,27 @@ kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) 
     return f64 ? launch_dist_dot<double, float>(a, dev, s) : launch_dist_dot<float, float>(a, dev, s);
 }
 
-kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s, int64_t n_support) {
     if (a.q.n <= 0) return KKM_OK;
-    const size_t lds = sizeof(double) * (size_t)a.sup.C;
-    const unsigned blocks = (unsigned)std::min<int64_t>(a.q.n, 2 * (int64_t)dev.num_cus);
-    if (a.dtype == KKM_F64)
-        hipLaunchKernelGGL(refine_kernel<double>, dim3(blocks), dim3(256), lds, s, a);
-    else
-        hipLaunchKernelGGL(refine_kernel<float>, dim3(blocks), dim3(256), lds, s, a);
-    KKM_HIP(hipGetLastError());
-    return KKM_OK;
+    const bool per_block = n_support > 256;   // large supports: a whole block per listed row
+    const size_t lds = per_block ? sizeof(double) * (256 + (size_t)a.sup.C) : sizeof(double) * 4 * (256 + (size_t)a.sup.C);
+    const unsigned blocks = per_block ? (unsigned)std::min<int64_t>(a.q.n, 4 * (int64_t)dev.num_cus)
+                                      : (unsigned)std::min<int64_t>((a.q.n + 3) / 4, 2 * (int64_t)dev.num_cus);
+    return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
+        if (per_block) {
+            if (a.dtype == KKM_F64)
+                hipLaunchKernelGGL((refine_block_kernel<double, DP>), dim3(blocks), dim3(256), lds, s, a);
+            else
+                hipLaunchKernelGGL((refine_block_kernel<float, DP>), dim3(blocks), dim3(256), lds, s, a);
+        } else {
+            if (a.dtype == KKM_F64)
+                hipLaunchKernelGGL((refine_kernel<double, DP>), dim3(blocks), dim3(256), lds, s, a);
+            else
+                hipLaunchKernelGGL((refine_kernel<float, DP>), dim3(blocks), dim3(256), lds, s, a);
+        }
+        KKM_HIP(hipGetLastError());
+        return KKM_OK;
+    });
 }
 
 kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s) {

@@ -1,8 +1,9 @@
-// Landmark phase of one mini-batch, as one cooperative kernel:
+// Landmark phase of one mini-batch:
 //
-//   1. the landmark kernel block K_LL = K(x_l, x_m), FP64, each workgroup its own rows;
-//   2. the initial landmark labels: given, or the nearest global medoid (Eq. 8, with K(m,m));
-//   3. the landmark loop (Eq. 14-17 restricted to the landmarks):
+//   1. the landmark kernel block K_LL = K(x_l, x_m) in FP64 (landmark_block_kernel, 16 x 16 tiles);
+//   2. the initial landmark labels: given, or the nearest global medoid (Eq. 8, with K(m,m))
+//      (landmark_init_kernel, one workgroup per landmark);
+//   3. one cooperative kernel for the landmark loop (Eq. 14-17 restricted to the landmarks):
 //        counting sort of the landmarks by label  -> CSR segments L_j, c_j = |L_j|
 //        S[m][j]  = sum_{m' in L_j} K(l_m, l_m')                (so f^(l_m, j) = S / c_j, Eq. 17)
 //        g^_j     = 1/c_j^2 sum_{m in L_j} S[m][j]              (Eq. 16)
@@ -16,24 +17,19 @@
 //
 // Every sum has a fixed order that depends only on the labels (CSR order within a segment, row
 // order, then workgroup order), so results are bitwise repeatable.  Cross-workgroup data is
-// published with a release fence before the grid barrier and read with agent-scope atomic loads.
-#include <hip/hip_cooperative_groups.h>
+// published with a release fence before the grid barrier and read after an acquire fence.
+#include <cstdlib>
 
 #include "kkm_internal.hpp"
 #include "kkm_launch.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace kkm {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ T ld_agent(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 struct LdsLayout {
+    double* K;         // [R][ell] own rows of the landmark block (when staged in LDS)
+    double* red;       // [max(256, C)] partial-sum scratch
     int32_t* lbl;      // [ell]
     int32_t* perm;     // [ell]
     int32_t* off;      // [C+1]
@@ -42,13 +38,22 @@ struct LdsLayout {
     double* S;         // [R][C]
     double* gh;        // [C]
     double* kself;     // [R]
+    int32_t* qoff;     // [C+1] first 64-element chunk of each segment (chunks per row: qoff[C])
+    double* part;      // [R][nq_max] chunk partial sums, nq_max = ceil(ell/64) + C
+    double* kall;      // [ell] K(l, l) of every landmark
+    int32_t* nlab;     // [ell] labels after an update
+    int32_t* chg;      // [ell + 1] changed landmarks in index order; chg[ell] = their number
+    int32_t* cnt;      // [C] landmarks per cluster
+    double* rcnt;      // [C] 1 / c_j
 };
 
 __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R) {
+__host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R, bool k_in_lds) {
     const int nchunks = (ell + 63) / 64;
     size_t b = 0;
+    if (k_in_lds) b += sizeof(double) * (size_t)R * ell;
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)(C > 256 ? C : 256);
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (C + 1);
@@ -57,13 +62,23 @@ __host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R) {
     b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)R * C;
     b = (b + 15) & ~size_t(15); b += sizeof(double) * C;
     b = (b + 15) & ~size_t(15); b += sizeof(double) * R;
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (C + 1);
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)R * ((ell + 63) / 64 + C);
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * ell;
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (ell + 1);
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * C;
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * C;
     return (b + 15) & ~size_t(15);
 }
 
-__device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R) {
+__device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool k_in_lds) {
     const int nchunks = (ell + 63) / 64;
     LdsLayout L;
     size_t b = 0;
+    L.K = reinterpret_cast<double*>(base);
+    if (k_in_lds) b += sizeof(double) * (size_t)R * ell;
+    b = al16(b); L.red = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)(C > 256 ? C : 256);
     b = al16(b); L.lbl = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.perm = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.off = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (C + 1);
@@ -71,7 +86,14 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R) {
     b = al16(b); L.chunk = reinterpret_cast<uint16_t*>(base + b); b += sizeof(uint16_t) * (size_t)nchunks * C;
     b = al16(b); L.S = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)R * C;
     b = al16(b); L.gh = reinterpret_cast<double*>(base + b); b += sizeof(double) * C;
-    b = al16(b); L.kself = reinterpret_cast<double*>(base + b);
+    b = al16(b); L.kself = reinterpret_cast<double*>(base + b); b += sizeof(double) * R;
+    b = al16(b); L.qoff = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (C + 1);
+    b = al16(b); L.part = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)R * ((ell + 63) / 64 + C);
+    b = al16(b); L.kall = reinterpret_cast<double*>(base + b); b += sizeof(double) * ell;
+    b = al16(b); L.nlab = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
+    b = al16(b); L.chg = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (ell + 1);
+    b = al16(b); L.cnt = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * C;
+    b = al16(b); L.rcnt = reinterpret_cast<double*>(base + b);
     return L;
 }
 
@@ -91,7 +113,7 @@ __device__ void csr_sort(const LdsLayout& L, int ell, int C) {
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         while (remaining) {
             const int leader = __ffsll((unsigned long long)remaining) - 1;
-            const int cur = __shfl(lab, leader, 64);
+            const int cur = __builtin_amdgcn_readlane(lab, leader);
             const uint64_t mask = __ballot(valid && lab == cur);
             if (valid && lab == cur) L.rank[m] = (uint8_t)__popcll(mask & below);
             if (lane == 0) L.chunk[ch * C + cur] = (uint16_t)__popcll(mask);
@@ -130,12 +152,192 @@ __device__ void csr_sort(const LdsLayout& L, int ell, int C) {
         const int lab = L.lbl[m];
         L.perm[L.off[lab] + L.chunk[(m >> 6) * C + lab] + L.rank[m]] = m;
     }
+    // 64-element chunks of every segment: qoff = exclusive scan of ceil(len_j / 64) (first wave)
+    if (wave == 0) {
+        int carry = 0;
+        for (int base = 0; base < C; base += 64) {
+            const int j = base + lane;
+            int v = (j < C) ? (L.off[j + 1] - L.off[j] + 63) / 64 : 0;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int t = __shfl_up(v, o, 64);
+                if (lane >= o) v += t;
+            }
+            if (j < C) L.qoff[j + 1] = carry + v;
+            carry += __shfl(v, 63, 64);
+        }
+        if (lane == 0) L.qoff[0] = 0;
+    }
     __syncthreads();
 }
 
+// S[r][j] = sum over segment j (CSR of L.lbl) of own row r, from scratch: every 64-element chunk of a
+// segment is summed in order by one thread, then the chunk sums of each (row, segment) in order.
+// Also sets L.cnt.  Whole workgroup; expects csr_sort(L) done.
+__device__ void full_sums(const LdsLayout& L, const double* Krows, int nr, int ell, int C) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nq = L.qoff[C];
+    for (int p = tid; p < nr * nq; p += nt) {
+        const int r = p / nq, qi = p - r * nq;
+        int lo_j = 0, hi_j = C;                 // segment j with qoff[j] <= qi < qoff[j+1]
+        while (hi_j - lo_j > 1) {
+            const int mid = (lo_j + hi_j) >> 1;
+            if (L.qoff[mid] <= qi) lo_j = mid; else hi_j = mid;
+        }
+        const int j = lo_j;
+        const int k0 = L.off[j] + (qi - L.qoff[j]) * 64;
+        const int k1 = min(L.off[j + 1], k0 + 64);
+        const double* Kr = Krows + (int64_t)r * ell;
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = k0; k < k1; ++k) s += Kr[L.perm[k]];
+        L.part[p] = s;
+    }
+    __syncthreads();
+    for (int p = tid; p < nr * C; p += nt) {
+        const int r = p / C, j = p - r * C;
+        double s = 0.0;
+        for (int qi = L.qoff[j]; qi < L.qoff[j + 1]; ++qi) s += L.part[r * nq + qi];
+        L.S[p] = s;
+    }
+    for (int j = tid; j < C; j += nt) L.cnt[j] = L.off[j + 1] - L.off[j];
+    __syncthreads();
+}
+
+// Barrier over the co-resident workgroups of the cooperative launch: a monotonically increasing
+// arrival counter (cleared by the block kernel launched just before on the same stream).  Writes are
+// released at agent scope before arriving; after the wait, an acquire fence drops stale cache lines
+// so that plain loads see the other workgroups' writes.  The wait is bounded: past kSpinCap polls
+// the workgroup records an error and proceeds, so the kernel always terminates.
+constexpr unsigned kSpinCap = 1u << 26;
+
+__device__ __forceinline__ void grid_barrier(const LandmarkArgs& a, unsigned& target) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    target += gridDim.x;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (__hip_atomic_load(a.barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > kSpinCap) {
+                atomicOr(a.error, 1);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Wall-clock stamp of workgroup 0 (profiling aid): slot 0 holds the count.
+__device__ __forceinline__ void stamp(const LandmarkArgs& a) {
+    if (a.trace && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t n = a.trace[0];
+        if (n < 63) {
+            a.trace[1 + n] = (int64_t)wall_clock64();
+            a.trace[0] = n + 1;
+        }
+    }
+}
+
+// 1. K_LL in FP64, one 32 x 32 tile per workgroup (4 entries per thread), the two row sets staged
+//    in LDS as doubles.  Linear and RBF kernels are symmetric: only tiles on or above the diagonal
+//    are evaluated and mirrored.  Block 0 also clears the loop's counters.
+template <typename TI>
+__global__ __launch_bounds__(256) void landmark_block_kernel(LandmarkArgs a, int tiles) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ell = a.ell;
+    const bool sym = a.ktype != KKM_KERNEL_RMSD;
+    int tr = blockIdx.y, tc = blockIdx.x;
+    if (sym) {   // blockIdx.x enumerates the upper-triangular tiles (tr <= tc)
+        int t = blockIdx.x;
+        tr = 0;
+        while (t >= tiles - tr) { t -= tiles - tr; ++tr; }
+        tc = tr + t;
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        for (int i = threadIdx.x; i <= a.max_updates; i += blockDim.x) a.changed[i] = 0;
+        for (int i = threadIdx.x; i < a.n_zero_ints; i += blockDim.x) a.zero_ints[i] = 0;
+        for (int i = threadIdx.x; i < a.C; i += blockDim.x) a.colmin[i] = ~0ull;
+        if (threadIdx.x == 0) {
+            *a.barrier = 0u;
+            *a.error = 0;
+            *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
+        }
+    }
+    double* A = reinterpret_cast<double*>(smem);          // [32][d]
+    double* Bm = A + 32 * a.d;                             // [32][d]
+    const int r0 = tr * 32, c0 = tc * 32;
+    const TI* X = static_cast<const TI*>(a.X);
+    for (int64_t i = threadIdx.x; i < 32 * a.d; i += blockDim.x) {
+        const int r = (int)(i / a.d);
+        const int64_t c = i % a.d;
+        const int ra = min(ell - 1, r0 + r), rb = min(ell - 1, c0 + r);
+        A[i] = (double)X[(a.base + (int64_t)a.lm[ra] * a.stride) * a.d + c];
+        Bm[i] = (double)X[(a.base + (int64_t)a.lm[rb] * a.stride) * a.d + c];
+    }
+    __syncthreads();
+    const KSpec ks{a.ktype, a.n_atoms, a.d, a.inv2s2};
+    const int tx = threadIdx.x & 31, ty0 = threadIdx.x >> 5;   // rows ty0, ty0 + 8, ty0 + 16, ty0 + 24
+    for (int k = 0; k < 4; ++k) {
+        const int ty = ty0 + 8 * k;
+        const int r = r0 + ty, c = c0 + tx;
+        if (r < ell && c < ell && (!sym || tr < tc || ty <= tx)) {
+            const double v = k64(ks, A + ty * a.d, Bm + tx * a.d);
+            a.Kbuf[(int64_t)r * ell + c] = v;
+            if (sym) a.Kbuf[(int64_t)c * ell + r] = v;
+        }
+    }
+}
+
+// 2. Initial label of one landmark: given, or argmin_j K(x,x) - 2 K(x, m_j) + K(m_j, m_j) (Eq. 8)
+//    over the clusters with a medoid, lowest j on ties.
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void landmark_init_kernel(LandmarkArgs a) {
+    const int r = blockIdx.x;
+    if (a.init_mode == 0) {
+        if (threadIdx.x == 0) a.lab[r] = a.lab_init[r];
+        return;
+    }
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* x = reinterpret_cast<double*>(smem);          // [d]
+    const TI* X = static_cast<const TI*>(a.X);
+    const TI* xr = X + (a.base + (int64_t)a.lm[r] * a.stride) * a.d;
+    for (int64_t c = threadIdx.x; c < a.d; c += blockDim.x) x[c] = (double)xr[c];
+    __syncthreads();
+    const KSpec ks{a.ktype, a.n_atoms, a.d, a.inv2s2};
+    const double kxx = kself64(ks, x);
+    const TI* M = static_cast<const TI*>(a.M);
+    double bv = kInf;
+    int bj = a.C;
+    for (int j = threadIdx.x; j < a.C; j += blockDim.x) {
+        const double ms = a.Mself[j];
+        if (!(ms < kInf)) continue;
+        const double dj = kxx - 2.0 * k64p<DP>(ks, x, M + (int64_t)j * a.Mpad) + ms;
+        if (dj < bv) { bv = dj; bj = j; }
+    }
+    __shared__ double sv[256];
+    __shared__ int si[256];
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bj;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double v2 = sv[threadIdx.x + w];
+            const int i2 = si[threadIdx.x + w];
+            if (v2 < sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.lab[r] = si[0] < a.C ? si[0] : 0;
+}
+
+// 3-4. The landmark loop and the centroid support (cooperative launch, grid <= device CUs).
 template <typename TI>
 __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
-    cg::grid_group grid = cg::this_grid();
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
@@ -143,115 +345,131 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
     const int ell = a.ell, C = a.C;
     const int R = (ell + G - 1) / G;
     const int r0 = min(ell, wg * R), r1 = min(ell, r0 + R), nr = r1 - r0;
-    LdsLayout L = carve_lds(smem, ell, C, R);
+    const bool kl = a.k_in_lds != 0;
+    LdsLayout L = carve_lds(smem, ell, C, R, kl);
     const TI* X = static_cast<const TI*>(a.X);
     const KSpec ks{a.ktype, a.n_atoms, a.d, a.inv2s2};
     auto row = [&](int pos) { return X + (a.base + (int64_t)pos * a.stride) * a.d; };
+    double* Krows = a.Kbuf + (int64_t)r0 * ell;     // own row r at Krows + r * ell
+    unsigned target = 0;
 
-    if (wg == 0) {
-        for (int i = tid; i <= a.max_updates; i += nt) a.changed[i] = 0;
-        for (int i = tid; i < a.n_zero_ints; i += nt) a.zero_ints[i] = 0;
-        if (tid == 0) *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
+    stamp(a);
+    if (kl) {
+        for (int64_t i = tid; i < (int64_t)nr * ell; i += nt) L.K[i] = Krows[i];
+        Krows = L.K;
     }
-
-    // 1. own rows of the landmark block
-    for (int64_t idx = tid; idx < (int64_t)nr * ell; idx += nt) {
-        const int r = (int)(idx / ell), c = (int)(idx % ell);
-        a.Kbuf[(int64_t)(r0 + r) * ell + c] = k64(ks, row(a.lm[r0 + r]), row(a.lm[c]));
+    for (int m = tid; m < ell; m += nt) {
+        L.kall[m] = a.Kbuf[(int64_t)m * ell + m];
+        L.lbl[m] = a.lab[m];
     }
-    for (int r = tid; r < nr; r += nt) L.kself[r] = kself64(ks, row(a.lm[r0 + r]));
+    __syncthreads();
+    stamp(a);
 
-    // 2. initial labels of own rows
-    for (int r = tid; r < nr; r += nt) {
-        int lab = 0;
-        if (a.init_mode == 0) {
-            lab = a.lab_init[r0 + r];
-        } else {
-            const TI* x = row(a.lm[r0 + r]);
-            const TI* M = static_cast<const TI*>(a.M);
-            const double kxx = L.kself[r];
-            double best = kInf;
-            for (int j = 0; j < C; ++j) {
-                const double ms = a.Mself[j];
-                if (!(ms < kInf)) continue;
-                const double dj = kxx - 2.0 * k64(ks, x, M + (int64_t)j * a.Mpad) + ms;
-                if (dj < best) { best = dj; lab = j; }
-            }
-        }
-        a.lab[r0 + r] = lab;
-    }
-    __threadfence();
-    grid.sync();
+    csr_sort(L, ell, C);
+    full_sums(L, Krows, nr, ell, C);
+    stamp(a);
 
-    // 3. the landmark loop
-    int cur = 0, it = 0;
+    // One barrier per update: publish own rows of S and the partial g^ (buffers alternate between
+    // updates: a workgroup can only write a buffer again after the next barrier, which the others
+    // reach after their reads); then every workgroup reads all of S, forms g^ and decides every
+    // landmark's label (identical work everywhere).  Own rows of S then follow the label changes,
+    // incrementally in landmark order, or from scratch when many labels changed.
+    const int nsub = C < nt ? nt / C : 1;     // threads per cluster in the partial reduction
+    int it = 0;
     for (;;) {
-        const int32_t* labc = a.lab + (int64_t)cur * ell;
-        for (int i = tid; i < ell; i += nt) L.lbl[i] = ld_agent(labc + i);
-        __syncthreads();
-        csr_sort(L, ell, C);
-
-        // S[r][j] for own rows: short segments one lane each, long ones a whole wave
-        for (int r = wave; r < nr; r += nwaves) {
-            const double* Krow = a.Kbuf + (int64_t)(r0 + r) * ell;
-            for (int j = lane; j < C; j += 64) {
-                const int lo = L.off[j], hi = L.off[j + 1];
-                if (hi - lo < 64) {
-                    double s = 0.0;
-                    for (int k = lo; k < hi; ++k) s += Krow[L.perm[k]];
-                    L.S[r * C + j] = s;
-                }
-            }
-            for (int j = 0; j < C; ++j) {
-                const int lo = L.off[j], hi = L.off[j + 1];
-                if (hi - lo >= 64) {
-                    double s = 0.0;
-                    for (int k = lo + lane; k < hi; k += 64) s += Krow[L.perm[k]];
-                    s = wave_sum(s);
-                    if (lane == 0) L.S[r * C + j] = s;
-                }
-            }
-        }
-        __syncthreads();
-        // partial g^ of this workgroup, own rows in order
+        double* Sall = a.Sall + (int64_t)(it & 1) * ell * C;
+        double* partial = a.partial + (int64_t)(it & 1) * G * C;
+        for (int p = tid; p < nr * C; p += nt) Sall[(int64_t)r0 * C + p] = L.S[p];
         for (int j = tid; j < C; j += nt) {
             double acc = 0.0;
             for (int r = 0; r < nr; ++r)
                 if (L.lbl[r0 + r] == j) acc += L.S[r * C + j];
-            a.partial[(int64_t)wg * C + j] = acc;
+            partial[(int64_t)wg * C + j] = acc;
+            L.rcnt[j] = L.cnt[j] > 0 ? 1.0 / (double)L.cnt[j] : 0.0;
         }
-        __threadfence();
-        grid.sync();
+        grid_barrier(a, target);
+        stamp(a);
+        // g^_j = 1/c_j^2 sum_g partial[g][j]: nsub interleaved sub-sums per cluster, then in order
+        for (int p = tid; p < nsub * C; p += nt) {
+            const int j = p % C, sub = p / C;
+            double acc = 0.0;
+#pragma unroll 4
+            for (int g = sub; g < G; g += nsub) acc += partial[(int64_t)g * C + j];
+            L.red[p] = acc;
+        }
+        __syncthreads();
         for (int j = tid; j < C; j += nt) {
             double acc = 0.0;
-            for (int g = 0; g < G; ++g) acc += ld_agent(a.partial + (int64_t)g * C + j);
-            const double cj = (double)(L.off[j + 1] - L.off[j]);
+            for (int sub = 0; sub < nsub; ++sub) acc += L.red[sub * C + j];
+            const double cj = (double)L.cnt[j];
             L.gh[j] = cj > 0.0 ? acc / (cj * cj) : kInf;
         }
         __syncthreads();
+        stamp(a);
         if (it >= a.max_updates) break;
 
-        // Eq. 15 on own rows
-        int32_t* labn = a.lab + (int64_t)(1 - cur) * ell;
-        for (int r = tid; r < nr; r += nt) {
+        // Eq. 15 for every landmark
+        for (int m = tid; m < ell; m += nt) {
+            const double* Sm = Sall + (int64_t)m * C;
             double best = kInf;
-            int bj = L.lbl[r0 + r];
+            int bj = L.lbl[m];
             bool found = false;
             for (int j = 0; j < C; ++j) {
-                const int cnt = L.off[j + 1] - L.off[j];
-                if (cnt == 0) continue;
-                const double dj = L.kself[r] - 2.0 * L.S[r * C + j] / (double)cnt + L.gh[j];
+                if (L.cnt[j] == 0) continue;
+                const double dj = L.kall[m] - 2.0 * Sm[j] * L.rcnt[j] + L.gh[j];
                 if (!found || dj < best) { best = dj; bj = j; found = true; }
             }
-            labn[r0 + r] = bj;
-            if (bj != L.lbl[r0 + r]) atomicAdd(a.changed + it, 1);
+            L.nlab[m] = bj;
         }
-        __threadfence();
-        grid.sync();
+        __syncthreads();
+        // changed landmarks in index order (first wave)
+        if (wave == 0) {
+            int base_out = 0;
+            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            for (int c0 = 0; c0 < ell; c0 += 64) {
+                const int m = c0 + lane;
+                const bool ch = m < ell && L.nlab[m] != L.lbl[m];
+                const uint64_t mask = __ballot(ch);
+                if (ch) L.chg[base_out + __popcll(mask & below)] = m;
+                base_out += __popcll(mask);
+            }
+            if (lane == 0) L.chg[ell] = base_out;
+        }
+        __syncthreads();
+        const int nch = L.chg[ell];
         ++it;
-        if (ld_agent(a.changed + (it - 1)) == 0) break;
-        cur = 1 - cur;
+        if (nch == 0) break;
+        if ((int64_t)nch * C > ell) {
+            for (int m = tid; m < ell; m += nt) L.lbl[m] = L.nlab[m];
+            __syncthreads();
+            csr_sort(L, ell, C);
+            full_sums(L, Krows, nr, ell, C);
+        } else {
+            // S[r][j] -= K(r, m) for changes leaving j, += for changes entering j, in index order
+            for (int p = tid; p < nr * C; p += nt) {
+                const int r = p / C, j = p - r * C;
+                const double* Kr = Krows + (int64_t)r * ell;
+                double sv = L.S[p];
+                for (int t = 0; t < nch; ++t) {
+                    const int m = L.chg[t];
+                    if (L.lbl[m] == j) sv -= Kr[m];
+                    if (L.nlab[m] == j) sv += Kr[m];
+                }
+                L.S[p] = sv;
+            }
+            for (int t = tid; t < nch; t += nt) {
+                const int m = L.chg[t];
+                atomicSub(L.cnt + L.lbl[m], 1);
+                atomicAdd(L.cnt + L.nlab[m], 1);
+            }
+            __syncthreads();
+            for (int t = tid; t < nch; t += nt) L.lbl[L.chg[t]] = L.nlab[L.chg[t]];
+            __syncthreads();
+        }
+        stamp(a);
     }
+    // CSR of the final labels for the support
+    csr_sort(L, ell, C);
 
     // 4. outputs: final labels, segments, g^, and the support of the final centroids
     for (int r = tid; r < nr; r += nt) a.lab_final[r0 + r] = L.lbl[r0 + r];
@@ -262,7 +480,18 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             a.ghat[j] = cnt > 0 ? L.gh[j] : kInf;
             a.segabs[j] = cnt > 0 ? 1.0 : 0.0;
         }
+        if (tid < 5) {
+            // contiguous cluster runs holding about a quarter of the support each (distance pass)
+            int j = 0;
+            if (tid == 4) j = C;
+            else if (tid > 0) {
+                const int want = (ell * tid + 3) / 4;
+                while (j < C && L.off[j] < want) ++j;
+            }
+            a.split[tid] = j;
+        }
         if (tid == 0) *a.updates_out = it;
+        for (int m = tid; m < ell; m += nt) a.lab[ell + m] = L.lbl[m];   // final landmark labels
     }
     TI* sup = static_cast<TI*>(a.support);
     for (int k = wg * nt + tid; k < ell; k += G * nt) {
@@ -290,30 +519,65 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
 
 }  // namespace
 
-size_t landmark_lds_bytes_host(int ell, int C, int G) {
+size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds) {
     const int R = (ell + G - 1) / G;
-    return landmark_lds_bytes(ell, C, R);
+    return landmark_lds_bytes(ell, C, R, k_in_lds);
 }
 
 int landmark_grid(const DeviceInfo& dev, int ell) {
+    // at least 4 landmark rows per workgroup and at most KKM_LANDMARK_WGS workgroups (default 64):
+    // the loop is bound by its two grid barriers per update, whose cost grows with the grid
+    static int cap = [] {
+        const char* e = std::getenv("KKM_LANDMARK_WGS");
+        const int v = e ? std::atoi(e) : 0;
+        return v > 0 ? v : 64;
+    }();
     int G = (ell + 3) / 4;
+    if (G > cap) G = cap;
     if (G > dev.num_cus) G = dev.num_cus;
     if (G < 1) G = 1;
     return G;
 }
 
+bool landmark_k_in_lds(const DeviceInfo& dev, int ell, int C, int G) {
+    static const bool allowed = [] {
+        const char* e = std::getenv("KKM_LANDMARK_K_IN_LDS");
+        return !(e && e[0] == '0');
+    }();
+    return allowed && landmark_lds_bytes_host(ell, C, G, true) <= dev.max_lds_per_block;
+}
+
 kkm_status launch_landmark_phase(const LandmarkArgs& args, int dtype, const DeviceInfo& dev, hipStream_t stream) {
     const int G = args.grid;
-    const size_t lds = landmark_lds_bytes_host(args.ell, args.C, G);
+    const size_t lds = landmark_lds_bytes_host(args.ell, args.C, G, args.k_in_lds != 0);
     if (lds > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "landmark set too large for one workgroup's LDS (l=" +
                                              std::to_string(args.ell) + ", C=" + std::to_string(args.C) +
                                              "); use more mini-batches");
+    const size_t lds_tile = sizeof(double) * 64 * (size_t)args.d;
+    const size_t lds_row = sizeof(double) * (size_t)args.d;
+    if (lds_tile > dev.max_lds_per_block) return fail(KKM_ERR_UNSUPPORTED, "sample dimension too large");
+    const int tiles = (args.ell + 31) / 32;
+    const dim3 bgrid = args.ktype != KKM_KERNEL_RMSD ? dim3((unsigned)(tiles * (tiles + 1) / 2), 1)
+                                                     : dim3((unsigned)tiles, (unsigned)tiles);
+    if (dtype == KKM_F64)
+        hipLaunchKernelGGL(landmark_block_kernel<double>, bgrid, dim3(256), lds_tile, stream, args, tiles);
+    else
+        hipLaunchKernelGGL(landmark_block_kernel<float>, bgrid, dim3(256), lds_tile, stream, args, tiles);
+    KKM_HIP(hipGetLastError());
+    KKM_TRY(dispatch_dp(eval_dp(args.ktype, args.d), [&]<int DP>() -> kkm_status {
+        if (dtype == KKM_F64)
+            hipLaunchKernelGGL((landmark_init_kernel<double, DP>), dim3(args.ell), dim3(256), lds_row, stream, args);
+        else
+            hipLaunchKernelGGL((landmark_init_kernel<float, DP>), dim3(args.ell), dim3(256), lds_row, stream, args);
+        KKM_HIP(hipGetLastError());
+        return KKM_OK;
+    }));
     LandmarkArgs a = args;
     void* params[] = {&a};
     const void* fn = dtype == KKM_F64 ? reinterpret_cast<const void*>(&landmark_phase_kernel<double>)
                                       : reinterpret_cast<const void*>(&landmark_phase_kernel<float>);
-    if (lds > 65536) KKM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    KKM_TRY(allow_dynamic_lds(fn, lds));
     int per_cu = 0;
     KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
     if (per_cu * dev.num_cus < G)

@@ -22,6 +22,8 @@ __device__ __forceinline__ const TI* brow(const BatchView& b, int64_t pos) {
     return static_cast<const TI*>(b.X) + (b.base + pos * b.stride) * b.d;
 }
 
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
 // (value, index) minimum with the lowest index on equal values
 __device__ __forceinline__ void vmin(double& v, int64_t& i, double v2, int64_t i2) {
     if (v2 < v || (v2 == v && i2 < i)) { v = v2; i = i2; }
@@ -88,14 +90,14 @@ __global__ __launch_bounds__(1024) void kpp_pick_kernel(const double* __restrict
     }
 }
 
-template <typename TI>
+template <typename TI, int DP>
 __global__ __launch_bounds__(256) void kpp_dist_kernel(BatchView b, KSpec ks, int k, const int32_t* chosen,
                                                        double* D2) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= b.n) return;
     const TI* x = brow<TI>(b, q);
     const TI* m = brow<TI>(b, chosen[k]);
-    double v = (kself64(ks, x) - 2.0 * k64(ks, x, m)) + kself64(ks, m);
+    double v = (kself64(ks, x) - 2.0 * k64p<DP>(ks, x, m)) + kself64(ks, m);
     v = v > 0.0 ? v : 0.0;
     D2[q] = k == 0 ? v : fmin(D2[q], v);
 }
@@ -118,50 +120,78 @@ __global__ void set_medoids_kernel(BatchView b, KSpec ks, int C, const int32_t* 
     }
 }
 
-// ----------------------------------------------------------------------------- members / medoids / merge
-__global__ __launch_bounds__(256) void members_kernel(SelectArgs a) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.b.n) return;
-    const int j = a.labels[q];
-    atomicAdd(a.counts + j, 1);
-    if (a.label_out) a.label_out[a.b.base + q * a.b.stride] = j;
-}
+// ----------------------------------------------------------------------------- batch medoids (Eq. 10)
+// The batch-wide distance pass leaves, for every cluster j, U_j = min over rows of D + E (an upper
+// bound on the smallest exact distance).  Candidates are the rows with D - E <= U_j; each is
+// re-evaluated in FP64 and the lowest (value, position) is the batch medoid.
+constexpr int kRowsPerBlock = 256;
 
-// Eq. 10 with FP32 distances: candidates are the rows whose interval [D - E, D + E] can hold the
-// minimum; their distance is recomputed in FP64 and the lowest (value, position) wins.
-template <typename TI, typename TD>
-__global__ __launch_bounds__(256) void batch_medoid_kernel(SelectArgs a) {
-    const int j = blockIdx.x;
-    if (a.counts[j] == 0) {
-        if (threadIdx.x == 0) a.bmed[j] = -1;
-        return;
-    }
-    const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
-    const int64_t n = a.b.n;
-    double up = kInf;
-    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) up = fmin(up, (double)Dt[q] + (double)a.Erow[q]);
-    int64_t dummy = 0;
-    block_vmin(up, dummy);
-    const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
-    const TI* rows = static_cast<const TI*>(a.sup.rows);
-    const double g = a.sup.self[j];
-    double bv = kInf;
-    int64_t bi = INT64_MAX;
-    int cands = 0;
-    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) {
-        if ((double)Dt[q] - (double)a.Erow[q] <= up) {
-            const TI* x = brow<TI>(a.b, q);
-            double f = 0.0;
-            for (int l = lo; l < hi; ++l) f += a.sup.coef64[l] * k64(a.ks, x, rows + (int64_t)l * a.sup.dpad);
-            const double v = kself64(a.ks, x) - 2.0 * f + g;
-            vmin(bv, bi, v, q);
-            ++cands;
+// Grid (row chunks) x (clusters): member counts per chunk, label scatter, candidate list.
+template <typename TD>
+__global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
+    const int j = blockIdx.y, chunk = blockIdx.x;
+    const int64_t q = (int64_t)chunk * kRowsPerBlock + threadIdx.x;
+    const bool active = q < a.b.n;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    if (active) {
+        const int lab = a.labels[q];
+        if (j == 0 && a.label_out) a.label_out[a.b.base + q * a.b.stride] = lab;
+        if (lab == j) atomicAdd(&cnt, 1);
+        const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
+        const double D = (double)Dt[q];
+        const double U = ord_dec(a.colmin[j]);
+        if (D < kInf && D - (double)a.Erow[q] <= U) {
+            const int pos = atomicAdd(a.cand_count, 1);
+            if (pos < a.cand_cap) {
+                a.cand_q[pos] = (int32_t)q;
+                a.cand_j[pos] = j;
+            }
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) a.mpart_c[(int64_t)j * a.nchunk + chunk] = cnt;
+}
+
+// One wavefront per candidate: d(x, j) = K(x,x) - 2 sum_l a_l K(x, s_l) + self_j in FP64.
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void candidate_eval_kernel(SelectArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6), nw = gridDim.x * 4;
+    const int count = min(*a.cand_count, a.cand_cap);
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    for (int i = gw; i < count; i += nw) {
+        const int64_t q = a.cand_q[i];
+        const int j = a.cand_j[i];
+        const TI* x = brow<TI>(a.b, q);
+        const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
+        double f = 0.0;
+        for (int l = lo + lane; l < hi; l += 64) f += a.sup.coef64[l] * k64p<DP>(a.ks, x, rows + (int64_t)l * a.sup.dpad);
+        f = wave_sum(f);
+        if (lane == 0) a.cand_v[i] = kself64(a.ks, x) - 2.0 * f + a.sup.self[j];
+    }
+}
+
+// Batch medoid of cluster j among the evaluated candidates, and its member count, by one block.
+__device__ void reduce_cluster(const SelectArgs& a, int j, int32_t* members, int32_t* med) {
+    const int count = min(*a.cand_count, a.cand_cap);
+    double bv = kInf;
+    int64_t bi = INT64_MAX;
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+        if (a.cand_j[i] == j) vmin(bv, bi, a.cand_v[i], a.cand_q[i]);
     block_vmin(bv, bi);
-    if (cands) atomicAdd(a.cand_total, cands);
-    // no candidate only when every distance is +inf or NaN (non-finite input, reported by the caller)
-    if (threadIdx.x == 0) a.bmed[j] = bi == INT64_MAX ? 0 : (int32_t)bi;
+    __shared__ int32_t sh_c;
+    if (threadIdx.x == 0) sh_c = 0;
+    __syncthreads();
+    int32_t c = 0;
+    for (int k = threadIdx.x; k < a.nchunk; k += blockDim.x) c += a.mpart_c[(int64_t)j * a.nchunk + k];
+    if (c) atomicAdd(&sh_c, c);
+    __syncthreads();
+    *members = sh_c;
+    // no candidate only when every distance is +inf or NaN (non-finite input, reported separately)
+    *med = sh_c == 0 ? -1 : (bi == INT64_MAX ? 0 : (int32_t)bi);
+    __syncthreads();
 }
 
 __device__ __forceinline__ double merge_alpha(int32_t members, int64_t w) {
@@ -169,42 +199,53 @@ __device__ __forceinline__ double merge_alpha(int32_t members, int64_t w) {
     return den > 0.0 ? (double)members / den : 0.0;
 }
 
-template <typename TI>
-__global__ __launch_bounds__(256) void merge_partial_kernel(SelectArgs a, int64_t chunk) {
-    const int j = blockIdx.y;
-    const double alpha = merge_alpha(a.counts[j], a.wcount[j]);
-    if (!(alpha > 0.0) || a.bmed[j] < 0) return;
-    const TI* xm = brow<TI>(a.b, a.bmed[j]);
-    const TI* mj = static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
-    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min<int64_t>(a.b.n, lo + chunk);
+// ----------------------------------------------------------------------------- merge (Eq. 11-13)
+// Grid (row chunks) x (clusters): score(x) = K(x,x) - 2 alpha K(x, m_j^i) - 2 (1 - alpha) K(x, m_j)
+// for the chunk's rows, block minimum (lowest position on ties).  Chunk 0 records m_j^i and |w_j^i|.
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void merge_partial_kernel(SelectArgs a) {
+    const int j = blockIdx.y, chunk = blockIdx.x;
+    int32_t mem = 0, med = -1;
+    reduce_cluster(a, j, &mem, &med);
+    if (chunk == 0 && threadIdx.x == 0) {
+        a.counts[j] = mem;
+        a.bmed[j] = med;
+    }
+    const double alpha = merge_alpha(mem, a.wcount[j]);
+    if (!(alpha > 0.0) || med < 0) return;   // uniform over the block
+    const int64_t q = (int64_t)chunk * kRowsPerBlock + threadIdx.x;
     double bv = kInf;
     int64_t bi = INT64_MAX;
-    for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) {
+    if (q < a.b.n) {
         const TI* x = brow<TI>(a.b, q);
-        double sc = kself64(a.ks, x) - 2.0 * alpha * k64(a.ks, x, xm);
-        if (alpha < 1.0) sc = sc - 2.0 * (1.0 - alpha) * k64(a.ks, x, mj);
-        vmin(bv, bi, sc, q);
+        double sc = kself64(a.ks, x) - 2.0 * alpha * k64p<DP>(a.ks, x, brow<TI>(a.b, med));
+        if (alpha < 1.0)
+            sc = sc - 2.0 * (1.0 - alpha) * k64p<DP>(a.ks, x, static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad);
+        bv = sc;
+        bi = q;
     }
     block_vmin(bv, bi);
     if (threadIdx.x == 0) {
-        a.mpart_v[(int64_t)j * a.nchunk + blockIdx.x] = bv;
-        a.mpart_i[(int64_t)j * a.nchunk + blockIdx.x] = (int32_t)(bi == INT64_MAX ? -1 : bi);
+        const int64_t at = (int64_t)j * a.nchunk + chunk;
+        a.gpart_v[at] = bv;
+        a.gpart_i[at] = bi == INT64_MAX ? -1 : (int32_t)bi;
     }
 }
 
 template <typename TI>
 __global__ __launch_bounds__(256) void merge_final_kernel(SelectArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.cand_total) *a.cand_total += *a.cand_count;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.C; j += gridDim.x * blockDim.x) {
-        const int32_t mem = a.counts[j];
+        const int32_t mem = a.counts[j], med = a.bmed[j];
         const double alpha = merge_alpha(mem, a.wcount[j]);
-        if (alpha > 0.0) {
+        if (alpha > 0.0 && med >= 0) {
             double bv = kInf;
             int64_t bi = INT64_MAX;
             for (int c = 0; c < a.nchunk; ++c) {
-                const int32_t i = a.mpart_i[(int64_t)j * a.nchunk + c];
-                if (i >= 0) vmin(bv, bi, a.mpart_v[(int64_t)j * a.nchunk + c], i);
+                const int32_t i = a.gpart_i[(int64_t)j * a.nchunk + c];
+                if (i >= 0) vmin(bv, bi, a.gpart_v[(int64_t)j * a.nchunk + c], i);
             }
-            if (bi == INT64_MAX) bi = a.bmed[j];
+            if (bi == INT64_MAX) bi = med;
             const TI* x = brow<TI>(a.b, bi);
             TI* M = static_cast<TI*>(a.M) + (int64_t)j * a.Mpad;
             for (int64_t c = 0; c < a.Mpad; ++c) M[c] = c < a.b.d ? x[c] : TI(0);
@@ -212,7 +253,7 @@ __global__ __launch_bounds__(256) void merge_final_kernel(SelectArgs a) {
             a.Midx[j] = a.b.base + bi * a.b.stride;
         }
         a.wcount[j] += mem;
-        if (a.info_bmed) a.info_bmed[j] = mem > 0 ? a.b.base + (int64_t)a.bmed[j] * a.b.stride : -1;
+        if (a.info_bmed) a.info_bmed[j] = med >= 0 ? a.b.base + (int64_t)med * a.b.stride : -1;
         if (a.info_bcnt) a.info_bcnt[j] = mem;
         if (a.info_gmed) a.info_gmed[j] = a.Mself[j] < kInf ? a.Midx[j] : -1;
     }
@@ -249,6 +290,7 @@ __global__ __launch_bounds__(1024) void model_from_medoids_kernel(kkm_model m, c
         mx = fmaxf(mx, n32);
     }
     if (threadIdx.x == 0) m.offsets[m.C] = m.C;
+    if (threadIdx.x < 5) m.split[threadIdx.x] = threadIdx.x == 4 ? m.C : (m.C * threadIdx.x + 3) / 4;
     red[threadIdx.x] = mx;
     __syncthreads();
     for (int w = 512; w >= 1; w >>= 1) {
@@ -285,6 +327,16 @@ __global__ __launch_bounds__(1024) void model_norms_kernel(kkm_model m) {
         __syncthreads();
     }
     if (threadIdx.x == 0) *m.snorm_max = red[0];
+    if (threadIdx.x < 5) {
+        const int t = threadIdx.x;
+        int j = 0;
+        if (t == 4) j = m.C;
+        else if (t > 0) {
+            const int64_t target = (m.used * t + 3) / 4;
+            while (j < m.C && m.offsets[j] < target) ++j;
+        }
+        m.split[t] = j;
+    }
 }
 
 // self term a^T K_SS a of segment j (one block per cluster), fixed summation order
@@ -344,21 +396,24 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
-inline unsigned nblocks(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
 }  // namespace
 
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
                            int32_t* chosen, double* D2, hipStream_t s) {
+    const int dp = eval_dp(ks.type, ks.d);
     for (int k = 0; k < C; ++k) {
         hipLaunchKernelGGL(kpp_pick_kernel, dim3(1), dim3(1024), 0, s, D2, b.n, k, uniforms, chosen);
         KKM_HIP(hipGetLastError());
         if (k == C - 1) break;
-        if (dtype == KKM_F64)
-            hipLaunchKernelGGL(kpp_dist_kernel<double>, dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
-        else
-            hipLaunchKernelGGL(kpp_dist_kernel<float>, dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
-        KKM_HIP(hipGetLastError());
+        KKM_TRY(dispatch_dp(dp, [&]<int DP>() -> kkm_status {
+            if (dtype == KKM_F64)
+                hipLaunchKernelGGL((kpp_dist_kernel<double, DP>), dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
+            else
+                hipLaunchKernelGGL((kpp_dist_kernel<float, DP>), dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
+            KKM_HIP(hipGetLastError());
+            return KKM_OK;
+        }));
     }
     return KKM_OK;
 }
@@ -375,37 +430,31 @@ kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, in
     return KKM_OK;
 }
 
-kkm_status launch_members(const SelectArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(members_kernel, dim3(nblocks(a.b.n, 256)), dim3(256), 0, s, a);
-    KKM_HIP(hipGetLastError());
-    return KKM_OK;
-}
+int select_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kRowsPerBlock - 1) / kRowsPerBlock); }
 
-kkm_status launch_batch_medoids(const SelectArgs& a, bool tile_f64, hipStream_t s) {
-    if (a.dtype == KKM_F64) {
-        if (tile_f64) hipLaunchKernelGGL((batch_medoid_kernel<double, double>), dim3(a.C), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((batch_medoid_kernel<double, float>), dim3(a.C), dim3(256), 0, s, a);
-    } else {
-        if (tile_f64) hipLaunchKernelGGL((batch_medoid_kernel<float, double>), dim3(a.C), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((batch_medoid_kernel<float, float>), dim3(a.C), dim3(256), 0, s, a);
-    }
+kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& dev, hipStream_t s) {
+    const dim3 grid(a.nchunk, a.C);
+    if (tile_f64) hipLaunchKernelGGL(medoid_candidates_kernel<double>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(medoid_candidates_kernel<float>, grid, dim3(256), 0, s, a);
     KKM_HIP(hipGetLastError());
-    return KKM_OK;
-}
-
-kkm_status launch_merge(const SelectArgs& a, hipStream_t s) {
-    const int64_t chunk = (a.b.n + a.nchunk - 1) / a.nchunk;
-    if (a.dtype == KKM_F64) {
-        hipLaunchKernelGGL(merge_partial_kernel<double>, dim3(a.nchunk, a.C), dim3(256), 0, s, a, chunk);
+    const unsigned cand_blocks = (unsigned)std::max(1, 4 * dev.num_cus);
+    return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
+        if (a.dtype == KKM_F64) {
+            hipLaunchKernelGGL((candidate_eval_kernel<double, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
+            KKM_HIP(hipGetLastError());
+            hipLaunchKernelGGL((merge_partial_kernel<double, DP>), grid, dim3(256), 0, s, a);
+            KKM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(merge_final_kernel<double>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((candidate_eval_kernel<float, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
+            KKM_HIP(hipGetLastError());
+            hipLaunchKernelGGL((merge_partial_kernel<float, DP>), grid, dim3(256), 0, s, a);
+            KKM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(merge_final_kernel<float>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
+        }
         KKM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(merge_final_kernel<double>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
-    } else {
-        hipLaunchKernelGGL(merge_partial_kernel<float>, dim3(a.nchunk, a.C), dim3(256), 0, s, a, chunk);
-        KKM_HIP(hipGetLastError());
-        hipLaunchKernelGGL(merge_final_kernel<float>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
-    }
-    KKM_HIP(hipGetLastError());
-    return KKM_OK;
+        return KKM_OK;
+    });
 }
 
 kkm_status launch_model_from_medoids(kkm_model* m, const void* M, int64_t Mpad, const double* Mself,
@@ -445,6 +494,27 @@ kkm_status launch_centre(const void* X, void* Y, int64_t n, int A, int dtype, hi
     else
         hipLaunchKernelGGL(centre_kernel<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
                            static_cast<const float*>(X), static_cast<float*>(Y), n, A);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+__global__ void add_i32_kernel(int32_t* dst, const int32_t* src) {
+    if (threadIdx.x == 0) *dst += *src;
+}
+
+kkm_status launch_add_i32(int32_t* dst, const int32_t* src, hipStream_t s) {
+    hipLaunchKernelGGL(add_i32_kernel, dim3(1), dim3(64), 0, s, dst, src);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+kkm_status launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return KKM_OK;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)std::min<int64_t>(1024, nblocks(n, 256))), dim3(256), 0, s, p, n, v);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
 }

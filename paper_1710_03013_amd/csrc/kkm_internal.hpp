@@ -70,6 +70,8 @@ struct DeviceInfo {
     bool coop = false;
 };
 kkm_status device_info(DeviceInfo* out);
+// Allow a kernel more than 64 KiB of dynamic LDS (no-op below that; once per device and kernel).
+kkm_status allow_dynamic_lds(const void* fn, size_t bytes);
 
 }  // namespace kkm
 
@@ -95,6 +97,7 @@ struct kkm_model {
     double* self = nullptr;   // [C] a^T K a (FP64); +inf disables the cluster
     double* segabs = nullptr; // [C] sum_l |a_l| over segment j
     float* snorm_max = nullptr; // [1] max ||s||^2 over the support (error bounds)
+    int32_t* split = nullptr;   // [5] cluster runs of the four wavefronts of a distance tile
     int64_t* counts = nullptr;  // [C] |w_j| of a fitted model
     int64_t* medoid_index = nullptr; // [C]
 };
@@ -108,6 +111,16 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
+}
+
+// Order-preserving map of doubles to unsigned 64-bit integers (for atomicMin on values).
+__device__ __forceinline__ unsigned long long ord_enc(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ord_dec(unsigned long long e) {
+    const unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+    return __longlong_as_double((long long)b);
 }
 
 __device__ __forceinline__ float exp_neg(float a) {     // exp(-a), a >= 0
@@ -238,6 +251,54 @@ template <typename TA, typename TB>
 __device__ inline double k64(const KSpec& ks, const TA* __restrict__ a, const TB* __restrict__ b) {
     if (ks.type == KKM_KERNEL_RMSD) return rmsd_kfun64(a, b, ks.n_atoms, ks.inv2s2);
     return kfun64_rows(ks.type, a, b, ks.d, ks.inv2s2);
+}
+
+// K(a, b) in FP64 for rows of length ks.d <= DP (linear / RBF): both rows are read with a fully
+// unrolled, guarded loop so that every load is in flight at once.  DP == 0 (RMSD, or rows longer than
+// the register budget) falls back to k64.
+template <int DP, typename TA, typename TB>
+__device__ __forceinline__ double k64p(const KSpec& ks, const TA* __restrict__ a, const TB* __restrict__ b) {
+    if constexpr (DP == 0) {
+        return k64(ks, a, b);
+    } else {
+        double va[DP], vb[DP];
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+            const bool in = k < ks.d;
+            va[k] = in ? (double)a[k] : 0.0;
+            vb[k] = in ? (double)b[k] : 0.0;
+        }
+        double acc = 0.0;
+        if (ks.type == KKM_KERNEL_LINEAR) {
+#pragma unroll
+            for (int k = 0; k < DP; ++k) acc = fma(va[k], vb[k], acc);
+            return acc;
+        }
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+            const double t = va[k] - vb[k];
+            acc = fma(t, t, acc);
+        }
+        return ::exp(-acc * ks.inv2s2);
+    }
+}
+
+// Compile-time row length for k64p: the padded dimension for linear / RBF, 0 for RMSD.
+inline int eval_dp(int ktype, int64_t d) { return ktype == KKM_KERNEL_RMSD ? 0 : padded_dim(d); }
+
+// Calls F.template operator()<DP>() for the DP of eval_dp.
+template <typename F>
+inline kkm_status dispatch_dp(int dp, F&& f) {
+    switch (dp) {
+        case 0: return f.template operator()<0>();
+        case 4: return f.template operator()<4>();
+        case 8: return f.template operator()<8>();
+        case 16: return f.template operator()<16>();
+        case 32: return f.template operator()<32>();
+        case 64: return f.template operator()<64>();
+        case 128: return f.template operator()<128>();
+        default: return KKM_ERR_INTERNAL;
+    }
 }
 
 // K(a, a) in FP64.

@@ -28,8 +28,9 @@ struct LandmarkArgs {
     int64_t Mpad;
     const double* Mself;    // [C] K(m,m), +inf where the medoid is unset
     double* Kbuf;           // [ell][ell] scratch
-    int32_t* lab;           // [2][ell] scratch
-    double* partial;        // [grid][C] scratch
+    int32_t* lab;           // [2][ell] scratch: initial labels, then final labels
+    double* Sall;           // [2][ell][C] scratch: every workgroup's rows of S (alternating buffers)
+    double* partial;        // [2][grid][C] scratch (alternating buffers)
     int32_t* changed;       // [max_updates+1] scratch
     int32_t* zero_ints;     // ints to clear for the later kernels of the batch
     int32_t n_zero_ints;
@@ -47,9 +48,17 @@ struct LandmarkArgs {
     double* coef64;
     int32_t* src_index;     // [ell] batch position of each support row
     float* snorm_max;       // [1]
+    int32_t* split;         // [5] cluster runs of the distance pass's four wavefronts
+    int32_t k_in_lds;       // own rows of the landmark block kept in LDS (else in Kbuf)
+    int64_t* trace;         // [64] device wall-clock stamps of workgroup 0, or null
+    unsigned long long* colmin;   // [C] set to the empty value for the batch's distance pass
+    unsigned* barrier;      // [1] arrival counter of the loop's grid barrier
+    int32_t* error;         // [1] set when a barrier wait exceeded its cap
 };
+// Workgroups of the landmark phase for a landmark set of size ell (KKM_LANDMARK_ROWS rows each).
 int landmark_grid(const DeviceInfo& dev, int ell);
-size_t landmark_lds_bytes_host(int ell, int C, int G);
+size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds);
+bool landmark_k_in_lds(const DeviceInfo& dev, int ell, int C, int G);
 kkm_status launch_landmark_phase(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
 
 // ---------------------------------------------------------------- sparse-centroid distances (k_dist.hip)
@@ -65,6 +74,7 @@ struct SupportView {
     const double* self;     // [C]
     const double* segabs;   // [C]
     const float* snorm_max; // [1]
+    const int32_t* split;   // [5] cluster runs of the four wavefronts of a distance tile
     int32_t C;
 };
 
@@ -84,14 +94,16 @@ struct DistArgs {
     int32_t* refine_list;   // [n]
     int32_t* refine_count;  // [1]
     int32_t* nonfinite;     // [1]
+    unsigned long long* colmin;   // [C] ord_enc(min over rows of D + Erow), or null (fit only)
+    int64_t n_support;      // rows of sup (offsets[C])
 };
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
 // True when launch_dist evaluates (and stores Dt) in FP64 for these arguments.
 bool dist_is_fp64(const DistArgs& a);
 // LDS bytes the distance tile needs for C clusters.
 size_t dist_lds_bytes(const DistArgs& a);
-// FP64 re-decision of the rows listed by launch_dist.
-kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
+// FP64 re-decision of the rows listed by launch_dist (n_support: support rows of a.sup).
+kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s, int64_t n_support);
 // Deterministic FP64 sum of best[0..n) into out[0] (partials: >= 1024 doubles of scratch).
 kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s);
 
@@ -106,29 +118,36 @@ struct SelectArgs {
     int64_t Mpad;
     double* Mself;          // [C]
     int64_t* Midx;          // [C] sample index
-    int64_t* wcount;        // [C]
+    int64_t* wcount;        // [C] running |w_j|
     // batch state
-    const int32_t* labels;  // [n] batch labels
-    int32_t* counts;        // [C] |w_j^i|
-    int32_t* bmed;          // [C] batch medoid positions
+    const int32_t* labels;  // [n] batch labels (after FP64 re-decisions)
+    int32_t* counts;        // [C] out: |w_j^i|
+    int32_t* bmed;          // [C] out: batch medoid positions (-1: empty)
     int32_t* label_out;     // [N] caller labels (scatter), or null
-    const float* Dt;        // [C][ldD]
+    const float* Dt;        // [C][ldD] distances of the batch pass (float or double)
     int64_t ldD;
-    const float* Erow;      // [n]
+    const float* Erow;      // [n] error bound of each row's distances
+    const unsigned long long* colmin;   // [C] ord_enc(min over rows of D + E)
     SupportView sup;        // support of the batch centroids (FP64 re-evaluation of candidates)
-    double* mpart_v;        // [C][nchunk] merge partial minima
-    int32_t* mpart_i;
-    int32_t nchunk;
-    int32_t* cand_total;    // [1] medoid candidates evaluated (accumulates)
+    int32_t nchunk;         // select_chunks(n)
+    int32_t* mpart_c;       // [C][nchunk] member-count partials
+    int32_t* cand_q;        // [cand_cap] candidate rows
+    int32_t* cand_j;        // [cand_cap] their clusters
+    double* cand_v;         // [cand_cap] their FP64 distances
+    int32_t* cand_count;    // [1] (cleared before the batch)
+    int32_t cand_cap;
+    int32_t* cand_total;    // [1] accumulates cand_count over batches, or null
+    double* gpart_v;        // [C][nchunk] merge partials
+    int32_t* gpart_i;
     // per-batch info rows (device, length C) or null
     int64_t* info_bmed;
     int64_t* info_bcnt;
     int64_t* info_gmed;
 };
-kkm_status launch_members(const SelectArgs& a, hipStream_t s);
+int select_chunks(int64_t n);
+// Member counts, label scatter, batch medoids (Eq. 10) and the merge (Eq. 11-13).
 // tile_f64: the distance tile Dt holds doubles (FP64 precision) rather than floats.
-kkm_status launch_batch_medoids(const SelectArgs& a, bool tile_f64, hipStream_t s);
-kkm_status launch_merge(const SelectArgs& a, hipStream_t s);
+kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& dev, hipStream_t s);
 
 // k-means++ on a batch: uniforms[C] device, chosen[C] device out, D2 [n] scratch.
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
@@ -145,5 +164,9 @@ kkm_status launch_model_prepare(kkm_model* m, hipStream_t s);
 kkm_status launch_centre(const void* X, void* Y, int64_t n, int A, int dtype, hipStream_t s);
 // Set n ints to zero (a kernel, so that the call can sit inside a captured graph).
 kkm_status launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
+// *dst += *src on the device.
+kkm_status launch_add_i32(int32_t* dst, const int32_t* src, hipStream_t s);
+// Set n 64-bit words to v (a kernel, for the same reason).
+kkm_status launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 
 }  // namespace kkm
