@@ -105,6 +105,8 @@ struct FitWs {
     double* snorm64;
     float* coef32;
     double* coef64;
+    uint16_t* sup_hi;
+    uint16_t* sup_lo;
     int32_t* src_index;
     float* snorm_max;
     int32_t* split;        // [5]
@@ -152,11 +154,14 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.offsets = c.take<int32_t>(C + 1);
     w.ghat = c.take<double>(C);
     w.segabs = c.take<double>(C);
-    w.support = c.take<char>((size_t)P.ellmax * P.dpad * es);
-    w.snorm32 = c.take<float>(P.ellmax);
-    w.snorm64 = c.take<double>(P.ellmax);
-    w.coef32 = c.take<float>(P.ellmax);
-    w.coef64 = c.take<double>(P.ellmax);
+    const size_t srows = (size_t)P.ellmax + 32;   // whole 32-row tiles for the matrix-core pass
+    w.support = c.take<char>(srows * P.dpad * es);
+    w.snorm32 = c.take<float>(srows);
+    w.snorm64 = c.take<double>(srows);
+    w.coef32 = c.take<float>(srows);
+    w.coef64 = c.take<double>(srows);
+    w.sup_hi = c.take<uint16_t>(srows * bf16_pad(P.dpad));
+    w.sup_lo = c.take<uint16_t>(srows * bf16_pad(P.dpad));
     w.src_index = c.take<int32_t>(P.ellmax);
     w.snorm_max = c.take<float>(1);
     w.split = c.take<int32_t>(5);
@@ -368,6 +373,10 @@ SupportView model_support(const kkm_model* m) {
     s.segabs = m->segabs;
     s.snorm_max = m->snorm_max;
     s.split = m->split;
+    s.nonneg = m->nonneg;
+    s.hi = m->hi;
+    s.lo = m->lo;
+    s.bpad = m->bpad;
     s.C = m->C;
     return s;
 }
@@ -533,6 +542,9 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.src_index = w.src_index;
         la.snorm_max = w.snorm_max;
         la.split = w.split;
+        la.sup_hi = w.sup_hi;
+        la.sup_lo = w.sup_lo;
+        la.bpad = bf16_pad(P.dpad);
         la.k_in_lds = landmark_k_in_lds(dev, ell, C, la.grid) ? 1 : 0;
         la.trace = (i == 0 && info && info->landmark_trace) ? w.trace : nullptr;
         la.barrier = w.barrier;
@@ -555,6 +567,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sv.segabs = w.segabs;
         sv.snorm_max = w.snorm_max;
         sv.split = w.split;
+        sv.nonneg = 1;
+        sv.hi = w.sup_hi;
+        sv.lo = w.sup_lo;
+        sv.bpad = bf16_pad(P.dpad);
         sv.C = C;
 
         DistArgs da{};
@@ -634,6 +650,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         KKM_HIP(hipMemcpyAsync(info->landmark_trace, w.trace, sizeof(int64_t) * 64, hipMemcpyDeviceToHost, s));
     KKM_HIP(hipStreamSynchronize(s));
     model->used = C;
+    model->nonneg = 1;
     (void)es;
 
     if (info) {

@@ -181,6 +181,7 @@ kkm_status kkm_model_create(const kkm_kernel* kernel, int64_t d, int32_t C, int6
     m->kernel = *kernel;
     m->d = d;
     m->dpad = kernel->type == KKM_KERNEL_RMSD ? (int32_t)d : padded_dim(d);
+    m->bpad = bf16_pad(m->dpad);
     m->C = C;
     m->cap = max_support;
     m->used = 0;
@@ -188,12 +189,15 @@ kkm_status kkm_model_create(const kkm_kernel* kernel, int64_t d, int32_t C, int6
     m->device = dev.device;
     const size_t es = dtype == KKM_F64 ? 8 : 4;
     Carver cv(nullptr);
+    const size_t rows = (size_t)max_support + 32;   // the matrix-core pass reads whole 32-row tiles
     auto layout = [&](Carver& c) {
-        m->support = c.take<char>((size_t)max_support * m->dpad * es);
-        m->snorm32 = c.take<float>(max_support);
-        m->snorm64 = c.take<double>(max_support);
-        m->coef32 = c.take<float>(max_support);
-        m->coef64 = c.take<double>(max_support);
+        m->support = c.take<char>(rows * m->dpad * es);
+        m->snorm32 = c.take<float>(rows);
+        m->snorm64 = c.take<double>(rows);
+        m->coef32 = c.take<float>(rows);
+        m->coef64 = c.take<double>(rows);
+        m->hi = c.take<uint16_t>(rows * m->bpad);
+        m->lo = c.take<uint16_t>(rows * m->bpad);
         m->offsets = c.take<int32_t>(C + 1);
         m->self = c.take<double>(C);
         m->segabs = c.take<double>(C);
@@ -241,8 +245,11 @@ kkm_status kkm_model_load(kkm_model* m, const void* support, int64_t n_support, 
     if (offsets[0] != 0 || offsets[m->C] != n_support) return fail(KKM_ERR_INVALID_ARG, "offsets must run from 0 to n_support");
     for (int j = 0; j < m->C; ++j)
         if (offsets[j + 1] < offsets[j]) return fail(KKM_ERR_INVALID_ARG, "offsets must be non-decreasing");
-    for (int64_t l = 0; l < n_support; ++l)
+    int32_t nonneg = 1;
+    for (int64_t l = 0; l < n_support; ++l) {
         if (!std::isfinite(coef[l])) return fail(KKM_ERR_NONFINITE, "non-finite coefficient");
+        if (coef[l] < 0.0) nonneg = 0;
+    }
     const size_t es = m->dtype == KKM_F64 ? 8 : 4;
     std::vector<char> rows((size_t)std::max<int64_t>(1, n_support) * m->dpad * es, 0);
     for (int64_t l = 0; l < n_support; ++l) {
@@ -281,6 +288,7 @@ kkm_status kkm_model_load(kkm_model* m, const void* support, int64_t n_support, 
     KKM_HIP(hipMemcpy(m->counts, zero.data(), sizeof(int64_t) * m->C, hipMemcpyHostToDevice));
     KKM_HIP(hipMemcpy(m->medoid_index, minus.data(), sizeof(int64_t) * m->C, hipMemcpyHostToDevice));
     m->used = n_support;
+    m->nonneg = nonneg;
     KKM_TRY(launch_model_prepare(m, nullptr));
     KKM_HIP(hipDeviceSynchronize());
     if (cur != m->device) KKM_HIP(hipSetDevice(cur));

@@ -35,9 +35,11 @@ struct EvalDot {
     TC inv2s2;
     int64_t d;
     float snmax;
+    int nonneg;
 
     __device__ bool load(const DistArgs& a, int64_t q) {
         const TI* r = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        nonneg = a.sup.nonneg;
         bool ok = true;
 #pragma unroll
         for (int k = 0; k < DP; ++k) {
@@ -80,7 +82,8 @@ struct EvalDot {
             extra = (float)(d + 2) * u * q;
         } else {
             const float rho = (float)(2 * d + 6) * u * (q + snmax) * (float)inv2s2;
-            ef = (rho + (float)(len + 8) * u) * segabs;
+            const float mass = nonneg ? fabsf(acc) * 1.0001f + 1e-30f : segabs;
+            ef = (rho + (float)(len + 8) * u) * mass;
         }
         const float e = 2.0f * ef + 3.0f * u * (fabsf((float)kqq) + 2.0f * fabsf(acc) + fabsf(g)) + extra;
         return 2.0f * e;
@@ -181,7 +184,9 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
             a.gap[q] = second < (TC)kInf ? (float)(((double)second - (double)best) / (scale > 0 ? scale : 1.0))
                                          : __builtin_huge_valf();
         }
-        if (E > 0.0f && (double)second - (double)best <= 2.0 * (double)E) {
+        const double gap = (double)second - (double)best;
+        const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)ev.kqq));
+        if (E > 0.0f && gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale) {
             const int pos = atomicAdd(a.refine_count, 1);
             a.refine_list[pos] = (int32_t)q;
         }
@@ -417,6 +422,7 @@ size_t dist_lds_bytes(const DistArgs& a) { return (dist_is_fp64(a) ? 8 : 4) * (s
 
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     if (a.q.n <= 0) return KKM_OK;
+    if (mfma_dist_applies(a)) return launch_dist_mfma(a, dev, s);
     const bool f64 = a.dtype == KKM_F64;
     if (dist_is_fp64(a)) {
         return f64 ? launch_dist_ev<EvalGeneric64<double>>(a, dev, s) : launch_dist_ev<EvalGeneric64<float>>(a, dev, s);

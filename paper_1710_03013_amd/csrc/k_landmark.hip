@@ -513,7 +513,25 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         a.coef64[k] = 1.0 / (double)cnt;
         a.coef32[k] = (float)(1.0 / (double)cnt);
         a.src_index[k] = a.lm[m];
+        for (int64_t c = 0; c < a.bpad; ++c) {
+            uint16_t hi = 0, lo = 0;
+            if (c < a.d) bf16_split((float)src[c], hi, lo);
+            a.sup_hi[(int64_t)k * a.bpad + c] = hi;
+            a.sup_lo[(int64_t)k * a.bpad + c] = lo;
+        }
         atomicMax(reinterpret_cast<unsigned int*>(a.snorm_max), __float_as_uint(n32));
+    }
+    // rows [ell, ell + 32) are read by whole-tile loads: keep them zero
+    for (int k = ell + wg * nt + tid; k < ell + 32; k += G * nt) {
+        for (int64_t c = 0; c < a.dpad; ++c) sup[(int64_t)k * a.dpad + c] = TI(0);
+        for (int64_t c = 0; c < a.bpad; ++c) {
+            a.sup_hi[(int64_t)k * a.bpad + c] = 0;
+            a.sup_lo[(int64_t)k * a.bpad + c] = 0;
+        }
+        a.snorm64[k] = 0.0;
+        a.snorm32[k] = 0.0f;
+        a.coef64[k] = 0.0;
+        a.coef32[k] = 0.0f;
     }
 }
 

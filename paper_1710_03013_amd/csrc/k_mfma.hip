@@ -1,0 +1,265 @@
+// Distances to sparse centroids with the dot products on the matrix cores (linear / RBF kernels):
+//
+//   d(x, j) = K(x,x) - 2 sum_{l in segment j} a_l K(x, s_l) + self_j,
+//   K(x, s) = x.s (linear) or exp(-(||x||^2 + ||s||^2 - 2 x.s) / (2 sigma^2)) (RBF).
+//
+// A workgroup owns 32 samples (the N dimension of a 32x32 MFMA tile); each of its four wavefronts
+// walks a cluster-aligned quarter of the support in 32-row tiles (the M dimension) aligned to
+// multiples of 32.  The two lane halves take contiguous halves of the dimensions as their share of
+// the K index (any order of K gives the same dot product), so operand fragments are contiguous
+// loads.  Result lane l holds rows 8(i/4) + 4(l/32) + i%4 of sample l%32 (i = 0..15): the kernel
+// function is applied in registers, and each segment's sum is a masked sum over the lane's 16
+// values plus one exchange with the partner lane l^32, accumulated in the order of the tiles.
+//
+// Precision: FP32 (v_mfma_f32_32x32x2_f32), or BF16x3 -- x = hi + lo with hi, lo in bfloat16 and
+// x.s ~ hi.hi' + hi.lo' + lo.hi' on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Both carry a
+// per-row error bound, and near ties are decided again in FP64 (launch_refine).
+#include <cstdlib>
+
+#include "kkm_internal.hpp"
+#include "kkm_launch.hpp"
+
+namespace kkm {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr float kU32 = 5.9604645e-8f;     // unit roundoff of float
+constexpr float kUbf = 3.0517578e-5f;     // 2^-15: three neglected terms of order 2^-16 |x||y| each
+
+__device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float sn, float inv2s2) {
+    if (type == KKM_KERNEL_LINEAR) return dot;
+    float d2 = qn + sn - 2.0f * dot;
+    d2 = d2 > 0.0f ? d2 : 0.0f;
+    return __builtin_amdgcn_exp2f(-d2 * inv2s2 * 1.4426950408889634f);
+}
+
+template <typename TI, int DP, bool BF3>
+__global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
+    constexpr int H = DP / 2;                      // dimensions per lane half
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* Dl = reinterpret_cast<float*>(smem_raw);   // [C][32]
+    __shared__ float Ew[4][32];
+    __shared__ int jb[5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int64_t q = (int64_t)blockIdx.x * 32 + col;
+    const bool active = q < a.q.n;
+    const int C = a.sup.C;
+    const int32_t* off = a.sup.offsets;
+    const int type = a.ks.type;
+    const float inv2s2 = (float)a.ks.inv2s2;
+
+    if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
+
+    // the sample's half of the dimensions, its squared norm, and its bf16 split
+    const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
+    float xq[H];
+    bool ok = true;
+    float qn = 0.0f;
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        const int dim = h * H + s;
+        const TI v = dim < a.q.d ? xr[dim] : TI(0);
+        ok = ok && isfinite((double)v);
+        xq[s] = (float)v;
+        qn = fmaf(xq[s], xq[s], qn);
+    }
+    qn += __shfl_xor(qn, 32, 64);
+    if (active && !ok) atomicOr(a.nonfinite, 1);   // either half may hold the bad value
+    const float kqq = type == KKM_KERNEL_LINEAR ? qn : 1.0f;
+    bf16x8 bh[BF3 ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
+    if constexpr (BF3) {
+#pragma unroll
+        for (int v = 0; v < H / 8; ++v)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float x = xq[8 * v + t];
+                const __bf16 hi = (__bf16)x;
+                bh[v][t] = hi;
+                bl[v][t] = (__bf16)(x - (float)hi);
+            }
+    }
+    const float snmax = *a.sup.snorm_max;
+    __syncthreads();
+
+    float emax = 0.0f;
+    const int j0 = jb[wave], j1 = jb[wave + 1];
+    const int start = off[j0], end = off[j1];
+    int j = j0;
+    float accf = 0.0f;
+    const float* rows32 = static_cast<const float*>(a.sup.rows);
+    auto finalize = [&](int jj) {
+        const int lo = off[jj], hi = off[jj + 1];
+        const double g = a.sup.self[jj];
+        float D;
+        if (hi > lo && g < kInf) {
+            D = kqq - 2.0f * accf + (float)g;
+            // error bound of D (FP32 / BF16x3 dot products, FP32 norms and sums)
+            const float len = (float)(hi - lo), segabs = (float)a.sup.segabs[jj];
+            const float dot_rel = BF3 ? kUbf + (3.0f * DP + 2.0f) * kU32 : (DP + 2.0f) * kU32;
+            const float kmax = sqrtf(qn * snmax) * 1.0001f;
+            float ef;
+            if (type == KKM_KERNEL_LINEAR) {
+                ef = (dot_rel * kmax + (len + 2.0f) * kU32 * kmax) * segabs;
+            } else {
+                // exp's relative error is rho (from the squared-distance error) plus a few ulps, so the
+                // sum's error scales with the sum of |a_l| K: the sum itself when no a_l is negative
+                const float rho = (2.0f * dot_rel * kmax + (DP + 6.0f) * kU32 * (qn + snmax)) * inv2s2;
+                const float mass = a.sup.nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
+                ef = (rho + (len + 8.0f) * kU32) * mass;
+            }
+            const float e = 2.0f * ef + 3.0f * kU32 * (fabsf(kqq) + 2.0f * fabsf(accf) + fabsf((float)g)) +
+                            (type == KKM_KERNEL_LINEAR ? (DP + 2.0f) * kU32 * qn : 0.0f);
+            emax = fmaxf(emax, 2.0f * e);
+        } else {
+            D = __builtin_huge_valf();
+        }
+        if (h == 0) Dl[jj * 32 + col] = D;
+        accf = 0.0f;
+    };
+
+    for (int r0 = start & ~31; r0 < end; r0 += 32) {
+        const int tile_end = min(r0 + 32, end);
+        // A fragment: support row r0 + col, the lane half's dimensions
+        const int64_t arow = r0 + col;
+        floatx16 acc = {};
+        if constexpr (BF3) {
+            const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi + arow * a.sup.bpad + h * H);
+            const bf16x8* al = reinterpret_cast<const bf16x8*>(a.sup.lo + arow * a.sup.bpad + h * H);
+#pragma unroll
+            for (int v = 0; v < H / 8; ++v) {
+                const bf16x8 xh = ah[v], xl = al[v];
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, bh[v], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, bl[v], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, bh[v], acc, 0, 0, 0);
+            }
+        } else {
+            const float* ar = rows32 + arow * a.sup.dpad + h * H;
+            float af[H];
+#pragma unroll
+            for (int s = 0; s < H; ++s) af[s] = ar[s];
+#pragma unroll
+            for (int s = 0; s < H; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], xq[s], acc, 0, 0, 0);
+        }
+        // epilogue: v_i = a_l K(x, s_l) for the lane's rows l = r0 + 8(i/4) + 4h + i%4
+        float v[16];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int rb = r0 + 8 * b + 4 * h;
+            const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
+            const float4 cf4 = *reinterpret_cast<const float4*>(a.sup.coef32 + rb);
+            v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
+            v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
+            v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
+            v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
+        }
+        // segments meeting this tile, in order
+        while (j < j1 && off[j] < tile_end) {
+            const int lo = max(off[j], r0), hi = min(off[j + 1], tile_end);
+            float part = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = r0 + 8 * (i / 4) + 4 * h + (i % 4);
+                part += (row >= lo && row < hi) ? v[i] : 0.0f;
+            }
+            part += __shfl_xor(part, 32, 64);
+            accf += part;
+            if (off[j + 1] <= tile_end) {
+                finalize(j);
+                ++j;
+            } else {
+                break;
+            }
+        }
+    }
+    while (j < j1) {   // empty segments after the last row of this quarter
+        finalize(j);
+        ++j;
+    }
+    if (h == 0) Ew[wave][col] = emax;
+    __syncthreads();
+
+    const float E = fmaxf(fmaxf(Ew[0][col], Ew[1][col]), fmaxf(Ew[2][col], Ew[3][col]));
+    if (wave == 0 && h == 0 && active) {
+        float best = __builtin_huge_valf(), second = __builtin_huge_valf();
+        int bj = 0;
+        for (int jj = 0; jj < C; ++jj) {
+            const float D = Dl[jj * 32 + col];
+            if (D < best) { second = best; best = D; bj = jj; }
+            else if (D < second) { second = D; }
+        }
+        a.labels[q] = bj;
+        if (a.best) a.best[q] = (double)best;
+        if (a.Erow) a.Erow[q] = E;
+        if (a.gap) {
+            const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)kqq));
+            a.gap[q] = second < __builtin_huge_valf() ? (float)(((double)second - (double)best) / (scale > 0 ? scale : 1.0))
+                                                      : __builtin_huge_valf();
+        }
+        const double gap = (double)second - (double)best;
+        const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)kqq));
+        if (gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale) {
+            const int pos = atomicAdd(a.refine_count, 1);
+            a.refine_list[pos] = (int32_t)q;
+        }
+    }
+    if (a.Dt) {
+        float* Dt = a.Dt;
+        for (int jj = wave; jj < C; jj += 4) {
+            const float D = Dl[jj * 32 + col];
+            if (active && h == 0) Dt[(int64_t)jj * a.ldD + q] = D;
+            if (a.colmin) {
+                double vv = (active && h == 0) ? (double)D + (double)E : kInf;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) vv = fmin(vv, __shfl_xor(vv, o, kWave));
+                if (lane == 0 && vv < kInf) atomicMin(a.colmin + jj, ord_enc(vv));
+            }
+        }
+    }
+}
+
+template <typename TI, bool BF3>
+kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    const size_t lds = sizeof(float) * (size_t)a.sup.C * 32;
+    if (lds > dev.max_lds_per_block) return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
+    const unsigned blocks = (unsigned)((a.q.n + 31) / 32);
+    auto go = [&](auto fn) -> kkm_status {
+        KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
+        KKM_HIP(hipGetLastError());
+        return KKM_OK;
+    };
+    switch (a.sup.dpad) {
+        case 4: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 4, false>); break;
+        case 8: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 8, false>); break;
+        case 16: return go(mfma_dist_kernel<TI, 16, BF3>);
+        case 32: return go(mfma_dist_kernel<TI, 32, BF3>);
+        case 64: return go(mfma_dist_kernel<TI, 64, BF3>);
+        case 128: return go(mfma_dist_kernel<TI, 128, BF3>);
+        default: break;
+    }
+    return fail(KKM_ERR_UNSUPPORTED, "matrix-core distance pass: unsupported padded dimension");
+}
+
+}  // namespace
+
+bool mfma_dist_applies(const DistArgs& a) {
+    static const bool off = [] {
+        const char* e = std::getenv("KKM_DIST_VALU");
+        return e && e[0] == '1';
+    }();
+    if (off || a.ks.type == KKM_KERNEL_RMSD || a.precision == KKM_PREC_FP64 || a.dtype != KKM_F32) return false;
+    if (a.precision == KKM_PREC_BF16X3) return a.sup.hi && a.sup.lo && a.sup.dpad >= 16;
+    return true;
+}
+
+kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    if (a.q.n <= 0) return KKM_OK;
+    if (a.precision == KKM_PREC_BF16X3) return launch_mfma_t<float, true>(a, dev, s);
+    return launch_mfma_t<float, false>(a, dev, s);
+}
+
+}  // namespace kkm

@@ -282,6 +282,12 @@ __global__ __launch_bounds__(1024) void model_from_medoids_kernel(kkm_model m, c
         m.snorm32[j] = n32;
         m.coef64[j] = 1.0;
         m.coef32[j] = 1.0f;
+        for (int64_t c = 0; c < m.bpad; ++c) {
+            uint16_t hi = 0, lo = 0;
+            if (c < m.d) bf16_split((float)dst[c], hi, lo);
+            m.hi[(int64_t)j * m.bpad + c] = hi;
+            m.lo[(int64_t)j * m.bpad + c] = lo;
+        }
         m.offsets[j] = j;
         m.self[j] = Mself[j];
         m.segabs[j] = 1.0;
@@ -318,6 +324,12 @@ __global__ __launch_bounds__(1024) void model_norms_kernel(kkm_model m) {
         m.snorm64[l] = n64;
         m.snorm32[l] = n32;
         m.coef32[l] = (float)m.coef64[l];
+        for (int64_t c = 0; c < m.bpad; ++c) {
+            uint16_t hi = 0, lo = 0;
+            if (c < m.d) bf16_split((float)S[l * m.dpad + c], hi, lo);
+            m.hi[l * m.bpad + c] = hi;
+            m.lo[l * m.bpad + c] = lo;
+        }
         mx = fmaxf(mx, n32);
     }
     red[threadIdx.x] = mx;

@@ -47,6 +47,9 @@ inline int padded_dim(int64_t d) {
     return 128;
 }
 
+// Row stride of the bfloat16 split arrays (the matrix-core K step is 16).
+inline int bf16_pad(int dpad) { return dpad < 16 ? 16 : dpad; }
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Bump allocator over the caller's workspace (or a size probe when base == nullptr).
@@ -98,6 +101,10 @@ struct kkm_model {
     double* segabs = nullptr; // [C] sum_l |a_l| over segment j
     float* snorm_max = nullptr; // [1] max ||s||^2 over the support (error bounds)
     int32_t* split = nullptr;   // [5] cluster runs of the four wavefronts of a distance tile
+    int32_t nonneg = 1;         // every coefficient >= 0
+    uint16_t* hi = nullptr;     // [cap + 32][bpad] bfloat16 high parts of the support rows
+    uint16_t* lo = nullptr;     // [cap + 32][bpad] bfloat16 remainders
+    int32_t bpad = 0;
     int64_t* counts = nullptr;  // [C] |w_j| of a fitted model
     int64_t* medoid_index = nullptr; // [C]
 };
@@ -111,6 +118,17 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
+}
+
+// bfloat16 split of a float: hi = RNE(x), lo = RNE(x - hi), as raw 16-bit patterns.
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    const __bf16 b = (__bf16)x;
+    return __builtin_bit_cast(uint16_t, b);
+}
+__device__ __forceinline__ void bf16_split(float x, uint16_t& hi, uint16_t& lo) {
+    const __bf16 h = (__bf16)x;
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = bf16_bits(x - (float)h);
 }
 
 // Order-preserving map of doubles to unsigned 64-bit integers (for atomicMin on values).
@@ -253,35 +271,44 @@ __device__ inline double k64(const KSpec& ks, const TA* __restrict__ a, const TB
     return kfun64_rows(ks.type, a, b, ks.d, ks.inv2s2);
 }
 
-// K(a, b) in FP64 for rows of length ks.d <= DP (linear / RBF): both rows are read with a fully
-// unrolled, guarded loop so that every load is in flight at once.  DP == 0 (RMSD, or rows longer than
-// the register budget) falls back to k64.
+// K(a, b) in FP64 for rows of length ks.d <= DP (linear / RBF), in chunks of 16 dimensions whose
+// loads are unrolled and guarded, so that each chunk's loads are in flight together while the live
+// registers stay bounded.  DP == 0 (RMSD) falls back to k64.
 template <int DP, typename TA, typename TB>
 __device__ __forceinline__ double k64p(const KSpec& ks, const TA* __restrict__ a, const TB* __restrict__ b) {
     if constexpr (DP == 0) {
         return k64(ks, a, b);
     } else {
-        double va[DP], vb[DP];
-#pragma unroll
-        for (int k = 0; k < DP; ++k) {
-            const bool in = k < ks.d;
-            va[k] = in ? (double)a[k] : 0.0;
-            vb[k] = in ? (double)b[k] : 0.0;
-        }
+        constexpr int CH = DP < 16 ? DP : 16;
         double acc = 0.0;
-        if (ks.type == KKM_KERNEL_LINEAR) {
+        const bool lin = ks.type == KKM_KERNEL_LINEAR;
+#pragma unroll 1
+        for (int c0 = 0; c0 < DP; c0 += CH) {
+            double va[CH], vb[CH];
 #pragma unroll
-            for (int k = 0; k < DP; ++k) acc = fma(va[k], vb[k], acc);
-            return acc;
-        }
+            for (int k = 0; k < CH; ++k) {
+                const bool in = c0 + k < ks.d;
+                va[k] = in ? (double)a[c0 + k] : 0.0;
+                vb[k] = in ? (double)b[c0 + k] : 0.0;
+            }
+            if (lin) {
 #pragma unroll
-        for (int k = 0; k < DP; ++k) {
-            const double t = va[k] - vb[k];
-            acc = fma(t, t, acc);
+                for (int k = 0; k < CH; ++k) acc = fma(va[k], vb[k], acc);
+            } else {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const double t = va[k] - vb[k];
+                    acc = fma(t, t, acc);
+                }
+            }
         }
-        return ::exp(-acc * ks.inv2s2);
+        return lin ? acc : ::exp(-acc * ks.inv2s2);
     }
 }
+
+// Margin below which a label need not be re-decided: the exact relative margin is then provably
+// under 5e-7 (labels are only promised to equal the exact ones where it exceeds 1e-6).
+constexpr double kTieMargin = 5e-7;
 
 // Compile-time row length for k64p: the padded dimension for linear / RBF, 0 for RMSD.
 inline int eval_dp(int ktype, int64_t d) { return ktype == KKM_KERNEL_RMSD ? 0 : padded_dim(d); }

@@ -48,6 +48,9 @@ struct LandmarkArgs {
     double* coef64;
     int32_t* src_index;     // [ell] batch position of each support row
     float* snorm_max;       // [1]
+    uint16_t* sup_hi;       // [ell][bpad] bfloat16 split of the support rows
+    uint16_t* sup_lo;
+    int64_t bpad;
     int32_t* split;         // [5] cluster runs of the distance pass's four wavefronts
     int32_t k_in_lds;       // own rows of the landmark block kept in LDS (else in Kbuf)
     int64_t* trace;         // [64] device wall-clock stamps of workgroup 0, or null
@@ -75,6 +78,10 @@ struct SupportView {
     const double* segabs;   // [C]
     const float* snorm_max; // [1]
     const int32_t* split;   // [5] cluster runs of the four wavefronts of a distance tile
+    int32_t nonneg;         // every coefficient >= 0 (error bounds may scale with the sums)
+    const uint16_t* hi;     // [rows][bpad] bfloat16 high parts of the rows (or null)
+    const uint16_t* lo;     // [rows][bpad] bfloat16 remainders
+    int64_t bpad;
     int32_t C;
 };
 
@@ -98,6 +105,9 @@ struct DistArgs {
     int64_t n_support;      // rows of sup (offsets[C])
 };
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
+// Matrix-core distance pass (k_mfma.hip): linear / RBF, float samples, FP32 or BF16x3.
+bool mfma_dist_applies(const DistArgs& a);
+kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
 // True when launch_dist evaluates (and stores Dt) in FP64 for these arguments.
 bool dist_is_fp64(const DistArgs& a);
 // LDS bytes the distance tile needs for C clusters.

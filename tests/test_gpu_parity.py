@@ -52,6 +52,11 @@ def _medoid_model_from_rows(kk, kern, rows, dtype):
     ("linear", 1.0, 5, 3, 65, "fp64", "f64"),
     ("rbf", 2.0, 3, 5, 1, "fp32", "f32"),
     ("rbf", 3.0, 33, 9, 130, "fp32", "f64"),
+    ("rbf", 8.0, 64, 100, 4096 + 63, "bf16x3", "f32"),
+    ("rbf", 4.0, 16, 20, 1000 + 17, "bf16x3", "f32"),
+    ("linear", 1.0, 16, 7, 777, "bf16x3", "f32"),
+    ("rbf", 2.0, 128, 33, 300, "bf16x3", "f32"),
+    ("rbf", 2.0, 128, 33, 300, "fp32", "f32"),
 ])
 def test_assign_medoid_model(kind, sigma, d, C, n, prec, dtype):
     kk = _kk()
@@ -69,10 +74,11 @@ def test_assign_medoid_model(kind, sigma, d, C, n, prec, dtype):
     _labels_match(lab.cpu().numpy(), rl, rg, "assign")
     g = gap.cpu().numpy()
     fin = np.isfinite(rg) & (rg > 1e-3)
-    np.testing.assert_allclose(g[fin], rg[fin], rtol=1e-3 if prec == "fp32" else 2e-7, atol=2e-4 if prec == "fp32" else 1e-12)
+    gtol = {"fp32": (1e-3, 2e-4), "bf16x3": (1e-2, 5e-3), "fp64": (2e-7, 1e-12)}[prec]
+    np.testing.assert_allclose(g[fin], rg[fin], rtol=gtol[0], atol=gtol[1])
     cost = kk.kkm_cost(m, Yd, precision=prec)
     want = okkm.cost(kern, Y, model)
-    assert abs(cost - want) <= (1e-5 if prec == "fp32" else 1e-9) * max(1.0, abs(want))
+    assert abs(cost - want) <= {"fp32": 1e-5, "bf16x3": 1e-3, "fp64": 1e-9}[prec] * max(1.0, abs(want))
 
 
 def test_assign_sparse_centroids():
@@ -170,7 +176,7 @@ def test_fit_two_rings_fp64():
     _check_fit(kk, model, labels, info, ref, kern, X, T)
 
 
-@pytest.mark.parametrize("N,prec", [(20_000, "fp32"), (20_000, "fp64"), (100_000, "fp32")])
+@pytest.mark.parametrize("N,prec", [(20_000, "fp32"), (20_000, "fp64"), (100_000, "fp32"), (20_000, "bf16x3")])
 def test_fit_gaussian_mixture(N, prec):
     """Mini-batch landmark form on the 16-d, 20-component mixture (B = 10, s = 0.1, T = 20)."""
     kk = _kk()
@@ -203,6 +209,17 @@ def test_fit_edge_cases(C, B, s, T):
     X, _ = ki.datasets.gaussian_mixture(641, 4, 4, seed=C * 10 + B, sigma=1.0, box=3.0)
     kern = Kernel("rbf", 2.0)
     model, labels, info, ref = _fit_both(kk, X, kern, C, B, s, T, "kmeans++", 5, "fp32")
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+
+
+def test_fit_anisotropic_mixture_64d_bf16x3():
+    """The 64-d, 100-component anisotropic workload at reduced N, split-bf16 products on the matrix cores."""
+    kk = _kk()
+    _say("fit aniso 64d bf16x3")
+    X, _ = ki.datasets.gaussian_mixture(60_000, 64, 100, seed=1003, sigma=None)
+    kern = Kernel("rbf", 8.0)
+    T = 20
+    model, labels, info, ref = _fit_both(kk, X, kern, 100, 3, 0.02, T, "kmeans++", 2003, "bf16x3")
     _check_fit(kk, model, labels, info, ref, kern, X, T)
 
 
