@@ -167,13 +167,15 @@ class Model:
         self.kernel = kernel
         self.d, self.C, self.dtype = d, C, dtype
 
-    def __del__(self):
-        if getattr(self, "ptr", None) and self.ptr.value:
+    def __del__(self, _lib=lib, _null=ct.c_void_p):
+        # default arguments keep the loader reachable while the interpreter shuts down
+        ptr = getattr(self, "ptr", None)
+        if ptr is not None and ptr.value:
             try:
-                lib().kkm_model_free(self.ptr)
+                _lib().kkm_model_free(ptr)
             except Exception:
                 pass
-            self.ptr = ct.c_void_p(0)
+            self.ptr = _null(0)
 
 
 def kkm_model_create(kernel="rbf", d=1, C=1, max_support=None, dtype="f32", sigma=1.0, n_atoms=0) -> Model:

@@ -92,8 +92,9 @@ struct FitWs {
     int64_t* Midx;
     int64_t* wcount;
     double* Kbuf;
+    double* Kmed;
     int32_t* lab;
-    double* Sall;
+    int32_t* nlab_x;
     double* partial;
     int32_t* changed;
     int32_t* lab_final;
@@ -105,6 +106,7 @@ struct FitWs {
     double* snorm64;
     float* coef32;
     double* coef64;
+    float* sup_pan;
     uint16_t* sup_hi;
     uint16_t* sup_lo;
     int32_t* src_index;
@@ -112,6 +114,7 @@ struct FitWs {
     int32_t* split;        // [5]
     int32_t* counts_b;     // [C+1] cleared by the landmark phase of each batch; [C] = candidate count
     unsigned long long* colmin;   // [C]
+    double* colpart;              // [C][dist_block_cap(nmax)]
     int32_t* cand_q;
     int32_t* cand_j;
     double* cand_v;
@@ -125,6 +128,8 @@ struct FitWs {
     int32_t* mpart_c;
     double* gpart_v;
     int32_t* gpart_i;
+    void* mtarget;
+    double* malpha;
     int32_t* updates;      // [B]
     int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
     int64_t* trace;        // [64]
@@ -145,10 +150,11 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.Mself = c.take<double>(C);
     w.Midx = c.take<int64_t>(C);
     w.wcount = c.take<int64_t>(C);
-    w.Kbuf = c.take<double>((size_t)P.ellmax * P.ellmax);
+    w.Kbuf = c.take<double>((size_t)P.ellmax * landmark_ldk(P.ellmax));
+    w.Kmed = c.take<double>((size_t)P.ellmax * C);
     w.lab = c.take<int32_t>(2 * P.ellmax);
-    w.Sall = c.take<double>((size_t)2 * P.ellmax * C);
-    w.partial = c.take<double>((size_t)2 * P.gmax * C);
+    w.nlab_x = c.take<int32_t>((size_t)P.ellmax);
+    w.partial = c.take<double>((size_t)P.gmax * C);
     w.changed = c.take<int32_t>(P.T + 1);
     w.lab_final = c.take<int32_t>(P.ellmax);
     w.offsets = c.take<int32_t>(C + 1);
@@ -160,13 +166,15 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.snorm64 = c.take<double>(srows);
     w.coef32 = c.take<float>(srows);
     w.coef64 = c.take<double>(srows);
-    w.sup_hi = c.take<uint16_t>(srows * bf16_pad(P.dpad));
-    w.sup_lo = c.take<uint16_t>(srows * bf16_pad(P.dpad));
+    w.sup_pan = P.dtype == KKM_F32 ? c.take<float>(panel_rows(srows) * P.dpad) : nullptr;
+    w.sup_hi = c.take<uint16_t>(panel_rows(srows) * bf16_pad(P.dpad));
+    w.sup_lo = c.take<uint16_t>(panel_rows(srows) * bf16_pad(P.dpad));
     w.src_index = c.take<int32_t>(P.ellmax);
     w.snorm_max = c.take<float>(1);
     w.split = c.take<int32_t>(5);
     w.counts_b = c.take<int32_t>(C + 1);
     w.colmin = c.take<unsigned long long>(C);
+    w.colpart = c.take<double>((size_t)C * dist_block_cap(P.nmax));
     w.cand_q = c.take<int32_t>((size_t)P.cand_cap);
     w.cand_j = c.take<int32_t>((size_t)P.cand_cap);
     w.cand_v = c.take<double>((size_t)P.cand_cap);
@@ -180,6 +188,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
     w.gpart_v = c.take<double>((size_t)C * P.nchunk);
     w.gpart_i = c.take<int32_t>((size_t)C * P.nchunk);
+    w.mtarget = c.take<char>((size_t)2 * C * P.dpad * es);
+    w.malpha = c.take<double>(C);
     w.updates = c.take<int32_t>(P.B);
     w.info = c.take<int64_t>((size_t)3 * P.B * C);
     w.trace = c.take<int64_t>(64);
@@ -303,9 +313,9 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
     P.cand_cap = std::min<int64_t>((int64_t)P.nmax * P.C, (int64_t)1 << 30);
     if (dev) {
         for (int i = 0; i < P.B; ++i) {
-            const int G = landmark_grid(*dev, (int)P.ell[i]);
-            P.gmax = std::max(P.gmax, G);
-            if (landmark_lds_bytes_host((int)P.ell[i], P.C, G, false) > dev->max_lds_per_block)
+            const LandmarkShape sh = landmark_shape(*dev, (int)P.ell[i], P.C);
+            P.gmax = std::max(P.gmax, sh.grid);
+            if (!sh.k_in_lds && landmark_lds_bytes_host((int)P.ell[i], P.C, sh.grid, false) > dev->max_lds_per_block)
                 return fail(KKM_ERR_UNSUPPORTED, "landmark set of batch " + std::to_string(i) +
                                                      " too large for one workgroup's LDS; use more mini-batches");
         }
@@ -374,6 +384,7 @@ SupportView model_support(const kkm_model* m) {
     s.snorm_max = m->snorm_max;
     s.split = m->split;
     s.nonneg = m->nonneg;
+    s.pan = m->pan;
     s.hi = m->hi;
     s.lo = m->lo;
     s.bpad = m->bpad;
@@ -512,7 +523,9 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.ell = ell;
         la.C = C;
         la.max_updates = P.T - 1;
-        la.grid = landmark_grid(dev, ell);
+        const LandmarkShape lsh = landmark_shape(dev, ell, C);
+        la.grid = lsh.grid;
+        la.k_in_lds = lsh.k_in_lds;
         la.ktype = kernel->type;
         la.n_atoms = kernel->n_atoms;
         la.inv2s2 = ks.inv2s2;
@@ -522,8 +535,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.Mpad = P.dpad;
         la.Mself = w.Mself;
         la.Kbuf = w.Kbuf;
+        la.ldk = landmark_ldk(ell);
+        la.Kmed = w.Kmed;
         la.lab = w.lab;
-        la.Sall = w.Sall;
+        la.nlab_x = w.nlab_x;
         la.partial = w.partial;
         la.changed = w.changed;
         la.zero_ints = w.counts_b;
@@ -542,10 +557,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.src_index = w.src_index;
         la.snorm_max = w.snorm_max;
         la.split = w.split;
+        la.sup_pan = w.sup_pan;
         la.sup_hi = w.sup_hi;
         la.sup_lo = w.sup_lo;
         la.bpad = bf16_pad(P.dpad);
-        la.k_in_lds = landmark_k_in_lds(dev, ell, C, la.grid) ? 1 : 0;
         la.trace = (i == 0 && info && info->landmark_trace) ? w.trace : nullptr;
         la.barrier = w.barrier;
         la.colmin = w.colmin;
@@ -568,6 +583,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sv.snorm_max = w.snorm_max;
         sv.split = w.split;
         sv.nonneg = 1;
+        sv.pan = w.sup_pan;
         sv.hi = w.sup_hi;
         sv.lo = w.sup_lo;
         sv.bpad = bf16_pad(P.dpad);
@@ -589,6 +605,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         da.refine_count = w.refine_counts + i;
         da.nonfinite = w.flags;
         da.colmin = w.colmin;
+        da.colpart = w.colpart;
+        da.colpart_cap = dist_block_cap(P.nmax);
         da.n_support = ell;
         KKM_TRY(tm.begin());
         KKM_TRY(launch_dist(da, dev, s));
@@ -627,6 +645,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.cand_cap = (int32_t)P.cand_cap;
         sa.gpart_v = w.gpart_v;
         sa.gpart_i = w.gpart_i;
+        sa.mtarget = w.mtarget;
+        sa.malpha = w.malpha;
 
         sa.info_bmed = w.info + (size_t)i * C;
         sa.info_bcnt = w.info + (size_t)(P.B + i) * C;

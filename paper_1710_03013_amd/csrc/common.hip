@@ -196,8 +196,9 @@ kkm_status kkm_model_create(const kkm_kernel* kernel, int64_t d, int32_t C, int6
         m->snorm64 = c.take<double>(rows);
         m->coef32 = c.take<float>(rows);
         m->coef64 = c.take<double>(rows);
-        m->hi = c.take<uint16_t>(rows * m->bpad);
-        m->lo = c.take<uint16_t>(rows * m->bpad);
+        m->pan = dtype == KKM_F32 ? c.take<float>(panel_rows(rows) * m->dpad) : nullptr;
+        m->hi = c.take<uint16_t>(panel_rows(rows) * m->bpad);
+        m->lo = c.take<uint16_t>(panel_rows(rows) * m->bpad);
         m->offsets = c.take<int32_t>(C + 1);
         m->self = c.take<double>(C);
         m->segabs = c.take<double>(C);

@@ -168,6 +168,7 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
     __syncthreads();
 
     const float E = fmaxf(fmaxf(Ew[0][ql], Ew[1][ql]), fmaxf(Ew[2][ql], Ew[3][ql]));
+    bool need = false;   // row listed for the FP64 re-decision
     if (wave == 0 && part == 0 && active) {
         TC best = (TC)kInf, second = (TC)kInf;
         int bj = 0;
@@ -186,11 +187,9 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
         }
         const double gap = (double)second - (double)best;
         const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)ev.kqq));
-        if (E > 0.0f && gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale) {
-            const int pos = atomicAdd(a.refine_count, 1);
-            a.refine_list[pos] = (int32_t)q;
-        }
+        need = E > 0.0f && gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale;
     }
+    if (wave == 0) append_rows(need, q, a.refine_count, a.refine_list);
     if (a.Dt) {
         // store the tile and lower each column's running minimum of D + E (order-independent)
         TC* Dt = static_cast<TC*>(static_cast<void*>(a.Dt));
@@ -201,7 +200,7 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
                 double v = (active && part == 0) ? (double)D + (double)E : kInf;
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
-                if (lane == 0 && v < kInf) atomicMin(a.colmin + j, ord_enc(v));
+                if (lane == 0) a.colpart[(int64_t)j * a.colpart_cap + blockIdx.x] = v;
             }
         }
     }
@@ -371,6 +370,17 @@ __global__ __launch_bounds__(256) void sum_partial_kernel(const double* __restri
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// One wavefront per cluster: minimum of the workgroup partials of D + E.
+__global__ __launch_bounds__(64) void colmin_reduce_kernel(const double* __restrict__ colpart, int64_t ld, int64_t nblk,
+                                                           unsigned long long* colmin) {
+    const int j = blockIdx.x;
+    double v = kInf;
+    for (int64_t b = threadIdx.x; b < nblk; b += 64) v = fmin(v, colpart[(int64_t)j * ld + b]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    if (threadIdx.x == 0) colmin[j] = v < kInf ? ord_enc(v) : ~0ull;
+}
+
 template <class Ev, int LPQ>
 kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     using TC = typename TcOf<Ev>::type;
@@ -381,8 +391,10 @@ kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t
     const void* fn = reinterpret_cast<const void*>(&dist_kernel<Ev, LPQ>);
     KKM_TRY(allow_dynamic_lds(fn, lds));
     const unsigned blocks = (unsigned)((a.q.n + QT - 1) / QT);
+    if (a.colmin && (int64_t)blocks > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
     hipLaunchKernelGGL((dist_kernel<Ev, LPQ>), dim3(blocks), dim3(256), lds, s, a);
     KKM_HIP(hipGetLastError());
+    if (a.colmin) return launch_colmin_reduce(a, blocks, s);
     return KKM_OK;
 }
 
@@ -452,6 +464,12 @@ kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     });
+}
+
+kkm_status launch_colmin_reduce(const DistArgs& a, int64_t nblk, hipStream_t s) {
+    hipLaunchKernelGGL(colmin_reduce_kernel, dim3(a.sup.C), dim3(64), 0, s, a.colpart, a.colpart_cap, nblk, a.colmin);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
 }
 
 kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s) {

@@ -47,12 +47,15 @@ struct LdsLayout {
     double* rcnt;      // [C] 1 / c_j
 };
 
+// Row stride of K_LL (in HBM and LDS): even, so rows start 16-byte aligned.
+__host__ __device__ inline int k_ld(int ell) { return (ell + 1) & ~1; }
+
 __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R, bool k_in_lds) {
     const int nchunks = (ell + 63) / 64;
     size_t b = 0;
-    if (k_in_lds) b += sizeof(double) * (size_t)R * ell;
+    if (k_in_lds) b += sizeof(double) * (size_t)R * k_ld(ell);
     b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)(C > 256 ? C : 256);
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
@@ -77,7 +80,7 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool 
     LdsLayout L;
     size_t b = 0;
     L.K = reinterpret_cast<double*>(base);
-    if (k_in_lds) b += sizeof(double) * (size_t)R * ell;
+    if (k_in_lds) b += sizeof(double) * (size_t)R * k_ld(ell);
     b = al16(b); L.red = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)(C > 256 ? C : 256);
     b = al16(b); L.lbl = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.perm = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
@@ -98,7 +101,7 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool 
 }
 
 // Stable counting sort of the ell labels in L.lbl into L.perm / L.off (whole workgroup).
-__device__ void csr_sort(const LdsLayout& L, int ell, int C) {
+__device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int nchunks = (ell + 63) / 64;
@@ -173,7 +176,7 @@ __device__ void csr_sort(const LdsLayout& L, int ell, int C) {
 // S[r][j] = sum over segment j (CSR of L.lbl) of own row r, from scratch: every 64-element chunk of a
 // segment is summed in order by one thread, then the chunk sums of each (row, segment) in order.
 // Also sets L.cnt.  Whole workgroup; expects csr_sort(L) done.
-__device__ void full_sums(const LdsLayout& L, const double* Krows, int nr, int ell, int C) {
+__device__ __forceinline__ void full_sums(const LdsLayout& L, const double* Krows, int ldk, int nr, int C) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int nq = L.qoff[C];
     for (int p = tid; p < nr * nq; p += nt) {
@@ -186,7 +189,7 @@ __device__ void full_sums(const LdsLayout& L, const double* Krows, int nr, int e
         const int j = lo_j;
         const int k0 = L.off[j] + (qi - L.qoff[j]) * 64;
         const int k1 = min(L.off[j + 1], k0 + 64);
-        const double* Kr = Krows + (int64_t)r * ell;
+        const double* Kr = Krows + (int64_t)r * ldk;
         double s = 0.0;
 #pragma unroll 8
         for (int k = k0; k < k1; ++k) s += Kr[L.perm[k]];
@@ -204,29 +207,42 @@ __device__ void full_sums(const LdsLayout& L, const double* Krows, int nr, int e
 }
 
 // Barrier over the co-resident workgroups of the cooperative launch: a monotonically increasing
-// arrival counter (cleared by the block kernel launched just before on the same stream).  Writes are
-// released at agent scope before arriving; after the wait, an acquire fence drops stale cache lines
-// so that plain loads see the other workgroups' writes.  The wait is bounded: past kSpinCap polls
-// the workgroup records an error and proceeds, so the kernel always terminates.
+// arrival counter (cleared by a kernel launched just before on the same stream).  After the
+// workgroup barrier, one thread arrives with a release RMW at agent scope (one L2 write-back covers
+// the workgroup's writes), polls with relaxed loads (no cache maintenance per poll), and issues one
+// acquire fence once the count is reached; the closing workgroup barrier passes that on to the other
+// threads, whose plain loads then see every workgroup's writes.  The wait is bounded: past kSpinCap
+// polls the workgroup records an error and proceeds, so the kernel always terminates.
 constexpr unsigned kSpinCap = 1u << 26;
 
 __device__ __forceinline__ void grid_barrier(const LandmarkArgs& a, unsigned& target) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     target += gridDim.x;
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned polls = 0;
-        while (__hip_atomic_load(a.barrier, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++polls > kSpinCap) {
                 atomicOr(a.error, 1);
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Counters the loop and the later kernels of the batch expect cleared (one workgroup).
+__device__ __forceinline__ void reset_batch_state(const LandmarkArgs& a) {
+    for (int i = threadIdx.x; i <= a.max_updates; i += blockDim.x) a.changed[i] = 0;
+    for (int i = threadIdx.x; i < a.n_zero_ints; i += blockDim.x) a.zero_ints[i] = 0;
+    for (int i = threadIdx.x; i < a.C; i += blockDim.x) a.colmin[i] = ~0ull;
+    if (threadIdx.x == 0) {
+        *a.barrier = 0u;
+        *a.error = 0;
+        *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
+    }
 }
 
 // Wall-clock stamp of workgroup 0 (profiling aid): slot 0 holds the count.
@@ -255,16 +271,7 @@ __global__ __launch_bounds__(256) void landmark_block_kernel(LandmarkArgs a, int
         while (t >= tiles - tr) { t -= tiles - tr; ++tr; }
         tc = tr + t;
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-        for (int i = threadIdx.x; i <= a.max_updates; i += blockDim.x) a.changed[i] = 0;
-        for (int i = threadIdx.x; i < a.n_zero_ints; i += blockDim.x) a.zero_ints[i] = 0;
-        for (int i = threadIdx.x; i < a.C; i += blockDim.x) a.colmin[i] = ~0ull;
-        if (threadIdx.x == 0) {
-            *a.barrier = 0u;
-            *a.error = 0;
-            *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
-        }
-    }
+    if (blockIdx.x == 0 && blockIdx.y == 0) reset_batch_state(a);
     double* A = reinterpret_cast<double*>(smem);          // [32][d]
     double* Bm = A + 32 * a.d;                             // [32][d]
     const int r0 = tr * 32, c0 = tc * 32;
@@ -284,8 +291,8 @@ __global__ __launch_bounds__(256) void landmark_block_kernel(LandmarkArgs a, int
         const int r = r0 + ty, c = c0 + tx;
         if (r < ell && c < ell && (!sym || tr < tc || ty <= tx)) {
             const double v = k64(ks, A + ty * a.d, Bm + tx * a.d);
-            a.Kbuf[(int64_t)r * ell + c] = v;
-            if (sym) a.Kbuf[(int64_t)c * ell + r] = v;
+            a.Kbuf[(int64_t)r * a.ldk + c] = v;
+            if (sym) a.Kbuf[(int64_t)c * a.ldk + r] = v;
         }
     }
 }
@@ -335,7 +342,114 @@ __global__ __launch_bounds__(256) void landmark_init_kernel(LandmarkArgs a) {
     if (threadIdx.x == 0) a.lab[r] = si[0] < a.C ? si[0] : 0;
 }
 
+// 1'. Linear / RBF kernels: K_LL and, for the Eq. 8 initialisation, K(x_l, m_j) for the C global
+//     medoids, in FP64: one 64 x 64 tile of the (landmarks) x (landmarks, medoids) matrix per
+//     workgroup, 4 x 4 entries per thread, both row sets staged in LDS 16 dimensions at a time.
+//     Same arithmetic as the FP64 evaluator (dimension order; explicit differences for RBF).
+//     Block (0, 0) also clears the loop's counters.
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
+    constexpr int T = 64, CH = DP < 16 ? DP : 16;
+    __shared__ double As[CH][T + 1];
+    __shared__ double Bs[CH][T + 1];
+    const int ell = a.ell, C = a.C, d = (int)a.d;
+    const int ncol = ell + (a.init_mode ? C : 0);
+    const int r0 = blockIdx.y * T, c0 = blockIdx.x * T;
+    if (blockIdx.x == 0 && blockIdx.y == 0) reset_batch_state(a);
+    if (c0 >= ncol) return;   // uniform
+    const TI* X = static_cast<const TI*>(a.X) + a.base * a.d;
+    const TI* M = static_cast<const TI*>(a.M);
+    const int64_t rs = a.stride * a.d;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const bool lin = a.ktype == KKM_KERNEL_LINEAR;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < DP; k0 += CH) {
+        __syncthreads();
+        for (int p = threadIdx.x; p < T * CH; p += blockDim.x) {
+            const int rr = p / CH, k = p - rr * CH;
+            const int dim = k0 + k;
+            const int r = r0 + rr, c = c0 + rr;
+            As[k][rr] = (r < ell && dim < d) ? (double)X[(int64_t)a.lm[r] * rs + dim] : 0.0;
+            double bv = 0.0;
+            if (c < ncol && dim < d)
+                bv = c < ell ? (double)X[(int64_t)a.lm[c] * rs + dim] : (double)M[(int64_t)(c - ell) * a.Mpad + dim];
+            Bs[k][rr] = bv;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < CH; ++k) {
+            double av[4], bw[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[k][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bw[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (lin) {
+                        acc[i][j] = fma(av[i], bw[j], acc[i][j]);
+                    } else {
+                        const double t = av[i] - bw[j];
+                        acc[i][j] = fma(t, t, acc[i][j]);
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+            if (r < ell && c < ncol) {
+                const double v = lin ? acc[i][j] : ::exp(-acc[i][j] * a.inv2s2);
+                if (c < ell) a.Kbuf[(int64_t)r * a.ldk + c] = v;
+                else a.Kmed[(int64_t)r * C + (c - ell)] = v;
+            }
+        }
+}
+
+// 2'. Initial labels from K(x_l, m_j) (Eq. 8): one wavefront per landmark, lowest j among equal
+//     minima over the clusters that have a medoid (0 when none has); or the given labels.
+__global__ __launch_bounds__(256) void landmark_init_from_k_kernel(LandmarkArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (l >= a.ell) return;   // uniform over the wavefront
+    const int C = a.C;
+    if (a.init_mode == 0) {
+        if (lane == 0) a.lab[l] = a.lab_init[l];
+        return;
+    }
+    const double kxx = a.Kbuf[(int64_t)l * a.ldk + l];
+    double bv = kInf;
+    int bj = C;
+    for (int j = lane; j < C; j += 64) {
+        const double ms = a.Mself[j];
+        if (!(ms < kInf)) continue;
+        const double v = kxx - 2.0 * a.Kmed[(int64_t)l * C + j] + ms;
+        if (bj == C || v < bv) { bv = v; bj = j; }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double v2 = __shfl_xor(bv, o, 64);
+        const int j2 = __shfl_xor(bj, o, 64);
+        if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
+    }
+    if (lane == 0) a.lab[l] = bj < C ? bj : 0;
+}
+
 // 3-4. The landmark loop and the centroid support (cooperative launch, grid <= device CUs).
+//
+// Workgroup wg owns landmark rows [r0, r1): their rows of K (in LDS when they fit) and of S.  Every
+// workgroup keeps all landmark labels and cluster counts.  One update takes two exchanges:
+//   publish the own part of sum_{m in L_j} S[m][j]  -> barrier -> g^ (same order everywhere),
+//   Eq. 15 for the own rows, publish their labels    -> barrier -> all labels, changed list,
+//   own rows of S follow the changes (incrementally in landmark order, or from scratch).
+// A buffer is rewritten only after the barrier that ends every reader's use of it.
 template <typename TI>
 __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -343,48 +457,54 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int wg = blockIdx.x, G = gridDim.x;
     const int ell = a.ell, C = a.C;
+    const int ldk = (int)a.ldk;
     const int R = (ell + G - 1) / G;
     const int r0 = min(ell, wg * R), r1 = min(ell, r0 + R), nr = r1 - r0;
     const bool kl = a.k_in_lds != 0;
     LdsLayout L = carve_lds(smem, ell, C, R, kl);
     const TI* X = static_cast<const TI*>(a.X);
-    const KSpec ks{a.ktype, a.n_atoms, a.d, a.inv2s2};
     auto row = [&](int pos) { return X + (a.base + (int64_t)pos * a.stride) * a.d; };
-    double* Krows = a.Kbuf + (int64_t)r0 * ell;     // own row r at Krows + r * ell
+    const double* Krows = a.Kbuf + (int64_t)r0 * ldk;     // own row r at Krows + r * ldk
     unsigned target = 0;
 
     stamp(a);
     if (kl) {
-        for (int64_t i = tid; i < (int64_t)nr * ell; i += nt) L.K[i] = Krows[i];
+        // the own rows are one contiguous, 16-byte aligned block: copy it as double2
+        typedef double dvec2 __attribute__((ext_vector_type(2)));
+        const int64_t n2 = (int64_t)nr * ldk / 2;
+        const dvec2* src = reinterpret_cast<const dvec2*>(Krows);
+        dvec2* dst = reinterpret_cast<dvec2*>(L.K);
+        int64_t i = tid;
+        for (; i + 7 * nt < n2; i += 8 * nt) {
+            dvec2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[i + u * nt];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dst[i + u * nt] = v[u];
+        }
+        for (; i < n2; i += nt) dst[i] = src[i];
         Krows = L.K;
     }
     for (int m = tid; m < ell; m += nt) {
-        L.kall[m] = a.Kbuf[(int64_t)m * ell + m];
+        L.kall[m] = a.Kbuf[(int64_t)m * ldk + m];
         L.lbl[m] = a.lab[m];
     }
     __syncthreads();
     stamp(a);
 
     csr_sort(L, ell, C);
-    full_sums(L, Krows, nr, ell, C);
+    full_sums(L, Krows, ldk, nr, C);
     stamp(a);
 
-    // One barrier per update: publish own rows of S and the partial g^ (buffers alternate between
-    // updates: a workgroup can only write a buffer again after the next barrier, which the others
-    // reach after their reads); then every workgroup reads all of S, forms g^ and decides every
-    // landmark's label (identical work everywhere).  Own rows of S then follow the label changes,
-    // incrementally in landmark order, or from scratch when many labels changed.
     const int nsub = C < nt ? nt / C : 1;     // threads per cluster in the partial reduction
     int it = 0;
     for (;;) {
-        double* Sall = a.Sall + (int64_t)(it & 1) * ell * C;
-        double* partial = a.partial + (int64_t)(it & 1) * G * C;
-        for (int p = tid; p < nr * C; p += nt) Sall[(int64_t)r0 * C + p] = L.S[p];
+        // own part of sum_{m in L_j} S[m][j], in row order
         for (int j = tid; j < C; j += nt) {
             double acc = 0.0;
             for (int r = 0; r < nr; ++r)
                 if (L.lbl[r0 + r] == j) acc += L.S[r * C + j];
-            partial[(int64_t)wg * C + j] = acc;
+            a.partial[(int64_t)wg * C + j] = acc;
             L.rcnt[j] = L.cnt[j] > 0 ? 1.0 / (double)L.cnt[j] : 0.0;
         }
         grid_barrier(a, target);
@@ -394,7 +514,7 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             const int j = p % C, sub = p / C;
             double acc = 0.0;
 #pragma unroll 4
-            for (int g = sub; g < G; g += nsub) acc += partial[(int64_t)g * C + j];
+            for (int g = sub; g < G; g += nsub) acc += a.partial[(int64_t)g * C + j];
             L.red[p] = acc;
         }
         __syncthreads();
@@ -405,22 +525,29 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             L.gh[j] = cj > 0.0 ? acc / (cj * cj) : kInf;
         }
         __syncthreads();
-        stamp(a);
         if (it >= a.max_updates) break;
 
-        // Eq. 15 for every landmark
-        for (int m = tid; m < ell; m += nt) {
-            const double* Sm = Sall + (int64_t)m * C;
-            double best = kInf;
-            int bj = L.lbl[m];
-            bool found = false;
-            for (int j = 0; j < C; ++j) {
+        // Eq. 15 for the own rows (one wavefront per row; lowest j among equal minima)
+        for (int r = wave; r < nr; r += nwaves) {
+            const int m = r0 + r;
+            double bv = kInf;
+            int bj = C;
+            for (int j = lane; j < C; j += 64) {
                 if (L.cnt[j] == 0) continue;
-                const double dj = L.kall[m] - 2.0 * Sm[j] * L.rcnt[j] + L.gh[j];
-                if (!found || dj < best) { best = dj; bj = j; found = true; }
+                const double dj = L.kall[m] - 2.0 * L.S[r * C + j] * L.rcnt[j] + L.gh[j];
+                if (bj == C || dj < bv) { bv = dj; bj = j; }
             }
-            L.nlab[m] = bj;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double v2 = __shfl_xor(bv, o, 64);
+                const int j2 = __shfl_xor(bj, o, 64);
+                if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
+            }
+            if (lane == 0) a.nlab_x[m] = bj < C ? bj : L.lbl[m];
         }
+        grid_barrier(a, target);
+        stamp(a);
+        for (int m = tid; m < ell; m += nt) L.nlab[m] = a.nlab_x[m];
         __syncthreads();
         // changed landmarks in index order (first wave)
         if (wave == 0) {
@@ -443,12 +570,12 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             for (int m = tid; m < ell; m += nt) L.lbl[m] = L.nlab[m];
             __syncthreads();
             csr_sort(L, ell, C);
-            full_sums(L, Krows, nr, ell, C);
+            full_sums(L, Krows, ldk, nr, C);
         } else {
             // S[r][j] -= K(r, m) for changes leaving j, += for changes entering j, in index order
             for (int p = tid; p < nr * C; p += nt) {
                 const int r = p / C, j = p - r * C;
-                const double* Kr = Krows + (int64_t)r * ell;
+                const double* Kr = Krows + (int64_t)r * ldk;
                 double sv = L.S[p];
                 for (int t = 0; t < nch; ++t) {
                     const int m = L.chg[t];
@@ -494,6 +621,7 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         for (int m = tid; m < ell; m += nt) a.lab[ell + m] = L.lbl[m];   // final landmark labels
     }
     TI* sup = static_cast<TI*>(a.support);
+    float nmax = 0.0f;
     for (int k = wg * nt + tid; k < ell; k += G * nt) {
         const int m = L.perm[k];
         const int j = L.lbl[m];
@@ -513,21 +641,35 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         a.coef64[k] = 1.0 / (double)cnt;
         a.coef32[k] = (float)(1.0 / (double)cnt);
         a.src_index[k] = a.lm[m];
-        for (int64_t c = 0; c < a.bpad; ++c) {
-            uint16_t hi = 0, lo = 0;
-            if (c < a.d) bf16_split((float)src[c], hi, lo);
-            a.sup_hi[(int64_t)k * a.bpad + c] = hi;
-            a.sup_lo[(int64_t)k * a.bpad + c] = lo;
-        }
-        atomicMax(reinterpret_cast<unsigned int*>(a.snorm_max), __float_as_uint(n32));
+        const int PD = (int)a.dpad;
+        const bool panels = a.ktype != KKM_KERNEL_RMSD;   // power-of-two padded rows only
+        if (panels && a.sup_pan)
+            for (int c = 0; c < PD; ++c) a.sup_pan[panel32_index(k, c, PD)] = c < a.d ? (float)src[c] : 0.0f;
+        if (panels && PD >= 16)
+            for (int c = 0; c < PD; ++c) {
+                uint16_t hi = 0, lo = 0;
+                if (c < a.d) bf16_split((float)src[c], hi, lo);
+                a.sup_hi[panel16_index(k, c, PD)] = hi;
+                a.sup_lo[panel16_index(k, c, PD)] = lo;
+            }
+        nmax = fmaxf(nmax, n32);
     }
+    // one atomic per workgroup for the largest squared norm (non-negative floats order as integers)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nmax = fmaxf(nmax, __shfl_xor(nmax, o, 64));
+    if (lane == 0 && nmax > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(a.snorm_max), __float_as_uint(nmax));
     // rows [ell, ell + 32) are read by whole-tile loads: keep them zero
     for (int k = ell + wg * nt + tid; k < ell + 32; k += G * nt) {
         for (int64_t c = 0; c < a.dpad; ++c) sup[(int64_t)k * a.dpad + c] = TI(0);
-        for (int64_t c = 0; c < a.bpad; ++c) {
-            a.sup_hi[(int64_t)k * a.bpad + c] = 0;
-            a.sup_lo[(int64_t)k * a.bpad + c] = 0;
-        }
+        const int PD = (int)a.dpad;
+        const bool panels = a.ktype != KKM_KERNEL_RMSD;
+        if (panels && a.sup_pan)
+            for (int c = 0; c < PD; ++c) a.sup_pan[panel32_index(k, c, PD)] = 0.0f;
+        if (panels && PD >= 16)
+            for (int c = 0; c < PD; ++c) {
+                a.sup_hi[panel16_index(k, c, PD)] = 0;
+                a.sup_lo[panel16_index(k, c, PD)] = 0;
+            }
         a.snorm64[k] = 0.0;
         a.snorm32[k] = 0.0f;
         a.coef64[k] = 0.0;
@@ -542,31 +684,30 @@ size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds) {
     return landmark_lds_bytes(ell, C, R, k_in_lds);
 }
 
-int landmark_grid(const DeviceInfo& dev, int ell) {
+LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C) {
     // at least 4 landmark rows per workgroup and at most KKM_LANDMARK_WGS workgroups (default 64):
-    // the loop is bound by its two grid barriers per update, whose cost grows with the grid
+    // the loop is bound by its grid barriers, whose cost grows with the grid; the grid is widened
+    // (up to the device) when that lets the own rows of K_LL stay in LDS
     static int cap = [] {
         const char* e = std::getenv("KKM_LANDMARK_WGS");
         const int v = e ? std::atoi(e) : 0;
         return v > 0 ? v : 64;
     }();
-    int G = (ell + 3) / 4;
-    if (G > cap) G = cap;
-    if (G > dev.num_cus) G = dev.num_cus;
-    if (G < 1) G = 1;
-    return G;
-}
-
-bool landmark_k_in_lds(const DeviceInfo& dev, int ell, int C, int G) {
-    static const bool allowed = [] {
+    static const bool k_lds_allowed = [] {
         const char* e = std::getenv("KKM_LANDMARK_K_IN_LDS");
         return !(e && e[0] == '0');
     }();
-    return allowed && landmark_lds_bytes_host(ell, C, G, true) <= dev.max_lds_per_block;
+    const int gmax = std::max(1, std::min(dev.num_cus, ell));
+    const int G0 = std::max(1, std::min((ell + 3) / 4, std::min(cap, gmax)));
+    if (k_lds_allowed)
+        for (int G = G0; G <= gmax; G = G < gmax ? std::min(gmax, G + std::max(1, G / 8)) : gmax + 1)
+            if (landmark_lds_bytes_host(ell, C, G, true) <= dev.max_lds_per_block) return LandmarkShape{G, 1};
+    return LandmarkShape{G0, 0};
 }
 
 kkm_status launch_landmark_phase(const LandmarkArgs& args, int dtype, const DeviceInfo& dev, hipStream_t stream) {
     const int G = args.grid;
+    if (args.ldk != k_ld(args.ell)) return fail(KKM_ERR_INTERNAL, "landmark block stride");
     const size_t lds = landmark_lds_bytes_host(args.ell, args.C, G, args.k_in_lds != 0);
     if (lds > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "landmark set too large for one workgroup's LDS (l=" +
@@ -575,19 +716,29 @@ kkm_status launch_landmark_phase(const LandmarkArgs& args, int dtype, const Devi
     const size_t lds_tile = sizeof(double) * 64 * (size_t)args.d;
     const size_t lds_row = sizeof(double) * (size_t)args.d;
     if (lds_tile > dev.max_lds_per_block) return fail(KKM_ERR_UNSUPPORTED, "sample dimension too large");
-    const int tiles = (args.ell + 31) / 32;
-    const dim3 bgrid = args.ktype != KKM_KERNEL_RMSD ? dim3((unsigned)(tiles * (tiles + 1) / 2), 1)
-                                                     : dim3((unsigned)tiles, (unsigned)tiles);
-    if (dtype == KKM_F64)
-        hipLaunchKernelGGL(landmark_block_kernel<double>, bgrid, dim3(256), lds_tile, stream, args, tiles);
-    else
-        hipLaunchKernelGGL(landmark_block_kernel<float>, bgrid, dim3(256), lds_tile, stream, args, tiles);
-    KKM_HIP(hipGetLastError());
     KKM_TRY(dispatch_dp(eval_dp(args.ktype, args.d), [&]<int DP>() -> kkm_status {
-        if (dtype == KKM_F64)
-            hipLaunchKernelGGL((landmark_init_kernel<double, DP>), dim3(args.ell), dim3(256), lds_row, stream, args);
-        else
-            hipLaunchKernelGGL((landmark_init_kernel<float, DP>), dim3(args.ell), dim3(256), lds_row, stream, args);
+        if constexpr (DP > 0) {
+            const int ncol = args.ell + (args.init_mode ? args.C : 0);
+            const dim3 kgrid((unsigned)((ncol + 63) / 64), (unsigned)((args.ell + 63) / 64));
+            if (dtype == KKM_F64)
+                hipLaunchKernelGGL((landmark_k_kernel<double, DP>), kgrid, dim3(256), 0, stream, args);
+            else
+                hipLaunchKernelGGL((landmark_k_kernel<float, DP>), kgrid, dim3(256), 0, stream, args);
+            KKM_HIP(hipGetLastError());
+            hipLaunchKernelGGL(landmark_init_from_k_kernel, dim3((unsigned)((args.ell + 3) / 4)), dim3(256), 0, stream, args);
+        } else {
+            const int tiles = (args.ell + 31) / 32;
+            const dim3 bgrid((unsigned)tiles, (unsigned)tiles);
+            if (dtype == KKM_F64) {
+                hipLaunchKernelGGL(landmark_block_kernel<double>, bgrid, dim3(256), lds_tile, stream, args, tiles);
+                KKM_HIP(hipGetLastError());
+                hipLaunchKernelGGL((landmark_init_kernel<double, DP>), dim3(args.ell), dim3(256), lds_row, stream, args);
+            } else {
+                hipLaunchKernelGGL(landmark_block_kernel<float>, bgrid, dim3(256), lds_tile, stream, args, tiles);
+                KKM_HIP(hipGetLastError());
+                hipLaunchKernelGGL((landmark_init_kernel<float, DP>), dim3(args.ell), dim3(256), lds_row, stream, args);
+            }
+        }
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     }));

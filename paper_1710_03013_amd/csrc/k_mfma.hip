@@ -6,8 +6,8 @@
 // A workgroup owns 32 samples (the N dimension of a 32x32 MFMA tile); each of its four wavefronts
 // walks a cluster-aligned quarter of the support in 32-row tiles (the M dimension) aligned to
 // multiples of 32.  The two lane halves take contiguous halves of the dimensions as their share of
-// the K index (any order of K gives the same dot product), so operand fragments are contiguous
-// loads.  Result lane l holds rows 8(i/4) + 4(l/32) + i%4 of sample l%32 (i = 0..15): the kernel
+// the K index (any order of K gives the same dot product); the support is read from its panel
+// layout, in which each step's fragment is 64 consecutive vectors.  Result lane l holds rows 8(i/4) + 4(l/32) + i%4 of sample l%32 (i = 0..15): the kernel
 // function is applied in registers, and each segment's sum is a masked sum over the lane's 16
 // values plus one exchange with the partner lane l^32, accumulated in the order of the tiles.
 //
@@ -59,12 +59,27 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     float xq[H];
     bool ok = true;
     float qn = 0.0f;
+    const bool xvec = H % 4 == 0 && a.q.d == DP && (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0;
+    if (xvec) {
+        const float4* x4 = reinterpret_cast<const float4*>(xr + h * H);
+#pragma unroll
+        for (int v = 0; v < H / 4; ++v) {
+            const float4 t = x4[v];
+            xq[4 * v] = t.x;
+            xq[4 * v + 1] = t.y;
+            xq[4 * v + 2] = t.z;
+            xq[4 * v + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < H; ++s) {
+            const int dim = h * H + s;
+            xq[s] = dim < a.q.d ? (float)xr[dim] : 0.0f;
+        }
+    }
 #pragma unroll
     for (int s = 0; s < H; ++s) {
-        const int dim = h * H + s;
-        const TI v = dim < a.q.d ? xr[dim] : TI(0);
-        ok = ok && isfinite((double)v);
-        xq[s] = (float)v;
+        ok = ok && isfinite(xq[s]);
         qn = fmaf(xq[s], xq[s], qn);
     }
     qn += __shfl_xor(qn, 32, 64);
@@ -90,7 +105,6 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     const int start = off[j0], end = off[j1];
     int j = j0;
     float accf = 0.0f;
-    const float* rows32 = static_cast<const float*>(a.sup.rows);
     auto finalize = [&](int jj) {
         const int lo = off[jj], hi = off[jj + 1];
         const double g = a.sup.self[jj];
@@ -123,24 +137,43 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
 
     for (int r0 = start & ~31; r0 < end; r0 += 32) {
         const int tile_end = min(r0 + 32, end);
-        // A fragment: support row r0 + col, the lane half's dimensions
-        const int64_t arow = r0 + col;
+        // A fragment: support row r0 + col, the lane half's dimensions, read from the panel of the
+        // tile (64 consecutive vectors per step group)
+        const int64_t tile = r0 >> 5;
         floatx16 acc = {};
         if constexpr (BF3) {
-            const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi + arow * a.sup.bpad + h * H);
-            const bf16x8* al = reinterpret_cast<const bf16x8*>(a.sup.lo + arow * a.sup.bpad + h * H);
+            const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi) + tile * (H / 8) * 64 + lane;
+            const bf16x8* al = reinterpret_cast<const bf16x8*>(a.sup.lo) + tile * (H / 8) * 64 + lane;
+            bf16x8 xh[H / 8], xl[H / 8];
 #pragma unroll
             for (int v = 0; v < H / 8; ++v) {
-                const bf16x8 xh = ah[v], xl = al[v];
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, bh[v], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, bl[v], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, bh[v], acc, 0, 0, 0);
+                xh[v] = ah[v * 64];
+                xl[v] = al[v * 64];
+            }
+#pragma unroll
+            for (int v = 0; v < H / 8; ++v) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[v], bh[v], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bl[v], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bh[v], acc, 0, 0, 0);
             }
         } else {
-            const float* ar = rows32 + arow * a.sup.dpad + h * H;
+            constexpr int VW = H < 4 ? H : 4;
+            const float* pb = a.sup.pan + (tile * (H / VW) * 64 + lane) * VW;
             float af[H];
 #pragma unroll
-            for (int s = 0; s < H; ++s) af[s] = ar[s];
+            for (int g = 0; g < H / VW; ++g) {
+                if constexpr (VW == 4) {
+                    const float4 t = *reinterpret_cast<const float4*>(pb + g * 64 * VW);
+                    af[4 * g] = t.x;
+                    af[4 * g + 1] = t.y;
+                    af[4 * g + 2] = t.z;
+                    af[4 * g + 3] = t.w;
+                } else {
+                    const float2 t = *reinterpret_cast<const float2*>(pb + g * 64 * VW);
+                    af[2 * g] = t.x;
+                    af[2 * g + 1] = t.y;
+                }
+            }
 #pragma unroll
             for (int s = 0; s < H; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], xq[s], acc, 0, 0, 0);
         }
@@ -183,6 +216,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     __syncthreads();
 
     const float E = fmaxf(fmaxf(Ew[0][col], Ew[1][col]), fmaxf(Ew[2][col], Ew[3][col]));
+    bool need = false;   // row listed for the FP64 re-decision
     if (wave == 0 && h == 0 && active) {
         float best = __builtin_huge_valf(), second = __builtin_huge_valf();
         int bj = 0;
@@ -201,11 +235,9 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
         }
         const double gap = (double)second - (double)best;
         const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)kqq));
-        if (gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale) {
-            const int pos = atomicAdd(a.refine_count, 1);
-            a.refine_list[pos] = (int32_t)q;
-        }
+        need = gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale;
     }
+    if (wave == 0) append_rows(need, q, a.refine_count, a.refine_list);
     if (a.Dt) {
         float* Dt = a.Dt;
         for (int jj = wave; jj < C; jj += 4) {
@@ -215,7 +247,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                 double vv = (active && h == 0) ? (double)D + (double)E : kInf;
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) vv = fmin(vv, __shfl_xor(vv, o, kWave));
-                if (lane == 0 && vv < kInf) atomicMin(a.colmin + jj, ord_enc(vv));
+                if (lane == 0) a.colpart[(int64_t)jj * a.colpart_cap + blockIdx.x] = vv;
             }
         }
     }
@@ -228,8 +260,10 @@ kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
     const unsigned blocks = (unsigned)((a.q.n + 31) / 32);
     auto go = [&](auto fn) -> kkm_status {
         KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
+        if (a.colmin && (int64_t)blocks > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
         hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
         KKM_HIP(hipGetLastError());
+        if (a.colmin) return launch_colmin_reduce(a, blocks, s);
         return KKM_OK;
     };
     switch (a.sup.dpad) {
@@ -253,7 +287,7 @@ bool mfma_dist_applies(const DistArgs& a) {
     }();
     if (off || a.ks.type == KKM_KERNEL_RMSD || a.precision == KKM_PREC_FP64 || a.dtype != KKM_F32) return false;
     if (a.precision == KKM_PREC_BF16X3) return a.sup.hi && a.sup.lo && a.sup.dpad >= 16;
-    return true;
+    return a.sup.pan != nullptr;
 }
 
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {

@@ -232,26 +232,170 @@ __global__ __launch_bounds__(256) void merge_partial_kernel(SelectArgs a) {
     }
 }
 
+// Linear / RBF kernels: one block per cluster settles |w_j^i|, m_j^i and alpha_j and lays out the two
+// merge targets of the cluster; a tiled pass then scores every batch row against all targets.
 template <typename TI>
-__global__ __launch_bounds__(256) void merge_final_kernel(SelectArgs a) {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.cand_total) *a.cand_total += *a.cand_count;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < a.C; j += gridDim.x * blockDim.x) {
-        const int32_t mem = a.counts[j], med = a.bmed[j];
-        const double alpha = merge_alpha(mem, a.wcount[j]);
-        if (alpha > 0.0 && med >= 0) {
-            double bv = kInf;
-            int64_t bi = INT64_MAX;
-            for (int c = 0; c < a.nchunk; ++c) {
-                const int32_t i = a.gpart_i[(int64_t)j * a.nchunk + c];
-                if (i >= 0) vmin(bv, bi, a.gpart_v[(int64_t)j * a.nchunk + c], i);
+__global__ __launch_bounds__(256) void merge_prep_kernel(SelectArgs a) {
+    const int j = blockIdx.x;
+    int32_t mem = 0, med = -1;
+    reduce_cluster(a, j, &mem, &med);
+    const double alpha = merge_alpha(mem, a.wcount[j]);
+    const bool on = alpha > 0.0 && med >= 0;
+    if (threadIdx.x == 0) {
+        a.counts[j] = mem;
+        a.bmed[j] = med;
+        a.malpha[j] = on ? alpha : 0.0;
+    }
+    TI* T = static_cast<TI*>(a.mtarget) + (int64_t)2 * j * a.Mpad;
+    const TI* xm = brow<TI>(a.b, on ? med : 0);
+    const TI* M = static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+    for (int64_t c = threadIdx.x; c < a.Mpad; c += blockDim.x) {
+        T[c] = on && c < a.b.d ? xm[c] : TI(0);
+        T[a.Mpad + c] = on && alpha < 1.0 ? M[c] : TI(0);
+    }
+}
+
+// Block = 256 batch rows x kMergeTJ clusters (two targets each).  Wave w scores the targets of
+// clusters 4w..4w+3 against all 256 rows, four consecutive rows per lane, so that every target value
+// read from LDS (a broadcast) feeds four rows and every row value feeds eight targets.  Rows are
+// staged through LDS dimension-major in chunks of 16 dimensions (coalesced global reads).  Scores
+// follow the per-row merge formula in FP64 (explicit differences for RBF); the (value, position)
+// minimum of each cluster over the block's rows goes to gpart.
+constexpr int kMergeTJ = 16;
+constexpr int kMergeRows = 256;
+constexpr int kMergeXs = kMergeRows + 4;   // LDS row stride of the staged chunk (keeps 16-byte alignment)
+
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
+    static_assert(kMergeRows == kRowsPerBlock, "merge chunks are the selection row chunks");
+    constexpr int NT = 2 * kMergeTJ;
+    constexpr int CH = DP < 16 ? DP : 16;
+    __shared__ double Ts[DP][NT];
+    __shared__ __align__(16) TI Xs[CH][kMergeXs];
+    const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
+    const int d = a.b.d;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int p = threadIdx.x; p < DP * NT; p += blockDim.x) {
+        const int k = p / NT, t = p - k * NT;
+        const int j = j0 + t / 2;
+        double v = 0.0;
+        if (j < a.C && k < d) v = (double)static_cast<const TI*>(a.mtarget)[(int64_t)(2 * j + (t & 1)) * a.Mpad + k];
+        Ts[k][t] = v;
+    }
+    const int64_t row0 = (int64_t)chunk * kMergeRows;
+    const int nrows = (int)min<int64_t>(kMergeRows, a.b.n - row0);
+    const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
+    double acc[4][8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[r][t] = 0.0;
+    double xx[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k0 = 0; k0 < DP; k0 += CH) {
+        __syncthreads();   // previous chunk consumed (and Ts written, on the first pass)
+        for (int p = threadIdx.x; p < kMergeRows * CH; p += blockDim.x) {
+            const int r = p / CH, k = p - r * CH;
+            TI v = TI(0);
+            if (r < nrows && k0 + k < d) v = brow<TI>(a.b, row0 + r)[k0 + k];
+            Xs[k][r] = v;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < CH; ++k) {
+            double xv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xv[r] = (double)Xs[k][4 * lane + r];
+            const double* tk = &Ts[k0 + k][8 * wave];
+            double tv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) tv[t] = tk[t];
+            if (lin) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    xx[r] = fma(xv[r], xv[r], xx[r]);
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) acc[r][t] = fma(xv[r], tv[t], acc[r][t]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const double df = xv[r] - tv[t];
+                        acc[r][t] = fma(df, df, acc[r][t]);
+                    }
             }
-            if (bi == INT64_MAX) bi = med;
-            const TI* x = brow<TI>(a.b, bi);
-            TI* M = static_cast<TI*>(a.M) + (int64_t)j * a.Mpad;
-            for (int64_t c = 0; c < a.Mpad; ++c) M[c] = c < a.b.d ? x[c] : TI(0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int j = j0 + 4 * wave + c;
+        if (j >= a.C) break;   // uniform over the wave
+        const double alpha = a.malpha[j];
+        double bv = kInf;
+        int64_t bi = INT64_MAX;
+        if (alpha > 0.0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pos = 4 * lane + r;
+                if (pos < nrows) {
+                    const double k1 = lin ? acc[r][2 * c] : ::exp(-acc[r][2 * c] * a.ks.inv2s2);
+                    double sc = (lin ? xx[r] : 1.0) - 2.0 * alpha * k1;
+                    if (alpha < 1.0) {
+                        const double k2 = lin ? acc[r][2 * c + 1] : ::exp(-acc[r][2 * c + 1] * a.ks.inv2s2);
+                        sc = sc - 2.0 * (1.0 - alpha) * k2;
+                    }
+                    vmin(bv, bi, sc, row0 + pos);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double v2 = __shfl_xor(bv, o, 64);
+            const int64_t i2 = __shfl_xor(bi, o, 64);
+            vmin(bv, bi, v2, i2);
+        }
+        if (lane == 0) {
+            const int64_t at = (int64_t)j * a.nchunk + chunk;
+            a.gpart_v[at] = bv;
+            a.gpart_i[at] = bi == INT64_MAX ? -1 : (int32_t)bi;
+        }
+    }
+}
+
+// One wavefront per cluster: the merged medoid is the lowest (score, position) over the chunk
+// partials; |w_j| += |w_j^i|; per-batch info rows.
+template <typename TI>
+__global__ __launch_bounds__(64) void merge_final_kernel(SelectArgs a) {
+    const int j = blockIdx.x, lane = threadIdx.x;
+    if (j == 0 && lane == 0 && a.cand_total) *a.cand_total += *a.cand_count;
+    const int32_t mem = a.counts[j], med = a.bmed[j];
+    const double alpha = merge_alpha(mem, a.wcount[j]);
+    if (alpha > 0.0 && med >= 0) {
+        double bv = kInf;
+        int64_t bi = INT64_MAX;
+        for (int c = lane; c < a.nchunk; c += 64) {
+            const int32_t i = a.gpart_i[(int64_t)j * a.nchunk + c];
+            if (i >= 0) vmin(bv, bi, a.gpart_v[(int64_t)j * a.nchunk + c], i);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double v2 = __shfl_xor(bv, o, 64);
+            const int64_t i2 = __shfl_xor(bi, o, 64);
+            vmin(bv, bi, v2, i2);
+        }
+        if (bi == INT64_MAX) bi = med;
+        const TI* x = brow<TI>(a.b, bi);
+        TI* M = static_cast<TI*>(a.M) + (int64_t)j * a.Mpad;
+        for (int64_t c = lane; c < a.Mpad; c += 64) M[c] = c < a.b.d ? x[c] : TI(0);
+        if (lane == 0) {
             a.Mself[j] = kself64(a.ks, x);
             a.Midx[j] = a.b.base + bi * a.b.stride;
         }
+    }
+    if (lane == 0) {
         a.wcount[j] += mem;
         if (a.info_bmed) a.info_bmed[j] = med >= 0 ? a.b.base + (int64_t)med * a.b.stride : -1;
         if (a.info_bcnt) a.info_bcnt[j] = mem;
@@ -282,12 +426,16 @@ __global__ __launch_bounds__(1024) void model_from_medoids_kernel(kkm_model m, c
         m.snorm32[j] = n32;
         m.coef64[j] = 1.0;
         m.coef32[j] = 1.0f;
-        for (int64_t c = 0; c < m.bpad; ++c) {
-            uint16_t hi = 0, lo = 0;
-            if (c < m.d) bf16_split((float)dst[c], hi, lo);
-            m.hi[(int64_t)j * m.bpad + c] = hi;
-            m.lo[(int64_t)j * m.bpad + c] = lo;
-        }
+        const bool panels = m.kernel.type != KKM_KERNEL_RMSD;   // power-of-two padded rows only
+        if (panels && m.pan)
+            for (int c = 0; c < m.dpad; ++c) m.pan[panel32_index(j, c, m.dpad)] = c < m.d ? (float)dst[c] : 0.0f;
+        if (panels && m.dpad >= 16)
+            for (int c = 0; c < m.dpad; ++c) {
+                uint16_t hi = 0, lo = 0;
+                if (c < m.d) bf16_split((float)dst[c], hi, lo);
+                m.hi[panel16_index(j, c, m.dpad)] = hi;
+                m.lo[panel16_index(j, c, m.dpad)] = lo;
+            }
         m.offsets[j] = j;
         m.self[j] = Mself[j];
         m.segabs[j] = 1.0;
@@ -324,12 +472,15 @@ __global__ __launch_bounds__(1024) void model_norms_kernel(kkm_model m) {
         m.snorm64[l] = n64;
         m.snorm32[l] = n32;
         m.coef32[l] = (float)m.coef64[l];
-        for (int64_t c = 0; c < m.bpad; ++c) {
-            uint16_t hi = 0, lo = 0;
-            if (c < m.d) bf16_split((float)S[l * m.dpad + c], hi, lo);
-            m.hi[l * m.bpad + c] = hi;
-            m.lo[l * m.bpad + c] = lo;
-        }
+        if (m.pan && m.kernel.type != KKM_KERNEL_RMSD)
+            for (int c = 0; c < m.dpad; ++c) m.pan[panel32_index(l, c, m.dpad)] = c < m.d ? (float)S[l * m.dpad + c] : 0.0f;
+        if (m.dpad >= 16 && m.kernel.type != KKM_KERNEL_RMSD)
+            for (int c = 0; c < m.dpad; ++c) {
+                uint16_t hi = 0, lo = 0;
+                if (c < m.d) bf16_split((float)S[l * m.dpad + c], hi, lo);
+                m.hi[panel16_index(l, c, m.dpad)] = hi;
+                m.lo[panel16_index(l, c, m.dpad)] = lo;
+            }
         mx = fmaxf(mx, n32);
     }
     red[threadIdx.x] = mx;
@@ -450,22 +601,25 @@ kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& d
     else hipLaunchKernelGGL(medoid_candidates_kernel<float>, grid, dim3(256), 0, s, a);
     KKM_HIP(hipGetLastError());
     const unsigned cand_blocks = (unsigned)std::max(1, 4 * dev.num_cus);
-    return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
-        if (a.dtype == KKM_F64) {
-            hipLaunchKernelGGL((candidate_eval_kernel<double, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
-            KKM_HIP(hipGetLastError());
-            hipLaunchKernelGGL((merge_partial_kernel<double, DP>), grid, dim3(256), 0, s, a);
-            KKM_HIP(hipGetLastError());
-            hipLaunchKernelGGL(merge_final_kernel<double>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
+    const dim3 tgrid(a.nchunk, (a.C + kMergeTJ - 1) / kMergeTJ);
+    auto run = [&]<typename TI, int DP>() -> kkm_status {
+        hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
+        KKM_HIP(hipGetLastError());
+        if constexpr (DP == 0) {
+            hipLaunchKernelGGL((merge_partial_kernel<TI, DP>), grid, dim3(256), 0, s, a);
         } else {
-            hipLaunchKernelGGL((candidate_eval_kernel<float, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(merge_prep_kernel<TI>, dim3(a.C), dim3(256), 0, s, a);
             KKM_HIP(hipGetLastError());
-            hipLaunchKernelGGL((merge_partial_kernel<float, DP>), grid, dim3(256), 0, s, a);
-            KKM_HIP(hipGetLastError());
-            hipLaunchKernelGGL(merge_final_kernel<float>, dim3(nblocks(a.C, 256)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((merge_tile_kernel<TI, DP>), tgrid, dim3(256), 0, s, a);
         }
         KKM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(merge_final_kernel<TI>, dim3(a.C), dim3(64), 0, s, a);
+        KKM_HIP(hipGetLastError());
         return KKM_OK;
+    };
+    return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
+        if (a.dtype == KKM_F64) return run.template operator()<double, DP>();
+        return run.template operator()<float, DP>();
     });
 }
 

@@ -50,6 +50,26 @@ inline int padded_dim(int64_t d) {
 // Row stride of the bfloat16 split arrays (the matrix-core K step is 16).
 inline int bf16_pad(int dpad) { return dpad < 16 ? 16 : dpad; }
 
+// Panel layouts of the support for the matrix-core pass.  Rows are grouped in tiles of 32; within a
+// tile the operand fragment that one MFMA step (or group of steps) needs from the 64 lanes is stored
+// as 64 consecutive vectors in lane order, lane = 32 h + (row % 32) holding dimensions
+// h (DP/2) + [vector start, vector start + width).  FP32 panels use vectors of min(4, DP/2) floats,
+// bfloat16 panels vectors of 8 (DP >= 16 only).  Both hold exactly 32 DP elements per tile.
+// rows to allocate for panels covering rows [0, rows): whole tiles
+inline size_t panel_rows(size_t rows) { return (rows + 31) & ~size_t(31); }
+
+__host__ __device__ inline int64_t panel32_index(int64_t r, int c, int DP) {
+    const int H = DP / 2, VW = H < 4 ? H : 4;
+    const int h = c / H, s = c - h * H;
+    const int g = s / VW, e = s - g * VW;
+    return (((r >> 5) * (H / VW) + g) * 64 + h * 32 + (int)(r & 31)) * VW + e;
+}
+__host__ __device__ inline int64_t panel16_index(int64_t r, int c, int DP) {
+    const int H = DP / 2;
+    const int h = c / H, s = c - h * H;
+    return (((r >> 5) * (H / 8) + (s >> 3)) * 64 + h * 32 + (int)(r & 31)) * 8 + (s & 7);
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Bump allocator over the caller's workspace (or a size probe when base == nullptr).
@@ -102,7 +122,8 @@ struct kkm_model {
     float* snorm_max = nullptr; // [1] max ||s||^2 over the support (error bounds)
     int32_t* split = nullptr;   // [5] cluster runs of the four wavefronts of a distance tile
     int32_t nonneg = 1;         // every coefficient >= 0
-    uint16_t* hi = nullptr;     // [cap + 32][bpad] bfloat16 high parts of the support rows
+    float* pan = nullptr;       // FP32 panel copy of the support (float models only)
+    uint16_t* hi = nullptr;     // bfloat16 panel of the high parts of the support rows (dpad >= 16)
     uint16_t* lo = nullptr;     // [cap + 32][bpad] bfloat16 remainders
     int32_t bpad = 0;
     int64_t* counts = nullptr;  // [C] |w_j| of a fitted model
@@ -139,6 +160,19 @@ __device__ __forceinline__ unsigned long long ord_enc(double v) {
 __device__ __forceinline__ double ord_dec(unsigned long long e) {
     const unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
     return __longlong_as_double((long long)b);
+}
+
+// Appends q to list for the lanes with flag set, with one atomic per wavefront (call from all lanes
+// of the wavefront).  List order across wavefronts is unspecified.
+__device__ __forceinline__ void append_rows(bool flag, int64_t q, int32_t* count, int32_t* list) {
+    const unsigned long long m = __ballot(flag);
+    if (m == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (flag) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)q;
 }
 
 __device__ __forceinline__ float exp_neg(float a) {     // exp(-a), a >= 0

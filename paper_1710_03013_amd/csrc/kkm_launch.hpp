@@ -27,10 +27,12 @@ struct LandmarkArgs {
     const void* M;          // [C][Mpad] global medoid rows (dtype of the fit)
     int64_t Mpad;
     const double* Mself;    // [C] K(m,m), +inf where the medoid is unset
-    double* Kbuf;           // [ell][ell] scratch
+    double* Kbuf;           // [ell][ldk] scratch: K_LL
+    int64_t ldk;            // row stride of Kbuf (ell rounded up to even)
+    double* Kmed;           // [ell][C] scratch: K(x_l, m_j) for the Eq. 8 initialisation
     int32_t* lab;           // [2][ell] scratch: initial labels, then final labels
-    double* Sall;           // [2][ell][C] scratch: every workgroup's rows of S (alternating buffers)
-    double* partial;        // [2][grid][C] scratch (alternating buffers)
+    int32_t* nlab_x;        // [ell] scratch: labels after an update, exchanged between workgroups
+    double* partial;        // [grid][C] scratch: each workgroup's part of the g^ sums
     int32_t* changed;       // [max_updates+1] scratch
     int32_t* zero_ints;     // ints to clear for the later kernels of the batch
     int32_t n_zero_ints;
@@ -48,7 +50,8 @@ struct LandmarkArgs {
     double* coef64;
     int32_t* src_index;     // [ell] batch position of each support row
     float* snorm_max;       // [1]
-    uint16_t* sup_hi;       // [ell][bpad] bfloat16 split of the support rows
+    float* sup_pan;         // FP32 panel copy of the support (float input), or null
+    uint16_t* sup_hi;       // bfloat16 panels of the split of the support rows (dpad >= 16)
     uint16_t* sup_lo;
     int64_t bpad;
     int32_t* split;         // [5] cluster runs of the distance pass's four wavefronts
@@ -59,9 +62,13 @@ struct LandmarkArgs {
     int32_t* error;         // [1] set when a barrier wait exceeded its cap
 };
 // Workgroups of the landmark phase for a landmark set of size ell (KKM_LANDMARK_ROWS rows each).
-int landmark_grid(const DeviceInfo& dev, int ell);
+struct LandmarkShape {
+    int grid;        // workgroups of the loop kernel
+    int k_in_lds;    // own rows of K_LL in LDS
+};
+LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C);
 size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds);
-bool landmark_k_in_lds(const DeviceInfo& dev, int ell, int C, int G);
+inline int64_t landmark_ldk(int64_t ell) { return (ell + 1) & ~int64_t(1); }
 kkm_status launch_landmark_phase(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
 
 // ---------------------------------------------------------------- sparse-centroid distances (k_dist.hip)
@@ -79,8 +86,9 @@ struct SupportView {
     const float* snorm_max; // [1]
     const int32_t* split;   // [5] cluster runs of the four wavefronts of a distance tile
     int32_t nonneg;         // every coefficient >= 0 (error bounds may scale with the sums)
-    const uint16_t* hi;     // [rows][bpad] bfloat16 high parts of the rows (or null)
-    const uint16_t* lo;     // [rows][bpad] bfloat16 remainders
+    const float* pan;       // FP32 panel copy of the rows (float models), or null
+    const uint16_t* hi;     // bfloat16 panel of the high parts of the rows (or null)
+    const uint16_t* lo;     // bfloat16 panel of the remainders
     int64_t bpad;
     int32_t C;
 };
@@ -102,6 +110,8 @@ struct DistArgs {
     int32_t* refine_count;  // [1]
     int32_t* nonfinite;     // [1]
     unsigned long long* colmin;   // [C] ord_enc(min over rows of D + Erow), or null (fit only)
+    double* colpart;        // [C][colpart_cap] per-workgroup minima behind colmin (with colmin)
+    int64_t colpart_cap;
     int64_t n_support;      // rows of sup (offsets[C])
 };
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
@@ -112,6 +122,10 @@ kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_
 bool dist_is_fp64(const DistArgs& a);
 // LDS bytes the distance tile needs for C clusters.
 size_t dist_lds_bytes(const DistArgs& a);
+// Workgroups of any distance pass over n rows (bound for colpart_cap).
+inline int64_t dist_block_cap(int64_t n) { return (n + 15) / 16 + 1; }
+// colmin[j] <- ord_enc(min over the first nblk entries of colpart row j) (~0: none finite).
+kkm_status launch_colmin_reduce(const DistArgs& a, int64_t nblk, hipStream_t s);
 // FP64 re-decision of the rows listed by launch_dist (n_support: support rows of a.sup).
 kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s, int64_t n_support);
 // Deterministic FP64 sum of best[0..n) into out[0] (partials: >= 1024 doubles of scratch).
@@ -149,6 +163,8 @@ struct SelectArgs {
     int32_t* cand_total;    // [1] accumulates cand_count over batches, or null
     double* gpart_v;        // [C][nchunk] merge partials
     int32_t* gpart_i;
+    void* mtarget;          // [2C][Mpad] merge targets: row 2j = m_j^i, row 2j+1 = m_j (input dtype)
+    double* malpha;         // [C] merge weight alpha_j (0: m_j stays)
     // per-batch info rows (device, length C) or null
     int64_t* info_bmed;
     int64_t* info_bcnt;
