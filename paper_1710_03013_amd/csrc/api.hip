@@ -2,6 +2,7 @@
 // per-batch launch sequence.  All arithmetic runs in the kernels of k_landmark / k_dist / k_select.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <vector>
 
@@ -135,6 +136,7 @@ struct FitWs {
     int64_t* trace;        // [64]
     unsigned* barrier;     // [1]
     int32_t* lm_error;     // [1]
+    char* status_end;      // end of the status block (refine_counts .. trace)
 };
 
 size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
@@ -182,19 +184,21 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.Erow = c.take<float>(P.nmax);
     w.labels_b = c.take<int32_t>(P.nmax);
     w.refine_list = c.take<int32_t>(P.nmax);
-    w.refine_counts = c.take<int32_t>(P.B);
-    w.flags = c.take<int32_t>(2);
     w.bmed = c.take<int32_t>(C);
     w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
     w.gpart_v = c.take<double>((size_t)C * P.nchunk);
     w.gpart_i = c.take<int32_t>((size_t)C * P.nchunk);
     w.mtarget = c.take<char>((size_t)2 * C * P.dpad * es);
     w.malpha = c.take<double>(C);
+    w.barrier = c.take<unsigned>(1);
+    // status block, read back with one copy: [refine_counts, flags, updates, lm_error, info, trace]
+    w.refine_counts = c.take<int32_t>(P.B);
+    w.flags = c.take<int32_t>(2);
     w.updates = c.take<int32_t>(P.B);
+    w.lm_error = c.take<int32_t>(1);
     w.info = c.take<int64_t>((size_t)3 * P.B * C);
     w.trace = c.take<int64_t>(64);
-    w.barrier = c.take<unsigned>(1);
-    w.lm_error = c.take<int32_t>(1);
+    w.status_end = c.take<char>(1);
     return c.off;
 }
 
@@ -463,7 +467,6 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     if (!model) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
     DeviceInfo dev;
     KKM_TRY(device_info(&dev));
-    if (!dev.coop) return fail(KKM_ERR_DEVICE, "device lacks cooperative launch");
     FitPlan P;
     KKM_TRY(make_plan(N, d, dtype, kernel, params, &dev, P));
     if (model->d != d || model->C != P.C || model->dtype != dtype || model->cap < P.C ||
@@ -488,7 +491,21 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
 
     KKM_TRY(launch_zero_i32(w.refine_counts, P.B, s));
     KKM_TRY(launch_zero_i32(w.flags, 2, s));
-    KKM_HIP(hipMemcpyAsync(w.lm, P.lm_host.data(), sizeof(int32_t) * P.ell_total, hipMemcpyHostToDevice, s));
+    // one host-to-device copy of the inputs block: [landmarks, initial labels, uniforms, medoids]
+    // (the staging vector outlives the copy: it is released after the final synchronisation)
+    std::vector<char> up;
+    {
+        char* ub = reinterpret_cast<char*>(w.lm);
+        up.assign(static_cast<size_t>(reinterpret_cast<char*>(w.chosen + C) - ub), 0);
+        auto put = [&](void* dev_ptr, const void* src, size_t bytes) {
+            if (bytes) std::memcpy(up.data() + (reinterpret_cast<char*>(dev_ptr) - ub), src, bytes);
+        };
+        put(w.lm, P.lm_host.data(), sizeof(int32_t) * P.ell_total);
+        if (P.p.init == KKM_INIT_KMEANSPP) put(w.uniforms, P.uniforms.data(), sizeof(double) * C);
+        else if (P.p.init == KKM_INIT_MEDOIDS) put(w.chosen, P.med0.data(), sizeof(int32_t) * C);
+        else put(w.lab_init, P.lab0.data(), sizeof(int32_t) * P.ell[0]);
+        KKM_HIP(hipMemcpyAsync(ub, up.data(), up.size(), hipMemcpyHostToDevice, s));
+    }
     const void* Xs = X;
     if (kernel->type == KKM_KERNEL_RMSD) {
         KKM_TRY(launch_centre(X, w.Xc, N, kernel->n_atoms, dtype, s));
@@ -499,14 +516,11 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     // batch-0 initialisation of the global medoids
     KKM_TRY(tm.begin());
     if (P.p.init == KKM_INIT_KMEANSPP) {
-        KKM_HIP(hipMemcpyAsync(w.uniforms, P.uniforms.data(), sizeof(double) * C, hipMemcpyHostToDevice, s));
         KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, s));
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
     } else if (P.p.init == KKM_INIT_MEDOIDS) {
-        KKM_HIP(hipMemcpyAsync(w.chosen, P.med0.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
     } else {
-        KKM_HIP(hipMemcpyAsync(w.lab_init, P.lab0.data(), sizeof(int32_t) * P.ell[0], hipMemcpyHostToDevice, s));
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, nullptr, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
     }
     KKM_TRY(tm.end(kPhInit));
@@ -658,17 +672,18 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     }
     KKM_TRY(launch_model_from_medoids(model, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
 
-    std::vector<int32_t> updates(P.B), refined(P.B), flags(2);
-    int32_t lm_err = 0;
-    KKM_HIP(hipMemcpyAsync(&lm_err, w.lm_error, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    std::vector<int64_t> infos((size_t)3 * P.B * C);
-    KKM_HIP(hipMemcpyAsync(updates.data(), w.updates, sizeof(int32_t) * P.B, hipMemcpyDeviceToHost, s));
-    KKM_HIP(hipMemcpyAsync(refined.data(), w.refine_counts, sizeof(int32_t) * P.B, hipMemcpyDeviceToHost, s));
-    KKM_HIP(hipMemcpyAsync(flags.data(), w.flags, sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
-    KKM_HIP(hipMemcpyAsync(infos.data(), w.info, sizeof(int64_t) * infos.size(), hipMemcpyDeviceToHost, s));
-    if (info && info->landmark_trace)
-        KKM_HIP(hipMemcpyAsync(info->landmark_trace, w.trace, sizeof(int64_t) * 64, hipMemcpyDeviceToHost, s));
+    // one device-to-host copy of the status block
+    const char* sb = reinterpret_cast<const char*>(w.refine_counts);
+    std::vector<char> st((size_t)(w.status_end - sb));
+    KKM_HIP(hipMemcpyAsync(st.data(), sb, st.size(), hipMemcpyDeviceToHost, s));
     KKM_HIP(hipStreamSynchronize(s));
+    auto host_at = [&](const void* dev_ptr) { return st.data() + (reinterpret_cast<const char*>(dev_ptr) - sb); };
+    const int32_t* refined = reinterpret_cast<const int32_t*>(host_at(w.refine_counts));
+    const int32_t* flags = reinterpret_cast<const int32_t*>(host_at(w.flags));
+    const int32_t* updates = reinterpret_cast<const int32_t*>(host_at(w.updates));
+    const int32_t lm_err = *reinterpret_cast<const int32_t*>(host_at(w.lm_error));
+    const int64_t* infos = reinterpret_cast<const int64_t*>(host_at(w.info));
+    if (info && info->landmark_trace) std::memcpy(info->landmark_trace, host_at(w.trace), sizeof(int64_t) * 64);
     model->used = C;
     model->nonneg = 1;
     (void)es;

@@ -1,9 +1,12 @@
 // Landmark phase of one mini-batch:
 //
-//   1. the landmark kernel block K_LL = K(x_l, x_m) in FP64 (landmark_block_kernel, 16 x 16 tiles);
+//   1. the landmark kernel block K_LL = K(x_l, x_m) in FP64 and, for the Eq. 8 initialisation,
+//      K(x_l, m_j) for the global medoids (landmark_k_kernel, 64 x 64 tiles; RMSD frames:
+//      landmark_block_kernel, 32 x 32 tiles);
 //   2. the initial landmark labels: given, or the nearest global medoid (Eq. 8, with K(m,m))
-//      (landmark_init_kernel, one workgroup per landmark);
-//   3. one cooperative kernel for the landmark loop (Eq. 14-17 restricted to the landmarks):
+//      (landmark_init_from_k_kernel, one wavefront per landmark; RMSD: landmark_init_kernel);
+//   3. one kernel for the landmark loop, all workgroups resident (Eq. 14-17 restricted to the
+//      landmarks):
 //        counting sort of the landmarks by label  -> CSR segments L_j, c_j = |L_j|
 //        S[m][j]  = sum_{m' in L_j} K(l_m, l_m')                (so f^(l_m, j) = S / c_j, Eq. 17)
 //        g^_j     = 1/c_j^2 sum_{m in L_j} S[m][j]              (Eq. 16)
@@ -206,7 +209,7 @@ __device__ __forceinline__ void full_sums(const LdsLayout& L, const double* Krow
     __syncthreads();
 }
 
-// Barrier over the co-resident workgroups of the cooperative launch: a monotonically increasing
+// Barrier over the co-resident workgroups of the loop kernel: a monotonically increasing
 // arrival counter (cleared by a kernel launched just before on the same stream).  After the
 // workgroup barrier, one thread arrives with a release RMW at agent scope (one L2 write-back covers
 // the workgroup's writes), polls with relaxed loads (no cache maintenance per poll), and issues one
@@ -442,7 +445,7 @@ __global__ __launch_bounds__(256) void landmark_init_from_k_kernel(LandmarkArgs 
     if (lane == 0) a.lab[l] = bj < C ? bj : 0;
 }
 
-// 3-4. The landmark loop and the centroid support (cooperative launch, grid <= device CUs).
+// 3-4. The landmark loop and the centroid support (grid <= device CUs, all workgroups resident).
 //
 // Workgroup wg owns landmark rows [r0, r1): their rows of K (in LDS when they fit) and of S.  Every
 // workgroup keeps all landmark labels and cluster counts.  One update takes two exchanges:
@@ -751,7 +754,16 @@ kkm_status launch_landmark_phase(const LandmarkArgs& args, int dtype, const Devi
     KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
     if (per_cu * dev.num_cus < G)
         return fail(KKM_ERR_DEVICE, "landmark loop grid does not fit co-resident on the device");
-    KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), params, (unsigned)lds, stream));
+    // The grid fits the device at once, so a plain launch makes every workgroup resident as soon as
+    // the CUs are free (work of other streams only delays the barrier; its waits are bounded and
+    // report an error).  A cooperative launch gives the same guarantee formally but costs ~20 us of
+    // queue synchronisation per launch; KKM_LANDMARK_COOPERATIVE=1 selects it.
+    static const bool coop = [] {
+        const char* e = std::getenv("KKM_LANDMARK_COOPERATIVE");
+        return e && e[0] == '1';
+    }();
+    if (coop) KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), params, (unsigned)lds, stream));
+    else KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(256), params, (unsigned)lds, stream));
     return KKM_OK;
 }
 
