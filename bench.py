@@ -2,8 +2,8 @@
 """Throughput of the mini-batch landmark kernel k-means hot path on one MI355X.
 
 One step = the whole path on one synthetic dataset, inputs already in HBM:
-  kkm_fit   -- per mini-batch: landmark block + landmark loop (one cooperative
-               kernel), the batch-wide distance pass with FP64 re-decisions,
+  kkm_fit   -- per mini-batch: landmark block + landmark loop (one kernel with
+               grid barriers), the batch-wide distance pass with FP64 re-decisions,
                member counts, batch medoids (Eq. 10) and the merge (Eq. 11-13);
   kkm_assign -- every sample of the dataset against the fitted medoids (Eq. 2).
 
@@ -38,8 +38,17 @@ WORKLOADS = {
     "md": (2, "md-frames N=200000 A=50 templates=10 rmsd(sigma=1.5) C=50 B=20 s=0.05 T=20"),
 }
 
-PEAK_FP32_VECTOR = 157.3e12   # published MI355X vector FP32 FLOP/s
-PEAK_FP64_VECTOR = 78.6e12    # published MI355X vector FP64 FLOP/s
+PEAK_FP32_VECTOR = 157.3e12   # published MI355X FP32 FLOP/s (vector and matrix cores)
+PEAK_FP64_VECTOR = 78.6e12    # published MI355X FP64 FLOP/s
+PEAK_BF16_MATRIX = 2.5e15     # published MI355X dense BF16 matrix-core FLOP/s
+
+# kernel names as rocprofv3 reports them, per (kernel function, precision)
+DIST_KERNEL_NAME = {("rbf", "fp32"): "mfma_dist_kernel", ("linear", "fp32"): "mfma_dist_kernel",
+                    ("rbf", "bf16x3"): "mfma_dist_kernel", ("linear", "bf16x3"): "mfma_dist_kernel"}
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel
+# calibration), keyed by (kernel, workload); absent = not measured for the current kernel source.
+TRAFFIC = {}
 
 
 def log(msg):
@@ -58,11 +67,11 @@ def dist_flops_per_eval(kind: str, d: int) -> float:
     return 18 * A + 150
 
 
-def landmark_flops_per_launch(kind: str, d: int, ell: int, updates: int, C: int) -> float:
-    """FP64 work of one landmark-phase launch: l^2 kernel evaluations (3d + 20 each),
-    l^2 adds per centroid evaluation, l C distance updates per label update."""
-    ev = 3 * d + 20 if kind != "rmsd" else 18 * (d // 3) + 300
-    return ell * ell * ev + (updates + 1) * (ell * ell + 3 * ell * C)
+def landmark_flops_per_launch(ell: int, updates: int, C: int) -> float:
+    """Algorithmic FP64 work of one landmark-loop launch: every assignment evaluated on the
+    landmarks costs l^2 adds for S = K_LL Z, l adds for g^ and 3 l C for Eq. 15; the loop
+    evaluates (landmark updates + 1) assignments.  (K_LL itself is built by another kernel.)"""
+    return (updates + 1) * (ell * ell + ell + 3 * ell * C)
 
 
 def cpu_baseline(X, cfg, landmarks, uniforms, init_labels):
@@ -165,25 +174,30 @@ def main() -> int:
     ms = ({k_: float(np.mean([i["ms"][k_] for i in infos])) for k_ in infos[0]["ms"]}
           if not args.no_phase_timing else None)
 
-    # dominant kernel: the per-phase time summed over the step
+    # dominant kernel: the isolated kernel with the largest time per step (HIP events around exactly
+    # that kernel's launches on the library's stream, inside the timed steps)
     ells = [len(l) for l in landmarks]
     roofline = None
+    rooflines = {}
     if ms is not None:
-        if ms["landmark"] >= ms["dist"]:
-            dom = "landmark_phase_kernel"
-            per_launch = np.mean([landmark_flops_per_launch(cfg["kernel"], d, ells[i],
-                                                            int(info["updates_per_batch"][i]), C) for i in range(B)])
-            dur = ms["landmark"] / B * 1e-3
-            peak, bound = PEAK_FP64_VECTOR, "alu"
-        else:
-            dom = "dist_kernel"
-            per_launch = np.mean([batch_n[i] * ells[i] for i in range(B)]) * dist_flops_per_eval(cfg["kernel"], d)
-            dur = ms["dist"] / B * 1e-3
-            peak, bound = (PEAK_FP32_VECTOR if prec != "fp64" else PEAK_FP64_VECTOR), "alu"
-        achieved = per_launch / dur
-        roofline = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": None, "kernel": dom,
-                    "avg_launch_us": dur * 1e6, "phase_ms_per_step": ms}
+        upd = [int(u) - 1 for u in info["updates_per_batch"]]   # landmark-only updates
+        lm_flops = float(np.mean([landmark_flops_per_launch(ells[i], upd[i], C) for i in range(B)]))
+        dist_flops = float(np.mean([batch_n[i] * ells[i] for i in range(B)])) * dist_flops_per_eval(cfg["kernel"], d)
+        dist_peak = {"fp64": PEAK_FP64_VECTOR, "fp32": PEAK_FP32_VECTOR, "bf16x3": PEAK_BF16_MATRIX}[prec]
+        cands = {
+            "landmark_phase_kernel": (ms["landmark_loop"], lm_flops, PEAK_FP64_VECTOR, "alu"),
+            DIST_KERNEL_NAME.get((cfg["kernel"], prec), "dist_kernel"):
+                (ms["dist"], dist_flops, dist_peak, "mfma" if (cfg["kernel"] != "rmsd" and prec != "fp64") else "alu"),
+        }
+        for name, (tot_ms, flops, peak, bound) in cands.items():
+            dur = tot_ms / B * 1e-3
+            achieved = flops / dur if dur > 0 else 0.0
+            rooflines[name] = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                               "frac": achieved / peak, "traffic": TRAFFIC.get((name, args.workload)),
+                               "kernel": name, "avg_launch_us": dur * 1e6, "flop_per_launch": flops}
+        dom = max(cands, key=lambda k_: cands[k_][0])
+        roofline = dict(rooflines[dom])
+        roofline["phase_ms_per_step"] = ms
 
     # assign latency at a fixed request size
     lat = []
@@ -219,6 +233,7 @@ def main() -> int:
         "refined_rows_per_step": int(info["rows_refined"]),
         "medoid_candidates_per_step": int(info["medoid_candidates"]),
         "roofline": roofline,
+        "rooflines": rooflines,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (one fit + one assign pass)")

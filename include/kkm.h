@@ -119,9 +119,10 @@ typedef struct kkm_fit_info {
     int32_t reserved;
     double ms_init;             /* out (time_phases): k-means++ / initial medoids */
     double ms_landmark;         /* out: landmark block, initial labels, landmark loop, centroid support */
-    double ms_dist;             /* out: batch-wide distance pass (Eq. 15-17 over every batch sample) */
+    double ms_dist;             /* out: batch-wide distance kernel (Eq. 15-17 over every batch sample) */
     double ms_refine;           /* out: FP64 re-decision of near-tie rows */
     double ms_select;           /* out: member counts, batch medoids (Eq. 10), merge (Eq. 11-13) */
+    double ms_landmark_loop;    /* out: the landmark loop kernel alone (part of ms_landmark) */
     int64_t* landmark_trace;    /* host [64] or NULL: device wall-clock stamps (100 MHz) taken by the first
                                    workgroup at the steps of batch 0's landmark phase: [0] count, then
                                    start, block done, init done, and per update: sort, sums, barrier,

@@ -63,7 +63,8 @@ class _FitInfo(ct.Structure):
                 ("rows_refined", ct.c_int64), ("medoid_candidates", ct.c_int64),
                 ("time_phases", ct.c_int32), ("reserved", ct.c_int32), ("ms_init", ct.c_double),
                 ("ms_landmark", ct.c_double), ("ms_dist", ct.c_double), ("ms_refine", ct.c_double),
-                ("ms_select", ct.c_double), ("landmark_trace", ct.POINTER(ct.c_int64))]
+                ("ms_select", ct.c_double), ("ms_landmark_loop", ct.c_double),
+                ("landmark_trace", ct.POINTER(ct.c_int64))]
 
 
 # name -> (restype, argtypes): every symbol include/kkm.h declares
@@ -285,8 +286,8 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
                global_medoids=gmed.reshape(B, C), evals_algorithmic=info.evals_algorithmic,
                evals_performed=info.evals_performed, rows_refined=info.rows_refined,
                medoid_candidates=info.medoid_candidates, workspace_bytes=need,
-               ms=dict(init=info.ms_init, landmark=info.ms_landmark, dist=info.ms_dist, refine=info.ms_refine,
-                       select=info.ms_select) if time_phases else None,
+               ms=dict(init=info.ms_init, landmark=info.ms_landmark, landmark_loop=info.ms_landmark_loop,
+                       dist=info.ms_dist, refine=info.ms_refine, select=info.ms_select) if time_phases else None,
                landmark_trace=trace[1:1 + int(trace[0])] if trace is not None else None)
     return model, labels, out
 

@@ -14,6 +14,10 @@ namespace {
 
 // Pairs of HIP events recorded on the caller's stream around phases of a fit (optional).  The
 // events live for one call only.
+// Timed spans of a fit: k-means++ / medoids; landmark block and initial labels; landmark loop kernel;
+// batch-wide distance kernel; FP64 re-decision; selection (column minima, medoids, merge).
+enum { kPhInit = 0, kPhLandmark = 1, kPhLoop = 2, kPhDist = 3, kPhRefine = 4, kPhSelect = 5, kPhases = 6 };
+
 struct PhaseTimer {
     bool on = false;
     hipStream_t s = nullptr;
@@ -50,8 +54,8 @@ struct PhaseTimer {
         p.clear();
     }
     // after the stream has been synchronised
-    void collect(double out[5]) {
-        for (int p = 0; p < 5; ++p) out[p] = 0.0;
+    void collect(double out[kPhases]) {
+        for (int p = 0; p < kPhases; ++p) out[p] = 0.0;
         auto& pl = pool(device);
         for (auto& sp : spans) {
             float ms = 0.0f;
@@ -59,7 +63,6 @@ struct PhaseTimer {
         }
     }
 };
-enum { kPhInit = 0, kPhLandmark = 1, kPhDist = 2, kPhRefine = 3, kPhSelect = 4 };
 
 // ----------------------------------------------------------------------------- fit plan
 struct FitPlan {
@@ -581,8 +584,11 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.error = w.lm_error;
         if (la.trace) KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
         KKM_TRY(tm.begin());
-        KKM_TRY(launch_landmark_phase(la, dtype, dev, s));
+        KKM_TRY(launch_landmark_block(la, dtype, dev, s));
         KKM_TRY(tm.end(kPhLandmark));
+        KKM_TRY(tm.begin());
+        KKM_TRY(launch_landmark_loop(la, dtype, dev, s));
+        KKM_TRY(tm.end(kPhLoop));
 
         SupportView sv;
         sv.rows = w.support;
@@ -622,6 +628,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         da.colpart = w.colpart;
         da.colpart_cap = dist_block_cap(P.nmax);
         da.n_support = ell;
+        int64_t dist_blocks = 0;
+        da.colpart_blocks = &dist_blocks;
         KKM_TRY(tm.begin());
         KKM_TRY(launch_dist(da, dev, s));
         KKM_TRY(tm.end(kPhDist));
@@ -667,6 +675,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
         KKM_TRY(tm.begin());
         sa.cand_total = w.flags + 1;
+        if (dist_blocks > 0) KKM_TRY(launch_colmin_reduce(da, dist_blocks, s));
         KKM_TRY(launch_select(sa, dist_is_fp64(da), dev, s));
         KKM_TRY(tm.end(kPhSelect));
     }
@@ -711,10 +720,11 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         info->evals_performed = perf;
         info->rows_refined = rows_ref;
         info->medoid_candidates = flags[1];
-        double ms[5];
+        double ms[kPhases];
         tm.collect(ms);
         info->ms_init = ms[kPhInit];
-        info->ms_landmark = ms[kPhLandmark];
+        info->ms_landmark = ms[kPhLandmark] + ms[kPhLoop];
+        info->ms_landmark_loop = ms[kPhLoop];
         info->ms_dist = ms[kPhDist];
         info->ms_refine = ms[kPhRefine];
         info->ms_select = ms[kPhSelect];

@@ -394,7 +394,7 @@ kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t
     if (a.colmin && (int64_t)blocks > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
     hipLaunchKernelGGL((dist_kernel<Ev, LPQ>), dim3(blocks), dim3(256), lds, s, a);
     KKM_HIP(hipGetLastError());
-    if (a.colmin) return launch_colmin_reduce(a, blocks, s);
+    if (a.colmin && a.colpart_blocks) *a.colpart_blocks = blocks;
     return KKM_OK;
 }
 

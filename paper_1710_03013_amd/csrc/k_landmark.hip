@@ -600,6 +600,7 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
     }
     // CSR of the final labels for the support
     csr_sort(L, ell, C);
+    stamp(a);
 
     // 4. outputs: final labels, segments, g^, and the support of the final centroids
     for (int r = tid; r < nr; r += nt) a.lab_final[r0 + r] = L.lbl[r0 + r];
@@ -623,61 +624,57 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         if (tid == 0) *a.updates_out = it;
         for (int m = tid; m < ell; m += nt) a.lab[ell + m] = L.lbl[m];   // final landmark labels
     }
+    // support rows in CSR order (and rows [ell, ell + 32) zeroed for whole-tile loads): one wavefront
+    // per row over all workgroups, lanes over the dimensions; row copy, FP32 / bfloat16 panels, norms
     TI* sup = static_cast<TI*>(a.support);
+    const int PD = (int)a.dpad;
+    const bool panels = a.ktype != KKM_KERNEL_RMSD;   // power-of-two padded rows only
     float nmax = 0.0f;
-    for (int k = wg * nt + tid; k < ell; k += G * nt) {
-        const int m = L.perm[k];
-        const int j = L.lbl[m];
-        const int cnt = L.off[j + 1] - L.off[j];
-        const TI* src = row(a.lm[m]);
-        TI* dst = sup + (int64_t)k * a.dpad;
-        double n64 = 0.0;
-        for (int64_t c = 0; c < a.dpad; ++c) {
-            const TI v = c < a.d ? src[c] : TI(0);
-            dst[c] = v;
-            n64 = fma((double)v, (double)v, n64);
+    for (int k = wg * nwaves + wave; k < ell + 32; k += G * nwaves) {
+        const bool real = k < ell;
+        int m = 0, cnt = 1;
+        if (real) {
+            m = L.perm[k];
+            const int j = L.lbl[m];
+            cnt = L.off[j + 1] - L.off[j];
         }
+        const TI* src = row(real ? a.lm[m] : 0);
+        double n64 = 0.0;
         float n32 = 0.0f;
-        for (int64_t c = 0; c < a.d; ++c) n32 = fmaf((float)src[c], (float)src[c], n32);
-        a.snorm64[k] = n64;
-        a.snorm32[k] = n32;
-        a.coef64[k] = 1.0 / (double)cnt;
-        a.coef32[k] = (float)(1.0 / (double)cnt);
-        a.src_index[k] = a.lm[m];
-        const int PD = (int)a.dpad;
-        const bool panels = a.ktype != KKM_KERNEL_RMSD;   // power-of-two padded rows only
-        if (panels && a.sup_pan)
-            for (int c = 0; c < PD; ++c) a.sup_pan[panel32_index(k, c, PD)] = c < a.d ? (float)src[c] : 0.0f;
-        if (panels && PD >= 16)
-            for (int c = 0; c < PD; ++c) {
+        for (int c = lane; c < PD; c += 64) {
+            const TI v = (real && c < a.d) ? src[c] : TI(0);
+            sup[(int64_t)k * PD + c] = v;
+            n64 = fma((double)v, (double)v, n64);
+            const float f = (float)v;
+            n32 = fmaf(f, f, n32);
+            if (panels && a.sup_pan) a.sup_pan[panel32_index(k, c, PD)] = f;
+            if (panels && PD >= 16) {
                 uint16_t hi = 0, lo = 0;
-                if (c < a.d) bf16_split((float)src[c], hi, lo);
+                if (real && c < a.d) bf16_split(f, hi, lo);
                 a.sup_hi[panel16_index(k, c, PD)] = hi;
                 a.sup_lo[panel16_index(k, c, PD)] = lo;
             }
+        }
+        n64 = wave_sum(n64);
+        n32 = wave_sum(n32);
+        if (lane == 0) {
+            a.snorm64[k] = n64;
+            a.snorm32[k] = n32;
+            a.coef64[k] = real ? 1.0 / (double)cnt : 0.0;
+            a.coef32[k] = real ? (float)(1.0 / (double)cnt) : 0.0f;
+            if (real) a.src_index[k] = a.lm[m];
+        }
         nmax = fmaxf(nmax, n32);
     }
     // one atomic per workgroup for the largest squared norm (non-negative floats order as integers)
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) nmax = fmaxf(nmax, __shfl_xor(nmax, o, 64));
-    if (lane == 0 && nmax > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(a.snorm_max), __float_as_uint(nmax));
-    // rows [ell, ell + 32) are read by whole-tile loads: keep them zero
-    for (int k = ell + wg * nt + tid; k < ell + 32; k += G * nt) {
-        for (int64_t c = 0; c < a.dpad; ++c) sup[(int64_t)k * a.dpad + c] = TI(0);
-        const int PD = (int)a.dpad;
-        const bool panels = a.ktype != KKM_KERNEL_RMSD;
-        if (panels && a.sup_pan)
-            for (int c = 0; c < PD; ++c) a.sup_pan[panel32_index(k, c, PD)] = 0.0f;
-        if (panels && PD >= 16)
-            for (int c = 0; c < PD; ++c) {
-                a.sup_hi[panel16_index(k, c, PD)] = 0;
-                a.sup_lo[panel16_index(k, c, PD)] = 0;
-            }
-        a.snorm64[k] = 0.0;
-        a.snorm32[k] = 0.0f;
-        a.coef64[k] = 0.0;
-        a.coef32[k] = 0.0f;
+    if (lane == 0) L.red[wave] = (double)nmax;
+    __syncthreads();
+    if (tid == 0) {
+        float mx = 0.0f;
+        for (int w = 0; w < nwaves; ++w) mx = fmaxf(mx, (float)L.red[w]);
+        if (mx > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(a.snorm_max), __float_as_uint(mx));
     }
+    stamp(a);
 }
 
 }  // namespace
@@ -708,18 +705,25 @@ LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C) {
     return LandmarkShape{G0, 0};
 }
 
-kkm_status launch_landmark_phase(const LandmarkArgs& args, int dtype, const DeviceInfo& dev, hipStream_t stream) {
-    const int G = args.grid;
+static kkm_status check_landmark_args(const LandmarkArgs& args, const DeviceInfo& dev, size_t* lds_out) {
     if (args.ldk != k_ld(args.ell)) return fail(KKM_ERR_INTERNAL, "landmark block stride");
-    const size_t lds = landmark_lds_bytes_host(args.ell, args.C, G, args.k_in_lds != 0);
+    const size_t lds = landmark_lds_bytes_host(args.ell, args.C, args.grid, args.k_in_lds != 0);
     if (lds > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "landmark set too large for one workgroup's LDS (l=" +
                                              std::to_string(args.ell) + ", C=" + std::to_string(args.C) +
                                              "); use more mini-batches");
+    if (sizeof(double) * 64 * (size_t)args.d > dev.max_lds_per_block)
+        return fail(KKM_ERR_UNSUPPORTED, "sample dimension too large");
+    *lds_out = lds;
+    return KKM_OK;
+}
+
+kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const DeviceInfo& dev, hipStream_t stream) {
+    size_t lds = 0;
+    KKM_TRY(check_landmark_args(args, dev, &lds));
     const size_t lds_tile = sizeof(double) * 64 * (size_t)args.d;
     const size_t lds_row = sizeof(double) * (size_t)args.d;
-    if (lds_tile > dev.max_lds_per_block) return fail(KKM_ERR_UNSUPPORTED, "sample dimension too large");
-    KKM_TRY(dispatch_dp(eval_dp(args.ktype, args.d), [&]<int DP>() -> kkm_status {
+    return dispatch_dp(eval_dp(args.ktype, args.d), [&]<int DP>() -> kkm_status {
         if constexpr (DP > 0) {
             const int ncol = args.ell + (args.init_mode ? args.C : 0);
             const dim3 kgrid((unsigned)((ncol + 63) / 64), (unsigned)((args.ell + 63) / 64));
@@ -744,7 +748,13 @@ kkm_status launch_landmark_phase(const LandmarkArgs& args, int dtype, const Devi
         }
         KKM_HIP(hipGetLastError());
         return KKM_OK;
-    }));
+    });
+}
+
+kkm_status launch_landmark_loop(const LandmarkArgs& args, int dtype, const DeviceInfo& dev, hipStream_t stream) {
+    size_t lds = 0;
+    KKM_TRY(check_landmark_args(args, dev, &lds));
+    const int G = args.grid;
     LandmarkArgs a = args;
     void* params[] = {&a};
     const void* fn = dtype == KKM_F64 ? reinterpret_cast<const void*>(&landmark_phase_kernel<double>)

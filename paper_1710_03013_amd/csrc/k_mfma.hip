@@ -263,7 +263,7 @@ kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
         if (a.colmin && (int64_t)blocks > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
         hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
         KKM_HIP(hipGetLastError());
-        if (a.colmin) return launch_colmin_reduce(a, blocks, s);
+        if (a.colmin && a.colpart_blocks) *a.colpart_blocks = blocks;
         return KKM_OK;
     };
     switch (a.sup.dpad) {

@@ -69,7 +69,9 @@ struct LandmarkShape {
 LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C);
 size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds);
 inline int64_t landmark_ldk(int64_t ell) { return (ell + 1) & ~int64_t(1); }
-kkm_status launch_landmark_phase(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
+// K_LL (+ K(x_l, m_j)) and the initial landmark labels; then the landmark loop and the support.
+kkm_status launch_landmark_block(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
+kkm_status launch_landmark_loop(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
 
 // ---------------------------------------------------------------- sparse-centroid distances (k_dist.hip)
 // Support of the centroids being assigned to: rows in CSR order, coefficients, self terms.
@@ -112,6 +114,8 @@ struct DistArgs {
     unsigned long long* colmin;   // [C] ord_enc(min over rows of D + Erow), or null (fit only)
     double* colpart;        // [C][colpart_cap] per-workgroup minima behind colmin (with colmin)
     int64_t colpart_cap;
+    int64_t* colpart_blocks;// host out (with colmin): workgroups of the pass; launch_colmin_reduce
+                            // then folds colpart into colmin
     int64_t n_support;      // rows of sup (offsets[C])
 };
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
