@@ -96,6 +96,104 @@ def cpu_baseline(X, cfg, landmarks, uniforms, init_labels):
                       f"BLAS threads={threads}, numpy elementwise single-threaded"}
 
 
+def serving_bench(args) -> int:
+    """Serving form: fitted models of the MD-frame and 64-d mixture workloads resident in HBM, a
+    Poisson stream of assign requests (sizes log-uniform in [1, 65536]) with fit jobs on ~5% of the
+    arrivals (N log-uniform in [1e4, 5e5], C in {10, 50, 100}, B = 10, s = 0.05), admitted by a
+    200 GB budget.  Inputs are resident before their arrival stamp.  Reports p50/p99 latency from
+    the arrival stamp to the host seeing completion, and assigned samples/s, per request rate."""
+    import torch
+    import kkm_inputs as ki
+    import paper_1710_03013_amd as kk
+    from paper_1710_03013_amd.serve import KkmBackend, Server
+
+    prec = args.precision or "fp32"
+    dev = torch.device("cuda:0")
+    log("[serve] generating the 64-d mixture and the MD frames")
+    X4, _ = ki.datasets.config_data(3)
+    X3, _ = ki.datasets.config_data(2)
+    data = {"mix64": torch.from_numpy(X4).to(dev), "md": torch.from_numpy(X3).to(dev)}
+    c4, c3 = ki.datasets.CONFIGS[3], ki.datasets.CONFIGS[2]
+    models = {}
+    log("[serve] fitting the resident models")
+    models["mix64"] = kk.kkm_fit(data["mix64"], "rbf", sigma=c4["sigma"], C=c4["C"], B=c4["B"], s=c4["s"],
+                                 max_iter=c4["T"], precision=prec, seed=2003)[0]
+    models["md"] = kk.kkm_fit(data["md"], "rmsd", sigma=c3["sigma"], n_atoms=c3["n_atoms"], C=c3["C"], B=c3["B"],
+                              s=c3["s"], max_iter=c3["T"], precision=prec, seed=2002)[0]
+    torch.cuda.synchronize()
+    rates = [float(r) for r in args.serving_rates.split(",")]
+    results = []
+    for rate in rates:
+        rng = np.random.default_rng(int(rate) + 7)
+        n_req = max(1, int(rate * args.serving_seconds))
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        arrivals = np.cumsum(gaps)
+        plan = []
+        for a in arrivals:
+            fam = "mix64" if rng.random() < 0.5 else "md"
+            if rng.random() < 0.05:
+                N = int(round(np.exp(rng.uniform(np.log(1e4), np.log(5e5)))))
+                N = min(N, data[fam].shape[0])   # the MD set holds 2e5 frames
+                C = int(rng.choice([10, 50, 100]))
+                o = int(rng.integers(0, data[fam].shape[0] - N + 1))
+                kw = dict(kernel="rbf", sigma=c4["sigma"]) if fam == "mix64" else \
+                    dict(kernel="rmsd", sigma=c3["sigma"], n_atoms=c3["n_atoms"])
+                kw.update(C=C, B=10, s=0.05, max_iter=20, seed=int(rng.integers(1 << 30)), precision=prec)
+                plan.append(("fit", a, fam, (o, N), kw))
+            else:
+                n = int(round(np.exp(rng.uniform(0.0, np.log(65536)))))
+                o = int(rng.integers(0, data[fam].shape[0] - n + 1))
+                plan.append(("assign", a, fam, (o, n), None))
+        srv = Server(KkmBackend(n_streams=4, precision=prec), budget_bytes=200 << 30, assign_slots=4, fit_workers=2)
+        for k_, m in models.items():
+            srv.add_model(k_, m)
+        reqs = []
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(plan) or not srv.idle:
+            now = time.perf_counter() - t0
+            while i < len(plan) and plan[i][1] <= now:
+                kind, a, fam, (o, n), kw = plan[i]
+                X = data[fam][o:o + n]
+                r = (srv.submit_fit(X, arrival=t0 + a, **kw) if kind == "fit"
+                     else srv.submit_assign(fam, X, arrival=t0 + a))
+                reqs.append(r)
+                i += 1
+            srv.poll()
+            if time.perf_counter() - t0 > args.serving_seconds * 20 + 60:
+                raise TimeoutError("serving run did not drain")
+        wall = time.perf_counter() - t0
+        lat_a = np.array([r.latency for r in reqs if r.kind == "assign" and r.error is None]) * 1e3
+        lat_f = np.array([r.latency for r in reqs if r.kind == "fit" and r.error is None]) * 1e3
+        errors = sum(1 for r in reqs if r.error is not None)
+        samples = sum(r.n for r in reqs if r.kind == "assign" and r.error is None)
+        res = {"rate_per_s": rate, "requests": len(reqs), "assign_requests": int(lat_a.size),
+               "fit_jobs": int(lat_f.size), "errors": errors, "wall_s": wall,
+               "assign_p50_ms": float(np.percentile(lat_a, 50)) if lat_a.size else None,
+               "assign_p99_ms": float(np.percentile(lat_a, 99)) if lat_a.size else None,
+               "fit_p50_ms": float(np.percentile(lat_f, 50)) if lat_f.size else None,
+               "fit_p99_ms": float(np.percentile(lat_f, 99)) if lat_f.size else None,
+               "samples_assigned_per_s": samples / wall, "launches": srv.launches,
+               "peak_hbm_gb_admitted": srv.peak_in_use / 1e9}
+        log(f"[serve] rate {rate}/s: {res}")
+        results.append(res)
+    out = {"metric": "serving: assign latency p50/p99 and samples assigned/s under a Poisson request stream",
+           "value": results[-1]["samples_assigned_per_s"], "unit": "samples/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": {"fp32": "f32", "bf16x3": "bf16x3+f32", "fp64": "f64"}[prec],
+           "data": "synthetic",
+           "config": {"workload": "serving: resident models of md-frames (rmsd, C=50) and mixture64 (rbf, C=100); "
+                                  "assign sizes log-uniform [1,65536]; 5% fit jobs N in [1e4,5e5], C in {10,50,100}, "
+                                  "B=10, s=0.05; HBM budget 200 GB", "precision": prec,
+                      "seconds_per_rate": args.serving_seconds},
+           "serving": results}
+    print(json.dumps(out), flush=True)
+    del srv, models, data
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +206,9 @@ def main() -> int:
     ap.add_argument("--latency-size", type=int, default=4096)
     ap.add_argument("--no-phase-timing", action="store_true",
                     help="do not record HIP events around the fit phases (no roofline entry)")
+    ap.add_argument("--serving", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--serving-rates", default="100,400,1600", help="request rates (per second) to sweep")
+    ap.add_argument("--serving-seconds", type=float, default=3.0, help="arrival window per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -121,6 +222,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.serving:
+        return serving_bench(args)
     k_idx, desc = WORKLOADS[args.workload]
     cfg = dict(ki.datasets.CONFIGS[k_idx])
     prec = args.precision or ("fp64" if cfg["dtype"] == "f64" else "fp32")
