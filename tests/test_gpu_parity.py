@@ -259,3 +259,68 @@ def test_rmsd_assign_and_fit_small():
     lab = kk.kkm_assign(model, torch.from_numpy(Y).cuda()).cpu().numpy()
     rl, rg, _ = okkm.assign(kern, Y, okkm.medoid_model(ref))
     _labels_match(lab, rl, rg, "rmsd assign")
+
+
+# ------------------------------------------------------------------------------------------ full sizes
+def _stride_prefix(X, B, k):
+    """Rows of the first k stride batches of X (B batches), laid out so that k stride batches of the
+    result are exactly those batches: row k*j + i of the result is row i + B*j of X."""
+    N = X.shape[0]
+    n = (N + B - 1) // B
+    idx = [i + B * j for j in range(n) for i in range(k) if i + B * j < N]
+    return X[np.asarray(idx)]
+
+
+def _sampled_assign_parity(kk, model, kern, X, n_sample, seed, prec, cost_tol):
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(X.shape[0], size=n_sample, replace=False))
+    Y = np.ascontiguousarray(X[rows])
+    exp = kk.kkm_model_export(model)
+    omodel = okkm.SparseModel(exp["support"].astype(np.float64), exp["offsets"], exp["coef"])
+    want, gaps, _ = okkm.assign(kern, Y, omodel)
+    Yd = torch.from_numpy(Y).cuda()
+    got = kk.kkm_assign(model, Yd, precision=prec).cpu().numpy()
+    _labels_match(got, want, gaps, f"sampled assign {prec}")
+    c_got = kk.kkm_cost(model, Yd, precision=prec)
+    c_want = okkm.cost(kern, Y, omodel)
+    assert abs(c_got - c_want) <= cost_tol * abs(c_want), (c_got, c_want)
+
+
+@pytest.mark.parametrize("prec,cost_tol", [("fp32", 1e-5), ("bf16x3", 1e-3)])
+def test_full_size_mixture64(prec, cost_tol):
+    """The 64-d workload at full size (N = 1e6, C = 100, B = 50, s = 0.02) in the benchmark's launch
+    configuration: the fitted model checked on a seeded 20 000-sample subsample (assign and cost
+    against the oracle), and the first three mini-batches teacher-forced against the oracle."""
+    kk = _kk()
+    _say(f"full mixture64 {prec}")
+    cfg = ki.datasets.CONFIGS[3]
+    X, _ = ki.datasets.config_data(3)
+    kern = Kernel("rbf", cfg["sigma"])
+    seed = 2003
+    L = ki.draw_all_landmarks(seed, X.shape[0], cfg["B"], cfg["s"])
+    u = ki.draw_kmpp_uniforms(seed, cfg["C"])
+    Xd = torch.from_numpy(X).cuda()
+    model, _, info = kk.kkm_fit(Xd, "rbf", sigma=cfg["sigma"], C=cfg["C"], B=cfg["B"], s=cfg["s"],
+                                max_iter=cfg["T"], precision=prec, seed=seed, landmarks=L, kmpp_uniforms=u)
+    torch.cuda.synchronize()
+    assert info["global_medoids"].shape == (cfg["B"], cfg["C"])
+    _sampled_assign_parity(kk, model, kern, X, 20_000, 77, prec, cost_tol)
+    # first three batches: the same landmarks and k-means++ draws, teacher-forced through the oracle
+    Xp = _stride_prefix(X, cfg["B"], 3)
+    model3, labels3, info3, ref3 = _fit_both(kk, Xp, kern, cfg["C"], 3, cfg["s"], cfg["T"], "kmeans++", seed, prec)
+    _check_fit(kk, model3, labels3, info3, ref3, kern, Xp, cfg["T"])
+
+
+def test_full_size_md_frames():
+    """The MD-frame workload at full size (N = 2e5 frames of 50 atoms, C = 50, B = 20, s = 0.05):
+    the fitted model checked on a seeded 4000-frame subsample against the oracle's RMSD kernel."""
+    kk = _kk()
+    _say("full md frames")
+    cfg = ki.datasets.CONFIGS[2]
+    X, _ = ki.datasets.config_data(2)
+    kern = Kernel("rmsd", cfg["sigma"], cfg["n_atoms"])
+    Xd = torch.from_numpy(X).cuda()
+    model, _, info = kk.kkm_fit(Xd, "rmsd", sigma=cfg["sigma"], n_atoms=cfg["n_atoms"], C=cfg["C"], B=cfg["B"],
+                                s=cfg["s"], max_iter=cfg["T"], seed=2002)
+    torch.cuda.synchronize()
+    _sampled_assign_parity(kk, model, kern, X, 4000, 78, "fp32", 1e-5)
