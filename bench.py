@@ -47,8 +47,29 @@ DIST_KERNEL_NAME = {("rbf", "fp32"): "mfma_dist_kernel", ("linear", "fp32"): "mf
                     ("rbf", "bf16x3"): "mfma_dist_kernel", ("linear", "bf16x3"): "mfma_dist_kernel"}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel
-# calibration), keyed by (kernel, workload); absent = not measured for the current kernel source.
-TRAFFIC = {}
+# calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
+# and its SHA-1 prefix at measurement time: a changed kernel source reports null.
+TRAFFIC_MEASURED = {
+    ("landmark_phase_kernel", "mixture16"): (10.046e6, "k_landmark.hip", "8a33ddbf0bfe"),
+    ("mfma_dist_kernel", "mixture16"): (3.130e6, "k_mfma.hip", "9eba0a854b63"),
+}
+
+
+def _traffic():
+    import hashlib
+    out = {}
+    for key, (nbytes, src, sha) in TRAFFIC_MEASURED.items():
+        path = os.path.join(ROOT, "paper_1710_03013_amd", "csrc", src)
+        try:
+            now = hashlib.sha1(open(path, "rb").read()).hexdigest()[:12]
+        except OSError:
+            continue
+        if now == sha:
+            out[key] = nbytes
+    return out
+
+
+TRAFFIC = _traffic()
 
 
 def log(msg):
@@ -207,6 +228,9 @@ def main() -> int:
     ap.add_argument("--no-phase-timing", action="store_true",
                     help="do not record HIP events around the fit phases (no roofline entry)")
     ap.add_argument("--serving", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run ten device-to-device copies of MIB MiB (the reference kernel for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counts to bytes) and exit")
     ap.add_argument("--serving-rates", default="100,400,1600", help="request rates (per second) to sweep")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="arrival window per rate")
     args = ap.parse_args()
@@ -224,6 +248,16 @@ def main() -> int:
         return 2
     if args.serving:
         return serving_bench(args)
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 10}), flush=True)
+        del src, dst
+        return 0
     k_idx, desc = WORKLOADS[args.workload]
     cfg = dict(ki.datasets.CONFIGS[k_idx])
     prec = args.precision or ("fp64" if cfg["dtype"] == "f64" else "fp32")
