@@ -91,6 +91,7 @@ struct FitWs {
     double* uniforms;
     int32_t* chosen;
     double* D2;
+    double* kpp_part;
     void* M;
     double* Mself;
     int64_t* Midx;
@@ -150,7 +151,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.lab_init = c.take<int32_t>(P.ellmax);
     w.uniforms = c.take<double>(C);
     w.chosen = c.take<int32_t>(C);
-    w.D2 = c.take<double>(P.nmax);
+    w.D2 = c.take<double>(2 * P.nmax);
+    w.kpp_part = c.take<double>(2 * 256);
     w.M = c.take<char>((size_t)C * P.dpad * es);
     w.Mself = c.take<double>(C);
     w.Midx = c.take<int64_t>(C);
@@ -494,6 +496,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
 
     KKM_TRY(launch_zero_i32(w.refine_counts, P.B, s));
     KKM_TRY(launch_zero_i32(w.flags, 2, s));
+    KKM_TRY(launch_zero_i32(w.lm_error, 1, s));
     // one host-to-device copy of the inputs block: [landmarks, initial labels, uniforms, medoids]
     // (the staging vector outlives the copy: it is released after the final synchronisation)
     std::vector<char> up;
@@ -519,7 +522,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     // batch-0 initialisation of the global medoids
     KKM_TRY(tm.begin());
     if (P.p.init == KKM_INIT_KMEANSPP) {
-        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, s));
+        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.barrier,
+                                w.lm_error, dev, s));
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
     } else if (P.p.init == KKM_INIT_MEDOIDS) {
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
@@ -729,7 +733,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         info->ms_refine = ms[kPhRefine];
         info->ms_select = ms[kPhSelect];
     }
-    if (lm_err) return fail(KKM_ERR_INTERNAL, "a landmark-loop barrier wait exceeded its cap");
+    if (lm_err) return fail(KKM_ERR_INTERNAL, "a grid-barrier wait (k-means++ or landmark loop) exceeded its cap");
     if (flags[0]) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
     return KKM_OK;
 }

@@ -242,8 +242,7 @@ __device__ __forceinline__ void reset_batch_state(const LandmarkArgs& a) {
     for (int i = threadIdx.x; i < a.n_zero_ints; i += blockDim.x) a.zero_ints[i] = 0;
     for (int i = threadIdx.x; i < a.C; i += blockDim.x) a.colmin[i] = ~0ull;
     if (threadIdx.x == 0) {
-        *a.barrier = 0u;
-        *a.error = 0;
+        *a.barrier = 0u;   // (the error flag accumulates over the fit: cleared once by the host)
         *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
     }
 }

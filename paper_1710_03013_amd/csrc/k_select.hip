@@ -10,6 +10,8 @@
 //
 // Every argmin keeps the lowest index on ties; minima are order-independent, so the chunked
 // reductions give the same result as a sequential scan.
+#include <cstdlib>
+
 #include "kkm_internal.hpp"
 #include "kkm_launch.hpp"
 
@@ -100,6 +102,189 @@ __global__ __launch_bounds__(256) void kpp_dist_kernel(BatchView b, KSpec ks, in
     double v = (kself64(ks, x) - 2.0 * k64p<DP>(ks, x, m)) + kself64(ks, m);
     v = v > 0.0 ? v : 0.0;
     D2[q] = k == 0 ? v : fmin(D2[q], v);
+}
+
+// Kernel k-means++ (Sec. 3.1) as one kernel whose workgroups are all resident: workgroup g owns the
+// contiguous rows [g R, (g + 1) R).  Pick k >= 1: every workgroup folds medoid k - 1 into its rows of
+// D^2 (D2 buffers alternate between picks), publishes its row sum, and after one grid barrier every
+// workgroup derives the same pick -- the owner chunk from the prefix of the G sums (in workgroup
+// order), then the row inside it by an ordered scan of that chunk.  The picked index is the first
+// row whose running sum exceeds u_k times the total (rows in index order; a pick with no mass falls
+// back to floor(u_k n)).
+struct KppArgs {
+    BatchView b;
+    KSpec ks;
+    int32_t C;
+    const double* uniforms;   // [C]
+    int32_t* chosen;          // [C] out
+    double* D2;               // [2][n]
+    double* part;             // [2][G]
+    unsigned* barrier;        // cleared before the launch
+    int32_t* error;           // set when a barrier wait exceeded its cap
+    int32_t lds_rows;         // own rows staged in LDS (linear / RBF, when they fit)
+};
+
+constexpr unsigned kKppSpinCap = 1u << 26;
+constexpr int kKppMaxGrid = 256;  // <= 256: one partial per thread in the owner search
+
+__device__ __forceinline__ void kpp_barrier(const KppArgs& a, unsigned& target) {
+    __syncthreads();
+    target += gridDim.x;
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned polls = 0;
+        while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > kKppSpinCap) {
+                atomicOr(a.error, 1);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Inclusive scan of one value per thread over the workgroup in a fixed order; *excl is the previous
+// thread's inclusive value (so excl of t + 1 equals incl of t bit for bit).  Returns the total.
+__device__ __forceinline__ double block_scan(double v, double* sh, double* excl, double* incl) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        const double add = t >= o ? sh[t - o] : 0.0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    *excl = t > 0 ? sh[t - 1] : 0.0;
+    *incl = sh[t];
+    const double total = sh[nt - 1];
+    __syncthreads();
+    return total;
+}
+
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
+    extern __shared__ __align__(16) unsigned char kpp_smem[];
+    __shared__ double sh[256];
+    __shared__ int32_t pick_sh;
+    __shared__ int32_t owner_sh;
+    __shared__ double base_sh;
+    constexpr int XS = DP + 1;                       // padded LDS row stride of the own rows
+    const int64_t n = a.b.n;
+    const int G = gridDim.x, g = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    const int64_t R = (n + G - 1) / G;
+    auto chunk = [&](int wg, int64_t* lo, int64_t* hi) {
+        *lo = min<int64_t>(n, (int64_t)wg * R);
+        *hi = min<int64_t>(n, *lo + R);
+    };
+    auto slice = [&](int64_t lo, int64_t hi, int64_t* qlo, int64_t* qhi) {   // thread t's contiguous part
+        const int64_t w = (hi - lo + nt - 1) / nt;
+        *qlo = min<int64_t>(hi, lo + (int64_t)t * w);
+        *qhi = min<int64_t>(hi, *qlo + w);
+    };
+    const TI* X = static_cast<const TI*>(a.b.X);
+    auto row = [&](int64_t q) { return X + (a.b.base + q * a.b.stride) * a.b.d; };
+    int64_t lo, hi, tlo, thi;
+    chunk(g, &lo, &hi);
+    slice(lo, hi, &tlo, &thi);
+    // linear / RBF with the own rows in LDS (the rows are read once; every pick reads LDS)
+    const bool lds_rows = DP > 0 && a.lds_rows != 0;
+    TI* xs = reinterpret_cast<TI*>(kpp_smem);                                      // [R][XS] + medoid row
+    double* d2own = reinterpret_cast<double*>(kpp_smem + ((sizeof(TI) * (R + 1) * XS + 15) & ~size_t(15)));   // [R]
+    if (lds_rows) {
+        for (int64_t p = t; p < (hi - lo) * DP; p += nt) {
+            const int64_t r = p / DP;
+            const int c = (int)(p - r * DP);
+            xs[r * XS + c] = c < a.b.d ? row(lo + r)[c] : TI(0);
+        }
+        __syncthreads();
+    }
+    unsigned target = 0;
+    int32_t prev = (int32_t)min<int64_t>((int64_t)floor(a.uniforms[0] * (double)n), n - 1);
+    if (g == 0 && t == 0) a.chosen[0] = prev;
+    for (int k = 1; k < a.C; ++k) {
+        const int cur = k & 1, old = cur ^ 1;
+        double* D2 = a.D2 + (int64_t)cur * n;
+        const double* D2o = a.D2 + (int64_t)old * n;
+        // fold medoid k - 1 into the own rows; row sums in order (thread slice, then threads)
+        const TI* m = row(prev);
+        if (lds_rows) {   // the medoid row, read once per pick into LDS (after the row of the own rows)
+            TI* ms = xs + R * XS;
+            for (int c = t; c < DP; c += nt) ms[c] = c < a.b.d ? m[c] : TI(0);
+            __syncthreads();
+            m = ms;
+        }
+        const double kmm = kself64(a.ks, m);
+        double ts = 0.0;
+        for (int64_t q = tlo; q < thi; ++q) {
+            double v;
+            if (lds_rows) {
+                if constexpr (DP > 0) {
+                    const TI* x = xs + (q - lo) * XS;
+                    v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, m)) + kmm;
+                }
+                v = v > 0.0 ? v : 0.0;
+                if (k > 1) v = fmin(d2own[q - lo], v);
+                d2own[q - lo] = v;
+            } else {
+                const TI* x = row(q);
+                v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, m)) + kmm;
+                v = v > 0.0 ? v : 0.0;
+                if (k > 1) v = fmin(D2o[q], v);
+            }
+            D2[q] = v;
+            ts += v;
+        }
+        double e0, i0;
+        const double gsum = block_scan(ts, sh, &e0, &i0);
+        if (t == 0) a.part[(int64_t)cur * G + g] = gsum;
+        kpp_barrier(a, target);
+        // every workgroup derives the same pick: owner chunk from the partials, then the row
+        const double* P = a.part + (int64_t)cur * G;
+        double pe, pi;
+        const double total = block_scan(t < G ? P[t] : 0.0, sh, &pe, &pi);   // G <= 256
+        const double u = a.uniforms[k];
+        if (t == 0) {
+            pick_sh = (int32_t)min<int64_t>((int64_t)floor(u * (double)n), n - 1);   // no mass: fallback
+            owner_sh = -1;
+        }
+        __syncthreads();
+        const double thr = u * total;
+        if (total > 0.0 && t < G && pi > thr && pe <= thr) {   // at most one thread
+            owner_sh = t;
+            base_sh = pe;
+        }
+        __syncthreads();
+        const int owner = owner_sh;
+        if (owner >= 0) {
+            int64_t olo, ohi, qlo, qhi;
+            chunk(owner, &olo, &ohi);
+            slice(olo, ohi, &qlo, &qhi);
+            double cs = 0.0;
+            for (int64_t q = qlo; q < qhi; ++q) cs += D2[q];
+            double ce, ci;
+            (void)block_scan(cs, sh, &ce, &ci);
+            const double base = base_sh;
+            if (base + ci > thr && base + ce <= thr) {   // at most one thread
+                double loc = base + ce;
+                int64_t pk = qhi - 1;
+                for (int64_t q = qlo; q < qhi; ++q) {
+                    loc += D2[q];
+                    if (loc > thr) {
+                        pk = q;
+                        break;
+                    }
+                }
+                pick_sh = (int32_t)pk;
+            }
+            __syncthreads();
+        }
+        prev = pick_sh;
+        if (g == 0 && t == 0) a.chosen[k] = prev;
+        __syncthreads();
+    }
 }
 
 template <typename TI>
@@ -563,22 +748,47 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
 }  // namespace
 
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
-                           int32_t* chosen, double* D2, hipStream_t s) {
+                           int32_t* chosen, double* D2, double* part, unsigned* barrier, int32_t* error,
+                           const DeviceInfo& dev, hipStream_t s) {
+    if (b.n <= 0) return fail(KKM_ERR_INVALID_ARG, "k-means++ on an empty batch");
+    // workgroups: at least KKM_KPP_WGS (default 128) when the rows allow, more when that lets every
+    // workgroup keep its rows in LDS; at most kKppMaxGrid and the CUs
+    static const int want = [] {
+        const char* e = std::getenv("KKM_KPP_WGS");
+        const int v = e ? std::atoi(e) : 0;
+        return v > 0 ? std::min(v, kKppMaxGrid) : 128;
+    }();
     const int dp = eval_dp(ks.type, ks.d);
-    for (int k = 0; k < C; ++k) {
-        hipLaunchKernelGGL(kpp_pick_kernel, dim3(1), dim3(1024), 0, s, D2, b.n, k, uniforms, chosen);
-        KKM_HIP(hipGetLastError());
-        if (k == C - 1) break;
-        KKM_TRY(dispatch_dp(dp, [&]<int DP>() -> kkm_status {
-            if (dtype == KKM_F64)
-                hipLaunchKernelGGL((kpp_dist_kernel<double, DP>), dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
-            else
-                hipLaunchKernelGGL((kpp_dist_kernel<float, DP>), dim3(nblocks(b.n, 256)), dim3(256), 0, s, b, ks, k, chosen, D2);
-            KKM_HIP(hipGetLastError());
-            return KKM_OK;
-        }));
+    const size_t es = dtype == KKM_F64 ? 8 : 4;
+    const int gmax = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kKppMaxGrid, (int64_t)dev.num_cus, b.n}));
+    int G = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)want, std::min<int64_t>(gmax, (b.n + 255) / 256)));
+    auto lds_for = [&](int g) {
+        const int64_t R = (b.n + g - 1) / g;
+        return ((es * (size_t)(R + 1) * (dp + 1) + 15) & ~size_t(15)) + 8 * (size_t)R;
+    };
+    bool lds_rows = false;
+    if (dp > 0) {
+        for (int g = G; g <= gmax; g = g < gmax ? std::min(gmax, g + std::max(1, g / 8)) : gmax + 1)
+            if (lds_for(g) + 4096 <= dev.max_lds_per_block) {
+                G = g;
+                lds_rows = true;
+                break;
+            }
     }
-    return KKM_OK;
+    const size_t lds = lds_rows ? lds_for(G) : 0;
+    KppArgs a{b, ks, C, uniforms, chosen, D2, part, barrier, error, lds_rows ? 1 : 0};
+    KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(barrier), 1, s));
+    return dispatch_dp(dp, [&]<int DP>() -> kkm_status {
+        const void* fn = dtype == KKM_F64 ? reinterpret_cast<const void*>(&kmeanspp_kernel<double, DP>)
+                                          : reinterpret_cast<const void*>(&kmeanspp_kernel<float, DP>);
+        KKM_TRY(allow_dynamic_lds(fn, lds));
+        int per_cu = 0;
+        KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
+        if (per_cu * dev.num_cus < G) return fail(KKM_ERR_DEVICE, "k-means++ grid does not fit co-resident");
+        void* params[] = {&a};
+        KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(256), params, lds, s));
+        return KKM_OK;
+    });
 }
 
 kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, int C, const int32_t* chosen, void* M,

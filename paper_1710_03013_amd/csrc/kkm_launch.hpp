@@ -179,9 +179,11 @@ int select_chunks(int64_t n);
 // tile_f64: the distance tile Dt holds doubles (FP64 precision) rather than floats.
 kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& dev, hipStream_t s);
 
-// k-means++ on a batch: uniforms[C] device, chosen[C] device out, D2 [n] scratch.
+// k-means++ on a batch: uniforms[C] device, chosen[C] device out, D2 [2n] and part [512] scratch,
+// barrier / error as for the landmark loop (barrier cleared here).
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
-                           int32_t* chosen, double* D2, hipStream_t s);
+                           int32_t* chosen, double* D2, double* part, unsigned* barrier, int32_t* error,
+                           const DeviceInfo& dev, hipStream_t s);
 // Global medoids <- batch rows `chosen` (valid, counts 0), or all unset when chosen == null.
 kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, int C, const int32_t* chosen,
                               void* M, int64_t Mpad, double* Mself, int64_t* Midx, int64_t* wcount, hipStream_t s);
