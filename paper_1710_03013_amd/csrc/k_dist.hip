@@ -276,14 +276,17 @@ __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
     }
 }
 
-// A whole block per listed row (supports of hundreds of rows and more): 256 support rows per step,
-// one per thread, then per-cluster sums in row order and a block reduction of best / second best.
+// A whole block per listed row (supports of hundreds of rows and more): up to kRefineChunk support
+// rows per pass (four per thread at a time), then per-cluster sums in row order and a block
+// reduction of best / second best.
+constexpr int kRefineChunk = 2048;
+
 template <typename TI, int DP>
 __global__ __launch_bounds__(256) void refine_block_kernel(DistArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int C = a.sup.C;
-    double* Kv = reinterpret_cast<double*>(smem_raw);   // [256]
-    double* facc = Kv + 256;                              // [C]
+    double* Kv = reinterpret_cast<double*>(smem_raw);   // [kRefineChunk]
+    double* facc = Kv + kRefineChunk;                     // [C]
     __shared__ double rb1[256], rb2[256];
     __shared__ int ri1[256];
     const int32_t* off = a.sup.offsets;
@@ -294,16 +297,28 @@ __global__ __launch_bounds__(256) void refine_block_kernel(DistArgs a) {
         const int64_t q = a.refine_list[i];
         const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
         for (int j = threadIdx.x; j < C; j += blockDim.x) facc[j] = 0.0;
-        for (int64_t base = 0; base < ns; base += 256) {
-            const int lim = (int)min<int64_t>(256, ns - base);
+        for (int64_t base = 0; base < ns; base += kRefineChunk) {
+            const int lim = (int)min<int64_t>(kRefineChunk, ns - base);
             __syncthreads();
-            if ((int)threadIdx.x < lim)
-                Kv[threadIdx.x] = a.sup.coef64[base + threadIdx.x] *
-                                  k64p<DP>(a.ks, xr, rows + (base + threadIdx.x) * a.sup.dpad);
+            // four support rows per thread at a time: their loads and exponentials overlap
+            for (int l0 = threadIdx.x; l0 < lim; l0 += 4 * blockDim.x) {
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int l = l0 + u * (int)blockDim.x;
+                    v[u] = l < lim ? k64p<DP>(a.ks, xr, rows + (base + l) * a.sup.dpad) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int l = l0 + u * (int)blockDim.x;
+                    if (l < lim) Kv[l] = a.sup.coef64[base + l] * v[u];
+                }
+            }
             __syncthreads();
             for (int j = threadIdx.x; j < C; j += blockDim.x) {
                 const int64_t lo = max<int64_t>(off[j], base), hi = min<int64_t>(off[j + 1], base + lim);
                 double s = facc[j];
+#pragma unroll 8
                 for (int64_t l = lo; l < hi; ++l) s += Kv[l - base];
                 facc[j] = s;
             }
@@ -446,7 +461,8 @@ kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) 
 kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s, int64_t n_support) {
     if (a.q.n <= 0) return KKM_OK;
     const bool per_block = n_support > 256;   // large supports: a whole block per listed row
-    const size_t lds = per_block ? sizeof(double) * (256 + (size_t)a.sup.C) : sizeof(double) * 4 * (256 + (size_t)a.sup.C);
+    const size_t lds = per_block ? sizeof(double) * (kRefineChunk + (size_t)a.sup.C)
+                                 : sizeof(double) * 4 * (256 + (size_t)a.sup.C);
     const unsigned blocks = per_block ? (unsigned)std::min<int64_t>(a.q.n, 4 * (int64_t)dev.num_cus)
                                       : (unsigned)std::min<int64_t>((a.q.n + 3) / 4, 2 * (int64_t)dev.num_cus);
     return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {

@@ -110,8 +110,33 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
     const int nchunks = (ell + 63) / 64;
     for (int i = tid; i < nchunks * C; i += nt) L.chunk[i] = 0;
     __syncthreads();
-    // ranks inside each 64-landmark chunk, one distinct label at a time
-    for (int ch = wave; ch < nchunks; ch += nwaves) {
+    // ranks inside each 64-landmark chunk
+    if (C <= 64) {
+        // few clusters: every label in turn over the wave's chunks (independent ballots, no
+        // dependence between chunks)
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        for (int ch0 = wave; ch0 < nchunks; ch0 += 4 * nwaves) {
+            int labs[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ch = ch0 + u * nwaves;
+                const int m = ch * 64 + lane;
+                labs[u] = (ch < nchunks && m < ell) ? L.lbl[m] : -1;
+            }
+            for (int j = 0; j < C; ++j) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int ch = ch0 + u * nwaves;
+                    const uint64_t mask = __ballot(labs[u] == j);
+                    if (labs[u] == j) L.rank[ch * 64 + lane] = (uint8_t)__popcll(mask & below);
+                    if (lane == 0 && ch < nchunks) L.chunk[ch * C + j] = (uint16_t)__popcll(mask);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // otherwise one distinct label at a time
+    for (int ch = wave; C > 64 && ch < nchunks; ch += nwaves) {
         const int m = ch * 64 + lane;
         const bool valid = m < ell;
         const int lab = valid ? L.lbl[m] : -1;
