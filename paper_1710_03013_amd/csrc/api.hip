@@ -191,8 +191,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.refine_list = c.take<int32_t>(P.nmax);
     w.bmed = c.take<int32_t>(C);
     w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
-    w.gpart_v = c.take<double>((size_t)C * P.nchunk);
-    w.gpart_i = c.take<int32_t>((size_t)C * P.nchunk);
+    w.gpart_v = c.take<double>((size_t)C * merge_chunks(P.nmax));
+    w.gpart_i = c.take<int32_t>((size_t)C * merge_chunks(P.nmax));
     w.mtarget = c.take<char>((size_t)2 * C * P.dpad * es);
     w.malpha = c.take<double>(C);
     w.barrier = c.take<unsigned>(1);

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void merge_partial_kernel(SelectArgs a) {
     }
     block_vmin(bv, bi);
     if (threadIdx.x == 0) {
-        const int64_t at = (int64_t)j * a.nchunk + chunk;
+        const int64_t at = (int64_t)j * a.mchunk + chunk;
         a.gpart_v[at] = bv;
         a.gpart_i[at] = bi == INT64_MAX ? -1 : (int32_t)bi;
     }
@@ -440,23 +440,22 @@ __global__ __launch_bounds__(256) void merge_prep_kernel(SelectArgs a) {
     }
 }
 
-// Block = 256 batch rows x kMergeTJ clusters (two targets each).  Wave w scores the targets of
-// clusters 4w..4w+3 against all 256 rows, four consecutive rows per lane, so that every target value
-// read from LDS (a broadcast) feeds four rows and every row value feeds eight targets.  Rows are
-// staged through LDS dimension-major in chunks of 16 dimensions (coalesced global reads).  Scores
-// follow the per-row merge formula in FP64 (explicit differences for RBF); the (value, position)
-// minimum of each cluster over the block's rows goes to gpart.
+// Block = kMergeRows batch rows x kMergeTJ clusters (two targets each).  Wave w scores the targets of
+// clusters 4w..4w+3 against all kMergeRows rows, one row per lane, so that every target value read
+// from LDS (a broadcast) feeds a row and every row value feeds eight targets.  Rows are staged
+// through LDS dimension-major in chunks of 16 dimensions (coalesced global reads).  Scores follow
+// the per-row merge formula in FP64 (explicit differences for RBF); the (value, position) minimum
+// of each cluster over the block's rows goes to gpart (kMergeRows-row chunks: merge_chunks).
 constexpr int kMergeTJ = 16;
-constexpr int kMergeRows = 256;
-constexpr int kMergeXs = kMergeRows + 4;   // LDS row stride of the staged chunk (keeps 16-byte alignment)
+constexpr int kMergeRows = 64;
+constexpr int kMergeXs = kMergeRows + 4;   // LDS row stride of the staged chunk
 
 template <typename TI, int DP>
 __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
-    static_assert(kMergeRows == kRowsPerBlock, "merge chunks are the selection row chunks");
     constexpr int NT = 2 * kMergeTJ;
     constexpr int CH = DP < 16 ? DP : 16;
     __shared__ double Ts[DP][NT];
-    __shared__ __align__(16) TI Xs[CH][kMergeXs];
+    __shared__ TI Xs[CH][kMergeXs];
     const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
     const int d = a.b.d;
     const int lane = threadIdx.x & 63;
@@ -471,12 +470,10 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
     const int64_t row0 = (int64_t)chunk * kMergeRows;
     const int nrows = (int)min<int64_t>(kMergeRows, a.b.n - row0);
     const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
-    double acc[4][8];
+    double acc[8];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc[r][t] = 0.0;
-    double xx[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+    double xx = 0.0;
 #pragma unroll 1
     for (int k0 = 0; k0 < DP; k0 += CH) {
         __syncthreads();   // previous chunk consumed (and Ts written, on the first pass)
@@ -489,28 +486,21 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
         __syncthreads();
 #pragma unroll 4
         for (int k = 0; k < CH; ++k) {
-            double xv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xv[r] = (double)Xs[k][4 * lane + r];
+            const double xv = (double)Xs[k][lane];
             const double* tk = &Ts[k0 + k][8 * wave];
             double tv[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) tv[t] = tk[t];
             if (lin) {
+                xx = fma(xv, xv, xx);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    xx[r] = fma(xv[r], xv[r], xx[r]);
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) acc[r][t] = fma(xv[r], tv[t], acc[r][t]);
-                }
+                for (int t = 0; t < 8; ++t) acc[t] = fma(xv, tv[t], acc[t]);
             } else {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        const double df = xv[r] - tv[t];
-                        acc[r][t] = fma(df, df, acc[r][t]);
-                    }
+                for (int t = 0; t < 8; ++t) {
+                    const double df = xv - tv[t];
+                    acc[t] = fma(df, df, acc[t]);
+                }
             }
         }
     }
@@ -521,20 +511,15 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
         const double alpha = a.malpha[j];
         double bv = kInf;
         int64_t bi = INT64_MAX;
-        if (alpha > 0.0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int pos = 4 * lane + r;
-                if (pos < nrows) {
-                    const double k1 = lin ? acc[r][2 * c] : ::exp(-acc[r][2 * c] * a.ks.inv2s2);
-                    double sc = (lin ? xx[r] : 1.0) - 2.0 * alpha * k1;
-                    if (alpha < 1.0) {
-                        const double k2 = lin ? acc[r][2 * c + 1] : ::exp(-acc[r][2 * c + 1] * a.ks.inv2s2);
-                        sc = sc - 2.0 * (1.0 - alpha) * k2;
-                    }
-                    vmin(bv, bi, sc, row0 + pos);
-                }
+        if (alpha > 0.0 && lane < nrows) {
+            const double k1 = lin ? acc[2 * c] : ::exp(-acc[2 * c] * a.ks.inv2s2);
+            double sc = (lin ? xx : 1.0) - 2.0 * alpha * k1;
+            if (alpha < 1.0) {
+                const double k2 = lin ? acc[2 * c + 1] : ::exp(-acc[2 * c + 1] * a.ks.inv2s2);
+                sc = sc - 2.0 * (1.0 - alpha) * k2;
             }
+            bv = sc;
+            bi = row0 + lane;
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -543,7 +528,7 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
             vmin(bv, bi, v2, i2);
         }
         if (lane == 0) {
-            const int64_t at = (int64_t)j * a.nchunk + chunk;
+            const int64_t at = (int64_t)j * a.mchunk + chunk;
             a.gpart_v[at] = bv;
             a.gpart_i[at] = bi == INT64_MAX ? -1 : (int32_t)bi;
         }
@@ -561,9 +546,9 @@ __global__ __launch_bounds__(64) void merge_final_kernel(SelectArgs a) {
     if (alpha > 0.0 && med >= 0) {
         double bv = kInf;
         int64_t bi = INT64_MAX;
-        for (int c = lane; c < a.nchunk; c += 64) {
-            const int32_t i = a.gpart_i[(int64_t)j * a.nchunk + c];
-            if (i >= 0) vmin(bv, bi, a.gpart_v[(int64_t)j * a.nchunk + c], i);
+        for (int c = lane; c < a.mchunk; c += 64) {
+            const int32_t i = a.gpart_i[(int64_t)j * a.mchunk + c];
+            if (i >= 0) vmin(bv, bi, a.gpart_v[(int64_t)j * a.mchunk + c], i);
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -804,15 +789,18 @@ kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, in
 }
 
 int select_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kRowsPerBlock - 1) / kRowsPerBlock); }
+int merge_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kMergeRows - 1) / kMergeRows); }
 
-kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& dev, hipStream_t s) {
-    const dim3 grid(a.nchunk, a.C);
-    if (tile_f64) hipLaunchKernelGGL(medoid_candidates_kernel<double>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(medoid_candidates_kernel<float>, grid, dim3(256), 0, s, a);
+kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& dev, hipStream_t s) {
+    const dim3 grid(a0.nchunk, a0.C);
+    if (tile_f64) hipLaunchKernelGGL(medoid_candidates_kernel<double>, grid, dim3(256), 0, s, a0);
+    else hipLaunchKernelGGL(medoid_candidates_kernel<float>, grid, dim3(256), 0, s, a0);
     KKM_HIP(hipGetLastError());
     const unsigned cand_blocks = (unsigned)std::max(1, 4 * dev.num_cus);
-    const dim3 tgrid(a.nchunk, (a.C + kMergeTJ - 1) / kMergeTJ);
+    SelectArgs a = a0;
+    const dim3 tgrid(merge_chunks(a.b.n), (a.C + kMergeTJ - 1) / kMergeTJ);
     auto run = [&]<typename TI, int DP>() -> kkm_status {
+        a.mchunk = DP == 0 ? a.nchunk : merge_chunks(a.b.n);
         hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
         KKM_HIP(hipGetLastError());
         if constexpr (DP == 0) {

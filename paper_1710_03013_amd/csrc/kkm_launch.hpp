@@ -165,8 +165,9 @@ struct SelectArgs {
     int32_t* cand_count;    // [1] (cleared before the batch)
     int32_t cand_cap;
     int32_t* cand_total;    // [1] accumulates cand_count over batches, or null
-    double* gpart_v;        // [C][nchunk] merge partials
+    double* gpart_v;        // [C][mchunk] merge partials (set by launch_select)
     int32_t* gpart_i;
+    int32_t mchunk;
     void* mtarget;          // [2C][Mpad] merge targets: row 2j = m_j^i, row 2j+1 = m_j (input dtype)
     double* malpha;         // [C] merge weight alpha_j (0: m_j stays)
     // per-batch info rows (device, length C) or null
@@ -175,6 +176,8 @@ struct SelectArgs {
     int64_t* info_gmed;
 };
 int select_chunks(int64_t n);
+// Merge partials per cluster for a batch of n rows (the workspace holds C * merge_chunks(nmax)).
+int merge_chunks(int64_t n);
 // Member counts, label scatter, batch medoids (Eq. 10) and the merge (Eq. 11-13).
 // tile_f64: the distance tile Dt holds doubles (FP64 precision) rather than floats.
 kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& dev, hipStream_t s);
