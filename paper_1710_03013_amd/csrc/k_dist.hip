@@ -210,11 +210,6 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
 // One wavefront per listed row: lanes evaluate a_l K(x, s_l) in FP64 for 256 support rows at a
 // time into LDS, each lane then adds the part of its clusters' segments (in row order), and the
 // best / second-best cluster is found by a wave reduction (lowest index on ties).
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename TI, int DP>
 __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {

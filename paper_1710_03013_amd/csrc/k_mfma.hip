@@ -40,19 +40,39 @@ template <typename TI, int DP, bool BF3>
 __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     constexpr int H = DP / 2;                      // dimensions per lane half
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int C = a.sup.C;
     float* Dl = reinterpret_cast<float*>(smem_raw);   // [C][32]
+    // segment metadata of the support, read once per workgroup: offsets, self terms, |a| sums
+    double* mself = reinterpret_cast<double*>(smem_raw + sizeof(float) * (size_t)C * 32);   // [C]
+    double* msegabs = mself + C;                                                             // [C]
+    int32_t* off = reinterpret_cast<int32_t*>(msegabs + C);                                 // [C+1]
     __shared__ float Ew[4][32];
+    __shared__ float Eg[4][32];
+    __shared__ double Bw1[4][32], Bw2[4][32];
+    __shared__ int Iw[4][32];
+    __shared__ float Pt[4][32 * 33];
     __shared__ int jb[5];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = lane >> 5, col = lane & 31;
-    const int64_t q = (int64_t)blockIdx.x * 32 + col;
-    const bool active = q < a.q.n;
-    const int C = a.sup.C;
-    const int32_t* off = a.sup.offsets;
     const int type = a.ks.type;
     const float inv2s2 = (float)a.ks.inv2s2;
 
     if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
+    for (int j = threadIdx.x; j <= C; j += blockDim.x) {
+        off[j] = a.sup.offsets[j];
+        if (j < C) {
+            mself[j] = a.sup.self[j];
+            msegabs[j] = a.sup.segabs[j];
+        }
+    }
+    const float snmax = *a.sup.snorm_max;
+    __syncthreads();
+
+    // groups of 32 samples, grid-stride
+    const int64_t ngroups = (a.q.n + 31) / 32;
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t q = grp * 32 + col;
+    const bool active = q < a.q.n;
 
     // the sample's half of the dimensions, its squared norm, and its bf16 split
     const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
@@ -97,44 +117,12 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                 bl[v][t] = (__bf16)(x - (float)hi);
             }
     }
-    const float snmax = *a.sup.snorm_max;
-    __syncthreads();
-
-    float emax = 0.0f;
     const int j0 = jb[wave], j1 = jb[wave + 1];
     const int start = off[j0], end = off[j1];
-    int j = j0;
-    float accf = 0.0f;
-    auto finalize = [&](int jj) {
-        const int lo = off[jj], hi = off[jj + 1];
-        const double g = a.sup.self[jj];
-        float D;
-        if (hi > lo && g < kInf) {
-            D = kqq - 2.0f * accf + (float)g;
-            // error bound of D (FP32 / BF16x3 dot products, FP32 norms and sums)
-            const float len = (float)(hi - lo), segabs = (float)a.sup.segabs[jj];
-            const float dot_rel = BF3 ? kUbf + (3.0f * DP + 2.0f) * kU32 : (DP + 2.0f) * kU32;
-            const float kmax = sqrtf(qn * snmax) * 1.0001f;
-            float ef;
-            if (type == KKM_KERNEL_LINEAR) {
-                ef = (dot_rel * kmax + (len + 2.0f) * kU32 * kmax) * segabs;
-            } else {
-                // exp's relative error is rho (from the squared-distance error) plus a few ulps, so the
-                // sum's error scales with the sum of |a_l| K: the sum itself when no a_l is negative
-                const float rho = (2.0f * dot_rel * kmax + (DP + 6.0f) * kU32 * (qn + snmax)) * inv2s2;
-                const float mass = a.sup.nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
-                ef = (rho + (len + 8.0f) * kU32) * mass;
-            }
-            const float e = 2.0f * ef + 3.0f * kU32 * (fabsf(kqq) + 2.0f * fabsf(accf) + fabsf((float)g)) +
-                            (type == KKM_KERNEL_LINEAR ? (DP + 2.0f) * kU32 * qn : 0.0f);
-            emax = fmaxf(emax, 2.0f * e);
-        } else {
-            D = __builtin_huge_valf();
-        }
-        if (h == 0) Dl[jj * 32 + col] = D;
-        accf = 0.0f;
-    };
-
+    float* P = Pt[wave];                         // [32 rows][33]: one tile of a_l K(x, s_l)
+    for (int p = lane; p < (j1 - j0) * 32; p += 64) Dl[j0 * 32 + p] = 0.0f;
+    wave_sync_lds();
+    int jc = j0;                                 // first segment that may still receive rows
     for (int r0 = start & ~31; r0 < end; r0 += 32) {
         const int tile_end = min(r0 + 32, end);
         // A fragment: support row r0 + col, the lane half's dimensions, read from the panel of the
@@ -177,65 +165,140 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
 #pragma unroll
             for (int s = 0; s < H; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], xq[s], acc, 0, 0, 0);
         }
-        // epilogue: v_i = a_l K(x, s_l) for the lane's rows l = r0 + 8(i/4) + 4h + i%4
-        float v[16];
+        // epilogue: a_l K(x, s_l) for the lane's rows l = r0 + 8(i/4) + 4h + i%4, into the LDS tile
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int rb = r0 + 8 * b + 4 * h;
             const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
             const float4 cf4 = *reinterpret_cast<const float4*>(a.sup.coef32 + rb);
-            v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
-            v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
-            v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
-            v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
+            const int lr = 8 * b + 4 * h;
+            P[(lr + 0) * 33 + col] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
+            P[(lr + 1) * 33 + col] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
+            P[(lr + 2) * 33 + col] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
+            P[(lr + 3) * 33 + col] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
         }
-        // segments meeting this tile, in order
-        while (j < j1 && off[j] < tile_end) {
-            const int lo = max(off[j], r0), hi = min(off[j + 1], tile_end);
-            float part = 0.0f;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int row = r0 + 8 * (i / 4) + 4 * h + (i % 4);
-                part += (row >= lo && row < hi) ? v[i] : 0.0f;
+        wave_sync_lds();
+        // segments meeting the tile, 64 at a time: lane half h takes every other segment, lane col
+        // its sample; each adds its rows of the tile in row order to the segment's accumulator
+        for (;;) {
+            const int sj = jc + lane;
+            const int o0 = sj < j1 ? off[sj] : end;
+            const int o1 = sj < j1 ? off[sj + 1] : end;
+            const uint64_t started = __ballot(sj < j1 && o0 < tile_end);   // a prefix: offsets ascend
+            const int nseg = __popcll(started);
+            for (int k0 = 0; k0 < nseg; k0 += 2) {
+                const int k = k0 + h;
+                const int lo_k = __shfl(o0, k, 64), hi_k = __shfl(o1, k, 64);
+                if (k < nseg) {
+                    const int lo = max(lo_k, r0), hi = min(hi_k, tile_end);
+                    float part = 0.0f;
+                    for (int r = lo; r < hi; ++r) part += P[(r - r0) * 33 + col];
+                    if (hi > lo) Dl[(jc + k) * 32 + col] += part;
+                }
             }
-            part += __shfl_xor(part, 32, 64);
-            accf += part;
-            if (off[j + 1] <= tile_end) {
-                finalize(j);
-                ++j;
-            } else {
+            if (nseg == 0) break;
+            // the last counted segment may continue in the next tile
+            const int last_end = __shfl(o1, nseg - 1, 64);
+            if (last_end > tile_end) {
+                jc += nseg - 1;
                 break;
             }
+            jc += nseg;
+            if (nseg < 64) break;
         }
+        wave_sync_lds();
     }
-    while (j < j1) {   // empty segments after the last row of this quarter
-        finalize(j);
-        ++j;
+
+    // distances, error bounds and the wave's best / second best per sample (lane half h takes
+    // every other cluster; lowest cluster index on equal distances).  The row decision compares
+    // D = K(x,x) + g_j - 2 f_j formed in FP64 from the FP32 sums f_j, so its error is that of the
+    // f_j alone (K(x,x) is common to the row and cancels in every difference): ef bounds |f_j - exact|.
+    // The stored FP32 distances carry in addition their rounding and, for the linear kernel, the
+    // error of the FP32 norm (row bound Ecol, used by the medoid candidates).
+    float egap = 0.0f, ecol = 0.0f;
+    double b1 = kInf, b2 = kInf;
+    int i1 = C;
+    const float dot_rel = BF3 ? kUbf + (3.0f * DP + 2.0f) * kU32 : (DP + 2.0f) * kU32;
+    const float kmax = sqrtf(qn * snmax) * 1.0001f;
+    for (int jj = j0 + h; jj < j1; jj += 2) {
+        const int lo = off[jj], hi = off[jj + 1];
+        const double g = mself[jj];
+        const float accf = Dl[jj * 32 + col];
+        double D64 = kInf;
+        float D = __builtin_huge_valf();
+        if (hi > lo && g < kInf) {
+            D64 = (double)kqq + g - 2.0 * (double)accf;
+            D = (float)D64;
+            const float len = (float)(hi - lo), segabs = (float)msegabs[jj];
+            float ef;
+            if (type == KKM_KERNEL_LINEAR) {
+                ef = (dot_rel * kmax + (len + 2.0f) * kU32 * kmax) * segabs;
+            } else {
+                // exp's relative error is rho (from the squared-distance error) plus a few ulps, so the
+                // sum's error scales with the sum of |a_l| K: the sum itself when no a_l is negative
+                const float rho = (2.0f * dot_rel * kmax + (DP + 6.0f) * kU32 * (qn + snmax)) * inv2s2;
+                const float mass = a.sup.nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
+                ef = (rho + (len + 8.0f) * kU32) * mass;
+            }
+            // (plus the FP64 rounding of D and of the self term, 4 units of 2^-53 of the magnitudes)
+            egap = fmaxf(egap, 2.0f * ef * 1.0001f +
+                                   (float)(4.5e-16 * (fabs((double)kqq) + fabs(g) + 2.0 * fabs((double)accf))));
+            const float e = 2.0f * ef + 2.0f * kU32 * fabsf(D) +
+                            (type == KKM_KERNEL_LINEAR ? (DP + 2.0f) * kU32 * qn : 0.0f);
+            ecol = fmaxf(ecol, 2.0f * e);
+        }
+        Dl[jj * 32 + col] = D;
+        if (D64 < b1) { b2 = b1; b1 = D64; i1 = jj; }
+        else if (D64 < b2) { b2 = D64; }
     }
-    if (h == 0) Ew[wave][col] = emax;
+    {   // merge the two lane halves
+        const double c1 = __shfl_xor(b1, 32, 64), c2 = __shfl_xor(b2, 32, 64);
+        const int k1 = __shfl_xor(i1, 32, 64);
+        if (c1 < b1 || (c1 == b1 && k1 < i1)) {
+            b2 = fmin(b1, c2);
+            b1 = c1;
+            i1 = k1;
+        } else {
+            b2 = fmin(b2, c1);
+        }
+        egap = fmaxf(egap, __shfl_xor(egap, 32, 64));
+        ecol = fmaxf(ecol, __shfl_xor(ecol, 32, 64));
+    }
+    if (h == 0) {
+        Ew[wave][col] = ecol;
+        Eg[wave][col] = egap;
+        Bw1[wave][col] = b1;
+        Bw2[wave][col] = b2;
+        Iw[wave][col] = i1;
+    }
     __syncthreads();
 
     const float E = fmaxf(fmaxf(Ew[0][col], Ew[1][col]), fmaxf(Ew[2][col], Ew[3][col]));
+    const float EG = fmaxf(fmaxf(Eg[0][col], Eg[1][col]), fmaxf(Eg[2][col], Eg[3][col]));
     bool need = false;   // row listed for the FP64 re-decision
     if (wave == 0 && h == 0 && active) {
-        float best = __builtin_huge_valf(), second = __builtin_huge_valf();
-        int bj = 0;
-        for (int jj = 0; jj < C; ++jj) {
-            const float D = Dl[jj * 32 + col];
-            if (D < best) { second = best; best = D; bj = jj; }
-            else if (D < second) { second = D; }
+        // waves hold ascending cluster ranges: a later wave wins only with a smaller distance
+        double best = Bw1[0][col], second = Bw2[0][col];
+        int bj = Iw[0][col];
+        for (int w = 1; w < 4; ++w) {
+            const double c1 = Bw1[w][col], c2 = Bw2[w][col];
+            if (c1 < best) {
+                second = fmin(best, c2);
+                best = c1;
+                bj = Iw[w][col];
+            } else {
+                second = fmin(second, c1);
+            }
         }
+        if (bj >= C) bj = 0;
         a.labels[q] = bj;
-        if (a.best) a.best[q] = (double)best;
+        if (a.best) a.best[q] = best;
         if (a.Erow) a.Erow[q] = E;
-        if (a.gap) {
-            const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)kqq));
-            a.gap[q] = second < __builtin_huge_valf() ? (float)(((double)second - (double)best) / (scale > 0 ? scale : 1.0))
-                                                      : __builtin_huge_valf();
-        }
-        const double gap = (double)second - (double)best;
-        const double scale = fmax(fmax(fabs((double)best), fabs((double)second)), fabs((double)kqq));
-        need = gap <= 2.0 * (double)E && gap + 2.0 * (double)E >= kTieMargin * scale;
+        const double scale = fmax(fmax(fabs(best), fabs(second)), fabs((double)kqq));
+        if (a.gap)
+            a.gap[q] = second < kInf ? (float)((second - best) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
+        const double gap = second - best;
+        need = gap <= 2.0 * (double)EG && gap + 2.0 * (double)EG >= kTieMargin * scale;
     }
     if (wave == 0) append_rows(need, q, a.refine_count, a.refine_list);
     if (a.Dt) {
@@ -247,23 +310,30 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                 double vv = (active && h == 0) ? (double)D + (double)E : kInf;
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) vv = fmin(vv, __shfl_xor(vv, o, kWave));
-                if (lane == 0) a.colpart[(int64_t)jj * a.colpart_cap + blockIdx.x] = vv;
+                if (lane == 0) a.colpart[(int64_t)jj * a.colpart_cap + grp] = vv;
             }
         }
     }
+    __syncthreads();   // the group's LDS (Dl, Pt, per-wave results) is reused by the next group
+    }   // groups
 }
 
 template <typename TI, bool BF3>
 kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
-    const size_t lds = sizeof(float) * (size_t)a.sup.C * 32;
-    if (lds > dev.max_lds_per_block) return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
-    const unsigned blocks = (unsigned)((a.q.n + 31) / 32);
+    const size_t C = (size_t)a.sup.C;
+    const size_t lds = sizeof(float) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
+    const size_t lds_static = sizeof(float) * (4 * 32 * 33 + 4 * 32 * 3) + sizeof(double) * 4 * 32 * 2 + 64;
+    if (lds + lds_static > dev.max_lds_per_block)
+        return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
+    // 32 samples per group; at most 8 workgroups per CU, each looping over groups
+    const int64_t groups = (a.q.n + 31) / 32;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
     auto go = [&](auto fn) -> kkm_status {
         KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
-        if (a.colmin && (int64_t)blocks > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
+        if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
         hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
         KKM_HIP(hipGetLastError());
-        if (a.colmin && a.colpart_blocks) *a.colpart_blocks = blocks;
+        if (a.colmin && a.colpart_blocks) *a.colpart_blocks = groups;
         return KKM_OK;
     };
     switch (a.sup.dpad) {

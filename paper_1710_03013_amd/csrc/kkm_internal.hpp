@@ -162,6 +162,13 @@ __device__ __forceinline__ double ord_dec(unsigned long long e) {
     return __longlong_as_double((long long)b);
 }
 
+// LDS writes of a wavefront become visible to its other lanes.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Appends q to list for the lanes with flag set, with one atomic per wavefront (call from all lanes
 // of the wavefront).  List order across wavefronts is unspecified.
 __device__ __forceinline__ void append_rows(bool flag, int64_t q, int32_t* count, int32_t* list) {
