@@ -165,46 +165,71 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
 #pragma unroll
             for (int s = 0; s < H; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], xq[s], acc, 0, 0, 0);
         }
-        // epilogue: a_l K(x, s_l) for the lane's rows l = r0 + 8(i/4) + 4h + i%4, into the LDS tile
+        // segments meeting the tile (the first 64 of them): a prefix of the lanes, offsets ascend
+        int sj = jc + lane;
+        int o0 = sj < j1 ? off[sj] : end;
+        int o1 = sj < j1 ? off[sj + 1] : end;
+        int nseg = __popcll(__ballot(sj < j1 && o0 < tile_end));
+        // epilogue: a_l K(x, s_l) for the lane's rows l = r0 + 8(i/4) + 4h + i%4
+        float v[16];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int rb = r0 + 8 * b + 4 * h;
             const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
             const float4 cf4 = *reinterpret_cast<const float4*>(a.sup.coef32 + rb);
-            const int lr = 8 * b + 4 * h;
-            P[(lr + 0) * 33 + col] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
-            P[(lr + 1) * 33 + col] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
-            P[(lr + 2) * 33 + col] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
-            P[(lr + 3) * 33 + col] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
+            v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
+            v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
+            v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
+            v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
         }
-        wave_sync_lds();
-        // segments meeting the tile, 64 at a time: lane half h takes every other segment, lane col
-        // its sample; each adds its rows of the tile in row order to the segment's accumulator
-        for (;;) {
-            const int sj = jc + lane;
-            const int o0 = sj < j1 ? off[sj] : end;
-            const int o1 = sj < j1 ? off[sj + 1] : end;
-            const uint64_t started = __ballot(sj < j1 && o0 < tile_end);   // a prefix: offsets ascend
-            const int nseg = __popcll(started);
-            for (int k0 = 0; k0 < nseg; k0 += 2) {
-                const int k = k0 + h;
-                const int lo_k = __shfl(o0, k, 64), hi_k = __shfl(o1, k, 64);
-                if (k < nseg) {
-                    const int lo = max(lo_k, r0), hi = min(hi_k, tile_end);
-                    float part = 0.0f;
-                    for (int r = lo; r < hi; ++r) part += P[(r - r0) * 33 + col];
-                    if (hi > lo) Dl[(jc + k) * 32 + col] += part;
+        // (the register path is compiled for short rows only, where it costs no occupancy)
+        if (DP <= 32 && nseg <= 2) {
+            // one or two (long) segments: masked sums of the lane's 16 values and its partner's
+#pragma unroll 1
+            for (int k = 0; k < nseg; ++k) {
+                const int lo = max(__shfl(o0, k, 64), r0), hi = min(__shfl(o1, k, 64), tile_end);
+                float part = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int row = r0 + 8 * (i / 4) + 4 * h + (i % 4);
+                    part += (row >= lo && row < hi) ? v[i] : 0.0f;
                 }
+                part += __shfl_xor(part, 32, 64);
+                if (h == 0 && hi > lo) Dl[(jc + k) * 32 + col] += part;
             }
-            if (nseg == 0) break;
-            // the last counted segment may continue in the next tile
-            const int last_end = __shfl(o1, nseg - 1, 64);
-            if (last_end > tile_end) {
-                jc += nseg - 1;
-                break;
+            if (nseg > 0) jc += __shfl(o1, nseg - 1, 64) > tile_end ? nseg - 1 : nseg;
+        } else {
+            // short segments: the tile through LDS; lane half h takes every other segment, lane col
+            // its sample, each adding its rows in row order
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) P[(8 * b + 4 * h + c) * 33 + col] = v[4 * b + c];
+            wave_sync_lds();
+            for (;;) {
+                for (int k0 = 0; k0 < nseg; k0 += 2) {
+                    const int k = k0 + h;
+                    const int lo_k = __shfl(o0, k, 64), hi_k = __shfl(o1, k, 64);
+                    if (k < nseg) {
+                        const int lo = max(lo_k, r0), hi = min(hi_k, tile_end);
+                        float part = 0.0f;
+                        for (int r = lo; r < hi; ++r) part += P[(r - r0) * 33 + col];
+                        if (hi > lo) Dl[(jc + k) * 32 + col] += part;
+                    }
+                }
+                // the last counted segment may continue in the next tile
+                if (__shfl(o1, nseg - 1, 64) > tile_end) {
+                    jc += nseg - 1;
+                    break;
+                }
+                jc += nseg;
+                if (nseg < 64) break;
+                sj = jc + lane;
+                o0 = sj < j1 ? off[sj] : end;
+                o1 = sj < j1 ? off[sj + 1] : end;
+                nseg = __popcll(__ballot(sj < j1 && o0 < tile_end));
+                if (nseg == 0) break;
             }
-            jc += nseg;
-            if (nseg < 64) break;
         }
         wave_sync_lds();
     }
