@@ -12,8 +12,10 @@
 namespace kkm {
 namespace {
 
-// Pairs of HIP events recorded on the caller's stream around phases of a fit (optional).  The
-// events live for one call only.
+// HIP events recorded on the caller's stream at the boundaries of the phases of a fit (optional):
+// back-to-back phases share their boundary event.  The events only time the stream, so they are
+// recorded with a device-scope release (no system-scope cache flush, which stalls the queue for
+// several microseconds per event).  The events live for one call only.
 // Timed spans of a fit: k-means++ / medoids; landmark block and initial labels; landmark loop kernel;
 // batch-wide distance kernel; FP64 re-decision; selection (column minima, medoids, merge).
 enum { kPhInit = 0, kPhLandmark = 1, kPhLoop = 2, kPhDist = 3, kPhRefine = 4, kPhSelect = 5, kPhases = 6 };
@@ -25,6 +27,7 @@ struct PhaseTimer {
     size_t used = 0;
     std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;   // (phase, (begin, end) pool slots)
     size_t open = 0;
+    bool open_valid = false;   // the last recorded event ends a phase and may begin the next one
     static std::vector<hipEvent_t>& pool(int device) {
         static thread_local std::map<int, std::vector<hipEvent_t>> pools;
         return pools[device];
@@ -33,21 +36,29 @@ struct PhaseTimer {
         auto& p = pool(device);
         if (used == p.size()) {
             hipEvent_t e;
-            KKM_HIP(hipEventCreate(&e));
+            KKM_HIP(hipEventCreateWithFlags(&e, hipEventReleaseToDevice));
             p.push_back(e);
         }
         *slot = used++;
         KKM_HIP(hipEventRecord(p[*slot], s));
         return KKM_OK;
     }
-    kkm_status begin() { return on ? record(&open) : KKM_OK; }
+    // begin() right after end() (no launch in between) reuses that end event
+    kkm_status begin() {
+        if (!on || open_valid) return KKM_OK;
+        return record(&open);
+    }
     kkm_status end(int phase) {
         if (!on) return KKM_OK;
         size_t e;
         KKM_TRY(record(&e));
         spans.push_back({phase, {open, e}});
+        open = e;
+        open_valid = true;
         return KKM_OK;
     }
+    // a launch outside every phase follows: the next phase records its own begin event
+    void gap() { open_valid = false; }
     ~PhaseTimer() {
         auto& p = pool(device);
         for (hipEvent_t e : p) (void)hipEventDestroy(e);
@@ -222,8 +233,11 @@ kkm_status check_kernel_args(const kkm_kernel* k, int64_t d) {
 double inv2s2_of(const kkm_kernel& k) { return k.type == KKM_KERNEL_LINEAR ? 0.0 : 1.0 / (2.0 * k.sigma * k.sigma); }
 
 // Validate everything and build the plan (host draws included); no device work.
+kkm_status finish_plan(FitPlan& P, const DeviceInfo* dev);
+
+// draws = false: sizes only (no landmark positions or initialisation draws), for the workspace query
 kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel, const kkm_params* params,
-                     const DeviceInfo* dev, FitPlan& P) {
+                     const DeviceInfo* dev, FitPlan& P, bool draws = true) {
     if (N < 1) return fail(KKM_ERR_INVALID_ARG, "N must be >= 1");
     if (d < 1) return fail(KKM_ERR_INVALID_ARG, "d must be >= 1");
     if (dtype != KKM_F32 && dtype != KKM_F64) return fail(KKM_ERR_INVALID_ARG, "bad dtype");
@@ -275,6 +289,7 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
     }
     P.ell_total = P.lm_off[P.B];
     if (P.ellmax > 65535) return fail(KKM_ERR_UNSUPPORTED, "at most 65535 landmarks per batch; use more mini-batches");
+    if (!draws) return finish_plan(P, dev);
     P.lm_host.resize(P.ell_total);
     std::vector<int64_t> tmp(P.ellmax);
     for (int i = 0; i < P.B; ++i) {
@@ -317,7 +332,12 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
             P.med0[j] = (int32_t)p.init_medoids[j];
         }
     }
-    P.tile_f64 = p.precision == KKM_PREC_FP64 || kernel->type == KKM_KERNEL_RMSD;
+    return finish_plan(P, dev);
+}
+
+// Sizes that follow from the batches and the device: tiles, chunks, landmark grids.
+kkm_status finish_plan(FitPlan& P, const DeviceInfo* dev) {
+    P.tile_f64 = P.p.precision == KKM_PREC_FP64 || P.kernel.type == KKM_KERNEL_RMSD;
     P.nchunk = select_chunks(P.nmax);
     P.cand_cap = std::min<int64_t>((int64_t)P.nmax * P.C, (int64_t)1 << 30);
     if (dev) {
@@ -459,7 +479,7 @@ size_t kkm_fit_workspace_bytes(int64_t N, int64_t d, int32_t dtype, const kkm_ke
     FitPlan P;
     DeviceInfo dev;
     const bool have_dev = device_info(&dev) == KKM_OK;
-    if (make_plan(N, d, dtype, kernel, params, have_dev ? &dev : nullptr, P) != KKM_OK) return 0;
+    if (make_plan(N, d, dtype, kernel, params, have_dev ? &dev : nullptr, P, false) != KKM_OK) return 0;
     FitWs w;
     Carver c(nullptr);
     return carve_fit(c, P, w);
@@ -586,7 +606,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.barrier = w.barrier;
         la.colmin = w.colmin;
         la.error = w.lm_error;
-        if (la.trace) KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
+        if (la.trace) {
+            KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
+            tm.gap();
+        }
         KKM_TRY(tm.begin());
         KKM_TRY(launch_landmark_block(la, dtype, dev, s));
         KKM_TRY(tm.end(kPhLandmark));

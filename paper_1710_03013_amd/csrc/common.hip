@@ -121,16 +121,23 @@ kkm_status kkm_draw_landmarks(uint64_t seed, int32_t batch, int64_t n, double s,
         for (int64_t i = 0; i < n; ++i) out[i] = i;
         return KKM_OK;
     }
+    // partial Fisher-Yates shuffle of 0..n-1 (first ell positions), then the picks in ascending
+    // order via a bitmap over 0..n-1; the buffers are kept per thread between calls
     rng::Stream g = rng::stream(seed, rng::kLandmarks, (uint64_t)batch);
-    std::vector<int64_t> idx(n);
+    static thread_local std::vector<int64_t> idx;
+    static thread_local std::vector<uint64_t> bits;
+    if ((int64_t)idx.size() < n) idx.resize(n);
     for (int64_t i = 0; i < n; ++i) idx[i] = i;
     for (int64_t k = 0; k < ell; ++k) {
         const int64_t r = k + (int64_t)g.bounded((uint64_t)(n - k));
         std::swap(idx[k], idx[r]);
     }
-    std::vector<int64_t> pick(idx.begin(), idx.begin() + ell);
-    std::sort(pick.begin(), pick.end());
-    for (int64_t i = 0; i < ell; ++i) out[i] = pick[i];
+    const int64_t nw = (n + 63) / 64;
+    bits.assign(nw, 0ull);
+    for (int64_t k = 0; k < ell; ++k) bits[idx[k] >> 6] |= 1ull << (idx[k] & 63);
+    int64_t o = 0;
+    for (int64_t wi = 0; wi < nw; ++wi)
+        for (uint64_t b = bits[wi]; b; b &= b - 1) out[o++] = wi * 64 + __builtin_ctzll(b);
     return KKM_OK;
 }
 

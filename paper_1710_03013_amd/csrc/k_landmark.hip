@@ -40,10 +40,10 @@ struct LdsLayout {
     uint16_t* chunk;   // [nchunks][C] count, then base, per chunk and label
     double* S;         // [R][C]
     double* gh;        // [C]
-    double* kself;     // [R]
+    double* kself;     // [R] K(l, l) of the own landmarks
     int32_t* qoff;     // [C+1] first 64-element chunk of each segment (chunks per row: qoff[C])
     double* part;      // [R][nq_max] chunk partial sums, nq_max = ceil(ell/64) + C
-    double* kall;      // [ell] K(l, l) of every landmark
+    int32_t* lmv;      // [ell] position of every landmark in the batch
     int32_t* nlab;     // [ell] labels after an update
     int32_t* chg;      // [ell + 1] changed landmarks in index order; chg[ell] = their number
     int32_t* cnt;      // [C] landmarks per cluster
@@ -70,7 +70,7 @@ __host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R, bool
     b = (b + 15) & ~size_t(15); b += sizeof(double) * R;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (C + 1);
     b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)R * ((ell + 63) / 64 + C);
-    b = (b + 15) & ~size_t(15); b += sizeof(double) * ell;
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (ell + 1);
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * C;
@@ -95,7 +95,7 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool 
     b = al16(b); L.kself = reinterpret_cast<double*>(base + b); b += sizeof(double) * R;
     b = al16(b); L.qoff = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (C + 1);
     b = al16(b); L.part = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)R * ((ell + 63) / 64 + C);
-    b = al16(b); L.kall = reinterpret_cast<double*>(base + b); b += sizeof(double) * ell;
+    b = al16(b); L.lmv = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.nlab = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.chg = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (ell + 1);
     b = al16(b); L.cnt = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * C;
@@ -108,28 +108,43 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int nchunks = (ell + 63) / 64;
-    for (int i = tid; i < nchunks * C; i += nt) L.chunk[i] = 0;
-    __syncthreads();
+    if (C > 64) {
+        for (int i = tid; i < nchunks * C; i += nt) L.chunk[i] = 0;
+        __syncthreads();
+    }
     // ranks inside each 64-landmark chunk
     if (C <= 64) {
         // few clusters: every label in turn over the wave's chunks (independent ballots, no
-        // dependence between chunks)
+        // dependence between chunks); ranks and counts are selected in registers (lane j keeps the
+        // count of label j) and stored once, so the label loop has no branches
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         for (int ch0 = wave; ch0 < nchunks; ch0 += 4 * nwaves) {
-            int labs[4];
+            int labs[4], rk[4], ct[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int ch = ch0 + u * nwaves;
                 const int m = ch * 64 + lane;
                 labs[u] = (ch < nchunks && m < ell) ? L.lbl[m] : -1;
+                rk[u] = 0;
+                ct[u] = 0;
             }
             for (int j = 0; j < C; ++j) {
+                const bool mine = lane == j;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int ch = ch0 + u * nwaves;
                     const uint64_t mask = __ballot(labs[u] == j);
-                    if (labs[u] == j) L.rank[ch * 64 + lane] = (uint8_t)__popcll(mask & below);
-                    if (lane == 0 && ch < nchunks) L.chunk[ch * C + j] = (uint16_t)__popcll(mask);
+                    const int rb = (int)__popcll(mask & below);
+                    rk[u] = labs[u] == j ? rb : rk[u];
+                    ct[u] = mine ? (int)__popcll(mask) : ct[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ch = ch0 + u * nwaves;
+                const int m = ch * 64 + lane;
+                if (ch < nchunks) {   // uniform over the wavefront
+                    if (m < ell) L.rank[m] = (uint8_t)rk[u];
+                    if (lane < C) L.chunk[ch * C + lane] = (uint16_t)ct[u];
                 }
             }
         }
@@ -152,51 +167,62 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
         }
     }
     __syncthreads();
-    // per label: exclusive prefix over chunks (in place) and the total count
-    for (int j = tid; j < C; j += nt) {
-        int run = 0;
-        for (int ch = 0; ch < nchunks; ++ch) {
-            const int t = L.chunk[ch * C + j];
-            L.chunk[ch * C + j] = (uint16_t)run;
-            run += t;
+    // per label: exclusive prefix over chunks (in place) and the total count; one label per
+    // wavefront with the chunks on the lanes when they fit, else serially per label
+    if (nchunks <= 64) {
+        for (int j = wave; j < C; j += nwaves) {
+            const int t = lane < nchunks ? L.chunk[lane * C + j] : 0;
+            int v = t;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(v, o, 64);
+                if (lane >= o) v += u;
+            }
+            if (lane < nchunks) L.chunk[lane * C + j] = (uint16_t)(v - t);
+            if (lane == 63) L.off[j + 1] = v;
         }
-        L.off[j + 1] = run;
+    } else {
+        for (int j = tid; j < C; j += nt) {
+            int run = 0;
+            for (int ch = 0; ch < nchunks; ++ch) {
+                const int t = L.chunk[ch * C + j];
+                L.chunk[ch * C + j] = (uint16_t)run;
+                run += t;
+            }
+            L.off[j + 1] = run;
+        }
     }
     __syncthreads();
-    // exclusive scan of the counts into the segment offsets (first wave)
+    // segment offsets = exclusive scan of the counts, and qoff = exclusive scan of the number of
+    // 64-element chunks ceil(len_j / 64) of every segment (first wave)
     if (wave == 0) {
-        int carry = 0;
+        int carry = 0, qcarry = 0;
         for (int base = 0; base < C; base += 64) {
             const int j = base + lane;
-            int v = (j < C) ? L.off[j + 1] : 0;
+            const int cnt = (j < C) ? L.off[j + 1] : 0;
+            int v = cnt, q = (cnt + 63) / 64;
+#pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const int t = __shfl_up(v, o, 64);
-                if (lane >= o) v += t;
+                const int tq = __shfl_up(q, o, 64);
+                if (lane >= o) { v += t; q += tq; }
             }
-            if (j < C) L.off[j + 1] = carry + v;
+            if (j < C) {
+                L.off[j + 1] = carry + v;
+                L.qoff[j + 1] = qcarry + q;
+            }
             carry += __shfl(v, 63, 64);
+            qcarry += __shfl(q, 63, 64);
         }
-        if (lane == 0) L.off[0] = 0;
+        if (lane == 0) {
+            L.off[0] = 0;
+            L.qoff[0] = 0;
+        }
     }
     __syncthreads();
     for (int m = tid; m < ell; m += nt) {
         const int lab = L.lbl[m];
         L.perm[L.off[lab] + L.chunk[(m >> 6) * C + lab] + L.rank[m]] = m;
-    }
-    // 64-element chunks of every segment: qoff = exclusive scan of ceil(len_j / 64) (first wave)
-    if (wave == 0) {
-        int carry = 0;
-        for (int base = 0; base < C; base += 64) {
-            const int j = base + lane;
-            int v = (j < C) ? (L.off[j + 1] - L.off[j] + 63) / 64 : 0;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int t = __shfl_up(v, o, 64);
-                if (lane >= o) v += t;
-            }
-            if (j < C) L.qoff[j + 1] = carry + v;
-            carry += __shfl(v, 63, 64);
-        }
-        if (lane == 0) L.qoff[0] = 0;
     }
     __syncthreads();
 }
@@ -272,14 +298,12 @@ __device__ __forceinline__ void reset_batch_state(const LandmarkArgs& a) {
     }
 }
 
-// Wall-clock stamp of workgroup 0 (profiling aid): slot 0 holds the count.
-__device__ __forceinline__ void stamp(const LandmarkArgs& a) {
-    if (a.trace && blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t n = a.trace[0];
-        if (n < 63) {
-            a.trace[1 + n] = (int64_t)wall_clock64();
-            a.trace[0] = n + 1;
-        }
+// Wall-clock stamp of workgroup 0 (profiling aid): slot 0 holds the count, which thread 0 also
+// keeps in ns (no load on the timed path).
+__device__ __forceinline__ void stamp(const LandmarkArgs& a, int& ns) {
+    if (a.trace && blockIdx.x == 0 && threadIdx.x == 0 && ns < 63) {
+        a.trace[1 + ns] = (int64_t)wall_clock64();
+        a.trace[0] = ++ns;
     }
 }
 
@@ -394,17 +418,36 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    // staging: element p = threadIdx.x + 256 u of a stage is (row rr = p / CH, dimension k = p % CH);
+    // the row starts are resolved once, and each stage issues all its loads before the LDS stores
+    constexpr int PER = T * CH / 256;
+    static_assert(PER * 256 == T * CH, "staging covers the tile exactly");
+    const TI* pa[PER];
+    const TI* pb[PER];
+    int kk[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = threadIdx.x + 256 * u;
+        const int rr = p / CH;
+        kk[u] = p - rr * CH;
+        const int r = r0 + rr, c = c0 + rr;
+        pa[u] = r < ell ? X + (int64_t)a.lm[r] * rs : nullptr;
+        pb[u] = c < ell ? X + (int64_t)a.lm[c] * rs : (c < ncol ? M + (int64_t)(c - ell) * a.Mpad : nullptr);
+    }
     for (int k0 = 0; k0 < DP; k0 += CH) {
+        double va[PER], vb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int dim = k0 + kk[u];
+            va[u] = (pa[u] && dim < d) ? (double)pa[u][dim] : 0.0;
+            vb[u] = (pb[u] && dim < d) ? (double)pb[u][dim] : 0.0;
+        }
         __syncthreads();
-        for (int p = threadIdx.x; p < T * CH; p += blockDim.x) {
-            const int rr = p / CH, k = p - rr * CH;
-            const int dim = k0 + k;
-            const int r = r0 + rr, c = c0 + rr;
-            As[k][rr] = (r < ell && dim < d) ? (double)X[(int64_t)a.lm[r] * rs + dim] : 0.0;
-            double bv = 0.0;
-            if (c < ncol && dim < d)
-                bv = c < ell ? (double)X[(int64_t)a.lm[c] * rs + dim] : (double)M[(int64_t)(c - ell) * a.Mpad + dim];
-            Bs[k][rr] = bv;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int p = threadIdx.x + 256 * u;
+            As[kk[u]][p / CH] = va[u];
+            Bs[kk[u]][p / CH] = vb[u];
         }
         __syncthreads();
 #pragma unroll 4
@@ -477,7 +520,9 @@ __global__ __launch_bounds__(256) void landmark_init_from_k_kernel(LandmarkArgs 
 //   Eq. 15 for the own rows, publish their labels    -> barrier -> all labels, changed list,
 //   own rows of S follow the changes (incrementally in landmark order, or from scratch).
 // A buffer is rewritten only after the barrier that ends every reader's use of it.
-template <typename TI>
+// KL: the own rows of K_LL are staged in LDS (else read from HBM); a compile-time choice, so the
+// reads compile to LDS or global instructions rather than generic ones.
+template <typename TI, bool KL>
 __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -487,41 +532,60 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
     const int ldk = (int)a.ldk;
     const int R = (ell + G - 1) / G;
     const int r0 = min(ell, wg * R), r1 = min(ell, r0 + R), nr = r1 - r0;
-    const bool kl = a.k_in_lds != 0;
-    LdsLayout L = carve_lds(smem, ell, C, R, kl);
+    LdsLayout L = carve_lds(smem, ell, C, R, KL);
     const TI* X = static_cast<const TI*>(a.X);
     auto row = [&](int pos) { return X + (a.base + (int64_t)pos * a.stride) * a.d; };
-    const double* Krows = a.Kbuf + (int64_t)r0 * ldk;     // own row r at Krows + r * ldk
+    const double* const Kg = a.Kbuf + (int64_t)r0 * ldk;
+    const double* const Krows = KL ? L.K : Kg;     // own row r at Krows + r * ldk
     unsigned target = 0;
+    int ns = 0;   // trace stamps taken (thread 0 of workgroup 0)
 
-    stamp(a);
-    if (kl) {
-        // the own rows are one contiguous, 16-byte aligned block: copy it as double2
-        typedef double dvec2 __attribute__((ext_vector_type(2)));
-        const int64_t n2 = (int64_t)nr * ldk / 2;
-        const dvec2* src = reinterpret_cast<const dvec2*>(Krows);
-        dvec2* dst = reinterpret_cast<dvec2*>(L.K);
-        int64_t i = tid;
-        for (; i + 7 * nt < n2; i += 8 * nt) {
-            dvec2 v[8];
+    stamp(a, ns);
+    // The own rows of K are one contiguous, 16-byte aligned block, copied to LDS as double2: the
+    // first 16 per thread are loaded before the CSR sort of the labels and stored after it.
+    typedef double dvec2 __attribute__((ext_vector_type(2)));
+    constexpr int KU = 16;
+    const int64_t n2 = KL ? (int64_t)nr * ldk / 2 : 0;
+    const dvec2* ksrc = reinterpret_cast<const dvec2*>(Kg);
+    dvec2* kdst = reinterpret_cast<dvec2*>(L.K);
+    dvec2 kv[KU];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[i + u * nt];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) dst[i + u * nt] = v[u];
-        }
-        for (; i < n2; i += nt) dst[i] = src[i];
-        Krows = L.K;
+    for (int u = 0; u < KU; ++u) {
+        const int64_t i = tid + (int64_t)u * nt;
+        if (i < n2) kv[u] = ksrc[i];
     }
     for (int m = tid; m < ell; m += nt) {
-        L.kall[m] = a.Kbuf[(int64_t)m * ldk + m];
         L.lbl[m] = a.lab[m];
+        L.lmv[m] = a.lm[m];
     }
+    for (int r = tid; r < nr; r += nt) L.kself[r] = a.Kbuf[(int64_t)(r0 + r) * ldk + r0 + r];
     __syncthreads();
-    stamp(a);
+    stamp(a, ns);
 
     csr_sort(L, ell, C);
+    if constexpr (KL) {
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int64_t i = tid + (int64_t)u * nt;
+            if (i < n2) kdst[i] = kv[u];
+        }
+        for (int64_t i0 = (int64_t)KU * nt; i0 < n2; i0 += (int64_t)KU * nt) {
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int64_t i = i0 + tid + (int64_t)u * nt;
+                if (i < n2) kv[u] = ksrc[i];
+            }
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int64_t i = i0 + tid + (int64_t)u * nt;
+                if (i < n2) kdst[i] = kv[u];
+            }
+        }
+        __syncthreads();
+    }
+    stamp(a, ns);
     full_sums(L, Krows, ldk, nr, C);
-    stamp(a);
+    stamp(a, ns);
 
     const int nsub = C < nt ? nt / C : 1;     // threads per cluster in the partial reduction
     int it = 0;
@@ -529,13 +593,25 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         // own part of sum_{m in L_j} S[m][j], in row order
         for (int j = tid; j < C; j += nt) {
             double acc = 0.0;
-            for (int r = 0; r < nr; ++r)
-                if (L.lbl[r0 + r] == j) acc += L.S[r * C + j];
+            int r = 0;
+            for (; r + 8 <= nr; r += 8) {
+                int lb[8];
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    lb[u] = L.lbl[r0 + r + u];
+                    v[u] = L.S[(r + u) * C + j];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += lb[u] == j ? v[u] : 0.0;
+            }
+            for (; r < nr; ++r) acc += L.lbl[r0 + r] == j ? L.S[r * C + j] : 0.0;
             a.partial[(int64_t)wg * C + j] = acc;
             L.rcnt[j] = L.cnt[j] > 0 ? 1.0 / (double)L.cnt[j] : 0.0;
         }
+        stamp(a, ns);
         grid_barrier(a, target);
-        stamp(a);
+        stamp(a, ns);
         // g^_j = 1/c_j^2 sum_g partial[g][j]: nsub interleaved sub-sums per cluster, then in order
         for (int p = tid; p < nsub * C; p += nt) {
             const int j = p % C, sub = p / C;
@@ -552,28 +628,45 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             L.gh[j] = cj > 0.0 ? acc / (cj * cj) : kInf;
         }
         __syncthreads();
+        stamp(a, ns);
         if (it >= a.max_updates) break;
 
-        // Eq. 15 for the own rows (one wavefront per row; lowest j among equal minima)
-        for (int r = wave; r < nr; r += nwaves) {
-            const int m = r0 + r;
-            double bv = kInf;
-            int bj = C;
-            for (int j = lane; j < C; j += 64) {
-                if (L.cnt[j] == 0) continue;
-                const double dj = L.kall[m] - 2.0 * L.S[r * C + j] * L.rcnt[j] + L.gh[j];
-                if (bj == C || dj < bv) { bv = dj; bj = j; }
+        // Eq. 15 for the own rows (one wavefront per row, four rows per wavefront at a time so
+        // their reductions overlap; lowest j among equal minima)
+        for (int rb = wave; rb < nr; rb += 4 * nwaves) {
+            double bv[4];
+            int bj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = rb + u * nwaves;
+                bv[u] = kInf;
+                bj[u] = C;
+                if (r < nr) {
+                    for (int j = lane; j < C; j += 64) {
+                        if (L.cnt[j] == 0) continue;
+                        const double dj = L.kself[r] - 2.0 * L.S[r * C + j] * L.rcnt[j] + L.gh[j];
+                        if (bj[u] == C || dj < bv[u]) { bv[u] = dj; bj[u] = j; }
+                    }
+                }
             }
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) {
-                const double v2 = __shfl_xor(bv, o, 64);
-                const int j2 = __shfl_xor(bj, o, 64);
-                if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double v2 = __shfl_xor(bv[u], o, 64);
+                    const int j2 = __shfl_xor(bj[u], o, 64);
+                    if (j2 < C && (bj[u] == C || v2 < bv[u] || (v2 == bv[u] && j2 < bj[u]))) { bv[u] = v2; bj[u] = j2; }
+                }
             }
-            if (lane == 0) a.nlab_x[m] = bj < C ? bj : L.lbl[m];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = rb + u * nwaves;
+                if (r < nr && lane == 0) a.nlab_x[r0 + r] = bj[u] < C ? bj[u] : L.lbl[r0 + r];
+            }
         }
+        stamp(a, ns);
         grid_barrier(a, target);
-        stamp(a);
+        stamp(a, ns);
         for (int m = tid; m < ell; m += nt) L.nlab[m] = a.nlab_x[m];
         __syncthreads();
         // changed landmarks in index order (first wave)
@@ -591,23 +684,49 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         }
         __syncthreads();
         const int nch = L.chg[ell];
+        stamp(a, ns);
         ++it;
         if (nch == 0) break;
-        if ((int64_t)nch * C > ell) {
+        // from scratch (sort + segment sums, ~ell steps per row) only when the incremental update
+        // (every own entry of S walks the changed list) would take longer
+        if ((int64_t)nch * ((nr * C + nt - 1) / nt) > (int64_t)ell) {
             for (int m = tid; m < ell; m += nt) L.lbl[m] = L.nlab[m];
             __syncthreads();
             csr_sort(L, ell, C);
             full_sums(L, Krows, ldk, nr, C);
         } else {
-            // S[r][j] -= K(r, m) for changes leaving j, += for changes entering j, in index order
+            // S[r][j] -= K(r, m) for changes leaving j, += for changes entering j, in index order.
+            // The old and new labels of change t are packed (old | new << 16) into the CSR
+            // permutation, which is stale until the next sort anyway.
+            for (int t = tid; t < nch; t += nt) {
+                const int m = L.chg[t];
+                L.perm[t] = L.lbl[m] | (L.nlab[m] << 16);
+            }
+            __syncthreads();
             for (int p = tid; p < nr * C; p += nt) {
                 const int r = p / C, j = p - r * C;
                 const double* Kr = Krows + (int64_t)r * ldk;
                 double sv = L.S[p];
-                for (int t = 0; t < nch; ++t) {
-                    const int m = L.chg[t];
-                    if (L.lbl[m] == j) sv -= Kr[m];
-                    if (L.nlab[m] == j) sv += Kr[m];
+                int t = 0;
+                for (; t + 4 <= nch; t += 4) {
+                    int ab[4];
+                    double kv4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ab[u] = L.perm[t + u];
+                        kv4[u] = Kr[L.chg[t + u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        sv = (ab[u] & 0xffff) == j ? sv - kv4[u] : sv;
+                        sv = (ab[u] >> 16) == j ? sv + kv4[u] : sv;
+                    }
+                }
+                for (; t < nch; ++t) {
+                    const int ab = L.perm[t];
+                    const double kx = Kr[L.chg[t]];
+                    sv = (ab & 0xffff) == j ? sv - kx : sv;
+                    sv = (ab >> 16) == j ? sv + kx : sv;
                 }
                 L.S[p] = sv;
             }
@@ -620,14 +739,15 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             for (int t = tid; t < nch; t += nt) L.lbl[L.chg[t]] = L.nlab[L.chg[t]];
             __syncthreads();
         }
-        stamp(a);
+        stamp(a, ns);
     }
     // CSR of the final labels for the support
     csr_sort(L, ell, C);
-    stamp(a);
+    stamp(a, ns);
 
     // 4. outputs: final labels, segments, g^, and the support of the final centroids
     for (int r = tid; r < nr; r += nt) a.lab_final[r0 + r] = L.lbl[r0 + r];
+    stamp(a, ns);
     if (wg == 0) {
         for (int j = tid; j <= C; j += nt) a.offsets[j] = L.off[j];
         for (int j = tid; j < C; j += nt) {
@@ -649,46 +769,69 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         for (int m = tid; m < ell; m += nt) a.lab[ell + m] = L.lbl[m];   // final landmark labels
     }
     // support rows in CSR order (and rows [ell, ell + 32) zeroed for whole-tile loads): one wavefront
-    // per row over all workgroups, lanes over the dimensions; row copy, FP32 / bfloat16 panels, norms
+    // per row over all workgroups, lanes over the dimensions, four rows per wavefront at a time (their
+    // loads issued together); row copy, FP32 / bfloat16 panels, norms
     TI* sup = static_cast<TI*>(a.support);
     const int PD = (int)a.dpad;
     const bool panels = a.ktype != KKM_KERNEL_RMSD;   // power-of-two padded rows only
+    const int GW = G * nwaves, kend = ell + 32;
     float nmax = 0.0f;
-    for (int k = wg * nwaves + wave; k < ell + 32; k += G * nwaves) {
-        const bool real = k < ell;
-        int m = 0, cnt = 1;
-        if (real) {
-            m = L.perm[k];
-            const int j = L.lbl[m];
-            cnt = L.off[j + 1] - L.off[j];
+    for (int k0 = wg * nwaves + wave; k0 < kend; k0 += 4 * GW) {
+        const TI* srcq[4];
+        int cntq[4], posq[4];
+        bool realq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * GW;
+            realq[u] = k < ell;
+            cntq[u] = 1;
+            posq[u] = 0;
+            if (realq[u]) {
+                const int m = L.perm[k];
+                const int j = L.lbl[m];
+                cntq[u] = L.off[j + 1] - L.off[j];
+                posq[u] = L.lmv[m];
+            }
+            srcq[u] = row(posq[u]);
         }
-        const TI* src = row(real ? a.lm[m] : 0);
-        double n64 = 0.0;
-        float n32 = 0.0f;
+        double n64[4] = {0.0, 0.0, 0.0, 0.0};
+        float n32[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int c = lane; c < PD; c += 64) {
-            const TI v = (real && c < a.d) ? src[c] : TI(0);
-            sup[(int64_t)k * PD + c] = v;
-            n64 = fma((double)v, (double)v, n64);
-            const float f = (float)v;
-            n32 = fmaf(f, f, n32);
-            if (panels && a.sup_pan) a.sup_pan[panel32_index(k, c, PD)] = f;
-            if (panels && PD >= 16) {
-                uint16_t hi = 0, lo = 0;
-                if (real && c < a.d) bf16_split(f, hi, lo);
-                a.sup_hi[panel16_index(k, c, PD)] = hi;
-                a.sup_lo[panel16_index(k, c, PD)] = lo;
+            TI v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = (realq[u] && c < a.d) ? srcq[u][c] : TI(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + u * GW;
+                if (k >= kend) continue;   // uniform over the wavefront
+                sup[(int64_t)k * PD + c] = v[u];
+                n64[u] = fma((double)v[u], (double)v[u], n64[u]);
+                const float f = (float)v[u];
+                n32[u] = fmaf(f, f, n32[u]);
+                if (panels && a.sup_pan) a.sup_pan[panel32_index(k, c, PD)] = f;
+                if (panels && PD >= 16) {
+                    uint16_t hi = 0, lo = 0;
+                    if (realq[u] && c < a.d) bf16_split(f, hi, lo);
+                    a.sup_hi[panel16_index(k, c, PD)] = hi;
+                    a.sup_lo[panel16_index(k, c, PD)] = lo;
+                }
             }
         }
-        n64 = wave_sum(n64);
-        n32 = wave_sum(n32);
-        if (lane == 0) {
-            a.snorm64[k] = n64;
-            a.snorm32[k] = n32;
-            a.coef64[k] = real ? 1.0 / (double)cnt : 0.0;
-            a.coef32[k] = real ? (float)(1.0 / (double)cnt) : 0.0f;
-            if (real) a.src_index[k] = a.lm[m];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * GW;
+            if (k >= kend) continue;   // uniform over the wavefront
+            const double s64 = wave_sum(n64[u]);
+            const float s32 = wave_sum(n32[u]);
+            if (lane == 0) {
+                a.snorm64[k] = s64;
+                a.snorm32[k] = s32;
+                a.coef64[k] = realq[u] ? 1.0 / (double)cntq[u] : 0.0;
+                a.coef32[k] = realq[u] ? (float)(1.0 / (double)cntq[u]) : 0.0f;
+                if (realq[u]) a.src_index[k] = posq[u];
+            }
+            nmax = fmaxf(nmax, s32);
         }
-        nmax = fmaxf(nmax, n32);
     }
     // one atomic per workgroup for the largest squared norm (non-negative floats order as integers)
     if (lane == 0) L.red[wave] = (double)nmax;
@@ -698,7 +841,7 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
         for (int w = 0; w < nwaves; ++w) mx = fmaxf(mx, (float)L.red[w]);
         if (mx > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(a.snorm_max), __float_as_uint(mx));
     }
-    stamp(a);
+    stamp(a, ns);
 }
 
 }  // namespace
@@ -781,8 +924,12 @@ kkm_status launch_landmark_loop(const LandmarkArgs& args, int dtype, const Devic
     const int G = args.grid;
     LandmarkArgs a = args;
     void* params[] = {&a};
-    const void* fn = dtype == KKM_F64 ? reinterpret_cast<const void*>(&landmark_phase_kernel<double>)
-                                      : reinterpret_cast<const void*>(&landmark_phase_kernel<float>);
+    const bool kl = args.k_in_lds != 0;
+    const void* fn = dtype == KKM_F64
+                         ? (kl ? reinterpret_cast<const void*>(&landmark_phase_kernel<double, true>)
+                               : reinterpret_cast<const void*>(&landmark_phase_kernel<double, false>))
+                         : (kl ? reinterpret_cast<const void*>(&landmark_phase_kernel<float, true>)
+                               : reinterpret_cast<const void*>(&landmark_phase_kernel<float, false>));
     KKM_TRY(allow_dynamic_lds(fn, lds));
     int per_cu = 0;
     KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
