@@ -14,8 +14,8 @@ namespace {
 
 // HIP events recorded on the caller's stream at the boundaries of the phases of a fit (optional):
 // back-to-back phases share their boundary event.  The events only time the stream, so they are
-// recorded with a device-scope release (no system-scope cache flush, which stalls the queue for
-// several microseconds per event).  The events live for one call only.
+// recorded without the system-scope fences (whose cache maintenance stalls the queue for several
+// microseconds per event).  The events live for one call only.
 // Timed spans of a fit: k-means++ / medoids; landmark block and initial labels; landmark loop kernel;
 // batch-wide distance kernel; FP64 re-decision; selection (column minima, medoids, merge).
 enum { kPhInit = 0, kPhLandmark = 1, kPhLoop = 2, kPhDist = 3, kPhRefine = 4, kPhSelect = 5, kPhases = 6 };
@@ -36,7 +36,7 @@ struct PhaseTimer {
         auto& p = pool(device);
         if (used == p.size()) {
             hipEvent_t e;
-            KKM_HIP(hipEventCreateWithFlags(&e, hipEventReleaseToDevice));
+            KKM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             p.push_back(e);
         }
         *slot = used++;

@@ -260,20 +260,30 @@ __device__ __forceinline__ void full_sums(const LdsLayout& L, const double* Krow
     __syncthreads();
 }
 
-// Barrier over the co-resident workgroups of the loop kernel: a monotonically increasing
-// arrival counter (cleared by a kernel launched just before on the same stream).  After the
-// workgroup barrier, one thread arrives with a release RMW at agent scope (one L2 write-back covers
-// the workgroup's writes), polls with relaxed loads (no cache maintenance per poll), and issues one
-// acquire fence once the count is reached; the closing workgroup barrier passes that on to the other
-// threads, whose plain loads then see every workgroup's writes.  The wait is bounded: past kSpinCap
-// polls the workgroup records an error and proceeds, so the kernel always terminates.
+// Values exchanged between the workgroups of the loop kernel (cluster partial sums, new labels) are
+// written and read as relaxed device-scope atomics: those accesses pass the per-XCD L2 caches, so
+// a value whose store has completed is what every other workgroup's device-scope load returns.
+template <typename T>
+__device__ __forceinline__ void xput(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+__device__ __forceinline__ T xget(T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Barrier over the co-resident workgroups of the loop kernel: a monotonically increasing arrival
+// counter (cleared by a kernel launched just before on the same stream).  Every thread first waits
+// until its exchange stores have completed, then after the workgroup barrier one thread arrives
+// with a device-scope RMW and polls with device-scope loads; the closing workgroup barrier
+// releases the other threads.  Since all exchanged data moves through device-scope accesses, no L2
+// write-back or invalidation is needed.  The wait is bounded: past kSpinCap polls the workgroup
+// records an error and proceeds, so the kernel always terminates.
 constexpr unsigned kSpinCap = 1u << 26;
 
 __device__ __forceinline__ void grid_barrier(const LandmarkArgs& a, unsigned& target) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's stores (the exchange stores among them) are done
     __syncthreads();
     target += gridDim.x;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned polls = 0;
         while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
@@ -282,9 +292,9 @@ __device__ __forceinline__ void grid_barrier(const LandmarkArgs& a, unsigned& ta
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Counters the loop and the later kernels of the batch expect cleared (one workgroup).
@@ -606,7 +616,7 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
                 for (int u = 0; u < 8; ++u) acc += lb[u] == j ? v[u] : 0.0;
             }
             for (; r < nr; ++r) acc += L.lbl[r0 + r] == j ? L.S[r * C + j] : 0.0;
-            a.partial[(int64_t)wg * C + j] = acc;
+            xput(a.partial + (int64_t)wg * C + j, acc);
             L.rcnt[j] = L.cnt[j] > 0 ? 1.0 / (double)L.cnt[j] : 0.0;
         }
         stamp(a, ns);
@@ -617,7 +627,7 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
             const int j = p % C, sub = p / C;
             double acc = 0.0;
 #pragma unroll 4
-            for (int g = sub; g < G; g += nsub) acc += a.partial[(int64_t)g * C + j];
+            for (int g = sub; g < G; g += nsub) acc += xget(a.partial + (int64_t)g * C + j);
             L.red[p] = acc;
         }
         __syncthreads();
@@ -661,13 +671,13 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int r = rb + u * nwaves;
-                if (r < nr && lane == 0) a.nlab_x[r0 + r] = bj[u] < C ? bj[u] : L.lbl[r0 + r];
+                if (r < nr && lane == 0) xput(a.nlab_x + r0 + r, bj[u] < C ? bj[u] : L.lbl[r0 + r]);
             }
         }
         stamp(a, ns);
         grid_barrier(a, target);
         stamp(a, ns);
-        for (int m = tid; m < ell; m += nt) L.nlab[m] = a.nlab_x[m];
+        for (int m = tid; m < ell; m += nt) L.nlab[m] = xget(a.nlab_x + m);
         __syncthreads();
         // changed landmarks in index order (first wave)
         if (wave == 0) {
