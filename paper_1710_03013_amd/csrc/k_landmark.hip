@@ -50,8 +50,9 @@ struct LdsLayout {
     double* rcnt;      // [C] 1 / c_j
 };
 
-// Row stride of K_LL (in HBM and LDS): even, so rows start 16-byte aligned.
-__host__ __device__ inline int k_ld(int ell) { return (ell + 1) & ~1; }
+// Row stride of K_LL (in HBM and LDS): a multiple of 16 doubles, so every row starts on a 128-byte
+// line and the block kernel's row segments are whole lines.
+__host__ __device__ inline int k_ld(int ell) { return (ell + 15) & ~15; }
 
 __device__ __forceinline__ size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(256) void landmark_init_kernel(LandmarkArgs a) {
 //     workgroup, 4 x 4 entries per thread, both row sets staged in LDS 16 dimensions at a time.
 //     Same arithmetic as the FP64 evaluator (dimension order; explicit differences for RBF).
 //     Block (0, 0) also clears the loop's counters.
-template <typename TI, int DP>
+template <typename TI, int DP, bool LIN>
 __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     constexpr int T = 64, CH = DP < 16 ? DP : 16;
     __shared__ double As[CH][T + 1];
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     const TI* M = static_cast<const TI*>(a.M);
     const int64_t rs = a.stride * a.d;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const bool lin = a.ktype == KKM_KERNEL_LINEAR;
+    constexpr bool lin = LIN;
     double acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    if (lin) {
+                    if constexpr (lin) {
                         acc[i][j] = fma(av[i], bw[j], acc[i][j]);
                     } else {
                         const double t = av[i] - bw[j];
@@ -904,10 +905,14 @@ kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const Devi
         if constexpr (DP > 0) {
             const int ncol = args.ell + (args.init_mode ? args.C : 0);
             const dim3 kgrid((unsigned)((ncol + 63) / 64), (unsigned)((args.ell + 63) / 64));
-            if (dtype == KKM_F64)
-                hipLaunchKernelGGL((landmark_k_kernel<double, DP>), kgrid, dim3(256), 0, stream, args);
-            else
-                hipLaunchKernelGGL((landmark_k_kernel<float, DP>), kgrid, dim3(256), 0, stream, args);
+            const bool lin = args.ktype == KKM_KERNEL_LINEAR;
+            if (dtype == KKM_F64) {
+                if (lin) hipLaunchKernelGGL((landmark_k_kernel<double, DP, true>), kgrid, dim3(256), 0, stream, args);
+                else hipLaunchKernelGGL((landmark_k_kernel<double, DP, false>), kgrid, dim3(256), 0, stream, args);
+            } else {
+                if (lin) hipLaunchKernelGGL((landmark_k_kernel<float, DP, true>), kgrid, dim3(256), 0, stream, args);
+                else hipLaunchKernelGGL((landmark_k_kernel<float, DP, false>), kgrid, dim3(256), 0, stream, args);
+            }
             KKM_HIP(hipGetLastError());
             hipLaunchKernelGGL(landmark_init_from_k_kernel, dim3((unsigned)((args.ell + 3) / 4)), dim3(256), 0, stream, args);
         } else {

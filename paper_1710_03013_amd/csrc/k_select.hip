@@ -53,57 +53,6 @@ __device__ void block_vmin(double& v, int64_t& i) {
 }
 
 // ----------------------------------------------------------------------------- k-means++
-__global__ __launch_bounds__(1024) void kpp_pick_kernel(const double* __restrict__ D2, int64_t n, int k,
-                                                        const double* __restrict__ uniforms, int32_t* chosen) {
-    __shared__ double incl[1024];
-    const int t = threadIdx.x;
-    const double u = uniforms[k];
-    const int64_t fallback = min<int64_t>((int64_t)floor(u * (double)n), n - 1);
-    if (k == 0) {
-        if (t == 0) chosen[0] = (int32_t)fallback;
-        return;
-    }
-    const int64_t w = (n + 1023) / 1024;
-    const int64_t lo = min<int64_t>(n, t * w), hi = min<int64_t>(n, lo + w);
-    double cs = 0.0;
-    for (int64_t q = lo; q < hi; ++q) cs += D2[q];
-    incl[t] = cs;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan, fixed order
-        const double add = t >= o ? incl[t - o] : 0.0;
-        __syncthreads();
-        incl[t] += add;
-        __syncthreads();
-    }
-    const double total = incl[1023];
-    if (t == 0) chosen[k] = (int32_t)fallback;   // overwritten below when D^2 has mass
-    __syncthreads();
-    if (!(total > 0.0)) return;
-    const double thr = u * total;
-    const double excl = t > 0 ? incl[t - 1] : 0.0;
-    if (incl[t] > thr && excl <= thr) {
-        double loc = 0.0;
-        int64_t pick = hi - 1;
-        for (int64_t q = lo; q < hi; ++q) {
-            loc += D2[q];
-            if (excl + loc > thr) { pick = q; break; }
-        }
-        chosen[k] = (int32_t)pick;
-    }
-}
-
-template <typename TI, int DP>
-__global__ __launch_bounds__(256) void kpp_dist_kernel(BatchView b, KSpec ks, int k, const int32_t* chosen,
-                                                       double* D2) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= b.n) return;
-    const TI* x = brow<TI>(b, q);
-    const TI* m = brow<TI>(b, chosen[k]);
-    double v = (kself64(ks, x) - 2.0 * k64p<DP>(ks, x, m)) + kself64(ks, m);
-    v = v > 0.0 ? v : 0.0;
-    D2[q] = k == 0 ? v : fmin(D2[q], v);
-}
-
 // Kernel k-means++ (Sec. 3.1) as one kernel whose workgroups are all resident: workgroup g owns the
 // contiguous rows [g R, (g + 1) R).  Pick k >= 1: every workgroup folds medoid k - 1 into its rows of
 // D^2 (D2 buffers alternate between picks), publishes its row sum, and after one grid barrier every
@@ -127,11 +76,23 @@ struct KppArgs {
 constexpr unsigned kKppSpinCap = 1u << 26;
 constexpr int kKppMaxGrid = 256;  // <= 256: one partial per thread in the owner search
 
+// The values exchanged between the workgroups (D^2 rows, per-workgroup sums) are written and read as
+// relaxed device-scope atomics, which pass the per-XCD L2 caches; the barrier then only waits for
+// every thread's stores to complete before one thread arrives (no L2 write-back or invalidation).
+template <typename T>
+__device__ __forceinline__ void kput(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+__device__ __forceinline__ T kget(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void kpp_barrier(const KppArgs& a, unsigned& target) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's stores (the exchange stores among them) are done
     __syncthreads();
     target += gridDim.x;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned polls = 0;
         while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
@@ -140,26 +101,31 @@ __device__ __forceinline__ void kpp_barrier(const KppArgs& a, unsigned& target) 
                 break;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Inclusive scan of one value per thread over the workgroup in a fixed order; *excl is the previous
-// thread's inclusive value (so excl of t + 1 equals incl of t bit for bit).  Returns the total.
+// Inclusive scan of one value per thread over the workgroup in a fixed order: within each wavefront
+// by shuffles, then the wavefront totals in wavefront order.  *excl is the previous thread's
+// inclusive value, bit for bit (the same additions of the same operands).  Returns the total.
 __device__ __forceinline__ double block_scan(double v, double* sh, double* excl, double* incl) {
-    const int t = threadIdx.x, nt = blockDim.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int o = 1; o < nt; o <<= 1) {
-        const double add = t >= o ? sh[t - o] : 0.0;
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    double x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    *excl = t > 0 ? sh[t - 1] : 0.0;
-    *incl = sh[t];
-    const double total = sh[nt - 1];
+    const double xprev = __shfl_up(x, 1, 64);
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    double base = 0.0;   // sum of the totals of the earlier wavefronts, in order
+    for (int i = 0; i < w; ++i) base = i == 0 ? sh[0] : base + sh[i];
+    double total = 0.0;
+    for (int i = 0; i < nw; ++i) total = i == 0 ? sh[0] : total + sh[i];
+    *incl = w == 0 ? x : base + x;
+    *excl = lane > 0 ? (w == 0 ? xprev : base + xprev) : base;
     __syncthreads();
     return total;
 }
@@ -232,19 +198,19 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
                 const TI* x = row(q);
                 v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, m)) + kmm;
                 v = v > 0.0 ? v : 0.0;
-                if (k > 1) v = fmin(D2o[q], v);
+                if (k > 1) v = fmin(kget(D2o + q), v);
             }
-            D2[q] = v;
+            kput(D2 + q, v);
             ts += v;
         }
         double e0, i0;
         const double gsum = block_scan(ts, sh, &e0, &i0);
-        if (t == 0) a.part[(int64_t)cur * G + g] = gsum;
+        if (t == 0) kput(a.part + (int64_t)cur * G + g, gsum);
         kpp_barrier(a, target);
         // every workgroup derives the same pick: owner chunk from the partials, then the row
         const double* P = a.part + (int64_t)cur * G;
         double pe, pi;
-        const double total = block_scan(t < G ? P[t] : 0.0, sh, &pe, &pi);   // G <= 256
+        const double total = block_scan(t < G ? kget(P + t) : 0.0, sh, &pe, &pi);   // G <= 256
         const double u = a.uniforms[k];
         if (t == 0) {
             pick_sh = (int32_t)min<int64_t>((int64_t)floor(u * (double)n), n - 1);   // no mass: fallback
@@ -263,7 +229,7 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
             chunk(owner, &olo, &ohi);
             slice(olo, ohi, &qlo, &qhi);
             double cs = 0.0;
-            for (int64_t q = qlo; q < qhi; ++q) cs += D2[q];
+            for (int64_t q = qlo; q < qhi; ++q) cs += kget(D2 + q);
             double ce, ci;
             (void)block_scan(cs, sh, &ce, &ci);
             const double base = base_sh;
@@ -271,7 +237,7 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
                 double loc = base + ce;
                 int64_t pk = qhi - 1;
                 for (int64_t q = qlo; q < qhi; ++q) {
-                    loc += D2[q];
+                    loc += kget(D2 + q);
                     if (loc > thr) {
                         pk = q;
                         break;

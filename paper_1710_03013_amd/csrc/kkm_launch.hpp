@@ -68,7 +68,7 @@ struct LandmarkShape {
 };
 LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C);
 size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds);
-inline int64_t landmark_ldk(int64_t ell) { return (ell + 1) & ~int64_t(1); }
+inline int64_t landmark_ldk(int64_t ell) { return (ell + 15) & ~int64_t(15); }
 // K_LL (+ K(x_l, m_j)) and the initial landmark labels; then the landmark loop and the support.
 kkm_status launch_landmark_block(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
 kkm_status launch_landmark_loop(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
