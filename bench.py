@@ -298,10 +298,14 @@ def main() -> int:
     infos = []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        infos.append(step(time_phases=not args.no_phase_timing))
+        # events only around the two candidate dominant kernels (three per batch)
+        infos.append(step(time_phases=0 if args.no_phase_timing else 2))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"[bench] {args.steps} timed steps in {t1 - t0:.3f} s")
+    # the breakdown over all phases from one more (untimed) step with events around every phase
+    phase_info = step(time_phases=True) if not args.no_phase_timing else None
+    torch.cuda.synchronize()
     elapsed = t1 - t0
     info = infos[-1]
     evals_step = info["evals_algorithmic"] + N * C
@@ -334,7 +338,8 @@ def main() -> int:
                                "kernel": name, "avg_launch_us": dur * 1e6, "flop_per_launch": flops}
         dom = max(cands, key=lambda k_: cands[k_][0])
         roofline = dict(rooflines[dom])
-        roofline["phase_ms_per_step"] = ms
+        roofline["kernel_ms_per_step"] = {"landmark_loop": ms["landmark_loop"], "dist": ms["dist"]}
+        roofline["phase_ms_per_step"] = {k_: float(v) for k_, v in phase_info["ms"].items()}
 
     # assign latency at a fixed request size
     lat = []

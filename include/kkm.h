@@ -115,7 +115,9 @@ typedef struct kkm_fit_info {
     int64_t evals_performed;    /* out: kernel evaluations the device carried out */
     int64_t rows_refined;       /* out: labels re-decided in FP64 */
     int64_t medoid_candidates;  /* out: medoid candidates re-evaluated in FP64 */
-    int32_t time_phases;        /* in: nonzero records HIP events on the stream around each phase */
+    int32_t time_phases;        /* in: 1 records HIP events on the stream around each phase; 2 only around
+                                   the landmark loop kernel and the batch-wide distance kernel (three
+                                   events per batch; the other ms_* stay 0); 0 none */
     int32_t reserved;
     double ms_init;             /* out (time_phases): k-means++ / initial medoids */
     double ms_landmark;         /* out: landmark block, initial labels, landmark loop, centroid support */

@@ -253,7 +253,10 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
             init="kmeans++", precision="fp32", seed=0, landmarks=None, kmpp_uniforms=None, init_labels=None,
             init_medoids=None, model=None, workspace=None, stream=None, want_labels=True, time_phases=False,
             landmark_trace=False):
-    """Fit on X (a CUDA tensor, N x d).  Returns (model, labels tensor or None, info dict)."""
+    """Fit on X (a CUDA tensor, N x d).  Returns (model, labels tensor or None, info dict).
+
+    time_phases: False / 0 no timing; True / 1 HIP events around every phase; 2 only around the
+    landmark loop kernel and the batch-wide distance kernel (info["ms"] holds 0 for the others)."""
     import torch
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
@@ -276,7 +279,7 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     bcnt = np.zeros(B * C, dtype=np.int64)
     gmed = np.zeros(B * C, dtype=np.int64)
     trace = np.zeros(64, dtype=np.int64) if landmark_trace else None
-    info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, int(bool(time_phases)))
+    info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, int(time_phases))
     if trace is not None:
         info.landmark_trace = _i64p(trace)
     _check(lib().kkm_fit(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p),

@@ -15,13 +15,15 @@ namespace {
 // HIP events recorded on the caller's stream at the boundaries of the phases of a fit (optional):
 // back-to-back phases share their boundary event.  The events only time the stream, so they are
 // recorded without the system-scope fences (whose cache maintenance stalls the queue for several
-// microseconds per event).  The events live for one call only.
+// microseconds per event).  The events are pooled per host thread and device and reused by later
+// calls (creating and destroying them is host work on every fit otherwise); they are not destroyed.
 // Timed spans of a fit: k-means++ / medoids; landmark block and initial labels; landmark loop kernel;
 // batch-wide distance kernel; FP64 re-decision; selection (column minima, medoids, merge).
 enum { kPhInit = 0, kPhLandmark = 1, kPhLoop = 2, kPhDist = 3, kPhRefine = 4, kPhSelect = 5, kPhases = 6 };
 
 struct PhaseTimer {
     bool on = false;
+    unsigned mask = ~0u;       // phases that are timed
     hipStream_t s = nullptr;
     int device = 0;
     size_t used = 0;
@@ -43,13 +45,20 @@ struct PhaseTimer {
         KKM_HIP(hipEventRecord(p[*slot], s));
         return KKM_OK;
     }
+    bool timed(int phase) const { return on && ((mask >> phase) & 1u); }
     // begin() right after end() (no launch in between) reuses that end event
-    kkm_status begin() {
-        if (!on || open_valid) return KKM_OK;
-        return record(&open);
+    kkm_status begin(int phase) {
+        if (!timed(phase) || open_valid) return KKM_OK;
+        KKM_TRY(record(&open));
+        open_valid = true;
+        return KKM_OK;
     }
     kkm_status end(int phase) {
         if (!on) return KKM_OK;
+        if (!timed(phase)) {
+            open_valid = false;
+            return KKM_OK;
+        }
         size_t e;
         KKM_TRY(record(&e));
         spans.push_back({phase, {open, e}});
@@ -59,11 +68,6 @@ struct PhaseTimer {
     }
     // a launch outside every phase follows: the next phase records its own begin event
     void gap() { open_valid = false; }
-    ~PhaseTimer() {
-        auto& p = pool(device);
-        for (hipEvent_t e : p) (void)hipEventDestroy(e);
-        p.clear();
-    }
     // after the stream has been synchronised
     void collect(double out[kPhases]) {
         for (int p = 0; p < kPhases; ++p) out[p] = 0.0;
@@ -511,6 +515,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     const size_t es = dtype == KKM_F64 ? 8 : 4;
     PhaseTimer tm;
     tm.on = info && info->time_phases;
+    if (tm.on && info->time_phases == 2) tm.mask = (1u << kPhLoop) | (1u << kPhDist);
     tm.s = s;
     tm.device = dev.device;
 
@@ -540,7 +545,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     auto view = [&](int i) { return BatchView{Xs, d, P.base[i], P.stride[i], P.n[i]}; };
 
     // batch-0 initialisation of the global medoids
-    KKM_TRY(tm.begin());
+    KKM_TRY(tm.begin(kPhInit));
     if (P.p.init == KKM_INIT_KMEANSPP) {
         KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.barrier,
                                 w.lm_error, dev, s));
@@ -610,10 +615,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
             KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
             tm.gap();
         }
-        KKM_TRY(tm.begin());
+        KKM_TRY(tm.begin(kPhLandmark));
         KKM_TRY(launch_landmark_block(la, dtype, dev, s));
         KKM_TRY(tm.end(kPhLandmark));
-        KKM_TRY(tm.begin());
+        KKM_TRY(tm.begin(kPhLoop));
         KKM_TRY(launch_landmark_loop(la, dtype, dev, s));
         KKM_TRY(tm.end(kPhLoop));
 
@@ -657,11 +662,11 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         da.n_support = ell;
         int64_t dist_blocks = 0;
         da.colpart_blocks = &dist_blocks;
-        KKM_TRY(tm.begin());
+        KKM_TRY(tm.begin(kPhDist));
         KKM_TRY(launch_dist(da, dev, s));
         KKM_TRY(tm.end(kPhDist));
         if (!dist_is_fp64(da)) {
-            KKM_TRY(tm.begin());
+            KKM_TRY(tm.begin(kPhRefine));
             KKM_TRY(launch_refine(da, dev, s, ell));
             KKM_TRY(tm.end(kPhRefine));
         }
@@ -700,7 +705,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.info_bmed = w.info + (size_t)i * C;
         sa.info_bcnt = w.info + (size_t)(P.B + i) * C;
         sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
-        KKM_TRY(tm.begin());
+        KKM_TRY(tm.begin(kPhSelect));
         sa.cand_total = w.flags + 1;
         if (dist_blocks > 0) KKM_TRY(launch_colmin_reduce(da, dist_blocks, s));
         KKM_TRY(launch_select(sa, dist_is_fp64(da), dev, s));
