@@ -30,9 +30,13 @@ namespace kkm {
 
 namespace {
 
+// Threads per workgroup of the loop kernel: one workgroup per CU (its LDS holds the own rows of K),
+// so a wide workgroup is what gives each SIMD several wavefronts to interleave.
+constexpr int kLoopThreads = 1024;
+
 struct LdsLayout {
     double* K;         // [R][ell] own rows of the landmark block (when staged in LDS)
-    double* red;       // [max(256, C)] partial-sum scratch
+    double* red;       // [max(kLoopThreads, C)] partial-sum scratch
     int32_t* lbl;      // [ell]
     int32_t* perm;     // [ell]
     int32_t* off;      // [C+1]
@@ -60,7 +64,7 @@ __host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R, bool
     const int nchunks = (ell + 63) / 64;
     size_t b = 0;
     if (k_in_lds) b += sizeof(double) * (size_t)R * k_ld(ell);
-    b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)(C > 256 ? C : 256);
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * (size_t)(C > kLoopThreads ? C : kLoopThreads);
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * ell;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (C + 1);
@@ -85,7 +89,7 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool 
     size_t b = 0;
     L.K = reinterpret_cast<double*>(base);
     if (k_in_lds) b += sizeof(double) * (size_t)R * k_ld(ell);
-    b = al16(b); L.red = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)(C > 256 ? C : 256);
+    b = al16(b); L.red = reinterpret_cast<double*>(base + b); b += sizeof(double) * (size_t)(C > kLoopThreads ? C : kLoopThreads);
     b = al16(b); L.lbl = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.perm = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.off = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (C + 1);
@@ -118,8 +122,8 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
         // few clusters: every label in turn over the wave's chunks (independent ballots, no
         // dependence between chunks); ranks and counts are selected in registers (lane j keeps the
         // count of label j) and stored once, so the label loop has no branches
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         for (int ch0 = wave; ch0 < nchunks; ch0 += 4 * nwaves) {
+            const int nu = min(4, (nchunks - ch0 + nwaves - 1) / nwaves);   // chunks of this wave (uniform)
             int labs[4], rk[4], ct[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -133,10 +137,14 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
                 const bool mine = lane == j;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const uint64_t mask = __ballot(labs[u] == j);
-                    const int rb = (int)__popcll(mask & below);
-                    rk[u] = labs[u] == j ? rb : rk[u];
-                    ct[u] = mine ? (int)__popcll(mask) : ct[u];
+                    if (u < nu) {   // uniform
+                        const uint64_t mask = __ballot(labs[u] == j);
+                        // lanes below this one with label j
+                        const int rb = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        rk[u] = labs[u] == j ? rb : rk[u];
+                        ct[u] = mine ? (int)__popcll(mask) : ct[u];
+                    }
                 }
             }
 #pragma unroll
@@ -168,30 +176,15 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
         }
     }
     __syncthreads();
-    // per label: exclusive prefix over chunks (in place) and the total count; one label per
-    // wavefront with the chunks on the lanes when they fit, else serially per label
-    if (nchunks <= 64) {
-        for (int j = wave; j < C; j += nwaves) {
-            const int t = lane < nchunks ? L.chunk[lane * C + j] : 0;
-            int v = t;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int u = __shfl_up(v, o, 64);
-                if (lane >= o) v += u;
-            }
-            if (lane < nchunks) L.chunk[lane * C + j] = (uint16_t)(v - t);
-            if (lane == 63) L.off[j + 1] = v;
+    // per label: exclusive prefix over chunks (in place) and the total count
+    for (int j = tid; j < C; j += nt) {
+        int run = 0;
+        for (int ch = 0; ch < nchunks; ++ch) {
+            const int t = L.chunk[ch * C + j];
+            L.chunk[ch * C + j] = (uint16_t)run;
+            run += t;
         }
-    } else {
-        for (int j = tid; j < C; j += nt) {
-            int run = 0;
-            for (int ch = 0; ch < nchunks; ++ch) {
-                const int t = L.chunk[ch * C + j];
-                L.chunk[ch * C + j] = (uint16_t)run;
-                run += t;
-            }
-            L.off[j + 1] = run;
-        }
+        L.off[j + 1] = run;
     }
     __syncthreads();
     // segment offsets = exclusive scan of the counts, and qoff = exclusive scan of the number of
@@ -534,7 +527,7 @@ __global__ __launch_bounds__(256) void landmark_init_from_k_kernel(LandmarkArgs 
 // KL: the own rows of K_LL are staged in LDS (else read from HBM); a compile-time choice, so the
 // reads compile to LDS or global instructions rather than generic ones.
 template <typename TI, bool KL>
-__global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
+__global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
@@ -553,9 +546,9 @@ __global__ __launch_bounds__(256) void landmark_phase_kernel(LandmarkArgs a) {
 
     stamp(a, ns);
     // The own rows of K are one contiguous, 16-byte aligned block, copied to LDS as double2: the
-    // first 16 per thread are loaded before the CSR sort of the labels and stored after it.
+    // first KU per thread are loaded before the CSR sort of the labels and stored after it.
     typedef double dvec2 __attribute__((ext_vector_type(2)));
-    constexpr int KU = 16;
+    constexpr int KU = 8;
     const int64_t n2 = KL ? (int64_t)nr * ldk / 2 : 0;
     const dvec2* ksrc = reinterpret_cast<const dvec2*>(Kg);
     dvec2* kdst = reinterpret_cast<dvec2*>(L.K);
@@ -947,7 +940,7 @@ kkm_status launch_landmark_loop(const LandmarkArgs& args, int dtype, const Devic
                                : reinterpret_cast<const void*>(&landmark_phase_kernel<float, false>));
     KKM_TRY(allow_dynamic_lds(fn, lds));
     int per_cu = 0;
-    KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
+    KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kLoopThreads, lds));
     if (per_cu * dev.num_cus < G)
         return fail(KKM_ERR_DEVICE, "landmark loop grid does not fit co-resident on the device");
     // The grid fits the device at once, so a plain launch makes every workgroup resident as soon as
@@ -958,8 +951,8 @@ kkm_status launch_landmark_loop(const LandmarkArgs& args, int dtype, const Devic
         const char* e = std::getenv("KKM_LANDMARK_COOPERATIVE");
         return e && e[0] == '1';
     }();
-    if (coop) KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), params, (unsigned)lds, stream));
-    else KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(256), params, (unsigned)lds, stream));
+    if (coop) KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kLoopThreads), params, (unsigned)lds, stream));
+    else KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(kLoopThreads), params, (unsigned)lds, stream));
     return KKM_OK;
 }
 
