@@ -52,6 +52,8 @@ struct LdsLayout {
     int32_t* chg;      // [ell + 1] changed landmarks in index order; chg[ell] = their number
     int32_t* cnt;      // [C] landmarks per cluster
     double* rcnt;      // [C] 1 / c_j
+    uint64_t* cmask;   // [nchunks] changed-landmark ballot of every 64-landmark chunk
+    int32_t* ccnt;     // [nchunks] its population count
 };
 
 // Row stride of K_LL (in HBM and LDS): a multiple of 16 doubles, so every row starts on a 128-byte
@@ -80,6 +82,8 @@ __host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R, bool
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * (ell + 1);
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * C;
     b = (b + 15) & ~size_t(15); b += sizeof(double) * C;
+    b = (b + 15) & ~size_t(15); b += sizeof(uint64_t) * nchunks;
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * nchunks;
     return (b + 15) & ~size_t(15);
 }
 
@@ -104,7 +108,9 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool 
     b = al16(b); L.nlab = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * ell;
     b = al16(b); L.chg = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * (ell + 1);
     b = al16(b); L.cnt = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * C;
-    b = al16(b); L.rcnt = reinterpret_cast<double*>(base + b);
+    b = al16(b); L.rcnt = reinterpret_cast<double*>(base + b); b += sizeof(double) * C;
+    b = al16(b); L.cmask = reinterpret_cast<uint64_t*>(base + b); b += sizeof(uint64_t) * nchunks;
+    b = al16(b); L.ccnt = reinterpret_cast<int32_t*>(base + b);
     return L;
 }
 
@@ -119,43 +125,24 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
     }
     // ranks inside each 64-landmark chunk
     if (C <= 64) {
-        // few clusters: every label in turn over the wave's chunks (independent ballots, no
-        // dependence between chunks); ranks and counts are selected in registers (lane j keeps the
-        // count of label j) and stored once, so the label loop has no branches
-        for (int ch0 = wave; ch0 < nchunks; ch0 += 4 * nwaves) {
-            const int nu = min(4, (nchunks - ch0 + nwaves - 1) / nwaves);   // chunks of this wave (uniform)
-            int labs[4], rk[4], ct[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int ch = ch0 + u * nwaves;
-                const int m = ch * 64 + lane;
-                labs[u] = (ch < nchunks && m < ell) ? L.lbl[m] : -1;
-                rk[u] = 0;
-                ct[u] = 0;
-            }
+        // few clusters: every label in turn over the wave's chunk (one ballot per label); the rank
+        // is selected in a register and lane j keeps the count of label j, so the label loop has no
+        // branches; both are stored once
+        for (int ch = wave; ch < nchunks; ch += nwaves) {
+            const int m = ch * 64 + lane;
+            const int lab = m < ell ? L.lbl[m] : -1;
+            int rk = 0, ct = 0;
             for (int j = 0; j < C; ++j) {
-                const bool mine = lane == j;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (u < nu) {   // uniform
-                        const uint64_t mask = __ballot(labs[u] == j);
-                        // lanes below this one with label j
-                        const int rb = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                        rk[u] = labs[u] == j ? rb : rk[u];
-                        ct[u] = mine ? (int)__popcll(mask) : ct[u];
-                    }
-                }
+                const bool hit = lab == j;
+                const uint64_t mask = __ballot(hit);
+                // lanes below this one with label j
+                const int rb = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                rk = hit ? rb : rk;
+                ct = lane == j ? (int)__popcll(mask) : ct;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int ch = ch0 + u * nwaves;
-                const int m = ch * 64 + lane;
-                if (ch < nchunks) {   // uniform over the wavefront
-                    if (m < ell) L.rank[m] = (uint8_t)rk[u];
-                    if (lane < C) L.chunk[ch * C + lane] = (uint16_t)ct[u];
-                }
-            }
+            if (m < ell) L.rank[m] = (uint8_t)rk;
+            if (lane < C) L.chunk[ch * C + lane] = (uint16_t)ct;
         }
         __syncthreads();
     }
@@ -671,22 +658,41 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         stamp(a, ns);
         grid_barrier(a, target);
         stamp(a, ns);
-        for (int m = tid; m < ell; m += nt) L.nlab[m] = xget(a.nlab_x + m);
-        __syncthreads();
-        // changed landmarks in index order (first wave)
-        if (wave == 0) {
-            int base_out = 0;
-            const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-            for (int c0 = 0; c0 < ell; c0 += 64) {
-                const int m = c0 + lane;
-                const bool ch = m < ell && L.nlab[m] != L.lbl[m];
-                const uint64_t mask = __ballot(ch);
-                if (ch) L.chg[base_out + __popcll(mask & below)] = m;
-                base_out += __popcll(mask);
+        // new labels and the changed landmarks in index order: every wavefront takes whole 64-landmark
+        // chunks (ballot of the changes, mask and count kept in LDS), then writes its chunks' entries
+        // after the prefix of the lower chunks' counts
+        {
+            const int nchunks = (ell + 63) / 64;
+            uint64_t* cmask = L.cmask;
+            int32_t* ccnt = L.ccnt;
+            for (int ch = wave; ch < nchunks; ch += nwaves) {
+                const int m = ch * 64 + lane;
+                bool chg = false;
+                if (m < ell) {
+                    const int nl = xget(a.nlab_x + m);
+                    L.nlab[m] = nl;
+                    chg = nl != L.lbl[m];
+                }
+                const uint64_t mask = __ballot(chg);
+                if (lane == 0) {
+                    cmask[ch] = mask;
+                    ccnt[ch] = (int)__popcll(mask);
+                }
             }
-            if (lane == 0) L.chg[ell] = base_out;
+            __syncthreads();
+            for (int ch = wave; ch < nchunks; ch += nwaves) {
+                int base_out = 0;
+                for (int c = 0; c < ch; ++c) base_out += ccnt[c];
+                const uint64_t mask = cmask[ch];
+                if ((mask >> lane) & 1ull) {
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    L.chg[base_out + below] = ch * 64 + lane;
+                }
+                if (ch == nchunks - 1 && lane == 0) L.chg[ell] = base_out + ccnt[ch];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const int nch = L.chg[ell];
         stamp(a, ns);
         ++it;
