@@ -707,7 +707,9 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
         KKM_TRY(tm.begin(kPhSelect));
         sa.cand_total = w.flags + 1;
-        if (dist_blocks > 0) KKM_TRY(launch_colmin_reduce(da, dist_blocks, s));
+        sa.colpart = w.colpart;
+        sa.colpart_ld = da.colpart_cap;
+        sa.colpart_blocks = dist_blocks;
         KKM_TRY(launch_select(sa, dist_is_fp64(da), dev, s));
         KKM_TRY(tm.end(kPhSelect));
     }

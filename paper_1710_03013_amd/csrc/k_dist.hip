@@ -381,16 +381,6 @@ __global__ __launch_bounds__(256) void sum_partial_kernel(const double* __restri
 }
 
 // One wavefront per cluster: minimum of the workgroup partials of D + E.
-__global__ __launch_bounds__(64) void colmin_reduce_kernel(const double* __restrict__ colpart, int64_t ld, int64_t nblk,
-                                                           unsigned long long* colmin) {
-    const int j = blockIdx.x;
-    double v = kInf;
-    for (int64_t b = threadIdx.x; b < nblk; b += 64) v = fmin(v, colpart[(int64_t)j * ld + b]);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    if (threadIdx.x == 0) colmin[j] = v < kInf ? ord_enc(v) : ~0ull;
-}
-
 template <class Ev, int LPQ>
 kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     using TC = typename TcOf<Ev>::type;
@@ -475,12 +465,6 @@ kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     });
-}
-
-kkm_status launch_colmin_reduce(const DistArgs& a, int64_t nblk, hipStream_t s) {
-    hipLaunchKernelGGL(colmin_reduce_kernel, dim3(a.sup.C), dim3(64), 0, s, a.colpart, a.colpart_cap, nblk, a.colmin);
-    KKM_HIP(hipGetLastError());
-    return KKM_OK;
 }
 
 kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s) {

@@ -622,38 +622,22 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         stamp(a, ns);
         if (it >= a.max_updates) break;
 
-        // Eq. 15 for the own rows (one wavefront per row, four rows per wavefront at a time so
-        // their reductions overlap; lowest j among equal minima)
-        for (int rb = wave; rb < nr; rb += 4 * nwaves) {
-            double bv[4];
-            int bj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int r = rb + u * nwaves;
-                bv[u] = kInf;
-                bj[u] = C;
-                if (r < nr) {
-                    for (int j = lane; j < C; j += 64) {
-                        if (L.cnt[j] == 0) continue;
-                        const double dj = L.kself[r] - 2.0 * L.S[r * C + j] * L.rcnt[j] + L.gh[j];
-                        if (bj[u] == C || dj < bv[u]) { bv[u] = dj; bj[u] = j; }
-                    }
-                }
+        // Eq. 15 for the own rows (one wavefront per row; lowest j among equal minima)
+        for (int r = wave; r < nr; r += nwaves) {
+            double bv = kInf;
+            int bj = C;
+            for (int j = lane; j < C; j += 64) {
+                if (L.cnt[j] == 0) continue;
+                const double dj = L.kself[r] - 2.0 * L.S[r * C + j] * L.rcnt[j] + L.gh[j];
+                if (bj == C || dj < bv) { bv = dj; bj = j; }
             }
 #pragma unroll
             for (int o = 32; o >= 1; o >>= 1) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double v2 = __shfl_xor(bv[u], o, 64);
-                    const int j2 = __shfl_xor(bj[u], o, 64);
-                    if (j2 < C && (bj[u] == C || v2 < bv[u] || (v2 == bv[u] && j2 < bj[u]))) { bv[u] = v2; bj[u] = j2; }
-                }
+                const double v2 = __shfl_xor(bv, o, 64);
+                const int j2 = __shfl_xor(bj, o, 64);
+                if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int r = rb + u * nwaves;
-                if (r < nr && lane == 0) xput(a.nlab_x + r0 + r, bj[u] < C ? bj[u] : L.lbl[r0 + r]);
-            }
+            if (lane == 0) xput(a.nlab_x + r0 + r, bj < C ? bj : L.lbl[r0 + r]);
         }
         stamp(a, ns);
         grid_barrier(a, target);

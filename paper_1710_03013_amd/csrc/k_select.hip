@@ -277,22 +277,39 @@ __global__ void set_medoids_kernel(BatchView b, KSpec ks, int C, const int32_t* 
 // re-evaluated in FP64 and the lowest (value, position) is the batch medoid.
 constexpr int kRowsPerBlock = 256;
 
-// Grid (row chunks) x (clusters): member counts per chunk, label scatter, candidate list.
+// Grid (row chunks) x (clusters): member counts per chunk, label scatter, candidate list.  U_j is
+// the minimum of the distance pass's per-block column minima (every block reduces them itself; the
+// minimum is exact in any order).
 template <typename TD>
 __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
     const int j = blockIdx.y, chunk = blockIdx.x;
     const int64_t q = (int64_t)chunk * kRowsPerBlock + threadIdx.x;
     const bool active = q < a.b.n;
     __shared__ int cnt;
+    __shared__ double umin[kRowsPerBlock / 64];
     if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
+    double U;
+    if (a.colpart_blocks > 0) {
+        double v = kInf;
+        for (int64_t b = threadIdx.x; b < a.colpart_blocks; b += blockDim.x)
+            v = fmin(v, a.colpart[(int64_t)j * a.colpart_ld + b]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+        if ((threadIdx.x & 63) == 0) umin[threadIdx.x >> 6] = v;
+        __syncthreads();
+        v = umin[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmin(v, umin[w]);
+        U = v < kInf ? v : ord_dec(~0ull);
+    } else {
+        __syncthreads();
+        U = ord_dec(a.colmin[j]);
+    }
     if (active) {
         const int lab = a.labels[q];
         if (j == 0 && a.label_out) a.label_out[a.b.base + q * a.b.stride] = lab;
         if (lab == j) atomicAdd(&cnt, 1);
         const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
         const double D = (double)Dt[q];
-        const double U = ord_dec(a.colmin[j]);
         if (D < kInf && D - (double)a.Erow[q] <= U) {
             const int pos = atomicAdd(a.cand_count, 1);
             if (pos < a.cand_cap) {

@@ -111,11 +111,11 @@ struct DistArgs {
     int32_t* refine_list;   // [n]
     int32_t* refine_count;  // [1]
     int32_t* nonfinite;     // [1]
-    unsigned long long* colmin;   // [C] ord_enc(min over rows of D + Erow), or null (fit only)
-    double* colpart;        // [C][colpart_cap] per-workgroup minima behind colmin (with colmin)
+    unsigned long long* colmin;   // [C] non-null in a fit: the pass then writes colpart (the medoid
+                                  // candidate kernel folds it into min over rows of D + Erow)
+    double* colpart;        // [C][colpart_cap] per-workgroup minima of D + Erow (with colmin)
     int64_t colpart_cap;
-    int64_t* colpart_blocks;// host out (with colmin): workgroups of the pass; launch_colmin_reduce
-                            // then folds colpart into colmin
+    int64_t* colpart_blocks;// host out (with colmin): workgroups of the pass
     int64_t n_support;      // rows of sup (offsets[C])
 };
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
@@ -129,7 +129,6 @@ size_t dist_lds_bytes(const DistArgs& a);
 // Workgroups of any distance pass over n rows (bound for colpart_cap).
 inline int64_t dist_block_cap(int64_t n) { return (n + 15) / 16 + 1; }
 // colmin[j] <- ord_enc(min over the first nblk entries of colpart row j) (~0: none finite).
-kkm_status launch_colmin_reduce(const DistArgs& a, int64_t nblk, hipStream_t s);
 // FP64 re-decision of the rows listed by launch_dist (n_support: support rows of a.sup).
 kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s, int64_t n_support);
 // Deterministic FP64 sum of best[0..n) into out[0] (partials: >= 1024 doubles of scratch).
@@ -155,7 +154,10 @@ struct SelectArgs {
     const float* Dt;        // [C][ldD] distances of the batch pass (float or double)
     int64_t ldD;
     const float* Erow;      // [n] error bound of each row's distances
-    const unsigned long long* colmin;   // [C] ord_enc(min over rows of D + E)
+    const unsigned long long* colmin;   // [C] ord_enc(min over rows of D + E), used when colpart_blocks == 0
+    const double* colpart;  // [C][colpart_ld] per-block column minima of D + E from the distance pass
+    int64_t colpart_ld;
+    int64_t colpart_blocks; // blocks of the distance pass (0: take colmin)
     SupportView sup;        // support of the batch centroids (FP64 re-evaluation of candidates)
     int32_t nchunk;         // select_chunks(n)
     int32_t* mpart_c;       // [C][nchunk] member-count partials
