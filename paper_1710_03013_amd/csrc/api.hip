@@ -115,6 +115,7 @@ struct FitWs {
     double* Kmed;
     int32_t* lab;
     int32_t* nlab_x;
+    double* sx;
     double* partial;
     int32_t* changed;
     int32_t* lab_final;
@@ -175,7 +176,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.Kbuf = c.take<double>((size_t)P.ellmax * landmark_ldk(P.ellmax));
     w.Kmed = c.take<double>((size_t)P.ellmax * C);
     w.lab = c.take<int32_t>(2 * P.ellmax);
-    w.nlab_x = c.take<int32_t>((size_t)P.ellmax);
+    w.nlab_x = c.take<int32_t>((size_t)2 * P.ellmax);
+    w.sx = c.take<double>((size_t)4 * P.ellmax);
     w.partial = c.take<double>((size_t)P.gmax * C);
     w.changed = c.take<int32_t>(P.T + 1);
     w.lab_final = c.take<int32_t>(P.ellmax);
@@ -585,6 +587,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         la.Kmed = w.Kmed;
         la.lab = w.lab;
         la.nlab_x = w.nlab_x;
+        la.sx = w.sx;
         la.partial = w.partial;
         la.changed = w.changed;
         la.zero_ints = w.counts_b;

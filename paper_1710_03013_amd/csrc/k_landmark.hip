@@ -33,6 +33,8 @@ namespace {
 // Threads per workgroup of the loop kernel: one workgroup per CU (its LDS holds the own rows of K),
 // so a wide workgroup is what gives each SIMD several wavefronts to interleave.
 constexpr int kLoopThreads = 1024;
+// Updates that change at most this many landmark labels move g^ by the pair formula (no exchange).
+constexpr int kPairMax = 64;
 
 struct LdsLayout {
     double* K;         // [R][ell] own rows of the landmark block (when staged in LDS)
@@ -54,6 +56,13 @@ struct LdsLayout {
     double* rcnt;      // [C] 1 / c_j
     uint64_t* cmask;   // [nchunks] changed-landmark ballot of every 64-landmark chunk
     int32_t* ccnt;     // [nchunks] its population count
+    double* T;         // [C] sum over m, m' in L_j of K(m, m')  (= c_j^2 g^_j)
+    double* dT;        // [C] its change over one update (pair path)
+    int32_t* pab;      // [kPairMax] old | new << 16 label of change t (pair path)
+    double* psa;       // [kPairMax] S[m_t][old]  before the update
+    double* psb;       // [kPairMax] S[m_t][new]  before the update
+    double* pwa;       // [kPairMax] sum_t' delta_t'(old_t) K(m_t, m_t')
+    double* pwb;       // [kPairMax] sum_t' delta_t'(new_t) K(m_t, m_t')
 };
 
 // Row stride of K_LL (in HBM and LDS): a multiple of 16 doubles, so every row starts on a 128-byte
@@ -84,6 +93,9 @@ __host__ __device__ inline size_t landmark_lds_bytes(int ell, int C, int R, bool
     b = (b + 15) & ~size_t(15); b += sizeof(double) * C;
     b = (b + 15) & ~size_t(15); b += sizeof(uint64_t) * nchunks;
     b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * nchunks;
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * 2 * (size_t)C;
+    b = (b + 15) & ~size_t(15); b += sizeof(int32_t) * kPairMax;
+    b = (b + 15) & ~size_t(15); b += sizeof(double) * 4 * kPairMax;
     return (b + 15) & ~size_t(15);
 }
 
@@ -110,7 +122,14 @@ __device__ LdsLayout carve_lds(unsigned char* base, int ell, int C, int R, bool 
     b = al16(b); L.cnt = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * C;
     b = al16(b); L.rcnt = reinterpret_cast<double*>(base + b); b += sizeof(double) * C;
     b = al16(b); L.cmask = reinterpret_cast<uint64_t*>(base + b); b += sizeof(uint64_t) * nchunks;
-    b = al16(b); L.ccnt = reinterpret_cast<int32_t*>(base + b);
+    b = al16(b); L.ccnt = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * nchunks;
+    b = al16(b); L.T = reinterpret_cast<double*>(base + b); b += sizeof(double) * C;
+    L.dT = L.T + C; b += sizeof(double) * C;
+    b = al16(b); L.pab = reinterpret_cast<int32_t*>(base + b); b += sizeof(int32_t) * kPairMax;
+    b = al16(b); L.psa = reinterpret_cast<double*>(base + b);
+    L.psb = L.psa + kPairMax;
+    L.pwa = L.psb + kPairMax;
+    L.pwb = L.pwa + kPairMax;
     return L;
 }
 
@@ -579,9 +598,9 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
     stamp(a, ns);
 
     const int nsub = C < nt ? nt / C : 1;     // threads per cluster in the partial reduction
-    int it = 0;
-    for (;;) {
-        // own part of sum_{m in L_j} S[m][j], in row order
+    // T_j and g^_j from every workgroup's part of sum_{m in L_j} S[m][j] (in row order), exchanged
+    // through one grid barrier, then summed in a fixed order; also 1 / c_j
+    auto exchange_T = [&]() {
         for (int j = tid; j < C; j += nt) {
             double acc = 0.0;
             int r = 0;
@@ -603,7 +622,7 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         stamp(a, ns);
         grid_barrier(a, target);
         stamp(a, ns);
-        // g^_j = 1/c_j^2 sum_g partial[g][j]: nsub interleaved sub-sums per cluster, then in order
+        // nsub interleaved sub-sums per cluster, then in order
         for (int p = tid; p < nsub * C; p += nt) {
             const int j = p % C, sub = p / C;
             double acc = 0.0;
@@ -616,13 +635,21 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
             double acc = 0.0;
             for (int sub = 0; sub < nsub; ++sub) acc += L.red[sub * C + j];
             const double cj = (double)L.cnt[j];
+            L.T[j] = acc;
             L.gh[j] = cj > 0.0 ? acc / (cj * cj) : kInf;
         }
         __syncthreads();
         stamp(a, ns);
+    };
+    exchange_T();
+    int it = 0, buf = 0;     // buf: which half of the double-buffered label / S exchange this update uses
+    for (;;) {
         if (it >= a.max_updates) break;
+        int32_t* nlx = a.nlab_x + (int64_t)buf * ell;
+        double* sx = a.sx + (int64_t)buf * 2 * ell;
 
-        // Eq. 15 for the own rows (one wavefront per row; lowest j among equal minima)
+        // Eq. 15 for the own rows (one wavefront per row; lowest j among equal minima); a changed row
+        // also publishes S at its old and new label (for the pair update of g^)
         for (int r = wave; r < nr; r += nwaves) {
             double bv = kInf;
             int bj = C;
@@ -637,7 +664,14 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 const int j2 = __shfl_xor(bj, o, 64);
                 if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
             }
-            if (lane == 0) xput(a.nlab_x + r0 + r, bj < C ? bj : L.lbl[r0 + r]);
+            if (lane == 0) {
+                const int m = r0 + r, old = L.lbl[m], nl = bj < C ? bj : old;
+                xput(nlx + m, nl);
+                if (nl != old) {
+                    xput(sx + 2 * (int64_t)m, L.S[r * C + old]);
+                    xput(sx + 2 * (int64_t)m + 1, L.S[r * C + nl]);
+                }
+            }
         }
         stamp(a, ns);
         grid_barrier(a, target);
@@ -653,7 +687,7 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 const int m = ch * 64 + lane;
                 bool chg = false;
                 if (m < ell) {
-                    const int nl = xget(a.nlab_x + m);
+                    const int nl = xget(nlx + m);
                     L.nlab[m] = nl;
                     chg = nl != L.lbl[m];
                 }
@@ -681,9 +715,56 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         stamp(a, ns);
         ++it;
         if (nch == 0) break;
-        // from scratch (sort + segment sums, ~ell steps per row) only when the incremental update
-        // (every own entry of S walks the changed list) would take longer
+
+        // Few changes: the change of T_j follows from the old S values of the changed landmarks and K
+        // between changed landmarks, with delta_t(j) = [j = new_t] - [j = old_t]:
+        //   dT_j = sum_t delta_t(j) (2 S[m_t][j] + sum_t' delta_t'(j) K(m_t, m_t'))
+        // (every workgroup evaluates it in the same order, so T stays identical everywhere)
+        const bool pair = nch <= kPairMax;
+        if (pair) {
+            for (int t = tid; t < nch; t += nt) {
+                const int m = L.chg[t];
+                L.pab[t] = L.lbl[m] | (L.nlab[m] << 16);
+                L.psa[t] = xget(sx + 2 * (int64_t)m);
+                L.psb[t] = xget(sx + 2 * (int64_t)m + 1);
+            }
+            __syncthreads();
+            // one wavefront per change t, lanes over the changes t'
+            for (int t = wave; t < nch; t += nwaves) {
+                const int mt = L.chg[t], abt = L.pab[t];
+                const int at = abt & 0xffff, bt = abt >> 16;
+                double wa = 0.0, wb = 0.0;
+                if (lane < nch) {
+                    const int ab2 = L.pab[lane];
+                    const int a2 = ab2 & 0xffff, b2 = ab2 >> 16;
+                    const double kv = a.Kbuf[(int64_t)mt * ldk + L.chg[lane]];
+                    wa = (double)((b2 == at) - (a2 == at)) * kv;
+                    wb = (double)((b2 == bt) - (a2 == bt)) * kv;
+                }
+                wa = wave_sum(wa);
+                wb = wave_sum(wb);
+                if (lane == 0) {
+                    L.pwa[t] = wa;
+                    L.pwb[t] = wb;
+                }
+            }
+            __syncthreads();
+            for (int j = tid; j < C; j += nt) {
+                double dt = 0.0;
+                for (int t = 0; t < nch; ++t) {
+                    const int ab = L.pab[t];
+                    if ((ab >> 16) == j) dt += 2.0 * L.psb[t] + L.pwb[t];
+                    if ((ab & 0xffff) == j) dt -= 2.0 * L.psa[t] + L.pwa[t];
+                }
+                L.dT[j] = dt;
+            }
+            // (the next barrier orders these before the update below overwrites pab's source labels)
+        }
+
+        // own rows of S: from scratch (sort + segment sums, ~ell steps per row) only when the
+        // incremental update (every own entry of S walks the changed list) would take longer
         if ((int64_t)nch * ((nr * C + nt - 1) / nt) > (int64_t)ell) {
+            __syncthreads();
             for (int m = tid; m < ell; m += nt) L.lbl[m] = L.nlab[m];
             __syncthreads();
             csr_sort(L, ell, C);
@@ -733,6 +814,19 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
             for (int t = tid; t < nch; t += nt) L.lbl[L.chg[t]] = L.nlab[L.chg[t]];
             __syncthreads();
         }
+        if (pair) {
+            for (int j = tid; j < C; j += nt) {
+                const double cj = (double)L.cnt[j];
+                const double T = L.T[j] + L.dT[j];
+                L.T[j] = T;
+                L.gh[j] = cj > 0.0 ? T / (cj * cj) : kInf;
+                L.rcnt[j] = cj > 0.0 ? 1.0 / cj : 0.0;
+            }
+            __syncthreads();
+        } else {
+            exchange_T();
+        }
+        buf ^= 1;
         stamp(a, ns);
     }
     // CSR of the final labels for the support

@@ -31,7 +31,9 @@ struct LandmarkArgs {
     int64_t ldk;            // row stride of Kbuf (ell rounded up to even)
     double* Kmed;           // [ell][C] scratch: K(x_l, m_j) for the Eq. 8 initialisation
     int32_t* lab;           // [2][ell] scratch: initial labels, then final labels
-    int32_t* nlab_x;        // [ell] scratch: labels after an update, exchanged between workgroups
+    int32_t* nlab_x;        // [2][ell] scratch: labels after an update, exchanged between workgroups
+                            // (two halves used by alternate updates)
+    double* sx;             // [2][ell][2] scratch: S of a changed landmark at its old and new label
     double* partial;        // [grid][C] scratch: each workgroup's part of the g^ sums
     int32_t* changed;       // [max_updates+1] scratch
     int32_t* zero_ints;     // ints to clear for the later kernels of the batch
