@@ -448,7 +448,8 @@ kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
     const bool per_block = n_support > 256;   // large supports: a whole block per listed row
     const size_t lds = per_block ? sizeof(double) * (kRefineChunk + (size_t)a.sup.C)
                                  : sizeof(double) * 4 * (256 + (size_t)a.sup.C);
-    const unsigned blocks = per_block ? (unsigned)std::min<int64_t>(a.q.n, 4 * (int64_t)dev.num_cus)
+    // (the listed rows are usually few: one workgroup per CU, each taking rows in turn)
+    const unsigned blocks = per_block ? (unsigned)std::min<int64_t>(a.q.n, (int64_t)dev.num_cus)
                                       : (unsigned)std::min<int64_t>((a.q.n + 3) / 4, 2 * (int64_t)dev.num_cus);
     return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
         if (per_block) {

@@ -404,13 +404,15 @@ __global__ __launch_bounds__(256) void landmark_init_kernel(LandmarkArgs a) {
 }
 
 // 1'. Linear / RBF kernels: K_LL and, for the Eq. 8 initialisation, K(x_l, m_j) for the C global
-//     medoids, in FP64: one 64 x 64 tile of the (landmarks) x (landmarks, medoids) matrix per
-//     workgroup, 4 x 4 entries per thread, both row sets staged in LDS 16 dimensions at a time.
+//     medoids, in FP64: one T x T tile of the (landmarks) x (landmarks, medoids) matrix per
+//     workgroup (T = 32, or 64 for rows of 4 dimensions), (T/16)^2 entries per thread, both row sets
+//     staged in LDS 16 dimensions at a time.
 //     Same arithmetic as the FP64 evaluator (dimension order; explicit differences for RBF).
 //     Block (0, 0) also clears the loop's counters.
-template <typename TI, int DP, bool LIN>
+template <typename TI, int DP, bool LIN, int T>
 __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
-    constexpr int T = 64, CH = DP < 16 ? DP : 16;
+    constexpr int CH = DP < 16 ? DP : 16;
+    constexpr int NI = T / 16;   // entries per thread along each side
     __shared__ double As[CH][T + 1];
     __shared__ double Bs[CH][T + 1];
     const int ell = a.ell, C = a.C, d = (int)a.d;
@@ -423,11 +425,11 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     const int64_t rs = a.stride * a.d;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     constexpr bool lin = LIN;
-    double acc[4][4];
+    double acc[NI][NI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < NI; ++j) acc[i][j] = 0.0;
     // staging: element p = threadIdx.x + 256 u of a stage is (row rr = p / CH, dimension k = p % CH);
     // the row starts are resolved once, and each stage issues all its loads before the LDS stores
     constexpr int PER = T * CH / 256;
@@ -462,15 +464,15 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
         __syncthreads();
 #pragma unroll 4
         for (int k = 0; k < CH; ++k) {
-            double av[4], bw[4];
+            double av[NI], bw[NI];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[k][ty + 16 * i];
+            for (int i = 0; i < NI; ++i) av[i] = As[k][ty + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bw[j] = Bs[k][tx + 16 * j];
+            for (int j = 0; j < NI; ++j) bw[j] = Bs[k][tx + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < NI; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < NI; ++j) {
                     if constexpr (lin) {
                         acc[i][j] = fma(av[i], bw[j], acc[i][j]);
                     } else {
@@ -481,9 +483,9 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
         }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NI; ++j) {
             const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
             if (r < ell && c < ncol) {
                 const double v = lin ? acc[i][j] : ::exp(-acc[i][j] * a.inv2s2);
@@ -981,14 +983,17 @@ kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const Devi
     return dispatch_dp(eval_dp(args.ktype, args.d), [&]<int DP>() -> kkm_status {
         if constexpr (DP > 0) {
             const int ncol = args.ell + (args.init_mode ? args.C : 0);
-            const dim3 kgrid((unsigned)((ncol + 63) / 64), (unsigned)((args.ell + 63) / 64));
+            // 32 x 32 tiles (four times the workgroups of 64 x 64, so more of them overlap their row
+            // gathers); 64 x 64 for rows of 4 dimensions, where a 32-row stage would not fill the block
+            constexpr int T = DP >= 8 ? 32 : 64;
+            const dim3 kgrid((unsigned)((ncol + T - 1) / T), (unsigned)((args.ell + T - 1) / T));
             const bool lin = args.ktype == KKM_KERNEL_LINEAR;
             if (dtype == KKM_F64) {
-                if (lin) hipLaunchKernelGGL((landmark_k_kernel<double, DP, true>), kgrid, dim3(256), 0, stream, args);
-                else hipLaunchKernelGGL((landmark_k_kernel<double, DP, false>), kgrid, dim3(256), 0, stream, args);
+                if (lin) hipLaunchKernelGGL((landmark_k_kernel<double, DP, true, T>), kgrid, dim3(256), 0, stream, args);
+                else hipLaunchKernelGGL((landmark_k_kernel<double, DP, false, T>), kgrid, dim3(256), 0, stream, args);
             } else {
-                if (lin) hipLaunchKernelGGL((landmark_k_kernel<float, DP, true>), kgrid, dim3(256), 0, stream, args);
-                else hipLaunchKernelGGL((landmark_k_kernel<float, DP, false>), kgrid, dim3(256), 0, stream, args);
+                if (lin) hipLaunchKernelGGL((landmark_k_kernel<float, DP, true, T>), kgrid, dim3(256), 0, stream, args);
+                else hipLaunchKernelGGL((landmark_k_kernel<float, DP, false, T>), kgrid, dim3(256), 0, stream, args);
             }
             KKM_HIP(hipGetLastError());
             hipLaunchKernelGGL(landmark_init_from_k_kernel, dim3((unsigned)((args.ell + 3) / 4)), dim3(256), 0, stream, args);
