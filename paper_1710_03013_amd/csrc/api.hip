@@ -149,8 +149,6 @@ struct FitWs {
     int32_t* mpart_c;
     double* gpart_v;
     int32_t* gpart_i;
-    void* mtarget;
-    double* malpha;
     int32_t* updates;      // [B]
     int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
     int64_t* trace;        // [64]
@@ -210,8 +208,6 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
     w.gpart_v = c.take<double>((size_t)C * merge_chunks(P.nmax));
     w.gpart_i = c.take<int32_t>((size_t)C * merge_chunks(P.nmax));
-    w.mtarget = c.take<char>((size_t)2 * C * P.dpad * es);
-    w.malpha = c.take<double>(C);
     w.barrier = c.take<unsigned>(1);
     // status block, read back with one copy: [refine_counts, flags, updates, lm_error, info, trace]
     w.refine_counts = c.take<int32_t>(P.B);
@@ -702,8 +698,6 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.cand_cap = (int32_t)P.cand_cap;
         sa.gpart_v = w.gpart_v;
         sa.gpart_i = w.gpart_i;
-        sa.mtarget = w.mtarget;
-        sa.malpha = w.malpha;
 
         sa.info_bmed = w.info + (size_t)i * C;
         sa.info_bcnt = w.info + (size_t)(P.B + i) * C;

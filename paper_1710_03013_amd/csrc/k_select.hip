@@ -400,32 +400,13 @@ __global__ __launch_bounds__(256) void merge_partial_kernel(SelectArgs a) {
     }
 }
 
-// Linear / RBF kernels: one block per cluster settles |w_j^i|, m_j^i and alpha_j and lays out the two
-// merge targets of the cluster; a tiled pass then scores every batch row against all targets.
-template <typename TI>
-__global__ __launch_bounds__(256) void merge_prep_kernel(SelectArgs a) {
-    const int j = blockIdx.x;
-    int32_t mem = 0, med = -1;
-    reduce_cluster(a, j, &mem, &med);
-    const double alpha = merge_alpha(mem, a.wcount[j]);
-    const bool on = alpha > 0.0 && med >= 0;
-    if (threadIdx.x == 0) {
-        a.counts[j] = mem;
-        a.bmed[j] = med;
-        a.malpha[j] = on ? alpha : 0.0;
-    }
-    TI* T = static_cast<TI*>(a.mtarget) + (int64_t)2 * j * a.Mpad;
-    const TI* xm = brow<TI>(a.b, on ? med : 0);
-    const TI* M = static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
-    for (int64_t c = threadIdx.x; c < a.Mpad; c += blockDim.x) {
-        T[c] = on && c < a.b.d ? xm[c] : TI(0);
-        T[a.Mpad + c] = on && alpha < 1.0 ? M[c] : TI(0);
-    }
-}
-
-// Block = kMergeRows batch rows x kMergeTJ clusters (two targets each).  Wave w scores the targets of
-// clusters 4w..4w+3 against all kMergeRows rows, one row per lane, so that every target value read
-// from LDS (a broadcast) feeds a row and every row value feeds eight targets.  Rows are staged
+// Linear / RBF kernels.  Block = kMergeRows batch rows x kMergeTJ clusters (two targets each).  The
+// block first settles its clusters: the batch medoid m_j^i is the lowest (value, position) candidate
+// (two exact LDS minimum passes: the ordered value, then the position among the candidates holding
+// it), |w_j^i| the sum of the member-count partials, and alpha_j; the blocks of row chunk 0 record
+// them.  Wave w then scores the targets (m_j^i and m_j) of clusters 4w..4w+3 against all kMergeRows
+// rows, one row per lane, so that every target value read from LDS (a broadcast) feeds a row and
+// every row value feeds eight targets.  Rows are staged
 // through LDS dimension-major in chunks of 16 dimensions (coalesced global reads).  Scores follow
 // the per-row merge formula in FP64 (explicit differences for RBF); the (value, position) minimum
 // of each cluster over the block's rows goes to gpart (kMergeRows-row chunks: merge_chunks).
@@ -439,15 +420,68 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
     constexpr int CH = DP < 16 ? DP : 16;
     __shared__ double Ts[DP][NT];
     __shared__ TI Xs[CH][kMergeXs];
+    __shared__ unsigned long long cmin[kMergeTJ];
+    __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
+    __shared__ double calpha[kMergeTJ];
     const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
     const int d = a.b.d;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // settle the block's clusters (the same result as one block reducing each cluster)
+    if (threadIdx.x < kMergeTJ) {
+        cmin[threadIdx.x] = ~0ull;
+        cpos[threadIdx.x] = INT32_MAX;
+        cmem[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int count = min(*a.cand_count, a.cand_cap);
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const int jj = a.cand_j[i] - j0;
+        const double v = a.cand_v[i];
+        if (jj >= 0 && jj < kMergeTJ && !isnan(v)) atomicMin(&cmin[jj], ord_enc(v + 0.0));   // -0 counts as +0
+    }
+    for (int p = threadIdx.x; p < kMergeTJ * a.nchunk; p += blockDim.x) {
+        const int jj = p / a.nchunk, k = p - jj * a.nchunk;
+        if (j0 + jj < a.C) {
+            const int32_t c = a.mpart_c[(int64_t)(j0 + jj) * a.nchunk + k];
+            if (c) atomicAdd(&cmem[jj], c);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const int jj = a.cand_j[i] - j0;
+        const double v = a.cand_v[i];
+        if (jj >= 0 && jj < kMergeTJ && !isnan(v) && ord_enc(v + 0.0) == cmin[jj]) atomicMin(&cpos[jj], a.cand_q[i]);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMergeTJ && j0 + (int)threadIdx.x < a.C) {
+        const int j = j0 + threadIdx.x;
+        const int32_t mem = cmem[threadIdx.x];
+        // no candidate only when every distance is +inf or NaN (non-finite input, reported separately)
+        const int32_t med = mem == 0 ? -1 : (cpos[threadIdx.x] == INT32_MAX ? 0 : cpos[threadIdx.x]);
+        const double alpha = merge_alpha(mem, a.wcount[j]);
+        const bool on = alpha > 0.0 && med >= 0;
+        cmed[threadIdx.x] = med;
+        calpha[threadIdx.x] = on ? alpha : 0.0;
+        if (chunk == 0) {
+            a.counts[j] = mem;
+            a.bmed[j] = med;
+        }
+    }
+    __syncthreads();
+    // targets, dimension-major: t = 2 (j - j0) is m_j^i, t + 1 is m_j (zero when unused)
     for (int p = threadIdx.x; p < DP * NT; p += blockDim.x) {
         const int k = p / NT, t = p - k * NT;
-        const int j = j0 + t / 2;
+        const int jj = t / 2, j = j0 + jj;
         double v = 0.0;
-        if (j < a.C && k < d) v = (double)static_cast<const TI*>(a.mtarget)[(int64_t)(2 * j + (t & 1)) * a.Mpad + k];
+        if (j < a.C && k < d) {
+            const double alpha = calpha[jj];
+            if ((t & 1) == 0) {
+                if (alpha > 0.0) v = (double)brow<TI>(a.b, cmed[jj])[k];
+            } else if (alpha > 0.0 && alpha < 1.0) {
+                v = (double)static_cast<const TI*>(a.M)[(int64_t)j * a.Mpad + k];
+            }
+        }
         Ts[k][t] = v;
     }
     const int64_t row0 = (int64_t)chunk * kMergeRows;
@@ -491,7 +525,7 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
     for (int c = 0; c < 4; ++c) {
         const int j = j0 + 4 * wave + c;
         if (j >= a.C) break;   // uniform over the wave
-        const double alpha = a.malpha[j];
+        const double alpha = calpha[4 * wave + c];
         double bv = kInf;
         int64_t bi = INT64_MAX;
         if (alpha > 0.0 && lane < nrows) {
@@ -789,8 +823,6 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
         if constexpr (DP == 0) {
             hipLaunchKernelGGL((merge_partial_kernel<TI, DP>), grid, dim3(256), 0, s, a);
         } else {
-            hipLaunchKernelGGL(merge_prep_kernel<TI>, dim3(a.C), dim3(256), 0, s, a);
-            KKM_HIP(hipGetLastError());
             hipLaunchKernelGGL((merge_tile_kernel<TI, DP>), tgrid, dim3(256), 0, s, a);
         }
         KKM_HIP(hipGetLastError());

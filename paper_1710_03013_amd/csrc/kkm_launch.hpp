@@ -172,8 +172,6 @@ struct SelectArgs {
     double* gpart_v;        // [C][mchunk] merge partials (set by launch_select)
     int32_t* gpart_i;
     int32_t mchunk;
-    void* mtarget;          // [2C][Mpad] merge targets: row 2j = m_j^i, row 2j+1 = m_j (input dtype)
-    double* malpha;         // [C] merge weight alpha_j (0: m_j stays)
     // per-batch info rows (device, length C) or null
     int64_t* info_bmed;
     int64_t* info_bcnt;
