@@ -416,20 +416,29 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     __shared__ double As[CH][T + 1];
     __shared__ double Bs[CH][T + 1];
     const int ell = a.ell, C = a.C, d = (int)a.d;
-    const int ncol = ell + (a.init_mode ? C : 0);
+    // medoid columns start on a tile boundary; when they fit one tile, its workgroups also take the
+    // Eq. 8 labels of their rows (lowest j among equal minima over the clusters with a medoid)
+    const int mc0 = (ell + T - 1) / T * T;
+    const int ncol = a.init_mode ? mc0 + C : ell;
+    const bool init_here = a.init_mode && C <= T;
     const int r0 = blockIdx.y * T, c0 = blockIdx.x * T;
     if (blockIdx.x == 0 && blockIdx.y == 0) reset_batch_state(a);
-    if (c0 >= ncol) return;   // uniform
+    if (blockIdx.x == 0 && !a.init_mode)   // given initial labels
+        for (int r = r0 + (int)threadIdx.x; r < min(ell, r0 + T); r += blockDim.x) a.lab[r] = a.lab_init[r];
+    if (c0 >= ncol || (c0 >= ell && c0 < mc0)) return;   // uniform
     const TI* X = static_cast<const TI*>(a.X) + a.base * a.d;
     const TI* M = static_cast<const TI*>(a.M);
     const int64_t rs = a.stride * a.d;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     constexpr bool lin = LIN;
     double acc[NI][NI];
+    double kxx[NI];   // linear kernel: K(x_r, x_r) by the same FMA chain as the diagonal entry
 #pragma unroll
-    for (int i = 0; i < NI; ++i)
+    for (int i = 0; i < NI; ++i) {
+        kxx[i] = 0.0;
 #pragma unroll
         for (int j = 0; j < NI; ++j) acc[i][j] = 0.0;
+    }
     // staging: element p = threadIdx.x + 256 u of a stage is (row rr = p / CH, dimension k = p % CH);
     // the row starts are resolved once, and each stage issues all its loads before the LDS stores
     constexpr int PER = T * CH / 256;
@@ -444,7 +453,7 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
         kk[u] = p - rr * CH;
         const int r = r0 + rr, c = c0 + rr;
         pa[u] = r < ell ? X + (int64_t)a.lm[r] * rs : nullptr;
-        pb[u] = c < ell ? X + (int64_t)a.lm[c] * rs : (c < ncol ? M + (int64_t)(c - ell) * a.Mpad : nullptr);
+        pb[u] = c < ell ? X + (int64_t)a.lm[c] * rs : (c >= mc0 && c < ncol ? M + (int64_t)(c - mc0) * a.Mpad : nullptr);
     }
     for (int k0 = 0; k0 < DP; k0 += CH) {
         double va[PER], vb[PER];
@@ -469,6 +478,10 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
             for (int i = 0; i < NI; ++i) av[i] = As[k][ty + 16 * i];
 #pragma unroll
             for (int j = 0; j < NI; ++j) bw[j] = Bs[k][tx + 16 * j];
+            if constexpr (lin) {
+#pragma unroll
+                for (int i = 0; i < NI; ++i) kxx[i] = fma(av[i], av[i], kxx[i]);
+            }
 #pragma unroll
             for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -482,6 +495,36 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
                 }
         }
     }
+    if (init_here && c0 == mc0) {
+        // Eq. 8 for rows r0 + ty + 16 i: the 16 lanes of a row (tx) hold its medoid columns
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int r = r0 + ty + 16 * i;
+            const double kself_r = lin ? kxx[i] : 1.0;   // RBF: exp(0)
+            double bv = kInf;
+            int bj = C;
+#pragma unroll
+            for (int j = 0; j < NI; ++j) {
+                const int m = tx + 16 * j;
+                if (m < C) {
+                    const double ms = a.Mself[m];
+                    if (ms < kInf) {
+                        const double kv = lin ? acc[i][j] : ::exp(-acc[i][j] * a.inv2s2);
+                        const double v = kself_r - 2.0 * kv + ms;
+                        if (bj == C || v < bv) { bv = v; bj = m; }
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) {
+                const double v2 = __shfl_xor(bv, o, 64);
+                const int j2 = __shfl_xor(bj, o, 64);
+                if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
+            }
+            if (tx == 0 && r < ell) a.lab[r] = bj < C ? bj : 0;
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -490,7 +533,7 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
             if (r < ell && c < ncol) {
                 const double v = lin ? acc[i][j] : ::exp(-acc[i][j] * a.inv2s2);
                 if (c < ell) a.Kbuf[(int64_t)r * a.ldk + c] = v;
-                else a.Kmed[(int64_t)r * C + (c - ell)] = v;
+                else if (c >= mc0) a.Kmed[(int64_t)r * C + (c - mc0)] = v;   // (columns in between: none)
             }
         }
 }
@@ -982,10 +1025,11 @@ kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const Devi
     const size_t lds_row = sizeof(double) * (size_t)args.d;
     return dispatch_dp(eval_dp(args.ktype, args.d), [&]<int DP>() -> kkm_status {
         if constexpr (DP > 0) {
-            const int ncol = args.ell + (args.init_mode ? args.C : 0);
             // 32 x 32 tiles (four times the workgroups of 64 x 64, so more of them overlap their row
             // gathers); 64 x 64 for rows of 4 dimensions, where a 32-row stage would not fill the block
             constexpr int T = DP >= 8 ? 32 : 64;
+            // columns: the landmarks, then (from the next tile boundary) the medoids
+            const int ncol = args.init_mode ? (args.ell + T - 1) / T * T + args.C : args.ell;
             const dim3 kgrid((unsigned)((ncol + T - 1) / T), (unsigned)((args.ell + T - 1) / T));
             const bool lin = args.ktype == KKM_KERNEL_LINEAR;
             if (dtype == KKM_F64) {
@@ -996,7 +1040,9 @@ kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const Devi
                 else hipLaunchKernelGGL((landmark_k_kernel<float, DP, false, T>), kgrid, dim3(256), 0, stream, args);
             }
             KKM_HIP(hipGetLastError());
-            hipLaunchKernelGGL(landmark_init_from_k_kernel, dim3((unsigned)((args.ell + 3) / 4)), dim3(256), 0, stream, args);
+            // the block kernel took the initial labels itself unless the medoids span several tiles
+            if (args.init_mode && args.C > T)
+                hipLaunchKernelGGL(landmark_init_from_k_kernel, dim3((unsigned)((args.ell + 3) / 4)), dim3(256), 0, stream, args);
         } else {
             const int tiles = (args.ell + 31) / 32;
             const dim3 bgrid((unsigned)tiles, (unsigned)tiles);
