@@ -874,6 +874,15 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         buf ^= 1;
         stamp(a, ns);
     }
+    // Support rows: wavefront gw takes the landmarks m = gw + u GW (u < 2 per round; rows m in
+    // [ell, ell + 32) are the zero padding for whole-tile loads, kept at position m).  The first 64
+    // dimensions of its first landmark are loaded before the CSR sort of the final labels, which then
+    // fixes each landmark's position k in the support.
+    TI* sup = static_cast<TI*>(a.support);
+    const int PD = (int)a.dpad;
+    const int GW = G * nwaves, kend = ell + 32;
+    const int mfirst = wg * nwaves + wave;
+    const TI pre = (mfirst < ell && lane < a.d) ? row(L.lmv[mfirst])[lane] : TI(0);
     // CSR of the final labels for the support
     csr_sort(L, ell, C);
     stamp(a, ns);
@@ -901,45 +910,40 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         if (tid == 0) *a.updates_out = it;
         for (int m = tid; m < ell; m += nt) a.lab[ell + m] = L.lbl[m];   // final landmark labels
     }
-    // support rows in CSR order (and rows [ell, ell + 32) zeroed for whole-tile loads): one wavefront
-    // per row over all workgroups, lanes over the dimensions, four rows per wavefront at a time (their
-    // loads issued together); row copy, FP32 / bfloat16 panels, norms
-    TI* sup = static_cast<TI*>(a.support);
-    const int PD = (int)a.dpad;
+    // support rows (one wavefront per row, lanes over the dimensions; two rows at a time): row copy,
+    // FP32 / bfloat16 panels, norms
     const bool panels = a.ktype != KKM_KERNEL_RMSD;   // power-of-two padded rows only
-    const int GW = G * nwaves, kend = ell + 32;
     float nmax = 0.0f;
-    for (int k0 = wg * nwaves + wave; k0 < kend; k0 += 4 * GW) {
-        const TI* srcq[4];
-        int cntq[4], posq[4];
-        bool realq[4];
+    for (int m0 = mfirst; m0 < kend; m0 += 2 * GW) {
+        const bool first = m0 == mfirst;
+        const TI* srcq[2];
+        int kq[2], cntq[2], posq[2];
+        bool realq[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * GW;
-            realq[u] = k < ell;
+        for (int u = 0; u < 2; ++u) {
+            const int m = m0 + u * GW;
+            realq[u] = m < ell;
+            kq[u] = m;   // padding rows keep their index
             cntq[u] = 1;
             posq[u] = 0;
             if (realq[u]) {
-                const int m = L.perm[k];
                 const int j = L.lbl[m];
+                kq[u] = L.off[j] + L.chunk[(m >> 6) * C + j] + L.rank[m];   // CSR position
                 cntq[u] = L.off[j + 1] - L.off[j];
                 posq[u] = L.lmv[m];
             }
             srcq[u] = row(posq[u]);
         }
-        double n64[4] = {0.0, 0.0, 0.0, 0.0};
-        float n32[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int c = lane; c < PD; c += 64) {
-            TI v[4];
+        double n64[2] = {0.0, 0.0};
+        float n32[2] = {0.0f, 0.0f};
+        auto emit = [&](int c, const TI (&val)[2]) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = (realq[u] && c < a.d) ? srcq[u][c] : TI(0);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = k0 + u * GW;
-                if (k >= kend) continue;   // uniform over the wavefront
-                sup[(int64_t)k * PD + c] = v[u];
-                n64[u] = fma((double)v[u], (double)v[u], n64[u]);
-                const float f = (float)v[u];
+            for (int u = 0; u < 2; ++u) {
+                const int k = kq[u];
+                if (m0 + u * GW >= kend) continue;   // uniform over the wavefront
+                sup[(int64_t)k * PD + c] = val[u];
+                n64[u] = fma((double)val[u], (double)val[u], n64[u]);
+                const float f = (float)val[u];
                 n32[u] = fmaf(f, f, n32[u]);
                 if (panels && a.sup_pan) a.sup_pan[panel32_index(k, c, PD)] = f;
                 if (panels && PD >= 16) {
@@ -949,11 +953,25 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                     a.sup_lo[panel16_index(k, c, PD)] = lo;
                 }
             }
+        };
+        {
+            const int c = lane;
+            TI val[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                val[u] = (first && u == 0) ? pre : ((realq[u] && c < a.d) ? srcq[u][c] : TI(0));
+            if (c < PD) emit(c, val);
+        }
+        for (int c = lane + 64; c < PD; c += 64) {
+            TI val[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) val[u] = (realq[u] && c < a.d) ? srcq[u][c] : TI(0);
+            emit(c, val);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u * GW;
-            if (k >= kend) continue;   // uniform over the wavefront
+        for (int u = 0; u < 2; ++u) {
+            if (m0 + u * GW >= kend) continue;   // uniform over the wavefront
+            const int k = kq[u];
             const double s64 = wave_sum(n64[u]);
             const float s32 = wave_sum(n32[u]);
             if (lane == 0) {
