@@ -50,8 +50,8 @@ DIST_KERNEL_NAME = {("rbf", "fp32"): "mfma_dist_kernel", ("linear", "fp32"): "mf
 # calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
 # and its SHA-1 prefix at measurement time: a changed kernel source reports null.
 TRAFFIC_MEASURED = {
-    ("landmark_phase_kernel", "mixture16"): (10.046e6, "k_landmark.hip", "8a33ddbf0bfe"),
-    ("mfma_dist_kernel", "mixture16"): (3.130e6, "k_mfma.hip", "9eba0a854b63"),
+    ("landmark_phase_kernel", "mixture16"): (10.276e6, "k_landmark.hip", "d46d491ccfb0"),
+    ("mfma_dist_kernel", "mixture16"): (3.191e6, "k_mfma.hip", "9c5697f4a427"),
 }
 
 

@@ -69,6 +69,15 @@ enum kkm_precision {
     KKM_PREC_BF16X3 = 2         /* x.y from split-bf16 products hi*hi + hi*lo + lo*hi on MFMA */
 };
 
+/* kkm_params.flags bits */
+enum kkm_fit_flags {
+    KKM_FIT_COOPERATIVE = 1     /* launch the kernels whose workgroups wait for each other (k-means++ and
+                                   the landmark loop) cooperatively, so that all their workgroups are
+                                   resident together even while other streams keep the GPU busy (a
+                                   plain launch then only guarantees a bounded wait, reported as
+                                   KKM_ERR_DEVICE); costs some microseconds per launch */
+};
+
 enum kkm_sampling {
     KKM_SAMPLE_STRIDE = 0,      /* X^i = { x_(i + jB) }           (Sec. 3.1) */
     KKM_SAMPLE_BLOCK = 1        /* X^i = a contiguous run         (Sec. 3.1) */
@@ -95,7 +104,7 @@ typedef struct kkm_params {
     int32_t sampling;           /* enum kkm_sampling */
     int32_t init;               /* enum kkm_init */
     int32_t precision;          /* enum kkm_precision */
-    int32_t reserved;
+    int32_t flags;              /* enum kkm_fit_flags bits, 0 by default */
     uint64_t seed;              /* draws not given below come from the SplitMix64 streams of this seed */
     const int64_t* landmarks;   /* host or NULL: concatenation over batches of l_i ascending
                                    batch positions (uniform without replacement, Sec. 3.2) */

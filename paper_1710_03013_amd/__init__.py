@@ -29,6 +29,7 @@ KKM_F32, KKM_F64 = 0, 1
 KKM_PREC_FP64, KKM_PREC_FP32, KKM_PREC_BF16X3 = 0, 1, 2
 KKM_SAMPLE_STRIDE, KKM_SAMPLE_BLOCK = 0, 1
 KKM_INIT_KMEANSPP, KKM_INIT_RANDOM_LABELS, KKM_INIT_MEDOIDS = 0, 1, 2
+KKM_FIT_COOPERATIVE = 1
 
 _KERNELS = {"linear": KKM_KERNEL_LINEAR, "rbf": KKM_KERNEL_RBF, "rmsd": KKM_KERNEL_RMSD}
 _PRECISIONS = {"fp64": KKM_PREC_FP64, "fp32": KKM_PREC_FP32, "bf16x3": KKM_PREC_BF16X3}
@@ -51,7 +52,7 @@ class _Kernel(ct.Structure):
 class _Params(ct.Structure):
     _fields_ = [("C", ct.c_int32), ("B", ct.c_int32), ("s", ct.c_double), ("max_iter", ct.c_int32),
                 ("sampling", ct.c_int32), ("init", ct.c_int32), ("precision", ct.c_int32),
-                ("reserved", ct.c_int32), ("seed", ct.c_uint64),
+                ("flags", ct.c_int32), ("seed", ct.c_uint64),
                 ("landmarks", ct.POINTER(ct.c_int64)), ("kmpp_uniforms", ct.POINTER(ct.c_double)),
                 ("init_labels", ct.POINTER(ct.c_int32)), ("init_medoids", ct.POINTER(ct.c_int64))]
 
@@ -216,8 +217,9 @@ def kkm_model_export(model: Model) -> dict:
 
 
 def _params(C, B, s, max_iter, sampling, init, precision, seed, landmarks, kmpp_uniforms, init_labels,
-            init_medoids, keep):
+            init_medoids, keep, cooperative=False):
     p = _Params()
+    p.flags = KKM_FIT_COOPERATIVE if cooperative else 0
     p.C, p.B, p.s, p.max_iter = int(C), int(B), float(s), int(max_iter)
     p.sampling = _SAMPLING[sampling] if isinstance(sampling, str) else int(sampling)
     p.init = _INITS[init] if isinstance(init, str) else int(init)
@@ -252,11 +254,13 @@ def kkm_fit_workspace_bytes(N, d, dtype, kernel, **params) -> int:
 def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20, sampling="stride",
             init="kmeans++", precision="fp32", seed=0, landmarks=None, kmpp_uniforms=None, init_labels=None,
             init_medoids=None, model=None, workspace=None, stream=None, want_labels=True, time_phases=False,
-            landmark_trace=False):
+            landmark_trace=False, cooperative=False):
     """Fit on X (a CUDA tensor, N x d).  Returns (model, labels tensor or None, info dict).
 
     time_phases: False / 0 no timing; True / 1 HIP events around every phase; 2 only around the
-    landmark loop kernel and the batch-wide distance kernel (info["ms"] holds 0 for the others)."""
+    landmark loop kernel and the batch-wide distance kernel (info["ms"] holds 0 for the others).
+    cooperative: launch the kernels whose workgroups wait for each other cooperatively (for callers
+    that keep other streams busy on the same GPU meanwhile)."""
     import torch
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
@@ -266,7 +270,7 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     dt = _dtype_code(X)
     keep = []
     p = _params(C, B, s, max_iter, sampling, init, precision, seed, landmarks, kmpp_uniforms, init_labels,
-                init_medoids, keep)
+                init_medoids, keep, cooperative)
     need = int(lib().kkm_fit_workspace_bytes(N, d, dt, ct.byref(k), ct.byref(p)))
     if need == 0:
         _check(lib().kkm_fit(None, N, d, dt, ct.byref(k), ct.byref(p), None, 0, None, None, None, None))

@@ -254,6 +254,7 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
         return fail(KKM_ERR_INVALID_ARG, "bad init");
     if (p.precision != KKM_PREC_FP64 && p.precision != KKM_PREC_FP32 && p.precision != KKM_PREC_BF16X3)
         return fail(KKM_ERR_INVALID_ARG, "bad precision");
+    if (p.flags & ~KKM_FIT_COOPERATIVE) return fail(KKM_ERR_INVALID_ARG, "unknown fit flags");
     P.N = N;
     P.d = d;
     P.dtype = dtype;
@@ -546,7 +547,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     KKM_TRY(tm.begin(kPhInit));
     if (P.p.init == KKM_INIT_KMEANSPP) {
         KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.barrier,
-                                w.lm_error, dev, s));
+                                w.lm_error, dev, s, (P.p.flags & KKM_FIT_COOPERATIVE) != 0));
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
     } else if (P.p.init == KKM_INIT_MEDOIDS) {
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
@@ -570,6 +571,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         const LandmarkShape lsh = landmark_shape(dev, ell, C);
         la.grid = lsh.grid;
         la.k_in_lds = lsh.k_in_lds;
+        la.cooperative = (P.p.flags & KKM_FIT_COOPERATIVE) != 0;
         la.ktype = kernel->type;
         la.n_atoms = kernel->n_atoms;
         la.inv2s2 = ks.inv2s2;

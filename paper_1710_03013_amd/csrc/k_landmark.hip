@@ -1104,7 +1104,8 @@ kkm_status launch_landmark_loop(const LandmarkArgs& args, int dtype, const Devic
         const char* e = std::getenv("KKM_LANDMARK_COOPERATIVE");
         return e && e[0] == '1';
     }();
-    if (coop) KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kLoopThreads), params, (unsigned)lds, stream));
+    if (coop || args.cooperative)
+        KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kLoopThreads), params, (unsigned)lds, stream));
     else KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(kLoopThreads), params, (unsigned)lds, stream));
     return KKM_OK;
 }

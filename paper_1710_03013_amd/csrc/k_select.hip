@@ -751,7 +751,7 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
 
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
                            int32_t* chosen, double* D2, double* part, unsigned* barrier, int32_t* error,
-                           const DeviceInfo& dev, hipStream_t s) {
+                           const DeviceInfo& dev, hipStream_t s, bool cooperative) {
     if (b.n <= 0) return fail(KKM_ERR_INVALID_ARG, "k-means++ on an empty batch");
     // workgroups: at least KKM_KPP_WGS (default 128) when the rows allow, more when that lets every
     // workgroup keep its rows in LDS; at most kKppMaxGrid and the CUs
@@ -788,7 +788,8 @@ kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C
         KKM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds));
         if (per_cu * dev.num_cus < G) return fail(KKM_ERR_DEVICE, "k-means++ grid does not fit co-resident");
         void* params[] = {&a};
-        KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(256), params, lds, s));
+        if (cooperative) KKM_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(256), params, lds, s));
+        else KKM_HIP(hipLaunchKernel(fn, dim3(G), dim3(256), params, lds, s));
         return KKM_OK;
     });
 }

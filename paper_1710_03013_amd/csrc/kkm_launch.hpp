@@ -58,6 +58,7 @@ struct LandmarkArgs {
     int64_t bpad;
     int32_t* split;         // [5] cluster runs of the distance pass's four wavefronts
     int32_t k_in_lds;       // own rows of the landmark block kept in LDS (else in Kbuf)
+    int32_t cooperative;    // host: launch the loop kernel cooperatively
     int64_t* trace;         // [64] device wall-clock stamps of workgroup 0, or null
     unsigned long long* colmin;   // [C] set to the empty value for the batch's distance pass
     unsigned* barrier;      // [1] arrival counter of the loop's grid barrier
@@ -188,7 +189,7 @@ kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& d
 // barrier / error as for the landmark loop (barrier cleared here).
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
                            int32_t* chosen, double* D2, double* part, unsigned* barrier, int32_t* error,
-                           const DeviceInfo& dev, hipStream_t s);
+                           const DeviceInfo& dev, hipStream_t s, bool cooperative = false);
 // Global medoids <- batch rows `chosen` (valid, counts 0), or all unset when chosen == null.
 kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, int C, const int32_t* chosen,
                               void* M, int64_t Mpad, double* Mself, int64_t* Midx, int64_t* wcount, hipStream_t s);

@@ -118,7 +118,9 @@ class KkmBackend:
         def run():
             try:
                 with torch.cuda.stream(s):
-                    box["result"] = self._fit(X, stream=s, **kw)
+                    # other streams keep the device busy meanwhile: the kernels whose workgroups wait
+                    # for each other are launched cooperatively
+                    box["result"] = self._fit(X, stream=s, **{"cooperative": True, **kw})
             except BaseException as e:   # reported on the request
                 box["error"] = e
 

@@ -66,6 +66,22 @@ def test_invalid_arguments_are_rejected():
     assert kk.kkm_fit_workspace_bytes(100, 150, kk.KKM_F32, rmsd, **args) > 0
 
 
+def test_fit_flags():
+    """The cooperative-launch flag is accepted and changes no size; unknown flag bits are rejected."""
+    kk = _kk()
+    k = kk._kernel("rbf", 4.0)
+    args = dict(C=20, B=10, s=0.1, max_iter=20, sampling="stride", init="kmeans++", precision="fp32", seed=1,
+                landmarks=None, kmpp_uniforms=None, init_labels=None, init_medoids=None)
+    plain = kk.kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, k, **args)
+    coop = kk.kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, k, cooperative=True, **args)
+    assert plain > 0 and coop == plain
+    keep = []
+    p = kk._params(20, 10, 0.1, 20, "stride", "kmeans++", "fp32", 1, None, None, None, None, keep, True)
+    assert p.flags == kk.KKM_FIT_COOPERATIVE
+    p.flags = 2
+    assert kk.lib().kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, kk.ct.byref(k), kk.ct.byref(p)) == 0
+
+
 def test_workspace_estimate_grows_with_problem_size():
     kk = _kk()
     k = kk._kernel("rbf", 4.0)
