@@ -237,6 +237,35 @@ def test_fit_is_deterministic():
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
 
 
+def test_fit_landmark_block_in_hbm():
+    """One batch of 3500 landmarks: a workgroup's rows of K_LL exceed its LDS at every grid size, so
+    the loop kernel reads them from HBM (its other variant)."""
+    kk = _kk()
+    _say("fit landmark block in HBM")
+    X, _ = ki.datasets.gaussian_mixture(3500, 8, 5, seed=11, sigma=1.0, box=4.0)
+    kern = Kernel("rbf", 2.0)
+    T = 10
+    model, labels, info, ref = _fit_both(kk, X, kern, 5, 1, 1.0, T, "kmeans++", 31, "fp32")
+    assert ref.min_gap > GAP
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+
+
+def test_fit_cooperative_launch_matches_plain():
+    """The cooperative-launch flag changes how the grid-synchronised kernels are launched, not what
+    they compute: both fits agree bit for bit."""
+    kk = _kk()
+    _say("fit cooperative vs plain")
+    X, _ = ki.datasets.gaussian_mixture(20_000, 16, 20, seed=6, sigma=1.0)
+    Xd = torch.from_numpy(X).cuda()
+    outs = []
+    for coop in (False, True):
+        m, lab, info = kk.kkm_fit(Xd, "rbf", sigma=4.0, C=20, B=10, s=0.1, max_iter=20, seed=78, cooperative=coop)
+        outs.append((lab.cpu().numpy(), kk.kkm_model_export(m)["support"], info["global_medoids"],
+                     info["updates_per_batch"]))
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_fit_rejects_nonfinite_input():
     kk = _kk()
     X, _ = ki.datasets.gaussian_mixture(500, 4, 3, seed=1, sigma=1.0)
