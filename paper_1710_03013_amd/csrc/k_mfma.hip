@@ -187,7 +187,9 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
             // one or two (long) segments: masked sums of the lane's 16 values and its partner's
 #pragma unroll 1
             for (int k = 0; k < nseg; ++k) {
-                const int lo = max(__shfl(o0, k, 64), r0), hi = min(__shfl(o1, k, 64), tile_end);
+                // (k is the same in every lane: a lane read instead of a shuffle)
+                const int lo = max(__builtin_amdgcn_readlane(o0, k), r0);
+                const int hi = min(__builtin_amdgcn_readlane(o1, k), tile_end);
                 float part = 0.0f;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                 part += __shfl_xor(part, 32, 64);
                 if (h == 0 && hi > lo) Dl[(jc + k) * 32 + col] += part;
             }
-            if (nseg > 0) jc += __shfl(o1, nseg - 1, 64) > tile_end ? nseg - 1 : nseg;
+            if (nseg > 0) jc += __builtin_amdgcn_readlane(o1, nseg - 1) > tile_end ? nseg - 1 : nseg;
         } else {
             // short segments: the tile through LDS; lane half h takes every other segment, lane col
             // its sample, each adding its rows in row order
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                     }
                 }
                 // the last counted segment may continue in the next tile
-                if (__shfl(o1, nseg - 1, 64) > tile_end) {
+                if (__builtin_amdgcn_readlane(o1, nseg - 1) > tile_end) {
                     jc += nseg - 1;
                     break;
                 }
