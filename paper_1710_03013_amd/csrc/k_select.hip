@@ -277,17 +277,26 @@ __global__ void set_medoids_kernel(BatchView b, KSpec ks, int C, const int32_t* 
 // re-evaluated in FP64 and the lowest (value, position) is the batch medoid.
 constexpr int kRowsPerBlock = 256;
 
-// Grid (row chunks) x (clusters): member counts per chunk, label scatter, candidate list.  U_j is
-// the minimum of the distance pass's per-block column minima (every block reduces them itself; the
-// minimum is exact in any order).
-template <typename TD>
+// Grid (row chunks) x (clusters): member counts per chunk, label scatter, and the candidates of the
+// block: rows with D - E <= U_j, where U_j is the minimum of the distance pass's per-block column
+// minima (every block reduces them itself; the minimum is exact in any order).  With EVAL the block
+// then evaluates its candidates in FP64,
+//   d(x, j) = K(x,x) - 2 sum_l a_l K(x, s_l) + self_j,
+// a group of lanes per candidate over the segment's support rows, and appends (row, cluster, value)
+// to the candidate list; without it (large grids, where the evaluation's registers would cost
+// occupancy) it appends (row, cluster) and candidate_eval_kernel follows.
+template <typename TD, typename TI, int DP, bool EVAL>
 __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
     const int j = blockIdx.y, chunk = blockIdx.x;
     const int64_t q = (int64_t)chunk * kRowsPerBlock + threadIdx.x;
     const bool active = q < a.b.n;
-    __shared__ int cnt;
+    __shared__ int cnt, ncand, base;
+    __shared__ int32_t cq[kRowsPerBlock];
     __shared__ double umin[kRowsPerBlock / 64];
-    if (threadIdx.x == 0) cnt = 0;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        ncand = 0;
+    }
     double U;
     if (a.colpart_blocks > 0) {
         double v = kInf;
@@ -310,19 +319,48 @@ __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
         if (lab == j) atomicAdd(&cnt, 1);
         const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
         const double D = (double)Dt[q];
-        if (D < kInf && D - (double)a.Erow[q] <= U) {
-            const int pos = atomicAdd(a.cand_count, 1);
-            if (pos < a.cand_cap) {
-                a.cand_q[pos] = (int32_t)q;
-                a.cand_j[pos] = j;
-            }
-        }
+        if (D < kInf && D - (double)a.Erow[q] <= U) cq[atomicAdd(&ncand, 1)] = (int32_t)q;
     }
     __syncthreads();
-    if (threadIdx.x == 0) a.mpart_c[(int64_t)j * a.nchunk + chunk] = cnt;
+    if (threadIdx.x == 0) {
+        a.mpart_c[(int64_t)j * a.nchunk + chunk] = cnt;
+        base = ncand ? atomicAdd(a.cand_count, ncand) : 0;
+    }
+    __syncthreads();
+    if constexpr (!EVAL) {
+        for (int c = threadIdx.x; c < ncand; c += blockDim.x)
+            if (base + c < a.cand_cap) {
+                a.cand_q[base + c] = cq[c];
+                a.cand_j[base + c] = j;
+            }
+        return;
+    }
+    // groups of L lanes per candidate, L the power of two (<= 64) covering the segment, so that
+    // short segments put several candidates on one wavefront
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
+    int L = 64;
+    while (L > 1 && L / 2 >= hi - lo) L >>= 1;
+    const int per_wave = 64 / L, sub = lane / L, sl = lane % L;
+    for (int c0 = wave * per_wave; c0 < ncand; c0 += nwaves * per_wave) {
+        const int c = c0 + sub;
+        const bool ok = c < ncand && base + c < a.cand_cap;   // (beyond the capacity: the list is full)
+        const int64_t qq = ok ? cq[c] : 0;
+        const TI* x = brow<TI>(a.b, qq);
+        double f = 0.0;
+        if (ok)
+            for (int l = lo + sl; l < hi; l += L) f += a.sup.coef64[l] * k64p<DP>(a.ks, x, rows + (int64_t)l * a.sup.dpad);
+        for (int o = L / 2; o >= 1; o >>= 1) f += __shfl_xor(f, o, 64);   // within the lane group
+        if (ok && sl == 0) {
+            a.cand_q[base + c] = (int32_t)qq;
+            a.cand_j[base + c] = j;
+            a.cand_v[base + c] = kself64(a.ks, x) - 2.0 * f + a.sup.self[j];
+        }
+    }
 }
 
-// One wavefront per candidate: d(x, j) = K(x,x) - 2 sum_l a_l K(x, s_l) + self_j in FP64.
+// One wavefront per listed candidate (the large-grid path): d(x, j) as above.
 template <typename TI, int DP>
 __global__ __launch_bounds__(256) void candidate_eval_kernel(SelectArgs a) {
     const int lane = threadIdx.x & 63;
@@ -811,15 +849,22 @@ int merge_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kMergeRows -
 
 kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& dev, hipStream_t s) {
     const dim3 grid(a0.nchunk, a0.C);
-    if (tile_f64) hipLaunchKernelGGL(medoid_candidates_kernel<double>, grid, dim3(256), 0, s, a0);
-    else hipLaunchKernelGGL(medoid_candidates_kernel<float>, grid, dim3(256), 0, s, a0);
-    KKM_HIP(hipGetLastError());
-    const unsigned cand_blocks = (unsigned)std::max(1, 4 * dev.num_cus);
     SelectArgs a = a0;
     const dim3 tgrid(merge_chunks(a.b.n), (a.C + kMergeTJ - 1) / kMergeTJ);
     auto run = [&]<typename TI, int DP>() -> kkm_status {
         a.mchunk = DP == 0 ? a.nchunk : merge_chunks(a.b.n);
-        hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3(cand_blocks), dim3(256), 0, s, a);
+        // candidates evaluated by the blocks that find them when the grid is small; otherwise listed
+        // for a separate pass (the evaluation's registers would halve the large grid's occupancy)
+        const bool fused = (int64_t)grid.x * grid.y <= 2048;
+        if (fused) {
+            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP, true>), grid, dim3(256), 0, s, a);
+        } else {
+            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP, false>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP, false>), grid, dim3(256), 0, s, a);
+            KKM_HIP(hipGetLastError());
+            hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3((unsigned)std::max(1, 4 * dev.num_cus)), dim3(256), 0, s, a);
+        }
         KKM_HIP(hipGetLastError());
         if constexpr (DP == 0) {
             hipLaunchKernelGGL((merge_partial_kernel<TI, DP>), grid, dim3(256), 0, s, a);
