@@ -1,10 +1,11 @@
 // Landmark phase of one mini-batch:
 //
 //   1. the landmark kernel block K_LL = K(x_l, x_m) in FP64 and, for the Eq. 8 initialisation,
-//      K(x_l, m_j) for the global medoids (landmark_k_kernel, 64 x 64 tiles; RMSD frames:
+//      K(x_l, m_j) for the global medoids (landmark_k_kernel, 32 x 32 tiles; RMSD frames:
 //      landmark_block_kernel, 32 x 32 tiles);
-//   2. the initial landmark labels: given, or the nearest global medoid (Eq. 8, with K(m,m))
-//      (landmark_init_from_k_kernel, one wavefront per landmark; RMSD: landmark_init_kernel);
+//   2. the initial landmark labels: given, or the nearest global medoid (Eq. 8, with K(m,m)) --
+//      taken by landmark_k_kernel itself when the medoid columns fit one tile, else by
+//      landmark_init_from_k_kernel (one wavefront per landmark; RMSD: landmark_init_kernel);
 //   3. one kernel for the landmark loop, all workgroups resident (Eq. 14-17 restricted to the
 //      landmarks):
 //        counting sort of the landmarks by label  -> CSR segments L_j, c_j = |L_j|
@@ -19,8 +20,8 @@
 // loop; one pass over the batch from the final centroids reproduces the paper's full loop.
 //
 // Every sum has a fixed order that depends only on the labels (CSR order within a segment, row
-// order, then workgroup order), so results are bitwise repeatable.  Cross-workgroup data is
-// published with a release fence before the grid barrier and read after an acquire fence.
+// order, then workgroup order), so results are bitwise repeatable.  Cross-workgroup data is written
+// and read with device-scope accesses, so the grid barrier needs no cache maintenance.
 #include <cstdlib>
 
 #include "kkm_internal.hpp"
@@ -570,11 +571,15 @@ __global__ __launch_bounds__(256) void landmark_init_from_k_kernel(LandmarkArgs 
 // 3-4. The landmark loop and the centroid support (grid <= device CUs, all workgroups resident).
 //
 // Workgroup wg owns landmark rows [r0, r1): their rows of K (in LDS when they fit) and of S.  Every
-// workgroup keeps all landmark labels and cluster counts.  One update takes two exchanges:
-//   publish the own part of sum_{m in L_j} S[m][j]  -> barrier -> g^ (same order everywhere),
-//   Eq. 15 for the own rows, publish their labels    -> barrier -> all labels, changed list,
-//   own rows of S follow the changes (incrementally in landmark order, or from scratch).
-// A buffer is rewritten only after the barrier that ends every reader's use of it.
+// workgroup keeps all landmark labels, cluster counts and T_j = c_j^2 g^_j.  Before the first update
+// the own parts of sum_{m in L_j} S[m][j] are exchanged (barrier) and summed in the same order
+// everywhere.  An update is then
+//   Eq. 15 for the own rows, publish their labels (and S at the old and new label of a changed row)
+//   -> barrier -> all labels, the changed list, own rows of S follow the changes (incrementally in
+//   landmark order, or from scratch), and T follows either by the pair formula (at most kPairMax
+//   changes, no exchange) or by a new exchange of the partial sums (barrier).
+// The label / S exchange alternates between two halves, and every other buffer is rewritten only
+// after the barrier that ends every reader's use of it.
 // KL: the own rows of K_LL are staged in LDS (else read from HBM); a compile-time choice, so the
 // reads compile to LDS or global instructions rather than generic ones.
 template <typename TI, bool KL>
