@@ -36,6 +36,9 @@ namespace {
 constexpr int kLoopThreads = 1024;
 // Updates that change at most this many landmark labels move g^ by the pair formula (no exchange).
 constexpr int kPairMax = 64;
+// Published labels carry the update that produced them above their low kLabelBits bits (labels are
+// below 1024), so a reader can wait on the label itself instead of a grid barrier.
+constexpr int kLabelBits = 11;
 
 struct LdsLayout {
     double* K;         // [R][ell] own rows of the landmark block (when staged in LDS)
@@ -303,6 +306,7 @@ __device__ __forceinline__ void reset_batch_state(const LandmarkArgs& a) {
     for (int i = threadIdx.x; i <= a.max_updates; i += blockDim.x) a.changed[i] = 0;
     for (int i = threadIdx.x; i < a.n_zero_ints; i += blockDim.x) a.zero_ints[i] = 0;
     for (int i = threadIdx.x; i < a.C; i += blockDim.x) a.colmin[i] = ~0ull;
+    for (int i = threadIdx.x; i < 2 * a.ell; i += blockDim.x) a.nlab_x[i] = 0;   // no update published yet
     if (threadIdx.x == 0) {
         *a.barrier = 0u;   // (the error flag accumulates over the fit: cleared once by the host)
         *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
@@ -697,6 +701,7 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         if (it >= a.max_updates) break;
         int32_t* nlx = a.nlab_x + (int64_t)buf * ell;
         double* sx = a.sx + (int64_t)buf * 2 * ell;
+        const int epoch = it + 1;   // published with the labels of this update
 
         // Eq. 15 for the own rows (one wavefront per row; lowest j among equal minima); a changed row
         // also publishes S at its old and new label (for the pair update of g^)
@@ -716,17 +721,19 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
             }
             if (lane == 0) {
                 const int m = r0 + r, old = L.lbl[m], nl = bj < C ? bj : old;
-                xput(nlx + m, nl);
                 if (nl != old) {
                     xput(sx + 2 * (int64_t)m, L.S[r * C + old]);
                     xput(sx + 2 * (int64_t)m + 1, L.S[r * C + nl]);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_s_waitcnt(0);   // the S values are complete before the label appears
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 }
+                xput(nlx + m, nl | (epoch << kLabelBits));
             }
         }
         stamp(a, ns);
-        grid_barrier(a, target);
-        stamp(a, ns);
-        // new labels and the changed landmarks in index order: every wavefront takes whole 64-landmark
+        // new labels (each lane waits until its landmark's label of this update has appeared: no grid
+        // barrier) and the changed landmarks in index order: every wavefront takes whole 64-landmark
         // chunks (ballot of the changes, mask and count kept in LDS), then writes its chunks' entries
         // after the prefix of the lower chunks' counts
         {
@@ -737,7 +744,18 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 const int m = ch * 64 + lane;
                 bool chg = false;
                 if (m < ell) {
-                    const int nl = xget(nlx + m);
+                    int v = xget(nlx + m);
+                    unsigned polls = 0;
+                    while (((unsigned)v >> kLabelBits) != (unsigned)epoch) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++polls > kSpinCap) {   // bounded: report, keep the old label
+                            atomicOr(a.error, 1);
+                            v = L.lbl[m];
+                            break;
+                        }
+                        v = xget(nlx + m);
+                    }
+                    const int nl = v & ((1 << kLabelBits) - 1);
                     L.nlab[m] = nl;
                     chg = nl != L.lbl[m];
                 }
