@@ -271,19 +271,58 @@ __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
     }
 }
 
-// A whole block per listed row (supports of hundreds of rows and more): up to kRefineChunk support
-// rows per pass (four per thread at a time), then per-cluster sums in row order and a block
-// reduction of best / second best.
+// A whole block per listed row (supports of hundreds of rows and more): 1024 threads, one support
+// row each per pass of up to kRefineChunk rows, so that every row's loads and exponential are in
+// flight at once; then per-cluster sums in row order and a reduction of best / second best
+// (lowest cluster on ties).  For linear / RBF the listed row is staged once in LDS as doubles,
+// zero past d; support rows are read over their padded length DP (the stored row stride) with the
+// dimensions past d masked, which adds fma(0, 0, acc) = acc: the same sum as the FP64 evaluation
+// elsewhere.
 constexpr int kRefineChunk = 2048;
+constexpr int kRefineThreads = 1024;
+
+// K(x, s) in FP64 with x as DP doubles in LDS (zero past d) and s a stored support row of DP values.
+template <int DP, typename TI>
+__device__ __forceinline__ double k64_staged(const KSpec& ks, const double* xs, const TI* __restrict__ s) {
+    const int d = (int)ks.d;
+    constexpr int CH = DP < 16 ? DP : 16;
+    double acc = 0.0;
+    if (ks.type == KKM_KERNEL_LINEAR) {
+#pragma unroll 1
+        for (int c0 = 0; c0 < DP; c0 += CH) {
+            double y[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) y[k] = (double)s[c0 + k];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) acc = fma(xs[c0 + k], c0 + k < d ? y[k] : 0.0, acc);
+        }
+        return acc;
+    }
+#pragma unroll 1
+    for (int c0 = 0; c0 < DP; c0 += CH) {
+        double y[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) y[k] = (double)s[c0 + k];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const double t = c0 + k < d ? xs[c0 + k] - y[k] : 0.0;
+            acc = fma(t, t, acc);
+        }
+    }
+    return ::exp(-acc * ks.inv2s2);
+}
 
 template <typename TI, int DP>
-__global__ __launch_bounds__(256) void refine_block_kernel(DistArgs a) {
+__global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int NW = kRefineThreads / 64;
     const int C = a.sup.C;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     double* Kv = reinterpret_cast<double*>(smem_raw);   // [kRefineChunk]
     double* facc = Kv + kRefineChunk;                     // [C]
-    __shared__ double rb1[256], rb2[256];
-    __shared__ int ri1[256];
+    __shared__ double xs[DP > 0 ? DP : 1];
+    __shared__ double rb1[NW], rb2[NW];
+    __shared__ int ri1[NW];
     const int32_t* off = a.sup.offsets;
     const int64_t ns = off[C];
     const TI* rows = static_cast<const TI*>(a.sup.rows);
@@ -291,69 +330,62 @@ __global__ __launch_bounds__(256) void refine_block_kernel(DistArgs a) {
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         const int64_t q = a.refine_list[i];
         const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
-        for (int j = threadIdx.x; j < C; j += blockDim.x) facc[j] = 0.0;
+        if constexpr (DP > 0) {
+            if (t < DP) xs[t] = t < a.q.d ? (double)xr[t] : 0.0;
+        }
+        for (int j = t; j < C; j += kRefineThreads) facc[j] = 0.0;
         for (int64_t base = 0; base < ns; base += kRefineChunk) {
             const int lim = (int)min<int64_t>(kRefineChunk, ns - base);
             __syncthreads();
-            // four support rows per thread at a time: their loads and exponentials overlap
-            for (int l0 = threadIdx.x; l0 < lim; l0 += 4 * blockDim.x) {
-                double v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int l = l0 + u * (int)blockDim.x;
-                    v[u] = l < lim ? k64p<DP>(a.ks, xr, rows + (base + l) * a.sup.dpad) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int l = l0 + u * (int)blockDim.x;
-                    if (l < lim) Kv[l] = a.sup.coef64[base + l] * v[u];
-                }
+            for (int l = t; l < lim; l += kRefineThreads) {
+                const TI* s = rows + (base + l) * a.sup.dpad;
+                const double cf = a.sup.coef64[base + l];   // loaded with the row
+                double v;
+                if constexpr (DP > 0) v = k64_staged<DP>(a.ks, xs, s);
+                else v = k64(a.ks, xr, s);
+                Kv[l] = cf * v;
             }
             __syncthreads();
-            for (int j = threadIdx.x; j < C; j += blockDim.x) {
+            for (int j = t; j < C; j += kRefineThreads) {
                 const int64_t lo = max<int64_t>(off[j], base), hi = min<int64_t>(off[j + 1], base + lim);
-                double s = facc[j];
+                double sj = facc[j];
 #pragma unroll 8
-                for (int64_t l = lo; l < hi; ++l) s += Kv[l - base];
-                facc[j] = s;
+                for (int64_t l = lo; l < hi; ++l) sj += Kv[l - base];
+                facc[j] = sj;
             }
         }
         __syncthreads();
         const double kqq = kself64(a.ks, xr);
         double b1 = kInf, b2 = kInf;
         int i1 = C;
-        for (int j = threadIdx.x; j < C; j += blockDim.x) {
+        for (int j = t; j < C; j += kRefineThreads) {
             const double g = a.sup.self[j];
             const double D = (off[j + 1] > off[j] && g < kInf) ? kqq - 2.0 * facc[j] + g : kInf;
             if (D < b1) { b2 = b1; b1 = D; i1 = j; }
             else if (D < b2) { b2 = D; }
         }
-        rb1[threadIdx.x] = b1;
-        rb2[threadIdx.x] = b2;
-        ri1[threadIdx.x] = i1;
-        __syncthreads();
-        for (int w = 128; w >= 1; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                const double c1 = rb1[threadIdx.x + w], c2 = rb2[threadIdx.x + w];
-                const int j1 = ri1[threadIdx.x + w];
-                double x1 = rb1[threadIdx.x], x2 = rb2[threadIdx.x];
-                int y1 = ri1[threadIdx.x];
-                if (c1 < x1 || (c1 == x1 && j1 < y1)) {
-                    x2 = fmin(x1, c2);
-                    x1 = c1;
-                    y1 = j1;
-                } else {
-                    x2 = fmin(x2, c1);
-                }
-                rb1[threadIdx.x] = x1;
-                rb2[threadIdx.x] = x2;
-                ri1[threadIdx.x] = y1;
+        auto merge = [](double& x1, double& x2, int& y1, double c1, double c2, int j1) {
+            if (c1 < x1 || (c1 == x1 && j1 < y1)) {
+                x2 = fmin(x1, c2);
+                x1 = c1;
+                y1 = j1;
+            } else {
+                x2 = fmin(x2, c1);
             }
-            __syncthreads();
+        };
+        for (int o = 32; o >= 1; o >>= 1)
+            merge(b1, b2, i1, __shfl_xor(b1, o, 64), __shfl_xor(b2, o, 64), __shfl_xor(i1, o, 64));
+        if (lane == 0) {
+            rb1[wave] = b1;
+            rb2[wave] = b2;
+            ri1[wave] = i1;
         }
-        if (threadIdx.x == 0) {
-            const double v1 = rb1[0], v2 = rb2[0];
-            a.labels[q] = ri1[0] < C ? ri1[0] : 0;
+        __syncthreads();
+        if (t == 0) {
+            double v1 = rb1[0], v2 = rb2[0];
+            int j1 = ri1[0];
+            for (int w = 1; w < NW; ++w) merge(v1, v2, j1, rb1[w], rb2[w], ri1[w]);
+            a.labels[q] = j1 < C ? j1 : 0;
             if (a.best) a.best[q] = v1;
             if (a.gap) {
                 const double scale = fmax(fmax(fabs(v1), fabs(v2)), fabs(kqq));
@@ -454,9 +486,9 @@ kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
     return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
         if (per_block) {
             if (a.dtype == KKM_F64)
-                hipLaunchKernelGGL((refine_block_kernel<double, DP>), dim3(blocks), dim3(256), lds, s, a);
+                hipLaunchKernelGGL((refine_block_kernel<double, DP>), dim3(blocks), dim3(kRefineThreads), lds, s, a);
             else
-                hipLaunchKernelGGL((refine_block_kernel<float, DP>), dim3(blocks), dim3(256), lds, s, a);
+                hipLaunchKernelGGL((refine_block_kernel<float, DP>), dim3(blocks), dim3(kRefineThreads), lds, s, a);
         } else {
             if (a.dtype == KKM_F64)
                 hipLaunchKernelGGL((refine_kernel<double, DP>), dim3(blocks), dim3(256), lds, s, a);

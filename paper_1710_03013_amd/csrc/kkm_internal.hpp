@@ -293,6 +293,8 @@ template <typename TA, typename TB>
 __device__ inline double rmsd_kfun64(const TA* __restrict__ a, const TB* __restrict__ b, int A, double inv2s2) {
     double R[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     double Ga = 0.0, Gb = 0.0;
+    // unrolled so that the loads of several atoms are in flight together (the sums stay in order)
+#pragma unroll 8
     for (int t = 0; t < A; ++t) {
         const double ax = a[3 * t], ay = a[3 * t + 1], az = a[3 * t + 2];
         const double bx = b[3 * t], by = b[3 * t + 1], bz = b[3 * t + 2];
@@ -312,25 +314,31 @@ __device__ inline double k64(const KSpec& ks, const TA* __restrict__ a, const TB
     return kfun64_rows(ks.type, a, b, ks.d, ks.inv2s2);
 }
 
-// K(a, b) in FP64 for rows of length ks.d <= DP (linear / RBF), in chunks of 16 dimensions whose
-// loads are unrolled and guarded, so that each chunk's loads are in flight together while the live
-// registers stay bounded.  DP == 0 (RMSD) falls back to k64.
+// K(a, b) in FP64 for rows of length ks.d <= DP (linear / RBF), in chunks of 16 dimensions.  Every
+// load of a chunk is issued unconditionally (an index past the row end is clamped to its last
+// element and the value masked to zero afterwards), so the chunk's loads are in flight together
+// instead of one branch and one wait per element; the live registers stay bounded by the chunk.
+// Rows of at most 16 dimensions take one chunk and no loop, so that the loads of several calls in a
+// row can be in flight together too.  Masked dimensions add fma(0, 0, acc) = acc exactly, so the
+// sum is the plain one in order.  DP == 0 (RMSD) falls back to k64.
 template <int DP, typename TA, typename TB>
 __device__ __forceinline__ double k64p(const KSpec& ks, const TA* __restrict__ a, const TB* __restrict__ b) {
     if constexpr (DP == 0) {
         return k64(ks, a, b);
     } else {
         constexpr int CH = DP < 16 ? DP : 16;
-        double acc = 0.0;
+        const int d = (int)ks.d;   // 1 <= d <= DP
         const bool lin = ks.type == KKM_KERNEL_LINEAR;
-#pragma unroll 1
-        for (int c0 = 0; c0 < DP; c0 += CH) {
+        double acc = 0.0;
+        auto chunk = [&](int c0) {
             double va[CH], vb[CH];
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const bool in = c0 + k < ks.d;
-                va[k] = in ? (double)a[c0 + k] : 0.0;
-                vb[k] = in ? (double)b[c0 + k] : 0.0;
+                const int i = min(c0 + k, d - 1);
+                const double x = (double)a[i], y = (double)b[i];
+                const bool in = c0 + k < d;
+                va[k] = in ? x : 0.0;
+                vb[k] = in ? y : 0.0;
             }
             if (lin) {
 #pragma unroll
@@ -342,6 +350,12 @@ __device__ __forceinline__ double k64p(const KSpec& ks, const TA* __restrict__ a
                     acc = fma(t, t, acc);
                 }
             }
+        };
+        if constexpr (DP <= 16) {
+            chunk(0);
+        } else {
+#pragma unroll 1
+            for (int c0 = 0; c0 < d; c0 += CH) chunk(c0);
         }
         return lin ? acc : ::exp(-acc * ks.inv2s2);
     }

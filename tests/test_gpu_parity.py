@@ -116,6 +116,39 @@ def test_assign_sparse_centroids():
         assert not np.any(got == 1)
 
 
+@pytest.mark.parametrize("kind,d,dtype", [("rbf", 40, "f32"), ("rbf", 16, "f64"), ("linear", 40, "f32")])
+def test_assign_near_ties_decided_in_fp64(kind, d, dtype):
+    """Cluster 2 repeats cluster 0's rows with coefficients scaled by 1 + 1e-4, so the two are
+    1e-7 to 1e-5 apart (relative) on every row: below the FP32 error bound, so the FP32 pass lists those
+    rows and the FP64 re-decision (a whole workgroup per row, the support being over 256 rows)
+    decides them.  Labels must follow the oracle wherever its margin exceeds 1e-6."""
+    kk = _kk()
+    _say(f"assign near ties {kind} d={d} {dtype}")
+    X, _ = ki.datasets.gaussian_mixture(2300, d, 4, seed=11, sigma=1.0, box=4.0)
+    if kind == "linear":
+        X = X / np.sqrt(d)
+    rng = np.random.default_rng(3)
+    A, Bs, D = X[:200], X[200:300], X[300:400]
+    S = np.concatenate([A, Bs, A, D])
+    offsets = np.array([0, 200, 300, 500, 600])
+    cA = rng.uniform(0.2, 1.0, 200)
+    cA /= cA.sum()
+    cD = rng.uniform(0.2, 1.0, 100)
+    cD /= cD.sum()
+    coef = np.concatenate([cA, np.full(100, 0.01), cA * (1.0 + 1e-4), cD])
+    sigma = 1.5 * np.sqrt(d)
+    kern = Kernel(kind, sigma)
+    m = kk.kkm_model_create(kind, d=d, C=4, max_support=600, dtype=dtype, sigma=sigma)
+    kk.kkm_model_load(m, S, offsets, coef)
+    Y = np.ascontiguousarray(X[400:], dtype=np.float32 if dtype == "f32" else np.float64)
+    rl, rg, _ = okkm.assign(kern, Y.astype(np.float64), okkm.SparseModel(S.astype(np.float64), offsets, coef))
+    near = (rl == 0) | (rl == 2)
+    assert (near & (rg > GAP)).sum() > 50
+    for prec in ("fp32", "bf16x3", "fp64") if dtype == "f32" else ("fp32", "fp64"):
+        lab, _ = kk.kkm_assign(m, torch.from_numpy(Y).cuda(), precision=prec, want_gap=True)
+        _labels_match(lab.cpu().numpy(), rl, rg, f"near ties {kind} d={d} {prec}")
+
+
 # ------------------------------------------------------------------------------------------ fit
 def _fit_both(kk, X, kern, C, B, s, T, init, seed, prec, sampling="stride", dtype=None, **kw):
     N = X.shape[0]
