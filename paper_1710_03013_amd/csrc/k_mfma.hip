@@ -3,9 +3,12 @@
 //   d(x, j) = K(x,x) - 2 sum_{l in segment j} a_l K(x, s_l) + self_j,
 //   K(x, s) = x.s (linear) or exp(-(||x||^2 + ||s||^2 - 2 x.s) / (2 sigma^2)) (RBF).
 //
-// A workgroup owns 32 samples (the N dimension of a 32x32 MFMA tile); each of its four wavefronts
-// walks a cluster-aligned quarter of the support in 32-row tiles (the M dimension) aligned to
-// multiples of 32.  The two lane halves take contiguous halves of the dimensions as their share of
+// A workgroup owns 32 samples (the N dimension of a 32x32 MFMA tile); the support is cut into four
+// cluster-aligned quarters walked in 32-row tiles (the M dimension) aligned to multiples of 32.  With
+// four wavefronts each walks one quarter; with eight, wavefronts w and w + 4 take the first and the
+// second half of quarter w's tiles, each summing into its own copy of the per-cluster sums, which
+// are added (first half + second half) before the decision: twice the wavefronts, half the chain
+// of dependent tiles each.  The two lane halves take contiguous halves of the dimensions as their share of
 // the K index (any order of K gives the same dot product); the support is read from its panel
 // layout, in which each step's fragment is 64 consecutive vectors.  Result lane l holds rows 8(i/4) + 4(l/32) + i%4 of sample l%32 (i = 0..15): the kernel
 // function is applied in registers, and each segment's sum is a masked sum over the lane's 16
@@ -36,21 +39,22 @@ __device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float
     return __builtin_amdgcn_exp2f(-d2 * inv2s2 * 1.4426950408889634f);
 }
 
-template <typename TI, int DP, bool BF3>
-__global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
+template <typename TI, int DP, bool BF3, int NW>
+__global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     constexpr int H = DP / 2;                      // dimensions per lane half
+    constexpr int NH = NW / 4;                     // wavefronts per quarter of the support
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int C = a.sup.C;
-    float* Dl = reinterpret_cast<float*>(smem_raw);   // [C][32]
+    float* Dl = reinterpret_cast<float*>(smem_raw);   // [NH][C][32]; copy 0 ends up holding D
     // segment metadata of the support, read once per workgroup: offsets, self terms, |a| sums
-    double* mself = reinterpret_cast<double*>(smem_raw + sizeof(float) * (size_t)C * 32);   // [C]
+    double* mself = reinterpret_cast<double*>(smem_raw + sizeof(float) * (size_t)NH * C * 32);   // [C]
     double* msegabs = mself + C;                                                             // [C]
     int32_t* off = reinterpret_cast<int32_t*>(msegabs + C);                                 // [C+1]
     __shared__ float Ew[4][32];
     __shared__ float Eg[4][32];
     __shared__ double Bw1[4][32], Bw2[4][32];
     __shared__ int Iw[4][32];
-    __shared__ float Pt[4][32 * 33];
+    __shared__ float Pt[NW][32 * 33];
     __shared__ int jb[5];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -117,13 +121,22 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                 bl[v][t] = (__bf16)(x - (float)hi);
             }
     }
-    const int j0 = jb[wave], j1 = jb[wave + 1];
+    const int quarter = wave & 3, half = wave >> 2;
+    const int j0 = jb[quarter], j1 = jb[quarter + 1];
     const int start = off[j0], end = off[j1];
+    float* Dw = Dl + (size_t)half * C * 32;     // this wavefront's per-cluster sums
     float* P = Pt[wave];                         // [32 rows][33]: one tile of a_l K(x, s_l)
-    for (int p = lane; p < (j1 - j0) * 32; p += 64) Dl[j0 * 32 + p] = 0.0f;
-    wave_sync_lds();
+    for (int p = lane; p < (j1 - j0) * 32; p += 64) Dw[j0 * 32 + p] = 0.0f;
+    // the wavefront's tiles: all of the quarter's, or the first (half 0) or second half of them
+    const int t0 = start & ~31;
+    const int ntiles = end > t0 ? (end - t0 + 31) / 32 : 0;
+    const int tsplit = t0 + 32 * ((ntiles + NH - 1) / NH);
+    const int rbeg = half == 0 ? t0 : tsplit;
+    const int rend = half == NH - 1 ? end : min(end, tsplit);
     int jc = j0;                                 // first segment that may still receive rows
-    for (int r0 = start & ~31; r0 < end; r0 += 32) {
+    while (jc < j1 && off[jc + 1] <= rbeg) ++jc;
+    wave_sync_lds();
+    for (int r0 = rbeg; r0 < rend; r0 += 32) {
         const int tile_end = min(r0 + 32, end);
         // A fragment: support row r0 + col, the lane half's dimensions, read from the panel of the
         // tile (64 consecutive vectors per step group)
@@ -197,7 +210,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                     part += (row >= lo && row < hi) ? v[i] : 0.0f;
                 }
                 part += __shfl_xor(part, 32, 64);
-                if (h == 0 && hi > lo) Dl[(jc + k) * 32 + col] += part;
+                if (h == 0 && hi > lo) Dw[(jc + k) * 32 + col] += part;
             }
             if (nseg > 0) jc += __builtin_amdgcn_readlane(o1, nseg - 1) > tile_end ? nseg - 1 : nseg;
         } else {
@@ -216,7 +229,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
                         const int lo = max(lo_k, r0), hi = min(hi_k, tile_end);
                         float part = 0.0f;
                         for (int r = lo; r < hi; ++r) part += P[(r - r0) * 33 + col];
-                        if (hi > lo) Dl[(jc + k) * 32 + col] += part;
+                        if (hi > lo) Dw[(jc + k) * 32 + col] += part;
                     }
                 }
                 // the last counted segment may continue in the next tile
@@ -242,15 +255,18 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     // f_j alone (K(x,x) is common to the row and cancels in every difference): ef bounds |f_j - exact|.
     // The stored FP32 distances carry in addition their rounding and, for the linear kernel, the
     // error of the FP32 norm (row bound Ecol, used by the medoid candidates).
+    // (with eight wavefronts the first four decide: the two halves' sums are complete here)
+    if constexpr (NH > 1) __syncthreads();
     float egap = 0.0f, ecol = 0.0f;
     double b1 = kInf, b2 = kInf;
     int i1 = C;
     const float dot_rel = BF3 ? kUbf + (3.0f * DP + 2.0f) * kU32 : (DP + 2.0f) * kU32;
     const float kmax = sqrtf(qn * snmax) * 1.0001f;
-    for (int jj = j0 + h; jj < j1; jj += 2) {
+    for (int jj = j0 + h; half == 0 && jj < j1; jj += 2) {
         const int lo = off[jj], hi = off[jj + 1];
         const double g = mself[jj];
-        const float accf = Dl[jj * 32 + col];
+        float accf = Dl[jj * 32 + col];
+        if constexpr (NH > 1) accf += Dl[(size_t)C * 32 + jj * 32 + col];
         double D64 = kInf;
         float D = __builtin_huge_valf();
         if (hi > lo && g < kInf) {
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
         egap = fmaxf(egap, __shfl_xor(egap, 32, 64));
         ecol = fmaxf(ecol, __shfl_xor(ecol, 32, 64));
     }
-    if (h == 0) {
+    if (h == 0 && half == 0) {
         Ew[wave][col] = ecol;
         Eg[wave][col] = egap;
         Bw1[wave][col] = b1;
@@ -330,7 +346,7 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     if (wave == 0) append_rows(need, q, a.refine_count, a.refine_list);
     if (a.Dt) {
         float* Dt = a.Dt;
-        for (int jj = wave; jj < C; jj += 4) {
+        for (int jj = wave; jj < C; jj += NW) {
             const float D = Dl[jj * 32 + col];
             if (active && h == 0) Dt[(int64_t)jj * a.ldD + q] = D;
             if (a.colmin) {
@@ -345,34 +361,53 @@ __global__ __launch_bounds__(256) void mfma_dist_kernel(DistArgs a) {
     }   // groups
 }
 
-template <typename TI, bool BF3>
-kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
-    const size_t C = (size_t)a.sup.C;
-    const size_t lds = sizeof(float) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
-    const size_t lds_static = sizeof(float) * (4 * 32 * 33 + 4 * 32 * 3) + sizeof(double) * 4 * 32 * 2 + 64;
-    if (lds + lds_static > dev.max_lds_per_block)
-        return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
-    // 32 samples per group; at most 8 workgroups per CU, each looping over groups
-    const int64_t groups = (a.q.n + 31) / 32;
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
+size_t mfma_lds_dynamic(size_t C, int nw) {
+    return sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
+}
+size_t mfma_lds_static(int nw) {
+    return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 + 64;
+}
+
+template <typename TI, bool BF3, int NW>
+kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsigned blocks) {
+    const size_t lds = mfma_lds_dynamic((size_t)a.sup.C, NW);
     auto go = [&](auto fn) -> kkm_status {
         KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
-        if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
-        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(NW * 64), lds, s, a);
         KKM_HIP(hipGetLastError());
-        if (a.colmin && a.colpart_blocks) *a.colpart_blocks = groups;
         return KKM_OK;
     };
     switch (a.sup.dpad) {
-        case 4: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 4, false>); break;
-        case 8: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 8, false>); break;
-        case 16: return go(mfma_dist_kernel<TI, 16, BF3>);
-        case 32: return go(mfma_dist_kernel<TI, 32, BF3>);
-        case 64: return go(mfma_dist_kernel<TI, 64, BF3>);
-        case 128: return go(mfma_dist_kernel<TI, 128, BF3>);
+        case 4: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 4, false, NW>); break;
+        case 8: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 8, false, NW>); break;
+        case 16: return go(mfma_dist_kernel<TI, 16, BF3, NW>);
+        case 32: return go(mfma_dist_kernel<TI, 32, BF3, NW>);
+        case 64: return go(mfma_dist_kernel<TI, 64, BF3, NW>);
+        case 128: return go(mfma_dist_kernel<TI, 128, BF3, NW>);
         default: break;
     }
     return fail(KKM_ERR_UNSUPPORTED, "matrix-core distance pass: unsupported padded dimension");
+}
+
+template <typename TI, bool BF3>
+kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    const size_t C = (size_t)a.sup.C;
+    if (mfma_lds_dynamic(C, 4) + mfma_lds_static(4) > dev.max_lds_per_block)
+        return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
+    // 32 samples per group; a bounded grid of workgroups, each looping over groups
+    const int64_t groups = (a.q.n + 31) / 32;
+    // Eight wavefronts per workgroup when four would leave the SIMDs under two wavefronts each
+    // (few groups: the pass is bound by each wavefront's chain of tiles), where their LDS fits;
+    // otherwise four, which duplicate less per-group work.
+    const bool eight = groups < 2 * (int64_t)dev.num_cus &&
+                       mfma_lds_dynamic(C, 8) + mfma_lds_static(8) <= dev.max_lds_per_block;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
+    if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
+    const kkm_status st = eight ? launch_mfma_nw<TI, BF3, 8>(a, s, groups, blocks)
+                                : launch_mfma_nw<TI, BF3, 4>(a, s, groups, blocks);
+    if (st != KKM_OK) return st;
+    if (a.colmin && a.colpart_blocks) *a.colpart_blocks = groups;
+    return KKM_OK;
 }
 
 }  // namespace
