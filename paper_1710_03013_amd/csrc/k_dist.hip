@@ -25,6 +25,7 @@ constexpr float kU32 = 5.9604645e-8f;  // unit roundoff of float
 template <typename TI, typename TC, int DP>
 struct EvalDot {
     static constexpr bool kPerLaneRows = false;
+    static constexpr bool kStaged = false;
     TC x[DP];
     TC qn, kqq;
     const TI* rows;
@@ -94,6 +95,7 @@ struct EvalDot {
 template <typename TI>
 struct EvalGeneric64 {
     static constexpr bool kPerLaneRows = true;
+    static constexpr bool kStaged = false;
     const TI* xr;
     const TI* rows;
     int64_t dpad;
@@ -114,9 +116,70 @@ struct EvalGeneric64 {
     __device__ __forceinline__ float bound(int, float, float, float) const { return 0.0f; }
 };
 
+// RMSD in FP64 with the workgroup's sample rows staged in LDS as TS, coordinate-major ([3A][QT]:
+// the lanes reading one coordinate of their samples touch consecutive words), so that an
+// evaluation reads only its support row from memory.  The sums are those of the FP64 RMSD kernel
+// function, term for term in the same order (staging converts nothing that the reads would not).
+template <typename TI, typename TS>
+struct EvalRmsd64 {
+    static constexpr bool kPerLaneRows = true;
+    static constexpr bool kStaged = true;
+    const TS* xs;     // the lane's sample: coordinate k at xs[k * qt]
+    int qt;
+    const TI* rows;
+    int64_t dpad;
+    int A;
+    double inv2s2, Ga, kqq;
+
+    // all threads of the workgroup: rows q0 .. q0 + QT - 1 (the last row repeated past the end)
+    __device__ static void stage(const DistArgs& a, TS* st, int QT, int64_t q0) {
+        const int D3 = (int)a.q.d;
+        const TI* X = static_cast<const TI*>(a.q.X);
+        for (int e = threadIdx.x; e < QT * D3; e += blockDim.x) {
+            const int sm = e / D3, k = e - sm * D3;
+            const int64_t qs = min<int64_t>(q0 + sm, a.q.n - 1);
+            st[k * QT + sm] = (TS)X[(a.q.base + qs * a.q.stride) * a.q.d + k];
+        }
+    }
+    __device__ bool load(const DistArgs& a, int64_t q) {
+        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        bool ok = true;
+        for (int64_t k = 0; k < a.q.d; ++k) ok = ok && isfinite((double)xr[k]);
+        A = a.ks.n_atoms;
+        double g = 0.0;
+        for (int t = 0; t < A; ++t) {
+            const double ax = xr[3 * t], ay = xr[3 * t + 1], az = xr[3 * t + 2];
+            g = fma(ax, ax, fma(ay, ay, fma(az, az, g)));
+        }
+        Ga = g;
+        kqq = kself64(a.ks, xr);
+        rows = static_cast<const TI*>(a.sup.rows);
+        dpad = a.sup.dpad;
+        inv2s2 = a.ks.inv2s2;
+        return ok;
+    }
+    __device__ __forceinline__ double eval(int l) const {
+        const TI* b = rows + (int64_t)l * dpad;
+        double R[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double Gb = 0.0;
+#pragma unroll 8
+        for (int t = 0; t < A; ++t) {
+            const double ax = xs[(3 * t) * qt], ay = xs[(3 * t + 1) * qt], az = xs[(3 * t + 2) * qt];
+            const double bx = b[3 * t], by = b[3 * t + 1], bz = b[3 * t + 2];
+            R[0] = fma(ax, bx, R[0]); R[1] = fma(ax, by, R[1]); R[2] = fma(ax, bz, R[2]);
+            R[3] = fma(ay, bx, R[3]); R[4] = fma(ay, by, R[4]); R[5] = fma(ay, bz, R[5]);
+            R[6] = fma(az, bx, R[6]); R[7] = fma(az, by, R[7]); R[8] = fma(az, bz, R[8]);
+            Gb = fma(bx, bx, fma(by, by, fma(bz, bz, Gb)));
+        }
+        return ::exp(-rmsd2_from_corr64(R, Ga, Gb, A) * inv2s2);
+    }
+    __device__ __forceinline__ float bound(int, float, float, float) const { return 0.0f; }
+};
+
 template <typename T> struct TcOf;
 template <typename TI, typename TC, int DP> struct TcOf<EvalDot<TI, TC, DP>> { using type = TC; };
 template <typename TI> struct TcOf<EvalGeneric64<TI>> { using type = double; };
+template <typename TI, typename TS> struct TcOf<EvalRmsd64<TI, TS>> { using type = double; };
 
 // ----------------------------------------------------------------------------- tile kernel
 // LPQ lanes per sample: a workgroup owns QT = 64 / LPQ samples; lane (ql, part) takes the support
@@ -139,6 +202,13 @@ __global__ __launch_bounds__(256) void dist_kernel(DistArgs a) {
 
     if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
     Ev ev;
+    if constexpr (Ev::kStaged) {   // the tile's rows into LDS after Dl (ordered by the barrier below)
+        auto* st = reinterpret_cast<std::remove_const_t<std::remove_pointer_t<decltype(ev.xs)>>*>(
+            smem_raw + sizeof(TC) * (size_t)C * QT);
+        Ev::stage(a, st, QT, (int64_t)blockIdx.x * QT);
+        ev.xs = st + ql;
+        ev.qt = QT;
+    }
     const bool ok = ev.load(a, active ? q : 0);
     if (active && part == 0 && !ok) atomicOr(a.nonfinite, 1);
     __syncthreads();
@@ -417,7 +487,8 @@ template <class Ev, int LPQ>
 kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     using TC = typename TcOf<Ev>::type;
     constexpr int QT = 64 / LPQ;
-    const size_t lds = sizeof(TC) * (size_t)a.sup.C * QT;
+    size_t lds = sizeof(TC) * (size_t)a.sup.C * QT;
+    if constexpr (Ev::kStaged) lds += sizeof(*Ev{}.xs) * (size_t)QT * a.q.d;
     if (lds > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile (C=" + std::to_string(a.sup.C) + ")");
     const void* fn = reinterpret_cast<const void*>(&dist_kernel<Ev, LPQ>);
@@ -432,17 +503,34 @@ kkm_status launch_dist_lpq(const DistArgs& a, const DeviceInfo& dev, hipStream_t
 
 // Lanes per sample: more when there are few 64-sample tiles for the device and the segments are
 // long enough to split.
-template <class Ev>
-kkm_status launch_dist_ev(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+int dist_lpq(const DistArgs& a, const DeviceInfo& dev, bool per_lane_rows) {
     const int64_t tiles = (a.q.n + 63) / 64;
     const double seg = (double)a.n_support / std::max(1, a.sup.C);
-    int lpq = 1;
-    // only the evaluator that reads support rows per lane gains: the register-row evaluator streams
+    // only the evaluators that read support rows per lane gain: the register-row evaluator streams
     // wave-uniform support rows through the scalar cache, which split lanes would turn into gathers
-    if (Ev::kPerLaneRows && tiles < 2 * (int64_t)dev.num_cus && seg >= 2.0) lpq = seg >= 6.0 ? 4 : 2;
+    if (per_lane_rows && tiles < 2 * (int64_t)dev.num_cus && seg >= 2.0) return seg >= 6.0 ? 4 : 2;
+    return 1;
+}
+
+template <class Ev>
+kkm_status launch_dist_ev(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    const int lpq = dist_lpq(a, dev, Ev::kPerLaneRows);
     if (lpq == 4) return launch_dist_lpq<Ev, 4>(a, dev, s);
     if (lpq == 2) return launch_dist_lpq<Ev, 2>(a, dev, s);
     return launch_dist_lpq<Ev, 1>(a, dev, s);
+}
+
+// RMSD: the sample tile staged in LDS as doubles when the workgroup's LDS stays within 64 KB (two
+// or more workgroups per CU), else as floats (float input only), else read from memory per lane.
+template <typename TI>
+kkm_status launch_dist_rmsd(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    const size_t QT = 64 / (size_t)dist_lpq(a, dev, true);
+    const size_t base = sizeof(double) * (size_t)a.sup.C * QT, cap = 64 * 1024;
+    if (base + sizeof(double) * QT * (size_t)a.q.d <= cap) return launch_dist_ev<EvalRmsd64<TI, double>>(a, dev, s);
+    if constexpr (std::is_same_v<TI, float>) {
+        if (base + sizeof(float) * QT * (size_t)a.q.d <= cap) return launch_dist_ev<EvalRmsd64<TI, float>>(a, dev, s);
+    }
+    return launch_dist_ev<EvalGeneric64<TI>>(a, dev, s);
 }
 
 template <typename TI, typename TC>
@@ -468,6 +556,7 @@ kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) 
     if (a.q.n <= 0) return KKM_OK;
     if (mfma_dist_applies(a)) return launch_dist_mfma(a, dev, s);
     const bool f64 = a.dtype == KKM_F64;
+    if (a.ks.type == KKM_KERNEL_RMSD) return f64 ? launch_dist_rmsd<double>(a, dev, s) : launch_dist_rmsd<float>(a, dev, s);
     if (dist_is_fp64(a)) {
         return f64 ? launch_dist_ev<EvalGeneric64<double>>(a, dev, s) : launch_dist_ev<EvalGeneric64<float>>(a, dev, s);
     }

@@ -36,6 +36,7 @@ namespace {
 constexpr int kLoopThreads = 1024;
 // Updates that change at most this many landmark labels move g^ by the pair formula (no exchange).
 constexpr int kPairMax = 64;
+constexpr int kPairPerWave = (kPairMax + kLoopThreads / 64 - 1) / (kLoopThreads / 64);   // changes per wavefront
 // Published labels carry the update that produced them above their low kLabelBits bits (labels are
 // below 1024), so a reader can wait on the label itself instead of a grid barrier.
 constexpr int kLabelBits = 11;
@@ -736,10 +737,15 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         // barrier) and the changed landmarks in index order: every wavefront takes whole 64-landmark
         // chunks (ballot of the changes, mask and count kept in LDS), then writes its chunks' entries
         // after the prefix of the lower chunks' counts
+        // With one chunk per wavefront, a lane that sees its landmark change loads the S values
+        // published with the label right away (they are complete before the label appears), so
+        // their loads overlap the other wavefronts' waits; the pair update then finds them in LDS.
+        const bool pre_sx = (ell + 63) / 64 <= nwaves;
         {
             const int nchunks = (ell + 63) / 64;
             uint64_t* cmask = L.cmask;
             int32_t* ccnt = L.ccnt;
+            double sa = 0.0, sb = 0.0;
             for (int ch = wave; ch < nchunks; ch += nwaves) {
                 const int m = ch * 64 + lane;
                 bool chg = false;
@@ -758,6 +764,10 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                     const int nl = v & ((1 << kLabelBits) - 1);
                     L.nlab[m] = nl;
                     chg = nl != L.lbl[m];
+                    if (chg && pre_sx) {
+                        sa = xget(sx + 2 * (int64_t)m);
+                        sb = xget(sx + 2 * (int64_t)m + 1);
+                    }
                 }
                 const uint64_t mask = __ballot(chg);
                 if (lane == 0) {
@@ -773,7 +783,12 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 if ((mask >> lane) & 1ull) {
                     const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    L.chg[base_out + below] = ch * 64 + lane;
+                    const int pos = base_out + below;
+                    L.chg[pos] = ch * 64 + lane;
+                    if (pre_sx && pos < kPairMax) {
+                        L.psa[pos] = sa;
+                        L.psb[pos] = sb;
+                    }
                 }
                 if (ch == nchunks - 1 && lane == 0) L.chg[ell] = base_out + ccnt[ch];
             }
@@ -790,24 +805,38 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         // (every workgroup evaluates it in the same order, so T stays identical everywhere)
         const bool pair = nch <= kPairMax;
         if (pair) {
+            // K between the changed landmarks, loaded first so that these loads and the loads of the
+            // published S values below (when not loaded already) are in flight together: wavefront w takes the changes
+            // t = w + u * nwaves (u < kPairPerWave covers kPairMax with kLoopThreads threads), lane t'
+            // the change t'
+            double kv[kPairPerWave];
+#pragma unroll
+            for (int u = 0; u < kPairPerWave; ++u) {
+                const int t = wave + u * nwaves;
+                kv[u] = (t < nch && lane < nch) ? a.Kbuf[(int64_t)L.chg[t] * ldk + L.chg[lane]] : 0.0;
+            }
             for (int t = tid; t < nch; t += nt) {
                 const int m = L.chg[t];
                 L.pab[t] = L.lbl[m] | (L.nlab[m] << 16);
-                L.psa[t] = xget(sx + 2 * (int64_t)m);
-                L.psb[t] = xget(sx + 2 * (int64_t)m + 1);
+                if (!pre_sx) {
+                    L.psa[t] = xget(sx + 2 * (int64_t)m);
+                    L.psb[t] = xget(sx + 2 * (int64_t)m + 1);
+                }
             }
             __syncthreads();
             // one wavefront per change t, lanes over the changes t'
-            for (int t = wave; t < nch; t += nwaves) {
-                const int mt = L.chg[t], abt = L.pab[t];
+#pragma unroll
+            for (int u = 0; u < kPairPerWave; ++u) {
+                const int t = wave + u * nwaves;
+                if (t >= nch) break;   // the same in every lane of the wavefront
+                const int abt = L.pab[t];
                 const int at = abt & 0xffff, bt = abt >> 16;
                 double wa = 0.0, wb = 0.0;
                 if (lane < nch) {
                     const int ab2 = L.pab[lane];
                     const int a2 = ab2 & 0xffff, b2 = ab2 >> 16;
-                    const double kv = a.Kbuf[(int64_t)mt * ldk + L.chg[lane]];
-                    wa = (double)((b2 == at) - (a2 == at)) * kv;
-                    wb = (double)((b2 == bt) - (a2 == bt)) * kv;
+                    wa = (double)((b2 == at) - (a2 == at)) * kv[u];
+                    wb = (double)((b2 == bt) - (a2 == bt)) * kv[u];
                 }
                 wa = wave_sum(wa);
                 wb = wave_sum(wb);
