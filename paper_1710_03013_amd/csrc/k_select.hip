@@ -452,20 +452,11 @@ constexpr int kMergeTJ = 16;
 constexpr int kMergeRows = 64;
 constexpr int kMergeXs = kMergeRows + 4;   // LDS row stride of the staged chunk
 
-template <typename TI, int DP>
-__global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
-    constexpr int NT = 2 * kMergeTJ;
-    constexpr int CH = DP < 16 ? DP : 16;
-    __shared__ double Ts[DP][NT];
-    __shared__ TI Xs[CH][kMergeXs];
-    __shared__ unsigned long long cmin[kMergeTJ];
-    __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
-    __shared__ double calpha[kMergeTJ];
-    const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
-    const int d = a.b.d;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // settle the block's clusters (the same result as one block reducing each cluster)
+// Settles clusters j0 .. j0 + kMergeTJ - 1 into LDS (all threads of the block): batch medoid cmed
+// (-1 when empty), alpha calpha (0 when the cluster takes no merge step); record: also writes
+// counts[j] and bmed[j].
+__device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned long long* cmin, int32_t* cpos,
+                             int32_t* cmem, int32_t* cmed, double* calpha) {
     if (threadIdx.x < kMergeTJ) {
         cmin[threadIdx.x] = ~0ull;
         cpos[threadIdx.x] = INT32_MAX;
@@ -501,12 +492,50 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
         const bool on = alpha > 0.0 && med >= 0;
         cmed[threadIdx.x] = med;
         calpha[threadIdx.x] = on ? alpha : 0.0;
-        if (chunk == 0) {
+        if (record) {
             a.counts[j] = mem;
             a.bmed[j] = med;
         }
     }
     __syncthreads();
+}
+
+// Large merge grids: the clusters are settled once, a block per kMergeTJ clusters, instead of by
+// every row chunk (whose repeated reads of the candidate list would dominate the merge).
+__global__ __launch_bounds__(256) void merge_settle_kernel(SelectArgs a) {
+    __shared__ unsigned long long cmin[kMergeTJ];
+    __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
+    __shared__ double calpha[kMergeTJ];
+    merge_settle(a, blockIdx.x * kMergeTJ, true, cmin, cpos, cmem, cmed, calpha);
+}
+
+// SETTLED: the clusters were settled by merge_settle_kernel (read back from counts / bmed).
+template <typename TI, int DP, bool SETTLED>
+__global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
+    constexpr int NT = 2 * kMergeTJ;
+    constexpr int CH = DP < 16 ? DP : 16;
+    __shared__ double Ts[DP][NT];
+    __shared__ TI Xs[CH][kMergeXs];
+    __shared__ unsigned long long cmin[kMergeTJ];
+    __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
+    __shared__ double calpha[kMergeTJ];
+    const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
+    const int d = a.b.d;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (SETTLED) {
+        if (threadIdx.x < kMergeTJ && j0 + (int)threadIdx.x < a.C) {
+            const int j = j0 + threadIdx.x;
+            const int32_t med = a.bmed[j];
+            const double alpha = merge_alpha(a.counts[j], a.wcount[j]);
+            cmed[threadIdx.x] = med;
+            calpha[threadIdx.x] = alpha > 0.0 && med >= 0 ? alpha : 0.0;
+        }
+        __syncthreads();
+    } else {
+        // settle the block's clusters (the same result as one block reducing each cluster)
+        merge_settle(a, j0, chunk == 0, cmin, cpos, cmem, cmed, calpha);
+    }
     // targets, dimension-major: t = 2 (j - j0) is m_j^i, t + 1 is m_j (zero when unused)
     for (int p = threadIdx.x; p < DP * NT; p += blockDim.x) {
         const int k = p / NT, t = p - k * NT;
@@ -869,7 +898,14 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
         if constexpr (DP == 0) {
             hipLaunchKernelGGL((merge_partial_kernel<TI, DP>), grid, dim3(256), 0, s, a);
         } else {
-            hipLaunchKernelGGL((merge_tile_kernel<TI, DP>), tgrid, dim3(256), 0, s, a);
+            // (more than 1024 tile blocks: settle the clusters once first)
+            if ((int64_t)tgrid.x * tgrid.y > 1024) {
+                hipLaunchKernelGGL(merge_settle_kernel, dim3(tgrid.y), dim3(256), 0, s, a);
+                KKM_HIP(hipGetLastError());
+                hipLaunchKernelGGL((merge_tile_kernel<TI, DP, true>), tgrid, dim3(256), 0, s, a);
+            } else {
+                hipLaunchKernelGGL((merge_tile_kernel<TI, DP, false>), tgrid, dim3(256), 0, s, a);
+            }
         }
         KKM_HIP(hipGetLastError());
         hipLaunchKernelGGL(merge_final_kernel<TI>, dim3(a.C), dim3(64), 0, s, a);
