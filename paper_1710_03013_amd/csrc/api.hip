@@ -518,9 +518,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     tm.s = s;
     tm.device = dev.device;
 
-    KKM_TRY(launch_zero_i32(w.refine_counts, P.B, s));
-    KKM_TRY(launch_zero_i32(w.flags, 2, s));
-    KKM_TRY(launch_zero_i32(w.lm_error, 1, s));
+    // refine counts, flags, update counts and the loop's error word: one range of the status block
+    KKM_TRY(launch_zero_i32(w.refine_counts, (w.lm_error + 1) - w.refine_counts, s));
     // one host-to-device copy of the inputs block: [landmarks, initial labels, uniforms, medoids]
     // (the staging vector outlives the copy: it is released after the final synchronisation)
     std::vector<char> up;

@@ -341,14 +341,35 @@ __global__ __launch_bounds__(256) void landmark_block_kernel(LandmarkArgs a, int
     if (blockIdx.x == 0 && blockIdx.y == 0) reset_batch_state(a);
     double* A = reinterpret_cast<double*>(smem);          // [32][d]
     double* Bm = A + 32 * a.d;                             // [32][d]
+    __shared__ int64_t rowa[32], rowb[32];                 // element offsets of the tile's rows
     const int r0 = tr * 32, c0 = tc * 32;
     const TI* X = static_cast<const TI*>(a.X);
-    for (int64_t i = threadIdx.x; i < 32 * a.d; i += blockDim.x) {
-        const int r = (int)(i / a.d);
-        const int64_t c = i % a.d;
-        const int ra = min(ell - 1, r0 + r), rb = min(ell - 1, c0 + r);
-        A[i] = (double)X[(a.base + (int64_t)a.lm[ra] * a.stride) * a.d + c];
-        Bm[i] = (double)X[(a.base + (int64_t)a.lm[rb] * a.stride) * a.d + c];
+    if (threadIdx.x < 32) {
+        const int ra = min(ell - 1, r0 + (int)threadIdx.x), rb = min(ell - 1, c0 + (int)threadIdx.x);
+        rowa[threadIdx.x] = (a.base + (int64_t)a.lm[ra] * a.stride) * a.d;
+        rowb[threadIdx.x] = (a.base + (int64_t)a.lm[rb] * a.stride) * a.d;
+    }
+    __syncthreads();
+    // four elements per thread at a time: their loads are issued before the LDS stores
+    const int64_t nel = 32 * a.d;
+    for (int64_t i0 = threadIdx.x; i0 < nel; i0 += 4 * (int64_t)blockDim.x) {
+        double va[4], vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = min(i0 + u * (int64_t)blockDim.x, nel - 1);
+            const int r = (int)(i / a.d);
+            const int64_t c = i - (int64_t)r * a.d;
+            va[u] = (double)X[rowa[r] + c];
+            vb[u] = (double)X[rowb[r] + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * (int64_t)blockDim.x;
+            if (i < nel) {
+                A[i] = va[u];
+                Bm[i] = vb[u];
+            }
+        }
     }
     __syncthreads();
     const KSpec ks{a.ktype, a.n_atoms, a.d, a.inv2s2};
@@ -449,25 +470,44 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     // the row starts are resolved once, and each stage issues all its loads before the LDS stores
     constexpr int PER = T * CH / 256;
     static_assert(PER * 256 == T * CH, "staging covers the tile exactly");
+    // The tile's row starts are resolved once into LDS (one index load per thread, all in flight
+    // together); every element load is then issued unconditionally -- rows past the tile are clamped
+    // to a real row and dimensions past d to the last one, the values scaled by a 0 / 1 mask -- so
+    // the loads of a stage are in flight together instead of one branch and one wait each.  (Scaling
+    // by 1 keeps every value bit for bit; masked entries add exact zeros.)
+    __shared__ const TI* rowp[2][T];
+    __shared__ float rowok[2][T];
+    if (threadIdx.x < 2 * T) {
+        const int side = threadIdx.x / T, t = threadIdx.x - side * T;
+        const int g = (side == 0 ? r0 : c0) + t;
+        const bool cm = side == 1 && g >= mc0 && g < ncol;
+        rowp[side][t] = cm ? M + (int64_t)(g - mc0) * a.Mpad : X + (int64_t)a.lm[min(g, ell - 1)] * rs;
+        rowok[side][t] = (g < ell || cm) ? 1.0f : 0.0f;
+    }
+    __syncthreads();
     const TI* pa[PER];
     const TI* pb[PER];
     int kk[PER];
+    double ma[PER], mb[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int p = threadIdx.x + 256 * u;
         const int rr = p / CH;
         kk[u] = p - rr * CH;
-        const int r = r0 + rr, c = c0 + rr;
-        pa[u] = r < ell ? X + (int64_t)a.lm[r] * rs : nullptr;
-        pb[u] = c < ell ? X + (int64_t)a.lm[c] * rs : (c >= mc0 && c < ncol ? M + (int64_t)(c - mc0) * a.Mpad : nullptr);
+        pa[u] = rowp[0][rr];
+        pb[u] = rowp[1][rr];
+        ma[u] = rowok[0][rr];
+        mb[u] = rowok[1][rr];
     }
     for (int k0 = 0; k0 < DP; k0 += CH) {
         double va[PER], vb[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int dim = k0 + kk[u];
-            va[u] = (pa[u] && dim < d) ? (double)pa[u][dim] : 0.0;
-            vb[u] = (pb[u] && dim < d) ? (double)pb[u][dim] : 0.0;
+            const int dc = min(dim, d - 1);
+            const double in = dim < d ? 1.0 : 0.0;
+            va[u] = (double)pa[u][dc] * (ma[u] * in);
+            vb[u] = (double)pb[u][dc] * (mb[u] * in);
         }
         __syncthreads();
 #pragma unroll
