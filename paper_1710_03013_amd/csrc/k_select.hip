@@ -787,25 +787,39 @@ __global__ __launch_bounds__(256) void model_self_kernel(kkm_model m, KSpec ks) 
     if (threadIdx.x == 0) m.segabs[j] = red[0];
 }
 
+// One wavefront per frame (four per workgroup, grid-stride): lane l reads elements l, l + 64, ...
+// of the frame's 3A coordinates (coalesced), whose axis is (l + k) mod 3 at step k since 64 = 1
+// mod 3; the three sums are reduced by a fixed butterfly, and the centred frame is written from a
+// second, cached read.
 template <typename TI>
 __global__ __launch_bounds__(256) void centre_kernel(const TI* __restrict__ X, TI* __restrict__ Y, int64_t n, int A) {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n) return;
-    const TI* x = X + f * 3 * A;
-    TI* y = Y + f * 3 * A;
-    double cx = 0.0, cy = 0.0, cz = 0.0;
-    for (int a = 0; a < A; ++a) {
-        cx += (double)x[3 * a];
-        cy += (double)x[3 * a + 1];
-        cz += (double)x[3 * a + 2];
-    }
-    cx /= A;
-    cy /= A;
-    cz /= A;
-    for (int a = 0; a < A; ++a) {
-        y[3 * a] = (TI)((double)x[3 * a] - cx);
-        y[3 * a + 1] = (TI)((double)x[3 * a + 1] - cy);
-        y[3 * a + 2] = (TI)((double)x[3 * a + 2] - cz);
+    const int lane = threadIdx.x & 63;
+    const int64_t D = 3 * (int64_t)A;
+    for (int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); f < n; f += (int64_t)gridDim.x * 4) {
+        const TI* x = X + f * D;
+        TI* y = Y + f * D;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        int axis = lane % 3;
+        for (int64_t e = lane; e < D; e += 64) {
+            const double v = (double)x[e];
+            sx += axis == 0 ? v : 0.0;
+            sy += axis == 1 ? v : 0.0;
+            sz += axis == 2 ? v : 0.0;
+            axis = axis == 2 ? 0 : axis + 1;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            sx += __shfl_xor(sx, o, 64);
+            sy += __shfl_xor(sy, o, 64);
+            sz += __shfl_xor(sz, o, 64);
+        }
+        const double cx = sx / A, cy = sy / A, cz = sz / A;
+        axis = lane % 3;
+        for (int64_t e = lane; e < D; e += 64) {
+            const double c = axis == 0 ? cx : (axis == 1 ? cy : cz);
+            y[e] = (TI)((double)x[e] - c);
+            axis = axis == 2 ? 0 : axis + 1;
+        }
     }
 }
 
@@ -949,11 +963,13 @@ kkm_status launch_model_prepare(kkm_model* m, hipStream_t s) {
 
 kkm_status launch_centre(const void* X, void* Y, int64_t n, int A, int dtype, hipStream_t s) {
     if (n <= 0) return KKM_OK;
+    // four frames per workgroup; at most 64K workgroups, each looping over frames
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
     if (dtype == KKM_F64)
-        hipLaunchKernelGGL(centre_kernel<double>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(centre_kernel<double>, dim3(blocks), dim3(256), 0, s,
                            static_cast<const double*>(X), static_cast<double*>(Y), n, A);
     else
-        hipLaunchKernelGGL(centre_kernel<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(centre_kernel<float>, dim3(blocks), dim3(256), 0, s,
                            static_cast<const float*>(X), static_cast<float*>(Y), n, A);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
