@@ -159,11 +159,22 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
     const bool lds_rows = DP > 0 && a.lds_rows != 0;
     TI* xs = reinterpret_cast<TI*>(kpp_smem);                                      // [R][XS] + medoid row
     double* d2own = reinterpret_cast<double*>(kpp_smem + ((sizeof(TI) * (R + 1) * XS + 15) & ~size_t(15)));   // [R]
-    if (lds_rows) {
-        for (int64_t p = t; p < (hi - lo) * DP; p += nt) {
-            const int64_t r = p / DP;
-            const int c = (int)(p - r * DP);
-            xs[r * XS + c] = c < a.b.d ? row(lo + r)[c] : TI(0);
+    if (lds_rows) {   // four elements per thread at a time, loads issued unconditionally (clamped, masked)
+        const int64_t nel = (hi - lo) * DP;
+        for (int64_t p0 = t; p0 < nel; p0 += 4 * (int64_t)nt) {
+            TI v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t p = min(p0 + u * (int64_t)nt, nel - 1);
+                const int64_t r = p / DP;
+                const int c = (int)(p - r * DP);
+                v[u] = row(lo + r)[min(c, (int)a.b.d - 1)] * (c < a.b.d ? TI(1) : TI(0));
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t p = p0 + u * (int64_t)nt;
+                if (p < nel) xs[(p / DP) * XS + (p - (p / DP) * DP)] = v[u];
+            }
         }
         __syncthreads();
     }
@@ -469,11 +480,22 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
         const double v = a.cand_v[i];
         if (jj >= 0 && jj < kMergeTJ && !isnan(v)) atomicMin(&cmin[jj], ord_enc(v + 0.0));   // -0 counts as +0
     }
-    for (int p = threadIdx.x; p < kMergeTJ * a.nchunk; p += blockDim.x) {
-        const int jj = p / a.nchunk, k = p - jj * a.nchunk;
-        if (j0 + jj < a.C) {
-            const int32_t c = a.mpart_c[(int64_t)(j0 + jj) * a.nchunk + k];
-            if (c) atomicAdd(&cmem[jj], c);
+    // member-count partials, four per thread at a time (indices clamped, values masked), so
+    // their loads are in flight together
+    const int npart = kMergeTJ * a.nchunk;
+    for (int p0 = threadIdx.x; p0 < npart; p0 += 4 * (int)blockDim.x) {
+        int32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = min(p0 + u * (int)blockDim.x, npart - 1);
+            const int jj = p / a.nchunk, k = p - jj * a.nchunk;
+            c[u] = a.mpart_c[(int64_t)min(j0 + jj, a.C - 1) * a.nchunk + k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p0 + u * (int)blockDim.x;
+            const int jj = p / a.nchunk;
+            if (p < npart && j0 + jj < a.C && c[u]) atomicAdd(&cmem[jj], c[u]);
         }
     }
     __syncthreads();
@@ -496,6 +518,9 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
             a.counts[j] = mem;
             a.bmed[j] = med;
         }
+    } else if (threadIdx.x < kMergeTJ) {   // past the last cluster: no medoid, no merge step
+        cmed[threadIdx.x] = -1;
+        calpha[threadIdx.x] = 0.0;
     }
     __syncthreads();
 }
@@ -523,6 +548,26 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
     const int d = a.b.d;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t row0 = (int64_t)chunk * kMergeRows;
+    const int nrows = (int)min<int64_t>(kMergeRows, a.b.n - row0);
+    // Staging of the block's rows, CH dimensions at a time: element u of a thread is (row p / CH,
+    // dimension p % CH) for p = threadIdx.x + 256 u.  Every load is issued unconditionally (row and
+    // dimension clamped into range, the value scaled by a 0 / 1 mask, which keeps every bit of the
+    // values inside the tile), so a stage's loads are in flight together; the first stage's loads
+    // are issued before the clusters are settled.
+    constexpr int XPER = kMergeRows * CH / 256;
+    static_assert(XPER * 256 == kMergeRows * CH, "staging covers the chunk exactly");
+    auto stage_load = [&](int k0, TI (&v)[XPER]) {
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int p = threadIdx.x + 256 * u;
+            const int r = p / CH, k = p - r * CH;
+            const TI x = brow<TI>(a.b, row0 + min(r, nrows - 1))[min(k0 + k, d - 1)];
+            v[u] = x * ((r < nrows && k0 + k < d) ? TI(1) : TI(0));
+        }
+    };
+    TI xst[XPER];
+    stage_load(0, xst);
     if constexpr (SETTLED) {
         if (threadIdx.x < kMergeTJ && j0 + (int)threadIdx.x < a.C) {
             const int j = j0 + threadIdx.x;
@@ -530,29 +575,38 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
             const double alpha = merge_alpha(a.counts[j], a.wcount[j]);
             cmed[threadIdx.x] = med;
             calpha[threadIdx.x] = alpha > 0.0 && med >= 0 ? alpha : 0.0;
+        } else if (threadIdx.x < kMergeTJ) {   // past the last cluster: no medoid, no merge step
+            cmed[threadIdx.x] = -1;
+            calpha[threadIdx.x] = 0.0;
         }
         __syncthreads();
     } else {
         // settle the block's clusters (the same result as one block reducing each cluster)
         merge_settle(a, j0, chunk == 0, cmin, cpos, cmem, cmed, calpha);
     }
-    // targets, dimension-major: t = 2 (j - j0) is m_j^i, t + 1 is m_j (zero when unused)
-    for (int p = threadIdx.x; p < DP * NT; p += blockDim.x) {
-        const int k = p / NT, t = p - k * NT;
-        const int jj = t / 2, j = j0 + jj;
-        double v = 0.0;
-        if (j < a.C && k < d) {
-            const double alpha = calpha[jj];
-            if ((t & 1) == 0) {
-                if (alpha > 0.0) v = (double)brow<TI>(a.b, cmed[jj])[k];
-            } else if (alpha > 0.0 && alpha < 1.0) {
-                v = (double)static_cast<const TI*>(a.M)[(int64_t)j * a.Mpad + k];
-            }
-        }
-        Ts[k][t] = v;
+    // targets, dimension-major: t = 2 (j - j0) is m_j^i, t + 1 is m_j (zero when unused); every
+    // load issued unconditionally (cluster, row and dimension clamped, the value masked), so the
+    // thread's loads are in flight together
+    constexpr int TPER = (DP * NT + 255) / 256;
+    double tx[TPER];
+#pragma unroll
+    for (int u = 0; u < TPER; ++u) {
+        const int pc = min((int)threadIdx.x + 256 * u, DP * NT - 1);
+        const int k = pc / NT, t = pc - k * NT;
+        const int jj = t / 2, j = min(j0 + jj, a.C - 1);
+        const double alpha = calpha[jj];
+        const bool med = (t & 1) == 0;
+        // (a cluster past the last one, or without a medoid, reads row 0: a valid address, masked)
+        const int mrow = j0 + jj < a.C ? max(cmed[jj], 0) : 0;
+        const TI* src = med ? brow<TI>(a.b, mrow) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+        const bool on = j0 + jj < a.C && k < d && (med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0));
+        tx[u] = (double)src[min(k, d - 1)] * (on ? 1.0 : 0.0);
     }
-    const int64_t row0 = (int64_t)chunk * kMergeRows;
-    const int nrows = (int)min<int64_t>(kMergeRows, a.b.n - row0);
+#pragma unroll
+    for (int u = 0; u < TPER; ++u) {
+        const int p = threadIdx.x + 256 * u;
+        if (p < DP * NT) Ts[p / NT][p - (p / NT) * NT] = tx[u];
+    }
     const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
     double acc[8];
 #pragma unroll
@@ -560,12 +614,12 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
     double xx = 0.0;
 #pragma unroll 1
     for (int k0 = 0; k0 < DP; k0 += CH) {
+        if (k0 > 0) stage_load(k0, xst);
         __syncthreads();   // previous chunk consumed (and Ts written, on the first pass)
-        for (int p = threadIdx.x; p < kMergeRows * CH; p += blockDim.x) {
-            const int r = p / CH, k = p - r * CH;
-            TI v = TI(0);
-            if (r < nrows && k0 + k < d) v = brow<TI>(a.b, row0 + r)[k0 + k];
-            Xs[k][r] = v;
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int p = threadIdx.x + 256 * u;
+            Xs[p - (p / CH) * CH][p / CH] = xst[u];
         }
         __syncthreads();
 #pragma unroll 4
