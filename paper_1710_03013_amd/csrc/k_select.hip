@@ -308,6 +308,12 @@ __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
         cnt = 0;
         ncand = 0;
     }
+    // the row's label, distance and bound are loaded first: their loads overlap the column minimum
+    const int64_t qa = active ? q : 0;
+    const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
+    const int lab = a.labels[qa];
+    const double D = (double)Dt[qa];
+    const double Eq = (double)a.Erow[qa];
     double U;
     if (a.colpart_blocks > 0) {
         double v = kInf;
@@ -325,12 +331,9 @@ __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
         U = ord_dec(a.colmin[j]);
     }
     if (active) {
-        const int lab = a.labels[q];
         if (j == 0 && a.label_out) a.label_out[a.b.base + q * a.b.stride] = lab;
         if (lab == j) atomicAdd(&cnt, 1);
-        const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt)) + (int64_t)j * a.ldD;
-        const double D = (double)Dt[q];
-        if (D < kInf && D - (double)a.Erow[q] <= U) cq[atomicAdd(&ncand, 1)] = (int32_t)q;
+        if (D < kInf && D - Eq <= U) cq[atomicAdd(&ncand, 1)] = (int32_t)q;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
