@@ -323,6 +323,25 @@ def test_rmsd_assign_and_fit_small():
     _labels_match(lab, rl, rg, "rmsd assign")
 
 
+def test_rmsd_assign_large_request():
+    """An RMSD assign large enough (n >= 32768) for one lane per sample, where the sample tile is
+    staged in LDS as float: sampled rows against the oracle."""
+    kk = _kk()
+    _say("rmsd large assign")
+    A, C = 50, 50
+    kern = Kernel("rmsd", 1.5, A)
+    X, _ = ki.datasets.md_frames(40000 + C, A=A, n_templates=10, seed=21)   # one set of templates
+    M = X[:C].reshape(C, A, 3)
+    M = (M - M.mean(axis=1, keepdims=True)).reshape(C, 3 * A).astype(np.float32)
+    m = kk.kkm_model_create("rmsd", d=3 * A, C=C, dtype="f32", sigma=1.5, n_atoms=A)
+    kk.kkm_model_load(m, M, np.arange(C + 1), np.ones(C))
+    Y = np.ascontiguousarray(X[C:])
+    got = kk.kkm_assign(m, torch.from_numpy(Y).cuda()).cpu().numpy()
+    rows = np.sort(np.random.default_rng(5).choice(Y.shape[0], size=1500, replace=False))
+    want, gaps, _ = okkm.assign(kern, Y[rows].astype(np.float64), okkm.SparseModel(M.astype(np.float64), np.arange(C + 1), np.ones(C)))
+    _labels_match(got[rows], want, gaps, "rmsd large assign")
+
+
 # ------------------------------------------------------------------------------------------ full sizes
 def _stride_prefix(X, B, k):
     """Rows of the first k stride batches of X (B batches), laid out so that k stride batches of the
