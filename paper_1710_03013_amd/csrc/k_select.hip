@@ -727,26 +727,37 @@ __global__ __launch_bounds__(1024) void model_from_medoids_kernel(kkm_model m, c
         TI* dst = S + (int64_t)j * m.dpad;
         double n64 = 0.0;
         float n32 = 0.0f;
-        for (int64_t c = 0; c < m.dpad; ++c) {
-            const TI v = c < Mpad ? src[c] : TI(0);
-            dst[c] = v;
-            n64 = fma((double)v, (double)v, n64);
-            n32 = fmaf((float)v, (float)v, n32);
+        const bool panels = m.kernel.type != KKM_KERNEL_RMSD;   // power-of-two padded rows only
+        // 16 elements at a time: their loads are issued unconditionally (index clamped into the row,
+        // values past it scaled to zero), then copied, summed in order and split into the panels
+        const int64_t rlen = min((int64_t)m.dpad, Mpad);
+        for (int64_t c0 = 0; c0 < m.dpad; c0 += 16) {
+            TI v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int64_t c = c0 + u;
+                v[u] = src[min(c, rlen - 1)] * (c < rlen ? TI(1) : TI(0));
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = (int)(c0 + u);
+                if (c >= m.dpad) break;
+                dst[c] = v[u];
+                n64 = fma((double)v[u], (double)v[u], n64);
+                n32 = fmaf((float)v[u], (float)v[u], n32);
+                if (panels && m.pan) m.pan[panel32_index(j, c, m.dpad)] = c < m.d ? (float)v[u] : 0.0f;
+                if (panels && m.dpad >= 16) {
+                    uint16_t hi = 0, lo = 0;
+                    if (c < m.d) bf16_split((float)v[u], hi, lo);
+                    m.hi[panel16_index(j, c, m.dpad)] = hi;
+                    m.lo[panel16_index(j, c, m.dpad)] = lo;
+                }
+            }
         }
         m.snorm64[j] = n64;
         m.snorm32[j] = n32;
         m.coef64[j] = 1.0;
         m.coef32[j] = 1.0f;
-        const bool panels = m.kernel.type != KKM_KERNEL_RMSD;   // power-of-two padded rows only
-        if (panels && m.pan)
-            for (int c = 0; c < m.dpad; ++c) m.pan[panel32_index(j, c, m.dpad)] = c < m.d ? (float)dst[c] : 0.0f;
-        if (panels && m.dpad >= 16)
-            for (int c = 0; c < m.dpad; ++c) {
-                uint16_t hi = 0, lo = 0;
-                if (c < m.d) bf16_split((float)dst[c], hi, lo);
-                m.hi[panel16_index(j, c, m.dpad)] = hi;
-                m.lo[panel16_index(j, c, m.dpad)] = lo;
-            }
         m.offsets[j] = j;
         m.self[j] = Mself[j];
         m.segabs[j] = 1.0;
