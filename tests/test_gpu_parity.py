@@ -270,6 +270,34 @@ def test_fit_is_deterministic():
     np.testing.assert_array_equal(outs[0][2], outs[1][2])
 
 
+def test_fit_best_of_restarts():
+    """Best of four k-means++ restarts (seeds 51..54): every restart's FP64 cost and the chosen seed
+    against the oracle's four fits with the same draws; the winner (not the first seed here) must
+    be the oracle's best fit, batch by batch."""
+    kk = _kk()
+    from paper_1710_03013_amd.restarts import fit_best_of
+    _say("fit best of restarts")
+    X, _ = ki.datasets.gaussian_mixture(6000, 8, 6, seed=41, sigma=1.0, box=4.0)
+    kern = Kernel("rbf", 2.0)
+    C, B, s, T, R, seed0 = 6, 2, 0.2, 10, 4, 51
+    N = X.shape[0]
+    refs, costs = [], []
+    for r in range(R):
+        L = ki.draw_all_landmarks(seed0 + r, N, B, s, "stride")
+        u = ki.draw_kmpp_uniforms(seed0 + r, C)
+        ref = okkm.fit(X, C, kern, B, T, L, kmpp_uniforms=u)
+        assert ref.min_gap > GAP
+        refs.append(ref)
+        costs.append(okkm.cost(kern, X, okkm.medoid_model(ref)))
+    Xd = torch.from_numpy(X).cuda()
+    model, labels, info = fit_best_of(Xd, restarts=R, seed=seed0, kernel="rbf", sigma=2.0, C=C, B=B, s=s,
+                                      max_iter=T)
+    np.testing.assert_allclose(info["restart_costs"], costs, rtol=1e-9)
+    want = int(np.argmin(costs))
+    assert want != 0 and info["restart"] == want
+    _check_fit(kk, model, labels.cpu().numpy(), info, refs[want], kern, X, T)
+
+
 def test_fit_landmark_block_in_hbm():
     """One batch of 3500 landmarks: a workgroup's rows of K_LL exceed its LDS at every grid size, so
     the loop kernel reads them from HBM (its other variant)."""
