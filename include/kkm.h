@@ -138,6 +138,11 @@ typedef struct kkm_fit_info {
                                    workgroup at the steps of batch 0's landmark phase: [0] count, then
                                    start, block done, init done, and per update: sort, sums, barrier,
                                    g^, barrier (profiling aid) */
+    double* medoid_displacement; /* host [B*C] or NULL: kernel-space displacement of each global medoid
+                                   at batch i, ||phi(m_j after batch i) - phi(m_j before)|| =
+                                   sqrt(K(n,n) - 2 K(n,o) + K(o,o)) in FP64 (the sampling-quality
+                                   observable of Sec. 4.1, Fig. 4); 0 when m_j is kept, NaN when it
+                                   was unset before the batch */
 } kkm_fit_info;
 
 /* A clustering model: C sparse centroids w_j = sum_{l in segment j} a_l phi(s_l), kept resident in

@@ -363,3 +363,25 @@ def cost(kern: Kernel, Y: np.ndarray, model: SparseModel) -> float:
     """Eq. 1 with labels from Eq. 2: sum over samples of the distance to the nearest centroid."""
     d = centroid_distances(kern, Y, model)
     return float(np.sum(np.min(d, axis=1)))
+
+
+# --------------------------------------------------------------------------
+# Sampling-quality observable (Sec. 4.1, Fig. 4)
+# --------------------------------------------------------------------------
+def medoid_displacement(kern: Kernel, X: np.ndarray, before: np.ndarray, after: np.ndarray) -> np.ndarray:
+    """Feature-space displacement of every cluster centre across one outer iteration:
+    ||phi(x_after) - phi(x_before)|| = sqrt(K(a,a) - 2 K(a,b) + K(b,b)) for the global medoid
+    indices before and after the merge of a batch; 0 when the medoid is kept and NaN when it was
+    unset before (index -1)."""
+    out = np.full(len(after), np.nan)
+    for j, (b, a) in enumerate(zip(np.asarray(before), np.asarray(after))):
+        if b < 0:
+            continue
+        if a == b:
+            out[j] = 0.0
+            continue
+        xa = np.asarray(X[a:a + 1], dtype=np.float64)
+        xb = np.asarray(X[b:b + 1], dtype=np.float64)
+        v = kern.diag(xa)[0] - 2.0 * kern(xa, xb)[0, 0] + kern.diag(xb)[0]
+        out[j] = np.sqrt(max(v, 0.0))
+    return out

@@ -65,7 +65,7 @@ class _FitInfo(ct.Structure):
                 ("time_phases", ct.c_int32), ("reserved", ct.c_int32), ("ms_init", ct.c_double),
                 ("ms_landmark", ct.c_double), ("ms_dist", ct.c_double), ("ms_refine", ct.c_double),
                 ("ms_select", ct.c_double), ("ms_landmark_loop", ct.c_double),
-                ("landmark_trace", ct.POINTER(ct.c_int64))]
+                ("landmark_trace", ct.POINTER(ct.c_int64)), ("medoid_displacement", ct.POINTER(ct.c_double))]
 
 
 # name -> (restype, argtypes): every symbol include/kkm.h declares
@@ -283,14 +283,17 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     bcnt = np.zeros(B * C, dtype=np.int64)
     gmed = np.zeros(B * C, dtype=np.int64)
     trace = np.zeros(64, dtype=np.int64) if landmark_trace else None
+    disp = np.zeros(B * C, dtype=np.float64)
     info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, int(time_phases))
     if trace is not None:
         info.landmark_trace = _i64p(trace)
+    info.medoid_displacement = _f64p(disp)
     _check(lib().kkm_fit(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p),
                          ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(stream)), model.ptr,
                          ct.c_void_p(labels.data_ptr()) if labels is not None else None, ct.byref(info)))
     out = dict(updates_per_batch=upd, batch_medoids=bmed.reshape(B, C), batch_counts=bcnt.reshape(B, C),
-               global_medoids=gmed.reshape(B, C), evals_algorithmic=info.evals_algorithmic,
+               global_medoids=gmed.reshape(B, C), medoid_displacement=disp.reshape(B, C),
+               evals_algorithmic=info.evals_algorithmic,
                evals_performed=info.evals_performed, rows_refined=info.rows_refined,
                medoid_candidates=info.medoid_candidates, workspace_bytes=need,
                ms=dict(init=info.ms_init, landmark=info.ms_landmark, landmark_loop=info.ms_landmark_loop,

@@ -151,6 +151,7 @@ struct FitWs {
     int32_t* gpart_i;
     int32_t* updates;      // [B]
     int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
+    double* info_disp;     // [B][C] displacement of every global medoid per batch
     int64_t* trace;        // [64]
     unsigned* barrier;     // [1]
     int32_t* lm_error;     // [1]
@@ -209,12 +210,13 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.gpart_v = c.take<double>((size_t)C * merge_chunks(P.nmax));
     w.gpart_i = c.take<int32_t>((size_t)C * merge_chunks(P.nmax));
     w.barrier = c.take<unsigned>(1);
-    // status block, read back with one copy: [refine_counts, flags, updates, lm_error, info, trace]
+    // status block, read back with one copy: [refine_counts, flags, updates, lm_error, info, info_disp, trace]
     w.refine_counts = c.take<int32_t>(P.B);
     w.flags = c.take<int32_t>(2);
     w.updates = c.take<int32_t>(P.B);
     w.lm_error = c.take<int32_t>(1);
     w.info = c.take<int64_t>((size_t)3 * P.B * C);
+    w.info_disp = c.take<double>((size_t)P.B * C);
     w.trace = c.take<int64_t>(64);
     w.status_end = c.take<char>(1);
     return c.off;
@@ -703,6 +705,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sa.info_bmed = w.info + (size_t)i * C;
         sa.info_bcnt = w.info + (size_t)(P.B + i) * C;
         sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
+        sa.info_disp = info && info->medoid_displacement ? w.info_disp + (size_t)i * C : nullptr;
         KKM_TRY(tm.begin(kPhSelect));
         sa.cand_total = w.flags + 1;
         sa.colpart = w.colpart;
@@ -725,6 +728,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     const int32_t lm_err = *reinterpret_cast<const int32_t*>(host_at(w.lm_error));
     const int64_t* infos = reinterpret_cast<const int64_t*>(host_at(w.info));
     if (info && info->landmark_trace) std::memcpy(info->landmark_trace, host_at(w.trace), sizeof(int64_t) * 64);
+    if (info && info->medoid_displacement)
+        std::memcpy(info->medoid_displacement, host_at(w.info_disp), sizeof(double) * (size_t)P.B * C);
     model->used = C;
     model->nonneg = 1;
     (void)es;

@@ -700,11 +700,22 @@ __global__ __launch_bounds__(64) void merge_final_kernel(SelectArgs a) {
         if (bi == INT64_MAX) bi = med;
         const TI* x = brow<TI>(a.b, bi);
         TI* M = static_cast<TI*>(a.M) + (int64_t)j * a.Mpad;
+        if (a.info_disp && lane == 0) {   // (reads the old medoid row before the copy below replaces it)
+            const double koo = a.Mself[j];
+            double dsp = __builtin_nan("");
+            if (koo < kInf) {
+                const double v = kself64(a.ks, x) - 2.0 * k64(a.ks, x, M) + koo;
+                dsp = sqrt(v > 0.0 ? v : 0.0);
+            }
+            a.info_disp[j] = dsp;
+        }
         for (int64_t c = lane; c < a.Mpad; c += 64) M[c] = c < a.b.d ? x[c] : TI(0);
         if (lane == 0) {
             a.Mself[j] = kself64(a.ks, x);
             a.Midx[j] = a.b.base + bi * a.b.stride;
         }
+    } else if (a.info_disp && lane == 0) {   // m_j kept
+        a.info_disp[j] = a.Mself[j] < kInf ? 0.0 : __builtin_nan("");
     }
     if (lane == 0) {
         a.wcount[j] += mem;

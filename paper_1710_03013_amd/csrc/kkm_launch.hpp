@@ -177,6 +177,7 @@ struct SelectArgs {
     int64_t* info_bmed;
     int64_t* info_bcnt;
     int64_t* info_gmed;
+    double* info_disp;      // displacement of every global medoid (kernel space), or null
 };
 int select_chunks(int64_t n);
 // Merge partials per cluster for a batch of n rows (the workspace holds C * merge_chunks(nmax)).

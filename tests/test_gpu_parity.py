@@ -220,6 +220,22 @@ def test_fit_gaussian_mixture(N, prec):
     model, labels, info, ref = _fit_both(kk, X, kern, 20, 10, 0.1, T, "kmeans++", 2001, prec)
     _check_fit(kk, model, labels, info, ref, kern, X, T)
     assert info["evals_algorithmic"] == ref.evals
+    if ref.min_gap > GAP:
+        _check_displacement(info, ref, kern, X, 20, 10, 2001)
+
+
+def _check_displacement(info, ref, kern, X, C, B, seed):
+    """Medoid displacement per batch (Sec. 4.1 observable) against the oracle's definition, the
+    medoids before batch 0 being the k-means++ picks of the same draws."""
+    idx0 = okkm.batches(X.shape[0], B)[0]
+    before = idx0[okkm.kmeanspp(kern, np.asarray(X[idx0], dtype=np.float64), C, ki.draw_kmpp_uniforms(seed, C))]
+    got = info["medoid_displacement"]
+    for i in range(B):
+        want = okkm.medoid_displacement(kern, X, before, ref.global_medoids[i])
+        np.testing.assert_array_equal(np.isnan(got[i]), np.isnan(want))
+        ok = ~np.isnan(want)
+        np.testing.assert_allclose(got[i][ok], want[ok], rtol=1e-9, atol=1e-12)
+        before = ref.global_medoids[i]
 
 
 def test_fit_linear_block_ragged_explicit_medoids():

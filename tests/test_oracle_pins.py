@@ -363,3 +363,22 @@ def test_accuracy_and_nmi_closed_cases():
     Hy = -(0.75 * np.log(0.75) + 0.25 * np.log(0.25))
     I = Hu - 0.75 * (-(2 / 3) * np.log(2 / 3) - (1 / 3) * np.log(1 / 3))
     assert abs(metrics.nmi(y, u) - I / np.sqrt(Hu * Hy)) < 1e-12
+
+
+def test_medoid_displacement_closed_forms():
+    """Sec. 4.1 observable: for the linear kernel the feature-space displacement is the Euclidean
+    distance between the two medoids; for RBF it is sqrt(2 - 2 exp(-|a-b|^2 / 2 sigma^2)); a kept
+    medoid moves 0 and an unset one gives NaN."""
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(30, 5))
+    before = np.array([3, 7, -1, 11, 4])
+    after = np.array([9, 7, 2, 20, 28])
+    lin = kkm.medoid_displacement(Kernel("linear", 1.0), X, before, after)
+    for j in (0, 3, 4):
+        assert abs(lin[j] - np.linalg.norm(X[after[j]] - X[before[j]])) < 1e-12
+    assert lin[1] == 0.0 and np.isnan(lin[2])
+    sig = 1.7
+    rbf = kkm.medoid_displacement(Kernel("rbf", sig), X, before, after)
+    for j in (0, 3, 4):
+        r2 = float(np.sum((X[after[j]] - X[before[j]]) ** 2))
+        assert abs(rbf[j] - np.sqrt(2.0 - 2.0 * np.exp(-r2 / (2 * sig * sig)))) < 1e-12
