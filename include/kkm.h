@@ -143,6 +143,11 @@ typedef struct kkm_fit_info {
                                    sqrt(K(n,n) - 2 K(n,o) + K(o,o)) in FP64 (the sampling-quality
                                    observable of Sec. 4.1, Fig. 4); 0 when m_j is kept, NaN when it
                                    was unset before the batch */
+    double* partial_cost;       /* host [B] or NULL: the partial cost Omega(W^i) of every batch (Sec. 4.1,
+                                   Fig. 4), Eq. 1 over the batch's rows with the batch's centroids of
+                                   Eq. 14 after its loop: the sum of each row's distance to its nearest
+                                   centroid, summed in FP64 in a fixed order (a row decided in FP32 adds
+                                   its distance formed from FP32 sums, within the row's error bound) */
 } kkm_fit_info;
 
 /* A clustering model: C sparse centroids w_j = sum_{l in segment j} a_l phi(s_l), kept resident in

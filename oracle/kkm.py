@@ -385,3 +385,10 @@ def medoid_displacement(kern: Kernel, X: np.ndarray, before: np.ndarray, after: 
         v = kern.diag(xa)[0] - 2.0 * kern(xa, xb)[0, 0] + kern.diag(xb)[0]
         out[j] = np.sqrt(max(v, 0.0))
     return out
+
+
+def partial_costs(fitres: FitResult) -> list:
+    """Partial cost Omega(W^i) of every batch (Sec. 4.1, Fig. 4): Eq. 1 over the batch's rows with
+    the batch's landmark centroids after its loop, i.e. the sum of each row's distance to its
+    nearest centroid under those centroids."""
+    return [float(np.sum(np.min(lp.dist, axis=1))) for lp in fitres.loops]

@@ -65,7 +65,8 @@ class _FitInfo(ct.Structure):
                 ("time_phases", ct.c_int32), ("reserved", ct.c_int32), ("ms_init", ct.c_double),
                 ("ms_landmark", ct.c_double), ("ms_dist", ct.c_double), ("ms_refine", ct.c_double),
                 ("ms_select", ct.c_double), ("ms_landmark_loop", ct.c_double),
-                ("landmark_trace", ct.POINTER(ct.c_int64)), ("medoid_displacement", ct.POINTER(ct.c_double))]
+                ("landmark_trace", ct.POINTER(ct.c_int64)), ("medoid_displacement", ct.POINTER(ct.c_double)),
+                ("partial_cost", ct.POINTER(ct.c_double))]
 
 
 # name -> (restype, argtypes): every symbol include/kkm.h declares
@@ -254,13 +255,15 @@ def kkm_fit_workspace_bytes(N, d, dtype, kernel, **params) -> int:
 def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20, sampling="stride",
             init="kmeans++", precision="fp32", seed=0, landmarks=None, kmpp_uniforms=None, init_labels=None,
             init_medoids=None, model=None, workspace=None, stream=None, want_labels=True, time_phases=False,
-            landmark_trace=False, cooperative=False):
+            landmark_trace=False, cooperative=False, cost_trace=False):
     """Fit on X (a CUDA tensor, N x d).  Returns (model, labels tensor or None, info dict).
 
     time_phases: False / 0 no timing; True / 1 HIP events around every phase; 2 only around the
     landmark loop kernel and the batch-wide distance kernel (info["ms"] holds 0 for the others).
     cooperative: launch the kernels whose workgroups wait for each other cooperatively (for callers
-    that keep other streams busy on the same GPU meanwhile)."""
+    that keep other streams busy on the same GPU meanwhile).
+    cost_trace: also return info["partial_cost"], the partial cost of every batch (one more
+    reduction per batch)."""
     import torch
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
@@ -288,11 +291,14 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     if trace is not None:
         info.landmark_trace = _i64p(trace)
     info.medoid_displacement = _f64p(disp)
+    pc = np.zeros(B, dtype=np.float64) if cost_trace else None
+    if pc is not None:
+        info.partial_cost = _f64p(pc)
     _check(lib().kkm_fit(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p),
                          ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(stream)), model.ptr,
                          ct.c_void_p(labels.data_ptr()) if labels is not None else None, ct.byref(info)))
     out = dict(updates_per_batch=upd, batch_medoids=bmed.reshape(B, C), batch_counts=bcnt.reshape(B, C),
-               global_medoids=gmed.reshape(B, C), medoid_displacement=disp.reshape(B, C),
+               global_medoids=gmed.reshape(B, C), medoid_displacement=disp.reshape(B, C), partial_cost=pc,
                evals_algorithmic=info.evals_algorithmic,
                evals_performed=info.evals_performed, rows_refined=info.rows_refined,
                medoid_candidates=info.medoid_candidates, workspace_bytes=need,

@@ -152,6 +152,9 @@ struct FitWs {
     int32_t* updates;      // [B]
     int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
     double* info_disp;     // [B][C] displacement of every global medoid per batch
+    double* pcost;         // [B] partial cost of every batch
+    double* best;          // [nmax] each batch row's distance to its nearest centroid (partial cost)
+    double* psum;          // [1024] partial sums of the partial cost
     int64_t* trace;        // [64]
     unsigned* barrier;     // [1]
     int32_t* lm_error;     // [1]
@@ -205,6 +208,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.Erow = c.take<float>(P.nmax);
     w.labels_b = c.take<int32_t>(P.nmax);
     w.refine_list = c.take<int32_t>(P.nmax);
+    w.best = c.take<double>(P.nmax);
+    w.psum = c.take<double>(1024);
     w.bmed = c.take<int32_t>(C);
     w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
     w.gpart_v = c.take<double>((size_t)C * merge_chunks(P.nmax));
@@ -217,6 +222,7 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.lm_error = c.take<int32_t>(1);
     w.info = c.take<int64_t>((size_t)3 * P.B * C);
     w.info_disp = c.take<double>((size_t)P.B * C);
+    w.pcost = c.take<double>((size_t)P.B);
     w.trace = c.take<int64_t>(64);
     w.status_end = c.take<char>(1);
     return c.off;
@@ -654,7 +660,8 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         da.Erow = w.Erow;
         da.labels = w.labels_b;
         da.gap = nullptr;
-        da.best = nullptr;
+        const bool pcost = info && info->partial_cost;
+        da.best = pcost ? w.best : nullptr;
         da.refine_list = w.refine_list;
         da.refine_count = w.refine_counts + i;
         da.nonfinite = w.flags;
@@ -671,6 +678,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
             KKM_TRY(tm.begin(kPhRefine));
             KKM_TRY(launch_refine(da, dev, s, ell));
             KKM_TRY(tm.end(kPhRefine));
+        }
+        if (pcost) {   // the batch's partial cost: its rows' distances summed in a fixed order
+            tm.gap();
+            KKM_TRY(launch_sum(w.best, bv.n, w.psum, w.pcost + i, s));
         }
 
         SelectArgs sa{};
@@ -730,6 +741,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     if (info && info->landmark_trace) std::memcpy(info->landmark_trace, host_at(w.trace), sizeof(int64_t) * 64);
     if (info && info->medoid_displacement)
         std::memcpy(info->medoid_displacement, host_at(w.info_disp), sizeof(double) * (size_t)P.B * C);
+    if (info && info->partial_cost) std::memcpy(info->partial_cost, host_at(w.pcost), sizeof(double) * (size_t)P.B);
     model->used = C;
     model->nonneg = 1;
     (void)es;

@@ -160,7 +160,8 @@ def _fit_both(kk, X, kern, C, B, s, T, init, seed, prec, sampling="stride", dtyp
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     model, labels, info = kk.kkm_fit(Xd, kern.kind, sigma=kern.sigma, n_atoms=kern.n_atoms, C=C, B=B, s=s,
                                      max_iter=T, sampling=sampling, init=init, precision=prec, seed=seed,
-                                     landmarks=L, kmpp_uniforms=u, init_labels=lab0, init_medoids=med0)
+                                     landmarks=L, kmpp_uniforms=u, init_labels=lab0, init_medoids=med0,
+                                     cost_trace=True)
     torch.cuda.synchronize()
     ref = okkm.fit(X, C, kern, B, T, L, sampling=sampling, init=init, kmpp_uniforms=u, init_labels=lab0,
                    init_medoids=med0)
@@ -222,6 +223,9 @@ def test_fit_gaussian_mixture(N, prec):
     assert info["evals_algorithmic"] == ref.evals
     if ref.min_gap > GAP:
         _check_displacement(info, ref, kern, X, 20, 10, 2001)
+    # partial cost of every batch (Sec. 4.1), to the cost tolerance of the precision
+    rtol = {"fp64": 1e-9, "fp32": 1e-5, "bf16x3": 1e-3}[prec]
+    np.testing.assert_allclose(info["partial_cost"], okkm.partial_costs(ref), rtol=rtol)
 
 
 def _check_displacement(info, ref, kern, X, C, B, seed):

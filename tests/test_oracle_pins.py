@@ -382,3 +382,17 @@ def test_medoid_displacement_closed_forms():
     for j in (0, 3, 4):
         r2 = float(np.sum((X[after[j]] - X[before[j]]) ** 2))
         assert abs(rbf[j] - np.sqrt(2.0 - 2.0 * np.exp(-r2 / (2 * sig * sig)))) < 1e-12
+
+
+def test_partial_cost_of_a_converged_full_batch_is_the_partition_cost():
+    """Sec. 4.1 partial cost: once the labels of a full batch (B = 1, s = 1) no longer change, the
+    centroids are the means of the final partition, so the partial cost equals the explicit
+    partition cost of the final labels (linear: the Euclidean k-means cost)."""
+    for seed in range(3):
+        X, _ = _blobs(40, 2, 3, seed)
+        U0 = np.random.default_rng(seed).integers(0, 3, size=40)
+        res = _full_batch_fit(X, 3, Kernel("linear"), U0, 50)
+        tr = res.loops[0].trajectory
+        assert np.array_equal(tr[-1], tr[-2])   # converged
+        pc = kkm.partial_costs(res)[0]
+        assert abs(pc - reference.explicit_cost(X, res.labels, 3)) < 1e-9 * max(1.0, pc)
