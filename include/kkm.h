@@ -184,6 +184,17 @@ void kkm_model_free(kkm_model* model);
 size_t kkm_fit_workspace_bytes(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
                                const kkm_params* params);
 
+/* The memory knob of Sec. 3.3 (Eq. 19 gives the smallest number of mini-batches for the paper's own
+ * footprint model): the smallest B, with every other field of *params as given (its B, landmarks,
+ * init_labels and init_medoids are not read), for which kkm_fit's workspace for N x d samples is at
+ * most budget_bytes (X itself is the caller's and not counted).  The workspace falls with B while the
+ * landmark block dominates and rises again with the per-batch state; B is searched on the falling
+ * side, below the B (a power of two up to N / C) of the smallest workspace: the B returned fits,
+ * and B - 1 does not.  Host only, no device work.  Returns 0 when no B fits or an argument is
+ * invalid (kkm_last_error says which). */
+int64_t kkm_fit_min_batches(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
+                            const kkm_params* params, size_t budget_bytes);
+
 /* Cluster X (device, N x d) with the paper's mini-batch landmark kernel k-means:
  *   for each batch i (stride or block sampling): draw l_i landmarks; initialise their labels (batch 0:
  *   k-means++ / random / given medoids; later batches: nearest global medoid, Eq. 8); iterate

@@ -18,7 +18,7 @@ __all__ = [
     "KKM_PREC_FP64", "KKM_PREC_FP32", "KKM_PREC_BF16X3", "KKM_SAMPLE_STRIDE", "KKM_SAMPLE_BLOCK",
     "KKM_INIT_KMEANSPP", "KKM_INIT_RANDOM_LABELS", "KKM_INIT_MEDOIDS", "KkmError", "Model", "lib",
     "kkm_model_create", "kkm_model_load", "kkm_model_export", "kkm_model_shape", "kkm_fit",
-    "kkm_fit_workspace_bytes", "kkm_assign", "kkm_assign_workspace_bytes", "kkm_cost",
+    "kkm_fit_workspace_bytes", "kkm_fit_min_batches", "kkm_assign", "kkm_assign_workspace_bytes", "kkm_cost",
     "kkm_landmark_count", "kkm_draw_landmarks", "kkm_draw_kmpp_uniforms", "kkm_draw_init_labels",
     "kkm_version", "EXPORTED_SYMBOLS",
 ]
@@ -82,6 +82,8 @@ _SIGS = {
     "kkm_model_free": (None, [ct.c_void_p]),
     "kkm_fit_workspace_bytes": (ct.c_size_t, [ct.c_int64, ct.c_int64, ct.c_int32, ct.POINTER(_Kernel),
                                               ct.POINTER(_Params)]),
+    "kkm_fit_min_batches": (ct.c_int64, [ct.c_int64, ct.c_int64, ct.c_int32, ct.POINTER(_Kernel),
+                                         ct.POINTER(_Params), ct.c_size_t]),
     "kkm_fit": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int32, ct.POINTER(_Kernel),
                            ct.POINTER(_Params), ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
                            ct.c_void_p, ct.POINTER(_FitInfo)]),
@@ -250,6 +252,17 @@ def kkm_fit_workspace_bytes(N, d, dtype, kernel, **params) -> int:
     keep = []
     p = _params(**params, keep=keep)
     return int(lib().kkm_fit_workspace_bytes(int(N), int(d), int(dtype), ct.byref(kernel), ct.byref(p)))
+
+
+def kkm_fit_min_batches(N, d, dtype, kernel, budget_bytes, **params) -> int:
+    """Smallest number of mini-batches whose fit workspace fits budget_bytes (params as for
+    kkm_fit_workspace_bytes; their B is not read).  Raises KkmError when none fits."""
+    keep = []
+    p = _params(**{"B": 1, **params}, keep=keep)
+    B = int(lib().kkm_fit_min_batches(int(N), int(d), int(dtype), ct.byref(kernel), ct.byref(p), int(budget_bytes)))
+    if B == 0:
+        raise KkmError(-1, lib().kkm_last_error().decode())
+    return B
 
 
 def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20, sampling="stride",

@@ -496,6 +496,53 @@ size_t kkm_fit_workspace_bytes(int64_t N, int64_t d, int32_t dtype, const kkm_ke
     return carve_fit(c, P, w);
 }
 
+int64_t kkm_fit_min_batches(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel, const kkm_params* params,
+                            size_t budget_bytes) {
+    if (!params) {
+        fail(KKM_ERR_INVALID_ARG, "params is NULL");
+        return 0;
+    }
+    if (N < 1 || params->C < 1) {
+        fail(KKM_ERR_INVALID_ARG, "N and C must be >= 1");
+        return 0;
+    }
+    kkm_params p = *params;
+    p.landmarks = nullptr;
+    p.init_labels = nullptr;
+    p.init_medoids = nullptr;
+    auto fits = [&](int64_t B) {
+        p.B = (int32_t)B;
+        const size_t w = kkm_fit_workspace_bytes(N, d, dtype, kernel, &p);
+        return w != 0 && w <= budget_bytes;
+    };
+    // The workspace falls with B while the landmark block dominates (l^2 ~ 1/B^2) and rises again
+    // with the per-batch state (~ B): the smallest fitting B lies on the falling side, below the B
+    // of the smallest workspace, found first among the powers of two up to N / C.
+    const int64_t hi0 = std::min<int64_t>(std::max<int64_t>(1, N / params->C), INT32_MAX);
+    int64_t bstar = 0;
+    size_t wstar = 0;
+    for (int64_t B = 1;; B = std::min(hi0, 2 * B)) {
+        p.B = (int32_t)B;
+        const size_t w = kkm_fit_workspace_bytes(N, d, dtype, kernel, &p);
+        if (w != 0 && (bstar == 0 || w < wstar)) {
+            bstar = B;
+            wstar = w;
+        }
+        if (B == hi0) break;
+    }
+    if (bstar == 0 || !fits(bstar)) {
+        fail(KKM_ERR_WORKSPACE, "no number of mini-batches up to N / C fits the workspace budget");
+        return 0;
+    }
+    int64_t lo = 0, hi = bstar;   // fits(hi); lo == 0 or !fits(lo)
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (fits(mid)) hi = mid;
+        else lo = mid;
+    }
+    return hi;
+}
+
 kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
                    const kkm_params* params, void* workspace, size_t workspace_bytes, void* stream, kkm_model* model,
                    int32_t* labels_out, kkm_fit_info* info) {

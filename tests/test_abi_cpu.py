@@ -102,3 +102,27 @@ def test_model_create_without_device_fails_cleanly():
     with pytest.raises(kk.KkmError) as e:
         kk.kkm_model_create("rbf", d=4, C=3)
     assert e.value.status == -3
+
+
+def test_fit_min_batches_is_the_smallest_fitting_b():
+    """The memory knob (Sec. 3.3): the returned B fits the workspace budget and B - 1 does not;
+    a larger budget never needs more batches; a budget below every B is reported."""
+    kk = _kk()
+    k = kk._kernel("rbf", 4.0)
+    args = dict(C=20, s=0.1, max_iter=20, sampling="stride", init="kmeans++", precision="fp32", seed=1,
+                landmarks=None, kmpp_uniforms=None, init_labels=None, init_medoids=None)
+
+    def ws(B):
+        return kk.kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, k, B=B, **args)
+
+    prev = None
+    for B_target in (1, 3, 10, 40):
+        budget = ws(B_target)
+        B = kk.kkm_fit_min_batches(100_000, 16, kk.KKM_F32, k, budget, **args)
+        assert 1 <= B <= B_target and ws(B) <= budget
+        assert B == 1 or ws(B - 1) > budget
+        if prev is not None:
+            assert B >= prev   # smaller budgets (larger B_target) need at least as many batches
+        prev = B
+    with pytest.raises(kk.KkmError):
+        kk.kkm_fit_min_batches(100_000, 16, kk.KKM_F32, k, 1024, **args)
