@@ -275,8 +275,8 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     landmark loop kernel and the batch-wide distance kernel (info["ms"] holds 0 for the others).
     cooperative: launch the kernels whose workgroups wait for each other cooperatively (for callers
     that keep other streams busy on the same GPU meanwhile).
-    cost_trace: also return info["partial_cost"], the partial cost of every batch (one more
-    reduction per batch)."""
+    cost_trace: also return the per-batch observables of Sec. 4.1: info["partial_cost"] (the partial
+    cost of every batch, one more reduction per batch) and info["medoid_displacement"] (B x C)."""
     import torch
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
@@ -299,19 +299,20 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     bcnt = np.zeros(B * C, dtype=np.int64)
     gmed = np.zeros(B * C, dtype=np.int64)
     trace = np.zeros(64, dtype=np.int64) if landmark_trace else None
-    disp = np.zeros(B * C, dtype=np.float64)
+    disp = np.zeros(B * C, dtype=np.float64) if cost_trace else None
+    pc = np.zeros(B, dtype=np.float64) if cost_trace else None
     info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, int(time_phases))
     if trace is not None:
         info.landmark_trace = _i64p(trace)
-    info.medoid_displacement = _f64p(disp)
-    pc = np.zeros(B, dtype=np.float64) if cost_trace else None
-    if pc is not None:
+    if cost_trace:
+        info.medoid_displacement = _f64p(disp)
         info.partial_cost = _f64p(pc)
     _check(lib().kkm_fit(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p),
                          ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(stream)), model.ptr,
                          ct.c_void_p(labels.data_ptr()) if labels is not None else None, ct.byref(info)))
     out = dict(updates_per_batch=upd, batch_medoids=bmed.reshape(B, C), batch_counts=bcnt.reshape(B, C),
-               global_medoids=gmed.reshape(B, C), medoid_displacement=disp.reshape(B, C), partial_cost=pc,
+               global_medoids=gmed.reshape(B, C),
+               medoid_displacement=disp.reshape(B, C) if disp is not None else None, partial_cost=pc,
                evals_algorithmic=info.evals_algorithmic,
                evals_performed=info.evals_performed, rows_refined=info.rows_refined,
                medoid_candidates=info.medoid_candidates, workspace_bytes=need,
