@@ -50,7 +50,7 @@ DIST_KERNEL_NAME = {("rbf", "fp32"): "mfma_dist_kernel", ("linear", "fp32"): "mf
 # calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
 # and its SHA-1 prefix at measurement time: a changed kernel source reports null.
 TRAFFIC_MEASURED = {
-    ("landmark_phase_kernel", "mixture16"): (10.573e6, "k_landmark.hip", "12c51db228ac"),
+    ("landmark_phase_kernel", "mixture16"): (10.579e6, "k_landmark.hip", "12c51db228ac"),
     ("mfma_dist_kernel", "mixture16"): (2.890e6, "k_mfma.hip", "8f0dd5a930b6"),
 }
 
