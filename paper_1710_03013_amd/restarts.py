@@ -20,7 +20,7 @@ def fit_best_of(X, restarts: int = 5, seed: int = 0, cost_precision: str = "fp64
     ``restart`` (the winner's index, its seed being seed + restart) and ``restart_costs``."""
     if restarts < 1:
         raise ValueError("restarts must be >= 1")
-    for k in ("seed", "landmarks", "kmpp_uniforms", "init_labels"):
+    for k in ("landmarks", "kmpp_uniforms", "init_labels"):   # (they follow from each restart's seed)
         if k in fit_kwargs:
             raise ValueError(f"fit_best_of sets {k} itself")
     best, costs = None, []
