@@ -396,3 +396,89 @@ def test_partial_cost_of_a_converged_full_batch_is_the_partition_cost():
         assert np.array_equal(tr[-1], tr[-2])   # converged
         pc = kkm.partial_costs(res)[0]
         assert abs(pc - reference.explicit_cost(X, res.labels, 3)) < 1e-9 * max(1.0, pc)
+
+
+# ---------------------------------------------------------------- Eq. 8, Eq. 10 and the RMSD kernel
+def test_eq8_initial_labels_are_nearest_euclidean_medoid_for_linear_kernel():
+    """Eq. 8 with the full feature-space distance K(x,x) - 2K(x,m) + K(m,m): for the linear kernel
+    the initial labels of batch i >= 1 are the labels of the nearest global medoid in plain
+    Euclidean distance.  The data make the printed form (K(m,m) dropped) pick other labels, so a
+    dropped term fails here."""
+    rng = np.random.default_rng(31)
+    # medoids of very different norms: dropping ||m||^2 favours the long one
+    M = np.array([[0.5, 0.0], [6.0, 0.0], [0.0, -4.0]])
+    X = rng.normal(scale=2.0, size=(200, 2))
+    want = np.argmin(((X[:, None, :] - M[None]) ** 2).sum(-1), axis=1)
+    got = kkm.nearest_medoid_labels(Kernel("linear"), X, M, np.ones(3, dtype=bool))
+    np.testing.assert_array_equal(got, want)
+    dropped = np.argmin(-2.0 * X @ M.T, axis=1)
+    assert (dropped != want).sum() > 20          # the pin discriminates the misprint
+    # a skipped (unset) medoid never wins
+    got2 = kkm.nearest_medoid_labels(Kernel("linear"), X, M, np.array([True, False, True]))
+    want2 = np.argmin(np.where([True, False, True], ((X[:, None, :] - M[None]) ** 2).sum(-1), np.inf), axis=1)
+    np.testing.assert_array_equal(got2, want2)
+
+
+def test_eq8_through_the_fit_on_the_second_batch():
+    """The same pin through fit(): linear kernel, B = 2, s = 1 (every sample a landmark), so the
+    loop's starting labels on batch 1 are visible as the first entry of its trajectory; they must
+    be the nearest-Euclidean-medoid labels for the global medoids left by batch 0."""
+    rng = np.random.default_rng(32)
+    C = 4
+    cen = np.array([[0.0, 0.0], [8.0, 0.0], [0.0, 8.0], [8.0, 8.0]]) + 3.0
+    X = cen[rng.integers(0, C, size=400)] + rng.normal(scale=1.5, size=(400, 2))
+    L = [np.arange(200), np.arange(200)]
+    res = kkm.fit(X, C, Kernel("linear"), 2, 20, L, kmpp_uniforms=ki.draw_kmpp_uniforms(4, C))
+    Mg = X[res.global_medoids[0]]
+    X1 = X[kkm.batches(400, 2)[1]]
+    want = np.argmin(((X1[:, None, :] - Mg[None]) ** 2).sum(-1), axis=1)
+    np.testing.assert_array_equal(res.loops[1].trajectory[0], want)
+    assert (np.argmin(-2.0 * X1 @ Mg.T, axis=1) != want).any()
+
+
+def test_eq10_batch_medoid_minimises_over_the_whole_batch():
+    """Eq. 10: m_j^i = argmin over all of X^i (not only the members of cluster j) of the distance to
+    w_j.  Linear kernel, s = 1, a converged batch: w_j is the explicit mean of cluster j.  Cluster 0
+    is two far groups whose mean lies near a member of cluster 1, so its medoid is that non-member;
+    restricting the argmin to members would pick a point of the far groups."""
+    X = np.array([[-10.0, 0.0], [10.0, 0.0], [0.0, 0.5], [0.0, 1.0], [-9.0, 0.0], [9.0, 0.0]])
+    U0 = np.array([0, 0, 1, 1, 0, 0])
+    res = kkm.fit(X, 2, Kernel("linear"), 1, 20, [np.arange(6)], init="random", init_labels=U0)
+    np.testing.assert_array_equal(res.labels, U0)            # converged with the given partition
+    mu0 = X[U0 == 0].mean(axis=0)
+    nearest = int(np.argmin(((X - mu0) ** 2).sum(1)))
+    assert U0[nearest] != 0                                  # the nearest sample is not a member
+    assert res.batch_medoids[0, 0] == nearest
+    mu1 = X[U0 == 1].mean(axis=0)
+    assert res.batch_medoids[0, 1] == int(np.argmin(((X - mu1) ** 2).sum(1)))
+    # the same through the function on the loop's distances
+    Mi, members = kkm.batch_medoids(res.loops[0].dist, res.labels, 2)
+    assert Mi[0] == nearest and members.tolist() == [4, 2]
+
+
+def test_rmsd_kernel_on_atom_major_rows():
+    """K(x, y) = exp(-RMSD^2 / (2 sigma^2)) on rows laid out atom by atom (x0 y0 z0 x1 y1 z1 ...):
+    a rigid copy gives exactly 1 (to rounding), and two-atom frames follow the closed form
+    RMSD^2 = (|a| - |b|)^2 / 4 for bonds a and b.  A sigma^2 / 2 sigma^2 slip or a coordinate-major
+    reshape of the rows fails one of these."""
+    rng = np.random.default_rng(33)
+    sigma = 1.3
+    kern = Kernel("rmsd", sigma, 2)
+    for _ in range(6):
+        p0, a = rng.normal(size=3), rng.normal(scale=2.0, size=3)
+        q0, b = rng.normal(size=3), rng.normal(scale=2.0, size=3)
+        x = np.concatenate([p0, p0 + a])[None]
+        y = np.concatenate([q0, q0 + b])[None]
+        r2 = (np.linalg.norm(a) - np.linalg.norm(b)) ** 2 / 4.0
+        assert abs(kern(x, y)[0, 0] - np.exp(-r2 / (2 * sigma * sigma))) < 1e-12
+    A = 9
+    kern9 = Kernel("rmsd", sigma, A)
+    F = rng.normal(scale=4.0, size=(A, 3))
+    R = ki.datasets.random_rotations(rng, 1)[0]
+    G = F @ R.T + rng.uniform(-20, 20, size=3)
+    assert abs(kern9(F.reshape(1, -1), G.reshape(1, -1))[0, 0] - 1.0) < 1e-12
+    # a known perturbation: the Kabsch route (pinned above) gives the value
+    H = F + rng.normal(scale=0.3, size=F.shape)
+    want = np.exp(-rmsd2_kabsch(F, H) / (2 * sigma * sigma))
+    assert abs(kern9(F.reshape(1, -1), H.reshape(1, -1))[0, 0] - want) < 1e-12
+    assert kern9.diag(F.reshape(1, -1))[0] == 1.0
