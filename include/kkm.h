@@ -60,13 +60,20 @@ enum kkm_kernel_type {
 
 enum kkm_dtype { KKM_F32 = 0, KKM_F64 = 1 };
 
-/* Arithmetic of the dominant n x |L| kernel block (and of kkm_assign).  FP32 and BF16X3
+/* Arithmetic of the dominant n x |L| kernel block (and of kkm_assign).  FP32, BF16 and BF16X3
  * decide every label whose margin is below a computed error bound again in FP64, so labels
- * equal those of exact arithmetic except where the FP64 margin itself vanishes. */
+ * equal those of exact arithmetic except where the FP64 margin itself vanishes.  The bfloat16
+ * forms run on the matrix cores for float32 samples with d >= 9 (padded to 16); other inputs
+ * take the FP32 path. */
 enum kkm_precision {
     KKM_PREC_FP64 = 0,
     KKM_PREC_FP32 = 1,
-    KKM_PREC_BF16X3 = 2         /* x.y from split-bf16 products hi*hi + hi*lo + lo*hi on MFMA */
+    KKM_PREC_BF16 = 2,          /* x.y from one bfloat16 product hi*hi' (FP32 accumulation) on MFMA: the
+                                   cheap gating pass, rows under its (wider) bound go to FP64; kkm_cost
+                                   then takes each row's distance to its cluster in FP64.  In kkm_fit the
+                                   batch pass feeds the medoid candidates, whose bound needs the
+                                   compensated products: a fit asked for BF16 runs BF16X3 there */
+    KKM_PREC_BF16X3 = 3         /* x.y from split-bf16 products hi*hi' + hi*lo' + lo*hi' on MFMA */
 };
 
 /* kkm_params.flags bits */
@@ -225,6 +232,24 @@ kkm_status kkm_assign(const kkm_model* model, const void* X, int64_t n, int32_t 
  * fixed order (the same bits on every run).  Uses the workspace of kkm_assign.  Synchronous. */
 kkm_status kkm_cost(const kkm_model* model, const void* X, int64_t n, int32_t dtype, int32_t precision,
                     void* workspace, size_t workspace_bytes, void* stream, double* cost_out);
+
+/* ---------------------------------------------------------------- kernel block (Sec. 2, Eq. 16) */
+
+/* Workspace bytes of kkm_kernel_block (0 if the arguments are invalid): RMSD needs a centred copy of
+ * both row sets, the other kernels none (256 is returned then). */
+size_t kkm_kernel_block_workspace_bytes(const kkm_kernel* kernel, int64_t nx, int64_t ny, int64_t d, int32_t dtype);
+
+/* The kernel matrix between two row sets, K_out[i * ny + j] = K(x_i, y_j) in FP64 (Sec. 2 writes every
+ * feature-space inner product as K; the landmark block of Eq. 16 is K(X_L, X_L)).  X: device [nx*d],
+ * Y: device [ny*d], rows in dtype; K_out: device [nx*ny] doubles.  Linear: x.y; RBF from explicit
+ * coordinate differences; RMSD: both frame sets are centred into the workspace, the 3x3 correlation
+ * of each pair is summed in FP64 and the largest eigenvalue of its 4x4 key matrix is found by
+ * Newton's method on the characteristic polynomial, solved again by Jacobi rotations where Newton
+ * converges slowly (a multiple or nearly multiple largest root: collinear or symmetric frames).  These
+ * are the FP64 evaluations the library's re-decisions, medoid and merge steps use.  Enqueued on
+ * stream; returns without waiting. */
+kkm_status kkm_kernel_block(const kkm_kernel* kernel, const void* X, int64_t nx, const void* Y, int64_t ny, int64_t d,
+                            int32_t dtype, void* workspace, size_t workspace_bytes, void* stream, double* K_out);
 
 /* ---------------------------------------------------------------- host-only helpers (no GPU) */
 

@@ -8,31 +8,35 @@ package loads libkkm.so and raises if it has not been built
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as ct
 import os
+import sys
+import weakref
 
 import numpy as np
 
 __all__ = [
     "KKM_OK", "KKM_KERNEL_LINEAR", "KKM_KERNEL_RBF", "KKM_KERNEL_RMSD", "KKM_F32", "KKM_F64",
-    "KKM_PREC_FP64", "KKM_PREC_FP32", "KKM_PREC_BF16X3", "KKM_SAMPLE_STRIDE", "KKM_SAMPLE_BLOCK",
+    "KKM_PREC_FP64", "KKM_PREC_FP32", "KKM_PREC_BF16", "KKM_PREC_BF16X3", "KKM_SAMPLE_STRIDE", "KKM_SAMPLE_BLOCK",
     "KKM_INIT_KMEANSPP", "KKM_INIT_RANDOM_LABELS", "KKM_INIT_MEDOIDS", "KkmError", "Model", "lib",
     "kkm_model_create", "kkm_model_load", "kkm_model_export", "kkm_model_shape", "kkm_fit",
     "kkm_fit_workspace_bytes", "kkm_fit_min_batches", "kkm_assign", "kkm_assign_workspace_bytes", "kkm_cost",
+    "kkm_kernel_block", "kkm_kernel_block_workspace_bytes",
     "kkm_landmark_count", "kkm_draw_landmarks", "kkm_draw_kmpp_uniforms", "kkm_draw_init_labels",
-    "kkm_version", "EXPORTED_SYMBOLS",
+    "kkm_version", "EXPORTED_SYMBOLS", "release_models",
 ]
 
 KKM_OK = 0
 KKM_KERNEL_LINEAR, KKM_KERNEL_RBF, KKM_KERNEL_RMSD = 0, 1, 2
 KKM_F32, KKM_F64 = 0, 1
-KKM_PREC_FP64, KKM_PREC_FP32, KKM_PREC_BF16X3 = 0, 1, 2
+KKM_PREC_FP64, KKM_PREC_FP32, KKM_PREC_BF16, KKM_PREC_BF16X3 = 0, 1, 2, 3
 KKM_SAMPLE_STRIDE, KKM_SAMPLE_BLOCK = 0, 1
 KKM_INIT_KMEANSPP, KKM_INIT_RANDOM_LABELS, KKM_INIT_MEDOIDS = 0, 1, 2
 KKM_FIT_COOPERATIVE = 1
 
 _KERNELS = {"linear": KKM_KERNEL_LINEAR, "rbf": KKM_KERNEL_RBF, "rmsd": KKM_KERNEL_RMSD}
-_PRECISIONS = {"fp64": KKM_PREC_FP64, "fp32": KKM_PREC_FP32, "bf16x3": KKM_PREC_BF16X3}
+_PRECISIONS = {"fp64": KKM_PREC_FP64, "fp32": KKM_PREC_FP32, "bf16": KKM_PREC_BF16, "bf16x3": KKM_PREC_BF16X3}
 _SAMPLING = {"stride": KKM_SAMPLE_STRIDE, "block": KKM_SAMPLE_BLOCK}
 _INITS = {"kmeans++": KKM_INIT_KMEANSPP, "random": KKM_INIT_RANDOM_LABELS, "medoids": KKM_INIT_MEDOIDS}
 
@@ -92,6 +96,10 @@ _SIGS = {
                               ct.c_size_t, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "kkm_cost": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_void_p,
                             ct.c_size_t, ct.c_void_p, ct.POINTER(ct.c_double)]),
+    "kkm_kernel_block_workspace_bytes": (ct.c_size_t, [ct.POINTER(_Kernel), ct.c_int64, ct.c_int64, ct.c_int64,
+                                                       ct.c_int32]),
+    "kkm_kernel_block": (ct.c_int, [ct.POINTER(_Kernel), ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64,
+                                    ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p]),
     "kkm_landmark_count": (ct.c_int64, [ct.c_int64, ct.c_double]),
     "kkm_draw_landmarks": (ct.c_int, [ct.c_uint64, ct.c_int32, ct.c_int64, ct.c_double, ct.POINTER(ct.c_int64)]),
     "kkm_draw_kmpp_uniforms": (ct.c_int, [ct.c_uint64, ct.c_int32, ct.POINTER(ct.c_double)]),
@@ -159,28 +167,97 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+class _OnStream:
+    """Runs a library call on `stream` (default: the current stream) in the order of the caller's
+    current stream: the library stream first waits for the current stream (which produced X), the
+    call's temporaries (contiguous copy, workspace, outputs) are allocated on the library stream, and
+    caller tensors read there are recorded on it, so the caching allocator does not hand their
+    memory out again before the library stream has finished with them."""
+
+    def __init__(self, stream):
+        import torch
+        self.torch = torch
+        self.cur = torch.cuda.current_stream()
+        self.s = stream if stream is not None else self.cur
+        self.other = self.s != self.cur
+
+    def __enter__(self):
+        if self.other:
+            self.s.wait_stream(self.cur)
+            self.ctx = self.torch.cuda.stream(self.s)
+            self.ctx.__enter__()
+        return self
+
+    def use(self, *tensors):
+        if self.other:
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self.s)
+
+    def __exit__(self, *exc):
+        if self.other:
+            self.ctx.__exit__(*exc)
+        return False
+
+
 def _workspace(nbytes: int, device):
     import torch
     return torch.empty(max(256, int(nbytes)), dtype=torch.uint8, device=device)
 
 
+_LIVE_MODELS = weakref.WeakSet()
+
+
 class Model:
-    """Owner of a kkm_model handle (device-resident sparse centroids)."""
+    """Owner of a kkm_model handle (device-resident sparse centroids).
+
+    The device memory is released when the object is collected, or at interpreter exit by
+    ``release_models`` (registered with atexit), which runs while the HIP runtime is still fully up;
+    a model still alive once the interpreter is finalising is left to the process exit instead of
+    calling into the runtime during teardown."""
 
     def __init__(self, ptr: int, kernel: _Kernel, d: int, C: int, dtype: int):
         self.ptr = ct.c_void_p(ptr)
         self.kernel = kernel
         self.d, self.C, self.dtype = d, C, dtype
+        _LIVE_MODELS.add(self)
 
-    def __del__(self, _lib=lib, _null=ct.c_void_p):
-        # default arguments keep the loader reachable while the interpreter shuts down
+    def free(self) -> None:
+        """Release the model's device memory now (the handle becomes empty)."""
         ptr = getattr(self, "ptr", None)
         if ptr is not None and ptr.value:
-            try:
-                _lib().kkm_model_free(ptr)
-            except Exception:
-                pass
-            self.ptr = _null(0)
+            lib().kkm_model_free(ptr)
+            self.ptr = ct.c_void_p(0)
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def release_models() -> None:
+    """Free every live model after the device has finished the work queued on it (called at exit,
+    before interpreter teardown; safe to call at any time: models freed here become empty)."""
+    live = [m for m in list(_LIVE_MODELS) if getattr(m, "ptr", None) is not None and m.ptr.value]
+    if not live:
+        return
+    try:
+        import torch
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for m in live:
+        try:
+            m.free()
+        except Exception:
+            pass
+
+
+atexit.register(release_models)
 
 
 def kkm_model_create(kernel="rbf", d=1, C=1, max_support=None, dtype="f32", sigma=1.0, n_atoms=0) -> Model:
@@ -280,7 +357,17 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     import torch
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
-    X = X.contiguous()
+    with _OnStream(stream) as os_:
+        os_.use(X, workspace)
+        return _kkm_fit(X.contiguous(), kernel, sigma, n_atoms, C, B, s, max_iter, sampling, init, precision, seed,
+                        landmarks, kmpp_uniforms, init_labels, init_medoids, model, workspace, os_.s, want_labels,
+                        time_phases, landmark_trace, cooperative, cost_trace)
+
+
+def _kkm_fit(X, kernel, sigma, n_atoms, C, B, s, max_iter, sampling, init, precision, seed, landmarks, kmpp_uniforms,
+             init_labels, init_medoids, model, workspace, stream, want_labels, time_phases, landmark_trace, cooperative,
+             cost_trace):
+    import torch
     N, d = X.shape
     k = _kernel(kernel, sigma, n_atoms)
     dt = _dtype_code(X)
@@ -331,32 +418,58 @@ def kkm_assign(model: Model, X, precision="fp32", want_gap=False, workspace=None
                stream=None):
     """Labels (int32 CUDA tensor) of the rows of X, and the relative margins if asked."""
     import torch
-    X = X.contiguous()
-    n = X.shape[0]
-    pr = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    need = kkm_assign_workspace_bytes(model, n, pr)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
-    if labels is None:
-        labels = torch.empty(n, dtype=torch.int32, device=X.device)
-    if want_gap and gap is None:
-        gap = torch.empty(n, dtype=torch.float32, device=X.device)
-    _check(lib().kkm_assign(model.ptr, ct.c_void_p(X.data_ptr()), n, _dtype_code(X), pr,
-                            ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(stream)),
-                            ct.c_void_p(labels.data_ptr()), ct.c_void_p(gap.data_ptr()) if gap is not None else None))
+    with _OnStream(stream) as os_:
+        os_.use(X, workspace, labels, gap)
+        X = X.contiguous()
+        n = X.shape[0]
+        pr = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        need = kkm_assign_workspace_bytes(model, n, pr)
+        ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+        if labels is None:
+            labels = torch.empty(n, dtype=torch.int32, device=X.device)
+        if want_gap and gap is None:
+            gap = torch.empty(n, dtype=torch.float32, device=X.device)
+        _check(lib().kkm_assign(model.ptr, ct.c_void_p(X.data_ptr()), n, _dtype_code(X), pr,
+                                ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(os_.s)),
+                                ct.c_void_p(labels.data_ptr()),
+                                ct.c_void_p(gap.data_ptr()) if gap is not None else None))
     return (labels, gap) if want_gap else labels
 
 
 def kkm_cost(model: Model, X, precision="fp32", workspace=None, stream=None) -> float:
     """Eq. 1 on the rows of X (FP64 sum in a fixed order)."""
-    X = X.contiguous()
-    n = X.shape[0]
-    pr = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    need = kkm_assign_workspace_bytes(model, n, pr)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
-    out = ct.c_double()
-    _check(lib().kkm_cost(model.ptr, ct.c_void_p(X.data_ptr()), n, _dtype_code(X), pr, ct.c_void_p(ws.data_ptr()),
-                          ws.numel(), ct.c_void_p(_stream_ptr(stream)), ct.byref(out)))
+    with _OnStream(stream) as os_:
+        os_.use(X, workspace)
+        X = X.contiguous()
+        n = X.shape[0]
+        pr = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        need = kkm_assign_workspace_bytes(model, n, pr)
+        ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+        out = ct.c_double()
+        _check(lib().kkm_cost(model.ptr, ct.c_void_p(X.data_ptr()), n, _dtype_code(X), pr,
+                              ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(os_.s)), ct.byref(out)))
     return out.value
+
+
+def kkm_kernel_block(X, Y, kernel="rbf", sigma=1.0, n_atoms=0, workspace=None, stream=None):
+    """K(x_i, y_j) in FP64 for the rows of X and Y (device tensors of one dtype): an nx x ny tensor."""
+    import torch
+    if X.dtype != Y.dtype or X.shape[1] != Y.shape[1]:
+        raise ValueError("X and Y need the same dtype and row length")
+    k = _kernel(kernel, sigma, n_atoms)
+    with _OnStream(stream) as os_:
+        os_.use(X, Y, workspace)
+        X, Y = X.contiguous(), Y.contiguous()
+        nx, d = X.shape
+        ny = Y.shape[0]
+        dt = _dtype_code(X)
+        need = int(lib().kkm_kernel_block_workspace_bytes(ct.byref(k), nx, ny, d, dt))
+        ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+        K = torch.empty((nx, ny), dtype=torch.float64, device=X.device)
+        _check(lib().kkm_kernel_block(ct.byref(k), ct.c_void_p(X.data_ptr()), nx, ct.c_void_p(Y.data_ptr()), ny, d, dt,
+                                      ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(os_.s)),
+                                      ct.c_void_p(K.data_ptr())))
+    return K
 
 
 def kkm_landmark_count(n: int, s: float) -> int:

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "kkm_internal.hpp"
@@ -15,34 +16,64 @@ namespace {
 // HIP events recorded on the caller's stream at the boundaries of the phases of a fit (optional):
 // back-to-back phases share their boundary event.  The events only time the stream, so they are
 // recorded without the system-scope fences (whose cache maintenance stalls the queue for several
-// microseconds per event).  The events are pooled per host thread and device and reused by later
-// calls (creating and destroying them is host work on every fit otherwise); they are not destroyed.
+// microseconds per event).
 // Timed spans of a fit: k-means++ / medoids; landmark block and initial labels; landmark loop kernel;
 // batch-wide distance kernel; FP64 re-decision; selection (column minima, medoids, merge).
 enum { kPhInit = 0, kPhLandmark = 1, kPhLoop = 2, kPhDist = 3, kPhRefine = 4, kPhSelect = 5, kPhases = 6 };
+
+// Process-wide free list of timing events per device.  A fit borrows events and hands them back when
+// it returns, so fits running concurrently on other host threads never share one, and later fits
+// reuse them (creating events is host work on every fit otherwise).  The pool is created on first
+// use and deliberately never destroyed: nothing of it runs during process teardown, when the HIP
+// runtime may already be shutting down.
+struct EventPool {
+    std::mutex mu;
+    std::map<int, std::vector<hipEvent_t>> free;
+    static EventPool& get() {
+        static EventPool* p = new EventPool;
+        return *p;
+    }
+    kkm_status take(int device, hipEvent_t* e) {
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto& f = free[device];
+            if (!f.empty()) {
+                *e = f.back();
+                f.pop_back();
+                return KKM_OK;
+            }
+        }
+        KKM_HIP(hipEventCreateWithFlags(e, hipEventDisableSystemFence));
+        return KKM_OK;
+    }
+    void give(int device, const std::vector<hipEvent_t>& evs) {
+        std::lock_guard<std::mutex> lock(mu);
+        auto& f = free[device];
+        f.insert(f.end(), evs.begin(), evs.end());
+    }
+};
 
 struct PhaseTimer {
     bool on = false;
     unsigned mask = ~0u;       // phases that are timed
     hipStream_t s = nullptr;
     int device = 0;
-    size_t used = 0;
-    std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;   // (phase, (begin, end) pool slots)
+    std::vector<hipEvent_t> evs;                                    // borrowed from the pool
+    std::vector<std::pair<int, std::pair<size_t, size_t>>> spans;   // (phase, (begin, end) indices into evs)
     size_t open = 0;
     bool open_valid = false;   // the last recorded event ends a phase and may begin the next one
-    static std::vector<hipEvent_t>& pool(int device) {
-        static thread_local std::map<int, std::vector<hipEvent_t>> pools;
-        return pools[device];
+    PhaseTimer() = default;
+    PhaseTimer(const PhaseTimer&) = delete;
+    PhaseTimer& operator=(const PhaseTimer&) = delete;
+    ~PhaseTimer() {
+        if (!evs.empty()) EventPool::get().give(device, evs);
     }
     kkm_status record(size_t* slot) {
-        auto& p = pool(device);
-        if (used == p.size()) {
-            hipEvent_t e;
-            KKM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
-            p.push_back(e);
-        }
-        *slot = used++;
-        KKM_HIP(hipEventRecord(p[*slot], s));
+        hipEvent_t e;
+        KKM_TRY(EventPool::get().take(device, &e));
+        evs.push_back(e);
+        *slot = evs.size() - 1;
+        KKM_HIP(hipEventRecord(e, s));
         return KKM_OK;
     }
     bool timed(int phase) const { return on && ((mask >> phase) & 1u); }
@@ -71,10 +102,9 @@ struct PhaseTimer {
     // after the stream has been synchronised
     void collect(double out[kPhases]) {
         for (int p = 0; p < kPhases; ++p) out[p] = 0.0;
-        auto& pl = pool(device);
         for (auto& sp : spans) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, pl[sp.second.first], pl[sp.second.second]) == hipSuccess) out[sp.first] += ms;
+            if (hipEventElapsedTime(&ms, evs[sp.second.first], evs[sp.second.second]) == hipSuccess) out[sp.first] += ms;
         }
     }
 };
@@ -260,7 +290,7 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
     if (p.sampling != KKM_SAMPLE_STRIDE && p.sampling != KKM_SAMPLE_BLOCK) return fail(KKM_ERR_INVALID_ARG, "bad sampling");
     if (p.init != KKM_INIT_KMEANSPP && p.init != KKM_INIT_RANDOM_LABELS && p.init != KKM_INIT_MEDOIDS)
         return fail(KKM_ERR_INVALID_ARG, "bad init");
-    if (p.precision != KKM_PREC_FP64 && p.precision != KKM_PREC_FP32 && p.precision != KKM_PREC_BF16X3)
+    if (p.precision < KKM_PREC_FP64 || p.precision > KKM_PREC_BF16X3)
         return fail(KKM_ERR_INVALID_ARG, "bad precision");
     if (p.flags & ~KKM_FIT_COOPERATIVE) return fail(KKM_ERR_INVALID_ARG, "unknown fit flags");
     P.N = N;
@@ -438,7 +468,7 @@ kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t d
     if (n < 0) return fail(KKM_ERR_INVALID_ARG, "n must be >= 0");
     if (n > 0 && !X) return fail(KKM_ERR_INVALID_ARG, "X is NULL");
     if (dtype != m->dtype) return fail(KKM_ERR_INVALID_ARG, "X dtype differs from the model dtype");
-    if (precision != KKM_PREC_FP64 && precision != KKM_PREC_FP32 && precision != KKM_PREC_BF16X3)
+    if (precision < KKM_PREC_FP64 || precision > KKM_PREC_BF16X3)
         return fail(KKM_ERR_INVALID_ARG, "bad precision");
     if (n >= (int64_t)1 << 31) return fail(KKM_ERR_UNSUPPORTED, "at most 2^31 - 1 rows per call");
     KKM_TRY(check_device_of(m));
@@ -476,6 +506,7 @@ kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t d
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
     KKM_TRY(launch_dist(da, dev, s));
     if (!dist_is_fp64(da)) KKM_TRY(launch_refine(da, dev, s, m->used));
+    if (want_best && dist_is_bf16(da)) KKM_TRY(launch_best64(da, dev, s));
     return KKM_OK;
 }
 
@@ -699,7 +730,10 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         DistArgs da{};
         da.q = bv;
         da.dtype = dtype;
-        da.precision = P.p.precision;
+        // the batch medoids take every row with D - E under the column minimum of D + E as a candidate:
+        // the plain BF16 bound would make nearly every row one, so a fit's batch pass takes the
+        // compensated BF16x3 products when BF16 is asked for
+        da.precision = P.p.precision == KKM_PREC_BF16 ? KKM_PREC_BF16X3 : P.p.precision;
         da.ks = ks;
         da.sup = sv;
         da.Dt = w.Dt;
@@ -830,6 +864,50 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     return KKM_OK;
 }
 
+size_t kkm_kernel_block_workspace_bytes(const kkm_kernel* kernel, int64_t nx, int64_t ny, int64_t d, int32_t dtype) {
+    if (!kernel || nx < 0 || ny < 0 || d < 1 || (dtype != KKM_F32 && dtype != KKM_F64)) return 0;
+    Carver c(nullptr);
+    const size_t es = dtype == KKM_F64 ? 8 : 4;
+    if (kernel->type == KKM_KERNEL_RMSD) {
+        c.take<char>((size_t)std::max<int64_t>(1, nx) * d * es);
+        c.take<char>((size_t)std::max<int64_t>(1, ny) * d * es);
+    }
+    return std::max<size_t>(c.off, 256);
+}
+
+kkm_status kkm_kernel_block(const kkm_kernel* kernel, const void* X, int64_t nx, const void* Y, int64_t ny, int64_t d,
+                            int32_t dtype, void* workspace, size_t workspace_bytes, void* stream, double* K_out) {
+    if (nx < 0 || ny < 0) return fail(KKM_ERR_INVALID_ARG, "nx and ny must be >= 0");
+    if (d < 1) return fail(KKM_ERR_INVALID_ARG, "d must be >= 1");
+    if (dtype != KKM_F32 && dtype != KKM_F64) return fail(KKM_ERR_INVALID_ARG, "bad dtype");
+    if (!kernel) return fail(KKM_ERR_INVALID_ARG, "kernel is NULL");
+    if (kernel->type != KKM_KERNEL_LINEAR && kernel->type != KKM_KERNEL_RBF && kernel->type != KKM_KERNEL_RMSD)
+        return fail(KKM_ERR_INVALID_ARG, "unknown kernel type");
+    if (kernel->type != KKM_KERNEL_LINEAR && !(kernel->sigma > 0.0 && std::isfinite(kernel->sigma)))
+        return fail(KKM_ERR_INVALID_ARG, "sigma must be finite and > 0");
+    if (kernel->type == KKM_KERNEL_RMSD && (kernel->n_atoms < 1 || d != 3 * (int64_t)kernel->n_atoms))
+        return fail(KKM_ERR_INVALID_ARG, "RMSD kernel needs d == 3 * n_atoms");
+    if (nx * ny > 0 && (!X || !Y || !K_out)) return fail(KKM_ERR_INVALID_ARG, "X, Y and K_out must not be NULL");
+    KKM_TRY(check_workspace(workspace, workspace_bytes, kkm_kernel_block_workspace_bytes(kernel, nx, ny, d, dtype)));
+    DeviceInfo dev;
+    KKM_TRY(device_info(&dev));
+    if (nx == 0 || ny == 0) return KKM_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const void* Xs = X;
+    const void* Ys = Y;
+    if (kernel->type == KKM_KERNEL_RMSD) {
+        Carver c(workspace);
+        const size_t es = dtype == KKM_F64 ? 8 : 4;
+        void* Xc = c.take<char>((size_t)nx * d * es);
+        void* Yc = c.take<char>((size_t)ny * d * es);
+        KKM_TRY(launch_centre(X, Xc, nx, kernel->n_atoms, dtype, s));
+        KKM_TRY(launch_centre(Y, Yc, ny, kernel->n_atoms, dtype, s));
+        Xs = Xc;
+        Ys = Yc;
+    }
+    return launch_kernel_block(kspec_of(*kernel, d), dtype, Xs, nx, Ys, ny, K_out, dev, s);
+}
+
 size_t kkm_assign_workspace_bytes(const kkm_model* m, int64_t n, int32_t precision) {
     if (!m || n < 0) return 0;
     (void)precision;
@@ -849,10 +927,13 @@ kkm_status kkm_assign(const kkm_model* m, const void* X, int64_t n, int32_t dtyp
 kkm_status kkm_cost(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
                     size_t ws_bytes, void* stream, double* cost_out) {
     if (!cost_out) return fail(KKM_ERR_INVALID_ARG, "cost_out is NULL");
-    AssignWs w;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!m) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
-    if (ws && ws_bytes >= kkm_assign_workspace_bytes(m, n, precision) && !(reinterpret_cast<uintptr_t>(ws) & 255)) {
+    if (n < 0) return fail(KKM_ERR_INVALID_ARG, "n must be >= 0");
+    // the labels of the pass live in the workspace: check it before carving them out
+    KKM_TRY(check_workspace(ws, ws_bytes, kkm_assign_workspace_bytes(m, n, precision)));
+    AssignWs w{};
+    {
         Carver c(ws);
         carve_assign(c, m, n, w);
     }

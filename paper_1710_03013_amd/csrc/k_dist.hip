@@ -466,6 +466,26 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
     }
 }
 
+// ----------------------------------------------------------------------------- FP64 best distance
+// best[q] = K(x,x) - 2 sum_{l in segment u_q} a_l K(x, s_l) + self_{u_q} in FP64 for the label u_q the
+// pass (and its re-decisions) settled on: the plain BF16 pass decides labels within its bound, but
+// its own distances are too coarse for a cost, so the cost takes this exact value of the chosen
+// cluster instead (one segment per row).
+template <typename TI, int DP>
+__global__ __launch_bounds__(256) void best64_kernel(DistArgs a) {
+    const int32_t* off = a.sup.offsets;
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.q.n; q += (int64_t)gridDim.x * blockDim.x) {
+        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+        const int j = a.labels[q];
+        const int lo = off[j], hi = off[j + 1];
+        double f = 0.0;
+        for (int l = lo; l < hi; ++l) f = fma(a.sup.coef64[l], k64p<DP>(a.ks, xr, rows + (int64_t)l * a.sup.dpad), f);
+        const double g = a.sup.self[j];
+        a.best[q] = (hi > lo && g < kInf) ? kself64(a.ks, xr) - 2.0 * f + g : kInf;
+    }
+}
+
 // ----------------------------------------------------------------------------- deterministic sum
 __global__ __launch_bounds__(256) void sum_partial_kernel(const double* __restrict__ v, int64_t n, int64_t chunk,
                                                           double* __restrict__ out) {
@@ -480,6 +500,21 @@ __global__ __launch_bounds__(256) void sum_partial_kernel(const double* __restri
         __syncthreads();
     }
     if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// ----------------------------------------------------------------------------- kernel block
+// K[i][j] = kappa(x_i, y_j) in FP64, one work-item per entry (grid-stride), consecutive work-items
+// on consecutive j so that the K stores are coalesced.  RMSD rows are centred frames.
+template <typename TI>
+__global__ __launch_bounds__(256) void kernel_block_kernel(KSpec ks, const TI* __restrict__ X, int64_t nx,
+                                                           const TI* __restrict__ Y, int64_t ny,
+                                                           double* __restrict__ K) {
+    const int64_t total = nx * ny;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ny, j = e - i * ny;
+        K[e] = k64(ks, X + i * ks.d, Y + j * ks.d);
+    }
 }
 
 // One wavefront per cluster: minimum of the workgroup partials of D + E.
@@ -584,6 +619,34 @@ kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
             else
                 hipLaunchKernelGGL((refine_kernel<float, DP>), dim3(blocks), dim3(256), lds, s, a);
         }
+        KKM_HIP(hipGetLastError());
+        return KKM_OK;
+    });
+}
+
+kkm_status launch_kernel_block(const KSpec& ks, int dtype, const void* X, int64_t nx, const void* Y, int64_t ny,
+                               double* K, const DeviceInfo& dev, hipStream_t s) {
+    const int64_t total = nx * ny;
+    if (total <= 0) return KKM_OK;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 64 * (int64_t)dev.num_cus);
+    if (dtype == KKM_F64)
+        hipLaunchKernelGGL(kernel_block_kernel<double>, dim3(blocks), dim3(256), 0, s, ks,
+                           static_cast<const double*>(X), nx, static_cast<const double*>(Y), ny, K);
+    else
+        hipLaunchKernelGGL(kernel_block_kernel<float>, dim3(blocks), dim3(256), 0, s, ks,
+                           static_cast<const float*>(X), nx, static_cast<const float*>(Y), ny, K);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+bool dist_is_bf16(const DistArgs& a) { return a.precision == KKM_PREC_BF16 && mfma_dist_applies(a); }
+
+kkm_status launch_best64(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    if (a.q.n <= 0 || !a.best) return KKM_OK;
+    const unsigned blocks = (unsigned)std::min<int64_t>((a.q.n + 255) / 256, 16 * (int64_t)dev.num_cus);
+    return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
+        if (a.dtype == KKM_F64) hipLaunchKernelGGL((best64_kernel<double, DP>), dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((best64_kernel<float, DP>), dim3(blocks), dim3(256), 0, s, a);
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     });

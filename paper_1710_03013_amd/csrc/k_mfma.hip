@@ -14,9 +14,22 @@
 // function is applied in registers, and each segment's sum is a masked sum over the lane's 16
 // values plus one exchange with the partner lane l^32, accumulated in the order of the tiles.
 //
-// Precision: FP32 (v_mfma_f32_32x32x2_f32), or BF16x3 -- x = hi + lo with hi, lo in bfloat16 and
-// x.s ~ hi.hi' + hi.lo' + lo.hi' on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Both carry a
-// per-row error bound, and near ties are decided again in FP64 (launch_refine).
+// Precision: FP32 (v_mfma_f32_32x32x2_f32); BF16 -- x.s ~ hi.hi' with hi = bfloat16(x), one
+// v_mfma_f32_32x32x16_bf16 per 16 dimensions, FP32 accumulation; or BF16x3 -- x = hi + lo with hi,
+// lo in bfloat16 and x.s ~ hi.hi' + hi.lo' + lo.hi' (three products).  Every form carries a per-row
+// error bound, and rows whose margin is under it are decided again in FP64 (launch_refine): BF16 is
+// the cheap pass that gates that refinement.
+//
+// Error of the bfloat16 forms (u = 2^-8, the unit roundoff of bfloat16 with round-to-nearest-even;
+// hi = RNE(x), lo = RNE(x - hi), r = x - hi - lo):  |x - hi| <= u|x|, |hi| <= (1 + u)|x|,
+// |lo| <= u(1 + u)|x|, |r| <= u|x - hi| <= u^2|x|.
+//   BF16:   x.y - hi.hi' = (x - hi) y + hi (y - hi'), so per product |.| <= u(2 + u)|x||y|.
+//   BF16x3: x.y - (hi.hi' + hi.lo' + lo.hi') = lo.lo' + hi.r' + r.hi' + lo.r' + r.lo' + r.r', each
+//           term bounded by the facts above: in all <= u^2 (3 + 6u)|x||y| <= 3 u^2 (1 + 2^-7)|x||y|.
+// Summed over the dimensions this is at most the constant times sum_k |x_k||y_k| <= ||x|| ||y||.  The
+// bfloat16 products are exact in FP32; their FP32 accumulation adds the (P DP + 2) u32 terms
+// (P = products per dimension).  Inputs below 2^-118 in magnitude (bfloat16 subnormal remainders) are
+// outside these relative bounds.
 #include <cstdlib>
 
 #include "kkm_internal.hpp"
@@ -30,7 +43,11 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kU32 = 5.9604645e-8f;     // unit roundoff of float
-constexpr float kUbf = 3.0517578e-5f;     // 2^-15: three neglected terms of order 2^-16 |x||y| each
+constexpr float kUbf1 = 7.8277588e-3f;    // BF16:   u (2 + u) = 2^-7 (1 + 2^-9), u = 2^-8
+constexpr float kUbf3 = 4.6134e-5f;       // BF16x3: 3 u^2 (1 + 2^-7) = 3 * 2^-16 * (1 + 2^-7), rounded up
+
+// precision modes of the pass
+constexpr int kPmF32 = 0, kPmBf16 = 1, kPmBf16x3 = 3;
 
 __device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float sn, float inv2s2) {
     if (type == KKM_KERNEL_LINEAR) return dot;
@@ -39,8 +56,10 @@ __device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float
     return __builtin_amdgcn_exp2f(-d2 * inv2s2 * 1.4426950408889634f);
 }
 
-template <typename TI, int DP, bool BF3, int NW>
+template <typename TI, int DP, int PM, int NW>
 __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
+    constexpr bool BF = PM != kPmF32;         // bfloat16 operands
+    constexpr bool BF3 = PM == kPmBf16x3;     // with the remainder products
     constexpr int H = DP / 2;                      // dimensions per lane half
     constexpr int NH = NW / 4;                     // wavefronts per quarter of the support
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -109,8 +128,8 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     qn += __shfl_xor(qn, 32, 64);
     if (active && !ok) atomicOr(a.nonfinite, 1);   // either half may hold the bad value
     const float kqq = type == KKM_KERNEL_LINEAR ? qn : 1.0f;
-    bf16x8 bh[BF3 ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
-    if constexpr (BF3) {
+    bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
+    if constexpr (BF) {
 #pragma unroll
         for (int v = 0; v < H / 8; ++v)
 #pragma unroll
@@ -118,7 +137,7 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
                 const float x = xq[8 * v + t];
                 const __bf16 hi = (__bf16)x;
                 bh[v][t] = hi;
-                bl[v][t] = (__bf16)(x - (float)hi);
+                if constexpr (BF3) bl[v][t] = (__bf16)(x - (float)hi);
             }
     }
     const int quarter = wave & 3, half = wave >> 2;
@@ -142,7 +161,14 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
         // tile (64 consecutive vectors per step group)
         const int64_t tile = r0 >> 5;
         floatx16 acc = {};
-        if constexpr (BF3) {
+        if constexpr (PM == kPmBf16) {
+            const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi) + tile * (H / 8) * 64 + lane;
+            bf16x8 xh[H / 8];
+#pragma unroll
+            for (int v = 0; v < H / 8; ++v) xh[v] = ah[v * 64];
+#pragma unroll
+            for (int v = 0; v < H / 8; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bh[v], acc, 0, 0, 0);
+        } else if constexpr (BF3) {
             const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi) + tile * (H / 8) * 64 + lane;
             const bf16x8* al = reinterpret_cast<const bf16x8*>(a.sup.lo) + tile * (H / 8) * 64 + lane;
             bf16x8 xh[H / 8], xl[H / 8];
@@ -260,7 +286,8 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     float egap = 0.0f, ecol = 0.0f;
     double b1 = kInf, b2 = kInf;
     int i1 = C;
-    const float dot_rel = BF3 ? kUbf + (3.0f * DP + 2.0f) * kU32 : (DP + 2.0f) * kU32;
+    const float dot_rel = BF3 ? kUbf3 + (3.0f * DP + 2.0f) * kU32
+                        : BF ? kUbf1 + (DP + 3.0f) * kU32 : (DP + 2.0f) * kU32;
     const float kmax = sqrtf(qn * snmax) * 1.0001f;
     for (int jj = j0 + h; half == 0 && jj < j1; jj += 2) {
         const int lo = off[jj], hi = off[jj + 1];
@@ -368,7 +395,7 @@ size_t mfma_lds_static(int nw) {
     return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 + 64;
 }
 
-template <typename TI, bool BF3, int NW>
+template <typename TI, int PM, int NW>
 kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsigned blocks) {
     const size_t lds = mfma_lds_dynamic((size_t)a.sup.C, NW);
     auto go = [&](auto fn) -> kkm_status {
@@ -378,18 +405,18 @@ kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsi
         return KKM_OK;
     };
     switch (a.sup.dpad) {
-        case 4: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 4, false, NW>); break;
-        case 8: if constexpr (!BF3) return go(mfma_dist_kernel<TI, 8, false, NW>); break;
-        case 16: return go(mfma_dist_kernel<TI, 16, BF3, NW>);
-        case 32: return go(mfma_dist_kernel<TI, 32, BF3, NW>);
-        case 64: return go(mfma_dist_kernel<TI, 64, BF3, NW>);
-        case 128: return go(mfma_dist_kernel<TI, 128, BF3, NW>);
+        case 4: if constexpr (PM == kPmF32) return go(mfma_dist_kernel<TI, 4, PM, NW>); break;
+        case 8: if constexpr (PM == kPmF32) return go(mfma_dist_kernel<TI, 8, PM, NW>); break;
+        case 16: return go(mfma_dist_kernel<TI, 16, PM, NW>);
+        case 32: return go(mfma_dist_kernel<TI, 32, PM, NW>);
+        case 64: return go(mfma_dist_kernel<TI, 64, PM, NW>);
+        case 128: return go(mfma_dist_kernel<TI, 128, PM, NW>);
         default: break;
     }
     return fail(KKM_ERR_UNSUPPORTED, "matrix-core distance pass: unsupported padded dimension");
 }
 
-template <typename TI, bool BF3>
+template <typename TI, int PM>
 kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     const size_t C = (size_t)a.sup.C;
     if (mfma_lds_dynamic(C, 4) + mfma_lds_static(4) > dev.max_lds_per_block)
@@ -403,8 +430,8 @@ kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
                        mfma_lds_dynamic(C, 8) + mfma_lds_static(8) <= dev.max_lds_per_block;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
     if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
-    const kkm_status st = eight ? launch_mfma_nw<TI, BF3, 8>(a, s, groups, blocks)
-                                : launch_mfma_nw<TI, BF3, 4>(a, s, groups, blocks);
+    const kkm_status st = eight ? launch_mfma_nw<TI, PM, 8>(a, s, groups, blocks)
+                                : launch_mfma_nw<TI, PM, 4>(a, s, groups, blocks);
     if (st != KKM_OK) return st;
     if (a.colmin && a.colpart_blocks) *a.colpart_blocks = groups;
     return KKM_OK;
@@ -419,13 +446,15 @@ bool mfma_dist_applies(const DistArgs& a) {
     }();
     if (off || a.ks.type == KKM_KERNEL_RMSD || a.precision == KKM_PREC_FP64 || a.dtype != KKM_F32) return false;
     if (a.precision == KKM_PREC_BF16X3) return a.sup.hi && a.sup.lo && a.sup.dpad >= 16;
+    if (a.precision == KKM_PREC_BF16) return a.sup.hi && a.sup.dpad >= 16;
     return a.sup.pan != nullptr;
 }
 
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     if (a.q.n <= 0) return KKM_OK;
-    if (a.precision == KKM_PREC_BF16X3) return launch_mfma_t<float, true>(a, dev, s);
-    return launch_mfma_t<float, false>(a, dev, s);
+    if (a.precision == KKM_PREC_BF16X3) return launch_mfma_t<float, kPmBf16x3>(a, dev, s);
+    if (a.precision == KKM_PREC_BF16) return launch_mfma_t<float, kPmBf16>(a, dev, s);
+    return launch_mfma_t<float, kPmF32>(a, dev, s);
 }
 
 }  // namespace kkm

@@ -253,10 +253,53 @@ __device__ __forceinline__ void horn_key(const T R[9], T N[4][4]) {
     N[2][1] = N[1][2]; N[3][1] = N[1][3]; N[3][2] = N[2][3];
 }
 
+// Largest eigenvalue of a symmetric 4x4 matrix by cyclic Jacobi rotations (Golub and Van Loan,
+// "Matrix Computations", Sec. 8.5): each rotation zeroes one off-diagonal pair; sweeps repeat until
+// the off-diagonal mass is negligible against the diagonal.  Backward stable, so the eigenvalue is
+// accurate to a few units of roundoff of ||N|| whatever the multiplicity.  N is overwritten.
+__device__ inline double sym4_max_eig_jacobi(double N[4][4]) {
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            diag += N[i][i] * N[i][i];
+            for (int j = i + 1; j < 4; ++j) off += N[i][j] * N[i][j];
+        }
+        if (off <= 1e-36 * diag || off == 0.0) break;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                const double apq = N[p][q];
+                if (apq == 0.0) continue;
+                // rotation angle: t = tan(theta) as the smaller root of t^2 + 2 tau t - 1 = 0
+                const double tau = (N[q][q] - N[p][p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+                for (int k = 0; k < 4; ++k) {   // columns p, q
+                    const double kp = N[k][p], kq = N[k][q];
+                    N[k][p] = c * kp - sn * kq;
+                    N[k][q] = sn * kp + c * kq;
+                }
+                for (int k = 0; k < 4; ++k) {   // rows p, q
+                    const double pk = N[p][k], qk = N[q][k];
+                    N[p][k] = c * pk - sn * qk;
+                    N[q][k] = sn * pk + c * qk;
+                }
+                N[p][q] = N[q][p] = 0.0;
+            }
+    }
+    return fmax(fmax(N[0][0], N[1][1]), fmax(N[2][2], N[3][3]));
+}
+
+// Iterations after which Newton's method counts as slow: from the upper bound a simple largest root
+// is reached in about ten; more means a (near) multiple root, where the iteration converges only
+// linearly and the polynomial's rounding limits the root to about the square root of the unit
+// roundoff.  Such pairs are solved again by Jacobi rotations of the key matrix.
+constexpr int kNewtonSlow = 20;
+
 // Largest eigenvalue of the key matrix by Newton's method on its characteristic polynomial
 // lambda^4 + c2 lambda^2 + c1 lambda + c0 (c2 = -tr(N^2)/2, c1 = -tr(N^3)/3, c0 = det N),
 // started from the upper bound (Ga + Gb)/2; the polynomial is convex above its largest root, so
-// the iterates decrease monotonically onto it.  Returns RMSD^2 = max(0, (Ga + Gb - 2 lambda) / A).
+// the iterates decrease monotonically onto it.  A slow iteration (kNewtonSlow) falls back to
+// Jacobi rotations.  Returns RMSD^2 = max(0, (Ga + Gb - 2 lambda) / A).
 __device__ inline double rmsd2_from_corr64(const double R[9], double Ga, double Gb, int A) {
     double N[4][4];
     horn_key(R, N);
@@ -275,14 +318,22 @@ __device__ inline double rmsd2_from_corr64(const double R[9], double Ga, double 
     const double c2 = -0.5 * tr2, c1 = -tr3 / 3.0, c0 = det4(N);
     const double E0 = 0.5 * (Ga + Gb);
     double lam = E0;
-    for (int it = 0; it < 60; ++it) {
+    bool converged = false;
+    for (int it = 0; it < kNewtonSlow; ++it) {
         const double l2 = lam * lam;
         const double p = (l2 + c2) * l2 + c1 * lam + c0;
         const double dp = (4.0 * l2 + 2.0 * c2) * lam + c1;
         if (!(dp > 0.0)) break;
         const double step = p / dp;
         lam -= step;
-        if (fabs(step) <= 1e-15 * E0) break;
+        if (fabs(step) <= 1e-15 * E0) {
+            converged = true;
+            break;
+        }
+    }
+    if (!converged) {
+        horn_key(R, N);
+        lam = sym4_max_eig_jacobi(N);
     }
     const double r2 = (Ga + Gb - 2.0 * lam) / A;
     return r2 > 0.0 ? r2 : 0.0;

@@ -122,7 +122,7 @@ struct DistArgs {
     int64_t n_support;      // rows of sup (offsets[C])
 };
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
-// Matrix-core distance pass (k_mfma.hip): linear / RBF, float samples, FP32 or BF16x3.
+// Matrix-core distance pass (k_mfma.hip): linear / RBF, float samples, FP32, BF16 or BF16x3.
 bool mfma_dist_applies(const DistArgs& a);
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
 // True when launch_dist evaluates (and stores Dt) in FP64 for these arguments.
@@ -134,6 +134,13 @@ inline int64_t dist_block_cap(int64_t n) { return (n + 15) / 16 + 1; }
 // colmin[j] <- ord_enc(min over the first nblk entries of colpart row j) (~0: none finite).
 // FP64 re-decision of the rows listed by launch_dist (n_support: support rows of a.sup).
 kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s, int64_t n_support);
+// True when launch_dist runs the plain BF16 matrix-core pass for these arguments.
+bool dist_is_bf16(const DistArgs& a);
+// a.best[q] <- the FP64 distance of row q to the cluster of a.labels[q] (after launch_refine).
+kkm_status launch_best64(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
+// K[i * ny + j] = kappa(x_i, y_j) in FP64 for rows of length ks.d (RMSD: centred frames).
+kkm_status launch_kernel_block(const KSpec& ks, int dtype, const void* X, int64_t nx, const void* Y, int64_t ny,
+                               double* K, const DeviceInfo& dev, hipStream_t s);
 // Deterministic FP64 sum of best[0..n) into out[0] (partials: >= 1024 doubles of scratch).
 kkm_status launch_sum(const double* best, int64_t n, double* partials, double* out, hipStream_t s);
 

@@ -10,6 +10,11 @@ within each kind, so a waiting fit does not hold back assign requests) while
     streams; ``fit_workers`` fits, each on its own stream and host thread, because
     ``kkm_fit`` returns host data and therefore waits for its stream).
 
+A request's rows may still be in production on the submitter's stream when it is submitted: the
+backend marks that point of the stream at submission (``mark_ready``), and the server stream that
+takes the request waits for the mark before reading the rows, which are also recorded on it so that
+their memory is not reused while it reads them.
+
 Small assign requests for the same model that are queued together are coalesced into one
 ``kkm_assign`` launch (rows concatenated, labels split back): every row's label depends only on
 that row and the model, so a request's labels are the same alone and in a batch.  Work admitted
@@ -44,6 +49,7 @@ class Request:
     result: Any = None
     error: Optional[BaseException] = None
     mem: int = 0
+    ready: Any = None              # backend mark of the point where X is complete (or None)
 
     @property
     def done(self) -> bool:
@@ -88,10 +94,24 @@ class KkmBackend:
         model = (C + 32) * (d * 4 + 64) + 4096
         return ws + model + 4 * N
 
+    # ---- ordering with the submitter's stream
+    def mark_ready(self, X):
+        """An event recorded on the submitter's current stream: X is complete once it has fired."""
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(X.device))
+        return ev
+
+    def _take(self, s, xs, ready):
+        for x, ev in zip(xs, ready or [None] * len(xs)):
+            if ev is not None:
+                s.wait_event(ev)
+            x.record_stream(s)
+
     # ---- assign
-    def launch_assign(self, model, xs: List[Any], slot: int):
+    def launch_assign(self, model, xs: List[Any], slot: int, ready: Optional[List[Any]] = None):
         torch = self.torch
         s = self.streams[slot % len(self.streams)]
+        self._take(s, xs, ready)
         with torch.cuda.stream(s):
             X = xs[0] if len(xs) == 1 else torch.cat(xs, 0)
             labels = self._assign(model, X, precision=self.precision, stream=s)
@@ -110,9 +130,10 @@ class KkmBackend:
         return out
 
     # ---- fit (its own stream and host thread)
-    def start_fit(self, X, kw, slot: int):
+    def start_fit(self, X, kw, slot: int, ready: Optional[List[Any]] = None):
         torch = self.torch
         s = torch.cuda.Stream(device=self.dev)
+        self._take(s, [X], ready)
         box: Dict[str, Any] = {}
 
         def run():
@@ -166,12 +187,18 @@ class Server:
         if model not in self.models:
             raise KeyError(f"unknown model {model!r}")
         r = Request("assign", self.clock() if arrival is None else arrival, model=model, X=X, n=int(X.shape[0]))
+        r.ready = self._mark(X)
         self.queue.append(r)
         return r
+
+    def _mark(self, X):
+        mark = getattr(self.backend, "mark_ready", None)
+        return mark(X) if mark is not None else None
 
     def submit_fit(self, X, register_as: Optional[str] = None, arrival: Optional[float] = None, **fit_kwargs) -> Request:
         r = Request("fit", self.clock() if arrival is None else arrival, X=X, n=int(X.shape[0]),
                     fit_kwargs=fit_kwargs, register_as=register_as)
+        r.ready = self._mark(X)
         self.queue.append(r)
         return r
 
@@ -230,7 +257,7 @@ class Server:
                     blocked.add("fit")
                     continue
                 del self.queue[i]
-                h = self.backend.start_fit(head.X, head.fit_kwargs, self._slot)
+                h = self.backend.start_fit(head.X, head.fit_kwargs, self._slot, ready=[head.ready])
                 group = [head]
                 kind = "fit"
             else:
@@ -266,7 +293,8 @@ class Server:
                     continue
                 ids = {id(r) for r in group}
                 self.queue = collections.deque(r for r in self.queue if id(r) not in ids)
-                h = self.backend.launch_assign(model, [r.X for r in group], self._slot)
+                h = self.backend.launch_assign(model, [r.X for r in group], self._slot,
+                                               ready=[r.ready for r in group])
                 kind = "assign"
             now = self.clock()
             for r in group:

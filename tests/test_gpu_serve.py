@@ -58,3 +58,30 @@ def test_results_same_alone_and_in_the_mix(setup, precision):
     for key in ("medoid_index", "counts"):
         np.testing.assert_array_equal(got[key], ref[key])
     np.testing.assert_array_equal(got["support"], ref["support"])
+
+
+def test_rows_written_on_the_submitting_stream(setup):
+    """Rows produced by a kernel on the submitter's stream right before submission, with no host
+    synchronisation: the server's streams must wait for them (a long matrix product runs first, and
+    the rows are written after it)."""
+    kk, Xd, model = setup
+    from paper_1710_03013_amd.serve import KkmBackend, Server
+    sizes, starts = [5000, 300, 20_000, 64], [100, 7000, 30_000, 55_000]
+    alone = [kk.kkm_assign(model, Xd[s:s + n]).cpu().numpy() for s, n in zip(starts, sizes)]
+    torch.cuda.synchronize()
+    srv = Server(KkmBackend(n_streams=2), budget_bytes=8 << 30, assign_slots=2, fit_workers=1)
+    srv.add_model("m", model)
+    a = torch.randn(4096, 4096, device="cuda") / 64.0
+    reqs = []
+    for s, n in zip(starts, sizes):
+        busy = a
+        for _ in range(6):
+            busy = busy @ a
+        y = torch.empty_like(Xd[s:s + n])
+        torch.add(Xd[s:s + n], busy[0, 0], alpha=0.0, out=y)   # written only after the products
+        reqs.append(srv.submit_assign("m", y))
+        del y, busy
+    srv.run_until_idle(timeout=120)
+    for r, want in zip(reqs, alone):
+        assert r.error is None
+        np.testing.assert_array_equal(r.result.cpu().numpy(), want)

@@ -38,7 +38,7 @@ class FakeBackend:
     def fit_bytes(self, X, kw):
         return 1000 + 16 * X.shape[0]
 
-    def launch_assign(self, model, xs, slot):
+    def launch_assign(self, model, xs, slot, ready=None):
         X = np.concatenate(xs, 0)
         self.launches.append(("assign", [x.shape[0] for x in xs]))
         return {"t": self.clock() + self.latency, "labels": model.labels(X), "sizes": [x.shape[0] for x in xs]}
@@ -53,7 +53,7 @@ class FakeBackend:
             o += n
         return out
 
-    def start_fit(self, X, kw, slot):
+    def start_fit(self, X, kw, slot, ready=None):
         self.launches.append(("fit", X.shape[0]))
         C = kw["C"]
         return {"t": self.clock() + 3 * self.latency, "model": FakeModel(X.shape[1], X[:C])}
