@@ -2,19 +2,23 @@
 """Throughput of the mini-batch landmark kernel k-means hot path on one MI355X.
 
 One step = the whole path on one synthetic dataset, inputs already in HBM:
-  kkm_fit   -- per mini-batch: landmark block + landmark loop (one kernel with
-               grid barriers), the batch-wide distance pass with FP64 re-decisions,
-               member counts, batch medoids (Eq. 10) and the merge (Eq. 11-13);
+  kkm_fit    -- seed only: the library draws the landmarks and the k-means++ uniforms on the host
+                inside the step; then per mini-batch the landmark block and loop, the batch-wide
+                distance pass with FP64 re-decisions, member counts, batch medoids (Eq. 10) and the
+                merge (Eq. 11-13);
   kkm_assign -- every sample of the dataset against the fitted medoids (Eq. 2).
 
-Default workload: N = 100 000 samples, d = 16, a 20-component isotropic Gaussian
-mixture (means uniform in [-10, 10]^16, std 1, float32), RBF sigma = 4,
-C = 20, B = 10 mini-batches, s = 0.1 (1000 landmarks per batch), T = 20.
+Default workload: the 64-d precision workload -- N = 10^6 samples, a 100-component anisotropic
+Gaussian mixture (means uniform in [-10, 10]^64, per-dimension std uniform in [0.5, 2], float32),
+RBF sigma = 8, C = 100, B = 50 mini-batches, s = 0.02 (400 landmarks per batch), T = 20 -- timed in
+the plain FP32 form and in the bfloat16 forms (BF16x3: split products; BF16: one product gating the
+FP64 re-decisions), each for --steps steps after --warmup.
 
-Metric: algorithmic kernel evaluations per second (Eq. 18's n|L| per batch plus
-the n x C medoid blocks, plus N x C for the assign pass).  Printed as one JSON
-line with a roofline entry for the dominant kernel (timed with HIP events on the
-library's stream inside the timed steps) and the FP64 oracle timed on the host.
+Metric: algorithmic kernel evaluations per second (Eq. 18's n|L| per batch plus the n x C medoid
+blocks, plus N x C for the assign pass) and samples assigned per second, FP32 against the bfloat16
+forms, with the assign latency at a fixed request size.  Printed as one JSON line with a roofline
+entry for the dominant kernel (HIP events on the library's stream inside the timed steps) and the
+FP64 oracle timed on the host on a bounded prefix of the same workload.
 """
 from __future__ import annotations
 
@@ -41,10 +45,6 @@ WORKLOADS = {
 PEAK_FP32_VECTOR = 157.3e12   # published MI355X FP32 FLOP/s (vector and matrix cores)
 PEAK_FP64_VECTOR = 78.6e12    # published MI355X FP64 FLOP/s
 PEAK_BF16_MATRIX = 2.5e15     # published MI355X dense BF16 matrix-core FLOP/s
-
-# kernel names as rocprofv3 reports them, per (kernel function, precision)
-DIST_KERNEL_NAME = {("rbf", "fp32"): "mfma_dist_kernel", ("linear", "fp32"): "mfma_dist_kernel",
-                    ("rbf", "bf16x3"): "mfma_dist_kernel", ("linear", "bf16x3"): "mfma_dist_kernel"}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel
 # calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
@@ -95,8 +95,11 @@ def landmark_flops_per_launch(ell: int, updates: int, C: int) -> float:
     return (updates + 1) * (ell * ell + ell + 3 * ell * C)
 
 
-def cpu_baseline(X, cfg, landmarks, uniforms, init_labels):
-    """The FP64 oracle, as it stands, on the same workload (one whole fit + one assign pass)."""
+def cpu_baseline(X, cfg, seed, max_batches):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: the fit of the first
+    `max_batches` stride batches (a prefix of the step's fit, same per-batch sizes and draws) and an
+    assign pass of one batch's rows against the resulting medoids."""
+    import kkm_inputs as ki
     from oracle import kkm as okkm
     from oracle.kernels import Kernel
     try:
@@ -104,17 +107,28 @@ def cpu_baseline(X, cfg, landmarks, uniforms, init_labels):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
+    N, B = X.shape[0], cfg["B"]
+    k = min(B, max_batches)
+    n = (N + B - 1) // B
+    idx = np.asarray([i + B * j for j in range(n) for i in range(k) if i + B * j < N])
+    Xp = X[idx]
+    L = ki.draw_all_landmarks(seed, N, B, cfg["s"])[:k]
     kern = Kernel(cfg["kernel"], cfg.get("sigma", 1.0), cfg.get("n_atoms", 0))
+    uniforms = ki.draw_kmpp_uniforms(seed, cfg["C"]) if cfg["init"] == "kmeans++" else None
+    init_labels = (ki.draw_init_labels(seed, len(ki.batch_index_sets(N, B)[0]), cfg["C"])
+                   if cfg["init"] == "random" else None)
     t0 = time.perf_counter()
-    ref = okkm.fit(X, cfg["C"], kern, cfg["B"], cfg["T"], landmarks, init=cfg["init"],
-                   kmpp_uniforms=uniforms, init_labels=init_labels)
+    ref = okkm.fit(Xp, cfg["C"], kern, k, cfg["T"], L, init=cfg["init"], kmpp_uniforms=uniforms,
+                   init_labels=init_labels)
     t1 = time.perf_counter()
-    okkm.assign(kern, X, okkm.medoid_model(ref))
+    rows = Xp[: len(idx) // k]
+    okkm.assign(kern, rows, okkm.medoid_model(ref))
     t2 = time.perf_counter()
-    evals = ref.evals + X.shape[0] * cfg["C"]
+    evals = ref.evals + rows.shape[0] * cfg["C"]
     return {"value": evals / (t2 - t0), "unit": "kernel evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full fit ({t1 - t0:.1f} s) and one assign pass ({t2 - t1:.1f} s) of the same workload; "
-                      f"BLAS threads={threads}, numpy elementwise single-threaded"}
+            "sample": f"fit of the first {k} of {B} stride batches ({len(idx)} samples, {t1 - t0:.1f} s) and an "
+                      f"assign pass of {rows.shape[0]} samples ({t2 - t1:.1f} s); BLAS threads={threads}, numpy "
+                      f"elementwise single-threaded"}
 
 
 def serving_bench(args) -> int:
@@ -250,10 +264,11 @@ def restarts_bench(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mixture16", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--workload", default="mixture64", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16x3", "bf16"],
+                    help="one form only (default: FP32 and the bfloat16 forms where they apply)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-requests", type=int, default=200)
     ap.add_argument("--latency-size", type=int, default=4096)
@@ -294,135 +309,199 @@ def main() -> int:
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 10}), flush=True)
         del src, dst
         return 0
+    return step_bench(args)
+
+
+# bounded oracle sample per workload: stride batches of the fit (about 10-30 s of host work)
+CPU_BASELINE_BATCHES = {"mixture64": 2, "mixture16": 10, "md": 1, "rings": 1}
+
+
+def step_bench(args) -> int:
+    import torch
+    import kkm_inputs as ki
+    import paper_1710_03013_amd as kk
+
     k_idx, desc = WORKLOADS[args.workload]
     cfg = dict(ki.datasets.CONFIGS[k_idx])
-    prec = args.precision or ("fp64" if cfg["dtype"] == "f64" else "fp32")
+    if args.precision:
+        precs = [args.precision]
+    elif cfg["dtype"] == "f64":
+        precs = ["fp64"]
+    elif cfg["kernel"] == "rmsd":
+        precs = ["fp32"]            # the bfloat16 forms are matrix-core forms of linear / RBF kernels
+    else:
+        precs = ["fp32", "bf16x3", "bf16"]
     seed = 2000 + k_idx
     log(f"[bench] generating {desc}")
     X, _ = ki.datasets.config_data(k_idx)
     N, d = X.shape
     C, B, s, T = cfg["C"], cfg["B"], cfg["s"], cfg["T"]
-    landmarks = ki.draw_all_landmarks(seed, N, B, s)
-    uniforms = ki.draw_kmpp_uniforms(seed, C) if cfg["init"] == "kmeans++" else None
-    n0 = len(ki.batch_index_sets(N, B)[0])
-    init_labels = ki.draw_init_labels(seed, n0, C) if cfg["init"] == "random" else None
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
-    log(f"[bench] device {props.name} CUs={props.multi_processor_count} "
-        f"lds/block={getattr(props, 'shared_memory_per_block', '?')}")
+    log(f"[bench] device {props.name} CUs={props.multi_processor_count}")
     Xd = torch.from_numpy(X).to(dev)
-    fit_kw = dict(kernel=cfg["kernel"], sigma=cfg.get("sigma", 1.0), n_atoms=cfg.get("n_atoms", 0), C=C, B=B, s=s,
-                  max_iter=T, init=cfg["init"], precision=prec, seed=seed, landmarks=landmarks,
-                  kmpp_uniforms=uniforms, init_labels=init_labels)
-    model = kk.kkm_model_create(cfg["kernel"], d=d, C=C, dtype=cfg["dtype"], sigma=cfg.get("sigma", 1.0),
-                                n_atoms=cfg.get("n_atoms", 0))
-    wbytes = kk.kkm_fit(Xd, model=model, **fit_kw)[2]["workspace_bytes"]
-    ws = torch.empty(wbytes, dtype=torch.uint8, device=dev)
-    labels = torch.empty(N, dtype=torch.int32, device=dev)
-    aws = torch.empty(max(256, kk.kkm_assign_workspace_bytes(model, N, prec)), dtype=torch.uint8, device=dev)
-
-    def step(time_phases=False):
-        _, _, info = kk.kkm_fit(Xd, model=model, workspace=ws, want_labels=True, time_phases=time_phases,
-                                **fit_kw)
-        kk.kkm_assign(model, Xd, precision=prec, workspace=aws, labels=labels)
-        return info
-
-    for w in range(args.warmup):
-        step()
-        log(f"[bench] warmup {w + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        # events only around the two candidate dominant kernels (three per batch)
-        infos.append(step(time_phases=0 if args.no_phase_timing else 2))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"[bench] {args.steps} timed steps in {t1 - t0:.3f} s")
-    # the breakdown over all phases from one more (untimed) step with events around every phase
-    phase_info = step(time_phases=True) if not args.no_phase_timing else None
-    torch.cuda.synchronize()
-    elapsed = t1 - t0
-    info = infos[-1]
-    evals_step = info["evals_algorithmic"] + N * C
-    value = evals_step * args.steps / elapsed
     batch_n = [len(ix) for ix in ki.batch_index_sets(N, B)]
-    assigned_step = int(np.dot(batch_n, info["updates_per_batch"])) + N
-    ms = ({k_: float(np.mean([i["ms"][k_] for i in infos])) for k_ in infos[0]["ms"]}
-          if not args.no_phase_timing else None)
+    ells = [ki.landmark_count(n, s) for n in batch_n]
+    results, lab_by_prec, models = {}, {}, {}
+    for prec in precs:
+        # seed-only fits: the library draws the landmarks and k-means++ uniforms inside every step
+        fit_kw = dict(kernel=cfg["kernel"], sigma=cfg.get("sigma", 1.0), n_atoms=cfg.get("n_atoms", 0), C=C, B=B,
+                      s=s, max_iter=T, init=cfg["init"], precision=prec, seed=seed)
+        model = kk.kkm_model_create(cfg["kernel"], d=d, C=C, dtype=cfg["dtype"], sigma=cfg.get("sigma", 1.0),
+                                    n_atoms=cfg.get("n_atoms", 0))
+        wbytes = kk.kkm_fit(Xd, model=model, **fit_kw)[2]["workspace_bytes"]
+        ws = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+        labels = torch.empty(N, dtype=torch.int32, device=dev)
+        aws = torch.empty(max(256, kk.kkm_assign_workspace_bytes(model, N, prec)), dtype=torch.uint8, device=dev)
+        ev_a = []
 
-    # dominant kernel: the isolated kernel with the largest time per step (HIP events around exactly
-    # that kernel's launches on the library's stream, inside the timed steps)
-    ells = [len(l) for l in landmarks]
-    roofline = None
-    rooflines = {}
-    if ms is not None:
+        def step(time_phases=0):
+            _, _, info = kk.kkm_fit(Xd, model=model, workspace=ws, want_labels=True, time_phases=time_phases,
+                                    **fit_kw)
+            if time_phases:   # events around the assign pass, on the stream it runs on (the current one)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+            kk.kkm_assign(model, Xd, precision=prec, workspace=aws, labels=labels)
+            if time_phases:
+                e1.record()
+                ev_a.append((e0, e1))
+            return info
+
+        for w in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        log(f"[bench] {prec}: {args.warmup} warmup steps done")
+        ev_a.clear()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            # events only around the landmark loop and the batch-wide distance kernel (three per batch)
+            # and around the assign pass
+            infos.append(step(time_phases=0 if args.no_phase_timing else 2))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        elapsed = t1 - t0
+        log(f"[bench] {prec}: {args.steps} timed steps in {elapsed:.3f} s")
+        assign_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_a])) if ev_a else None
+        # the breakdown over all phases from one more (untimed) step with events around every phase
+        phase_info = step(time_phases=1) if not args.no_phase_timing else None
+        torch.cuda.synchronize()
+        info = infos[-1]
+        evals_step = info["evals_algorithmic"] + N * C
+        assigned_step = int(np.dot(batch_n, info["updates_per_batch"])) + N
+        ms = ({k_: float(np.mean([i["ms"][k_] for i in infos])) for k_ in infos[0]["ms"]}
+              if not args.no_phase_timing else None)
+        # assign latency at a fixed request size
+        lat = []
+        q = Xd[: min(args.latency_size, N)]
+        qlab = torch.empty(q.shape[0], dtype=torch.int32, device=dev)
+        qws = torch.empty(max(256, kk.kkm_assign_workspace_bytes(model, q.shape[0], prec)), dtype=torch.uint8,
+                          device=dev)
+        for _ in range(args.latency_requests):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            kk.kkm_assign(model, q, precision=prec, workspace=qws, labels=qlab)
+            e1.record()
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        lat = np.asarray(lat) if lat else np.zeros(1)
+        lab_by_prec[prec] = labels.clone()
+        models[prec] = model
+        results[prec] = {
+            "kernel_evals_per_s": evals_step * args.steps / elapsed,
+            "samples_assigned_per_s": assigned_step * args.steps / elapsed,
+            "ms_per_step": elapsed / args.steps * 1e3,
+            "assign_pass_ms": assign_ms,
+            "assign_samples_per_s": N / (assign_ms * 1e-3) if assign_ms else None,
+            "kernel_ms_per_step": ({"landmark_loop": ms["landmark_loop"], "dist": ms["dist"],
+                                    "assign_pass": assign_ms} if ms else None),
+            "phase_ms_per_step": {k_: float(v) for k_, v in phase_info["ms"].items()} if phase_info else None,
+            "rows_refined_per_step": int(info["rows_refined"]),
+            "medoid_candidates_per_step": int(info["medoid_candidates"]),
+            "assign_latency_ms": {"request_size": int(q.shape[0]), "p50": float(np.percentile(lat, 50)),
+                                  "p99": float(np.percentile(lat, 99))},
+            "_infos": infos, "_ms": ms,
+        }
+        del ws, aws, qws, qlab, q
+
+    # label agreement of every form's assign pass with the FP64 assign of the same fitted model
+    for prec in precs:
+        if prec == "fp64":
+            results[prec]["label_agreement_vs_fp64"] = 1.0
+            continue
+        ref = kk.kkm_assign(models[prec], Xd, precision="fp64")
+        results[prec]["label_agreement_vs_fp64"] = float((ref == lab_by_prec[prec]).float().mean().item())
+
+    # roofline entries of the primary form (the first precision), HIP events inside its timed steps
+    prim = precs[0]
+    r = results[prim]
+    rooflines, roofline = {}, None
+    if r["_ms"] is not None:
+        info, ms = r["_infos"][-1], r["_ms"]
         upd = [int(u) - 1 for u in info["updates_per_batch"]]   # landmark-only updates
         lm_flops = float(np.mean([landmark_flops_per_launch(ells[i], upd[i], C) for i in range(B)]))
         dist_flops = float(np.mean([batch_n[i] * ells[i] for i in range(B)])) * dist_flops_per_eval(cfg["kernel"], d)
-        dist_peak = {"fp64": PEAK_FP64_VECTOR, "fp32": PEAK_FP32_VECTOR, "bf16x3": PEAK_BF16_MATRIX}[prec]
+        peak = {"fp64": PEAK_FP64_VECTOR, "fp32": PEAK_FP32_VECTOR, "bf16x3": PEAK_BF16_MATRIX,
+                "bf16": PEAK_BF16_MATRIX}[prim]
+        mfma = cfg["kernel"] != "rmsd" and prim != "fp64"
+        dist_name = "mfma_dist_kernel" if mfma else "dist_kernel"
+        assign_name = "mfma_assign1_kernel" if mfma else "dist_kernel"
         cands = {
-            "landmark_phase_kernel": (ms["landmark_loop"], lm_flops, PEAK_FP64_VECTOR, "alu"),
-            DIST_KERNEL_NAME.get((cfg["kernel"], prec), "dist_kernel"):
-                (ms["dist"], dist_flops, dist_peak, "mfma" if (cfg["kernel"] != "rmsd" and prec != "fp64") else "alu"),
+            "landmark_phase_kernel": (ms["landmark_loop"], B, lm_flops, PEAK_FP64_VECTOR, "alu"),
+            dist_name: (ms["dist"], B, dist_flops, peak, "mfma" if mfma else "alu"),
         }
-        for name, (tot_ms, flops, peak, bound) in cands.items():
-            dur = tot_ms / B * 1e-3
+        if r["assign_pass_ms"]:
+            # the assign pass's contraction: N x C dot products of length d
+            cands[assign_name + " (assign pass)"] = (r["assign_pass_ms"], 1, 2.0 * N * C * d, peak,
+                                                     "mfma" if mfma else "alu")
+        for name, (tot_ms, launches, flops, pk, bound) in cands.items():
+            dur = tot_ms / launches * 1e-3
             achieved = flops / dur if dur > 0 else 0.0
-            rooflines[name] = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                               "frac": achieved / peak, "traffic": TRAFFIC.get((name, args.workload)),
-                               "kernel": name, "avg_launch_us": dur * 1e6, "flop_per_launch": flops}
+            rooflines[name] = {"bound": bound, "achieved": achieved / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s",
+                               "frac": achieved / pk, "traffic": TRAFFIC.get((name.split()[0], args.workload)),
+                               "kernel": name, "avg_launch_us": dur * 1e6, "flop_per_launch": flops,
+                               "ms_per_step": tot_ms}
         dom = max(cands, key=lambda k_: cands[k_][0])
         roofline = dict(rooflines[dom])
-        roofline["kernel_ms_per_step"] = {"landmark_loop": ms["landmark_loop"], "dist": ms["dist"]}
-        roofline["phase_ms_per_step"] = {k_: float(v) for k_, v in phase_info["ms"].items()}
-
-    # assign latency at a fixed request size
-    lat = []
-    q = Xd[: min(args.latency_size, N)]
-    qlab = torch.empty(q.shape[0], dtype=torch.int32, device=dev)
-    qws = torch.empty(max(256, kk.kkm_assign_workspace_bytes(model, q.shape[0], prec)), dtype=torch.uint8, device=dev)
-    for r in range(args.latency_requests):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        kk.kkm_assign(model, q, precision=prec, workspace=qws, labels=qlab)
-        e1.record()
-        e1.synchronize()
-        lat.append(e0.elapsed_time(e1))
-    lat = np.asarray(lat) if lat else np.zeros(1)
-
+        roofline["kernel_ms_per_step"] = r["kernel_ms_per_step"]
+        roofline["phase_ms_per_step"] = r["phase_ms_per_step"]
+    for prec in precs:
+        results[prec].pop("_infos")
+        results[prec].pop("_ms")
+    ratios = {}
+    for prec in precs[1:]:
+        ratios[prec] = {"step_speedup": r["ms_per_step"] / results[prec]["ms_per_step"],
+                        "assign_pass_speedup": (r["assign_pass_ms"] / results[prec]["assign_pass_ms"]
+                                                if r["assign_pass_ms"] and results[prec]["assign_pass_ms"] else None)}
     out = {
-        "metric": "kernel evals/s (fit + assign, algorithmic count)",
-        "value": value,
+        "metric": "kernel evals/s + samples assigned/s (BF16 vs FP32); p50/p99 assign latency",
+        "value": r["kernel_evals_per_s"],
         "unit": "kernel evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32"}[prec] + " (landmark loop, medoids, merge: f64)",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32", "bf16": "bf16+f32"}[prim]
+                 + " (landmark loop, medoids, merge: f64)",
         "data": "synthetic",
-        "config": {"workload": desc, "N": N, "d": d, "C": C, "B": B, "s": s, "T": T, "precision": prec},
-        "samples_assigned_per_s": assigned_step * args.steps / elapsed,
-        "assign_latency_ms": {"request_size": int(q.shape[0]), "p50": float(np.percentile(lat, 50)),
-                              "p99": float(np.percentile(lat, 99))},
-        "refined_rows_per_step": int(info["rows_refined"]),
-        "medoid_candidates_per_step": int(info["medoid_candidates"]),
+        "config": {"workload": desc, "N": N, "d": d, "C": C, "B": B, "s": s, "T": T, "precision": prim,
+                   "draws": "seed only (landmarks and k-means++ uniforms drawn by the library inside each step)"},
+        "samples_assigned_per_s": r["samples_assigned_per_s"],
+        "assign_latency_ms": r["assign_latency_ms"],
+        "precisions": results,
+        "vs_fp32": ratios,
         "roofline": roofline,
         "rooflines": rooflines,
     }
     if not args.no_cpu_baseline:
-        log("[bench] timing the FP64 oracle on the host (one fit + one assign pass)")
-        out["cpu_baseline"] = cpu_baseline(X, cfg, landmarks, uniforms, init_labels)
+        nb = CPU_BASELINE_BATCHES.get(args.workload, 1)
+        log(f"[bench] timing the FP64 oracle on the host ({nb} batches + an assign pass)")
+        out["cpu_baseline"] = cpu_baseline(X, cfg, seed, nb)
         log("[bench] oracle done")
     print(json.dumps(out), flush=True)
-    # release device objects before the interpreter exits (profilers finalise after this point)
-    del model, ws, labels, aws, qws, qlab, q, Xd
-    import gc
-    gc.collect()
-    torch.cuda.synchronize()
     return 0
 
 

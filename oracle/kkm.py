@@ -180,25 +180,43 @@ def inner_loop(K_xl: np.ndarray, kxx: np.ndarray, landmarks: np.ndarray, U0: np.
 # --------------------------------------------------------------------------
 # Batch medoids (Eq. 10) and merge (Eq. 11-13)
 # --------------------------------------------------------------------------
-def batch_medoids(dist: np.ndarray, labels: np.ndarray, C: int):
-    """m_j^i = argmin over the batch of d_last[x, j], for clusters with members (Eq. 10)."""
+# Relative width within which two argmin candidates count as tied.  Diagnostic only: the argmins
+# themselves take the lowest index; the tie sets let a comparison accept any member of a set that
+# rounding (not the method) decides.
+TIE_REL = 1e-12
+
+
+def _near_minimum(v: np.ndarray, k: int) -> np.ndarray:
+    """Positions whose value is within TIE_REL (relative) of the minimum v[k]."""
+    return np.flatnonzero(np.abs(v - v[k]) <= TIE_REL * max(abs(float(v[k])), 1.0))
+
+
+def batch_medoids(dist: np.ndarray, labels: np.ndarray, C: int, ties: list | None = None):
+    """m_j^i = argmin over the batch of d_last[x, j], for clusters with members (Eq. 10).
+
+    ties (optional out): per cluster, the positions within TIE_REL of the minimum."""
     members = np.bincount(labels, minlength=C)
     Mi = np.full(C, -1, dtype=np.int64)
     for j in range(C):
         if members[j] > 0:
             Mi[j] = int(argmin_lowest(dist[:, j], axis=0))
+            if ties is not None:
+                ties.append(_near_minimum(dist[:, j], Mi[j]))
+        elif ties is not None:
+            ties.append(np.zeros(0, dtype=np.int64))
     return Mi, members
 
 
 def merge(kern: Kernel, Xb: np.ndarray, M: np.ndarray, M_valid: np.ndarray, wcount: np.ndarray,
-          Mi: np.ndarray, members: np.ndarray):
+          Mi: np.ndarray, members: np.ndarray, ties: list | None = None):
     """Convex merge of batch medoids into the global medoids (Eq. 11-13).
 
     alpha_j = |w_j^i| / (|w_j^i| + |w_j|)  (0 when both are 0: empty clusters are not updated);
     m_j <- argmin_x ||phi(x) - (1-alpha) phi(m_j) - alpha phi(m_j^i)||^2 over the batch
          = argmin_x K(x,x) - 2(1-alpha) K(x, m_j) - 2 alpha K(x, m_j^i) (+ a constant in x);
     |w_j| += |w_j^i|.
-    Returns the new (M, valid, wcount) and the chosen batch positions (-1 = not updated)."""
+    Returns the new (M, valid, wcount) and the chosen batch positions (-1 = not updated); ties
+    (optional out) receives per cluster the positions within TIE_REL of the minimum score."""
     C = len(wcount)
     M = M.copy()
     M_valid = M_valid.copy()
@@ -217,6 +235,10 @@ def merge(kern: Kernel, Xb: np.ndarray, M: np.ndarray, M_valid: np.ndarray, wcou
             chosen[j] = x
             M[j] = Xb[x]
             M_valid[j] = True
+            if ties is not None:
+                ties.append(_near_minimum(score, x))
+        elif ties is not None:
+            ties.append(np.zeros(0, dtype=np.int64))
         wcount[j] += members[j]
     return M, M_valid, wcount, chosen
 
@@ -239,6 +261,8 @@ class FitResult:
     label_gaps: np.ndarray       # (N,) relative margin of each final label
     evals: int                   # algorithmic kernel evaluations: n|L| + n C (init) + n C (merge)
     loops: list                  # LoopResult per batch
+    medoid_ties: list = field(default_factory=list)   # [B][C] global indices tied for Eq. 10's minimum
+    merge_ties: list = field(default_factory=list)    # [B][C] global indices tied for Eq. 12's minimum
 
 
 def fit(X: np.ndarray, C: int, kern: Kernel, B: int, T: int, landmarks: list,
@@ -263,6 +287,7 @@ def fit(X: np.ndarray, C: int, kern: Kernel, B: int, T: int, landmarks: list,
     bcnt = np.zeros((B, C), dtype=np.int64)
     gmed = np.full((B, C), -1, dtype=np.int64)
     updates, loops = [], []
+    med_ties, mrg_ties = [], []
     min_gap = INF
     evals = 0
     for i, idx in enumerate(parts):
@@ -294,9 +319,12 @@ def fit(X: np.ndarray, C: int, kern: Kernel, B: int, T: int, landmarks: list,
         loops.append(res)
         updates.append(res.updates)
         min_gap = min(min_gap, res.min_gap)
-        Mi, members = batch_medoids(res.dist, res.labels, C)
+        mt, gt = [], []
+        Mi, members = batch_medoids(res.dist, res.labels, C, ties=mt)
         evals += n * int(np.count_nonzero(members))
-        M, valid, wcount, chosen = merge(kern, Xb, M, valid, wcount, Mi, members)
+        M, valid, wcount, chosen = merge(kern, Xb, M, valid, wcount, Mi, members, ties=gt)
+        med_ties.append([idx[t] for t in mt])
+        mrg_ties.append([idx[t] for t in gt])
         for j in range(C):
             if chosen[j] >= 0:
                 M_idx[j] = idx[chosen[j]]
@@ -307,7 +335,7 @@ def fit(X: np.ndarray, C: int, kern: Kernel, B: int, T: int, landmarks: list,
         labels[idx] = res.labels
         gaps[idx] = gap_rel(res.dist, kxx)
     return FitResult(M, M_idx, valid, wcount, labels, updates, bmed, bcnt, gmed, min_gap,
-                     gaps, evals, loops)
+                     gaps, evals, loops, med_ties, mrg_ties)
 
 
 # --------------------------------------------------------------------------

@@ -109,6 +109,31 @@ struct PhaseTimer {
     }
 };
 
+// ----------------------------------------------------------------------------- fixed scratch
+// Scratch of kkm_assign_noalloc: a file-scope device array, one copy per GPU the library runs on,
+// held until the process ends.  Host code never uses the array's name as an address (on the host it
+// is only a stand-in for the symbol): the device address of each GPU's copy is looked up once with
+// hipGetSymbolAddress while that GPU is current, and that pointer is what kernels and copies get.
+constexpr size_t kNoAllocScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+kkm_status noalloc_scratch(int device, void** out) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        int cur = -1;
+        KKM_HIP(hipGetDevice(&cur));
+        if (cur != device) return fail(KKM_ERR_INVALID_ARG, "the model lives on another device than the current one");
+        void* p = nullptr;
+        KKM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        it = addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return KKM_OK;
+}
+
 // ----------------------------------------------------------------------------- fit plan
 struct FitPlan {
     int64_t N = 0, d = 0;
@@ -459,11 +484,11 @@ SupportView model_support(const kkm_model* m) {
     s.lo = m->lo;
     s.bpad = m->bpad;
     s.C = m->C;
+    s.medoid_form = m->medoid_form;
     return s;
 }
 
-kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
-                         size_t ws_bytes, hipStream_t s, int32_t* labels, float* gap, bool want_best, AssignWs& w) {
+kkm_status assign_validate(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision) {
     if (!m) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
     if (n < 0) return fail(KKM_ERR_INVALID_ARG, "n must be >= 0");
     if (n > 0 && !X) return fail(KKM_ERR_INVALID_ARG, "X is NULL");
@@ -471,12 +496,13 @@ kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t d
     if (precision < KKM_PREC_FP64 || precision > KKM_PREC_BF16X3)
         return fail(KKM_ERR_INVALID_ARG, "bad precision");
     if (n >= (int64_t)1 << 31) return fail(KKM_ERR_UNSUPPORTED, "at most 2^31 - 1 rows per call");
-    KKM_TRY(check_device_of(m));
-    Carver probe(nullptr);
-    const size_t need = carve_assign(probe, m, n, w);
-    KKM_TRY(check_workspace(ws, ws_bytes, need));
-    Carver c(ws);
-    carve_assign(c, m, n, w);
+    return check_device_of(m);
+}
+
+// The assign pass on scratch already carved (w): clears the counters, centres RMSD frames, runs the
+// distance pass, the FP64 re-decisions and (plain BF16 with a cost) the FP64 best distances.
+kkm_status assign_launch(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, hipStream_t s,
+                         int32_t* labels, float* gap, bool want_best, const AssignWs& w) {
     DeviceInfo dev;
     KKM_TRY(device_info(&dev));
     KKM_TRY(launch_zero_i32(w.refine_count, 2, s));
@@ -508,6 +534,17 @@ kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t d
     if (!dist_is_fp64(da)) KKM_TRY(launch_refine(da, dev, s, m->used));
     if (want_best && dist_is_bf16(da)) KKM_TRY(launch_best64(da, dev, s));
     return KKM_OK;
+}
+
+kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
+                         size_t ws_bytes, hipStream_t s, int32_t* labels, float* gap, bool want_best, AssignWs& w) {
+    KKM_TRY(assign_validate(m, X, n, dtype, precision));
+    Carver probe(nullptr);
+    const size_t need = carve_assign(probe, m, n, w);
+    KKM_TRY(check_workspace(ws, ws_bytes, need));
+    Carver c(ws);
+    carve_assign(c, m, n, w);
+    return assign_launch(m, X, n, dtype, precision, s, labels, gap, want_best, w);
 }
 
 }  // namespace
@@ -726,6 +763,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
         sv.lo = w.sup_lo;
         sv.bpad = bf16_pad(P.dpad);
         sv.C = C;
+        sv.medoid_form = 0;
 
         DistArgs da{};
         da.q = bv;
@@ -825,6 +863,12 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     if (info && info->partial_cost) std::memcpy(info->partial_cost, host_at(w.pcost), sizeof(double) * (size_t)P.B);
     model->used = C;
     model->nonneg = 1;
+    {   // a medoid model unless a cluster never received a medoid (its self term is then +inf)
+        const int64_t* last = reinterpret_cast<const int64_t*>(host_at(w.info)) + (size_t)(2 * P.B + P.B - 1) * C;
+        int32_t all = 1;
+        for (int j = 0; j < C; ++j) all &= last[j] >= 0 ? 1 : 0;
+        model->medoid_form = all;
+    }
     (void)es;
 
     if (info) {
@@ -922,6 +966,25 @@ kkm_status kkm_assign(const kkm_model* m, const void* X, int64_t n, int32_t dtyp
     AssignWs w;
     return assign_common(m, X, n, dtype, precision, ws, ws_bytes, static_cast<hipStream_t>(stream), labels_out, gap_out,
                          false, w);
+}
+
+kkm_status kkm_assign_noalloc(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision,
+                              void* stream, int32_t* labels_out, float* gap_out) {
+    if (!labels_out && n > 0) return fail(KKM_ERR_INVALID_ARG, "labels_out is NULL");
+    KKM_TRY(assign_validate(m, X, n, dtype, precision));
+    AssignWs w{};
+    Carver probe(nullptr);
+    const size_t need = carve_assign(probe, m, n, w);
+    if (need > kNoAllocScratchBytes)
+        return fail(KKM_ERR_UNSUPPORTED, "kkm_assign_noalloc: " + std::to_string(n) + " rows of this model need " +
+                                             std::to_string(need) + " bytes of scratch, more than its fixed " +
+                                             std::to_string(kNoAllocScratchBytes) +
+                                             "; split the rows or call kkm_assign with a workspace");
+    void* base = nullptr;
+    KKM_TRY(noalloc_scratch(m->device, &base));
+    Carver c(base);
+    carve_assign(c, m, n, w);
+    return assign_launch(m, X, n, dtype, precision, static_cast<hipStream_t>(stream), labels_out, gap_out, false, w);
 }
 
 kkm_status kkm_cost(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,

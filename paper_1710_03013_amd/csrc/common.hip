@@ -297,6 +297,9 @@ kkm_status kkm_model_load(kkm_model* m, const void* support, int64_t n_support, 
     KKM_HIP(hipMemcpy(m->medoid_index, minus.data(), sizeof(int64_t) * m->C, hipMemcpyHostToDevice));
     m->used = n_support;
     m->nonneg = nonneg;
+    int32_t medoids = n_support == m->C ? 1 : 0;   // one row per cluster, in cluster order, coefficient 1
+    for (int j = 0; medoids && j < m->C; ++j) medoids = offsets[j] == j && coef[j] == 1.0;
+    m->medoid_form = medoids;
     KKM_TRY(launch_model_prepare(m, nullptr));
     KKM_HIP(hipDeviceSynchronize());
     if (cur != m->device) KKM_HIP(hipSetDevice(cur));

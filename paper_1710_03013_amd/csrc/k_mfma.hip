@@ -56,6 +56,106 @@ __device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float
     return __builtin_amdgcn_exp2f(-d2 * inv2s2 * 1.4426950408889634f);
 }
 
+// x.s for the 32 support rows of panel tile `tile` and the wavefront's 32 samples: lane l ends up with
+// rows 8(i/4) + 4(l/32) + i%4 of sample l%32 in acc[i].  xq: the lane half's dimensions of its sample
+// (FP32), bh / bl: their bfloat16 split (BF16 forms).
+template <int DP, int PM>
+__device__ __forceinline__ floatx16 mfma_tile(const SupportView& sup, int64_t tile, int lane, const float* xq,
+                                              const bf16x8* bh, const bf16x8* bl) {
+    constexpr int H = DP / 2;
+    floatx16 acc = {};
+    if constexpr (PM == kPmBf16) {
+        const bf16x8* ah = reinterpret_cast<const bf16x8*>(sup.hi) + tile * (H / 8) * 64 + lane;
+        bf16x8 xh[H / 8];
+#pragma unroll
+        for (int v = 0; v < H / 8; ++v) xh[v] = ah[v * 64];
+#pragma unroll
+        for (int v = 0; v < H / 8; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bh[v], acc, 0, 0, 0);
+    } else if constexpr (PM == kPmBf16x3) {
+        const bf16x8* ah = reinterpret_cast<const bf16x8*>(sup.hi) + tile * (H / 8) * 64 + lane;
+        const bf16x8* al = reinterpret_cast<const bf16x8*>(sup.lo) + tile * (H / 8) * 64 + lane;
+        bf16x8 xh[H / 8], xl[H / 8];
+#pragma unroll
+        for (int v = 0; v < H / 8; ++v) {
+            xh[v] = ah[v * 64];
+            xl[v] = al[v * 64];
+        }
+#pragma unroll
+        for (int v = 0; v < H / 8; ++v) {
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[v], bh[v], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bl[v], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bh[v], acc, 0, 0, 0);
+        }
+    } else {
+        constexpr int VW = H < 4 ? H : 4;
+        const float* pb = sup.pan + (tile * (H / VW) * 64 + lane) * VW;
+        float af[H];
+#pragma unroll
+        for (int g = 0; g < H / VW; ++g) {
+            if constexpr (VW == 4) {
+                const float4 t = *reinterpret_cast<const float4*>(pb + g * 64 * VW);
+                af[4 * g] = t.x;
+                af[4 * g + 1] = t.y;
+                af[4 * g + 2] = t.z;
+                af[4 * g + 3] = t.w;
+            } else {
+                const float2 t = *reinterpret_cast<const float2*>(pb + g * 64 * VW);
+                af[2 * g] = t.x;
+                af[2 * g + 1] = t.y;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < H; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], xq[s], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// The lane half's dimensions of sample row xr (zero past d), with the squared norm over both halves,
+// the finiteness of the lane's part, and the bfloat16 split for the BF16 forms.
+template <typename TI, int DP, int PM>
+__device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok, int h, float* xq, bf16x8* bh,
+                                            bf16x8* bl, bool& ok) {
+    constexpr int H = DP / 2;
+    const bool xvec = H % 4 == 0 && d == DP && vec_ok;
+    if (xvec) {
+        const float4* x4 = reinterpret_cast<const float4*>(xr + h * H);
+#pragma unroll
+        for (int v = 0; v < H / 4; ++v) {
+            const float4 t = x4[v];
+            xq[4 * v] = t.x;
+            xq[4 * v + 1] = t.y;
+            xq[4 * v + 2] = t.z;
+            xq[4 * v + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < H; ++s) {
+            const int dim = h * H + s;
+            xq[s] = dim < d ? (float)xr[dim] : 0.0f;
+        }
+    }
+    float qn = 0.0f;
+    ok = true;
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+        ok = ok && isfinite(xq[s]);
+        qn = fmaf(xq[s], xq[s], qn);
+    }
+    qn += __shfl_xor(qn, 32, 64);
+    if constexpr (PM != kPmF32) {
+#pragma unroll
+        for (int v = 0; v < H / 8; ++v)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float x = xq[8 * v + t];
+                const __bf16 hi = (__bf16)x;
+                bh[v][t] = hi;
+                if constexpr (PM == kPmBf16x3) bl[v][t] = (__bf16)(x - (float)hi);
+            }
+    }
+    return qn;
+}
+
 template <typename TI, int DP, int PM, int NW>
 __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     constexpr bool BF = PM != kPmF32;         // bfloat16 operands
@@ -100,46 +200,11 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     // the sample's half of the dimensions, its squared norm, and its bf16 split
     const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
     float xq[H];
-    bool ok = true;
-    float qn = 0.0f;
-    const bool xvec = H % 4 == 0 && a.q.d == DP && (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0;
-    if (xvec) {
-        const float4* x4 = reinterpret_cast<const float4*>(xr + h * H);
-#pragma unroll
-        for (int v = 0; v < H / 4; ++v) {
-            const float4 t = x4[v];
-            xq[4 * v] = t.x;
-            xq[4 * v + 1] = t.y;
-            xq[4 * v + 2] = t.z;
-            xq[4 * v + 3] = t.w;
-        }
-    } else {
-#pragma unroll
-        for (int s = 0; s < H; ++s) {
-            const int dim = h * H + s;
-            xq[s] = dim < a.q.d ? (float)xr[dim] : 0.0f;
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < H; ++s) {
-        ok = ok && isfinite(xq[s]);
-        qn = fmaf(xq[s], xq[s], qn);
-    }
-    qn += __shfl_xor(qn, 32, 64);
+    bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
+    bool ok;
+    const float qn = load_query<TI, DP, PM>(xr, a.q.d, (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0, h, xq, bh, bl, ok);
     if (active && !ok) atomicOr(a.nonfinite, 1);   // either half may hold the bad value
     const float kqq = type == KKM_KERNEL_LINEAR ? qn : 1.0f;
-    bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
-    if constexpr (BF) {
-#pragma unroll
-        for (int v = 0; v < H / 8; ++v)
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float x = xq[8 * v + t];
-                const __bf16 hi = (__bf16)x;
-                bh[v][t] = hi;
-                if constexpr (BF3) bl[v][t] = (__bf16)(x - (float)hi);
-            }
-    }
     const int quarter = wave & 3, half = wave >> 2;
     const int j0 = jb[quarter], j1 = jb[quarter + 1];
     const int start = off[j0], end = off[j1];
@@ -160,50 +225,7 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
         // A fragment: support row r0 + col, the lane half's dimensions, read from the panel of the
         // tile (64 consecutive vectors per step group)
         const int64_t tile = r0 >> 5;
-        floatx16 acc = {};
-        if constexpr (PM == kPmBf16) {
-            const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi) + tile * (H / 8) * 64 + lane;
-            bf16x8 xh[H / 8];
-#pragma unroll
-            for (int v = 0; v < H / 8; ++v) xh[v] = ah[v * 64];
-#pragma unroll
-            for (int v = 0; v < H / 8; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bh[v], acc, 0, 0, 0);
-        } else if constexpr (BF3) {
-            const bf16x8* ah = reinterpret_cast<const bf16x8*>(a.sup.hi) + tile * (H / 8) * 64 + lane;
-            const bf16x8* al = reinterpret_cast<const bf16x8*>(a.sup.lo) + tile * (H / 8) * 64 + lane;
-            bf16x8 xh[H / 8], xl[H / 8];
-#pragma unroll
-            for (int v = 0; v < H / 8; ++v) {
-                xh[v] = ah[v * 64];
-                xl[v] = al[v * 64];
-            }
-#pragma unroll
-            for (int v = 0; v < H / 8; ++v) {
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[v], bh[v], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bl[v], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[v], bh[v], acc, 0, 0, 0);
-            }
-        } else {
-            constexpr int VW = H < 4 ? H : 4;
-            const float* pb = a.sup.pan + (tile * (H / VW) * 64 + lane) * VW;
-            float af[H];
-#pragma unroll
-            for (int g = 0; g < H / VW; ++g) {
-                if constexpr (VW == 4) {
-                    const float4 t = *reinterpret_cast<const float4*>(pb + g * 64 * VW);
-                    af[4 * g] = t.x;
-                    af[4 * g + 1] = t.y;
-                    af[4 * g + 2] = t.z;
-                    af[4 * g + 3] = t.w;
-                } else {
-                    const float2 t = *reinterpret_cast<const float2*>(pb + g * 64 * VW);
-                    af[2 * g] = t.x;
-                    af[2 * g + 1] = t.y;
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < H; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s], xq[s], acc, 0, 0, 0);
-        }
+        const floatx16 acc = mfma_tile<DP, PM>(a.sup, tile, lane, xq, bh, bl);
         // segments meeting the tile (the first 64 of them): a prefix of the lanes, offsets ascend
         int sj = jc + lane;
         int o0 = sj < j1 ? off[sj] : end;
@@ -388,6 +410,114 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     }   // groups
 }
 
+// Assign against a medoid model: every cluster has one support row with coefficient 1 and the self
+// term of that row (1 for RBF, ||m||^2 for linear).  Then d(x, j) = K(x,x) + self_j - 2 K(x, m_j) is
+// an increasing function of e_j = ||m_j||^2 - 2 x.m_j for both kernels (RBF: 2 - 2 exp(-(||x||^2 +
+// e_j) / (2 sigma^2)); linear: ||x||^2 + e_j), so the label is the argmin of e_j: the pass needs no
+// exponential and no segment sums, and only the best and second-best e become distances.
+// One wavefront per 32 samples (grid-stride over groups), walking every 32-row tile of the support;
+// lane l keeps the best two of its rows 8(i/4) + 4(l/32) + i%4 of each tile (visited in ascending
+// order, so the lowest index wins a tie), then merges with its partner lane l^32.
+//
+// Error bound of e: |x.m computed - exact| <= dot_rel kmax (kmax >= ||x|| ||m||), the FP32 norm
+// ||m||^2 and the subtraction add rounding of at most 3 u32 (snmax + 2 kmax): Ee.  A row whose two
+// smallest e are within 2 Ee is listed for the FP64 re-decision, unless the exact relative margin
+// in d is provably below kTieMargin (the bound on it follows from 1 - exp(-t) <= t for RBF).
+template <typename TI, int DP, int PM>
+__global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
+    constexpr int H = DP / 2;
+    constexpr bool BF = PM != kPmF32, BF3 = PM == kPmBf16x3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, col = lane & 31;
+    const int C = a.sup.C;
+    const int ntiles = (C + 31) / 32;
+    const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
+    const float c2 = (float)a.ks.inv2s2;
+    const float snmax = *a.sup.snorm_max;
+    const float dot_rel = BF3 ? kUbf3 + (3.0f * DP + 2.0f) * kU32 : BF ? kUbf1 + (DP + 3.0f) * kU32 : (DP + 2.0f) * kU32;
+    const bool vec_ok = (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0;
+    const int64_t ngroups = (a.q.n + 31) / 32;
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp < ngroups; grp += (int64_t)gridDim.x * 4) {
+        const int64_t q = grp * 32 + col;
+        const bool active = q < a.q.n;
+        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
+        float xq[H];
+        bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
+        bool ok;
+        const float qn = load_query<TI, DP, PM>(xr, a.q.d, vec_ok, h, xq, bh, bl, ok);
+        if (active && !ok) atomicOr(a.nonfinite, 1);
+        float e1 = __builtin_huge_valf(), e2 = __builtin_huge_valf();
+        int j1 = C;
+        for (int t = 0; t < ntiles; ++t) {
+            const floatx16 acc = mfma_tile<DP, PM>(a.sup, t, lane, xq, bh, bl);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int rb = 32 * t + 8 * b + 4 * h;
+                const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
+                const float sn[4] = {sn4.x, sn4.y, sn4.z, sn4.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int j = rb + c;
+                    const float e = j < C ? fmaf(-2.0f, acc[4 * b + c], sn[c]) : __builtin_huge_valf();
+                    if (e < e1) {
+                        e2 = e1;
+                        e1 = e;
+                        j1 = j;
+                    } else if (e < e2) {
+                        e2 = e;
+                    }
+                }
+            }
+        }
+        {   // the partner lane holds the interleaved rows of every tile
+            const float o1 = __shfl_xor(e1, 32, 64), o2 = __shfl_xor(e2, 32, 64);
+            const int k1 = __shfl_xor(j1, 32, 64);
+            if (o1 < e1 || (o1 == e1 && k1 < j1)) {
+                e2 = fminf(e1, o2);
+                e1 = o1;
+                j1 = k1;
+            } else {
+                e2 = fminf(e2, o1);
+            }
+        }
+        bool need = false;
+        if (h == 0 && active) {
+            const int bj = j1 < C ? j1 : 0;
+            const float kmax = sqrtf(qn * snmax) * 1.0001f;
+            const float Ee = 2.0f * dot_rel * kmax + 3.0f * kU32 * (snmax + 2.0f * kmax);
+            const double g1 = a.sup.self[bj];
+            double D1, D2, kqq;
+            if (lin) {
+                kqq = qn;
+                D1 = (double)qn + (double)e1 + (g1 - (double)a.sup.snorm32[bj]);
+                D2 = (double)qn + (double)e2;
+            } else {
+                kqq = 1.0;
+                const float K1 = exp_neg(fmaxf(qn + e1, 0.0f) * c2);
+                const float K2 = e2 < __builtin_huge_valf() ? exp_neg(fmaxf(qn + e2, 0.0f) * c2) : 0.0f;
+                D1 = kqq + g1 - 2.0 * (double)K1;
+                D2 = e2 < __builtin_huge_valf() ? 2.0 - 2.0 * (double)K2 : kInf;
+            }
+            a.labels[q] = bj;
+            if (a.best) a.best[q] = D1;
+            if (a.gap) {
+                const double scale = fmax(fmax(fabs(D1), fabs(D2)), fabs(kqq));
+                a.gap[q] = D2 < kInf ? (float)((D2 - D1) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
+            }
+            const float ge = e2 - e1;
+            if (ge <= 2.0f * Ee) {
+                // upper bound on the exact relative margin of d
+                const float qlo = qn * (1.0f - (DP + 2.0f) * kU32);
+                float ub;
+                if (lin) ub = (ge + 2.0f * Ee) / fmaxf(qlo, 1e-30f);
+                else ub = 2.0f * exp_neg(fmaxf(qlo + e1 - Ee, 0.0f) * c2) * (ge + 2.0f * Ee) * c2;
+                need = !(ub < (float)kTieMargin);
+            }
+        }
+        append_rows(need, q, a.refine_count, a.refine_list);
+    }
+}
+
 size_t mfma_lds_dynamic(size_t C, int nw) {
     return sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
 }
@@ -450,8 +580,34 @@ bool mfma_dist_applies(const DistArgs& a) {
     return a.sup.pan != nullptr;
 }
 
+template <int PM>
+kkm_status launch_assign1(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
+    const int64_t groups = (a.q.n + 31) / 32;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 16 * (int64_t)dev.num_cus));
+    auto go = [&](auto fn) -> kkm_status {
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, a);
+        KKM_HIP(hipGetLastError());
+        return KKM_OK;
+    };
+    switch (a.sup.dpad) {
+        case 4: if constexpr (PM == kPmF32) return go(mfma_assign1_kernel<float, 4, PM>); break;
+        case 8: if constexpr (PM == kPmF32) return go(mfma_assign1_kernel<float, 8, PM>); break;
+        case 16: return go(mfma_assign1_kernel<float, 16, PM>);
+        case 32: return go(mfma_assign1_kernel<float, 32, PM>);
+        case 64: return go(mfma_assign1_kernel<float, 64, PM>);
+        case 128: return go(mfma_assign1_kernel<float, 128, PM>);
+        default: break;
+    }
+    return fail(KKM_ERR_UNSUPPORTED, "matrix-core assign: unsupported padded dimension");
+}
+
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     if (a.q.n <= 0) return KKM_OK;
+    if (a.sup.medoid_form && !a.Dt && !a.colmin && !a.Erow) {
+        if (a.precision == KKM_PREC_BF16X3) return launch_assign1<kPmBf16x3>(a, dev, s);
+        if (a.precision == KKM_PREC_BF16) return launch_assign1<kPmBf16>(a, dev, s);
+        return launch_assign1<kPmF32>(a, dev, s);
+    }
     if (a.precision == KKM_PREC_BF16X3) return launch_mfma_t<float, kPmBf16x3>(a, dev, s);
     if (a.precision == KKM_PREC_BF16) return launch_mfma_t<float, kPmBf16>(a, dev, s);
     return launch_mfma_t<float, kPmF32>(a, dev, s);

@@ -128,6 +128,7 @@ struct kkm_model {
     int32_t bpad = 0;
     int64_t* counts = nullptr;  // [C] |w_j| of a fitted model
     int64_t* medoid_index = nullptr; // [C]
+    int32_t medoid_form = 0;    // support row j is cluster j's only row, coefficient 1, no cluster disabled
 };
 
 namespace kkm {

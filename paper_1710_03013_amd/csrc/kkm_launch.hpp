@@ -96,6 +96,7 @@ struct SupportView {
     const uint16_t* lo;     // bfloat16 panel of the remainders
     int64_t bpad;
     int32_t C;
+    int32_t medoid_form;    // every cluster one support row (row j), coefficient 1, every self term finite
 };
 
 struct DistArgs {
