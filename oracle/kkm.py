@@ -415,6 +415,19 @@ def medoid_displacement(kern: Kernel, X: np.ndarray, before: np.ndarray, after: 
     return out
 
 
+def global_costs(kern: Kernel, X: np.ndarray, fitres: FitResult) -> list:
+    """Global cost Omega(W) after every batch (Sec. 4.1, Fig. 4): Eq. 1 over ALL N samples with the
+    global medoids as they stand after the merge of batch i (clusters without a medoid yet are
+    skipped)."""
+    out = []
+    for i in range(fitres.global_medoids.shape[0]):
+        idx = fitres.global_medoids[i]
+        rows = np.asarray(X[idx[idx >= 0]], dtype=np.float64)
+        model = SparseModel(rows, np.arange(rows.shape[0] + 1), np.ones(rows.shape[0]))
+        out.append(cost(kern, X, model))
+    return out
+
+
 def partial_costs(fitres: FitResult) -> list:
     """Partial cost Omega(W^i) of every batch (Sec. 4.1, Fig. 4): Eq. 1 over the batch's rows with
     the batch's landmark centroids after its loop, i.e. the sum of each row's distance to its

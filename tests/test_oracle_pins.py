@@ -482,3 +482,20 @@ def test_rmsd_kernel_on_atom_major_rows():
     want = np.exp(-rmsd2_kabsch(F, H) / (2 * sigma * sigma))
     assert abs(kern9(F.reshape(1, -1), H.reshape(1, -1))[0, 0] - want) < 1e-12
     assert kern9.diag(F.reshape(1, -1))[0] == 1.0
+
+
+def test_global_cost_after_every_batch_closed_form():
+    """Sec. 4.1 global cost: after batch i, Eq. 1 over all N samples with the global medoids of that
+    moment.  Linear kernel: the explicit sum over samples of the squared Euclidean distance to the
+    nearest medoid; the last batch's value is the cost of the final medoid model."""
+    rng = np.random.default_rng(34)
+    X, _ = _blobs(300, 3, 4, 34)
+    L = ki.draw_all_landmarks(8, 300, 3, 0.5)
+    res = kkm.fit(X, 4, Kernel("linear"), 3, 10, L, kmpp_uniforms=ki.draw_kmpp_uniforms(8, 4))
+    gc = kkm.global_costs(Kernel("linear"), X, res)
+    assert len(gc) == 3
+    for i in range(3):
+        M = X[res.global_medoids[i]]
+        want = float(np.min(((X[:, None, :] - M[None]) ** 2).sum(-1), axis=1).sum())
+        assert abs(gc[i] - want) <= 1e-9 * want
+    assert abs(gc[-1] - kkm.cost(Kernel("linear"), X, kkm.medoid_model(res))) <= 1e-12 * gc[-1]
