@@ -78,6 +78,10 @@ enum kkm_precision {
 
 /* kkm_params.flags bits */
 enum kkm_fit_flags {
+    KKM_FIT_GLOBAL_COST = 2,    /* also take the global cost Omega(W) after every batch (Sec. 4.1, Fig. 4):
+                                   Eq. 1 over all N samples with the global medoids of that moment, in
+                                   the fit's precision, into kkm_fit_info.global_cost; the workspace then
+                                   holds a medoid model and an assign pass over N rows more */
     KKM_FIT_COOPERATIVE = 1     /* launch the kernels whose workgroups wait for each other (k-means++ and
                                    the landmark loop) cooperatively, so that all their workgroups are
                                    resident together even while other streams keep the GPU busy (a
@@ -155,6 +159,10 @@ typedef struct kkm_fit_info {
                                    Eq. 14 after its loop: the sum of each row's distance to its nearest
                                    centroid, summed in FP64 in a fixed order (a row decided in FP32 adds
                                    its distance formed from FP32 sums, within the row's error bound) */
+    double* global_cost;        /* host [B] or NULL (needs KKM_FIT_GLOBAL_COST in kkm_params.flags): the
+                                   global cost Omega(W) after the merge of every batch (Sec. 4.1, Fig. 4),
+                                   Eq. 1 over all N samples against the global medoids of that moment,
+                                   summed in FP64 in a fixed order as kkm_cost does */
 } kkm_fit_info;
 
 /* A clustering model: C sparse centroids w_j = sum_{l in segment j} a_l phi(s_l), kept resident in
@@ -216,6 +224,24 @@ int64_t kkm_fit_min_batches(int64_t N, int64_t d, int32_t dtype, const kkm_kerne
 kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
                    const kkm_params* params, void* workspace, size_t workspace_bytes, void* stream,
                    kkm_model* model, int32_t* labels_out, kkm_fit_info* info);
+
+/* ---------------------------------------------------------------- restarts (Sec. 4.5) */
+
+/* Workspace bytes of kkm_fit_restarts (0 if the arguments are invalid). */
+size_t kkm_fit_restarts_workspace_bytes(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
+                                        const kkm_params* params, int32_t restarts);
+
+/* Best of several restarts (Sec. 4.5 keeps the lowest-cost run of five kernel k-means++ fits): fit number r
+ * (r = 0 .. restarts-1) is kkm_fit with seed params->seed + r (its own landmarks and k-means++ draws:
+ * params->landmarks, kmpp_uniforms and init_labels must be NULL), followed by its cost, Eq. 1 over all N
+ * samples in FP64 with the fit's medoids (as kkm_cost in FP64).  All fits and costs run back to back on
+ * stream out of one workspace, with one synchronisation; the lowest cost wins (the lowest r on equal
+ * costs) and is written to model, labels_out and info as kkm_fit writes its result.  costs_out: host
+ * [restarts] or NULL; best_out: host, the winning r, or NULL.  Synchronous. */
+kkm_status kkm_fit_restarts(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
+                            const kkm_params* params, int32_t restarts, void* workspace, size_t workspace_bytes,
+                            void* stream, kkm_model* model, int32_t* labels_out, kkm_fit_info* info,
+                            double* costs_out, int32_t* best_out);
 
 /* ---------------------------------------------------------------- assign / cost (Eq. 1-2) */
 

@@ -21,7 +21,7 @@ __all__ = [
     "KKM_PREC_FP64", "KKM_PREC_FP32", "KKM_PREC_BF16", "KKM_PREC_BF16X3", "KKM_SAMPLE_STRIDE", "KKM_SAMPLE_BLOCK",
     "KKM_INIT_KMEANSPP", "KKM_INIT_RANDOM_LABELS", "KKM_INIT_MEDOIDS", "KkmError", "Model", "lib",
     "kkm_model_create", "kkm_model_load", "kkm_model_export", "kkm_model_shape", "kkm_fit",
-    "kkm_fit_workspace_bytes", "kkm_fit_min_batches", "kkm_assign", "kkm_assign_workspace_bytes", "kkm_cost",
+    "kkm_fit_workspace_bytes", "kkm_fit_min_batches", "kkm_fit_restarts", "kkm_assign", "kkm_assign_workspace_bytes", "kkm_cost",
     "kkm_kernel_block", "kkm_kernel_block_workspace_bytes",
     "kkm_landmark_count", "kkm_draw_landmarks", "kkm_draw_kmpp_uniforms", "kkm_draw_init_labels",
     "kkm_version", "EXPORTED_SYMBOLS", "release_models",
@@ -34,6 +34,7 @@ KKM_PREC_FP64, KKM_PREC_FP32, KKM_PREC_BF16, KKM_PREC_BF16X3 = 0, 1, 2, 3
 KKM_SAMPLE_STRIDE, KKM_SAMPLE_BLOCK = 0, 1
 KKM_INIT_KMEANSPP, KKM_INIT_RANDOM_LABELS, KKM_INIT_MEDOIDS = 0, 1, 2
 KKM_FIT_COOPERATIVE = 1
+KKM_FIT_GLOBAL_COST = 2
 
 _KERNELS = {"linear": KKM_KERNEL_LINEAR, "rbf": KKM_KERNEL_RBF, "rmsd": KKM_KERNEL_RMSD}
 _PRECISIONS = {"fp64": KKM_PREC_FP64, "fp32": KKM_PREC_FP32, "bf16": KKM_PREC_BF16, "bf16x3": KKM_PREC_BF16X3}
@@ -70,7 +71,7 @@ class _FitInfo(ct.Structure):
                 ("ms_landmark", ct.c_double), ("ms_dist", ct.c_double), ("ms_refine", ct.c_double),
                 ("ms_select", ct.c_double), ("ms_landmark_loop", ct.c_double),
                 ("landmark_trace", ct.POINTER(ct.c_int64)), ("medoid_displacement", ct.POINTER(ct.c_double)),
-                ("partial_cost", ct.POINTER(ct.c_double))]
+                ("partial_cost", ct.POINTER(ct.c_double)), ("global_cost", ct.POINTER(ct.c_double))]
 
 
 # name -> (restype, argtypes): every symbol include/kkm.h declares
@@ -91,6 +92,12 @@ _SIGS = {
     "kkm_fit": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int32, ct.POINTER(_Kernel),
                            ct.POINTER(_Params), ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
                            ct.c_void_p, ct.POINTER(_FitInfo)]),
+    "kkm_fit_restarts_workspace_bytes": (ct.c_size_t, [ct.c_int64, ct.c_int64, ct.c_int32, ct.POINTER(_Kernel),
+                                                       ct.POINTER(_Params), ct.c_int32]),
+    "kkm_fit_restarts": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int32, ct.POINTER(_Kernel),
+                                    ct.POINTER(_Params), ct.c_int32, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                    ct.c_void_p, ct.c_void_p, ct.POINTER(_FitInfo), ct.POINTER(ct.c_double),
+                                    ct.POINTER(ct.c_int32)]),
     "kkm_assign_workspace_bytes": (ct.c_size_t, [ct.c_void_p, ct.c_int64, ct.c_int32]),
     "kkm_assign": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_void_p,
                               ct.c_size_t, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
@@ -297,9 +304,9 @@ def kkm_model_export(model: Model) -> dict:
 
 
 def _params(C, B, s, max_iter, sampling, init, precision, seed, landmarks, kmpp_uniforms, init_labels,
-            init_medoids, keep, cooperative=False):
+            init_medoids, keep, cooperative=False, global_cost=False):
     p = _Params()
-    p.flags = KKM_FIT_COOPERATIVE if cooperative else 0
+    p.flags = (KKM_FIT_COOPERATIVE if cooperative else 0) | (KKM_FIT_GLOBAL_COST if global_cost else 0)
     p.C, p.B, p.s, p.max_iter = int(C), int(B), float(s), int(max_iter)
     p.sampling = _SAMPLING[sampling] if isinstance(sampling, str) else int(sampling)
     p.init = _INITS[init] if isinstance(init, str) else int(init)
@@ -345,7 +352,7 @@ def kkm_fit_min_batches(N, d, dtype, kernel, budget_bytes, **params) -> int:
 def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20, sampling="stride",
             init="kmeans++", precision="fp32", seed=0, landmarks=None, kmpp_uniforms=None, init_labels=None,
             init_medoids=None, model=None, workspace=None, stream=None, want_labels=True, time_phases=False,
-            landmark_trace=False, cooperative=False, cost_trace=False):
+            landmark_trace=False, cooperative=False, cost_trace=False, global_cost=False):
     """Fit on X (a CUDA tensor, N x d).  Returns (model, labels tensor or None, info dict).
 
     time_phases: False / 0 no timing; True / 1 HIP events around every phase; 2 only around the
@@ -353,7 +360,9 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
     cooperative: launch the kernels whose workgroups wait for each other cooperatively (for callers
     that keep other streams busy on the same GPU meanwhile).
     cost_trace: also return the per-batch observables of Sec. 4.1: info["partial_cost"] (the partial
-    cost of every batch, one more reduction per batch) and info["medoid_displacement"] (B x C)."""
+    cost of every batch, one more reduction per batch) and info["medoid_displacement"] (B x C).
+    global_cost: also return info["global_cost"], the global cost after every batch (an assign pass
+    over all N samples per batch)."""
     import torch
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
@@ -361,19 +370,19 @@ def kkm_fit(X, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
         os_.use(X, workspace)
         return _kkm_fit(X.contiguous(), kernel, sigma, n_atoms, C, B, s, max_iter, sampling, init, precision, seed,
                         landmarks, kmpp_uniforms, init_labels, init_medoids, model, workspace, os_.s, want_labels,
-                        time_phases, landmark_trace, cooperative, cost_trace)
+                        time_phases, landmark_trace, cooperative, cost_trace, global_cost)
 
 
 def _kkm_fit(X, kernel, sigma, n_atoms, C, B, s, max_iter, sampling, init, precision, seed, landmarks, kmpp_uniforms,
              init_labels, init_medoids, model, workspace, stream, want_labels, time_phases, landmark_trace, cooperative,
-             cost_trace):
+             cost_trace, global_cost):
     import torch
     N, d = X.shape
     k = _kernel(kernel, sigma, n_atoms)
     dt = _dtype_code(X)
     keep = []
     p = _params(C, B, s, max_iter, sampling, init, precision, seed, landmarks, kmpp_uniforms, init_labels,
-                init_medoids, keep, cooperative)
+                init_medoids, keep, cooperative, global_cost)
     need = int(lib().kkm_fit_workspace_bytes(N, d, dt, ct.byref(k), ct.byref(p)))
     if need == 0:
         _check(lib().kkm_fit(None, N, d, dt, ct.byref(k), ct.byref(p), None, 0, None, None, None, None))
@@ -388,24 +397,69 @@ def _kkm_fit(X, kernel, sigma, n_atoms, C, B, s, max_iter, sampling, init, preci
     trace = np.zeros(64, dtype=np.int64) if landmark_trace else None
     disp = np.zeros(B * C, dtype=np.float64) if cost_trace else None
     pc = np.zeros(B, dtype=np.float64) if cost_trace else None
+    gc = np.zeros(B, dtype=np.float64) if global_cost else None
     info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, int(time_phases))
     if trace is not None:
         info.landmark_trace = _i64p(trace)
     if cost_trace:
         info.medoid_displacement = _f64p(disp)
         info.partial_cost = _f64p(pc)
+    if global_cost:
+        info.global_cost = _f64p(gc)
     _check(lib().kkm_fit(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p),
                          ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(stream)), model.ptr,
                          ct.c_void_p(labels.data_ptr()) if labels is not None else None, ct.byref(info)))
     out = dict(updates_per_batch=upd, batch_medoids=bmed.reshape(B, C), batch_counts=bcnt.reshape(B, C),
                global_medoids=gmed.reshape(B, C),
-               medoid_displacement=disp.reshape(B, C) if disp is not None else None, partial_cost=pc,
+               medoid_displacement=disp.reshape(B, C) if disp is not None else None, partial_cost=pc, global_cost=gc,
                evals_algorithmic=info.evals_algorithmic,
                evals_performed=info.evals_performed, rows_refined=info.rows_refined,
                medoid_candidates=info.medoid_candidates, workspace_bytes=need,
                ms=dict(init=info.ms_init, landmark=info.ms_landmark, landmark_loop=info.ms_landmark_loop,
                        dist=info.ms_dist, refine=info.ms_refine, select=info.ms_select) if time_phases else None,
                landmark_trace=trace[1:1 + int(trace[0])] if trace is not None else None)
+    return model, labels, out
+
+
+def kkm_fit_restarts(X, restarts=5, kernel="rbf", sigma=1.0, n_atoms=0, C=2, B=1, s=1.0, max_iter=20,
+                     sampling="stride", init="kmeans++", precision="fp32", seed=0, init_medoids=None, model=None,
+                     workspace=None, stream=None, want_labels=True):
+    """Best of `restarts` fits with seeds seed .. seed + restarts - 1, the lowest FP64 cost over all of X
+    winning (the lowest restart on equal costs), all run by the library back to back on one stream.
+    Returns (model, labels tensor or None, info dict with "restart" and "restart_costs" added)."""
+    import torch
+    if not X.is_cuda:
+        raise ValueError("X must be a device tensor")
+    with _OnStream(stream) as os_:
+        os_.use(X, workspace)
+        X = X.contiguous()
+        N, d = X.shape
+        k = _kernel(kernel, sigma, n_atoms)
+        dt = _dtype_code(X)
+        keep = []
+        p = _params(C, B, s, max_iter, sampling, init, precision, seed, None, None, None, init_medoids, keep)
+        need = int(lib().kkm_fit_restarts_workspace_bytes(N, d, dt, ct.byref(k), ct.byref(p), int(restarts)))
+        if need == 0:
+            _check(lib().kkm_fit_restarts(None, N, d, dt, ct.byref(k), ct.byref(p), int(restarts), None, 0, None,
+                                          None, None, None, None, None))
+        ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, X.device)
+        if model is None:
+            model = kkm_model_create(k, d, C, C, dt)
+        labels = torch.empty(N, dtype=torch.int32, device=X.device) if want_labels else None
+        upd = np.zeros(B, dtype=np.int32)
+        bmed, bcnt, gmed = (np.zeros(B * C, dtype=np.int64) for _ in range(3))
+        info = _FitInfo(_i32p(upd), _i64p(bmed), _i64p(bcnt), _i64p(gmed), 0, 0, 0, 0, 0)
+        costs = np.zeros(int(restarts), dtype=np.float64)
+        best = ct.c_int32(-1)
+        _check(lib().kkm_fit_restarts(ct.c_void_p(X.data_ptr()), N, d, dt, ct.byref(k), ct.byref(p), int(restarts),
+                                      ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream_ptr(os_.s)),
+                                      model.ptr, ct.c_void_p(labels.data_ptr()) if labels is not None else None,
+                                      ct.byref(info), _f64p(costs), ct.byref(best)))
+    out = dict(updates_per_batch=upd, batch_medoids=bmed.reshape(B, C), batch_counts=bcnt.reshape(B, C),
+               global_medoids=gmed.reshape(B, C), evals_algorithmic=info.evals_algorithmic,
+               evals_performed=info.evals_performed, rows_refined=info.rows_refined,
+               medoid_candidates=info.medoid_candidates, workspace_bytes=need, restart=int(best.value),
+               restart_costs=costs)
     return model, labels, out
 
 

@@ -129,6 +129,18 @@ struct FitPlan {
     std::vector<int32_t> med0;         // batch-0 medoid positions (explicit init)
 };
 
+// ----------------------------------------------------------------------------- assign workspace
+struct AssignWs {
+    void* Qc;
+    int32_t* refine_list;
+    int32_t* refine_count;
+    int32_t* nonfinite;
+    double* best;
+    double* partials;
+    double* cost;
+    int32_t* labels_tmp;   // labels when the caller wants only the cost
+};
+
 struct FitWs {
     void* Xc;
     int32_t* lm;
@@ -183,6 +195,9 @@ struct FitWs {
     int64_t* info;         // [3][B][C] batch medoids, counts, global medoids
     double* info_disp;     // [B][C] displacement of every global medoid per batch
     double* pcost;         // [B] partial cost of every batch
+    double* gcost;         // [B] global cost after every batch (KKM_FIT_GLOBAL_COST)
+    kkm_model gmodel;      // the global medoids as a model in the workspace (KKM_FIT_GLOBAL_COST)
+    AssignWs gws;          // its assign pass over all N rows
     double* best;          // [nmax] each batch row's distance to its nearest centroid (partial cost)
     double* psum;          // [1024] partial sums of the partial cost
     int64_t* trace;        // [64]
@@ -190,6 +205,10 @@ struct FitWs {
     int32_t* lm_error;     // [1]
     char* status_end;      // end of the status block (refine_counts .. trace)
 };
+
+size_t carve_assign(Carver& c, const kkm_model* m, int64_t n, AssignWs& w);
+kkm_status assign_launch(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, hipStream_t s,
+                         int32_t* labels, float* gap, bool want_best, const AssignWs& w);
 
 size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     const size_t es = P.dtype == KKM_F64 ? 8 : 4;
@@ -253,8 +272,23 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.info = c.take<int64_t>((size_t)3 * P.B * C);
     w.info_disp = c.take<double>((size_t)P.B * C);
     w.pcost = c.take<double>((size_t)P.B);
+    w.gcost = c.take<double>((size_t)P.B);
     w.trace = c.take<int64_t>(64);
     w.status_end = c.take<char>(1);
+    if (P.p.flags & KKM_FIT_GLOBAL_COST) {   // the global medoids as a model, and an assign pass over N
+        kkm_model& m = w.gmodel;
+        m = kkm_model{};
+        m.kernel = P.kernel;
+        m.d = P.d;
+        m.dpad = P.dpad;
+        m.bpad = bf16_pad(P.dpad);
+        m.C = C;
+        m.cap = C;
+        m.used = C;
+        m.dtype = P.dtype;
+        model_layout(&m, c);
+        carve_assign(c, &m, P.N, w.gws);
+    }
     return c.off;
 }
 
@@ -292,7 +326,7 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
         return fail(KKM_ERR_INVALID_ARG, "bad init");
     if (p.precision < KKM_PREC_FP64 || p.precision > KKM_PREC_BF16X3)
         return fail(KKM_ERR_INVALID_ARG, "bad precision");
-    if (p.flags & ~KKM_FIT_COOPERATIVE) return fail(KKM_ERR_INVALID_ARG, "unknown fit flags");
+    if (p.flags & ~(KKM_FIT_COOPERATIVE | KKM_FIT_GLOBAL_COST)) return fail(KKM_ERR_INVALID_ARG, "unknown fit flags");
     P.N = N;
     P.d = d;
     P.dtype = dtype;
@@ -378,7 +412,8 @@ kkm_status make_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kern
 
 // Sizes that follow from the batches and the device: tiles, chunks, landmark grids.
 kkm_status finish_plan(FitPlan& P, const DeviceInfo* dev) {
-    P.tile_f64 = P.p.precision == KKM_PREC_FP64 || P.kernel.type == KKM_KERNEL_RMSD;
+    P.tile_f64 = P.p.precision == KKM_PREC_FP64 ||
+                 (P.kernel.type == KKM_KERNEL_RMSD && !rmsd_on_mfma(P.kernel.n_atoms, P.dtype));
     P.nchunk = select_chunks(P.nmax);
     P.cand_cap = std::min<int64_t>((int64_t)P.nmax * P.C, (int64_t)1 << 30);
     if (dev) {
@@ -413,18 +448,6 @@ kkm_status check_device_of(const kkm_model* m) {
     if (cur != m->device) return fail(KKM_ERR_INVALID_ARG, "the model lives on another device than the current one");
     return KKM_OK;
 }
-
-// ----------------------------------------------------------------------------- assign workspace
-struct AssignWs {
-    void* Qc;
-    int32_t* refine_list;
-    int32_t* refine_count;
-    int32_t* nonfinite;
-    double* best;
-    double* partials;
-    double* cost;
-    int32_t* labels_tmp;   // labels when the caller wants only the cost
-};
 
 size_t carve_assign(Carver& c, const kkm_model* m, int64_t n, AssignWs& w) {
     const size_t es = m->dtype == KKM_F64 ? 8 : 4;
@@ -522,6 +545,302 @@ kkm_status assign_common(const kkm_model* m, const void* X, int64_t n, int32_t d
     return assign_launch(m, X, n, dtype, precision, s, labels, gap, want_best, w);
 }
 
+kkm_status check_fit_model(const kkm_model* model, const FitPlan& P) {
+    if (model->d != P.d || model->C != P.C || model->dtype != P.dtype || model->cap < P.C ||
+        model->kernel.type != P.kernel.type || model->kernel.sigma != P.kernel.sigma ||
+        model->kernel.n_atoms != P.kernel.n_atoms || model->dpad != P.dpad)
+        return fail(KKM_ERR_INVALID_ARG, "model was created for another kernel, d, C, dtype or capacity");
+    return check_device_of(model);
+}
+
+// The device work of one fit up to the merge of its last batch (and, with KKM_FIT_GLOBAL_COST, the
+// global cost after every batch), on stream s: the plan is made and the workspace carved.  up stages
+// the host-to-device copy of the draws and must outlive it (until the stream is synchronised).
+kkm_status fit_enqueue(const FitPlan& P, FitWs& w, const void* X, hipStream_t s, const DeviceInfo& dev, PhaseTimer& tm,
+                       int32_t* labels_out, bool want_pcost, bool want_disp, bool want_trace, std::vector<char>& up) {
+    const int64_t N = P.N, d = P.d;
+    const int32_t dtype = P.dtype;
+    const KSpec ks = kspec_of(P.kernel, d);
+    const int C = P.C;
+    // refine counts, flags, update counts and the loop's error word: one range of the status block
+    KKM_TRY(launch_zero_i32(w.refine_counts, (w.lm_error + 1) - w.refine_counts, s));
+    // one host-to-device copy of the inputs block: [landmarks, initial labels, uniforms, medoids]
+    // (the staging vector outlives the copy: it is released after the final synchronisation)
+    {
+        char* ub = reinterpret_cast<char*>(w.lm);
+        up.assign(static_cast<size_t>(reinterpret_cast<char*>(w.chosen + C) - ub), 0);
+        auto put = [&](void* dev_ptr, const void* src, size_t bytes) {
+            if (bytes) std::memcpy(up.data() + (reinterpret_cast<char*>(dev_ptr) - ub), src, bytes);
+        };
+        put(w.lm, P.lm_host.data(), sizeof(int32_t) * P.ell_total);
+        if (P.p.init == KKM_INIT_KMEANSPP) put(w.uniforms, P.uniforms.data(), sizeof(double) * C);
+        else if (P.p.init == KKM_INIT_MEDOIDS) put(w.chosen, P.med0.data(), sizeof(int32_t) * C);
+        else put(w.lab_init, P.lab0.data(), sizeof(int32_t) * P.ell[0]);
+        KKM_HIP(hipMemcpyAsync(ub, up.data(), up.size(), hipMemcpyHostToDevice, s));
+    }
+    const void* Xs = X;
+    if (P.kernel.type == KKM_KERNEL_RMSD) {
+        KKM_TRY(launch_centre(X, w.Xc, N, P.kernel.n_atoms, dtype, s));
+        Xs = w.Xc;
+    }
+    auto view = [&](int i) { return BatchView{Xs, d, P.base[i], P.stride[i], P.n[i]}; };
+
+    // batch-0 initialisation of the global medoids
+    KKM_TRY(tm.begin(kPhInit));
+    if (P.p.init == KKM_INIT_KMEANSPP) {
+        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.barrier,
+                                w.lm_error, dev, s, (P.p.flags & KKM_FIT_COOPERATIVE) != 0));
+        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+    } else if (P.p.init == KKM_INIT_MEDOIDS) {
+        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+    } else {
+        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, nullptr, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+    }
+    KKM_TRY(tm.end(kPhInit));
+
+    for (int i = 0; i < P.B; ++i) {
+        const BatchView bv = view(i);
+        const int ell = (int)P.ell[i];
+        LandmarkArgs la{};
+        la.X = Xs;
+        la.d = d;
+        la.base = bv.base;
+        la.stride = bv.stride;
+        la.lm = w.lm + P.lm_off[i];
+        la.ell = ell;
+        la.C = C;
+        la.max_updates = P.T - 1;
+        const LandmarkShape lsh = landmark_shape(dev, ell, C);
+        la.grid = lsh.grid;
+        la.k_in_lds = lsh.k_in_lds;
+        la.cooperative = (P.p.flags & KKM_FIT_COOPERATIVE) != 0;
+        la.ktype = P.kernel.type;
+        la.n_atoms = P.kernel.n_atoms;
+        la.inv2s2 = ks.inv2s2;
+        la.init_mode = (i == 0 && P.p.init == KKM_INIT_RANDOM_LABELS) ? 0 : 1;
+        la.lab_init = w.lab_init;
+        la.M = w.M;
+        la.Mpad = P.dpad;
+        la.Mself = w.Mself;
+        la.Kbuf = w.Kbuf;
+        la.ldk = landmark_ldk(ell);
+        la.Kmed = w.Kmed;
+        la.lab = w.lab;
+        la.nlab_x = w.nlab_x;
+        la.sx = w.sx;
+        la.partial = w.partial;
+        la.changed = w.changed;
+        la.zero_ints = w.counts_b;
+        la.n_zero_ints = C + 1;
+        la.lab_final = w.lab_final;
+        la.offsets = w.offsets;
+        la.ghat = w.ghat;
+        la.segabs = w.segabs;
+        la.updates_out = w.updates + i;
+        la.support = w.support;
+        la.dpad = P.dpad;
+        la.snorm32 = w.snorm32;
+        la.snorm64 = w.snorm64;
+        la.coef32 = w.coef32;
+        la.coef64 = w.coef64;
+        la.src_index = w.src_index;
+        la.snorm_max = w.snorm_max;
+        la.split = w.split;
+        la.sup_pan = w.sup_pan;
+        la.sup_hi = w.sup_hi;
+        la.sup_lo = w.sup_lo;
+        la.bpad = bf16_pad(P.dpad);
+        la.trace = (i == 0 && want_trace) ? w.trace : nullptr;
+        la.barrier = w.barrier;
+        la.colmin = w.colmin;
+        la.error = w.lm_error;
+        if (la.trace) {
+            KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
+            tm.gap();
+        }
+        KKM_TRY(tm.begin(kPhLandmark));
+        KKM_TRY(launch_landmark_block(la, dtype, dev, s));
+        KKM_TRY(tm.end(kPhLandmark));
+        KKM_TRY(tm.begin(kPhLoop));
+        KKM_TRY(launch_landmark_loop(la, dtype, dev, s));
+        KKM_TRY(tm.end(kPhLoop));
+
+        SupportView sv;
+        sv.rows = w.support;
+        sv.dpad = P.dpad;
+        sv.snorm32 = w.snorm32;
+        sv.snorm64 = w.snorm64;
+        sv.coef32 = w.coef32;
+        sv.coef64 = w.coef64;
+        sv.offsets = w.offsets;
+        sv.self = w.ghat;
+        sv.segabs = w.segabs;
+        sv.snorm_max = w.snorm_max;
+        sv.split = w.split;
+        sv.nonneg = 1;
+        sv.pan = w.sup_pan;
+        sv.hi = w.sup_hi;
+        sv.lo = w.sup_lo;
+        sv.bpad = bf16_pad(P.dpad);
+        sv.C = C;
+        sv.medoid_form = 0;
+
+        DistArgs da{};
+        da.q = bv;
+        da.dtype = dtype;
+        // the batch medoids take every row with D - E under the column minimum of D + E as a candidate:
+        // the plain BF16 bound would make nearly every row one, so a fit's batch pass takes the
+        // compensated BF16x3 products when BF16 is asked for
+        da.precision = P.p.precision == KKM_PREC_BF16 ? KKM_PREC_BF16X3 : P.p.precision;
+        da.ks = ks;
+        da.sup = sv;
+        da.Dt = w.Dt;
+        da.ldD = P.nmax;
+        da.Erow = w.Erow;
+        da.labels = w.labels_b;
+        da.gap = nullptr;
+        const bool pcost = want_pcost;
+        da.best = pcost ? w.best : nullptr;
+        da.refine_list = w.refine_list;
+        da.refine_count = w.refine_counts + i;
+        da.nonfinite = w.flags;
+        da.colmin = w.colmin;
+        da.colpart = w.colpart;
+        da.colpart_cap = dist_block_cap(P.nmax);
+        da.n_support = ell;
+        int64_t dist_blocks = 0;
+        da.colpart_blocks = &dist_blocks;
+        KKM_TRY(tm.begin(kPhDist));
+        KKM_TRY(launch_dist(da, dev, s));
+        KKM_TRY(tm.end(kPhDist));
+        if (!dist_is_fp64(da)) {
+            KKM_TRY(tm.begin(kPhRefine));
+            KKM_TRY(launch_refine(da, dev, s, ell));
+            KKM_TRY(tm.end(kPhRefine));
+        }
+        if (pcost) {   // the batch's partial cost: its rows' distances summed in a fixed order
+            tm.gap();
+            KKM_TRY(launch_sum(w.best, bv.n, w.psum, w.pcost + i, s));
+        }
+
+        SelectArgs sa{};
+        sa.b = bv;
+        sa.dtype = dtype;
+        sa.ks = ks;
+        sa.C = C;
+        sa.M = w.M;
+        sa.Mpad = P.dpad;
+        sa.Mself = w.Mself;
+        sa.Midx = w.Midx;
+        sa.wcount = w.wcount;
+        sa.labels = w.labels_b;
+        sa.counts = w.counts_b;
+        sa.bmed = w.bmed;
+        sa.label_out = labels_out;
+        sa.Dt = w.Dt;
+        sa.ldD = P.nmax;
+        sa.Erow = w.Erow;
+        sa.sup = sv;
+        sa.nchunk = select_chunks(bv.n);
+        sa.mpart_c = w.mpart_c;
+        sa.colmin = w.colmin;
+        sa.cand_q = w.cand_q;
+        sa.cand_j = w.cand_j;
+        sa.cand_v = w.cand_v;
+        sa.cand_count = w.counts_b + C;
+        sa.cand_cap = (int32_t)P.cand_cap;
+        sa.gpart_v = w.gpart_v;
+        sa.gpart_i = w.gpart_i;
+
+        sa.info_bmed = w.info + (size_t)i * C;
+        sa.info_bcnt = w.info + (size_t)(P.B + i) * C;
+        sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
+        sa.info_disp = want_disp ? w.info_disp + (size_t)i * C : nullptr;
+        KKM_TRY(tm.begin(kPhSelect));
+        sa.cand_total = w.flags + 1;
+        sa.colpart = w.colpart;
+        sa.colpart_ld = da.colpart_cap;
+        sa.colpart_blocks = dist_blocks;
+        KKM_TRY(launch_select(sa, dist_is_fp64(da), dev, s));
+        KKM_TRY(tm.end(kPhSelect));
+        if (P.p.flags & KKM_FIT_GLOBAL_COST) {
+            // Omega(W) after this batch: the global medoids as they stand, against all N samples
+            tm.gap();
+            kkm_model& gm = w.gmodel;
+            gm.device = dev.device;
+            gm.medoid_form = P.p.init != KKM_INIT_RANDOM_LABELS;   // every medoid set from the first batch on
+            KKM_TRY(launch_model_from_medoids(&gm, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
+            KKM_TRY(assign_launch(&gm, X, N, dtype, P.p.precision, s, w.gws.labels_tmp, nullptr, true, w.gws));
+            KKM_TRY(launch_sum(w.gws.best, N, w.gws.partials, w.gcost + i, s));
+        }
+    }
+    return KKM_OK;
+}
+
+// After the stream has been synchronised: the fit's outputs from its status block copy st (model host
+// fields, info) and its error words.
+kkm_status fit_finish(const FitPlan& P, const FitWs& w, const std::vector<char>& st, kkm_model* model,
+                      kkm_fit_info* info, PhaseTimer& tm) {
+    const int C = P.C;
+    const char* sb = reinterpret_cast<const char*>(w.refine_counts);
+    auto host_at = [&](const void* dev_ptr) { return st.data() + (reinterpret_cast<const char*>(dev_ptr) - sb); };
+    const int32_t* refined = reinterpret_cast<const int32_t*>(host_at(w.refine_counts));
+    const int32_t* flags = reinterpret_cast<const int32_t*>(host_at(w.flags));
+    const int32_t* updates = reinterpret_cast<const int32_t*>(host_at(w.updates));
+    const int32_t lm_err = *reinterpret_cast<const int32_t*>(host_at(w.lm_error));
+    const int64_t* infos = reinterpret_cast<const int64_t*>(host_at(w.info));
+    if (info && info->landmark_trace) std::memcpy(info->landmark_trace, host_at(w.trace), sizeof(int64_t) * 64);
+    if (info && info->medoid_displacement)
+        std::memcpy(info->medoid_displacement, host_at(w.info_disp), sizeof(double) * (size_t)P.B * C);
+    if (info && info->partial_cost) std::memcpy(info->partial_cost, host_at(w.pcost), sizeof(double) * (size_t)P.B);
+    if (info && info->global_cost && (P.p.flags & KKM_FIT_GLOBAL_COST))
+        std::memcpy(info->global_cost, host_at(w.gcost), sizeof(double) * (size_t)P.B);
+    model->used = C;
+    model->nonneg = 1;
+    {   // a medoid model unless a cluster never received a medoid (its self term is then +inf)
+        const int64_t* last = reinterpret_cast<const int64_t*>(host_at(w.info)) + (size_t)(2 * P.B + P.B - 1) * C;
+        int32_t all = 1;
+        for (int j = 0; j < C; ++j) all &= last[j] >= 0 ? 1 : 0;
+        model->medoid_form = all;
+    }
+
+    if (info) {
+        int64_t alg = 0, perf = 0, rows_ref = 0;
+        for (int i = 0; i < P.B; ++i) {
+            const int64_t n = P.n[i], ell = P.ell[i];
+            int64_t nonempty = 0;
+            for (int j = 0; j < C; ++j) nonempty += infos[(size_t)(P.B + i) * C + j] > 0;
+            alg += n * ell + n * nonempty;
+            const bool eq8 = i > 0 || P.p.init != KKM_INIT_RANDOM_LABELS;
+            if (i > 0 || P.p.init == KKM_INIT_KMEANSPP) alg += n * C;
+            perf += ell * ell + (eq8 ? ell * C : 0) + n * ell + (int64_t)refined[i] * ell + 2 * n * nonempty;
+            if (i == 0 && P.p.init == KKM_INIT_KMEANSPP) perf += n * (C - 1);
+            rows_ref += refined[i];
+            if (info->updates_per_batch) info->updates_per_batch[i] = updates[i] + 1;
+            for (int j = 0; j < C; ++j) {
+                if (info->batch_medoids) info->batch_medoids[(size_t)i * C + j] = infos[(size_t)i * C + j];
+                if (info->batch_counts) info->batch_counts[(size_t)i * C + j] = infos[(size_t)(P.B + i) * C + j];
+                if (info->global_medoids) info->global_medoids[(size_t)i * C + j] = infos[(size_t)(2 * P.B + i) * C + j];
+            }
+        }
+        info->evals_algorithmic = alg;
+        info->evals_performed = perf;
+        info->rows_refined = rows_ref;
+        info->medoid_candidates = flags[1];
+        double ms[kPhases];
+        tm.collect(ms);
+        info->ms_init = ms[kPhInit];
+        info->ms_landmark = ms[kPhLandmark] + ms[kPhLoop];
+        info->ms_landmark_loop = ms[kPhLoop];
+        info->ms_dist = ms[kPhDist];
+        info->ms_refine = ms[kPhRefine];
+        info->ms_select = ms[kPhSelect];
+    }
+    if (lm_err) return fail(KKM_ERR_INTERNAL, "a grid-barrier wait (k-means++ or landmark loop) exceeded its cap");
+    if (flags[0]) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
+    return KKM_OK;
+}
+
 }  // namespace
 }  // namespace kkm
 
@@ -595,11 +914,7 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     KKM_TRY(device_info(&dev));
     FitPlan P;
     KKM_TRY(make_plan(N, d, dtype, kernel, params, &dev, P));
-    if (model->d != d || model->C != P.C || model->dtype != dtype || model->cap < P.C ||
-        model->kernel.type != kernel->type || model->kernel.sigma != kernel->sigma ||
-        model->kernel.n_atoms != kernel->n_atoms || model->dpad != P.dpad)
-        return fail(KKM_ERR_INVALID_ARG, "model was created for another kernel, d, C, dtype or capacity");
-    KKM_TRY(check_device_of(model));
+    KKM_TRY(check_fit_model(model, P));
     FitWs w;
     Carver probe(nullptr);
     const size_t need = carve_fit(probe, P, w);
@@ -607,280 +922,138 @@ kkm_status kkm_fit(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm
     Carver c(workspace);
     carve_fit(c, P, w);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const KSpec ks = kspec_of(*kernel, d);
-    const int C = P.C;
-    const size_t es = dtype == KKM_F64 ? 8 : 4;
     PhaseTimer tm;
     tm.on = info && info->time_phases;
     if (tm.on && info->time_phases == 2) tm.mask = (1u << kPhLoop) | (1u << kPhDist);
     tm.s = s;
     tm.device = dev.device;
-
-    // refine counts, flags, update counts and the loop's error word: one range of the status block
-    KKM_TRY(launch_zero_i32(w.refine_counts, (w.lm_error + 1) - w.refine_counts, s));
-    // one host-to-device copy of the inputs block: [landmarks, initial labels, uniforms, medoids]
-    // (the staging vector outlives the copy: it is released after the final synchronisation)
     std::vector<char> up;
-    {
-        char* ub = reinterpret_cast<char*>(w.lm);
-        up.assign(static_cast<size_t>(reinterpret_cast<char*>(w.chosen + C) - ub), 0);
-        auto put = [&](void* dev_ptr, const void* src, size_t bytes) {
-            if (bytes) std::memcpy(up.data() + (reinterpret_cast<char*>(dev_ptr) - ub), src, bytes);
-        };
-        put(w.lm, P.lm_host.data(), sizeof(int32_t) * P.ell_total);
-        if (P.p.init == KKM_INIT_KMEANSPP) put(w.uniforms, P.uniforms.data(), sizeof(double) * C);
-        else if (P.p.init == KKM_INIT_MEDOIDS) put(w.chosen, P.med0.data(), sizeof(int32_t) * C);
-        else put(w.lab_init, P.lab0.data(), sizeof(int32_t) * P.ell[0]);
-        KKM_HIP(hipMemcpyAsync(ub, up.data(), up.size(), hipMemcpyHostToDevice, s));
-    }
-    const void* Xs = X;
-    if (kernel->type == KKM_KERNEL_RMSD) {
-        KKM_TRY(launch_centre(X, w.Xc, N, kernel->n_atoms, dtype, s));
-        Xs = w.Xc;
-    }
-    auto view = [&](int i) { return BatchView{Xs, d, P.base[i], P.stride[i], P.n[i]}; };
-
-    // batch-0 initialisation of the global medoids
-    KKM_TRY(tm.begin(kPhInit));
-    if (P.p.init == KKM_INIT_KMEANSPP) {
-        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.barrier,
-                                w.lm_error, dev, s, (P.p.flags & KKM_FIT_COOPERATIVE) != 0));
-        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
-    } else if (P.p.init == KKM_INIT_MEDOIDS) {
-        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
-    } else {
-        KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, nullptr, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
-    }
-    KKM_TRY(tm.end(kPhInit));
-
-    for (int i = 0; i < P.B; ++i) {
-        const BatchView bv = view(i);
-        const int ell = (int)P.ell[i];
-        LandmarkArgs la{};
-        la.X = Xs;
-        la.d = d;
-        la.base = bv.base;
-        la.stride = bv.stride;
-        la.lm = w.lm + P.lm_off[i];
-        la.ell = ell;
-        la.C = C;
-        la.max_updates = P.T - 1;
-        const LandmarkShape lsh = landmark_shape(dev, ell, C);
-        la.grid = lsh.grid;
-        la.k_in_lds = lsh.k_in_lds;
-        la.cooperative = (P.p.flags & KKM_FIT_COOPERATIVE) != 0;
-        la.ktype = kernel->type;
-        la.n_atoms = kernel->n_atoms;
-        la.inv2s2 = ks.inv2s2;
-        la.init_mode = (i == 0 && P.p.init == KKM_INIT_RANDOM_LABELS) ? 0 : 1;
-        la.lab_init = w.lab_init;
-        la.M = w.M;
-        la.Mpad = P.dpad;
-        la.Mself = w.Mself;
-        la.Kbuf = w.Kbuf;
-        la.ldk = landmark_ldk(ell);
-        la.Kmed = w.Kmed;
-        la.lab = w.lab;
-        la.nlab_x = w.nlab_x;
-        la.sx = w.sx;
-        la.partial = w.partial;
-        la.changed = w.changed;
-        la.zero_ints = w.counts_b;
-        la.n_zero_ints = C + 1;
-        la.lab_final = w.lab_final;
-        la.offsets = w.offsets;
-        la.ghat = w.ghat;
-        la.segabs = w.segabs;
-        la.updates_out = w.updates + i;
-        la.support = w.support;
-        la.dpad = P.dpad;
-        la.snorm32 = w.snorm32;
-        la.snorm64 = w.snorm64;
-        la.coef32 = w.coef32;
-        la.coef64 = w.coef64;
-        la.src_index = w.src_index;
-        la.snorm_max = w.snorm_max;
-        la.split = w.split;
-        la.sup_pan = w.sup_pan;
-        la.sup_hi = w.sup_hi;
-        la.sup_lo = w.sup_lo;
-        la.bpad = bf16_pad(P.dpad);
-        la.trace = (i == 0 && info && info->landmark_trace) ? w.trace : nullptr;
-        la.barrier = w.barrier;
-        la.colmin = w.colmin;
-        la.error = w.lm_error;
-        if (la.trace) {
-            KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(w.trace), 2 * 64, s));
-            tm.gap();
-        }
-        KKM_TRY(tm.begin(kPhLandmark));
-        KKM_TRY(launch_landmark_block(la, dtype, dev, s));
-        KKM_TRY(tm.end(kPhLandmark));
-        KKM_TRY(tm.begin(kPhLoop));
-        KKM_TRY(launch_landmark_loop(la, dtype, dev, s));
-        KKM_TRY(tm.end(kPhLoop));
-
-        SupportView sv;
-        sv.rows = w.support;
-        sv.dpad = P.dpad;
-        sv.snorm32 = w.snorm32;
-        sv.snorm64 = w.snorm64;
-        sv.coef32 = w.coef32;
-        sv.coef64 = w.coef64;
-        sv.offsets = w.offsets;
-        sv.self = w.ghat;
-        sv.segabs = w.segabs;
-        sv.snorm_max = w.snorm_max;
-        sv.split = w.split;
-        sv.nonneg = 1;
-        sv.pan = w.sup_pan;
-        sv.hi = w.sup_hi;
-        sv.lo = w.sup_lo;
-        sv.bpad = bf16_pad(P.dpad);
-        sv.C = C;
-        sv.medoid_form = 0;
-
-        DistArgs da{};
-        da.q = bv;
-        da.dtype = dtype;
-        // the batch medoids take every row with D - E under the column minimum of D + E as a candidate:
-        // the plain BF16 bound would make nearly every row one, so a fit's batch pass takes the
-        // compensated BF16x3 products when BF16 is asked for
-        da.precision = P.p.precision == KKM_PREC_BF16 ? KKM_PREC_BF16X3 : P.p.precision;
-        da.ks = ks;
-        da.sup = sv;
-        da.Dt = w.Dt;
-        da.ldD = P.nmax;
-        da.Erow = w.Erow;
-        da.labels = w.labels_b;
-        da.gap = nullptr;
-        const bool pcost = info && info->partial_cost;
-        da.best = pcost ? w.best : nullptr;
-        da.refine_list = w.refine_list;
-        da.refine_count = w.refine_counts + i;
-        da.nonfinite = w.flags;
-        da.colmin = w.colmin;
-        da.colpart = w.colpart;
-        da.colpart_cap = dist_block_cap(P.nmax);
-        da.n_support = ell;
-        int64_t dist_blocks = 0;
-        da.colpart_blocks = &dist_blocks;
-        KKM_TRY(tm.begin(kPhDist));
-        KKM_TRY(launch_dist(da, dev, s));
-        KKM_TRY(tm.end(kPhDist));
-        if (!dist_is_fp64(da)) {
-            KKM_TRY(tm.begin(kPhRefine));
-            KKM_TRY(launch_refine(da, dev, s, ell));
-            KKM_TRY(tm.end(kPhRefine));
-        }
-        if (pcost) {   // the batch's partial cost: its rows' distances summed in a fixed order
-            tm.gap();
-            KKM_TRY(launch_sum(w.best, bv.n, w.psum, w.pcost + i, s));
-        }
-
-        SelectArgs sa{};
-        sa.b = bv;
-        sa.dtype = dtype;
-        sa.ks = ks;
-        sa.C = C;
-        sa.M = w.M;
-        sa.Mpad = P.dpad;
-        sa.Mself = w.Mself;
-        sa.Midx = w.Midx;
-        sa.wcount = w.wcount;
-        sa.labels = w.labels_b;
-        sa.counts = w.counts_b;
-        sa.bmed = w.bmed;
-        sa.label_out = labels_out;
-        sa.Dt = w.Dt;
-        sa.ldD = P.nmax;
-        sa.Erow = w.Erow;
-        sa.sup = sv;
-        sa.nchunk = select_chunks(bv.n);
-        sa.mpart_c = w.mpart_c;
-        sa.colmin = w.colmin;
-        sa.cand_q = w.cand_q;
-        sa.cand_j = w.cand_j;
-        sa.cand_v = w.cand_v;
-        sa.cand_count = w.counts_b + C;
-        sa.cand_cap = (int32_t)P.cand_cap;
-        sa.gpart_v = w.gpart_v;
-        sa.gpart_i = w.gpart_i;
-
-        sa.info_bmed = w.info + (size_t)i * C;
-        sa.info_bcnt = w.info + (size_t)(P.B + i) * C;
-        sa.info_gmed = w.info + (size_t)(2 * P.B + i) * C;
-        sa.info_disp = info && info->medoid_displacement ? w.info_disp + (size_t)i * C : nullptr;
-        KKM_TRY(tm.begin(kPhSelect));
-        sa.cand_total = w.flags + 1;
-        sa.colpart = w.colpart;
-        sa.colpart_ld = da.colpart_cap;
-        sa.colpart_blocks = dist_blocks;
-        KKM_TRY(launch_select(sa, dist_is_fp64(da), dev, s));
-        KKM_TRY(tm.end(kPhSelect));
-    }
+    KKM_TRY(fit_enqueue(P, w, X, s, dev, tm, labels_out, info && info->partial_cost, info && info->medoid_displacement,
+                        info && info->landmark_trace, up));
     KKM_TRY(launch_model_from_medoids(model, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
-
     // one device-to-host copy of the status block
     const char* sb = reinterpret_cast<const char*>(w.refine_counts);
     std::vector<char> st((size_t)(w.status_end - sb));
     KKM_HIP(hipMemcpyAsync(st.data(), sb, st.size(), hipMemcpyDeviceToHost, s));
     KKM_HIP(hipStreamSynchronize(s));
-    auto host_at = [&](const void* dev_ptr) { return st.data() + (reinterpret_cast<const char*>(dev_ptr) - sb); };
-    const int32_t* refined = reinterpret_cast<const int32_t*>(host_at(w.refine_counts));
-    const int32_t* flags = reinterpret_cast<const int32_t*>(host_at(w.flags));
-    const int32_t* updates = reinterpret_cast<const int32_t*>(host_at(w.updates));
-    const int32_t lm_err = *reinterpret_cast<const int32_t*>(host_at(w.lm_error));
-    const int64_t* infos = reinterpret_cast<const int64_t*>(host_at(w.info));
-    if (info && info->landmark_trace) std::memcpy(info->landmark_trace, host_at(w.trace), sizeof(int64_t) * 64);
-    if (info && info->medoid_displacement)
-        std::memcpy(info->medoid_displacement, host_at(w.info_disp), sizeof(double) * (size_t)P.B * C);
-    if (info && info->partial_cost) std::memcpy(info->partial_cost, host_at(w.pcost), sizeof(double) * (size_t)P.B);
-    model->used = C;
-    model->nonneg = 1;
-    {   // a medoid model unless a cluster never received a medoid (its self term is then +inf)
-        const int64_t* last = reinterpret_cast<const int64_t*>(host_at(w.info)) + (size_t)(2 * P.B + P.B - 1) * C;
-        int32_t all = 1;
-        for (int j = 0; j < C; ++j) all &= last[j] >= 0 ? 1 : 0;
-        model->medoid_form = all;
-    }
-    (void)es;
+    return fit_finish(P, w, st, model, info, tm);
+}
 
-    if (info) {
-        int64_t alg = 0, perf = 0, rows_ref = 0;
-        for (int i = 0; i < P.B; ++i) {
-            const int64_t n = P.n[i], ell = P.ell[i];
-            int64_t nonempty = 0;
-            for (int j = 0; j < C; ++j) nonempty += infos[(size_t)(P.B + i) * C + j] > 0;
-            alg += n * ell + n * nonempty;
-            const bool eq8 = i > 0 || P.p.init != KKM_INIT_RANDOM_LABELS;
-            if (i > 0 || P.p.init == KKM_INIT_KMEANSPP) alg += n * C;
-            perf += ell * ell + (eq8 ? ell * C : 0) + n * ell + (int64_t)refined[i] * ell + 2 * n * nonempty;
-            if (i == 0 && P.p.init == KKM_INIT_KMEANSPP) perf += n * (C - 1);
-            rows_ref += refined[i];
-            if (info->updates_per_batch) info->updates_per_batch[i] = updates[i] + 1;
-            for (int j = 0; j < C; ++j) {
-                if (info->batch_medoids) info->batch_medoids[(size_t)i * C + j] = infos[(size_t)i * C + j];
-                if (info->batch_counts) info->batch_counts[(size_t)i * C + j] = infos[(size_t)(P.B + i) * C + j];
-                if (info->global_medoids) info->global_medoids[(size_t)i * C + j] = infos[(size_t)(2 * P.B + i) * C + j];
-            }
-        }
-        info->evals_algorithmic = alg;
-        info->evals_performed = perf;
-        info->rows_refined = rows_ref;
-        info->medoid_candidates = flags[1];
-        double ms[kPhases];
-        tm.collect(ms);
-        info->ms_init = ms[kPhInit];
-        info->ms_landmark = ms[kPhLandmark] + ms[kPhLoop];
-        info->ms_landmark_loop = ms[kPhLoop];
-        info->ms_dist = ms[kPhDist];
-        info->ms_refine = ms[kPhRefine];
-        info->ms_select = ms[kPhSelect];
+// ----------------------------------------------------------------------------- restarts (Sec. 4.5)
+namespace {
+// Workspace of R restarts: per restart a fit workspace, its medoids as a model and its labels; one
+// assign workspace over the N samples for the cost passes (run one after another on the stream).
+struct RestartLayout {
+    std::vector<FitWs> w;
+    std::vector<kkm_model> m;
+    std::vector<int32_t*> labels;
+    std::vector<double*> cost;
+    AssignWs aws;
+};
+size_t carve_restarts(Carver& c, const FitPlan& P, int R, RestartLayout& L) {
+    L.w.assign(R, FitWs{});
+    L.m.assign(R, kkm_model{});
+    L.labels.assign(R, nullptr);
+    L.cost.assign(R, nullptr);
+    for (int r = 0; r < R; ++r) {
+        carve_fit(c, P, L.w[r]);
+        kkm_model& m = L.m[r];
+        m.kernel = P.kernel;
+        m.d = P.d;
+        m.dpad = P.dpad;
+        m.bpad = bf16_pad(P.dpad);
+        m.C = P.C;
+        m.cap = P.C;
+        m.used = P.C;
+        m.dtype = P.dtype;
+        model_layout(&m, c);
+        L.labels[r] = c.take<int32_t>((size_t)P.N);
+        L.cost[r] = c.take<double>(1);
     }
-    if (lm_err) return fail(KKM_ERR_INTERNAL, "a grid-barrier wait (k-means++ or landmark loop) exceeded its cap");
-    if (flags[0]) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
-    return KKM_OK;
+    carve_assign(c, &L.m[0], P.N, L.aws);
+    return c.off;
+}
+
+kkm_status restart_plan(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel, const kkm_params* params,
+                        int R, int r, const DeviceInfo* dev, FitPlan& P, bool draws) {
+    if (!params) return fail(KKM_ERR_INVALID_ARG, "params is NULL");
+    if (R < 1 || R > 1024) return fail(KKM_ERR_INVALID_ARG, "restarts must be in [1, 1024]");
+    if (params->landmarks || params->kmpp_uniforms || params->init_labels)
+        return fail(KKM_ERR_INVALID_ARG, "restarts draw their own landmarks and initialisation: pass none");
+    kkm_params p = *params;
+    p.seed = params->seed + (uint64_t)r;
+    return make_plan(N, d, dtype, kernel, &p, dev, P, draws);
+}
+}  // namespace
+
+size_t kkm_fit_restarts_workspace_bytes(int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
+                                        const kkm_params* params, int32_t restarts) {
+    FitPlan P;
+    DeviceInfo dev;
+    const bool have_dev = device_info(&dev) == KKM_OK;
+    if (restart_plan(N, d, dtype, kernel, params, restarts, 0, have_dev ? &dev : nullptr, P, false) != KKM_OK) return 0;
+    RestartLayout L;
+    Carver c(nullptr);
+    return carve_restarts(c, P, restarts, L);
+}
+
+kkm_status kkm_fit_restarts(const void* X, int64_t N, int64_t d, int32_t dtype, const kkm_kernel* kernel,
+                            const kkm_params* params, int32_t restarts, void* workspace, size_t workspace_bytes,
+                            void* stream, kkm_model* model, int32_t* labels_out, kkm_fit_info* info,
+                            double* costs_out, int32_t* best_out) {
+    if (!X) return fail(KKM_ERR_INVALID_ARG, "X is NULL");
+    if (!model) return fail(KKM_ERR_INVALID_ARG, "model is NULL");
+    DeviceInfo dev;
+    KKM_TRY(device_info(&dev));
+    const int R = restarts;
+    std::vector<FitPlan> P(std::max(1, R));
+    for (int r = 0; r < R; ++r) KKM_TRY(restart_plan(N, d, dtype, kernel, params, R, r, &dev, P[r], true));
+    if (R < 1) return fail(KKM_ERR_INVALID_ARG, "restarts must be >= 1");
+    KKM_TRY(check_fit_model(model, P[0]));
+    RestartLayout L;
+    {
+        Carver probe(nullptr);
+        KKM_TRY(check_workspace(workspace, workspace_bytes, carve_restarts(probe, P[0], R, L)));
+    }
+    Carver c(workspace);
+    carve_restarts(c, P[0], R, L);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // every restart back to back on the stream: its fit, its medoids as a model, its FP64 cost over
+    // all N samples (Eq. 1, as kkm_cost), and the copy of its status block; one synchronisation
+    std::vector<std::vector<char>> up(R), st(R);
+    std::vector<PhaseTimer> tms(R);
+    for (int r = 0; r < R; ++r) {
+        FitWs& w = L.w[r];
+        tms[r].device = dev.device;
+        KKM_TRY(fit_enqueue(P[r], w, X, s, dev, tms[r], L.labels[r], false, false, false, up[r]));
+        kkm_model& m = L.m[r];
+        m.device = dev.device;
+        m.medoid_form = P[r].p.init != KKM_INIT_RANDOM_LABELS;
+        KKM_TRY(launch_model_from_medoids(&m, w.M, P[r].dpad, w.Mself, w.Midx, w.wcount, s));
+        KKM_TRY(assign_launch(&m, X, N, dtype, KKM_PREC_FP64, s, L.aws.labels_tmp, nullptr, true, L.aws));
+        KKM_TRY(launch_sum(L.aws.best, N, L.aws.partials, L.cost[r], s));
+        const char* sb = reinterpret_cast<const char*>(w.refine_counts);
+        st[r].resize((size_t)(w.status_end - sb));
+        KKM_HIP(hipMemcpyAsync(st[r].data(), sb, st[r].size(), hipMemcpyDeviceToHost, s));
+    }
+    std::vector<double> cost(R);
+    for (int r = 0; r < R; ++r) KKM_HIP(hipMemcpyAsync(&cost[r], L.cost[r], sizeof(double), hipMemcpyDeviceToHost, s));
+    KKM_HIP(hipStreamSynchronize(s));
+    // the lowest cost wins, the lowest restart on equal costs (every fit's errors are reported first)
+    int best = 0;
+    for (int r = 0; r < R; ++r) {
+        kkm_model scratch_model{};
+        const kkm_status e = fit_finish(P[r], L.w[r], st[r], &scratch_model, nullptr, tms[r]);
+        if (e != KKM_OK) return e;
+        if (cost[r] < cost[best]) best = r;
+    }
+    if (costs_out) std::copy(cost.begin(), cost.end(), costs_out);
+    if (best_out) *best_out = best;
+    const FitWs& wb = L.w[best];
+    KKM_TRY(launch_model_from_medoids(model, wb.M, P[best].dpad, wb.Mself, wb.Midx, wb.wcount, s));
+    if (labels_out) KKM_HIP(hipMemcpyAsync(labels_out, L.labels[best], sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
+    KKM_HIP(hipStreamSynchronize(s));
+    return fit_finish(P[best], wb, st[best], model, info, tms[best]);
 }
 
 size_t kkm_kernel_block_workspace_bytes(const kkm_kernel* kernel, int64_t nx, int64_t ny, int64_t d, int32_t dtype) {

@@ -171,6 +171,33 @@ static kkm_status check_kernel(const kkm_kernel* k, int64_t d) {
     return KKM_OK;
 }
 
+}  // extern "C"
+
+namespace kkm {
+void model_layout(kkm_model* m, Carver& c) {
+    const size_t es = m->dtype == KKM_F64 ? 8 : 4;
+    const size_t rows = (size_t)m->cap + 32;   // the matrix-core pass reads whole 32-row tiles
+    const int C = m->C;
+    m->support = c.take<char>(rows * m->dpad * es);
+    m->snorm32 = c.take<float>(rows);
+    m->snorm64 = c.take<double>(rows);
+    m->coef32 = c.take<float>(rows);
+    m->coef64 = c.take<double>(rows);
+    m->pan = m->dtype == KKM_F32 ? c.take<float>(panel_rows(rows) * m->dpad) : nullptr;
+    m->hi = c.take<uint16_t>(panel_rows(rows) * m->bpad);
+    m->lo = c.take<uint16_t>(panel_rows(rows) * m->bpad);
+    m->offsets = c.take<int32_t>(C + 1);
+    m->self = c.take<double>(C);
+    m->segabs = c.take<double>(C);
+    m->snorm_max = c.take<float>(1);
+    m->split = c.take<int32_t>(5);
+    m->counts = c.take<int64_t>(C);
+    m->medoid_index = c.take<int64_t>(C);
+}
+}  // namespace kkm
+
+extern "C" {
+
 kkm_status kkm_model_create(const kkm_kernel* kernel, int64_t d, int32_t C, int64_t max_support, int32_t dtype,
                             kkm_model** out) {
     if (!out) return fail(KKM_ERR_INVALID_ARG, "out is NULL");
@@ -194,26 +221,8 @@ kkm_status kkm_model_create(const kkm_kernel* kernel, int64_t d, int32_t C, int6
     m->used = 0;
     m->dtype = dtype;
     m->device = dev.device;
-    const size_t es = dtype == KKM_F64 ? 8 : 4;
     Carver cv(nullptr);
-    const size_t rows = (size_t)max_support + 32;   // the matrix-core pass reads whole 32-row tiles
-    auto layout = [&](Carver& c) {
-        m->support = c.take<char>(rows * m->dpad * es);
-        m->snorm32 = c.take<float>(rows);
-        m->snorm64 = c.take<double>(rows);
-        m->coef32 = c.take<float>(rows);
-        m->coef64 = c.take<double>(rows);
-        m->pan = dtype == KKM_F32 ? c.take<float>(panel_rows(rows) * m->dpad) : nullptr;
-        m->hi = c.take<uint16_t>(panel_rows(rows) * m->bpad);
-        m->lo = c.take<uint16_t>(panel_rows(rows) * m->bpad);
-        m->offsets = c.take<int32_t>(C + 1);
-        m->self = c.take<double>(C);
-        m->segabs = c.take<double>(C);
-        m->snorm_max = c.take<float>(1);
-        m->split = c.take<int32_t>(5);
-        m->counts = c.take<int64_t>(C);
-        m->medoid_index = c.take<int64_t>(C);
-    };
+    auto layout = [&](Carver& c) { model_layout(m, c); };
     layout(cv);
     void* block = nullptr;
     hipError_t e = hipMalloc(&block, cv.off);

@@ -583,7 +583,9 @@ kkm_status launch_dist_dot(const DistArgs& a, const DeviceInfo& dev, hipStream_t
 
 }  // namespace
 
-bool dist_is_fp64(const DistArgs& a) { return a.precision == KKM_PREC_FP64 || a.ks.type == KKM_KERNEL_RMSD; }
+bool dist_is_fp64(const DistArgs& a) {
+    return a.precision == KKM_PREC_FP64 || (a.ks.type == KKM_KERNEL_RMSD && !mfma_dist_applies(a));
+}
 
 size_t dist_lds_bytes(const DistArgs& a) { return (dist_is_fp64(a) ? 8 : 4) * (size_t)a.sup.C * 64; }  // LPQ = 1
 

@@ -1005,6 +1005,9 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
     // support rows (one wavefront per row, lanes over the dimensions; two rows at a time): row copy,
     // FP32 / bfloat16 panels, norms
     const bool panels = a.ktype != KKM_KERNEL_RMSD;   // power-of-two padded rows only
+    // RMSD frames: the matrix-core cross-covariance panel (float frames, even atom count)
+    const bool rpanel = !panels && a.sup_pan && (a.n_atoms % 2) == 0;
+    const int rsteps = a.n_atoms / 2;
     float nmax = 0.0f;
     for (int m0 = mfirst; m0 < kend; m0 += 2 * GW) {
         const bool first = m0 == mfirst;
@@ -1038,6 +1041,7 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 const float f = (float)val[u];
                 n32[u] = fmaf(f, f, n32[u]);
                 if (panels && a.sup_pan) a.sup_pan[panel32_index(k, c, PD)] = f;
+                if (rpanel && c < a.d) a.sup_pan[rmsd_panel_index(k, c / 3, c % 3, rsteps)] = f;
                 if (panels && PD >= 16) {
                     uint16_t hi = 0, lo = 0;
                     if (realq[u] && c < a.d) bf16_split(f, hi, lo);

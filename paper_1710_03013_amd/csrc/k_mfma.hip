@@ -46,8 +46,8 @@ constexpr float kU32 = 5.9604645e-8f;     // unit roundoff of float
 constexpr float kUbf1 = 7.8277588e-3f;    // BF16:   u (2 + u) = 2^-7 (1 + 2^-9), u = 2^-8
 constexpr float kUbf3 = 4.6134e-5f;       // BF16x3: 3 u^2 (1 + 2^-7) = 3 * 2^-16 * (1 + 2^-7), rounded up
 
-// precision modes of the pass
-constexpr int kPmF32 = 0, kPmBf16 = 1, kPmBf16x3 = 3;
+// precision modes of the pass (kPmRmsd: RMSD frames, FP32 cross-covariance and FP64 eigenvalue)
+constexpr int kPmF32 = 0, kPmBf16 = 1, kPmBf16x3 = 3, kPmRmsd = 4;
 
 __device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float sn, float inv2s2) {
     if (type == KKM_KERNEL_LINEAR) return dot;
@@ -156,9 +156,92 @@ __device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok
     return qn;
 }
 
+// ----------------------------------------------------------------------------- RMSD frames
+// The superposition of two centred frames needs their 3x3 correlation R = sum_a x_a s_a^T: nine dot
+// products over the atoms, i.e. nine GEMM planes for a tile of query and support frames.  They run on
+// v_mfma_f32_32x32x2f32, two atoms per step (the A operand a support coordinate, the B operand a query
+// coordinate); per pair the squared RMSD then comes from the largest eigenvalue of the 4x4 key matrix
+// of R in FP64 (Newton's method, Jacobi for slow pairs), r^2 = max(0, (G_x + G_s - 2 lambda) / A).
+//
+// Error: the FP32 accumulation of the 2 A products of each entry gives |dR_pq| <= (A + 2) u32
+// sum_a |x_ap||s_aq| <= (A + 2) u32 sqrt(G_xp G_sq), so ||dR||_F <= (A + 2) u32 sqrt(G_x G_s); the key
+// matrix is linear in R with ||N(dR)||_F = 2 ||dR||_F, so (Weyl) |d lambda| <= 2 (A + 2) u32
+// sqrt(G_x G_s), and r^2 moves by at most 4 (A + 2) u32 sqrt(G_x G_s) / A, plus the FP64 solve (a few
+// 1e-16 of G_x + G_s) and the float rounding of r^2.  The frames themselves are the centred float rows
+// that the FP64 re-decision reads too.
+
+// Stage the group's 32 query frames in LDS in the B-operand layout: value (3 t + p) * 64 + lane is
+// coordinate p of atom 2 t + lane / 32 of query frame lane % 32 (zero past the last frame).  All
+// threads of the workgroup; the caller synchronises.
+__device__ __forceinline__ void stage_rmsd_queries(const DistArgs& a, int64_t grp, int nsteps, float* xs) {
+    const float* X = static_cast<const float*>(a.q.X);
+    const int total = nsteps * 192;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int l = e & 63, tp = e >> 6;
+        const int t = tp / 3, p = tp - 3 * t;
+        const int64_t qq = grp * 32 + (l & 31);
+        xs[e] = qq < a.q.n ? X[(a.q.base + qq * a.q.stride) * a.q.d + 3 * (2 * t + (l >> 5)) + p] : 0.0f;
+    }
+}
+
+// G_x of the lane's query frame in FP64 (both lane halves hold it) and whether its part is finite.
+__device__ __forceinline__ double rmsd_query_norm(const float* xs, int lane, int nsteps, bool& ok) {
+    double g = 0.0;
+    ok = true;
+    for (int e = lane; e < nsteps * 192; e += 64) {
+        const double v = xs[e];
+        ok = ok && isfinite(v);
+        g = fma(v, v, g);
+    }
+    return g + __shfl_xor(g, 32, 64);
+}
+
+// r2[i] = squared RMSD of the lane's 16 pairs: support rows tile * 32 + 8(i/4) + 4(l/32) + i%4 against
+// query frame l % 32 (staged in xs).
+__device__ __forceinline__ void rmsd_tile(const SupportView& sup, int64_t tile, int lane, int nsteps, const float* xs,
+                                          double Gq, int A, float* r2) {
+    floatx16 c[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c[k] = floatx16{};
+    const float* pb = sup.pan + tile * nsteps * 192 + lane;
+    const float* xb = xs + lane;
+    for (int t = 0; t < nsteps; ++t) {
+        const float s0 = pb[0], s1 = pb[64], s2 = pb[128];
+        const float x0 = xb[0], x1 = xb[64], x2 = xb[128];
+        pb += 192;
+        xb += 192;
+        c[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(s0, x0, c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1, x0, c[1], 0, 0, 0);
+        c[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(s2, x0, c[2], 0, 0, 0);
+        c[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(s0, x1, c[3], 0, 0, 0);
+        c[4] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1, x1, c[4], 0, 0, 0);
+        c[5] = __builtin_amdgcn_mfma_f32_32x32x2f32(s2, x1, c[5], 0, 0, 0);
+        c[6] = __builtin_amdgcn_mfma_f32_32x32x2f32(s0, x2, c[6], 0, 0, 0);
+        c[7] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1, x2, c[7], 0, 0, 0);
+        c[8] = __builtin_amdgcn_mfma_f32_32x32x2f32(s2, x2, c[8], 0, 0, 0);
+    }
+    const int h = lane >> 5;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t r = tile * 32 + 8 * (i / 4) + 4 * h + (i % 4);
+        const double Gs = sup.snorm64[r];
+        double R[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = (double)c[k][i];
+        // a frame collapsed onto its centroid has R = 0 and lambda = 0
+        r2[i] = (Gs > 0.0 && Gq > 0.0) ? (float)rmsd2_from_corr64(R, Gq, Gs, A) : (float)((Gq + Gs) / A);
+    }
+}
+
+// Bound on |r^2 computed - exact| for a query of norm Gq against supports of norm at most Gs (above).
+__device__ __forceinline__ float rmsd_r2_bound(float Gq, float Gs, int A) {
+    return (4.0f * (A + 2) * kU32 * sqrtf(Gq * Gs) * 1.0001f + (kU32 + 1e-13f) * (Gq + Gs)) / (float)A;
+}
+
 template <typename TI, int DP, int PM, int NW>
 __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
-    constexpr bool BF = PM != kPmF32;         // bfloat16 operands
+    constexpr bool RM = PM == kPmRmsd;        // RMSD frames
+    constexpr bool BF = PM == kPmBf16 || PM == kPmBf16x3;   // bfloat16 operands
     constexpr bool BF3 = PM == kPmBf16x3;     // with the remainder products
     constexpr int H = DP / 2;                      // dimensions per lane half
     constexpr int NH = NW / 4;                     // wavefronts per quarter of the support
@@ -169,6 +252,10 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     double* mself = reinterpret_cast<double*>(smem_raw + sizeof(float) * (size_t)NH * C * 32);   // [C]
     double* msegabs = mself + C;                                                             // [C]
     int32_t* off = reinterpret_cast<int32_t*>(msegabs + C);                                 // [C+1]
+    // RMSD: the group's query frames in the B-operand layout
+    const int nsteps = RM ? a.ks.n_atoms / 2 : 0;
+    float* xs = reinterpret_cast<float*>(smem_raw + ((sizeof(float) * (size_t)NH * C * 32 + sizeof(double) * 2 * C +
+                                                      sizeof(int32_t) * (C + 1) + 15) & ~size_t(15)));
     __shared__ float Ew[4][32];
     __shared__ float Eg[4][32];
     __shared__ double Bw1[4][32], Bw2[4][32];
@@ -197,12 +284,22 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     const int64_t q = grp * 32 + col;
     const bool active = q < a.q.n;
 
-    // the sample's half of the dimensions, its squared norm, and its bf16 split
+    // the sample's half of the dimensions, its squared norm, and its bf16 split (RMSD: the group's
+    // frames staged in LDS and G_x of the lane's frame)
     const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
     float xq[H];
     bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
     bool ok;
-    const float qn = load_query<TI, DP, PM>(xr, a.q.d, (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0, h, xq, bh, bl, ok);
+    double Gq = 0.0;
+    float qn;
+    if constexpr (RM) {
+        stage_rmsd_queries(a, grp, nsteps, xs);
+        __syncthreads();
+        Gq = rmsd_query_norm(xs, lane, nsteps, ok);
+        qn = (float)Gq;
+    } else {
+        qn = load_query<TI, DP, PM>(xr, a.q.d, (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0, h, xq, bh, bl, ok);
+    }
     if (active && !ok) atomicOr(a.nonfinite, 1);   // either half may hold the bad value
     const float kqq = type == KKM_KERNEL_LINEAR ? qn : 1.0f;
     const int quarter = wave & 3, half = wave >> 2;
@@ -225,7 +322,15 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
         // A fragment: support row r0 + col, the lane half's dimensions, read from the panel of the
         // tile (64 consecutive vectors per step group)
         const int64_t tile = r0 >> 5;
-        const floatx16 acc = mfma_tile<DP, PM>(a.sup, tile, lane, xq, bh, bl);
+        floatx16 acc;
+        if constexpr (RM) {
+            float r2[16];
+            rmsd_tile(a.sup, tile, lane, nsteps, xs, Gq, a.ks.n_atoms, r2);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[i] = r2[i];
+        } else {
+            acc = mfma_tile<DP, PM>(a.sup, tile, lane, xq, bh, bl);
+        }
         // segments meeting the tile (the first 64 of them): a prefix of the lanes, offsets ascend
         int sj = jc + lane;
         int o0 = sj < j1 ? off[sj] : end;
@@ -238,10 +343,17 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
             const int rb = r0 + 8 * b + 4 * h;
             const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
             const float4 cf4 = *reinterpret_cast<const float4*>(a.sup.coef32 + rb);
-            v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
-            v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
-            v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
-            v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
+            if constexpr (RM) {   // acc holds the squared RMSD
+                v[4 * b + 0] = cf4.x * exp_neg(acc[4 * b + 0] * inv2s2);
+                v[4 * b + 1] = cf4.y * exp_neg(acc[4 * b + 1] * inv2s2);
+                v[4 * b + 2] = cf4.z * exp_neg(acc[4 * b + 2] * inv2s2);
+                v[4 * b + 3] = cf4.w * exp_neg(acc[4 * b + 3] * inv2s2);
+            } else {
+                v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
+                v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
+                v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
+                v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
+            }
         }
         // (the register path is compiled for short rows only, where it costs no occupancy)
         if (DP <= 32 && nseg <= 2) {
@@ -323,7 +435,14 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
             D = (float)D64;
             const float len = (float)(hi - lo), segabs = (float)msegabs[jj];
             float ef;
-            if (type == KKM_KERNEL_LINEAR) {
+            if (RM) {
+                // relative error of K = exp(-r^2 / (2 sigma^2)): the r^2 bound times 1 / (2 sigma^2), the
+                // float rounding of the exponent's argument and a few ulps of the exponential
+                const float rho = rmsd_r2_bound(qn, snmax, a.ks.n_atoms) * inv2s2 +
+                                  (inv2s2 * (qn + snmax) / (float)a.ks.n_atoms + 4.0f) * kU32;
+                const float mass = a.sup.nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
+                ef = (rho + (len + 8.0f) * kU32) * mass;
+            } else if (type == KKM_KERNEL_LINEAR) {
                 ef = (dot_rel * kmax + (len + 2.0f) * kU32 * kmax) * segabs;
             } else {
                 // exp's relative error is rho (from the squared-distance error) plus a few ulps, so the
@@ -426,7 +545,8 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
 template <typename TI, int DP, int PM>
 __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
     constexpr int H = DP / 2;
-    constexpr bool BF = PM != kPmF32, BF3 = PM == kPmBf16x3;
+    constexpr bool RM = PM == kPmRmsd;
+    constexpr bool BF = PM == kPmBf16 || PM == kPmBf16x3, BF3 = PM == kPmBf16x3;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = lane >> 5, col = lane & 31;
     const int C = a.sup.C;
@@ -436,7 +556,13 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
     const float snmax = *a.sup.snorm_max;
     const float dot_rel = BF3 ? kUbf3 + (3.0f * DP + 2.0f) * kU32 : BF ? kUbf1 + (DP + 3.0f) * kU32 : (DP + 2.0f) * kU32;
     const bool vec_ok = (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0;
+    // RMSD: each wavefront stages its own 32 frames (one B-operand block per wavefront)
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nsteps = RM ? a.ks.n_atoms / 2 : 0;
+    float* xs = reinterpret_cast<float*>(smem_raw) + (size_t)wave * 192 * nsteps;
     const int64_t ngroups = (a.q.n + 31) / 32;
+    // (every wavefront of the workgroup runs the same number of group iterations: the RMSD staging
+    // is per wavefront, so no workgroup barrier is needed)
     for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp < ngroups; grp += (int64_t)gridDim.x * 4) {
         const int64_t q = grp * 32 + col;
         const bool active = q < a.q.n;
@@ -444,12 +570,36 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
         float xq[H];
         bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
         bool ok;
-        const float qn = load_query<TI, DP, PM>(xr, a.q.d, vec_ok, h, xq, bh, bl, ok);
+        float qn;
+        double Gq = 0.0;
+        if constexpr (RM) {
+            const float* X = static_cast<const float*>(a.q.X);
+            wave_sync_lds();   // the previous group's reads of xs are done
+            for (int e = lane; e < nsteps * 192; e += 64) {
+                const int l = e & 63, tp = e >> 6;
+                const int t = tp / 3, p = tp - 3 * t;
+                const int64_t qq = grp * 32 + (l & 31);
+                xs[e] = qq < a.q.n ? X[(a.q.base + qq * a.q.stride) * a.q.d + 3 * (2 * t + (l >> 5)) + p] : 0.0f;
+            }
+            wave_sync_lds();
+            Gq = rmsd_query_norm(xs, lane, nsteps, ok);
+            qn = (float)Gq;
+        } else {
+            qn = load_query<TI, DP, PM>(xr, a.q.d, vec_ok, h, xq, bh, bl, ok);
+        }
         if (active && !ok) atomicOr(a.nonfinite, 1);
         float e1 = __builtin_huge_valf(), e2 = __builtin_huge_valf();
         int j1 = C;
         for (int t = 0; t < ntiles; ++t) {
-            const floatx16 acc = mfma_tile<DP, PM>(a.sup, t, lane, xq, bh, bl);
+            floatx16 acc;
+            if constexpr (RM) {
+                float r2[16];
+                rmsd_tile(a.sup, t, lane, nsteps, xs, Gq, a.ks.n_atoms, r2);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[i] = r2[i];
+            } else {
+                acc = mfma_tile<DP, PM>(a.sup, t, lane, xq, bh, bl);
+            }
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int rb = 32 * t + 8 * b + 4 * h;
@@ -458,7 +608,9 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const int j = rb + c;
-                    const float e = j < C ? fmaf(-2.0f, acc[4 * b + c], sn[c]) : __builtin_huge_valf();
+                    // RBF / linear: e = ||m||^2 - 2 x.m; RMSD: e = r^2 (d = 2 - 2 exp(-r^2 / (2 sigma^2)))
+                    const float ev = RM ? acc[4 * b + c] : fmaf(-2.0f, acc[4 * b + c], sn[c]);
+                    const float e = j < C ? ev : __builtin_huge_valf();
                     if (e < e1) {
                         e2 = e1;
                         e1 = e;
@@ -484,10 +636,17 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
         if (h == 0 && active) {
             const int bj = j1 < C ? j1 : 0;
             const float kmax = sqrtf(qn * snmax) * 1.0001f;
-            const float Ee = 2.0f * dot_rel * kmax + 3.0f * kU32 * (snmax + 2.0f * kmax);
+            const float Ee = RM ? rmsd_r2_bound(qn, snmax, a.ks.n_atoms) + kU32 * (qn + snmax) / (float)a.ks.n_atoms
+                                : 2.0f * dot_rel * kmax + 3.0f * kU32 * (snmax + 2.0f * kmax);
             const double g1 = a.sup.self[bj];
             double D1, D2, kqq;
-            if (lin) {
+            if (RM) {
+                kqq = 1.0;
+                const float K1 = exp_neg(fmaxf(e1, 0.0f) * c2);
+                const float K2 = e2 < __builtin_huge_valf() ? exp_neg(fmaxf(e2, 0.0f) * c2) : 0.0f;
+                D1 = kqq + g1 - 2.0 * (double)K1;
+                D2 = e2 < __builtin_huge_valf() ? 2.0 - 2.0 * (double)K2 : kInf;
+            } else if (lin) {
                 kqq = qn;
                 D1 = (double)qn + (double)e1 + (g1 - (double)a.sup.snorm32[bj]);
                 D2 = (double)qn + (double)e2;
@@ -510,6 +669,7 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
                 const float qlo = qn * (1.0f - (DP + 2.0f) * kU32);
                 float ub;
                 if (lin) ub = (ge + 2.0f * Ee) / fmaxf(qlo, 1e-30f);
+                else if (RM) ub = 2.0f * exp_neg(fmaxf(e1 - Ee, 0.0f) * c2) * (ge + 2.0f * Ee) * c2;
                 else ub = 2.0f * exp_neg(fmaxf(qlo + e1 - Ee, 0.0f) * c2) * (ge + 2.0f * Ee) * c2;
                 need = !(ub < (float)kTieMargin);
             }
@@ -518,8 +678,9 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
     }
 }
 
-size_t mfma_lds_dynamic(size_t C, int nw) {
-    return sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
+size_t mfma_lds_dynamic(size_t C, int nw, int rmsd_steps = 0) {
+    const size_t base = sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
+    return rmsd_steps ? ((base + 15) & ~size_t(15)) + sizeof(float) * 192 * (size_t)rmsd_steps : base;
 }
 size_t mfma_lds_static(int nw) {
     return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 + 64;
@@ -527,13 +688,14 @@ size_t mfma_lds_static(int nw) {
 
 template <typename TI, int PM, int NW>
 kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsigned blocks) {
-    const size_t lds = mfma_lds_dynamic((size_t)a.sup.C, NW);
+    const size_t lds = mfma_lds_dynamic((size_t)a.sup.C, NW, PM == kPmRmsd ? a.ks.n_atoms / 2 : 0);
     auto go = [&](auto fn) -> kkm_status {
         KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
         hipLaunchKernelGGL(fn, dim3(blocks), dim3(NW * 64), lds, s, a);
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     };
+    if constexpr (PM == kPmRmsd) return go(mfma_dist_kernel<TI, 16, PM, NW>);
     switch (a.sup.dpad) {
         case 4: if constexpr (PM == kPmF32) return go(mfma_dist_kernel<TI, 4, PM, NW>); break;
         case 8: if constexpr (PM == kPmF32) return go(mfma_dist_kernel<TI, 8, PM, NW>); break;
@@ -549,7 +711,8 @@ kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsi
 template <typename TI, int PM>
 kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     const size_t C = (size_t)a.sup.C;
-    if (mfma_lds_dynamic(C, 4) + mfma_lds_static(4) > dev.max_lds_per_block)
+    const int rs = PM == kPmRmsd ? a.ks.n_atoms / 2 : 0;
+    if (mfma_lds_dynamic(C, 4, rs) + mfma_lds_static(4) > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
     // 32 samples per group; a bounded grid of workgroups, each looping over groups
     const int64_t groups = (a.q.n + 31) / 32;
@@ -557,7 +720,7 @@ kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
     // (few groups: the pass is bound by each wavefront's chain of tiles), where their LDS fits;
     // otherwise four, which duplicate less per-group work.
     const bool eight = groups < 2 * (int64_t)dev.num_cus &&
-                       mfma_lds_dynamic(C, 8) + mfma_lds_static(8) <= dev.max_lds_per_block;
+                       mfma_lds_dynamic(C, 8, rs) + mfma_lds_static(8) <= dev.max_lds_per_block;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
     if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
     const kkm_status st = eight ? launch_mfma_nw<TI, PM, 8>(a, s, groups, blocks)
@@ -569,12 +732,17 @@ kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
 
 }  // namespace
 
-bool mfma_dist_applies(const DistArgs& a) {
+bool mfma_disabled() {
     static const bool off = [] {
         const char* e = std::getenv("KKM_DIST_VALU");
         return e && e[0] == '1';
     }();
-    if (off || a.ks.type == KKM_KERNEL_RMSD || a.precision == KKM_PREC_FP64 || a.dtype != KKM_F32) return false;
+    return off;
+}
+
+bool mfma_dist_applies(const DistArgs& a) {
+    if (mfma_disabled() || a.precision == KKM_PREC_FP64 || a.dtype != KKM_F32) return false;
+    if (a.ks.type == KKM_KERNEL_RMSD) return rmsd_mfma_ok(a.ks.n_atoms, a.dtype) && a.sup.pan != nullptr;
     if (a.precision == KKM_PREC_BF16X3) return a.sup.hi && a.sup.lo && a.sup.dpad >= 16;
     if (a.precision == KKM_PREC_BF16) return a.sup.hi && a.sup.dpad >= 16;
     return a.sup.pan != nullptr;
@@ -584,11 +752,14 @@ template <int PM>
 kkm_status launch_assign1(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     const int64_t groups = (a.q.n + 31) / 32;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 16 * (int64_t)dev.num_cus));
+    const size_t lds = PM == kPmRmsd ? sizeof(float) * 4 * 192 * (size_t)(a.ks.n_atoms / 2) : 0;
     auto go = [&](auto fn) -> kkm_status {
-        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, a);
+        KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     };
+    if constexpr (PM == kPmRmsd) return go(mfma_assign1_kernel<float, 16, PM>);
     switch (a.sup.dpad) {
         case 4: if constexpr (PM == kPmF32) return go(mfma_assign1_kernel<float, 4, PM>); break;
         case 8: if constexpr (PM == kPmF32) return go(mfma_assign1_kernel<float, 8, PM>); break;
@@ -603,6 +774,10 @@ kkm_status launch_assign1(const DistArgs& a, const DeviceInfo& dev, hipStream_t 
 
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     if (a.q.n <= 0) return KKM_OK;
+    if (a.ks.type == KKM_KERNEL_RMSD) {
+        if (a.sup.medoid_form && !a.Dt && !a.colmin && !a.Erow) return launch_assign1<kPmRmsd>(a, dev, s);
+        return launch_mfma_t<float, kPmRmsd>(a, dev, s);
+    }
     if (a.sup.medoid_form && !a.Dt && !a.colmin && !a.Erow) {
         if (a.precision == KKM_PREC_BF16X3) return launch_assign1<kPmBf16x3>(a, dev, s);
         if (a.precision == KKM_PREC_BF16) return launch_assign1<kPmBf16>(a, dev, s);

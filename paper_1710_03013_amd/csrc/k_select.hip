@@ -757,6 +757,8 @@ __global__ __launch_bounds__(1024) void model_from_medoids_kernel(kkm_model m, c
                 n64 = fma((double)v[u], (double)v[u], n64);
                 n32 = fmaf((float)v[u], (float)v[u], n32);
                 if (panels && m.pan) m.pan[panel32_index(j, c, m.dpad)] = c < m.d ? (float)v[u] : 0.0f;
+                if (!panels && m.pan && m.kernel.n_atoms % 2 == 0 && c < m.d)
+                    m.pan[rmsd_panel_index(j, c / 3, c % 3, m.kernel.n_atoms / 2)] = (float)v[u];
                 if (panels && m.dpad >= 16) {
                     uint16_t hi = 0, lo = 0;
                     if (c < m.d) bf16_split((float)v[u], hi, lo);
@@ -807,6 +809,8 @@ __global__ __launch_bounds__(1024) void model_norms_kernel(kkm_model m) {
         m.coef32[l] = (float)m.coef64[l];
         if (m.pan && m.kernel.type != KKM_KERNEL_RMSD)
             for (int c = 0; c < m.dpad; ++c) m.pan[panel32_index(l, c, m.dpad)] = c < m.d ? (float)S[l * m.dpad + c] : 0.0f;
+        if (m.pan && m.kernel.type == KKM_KERNEL_RMSD && m.kernel.n_atoms % 2 == 0)
+            for (int c = 0; c < m.d; ++c) m.pan[rmsd_panel_index(l, c / 3, c % 3, m.kernel.n_atoms / 2)] = (float)S[l * m.dpad + c];
         if (m.dpad >= 16 && m.kernel.type != KKM_KERNEL_RMSD)
             for (int c = 0; c < m.dpad; ++c) {
                 uint16_t hi = 0, lo = 0;

@@ -70,6 +70,19 @@ __host__ __device__ inline int64_t panel16_index(int64_t r, int c, int DP) {
     return (((r >> 5) * (H / 8) + (s >> 3)) * 64 + h * 32 + (int)(r & 31)) * 8 + (s & 7);
 }
 
+// Panel layout of RMSD support frames for the matrix-core cross-covariance: per 32-row tile, for
+// every pair of atoms t = a / 2 and coordinate q, the 64 values one MFMA operand needs, lane
+// 32 (a % 2) + row % 32 holding coordinate q of atom a of that row.  A tile holds 32 * 3 * A values
+// (A even), the same count as 32 rows of the frames themselves.
+__host__ __device__ inline int64_t rmsd_panel_index(int64_t r, int atom, int q, int nsteps) {
+    return (((r >> 5) * nsteps + (atom >> 1)) * 3 + q) * 64 + (atom & 1) * 32 + (int)(r & 31);
+}
+// RMSD frames take the matrix-core path for float frames with an even atom count up to this many.
+constexpr int kRmsdMfmaMaxAtoms = 64;   // (the assign kernel stages 4 x 96 A floats of LDS)
+inline bool rmsd_mfma_ok(int n_atoms, int dtype) {
+    return dtype == KKM_F32 && n_atoms >= 2 && n_atoms % 2 == 0 && n_atoms <= kRmsdMfmaMaxAtoms;
+}
+
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Bump allocator over the caller's workspace (or a size probe when base == nullptr).
@@ -132,6 +145,10 @@ struct kkm_model {
 };
 
 namespace kkm {
+
+// Carve the device arrays of model m (its kernel, d, dpad, bpad, C, cap and dtype set) from c: the
+// layout of kkm_model_create's one allocation, also used for models that live in a workspace.
+void model_layout(kkm_model* m, Carver& c);
 
 // ----------------------------------------------------------------------------- device helpers
 template <typename T>
@@ -258,7 +275,7 @@ __device__ __forceinline__ void horn_key(const T R[9], T N[4][4]) {
 // "Matrix Computations", Sec. 8.5): each rotation zeroes one off-diagonal pair; sweeps repeat until
 // the off-diagonal mass is negligible against the diagonal.  Backward stable, so the eigenvalue is
 // accurate to a few units of roundoff of ||N|| whatever the multiplicity.  N is overwritten.
-__device__ inline double sym4_max_eig_jacobi(double N[4][4]) {
+static __device__ __attribute__((noinline)) double sym4_max_eig_jacobi(double N[4][4]) {
     for (int sweep = 0; sweep < 16; ++sweep) {
         double off = 0.0, diag = 0.0;
         for (int i = 0; i < 4; ++i) {

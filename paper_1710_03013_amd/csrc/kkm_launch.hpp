@@ -125,6 +125,10 @@ struct DistArgs {
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
 // Matrix-core distance pass (k_mfma.hip): linear / RBF, float samples, FP32, BF16 or BF16x3.
 bool mfma_dist_applies(const DistArgs& a);
+// KKM_DIST_VALU=1 in the environment: every distance pass on the VALU kernels.
+bool mfma_disabled();
+// True when the RMSD distance pass of float frames with n_atoms atoms runs on the matrix cores.
+inline bool rmsd_on_mfma(int n_atoms, int dtype) { return !mfma_disabled() && rmsd_mfma_ok(n_atoms, dtype); }
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
 // True when launch_dist evaluates (and stores Dt) in FP64 for these arguments.
 bool dist_is_fp64(const DistArgs& a);

@@ -176,6 +176,7 @@ class Server:
         self.running: List[tuple] = []      # (kind, handle, [requests], mem, slot)
         self.in_use = 0
         self.peak_in_use = 0
+        self.budget_waits = 0               # admission passes in which the budget held a request back
         self._slot = 0
         self.launches = 0
 
@@ -254,6 +255,7 @@ class Server:
                     head.finished = self.clock()
                     continue
                 if self.in_use + mem > self.budget:
+                    self.budget_waits += 1
                     blocked.add("fit")
                     continue
                 del self.queue[i]
@@ -289,6 +291,7 @@ class Server:
                         rows += r.n
                         mem = m2
                 if self.in_use + mem > self.budget:
+                    self.budget_waits += 1
                     blocked.add("assign")
                     continue
                 ids = {id(r) for r in group}

@@ -78,8 +78,12 @@ def test_fit_flags():
     keep = []
     p = kk._params(20, 10, 0.1, 20, "stride", "kmeans++", "fp32", 1, None, None, None, None, keep, True)
     assert p.flags == kk.KKM_FIT_COOPERATIVE
-    p.flags = 2
+    p.flags = 4
     assert kk.lib().kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, kk.ct.byref(k), kk.ct.byref(p)) == 0
+    # the global-cost trace adds a medoid model and an assign pass over the N rows
+    p.flags = kk.KKM_FIT_GLOBAL_COST
+    traced = kk.lib().kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, kk.ct.byref(k), kk.ct.byref(p))
+    assert traced > plain + 100_000 * (4 + 8 + 4)
 
 
 def test_workspace_estimate_grows_with_problem_size():

@@ -171,7 +171,7 @@ def _fit_both(kk, X, kern, C, B, s, T, init, seed, prec, sampling="stride", dtyp
     model, labels, info = kk.kkm_fit(Xd, kern.kind, sigma=kern.sigma, n_atoms=kern.n_atoms, C=C, B=B, s=s,
                                      max_iter=T, sampling=sampling, init=init, precision=prec, seed=seed,
                                      landmarks=L, kmpp_uniforms=u, init_labels=lab0, init_medoids=med0,
-                                     cost_trace=True)
+                                     cost_trace=True, global_cost=kw.get("global_cost", False))
     torch.cuda.synchronize()
     _say(f"  device fit done ({info['updates_per_batch'].tolist()} updates); oracle fit")
     ref = okkm.fit(X, C, kern, B, T, L, sampling=sampling, init=init, kmpp_uniforms=u, init_labels=lab0,
@@ -624,3 +624,61 @@ def test_full_size_md_prefix():
     assert max(ref.updates) >= 3, ref.updates
     _check_fit(kk, model, labels, info, ref, kern, Xp, cfg["T"], expect="trajectory")
     _sampled_assign_parity(kk, model, kern, Xp, 2000, 81, "fp32", COST_TOL["fp32"])
+
+
+def test_rmsd_assign_near_ties_on_the_matrix_cores():
+    """RMSD frames on the matrix-core path with two medoids that nearly superpose (a rotated copy
+    moved by 0.01 A per coordinate): for frames near them the two squared RMSDs differ by less than
+    the FP32 cross-covariance bound, so those rows are decided again in FP64; labels must follow the
+    oracle wherever its margin exceeds 1e-6, in FP32 and in the cost."""
+    kk = _kk()
+    _say("rmsd near ties (matrix cores)")
+    A, sigma = 50, 1.5
+    X, _ = ki.datasets.md_frames(4000, A=A, n_templates=4, seed=52)
+    rng = np.random.default_rng(53)
+    F0 = X[0].reshape(A, 3).astype(np.float64)
+    F1 = F0 @ ki.datasets.random_rotations(rng, 1)[0].T + rng.normal(scale=0.01, size=F0.shape)
+    M = np.concatenate([X[:1], F1.reshape(1, -1).astype(np.float32), X[1:9]])
+    kern = Kernel("rmsd", sigma, A)
+    m = kk.kkm_model_create("rmsd", d=3 * A, C=10, dtype="f32", sigma=sigma, n_atoms=A)
+    kk.kkm_model_load(m, M, np.arange(11), np.ones(10))
+    Y = np.ascontiguousarray(X[10:])
+    model = okkm.SparseModel(M.astype(np.float64), np.arange(11), np.ones(10))
+    rl, rg, _ = okkm.assign(kern, Y, model)
+    near = (rl == 0) | (rl == 1)
+    assert near.sum() > 100
+    Yd = torch.from_numpy(Y).cuda()
+    want = okkm.cost(kern, Y, model)
+    # float frames are centred by the device into float (one rounding per coordinate, |dx| <= 2^-24 |x|),
+    # which moves each squared RMSD by at most 6 2^-24 (G_x + G_m) / A and so each row's distance
+    # 2 - 2K by at most 2 K c 6 2^-24 (G_x + G_m) / A (c = 1 / (2 sigma^2)); the FP64 form is exact for
+    # the centred float frames, so its cost bar adds this to the 1e-9 of FP64 arithmetic
+    G = lambda Z: np.sum((Z.reshape(len(Z), A, 3) - Z.reshape(len(Z), A, 3).mean(1, keepdims=True)) ** 2, axis=(1, 2))
+    Gy, Gm = G(Y.astype(np.float64)), G(M.astype(np.float64))
+    _, _, dist = okkm.assign(kern, Y, model)
+    K = 1.0 - dist[np.arange(len(Y)), rl] / 2.0
+    centring = float(np.sum(2.0 * K / (2 * sigma * sigma) * 6 * 2.0 ** -24 * (Gy + Gm[rl]) / A))
+    for prec in ("fp32", "fp64"):
+        lab = kk.kkm_assign(m, Yd, precision=prec).cpu().numpy()
+        _labels_match(lab, rl, rg, f"rmsd near ties {prec}")
+        cost = kk.kkm_cost(m, Yd, precision=prec)
+        assert abs(cost - want) <= COST_TOL[prec] * abs(want) + centring, (prec, cost, want, centring)
+        _say(f"  {prec}: cost error {abs(cost - want):.3g} (centring bound {centring:.3g})")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x3"])
+def test_fit_global_cost_trace(prec):
+    """Global cost Omega(W) after every batch (Sec. 4.1, Fig. 4): the device's value of each batch
+    against the oracle's Eq. 1 over all N samples with the global medoids of that moment."""
+    kk = _kk()
+    _say(f"global cost trace {prec}")
+    X, _ = ki.datasets.gaussian_mixture(20_000, 16, 20, seed=1001, sigma=1.0)
+    kern = Kernel("rbf", 4.0)
+    T = 20
+    model, labels, info, ref = _fit_both(kk, X, kern, 20, 10, 0.1, T, "kmeans++", 2001, prec, global_cost=True)
+    _check_fit(kk, model, labels, info, ref, kern, X, T)
+    want = okkm.global_costs(kern, X, ref)
+    np.testing.assert_allclose(info["global_cost"], want, rtol=COST_TOL[prec])
+    # the cost after the last batch is the final model's cost
+    assert abs(info["global_cost"][-1] - kk.kkm_cost(model, torch.from_numpy(X).cuda(), precision=prec)) <= \
+        COST_TOL[prec] * want[-1]

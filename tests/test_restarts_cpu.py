@@ -1,44 +1,45 @@
-"""Selection rule of the best-of-restarts helper with the library calls replaced by host stand-ins
-(no GPU): seeds seed .. seed + R - 1 in order, the lowest cost kept, the lowest seed on equal
-costs, and the arguments the helper sets itself rejected."""
+"""The restarts entry point without a GPU: its workspace holds one fit (plus its medoid model and
+labels) per restart and one assign pass, it refuses draws that each restart must make itself, and the
+Python face refuses them before calling the library."""
+import numpy as np
 import pytest
 
+import paper_1710_03013_amd as kk
 import paper_1710_03013_amd.restarts as rs
 
 
-def _fake(monkeypatch, costs):
-    calls = []
-
-    def fake_fit(X, seed=0, stream=None, **kw):
-        calls.append(seed)
-        return ("model", seed), ("labels", seed), {"seed": seed}
-
-    def fake_cost(model, X, precision="fp64", stream=None):
-        return costs[model[1]]
-
-    monkeypatch.setattr(rs, "kkm_fit", fake_fit)
-    monkeypatch.setattr(rs, "kkm_cost", fake_cost)
-    return calls
+def _args(**kw):
+    a = dict(C=20, B=10, s=0.1, max_iter=20, sampling="stride", init="kmeans++", precision="fp32", seed=7,
+             landmarks=None, kmpp_uniforms=None, init_labels=None, init_medoids=None)
+    a.update(kw)
+    return a
 
 
-def test_lowest_cost_wins(monkeypatch):
-    calls = _fake(monkeypatch, {10: 5.0, 11: 3.0, 12: 4.0, 13: 3.5})
-    model, labels, info = rs.fit_best_of(None, restarts=4, seed=10)
-    assert calls == [10, 11, 12, 13]
-    assert model == ("model", 11) and labels == ("labels", 11) and info["restart"] == 1
-    assert info["restart_costs"] == [5.0, 3.0, 4.0, 3.5]
+def _ws(R, **kw):
+    k = kk._kernel("rbf", 4.0)
+    keep = []
+    p = kk._params(**_args(**kw), keep=keep)
+    return int(kk.lib().kkm_fit_restarts_workspace_bytes(100_000, 16, kk.KKM_F32, kk.ct.byref(k), kk.ct.byref(p), R))
 
 
-def test_equal_costs_keep_the_lowest_seed(monkeypatch):
-    _fake(monkeypatch, {0: 2.0, 1: 1.0, 2: 1.0})
-    _, _, info = rs.fit_best_of(None, restarts=3, seed=0)
-    assert info["restart"] == 1
+def test_workspace_grows_by_one_fit_per_restart():
+    one = kk.kkm_fit_workspace_bytes(100_000, 16, kk.KKM_F32, kk._kernel("rbf", 4.0), **_args())
+    w1, w2, w5 = _ws(1), _ws(2), _ws(5)
+    assert w1 > one
+    per = w2 - w1
+    assert per >= one + 4 * 100_000          # a fit, its medoid model and its labels
+    assert w5 == w1 + 4 * per
 
 
-def test_arguments_the_helper_sets_are_rejected(monkeypatch):
-    _fake(monkeypatch, {0: 1.0})
-    for k in ("landmarks", "kmpp_uniforms", "init_labels"):
+def test_restart_draws_are_refused():
+    assert _ws(3, landmarks=[np.arange(1000)] * 10) == 0
+    assert _ws(3, kmpp_uniforms=np.full(20, 0.5)) == 0
+    assert _ws(0) == 0 and _ws(2000) == 0
+
+
+def test_python_face_refuses_draws():
+    for key in ("landmarks", "kmpp_uniforms", "init_labels"):
         with pytest.raises(ValueError):
-            rs.fit_best_of(None, restarts=1, **{k: 1})
+            rs.fit_best_of(None, restarts=2, **{key: np.zeros(3)})
     with pytest.raises(ValueError):
         rs.fit_best_of(None, restarts=0)
