@@ -254,6 +254,17 @@ kkm_status kkm_assign(const kkm_model* model, const void* X, int64_t n, int32_t 
                       void* workspace, size_t workspace_bytes, void* stream,
                       int32_t* labels_out, float* gap_out);
 
+/* kkm_assign without a workspace, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same labels and margins as
+ * kkm_assign, with the scratch taken from a fixed 48 MiB device array that the library holds on every
+ * GPU it runs on until the process ends.  Allocates nothing.  Rows of n * (4 bytes + for RMSD one
+ * centred frame) plus fixed parts must fit that array (about 3 million rows of d = 64, 80 000 frames of
+ * 50 atoms): a larger n returns KKM_ERR_UNSUPPORTED and enqueues nothing.  All calls on one GPU share
+ * its array: calls that overlap on that GPU (other streams or host threads) race and must be
+ * serialised by the caller.  Enqueued on stream; returns without waiting. */
+kkm_status kkm_assign_noalloc(const kkm_model* model, const void* X, int64_t n, int32_t dtype, int32_t precision,
+                              void* stream, int32_t* labels_out, float* gap_out);
+
 /* *cost_out (host) = sum_i min_j ||phi(x_i) - w_j||^2  (Eq. 1 with Eq. 2 labels), summed in FP64 in a
  * fixed order (the same bits on every run).  Uses the workspace of kkm_assign.  Synchronous. */
 kkm_status kkm_cost(const kkm_model* model, const void* X, int64_t n, int32_t dtype, int32_t precision,

@@ -22,7 +22,7 @@ __all__ = [
     "KKM_INIT_KMEANSPP", "KKM_INIT_RANDOM_LABELS", "KKM_INIT_MEDOIDS", "KkmError", "Model", "lib",
     "kkm_model_create", "kkm_model_load", "kkm_model_export", "kkm_model_shape", "kkm_fit",
     "kkm_fit_workspace_bytes", "kkm_fit_min_batches", "kkm_fit_restarts", "kkm_assign", "kkm_assign_workspace_bytes", "kkm_cost",
-    "kkm_kernel_block", "kkm_kernel_block_workspace_bytes",
+    "kkm_kernel_block", "kkm_kernel_block_workspace_bytes", "kkm_assign_noalloc",
     "kkm_landmark_count", "kkm_draw_landmarks", "kkm_draw_kmpp_uniforms", "kkm_draw_init_labels",
     "kkm_version", "EXPORTED_SYMBOLS", "release_models",
 ]
@@ -103,6 +103,8 @@ _SIGS = {
                               ct.c_size_t, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "kkm_cost": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_void_p,
                             ct.c_size_t, ct.c_void_p, ct.POINTER(ct.c_double)]),
+    "kkm_assign_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_void_p,
+                                      ct.c_void_p, ct.c_void_p]),
     "kkm_kernel_block_workspace_bytes": (ct.c_size_t, [ct.POINTER(_Kernel), ct.c_int64, ct.c_int64, ct.c_int64,
                                                        ct.c_int32]),
     "kkm_kernel_block": (ct.c_int, [ct.POINTER(_Kernel), ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64,
@@ -488,6 +490,21 @@ def kkm_assign(model: Model, X, precision="fp32", want_gap=False, workspace=None
                                 ct.c_void_p(labels.data_ptr()),
                                 ct.c_void_p(gap.data_ptr()) if gap is not None else None))
     return (labels, gap) if want_gap else labels
+
+
+def kkm_assign_noalloc(model: Model, X, labels, gap=None, precision="fp32", stream=None):
+    """kkm_assign into caller-given outputs (int32 labels, optional float32 gaps) with the library's fixed
+    scratch: the call allocates nothing (X must already be contiguous).  Calls overlapping on one GPU
+    race on that scratch."""
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous (the call allocates nothing, not even a contiguous copy)")
+    pr = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    with _OnStream(stream) as os_:
+        os_.use(X, labels, gap)
+        _check(lib().kkm_assign_noalloc(model.ptr, ct.c_void_p(X.data_ptr()), X.shape[0], _dtype_code(X), pr,
+                                        ct.c_void_p(_stream_ptr(os_.s)), ct.c_void_p(labels.data_ptr()),
+                                        ct.c_void_p(gap.data_ptr()) if gap is not None else None))
+    return labels
 
 
 def kkm_cost(model: Model, X, precision="fp32", workspace=None, stream=None) -> float:

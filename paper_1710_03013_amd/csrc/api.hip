@@ -109,6 +109,31 @@ struct PhaseTimer {
     }
 };
 
+// ----------------------------------------------------------------------------- fixed scratch
+// Scratch of kkm_assign_noalloc: a file-scope device array, one copy per GPU the library runs on,
+// held until the process ends.  Host code never uses the array's name as an address (on the host it
+// is only a stand-in for the symbol): the device address of each GPU's copy is looked up once with
+// hipGetSymbolAddress while that GPU is current, and that pointer is what kernels and copies get.
+constexpr size_t kNoAllocScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+kkm_status noalloc_scratch(int device, void** out) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        int cur = -1;
+        KKM_HIP(hipGetDevice(&cur));
+        if (cur != device) return fail(KKM_ERR_INVALID_ARG, "the model lives on another device than the current one");
+        void* p = nullptr;
+        KKM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        it = addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return KKM_OK;
+}
+
 // ----------------------------------------------------------------------------- fit plan
 struct FitPlan {
     int64_t N = 0, d = 0;
@@ -1114,6 +1139,25 @@ kkm_status kkm_assign(const kkm_model* m, const void* X, int64_t n, int32_t dtyp
     AssignWs w;
     return assign_common(m, X, n, dtype, precision, ws, ws_bytes, static_cast<hipStream_t>(stream), labels_out, gap_out,
                          false, w);
+}
+
+kkm_status kkm_assign_noalloc(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision,
+                              void* stream, int32_t* labels_out, float* gap_out) {
+    if (!labels_out && n > 0) return fail(KKM_ERR_INVALID_ARG, "labels_out is NULL");
+    KKM_TRY(assign_validate(m, X, n, dtype, precision));
+    AssignWs w{};
+    Carver probe(nullptr);
+    const size_t need = carve_assign(probe, m, n, w);
+    if (need > kNoAllocScratchBytes)
+        return fail(KKM_ERR_UNSUPPORTED, "kkm_assign_noalloc: " + std::to_string(n) + " rows of this model need " +
+                                             std::to_string(need) + " bytes of scratch, more than its fixed " +
+                                             std::to_string(kNoAllocScratchBytes) +
+                                             "; split the rows or call kkm_assign with a workspace");
+    void* base = nullptr;
+    KKM_TRY(noalloc_scratch(m->device, &base));
+    Carver c(base);
+    carve_assign(c, m, n, w);
+    return assign_launch(m, X, n, dtype, precision, static_cast<hipStream_t>(stream), labels_out, gap_out, false, w);
 }
 
 kkm_status kkm_cost(const kkm_model* m, const void* X, int64_t n, int32_t dtype, int32_t precision, void* ws,
