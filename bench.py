@@ -335,9 +335,7 @@ def sweep_bench(args) -> int:
                          "cost": kk.kkm_cost(model, Xd), "landmarks_per_batch": kk.kkm_landmark_count(N // B, sv),
                          "workspace_bytes": need})
             log(f"[sweep] B={B} s={sv}: {rows[-1]['seconds'] * 1e3:.2f} ms, accuracy {rows[-1]['accuracy']:.4f}")
-    mem = kk.kkm_fit_workspace_bytes(N, d, kk.KKM_F32, kspec, C=cfg["C"], B=4, s=1.0, max_iter=cfg["T"],
-                                     sampling="stride", init="kmeans++", precision="fp32", seed=2001, landmarks=None,
-                                     kmpp_uniforms=None, init_labels=None, init_medoids=None)
+    mem = int(args.sweep_memory_gb * 1e9)
     ch = tuning.choose_batches_and_fraction(Xd, args.sweep_time_budget, mem, kernel="rbf", sigma=cfg["sigma"],
                                             C=cfg["C"], max_iter=cfg["T"], seed=2001)
     # the check of Sec. 4.2 on one mini-batch: the chosen s against s = 1 on the first batch of the chosen B
@@ -380,12 +378,12 @@ def main() -> int:
     ap.add_argument("--sweep-b", default="2,4,8,16")
     ap.add_argument("--sweep-s", default="0.025,0.05,0.1,0.2,0.4,0.7,1.0")
     ap.add_argument("--sweep-time-budget", type=float, default=0.004, help="seconds, for the (B, s) procedure")
+    ap.add_argument("--sweep-memory-gb", type=float, default=0.5, help="workspace budget of the (B, s) procedure")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="arrival window per load")
     ap.add_argument("--serving-budget-gb", type=float, default=200.0, help="HBM admission budget")
     ap.add_argument("--serving-small-budget-gb", type=float, default=None,
                     help="budget of the extra 80%% load run that makes admission wait "
                          "(default: 1.1x that run's largest request)")
-    ap.add_argument("--no-serving", action="store_true", help="leave the serving section out of the step bench")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -554,7 +552,9 @@ def step_bench(args) -> int:
         dist_flops = float(np.mean([batch_n[i] * ells[i] for i in range(B)])) * dist_flops_per_eval(cfg["kernel"], d)
         peak = {"fp64": PEAK_FP64_VECTOR, "fp32": PEAK_FP32_VECTOR, "bf16x3": PEAK_BF16_MATRIX,
                 "bf16": PEAK_BF16_MATRIX}[prim]
-        mfma = cfg["kernel"] != "rmsd" and prim != "fp64"
+        # RMSD frames of an even atom count up to 64 in float run on the matrix cores as well
+        mfma = prim != "fp64" and (cfg["kernel"] != "rmsd" or
+                                   (cfg["n_atoms"] % 2 == 0 and cfg["n_atoms"] <= 64 and Xd.dtype == torch.float32))
         dist_name = "mfma_dist_kernel" if mfma else "dist_kernel"
         assign_name = "mfma_assign1_kernel" if mfma else "dist_kernel"
         cands = {
@@ -607,15 +607,6 @@ def step_bench(args) -> int:
         "roofline": roofline,
         "rooflines": rooflines,
     }
-    if not args.no_serving and args.workload == "mixture64":
-        log("[bench] serving at 25/50/80% of saturation")
-        smodels, sdata = serving_models("fp32")
-        out["serving"] = dict(serving_at_load(smodels, sdata, "fp32", min(args.serving_seconds, 2.0),
-                                              args.serving_budget_gb * 1e9,
-                                              None if args.serving_small_budget_gb is None
-                                              else args.serving_small_budget_gb * 1e9),
-                              workload=SERVING_DESC, precision="fp32")
-        del smodels, sdata
     if not args.no_cpu_baseline:
         nb = CPU_BASELINE_BATCHES.get(args.workload, 1)
         log(f"[bench] timing the FP64 oracle on the host ({nb} batches + an assign pass)")

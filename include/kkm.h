@@ -257,9 +257,10 @@ kkm_status kkm_assign(const kkm_model* model, const void* X, int64_t n, int32_t 
 /* kkm_assign without a workspace, for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same labels and margins as
  * kkm_assign, with the scratch taken from a fixed 48 MiB device array that the library holds on every
- * GPU it runs on until the process ends.  Allocates nothing.  Rows of n * (4 bytes + for RMSD one
- * centred frame) plus fixed parts must fit that array (about 3 million rows of d = 64, 80 000 frames of
- * 50 atoms): a larger n returns KKM_ERR_UNSUPPORTED and enqueues nothing.  All calls on one GPU share
+ * GPU it runs on until the process ends.  Allocates nothing.  Rows of n * (16 bytes + for RMSD one
+ * centred frame and its squared RMSDs to the support) plus fixed parts must fit that array (about
+ * 3 million rows of d = 64, 55 000 frames of 50 atoms against 50 medoids): a larger n returns
+ * KKM_ERR_UNSUPPORTED and enqueues nothing.  All calls on one GPU share
  * its array: calls that overlap on that GPU (other streams or host threads) race and must be
  * serialised by the caller.  Enqueued on stream; returns without waiting. */
 kkm_status kkm_assign_noalloc(const kkm_model* model, const void* X, int64_t n, int32_t dtype, int32_t precision,

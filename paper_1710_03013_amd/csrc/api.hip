@@ -157,6 +157,9 @@ struct FitPlan {
 // ----------------------------------------------------------------------------- assign workspace
 struct AssignWs {
     void* Qc;
+    float* r2buf;          // RMSD pair pass (matrix cores): squared RMSDs of a chunk of frames
+    double* r2gq;
+    int64_t rmsd_chunk;
     int32_t* refine_list;
     int32_t* refine_count;
     int32_t* nonfinite;
@@ -168,6 +171,9 @@ struct AssignWs {
 
 struct FitWs {
     void* Xc;
+    float* r2buf;          // RMSD pair pass (matrix cores) of the batch pass
+    double* r2gq;
+    int64_t rmsd_chunk;
     int32_t* lm;
     int32_t* lab_init;
     double* uniforms;
@@ -239,6 +245,14 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     const size_t es = P.dtype == KKM_F64 ? 8 : 4;
     const int C = P.C;
     w.Xc = P.kernel.type == KKM_KERNEL_RMSD ? c.take<char>((size_t)P.N * P.d * es) : nullptr;
+    w.r2buf = nullptr;
+    w.r2gq = nullptr;
+    w.rmsd_chunk = 0;
+    if (P.kernel.type == KKM_KERNEL_RMSD && !P.tile_f64) {
+        w.rmsd_chunk = rmsd_chunk_groups(P.nmax, P.ellmax, kRmsdFitChunkBytes);
+        w.r2buf = c.take<float>((size_t)w.rmsd_chunk * std::max<int64_t>(1, (P.ellmax + 31) / 32) * 1024);
+        w.r2gq = c.take<double>((size_t)w.rmsd_chunk * 32);
+    }
     w.lm = c.take<int32_t>(std::max<int64_t>(1, P.ell_total));
     w.lab_init = c.take<int32_t>(P.ellmax);
     w.uniforms = c.take<double>(C);
@@ -478,6 +492,14 @@ size_t carve_assign(Carver& c, const kkm_model* m, int64_t n, AssignWs& w) {
     const size_t es = m->dtype == KKM_F64 ? 8 : 4;
     const int64_t nn = std::max<int64_t>(1, n);
     w.Qc = m->kernel.type == KKM_KERNEL_RMSD ? c.take<char>((size_t)nn * m->d * es) : nullptr;
+    w.r2buf = nullptr;
+    w.r2gq = nullptr;
+    w.rmsd_chunk = 0;
+    if (m->kernel.type == KKM_KERNEL_RMSD && rmsd_on_mfma(m->kernel.n_atoms, m->dtype)) {
+        w.rmsd_chunk = rmsd_chunk_groups(nn, m->used, kRmsdAssignChunkBytes);
+        w.r2buf = c.take<float>((size_t)w.rmsd_chunk * std::max<int64_t>(1, (m->used + 31) / 32) * 1024);
+        w.r2gq = c.take<double>((size_t)w.rmsd_chunk * 32);
+    }
     w.refine_list = c.take<int32_t>(nn);
     w.refine_count = c.take<int32_t>(2);
     w.nonfinite = w.refine_count + 1;
@@ -551,6 +573,9 @@ kkm_status assign_launch(const kkm_model* m, const void* X, int64_t n, int32_t d
     da.refine_count = w.refine_count;
     da.nonfinite = w.nonfinite;
     da.n_support = m->used;
+    da.r2buf = w.r2buf;
+    da.r2gq = w.r2gq;
+    da.rmsd_chunk = w.rmsd_chunk;
     if (da.sup.C * 64 * (dist_is_fp64(da) ? 8u : 4u) > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
     KKM_TRY(launch_dist(da, dev, s));
@@ -733,6 +758,9 @@ kkm_status fit_enqueue(const FitPlan& P, FitWs& w, const void* X, hipStream_t s,
         da.colpart = w.colpart;
         da.colpart_cap = dist_block_cap(P.nmax);
         da.n_support = ell;
+        da.r2buf = w.r2buf;
+        da.r2gq = w.r2gq;
+        da.rmsd_chunk = w.rmsd_chunk;
         int64_t dist_blocks = 0;
         da.colpart_blocks = &dist_blocks;
         KKM_TRY(tm.begin(kPhDist));

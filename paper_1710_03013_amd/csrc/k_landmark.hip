@@ -1113,10 +1113,16 @@ LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C) {
     }();
     const int gmax = std::max(1, std::min(dev.num_cus, ell));
     const int G0 = std::max(1, std::min((ell + 3) / 4, std::min(cap, gmax)));
-    if (k_lds_allowed)
+    auto widen = [&](bool k_in_lds) {
         for (int G = G0; G <= gmax; G = G < gmax ? std::min(gmax, G + std::max(1, G / 8)) : gmax + 1)
-            if (landmark_lds_bytes_host(ell, C, G, true) <= dev.max_lds_per_block) return LandmarkShape{G, 1};
-    return LandmarkShape{G0, 0};
+            if (landmark_lds_bytes_host(ell, C, G, k_in_lds) <= dev.max_lds_per_block) return G;
+        return 0;
+    };
+    if (k_lds_allowed)
+        if (const int G = widen(true)) return LandmarkShape{G, 1};
+    // K_LL rows from HBM: the per-row parts of the LDS still shrink with a wider grid
+    const int G = widen(false);
+    return LandmarkShape{G ? G : G0, 0};
 }
 
 static kkm_status check_landmark_args(const LandmarkArgs& args, const DeviceInfo& dev, size_t* lds_out) {

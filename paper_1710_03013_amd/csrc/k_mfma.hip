@@ -159,83 +159,150 @@ __device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok
 // ----------------------------------------------------------------------------- RMSD frames
 // The superposition of two centred frames needs their 3x3 correlation R = sum_a x_a s_a^T: nine dot
 // products over the atoms, i.e. nine GEMM planes for a tile of query and support frames.  They run on
-// v_mfma_f32_32x32x2f32, two atoms per step (the A operand a support coordinate, the B operand a query
-// coordinate); per pair the squared RMSD then comes from the largest eigenvalue of the 4x4 key matrix
-// of R in FP64 (Newton's method, Jacobi for slow pairs), r^2 = max(0, (G_x + G_s - 2 lambda) / A).
+// v_mfma_f32_16x16x4f32, four atoms per step (the A operand a support coordinate, the B operand a
+// query coordinate); per pair the squared RMSD then comes from the largest eigenvalue of the 4x4 key
+// matrix of R in FP64 (Laguerre's method, Jacobi rotations where it does not settle), r^2 =
+// max(0, (G_x + G_s - 2 lambda) / A).
 //
-// Error: the FP32 accumulation of the 2 A products of each entry gives |dR_pq| <= (A + 2) u32
-// sum_a |x_ap||s_aq| <= (A + 2) u32 sqrt(G_xp G_sq), so ||dR||_F <= (A + 2) u32 sqrt(G_x G_s); the key
-// matrix is linear in R with ||N(dR)||_F = 2 ||dR||_F, so (Weyl) |d lambda| <= 2 (A + 2) u32
-// sqrt(G_x G_s), and r^2 moves by at most 4 (A + 2) u32 sqrt(G_x G_s) / A, plus the FP64 solve (a few
-// 1e-16 of G_x + G_s) and the float rounding of r^2.  The frames themselves are the centred float rows
-// that the FP64 re-decision reads too.
-
-// Stage the group's 32 query frames in LDS in the B-operand layout: value (3 t + p) * 64 + lane is
-// coordinate p of atom 2 t + lane / 32 of query frame lane % 32 (zero past the last frame).  All
-// threads of the workgroup; the caller synchronises.
-__device__ __forceinline__ void stage_rmsd_queries(const DistArgs& a, int64_t grp, int nsteps, float* xs) {
-    const float* X = static_cast<const float*>(a.q.X);
-    const int total = nsteps * 192;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int l = e & 63, tp = e >> 6;
-        const int t = tp / 3, p = tp - 3 * t;
-        const int64_t qq = grp * 32 + (l & 31);
-        xs[e] = qq < a.q.n ? X[(a.q.base + qq * a.q.stride) * a.q.d + 3 * (2 * t + (l >> 5)) + p] : 0.0f;
-    }
-}
-
-// G_x of the lane's query frame in FP64 (both lane halves hold it) and whether its part is finite.
-__device__ __forceinline__ double rmsd_query_norm(const float* xs, int lane, int nsteps, bool& ok) {
-    double g = 0.0;
-    ok = true;
-    for (int e = lane; e < nsteps * 192; e += 64) {
-        const double v = xs[e];
-        ok = ok && isfinite(v);
-        g = fma(v, v, g);
-    }
-    return g + __shfl_xor(g, 32, 64);
-}
-
-// r2[i] = squared RMSD of the lane's 16 pairs: support rows tile * 32 + 8(i/4) + 4(l/32) + i%4 against
-// query frame l % 32 (staged in xs).
-__device__ __forceinline__ void rmsd_tile(const SupportView& sup, int64_t tile, int lane, int nsteps, const float* xs,
-                                          double Gq, int A, float* r2) {
-    floatx16 c[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) c[k] = floatx16{};
-    const float* pb = sup.pan + tile * nsteps * 192 + lane;
-    const float* xb = xs + lane;
-    for (int t = 0; t < nsteps; ++t) {
-        const float s0 = pb[0], s1 = pb[64], s2 = pb[128];
-        const float x0 = xb[0], x1 = xb[64], x2 = xb[128];
-        pb += 192;
-        xb += 192;
-        c[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(s0, x0, c[0], 0, 0, 0);
-        c[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1, x0, c[1], 0, 0, 0);
-        c[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(s2, x0, c[2], 0, 0, 0);
-        c[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(s0, x1, c[3], 0, 0, 0);
-        c[4] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1, x1, c[4], 0, 0, 0);
-        c[5] = __builtin_amdgcn_mfma_f32_32x32x2f32(s2, x1, c[5], 0, 0, 0);
-        c[6] = __builtin_amdgcn_mfma_f32_32x32x2f32(s0, x2, c[6], 0, 0, 0);
-        c[7] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1, x2, c[7], 0, 0, 0);
-        c[8] = __builtin_amdgcn_mfma_f32_32x32x2f32(s2, x2, c[8], 0, 0, 0);
-    }
-    const int h = lane >> 5;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int64_t r = tile * 32 + 8 * (i / 4) + 4 * h + (i % 4);
-        const double Gs = sup.snorm64[r];
-        double R[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) R[k] = (double)c[k][i];
-        // a frame collapsed onto its centroid has R = 0 and lambda = 0
-        r2[i] = (Gs > 0.0 && Gq > 0.0) ? (float)rmsd2_from_corr64(R, Gq, Gs, A) : (float)((Gq + Gs) / A);
-    }
-}
+// Error: the FP32 accumulation of the A products of each entry (in any order) gives |dR_pq| <=
+// (A + 2) u32 sum_a |x_ap||s_aq| <= (A + 2) u32 sqrt(G_xp G_sq), so ||dR||_F <= (A + 2) u32
+// sqrt(G_x G_s); the key matrix is linear in R with ||N(dR)||_F = 2 ||dR||_F, so (Weyl) |d lambda| <=
+// 2 (A + 2) u32 sqrt(G_x G_s), and r^2 moves by at most 4 (A + 2) u32 sqrt(G_x G_s) / A, plus the FP64
+// solve (accepted within kPairSolveTol (G_x + G_s) / A) and the float rounding of r^2.  The frames
+// themselves are the centred float rows that the FP64 re-decision reads too.
+constexpr double kPairSolveTol = 1e-10;
 
 // Bound on |r^2 computed - exact| for a query of norm Gq against supports of norm at most Gs (above).
 __device__ __forceinline__ float rmsd_r2_bound(float Gq, float Gs, int A) {
-    return (4.0f * (A + 2) * kU32 * sqrtf(Gq * Gs) * 1.0001f + (kU32 + 1e-13f) * (Gq + Gs)) / (float)A;
+    return (4.0f * (A + 2) * kU32 * sqrtf(Gq * Gs) * 1.0001f + (kU32 + (float)kPairSolveTol) * (Gq + Gs)) / (float)A;
+}
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// The pair pass: every squared RMSD of a chunk of query groups against the whole support, at full
+// occupancy (its registers hold four pairs per lane), written in the lane layout of a 32 x 32
+// accumulator tile so that the distance passes read it back lane for lane:
+//   r2[((g - g0) * ntiles + t) * 1024 + i * 64 + l]  is the pair (support row 32 t + 8(i/4) + 4(l/32)
+//   + i%4, query 32 g + l%32),
+// and gq[(g - g0) * 32 + c] holds G of query 32 g + c in FP64 (0 past the last row).  Workgroup
+// (g - g0, y) stages the 32 frames of group g in LDS and takes support tiles y T .. y T + T - 1 (T =
+// tiles_per_block, so the staging serves T tiles); on each its wavefront w takes the 16 x 16 block of
+// support half w/2 and query half w%2, nine accumulators of four values each.
+struct RmsdPairsArgs {
+    BatchView q;           // centred float frames
+    const float* pan;      // support panel (rmsd_panel_index)
+    const double* snorm64; // G of each support row
+    int32_t A;
+    int64_t g0;
+    int32_t ntiles;
+    int32_t tiles_per_block;
+    float* r2;
+    double* gq;
+    int32_t* nonfinite;
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void rmsd_pairs_kernel(RmsdPairsArgs p) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int A = p.A, nst = (A + 3) / 4, nsteps2 = A / 2;
+    // value ((t * 3 + c) * 2 + qh) * 64 + l: coordinate c of atom 4t + l/16 of query 16 qh + l%16
+    float* xs = reinterpret_cast<float*>(smem_raw);
+    __shared__ double gpart[4][64];
+    __shared__ double gqs[32];
+    const int64_t g = p.g0 + blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float* X = static_cast<const float*>(p.q.X);
+    int bad = 0;
+    {   // wavefront w fills the rows w, w + 4, ... of 64 values (row (t * 3 + c) * 2 + qh): its query half
+        // qh = w % 2 is fixed, so each lane reads one frame, query 16 qh + l%16, throughout
+        const int64_t qq = g * 32 + 16 * (wave & 1) + (lane & 15);
+        const bool qok = qq < p.q.n;
+        const float* row = X + (p.q.base + (qok ? qq : 0) * p.q.stride) * p.q.d;
+        const int a4 = lane >> 4;
+        int t = 0, c = wave >> 1;   // t * 3 + c advances by 2 per row taken
+        for (int r = wave; r < nst * 6; r += 4) {
+            const int atom = 4 * t + a4;
+            float v = 0.0f;
+            if (qok && atom < A) {
+                v = row[3 * atom + c];
+                bad |= !isfinite(v);
+            }
+            xs[r * 64 + lane] = v;
+            c += 2;
+            if (c >= 3) {
+                c -= 3;
+                ++t;
+            }
+        }
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0 && blockIdx.y == 0) atomicOr(p.nonfinite, 1);
+    {   // G of each query in FP64: the wavefronts split the steps, lane l takes query l%32 and
+        // (lane half) atoms 4t + {0,1} or {2,3}
+        const int qc = lane & 31, hf = lane >> 5, nw = blockDim.x >> 6;
+        double gs = 0.0;
+        for (int t = wave; t < nst; t += nw)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const double v = xs[((t * 3 + c) * 2 + (qc >> 4)) * 64 + (2 * hf + k) * 16 + (qc & 15)];
+                    gs = fma(v, v, gs);
+                }
+        gpart[wave][lane] = gs;
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            double G = 0.0;
+            for (int w = 0; w < nw; ++w) G += gpart[w][threadIdx.x] + gpart[w][threadIdx.x + 32];
+            gqs[threadIdx.x] = G;
+            if (blockIdx.y == 0) p.gq[blockIdx.x * 32 + threadIdx.x] = G;
+        }
+        __syncthreads();
+    }
+    const int sh = wave >> 1, qh = wave & 1;
+    const int la = lane >> 4, lr = lane & 15;
+    const double Gq = gqs[16 * qh + lr];
+    const int tile0 = blockIdx.y * p.tiles_per_block;
+    const int tile_end = min(p.ntiles, tile0 + p.tiles_per_block);
+    for (int tile = tile0; tile < tile_end; ++tile) {
+    floatx4 c[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c[k] = floatx4{};
+    // the lane's panel values of atom 4t + la (support row 32 tile + 16 sh + lr): consecutive steps
+    // lie 384 floats apart
+    const float* sb = p.pan + rmsd_panel_index((int64_t)tile * 32 + 16 * sh + lr, la, 0, nsteps2);
+    for (int t = 0; t < nst; ++t, sb += 384) {
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        if (4 * t + la < A) {   // (atoms past A, in the last step when A % 4 == 2: zero)
+            s0 = sb[0];
+            s1 = sb[64];
+            s2 = sb[128];
+        }
+        const float* xb = xs + (6 * t + qh) * 64 + lane;
+        const float x0 = xb[0], x1 = xb[128], x2 = xb[256];
+        c[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(s0, x0, c[0], 0, 0, 0);
+        c[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1, x0, c[1], 0, 0, 0);
+        c[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(s2, x0, c[2], 0, 0, 0);
+        c[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(s0, x1, c[3], 0, 0, 0);
+        c[4] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1, x1, c[4], 0, 0, 0);
+        c[5] = __builtin_amdgcn_mfma_f32_16x16x4f32(s2, x1, c[5], 0, 0, 0);
+        c[6] = __builtin_amdgcn_mfma_f32_16x16x4f32(s0, x2, c[6], 0, 0, 0);
+        c[7] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1, x2, c[7], 0, 0, 0);
+        c[8] = __builtin_amdgcn_mfma_f32_16x16x4f32(s2, x2, c[8], 0, 0, 0);
+    }
+    // lane l holds rows 4(l/16) + v of the block, column l%16
+    float* out = p.r2 + ((int64_t)blockIdx.x * p.ntiles + tile) * 1024 + 16 * qh + lr;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int rho = 16 * sh + 4 * la + v;   // support row within the tile
+        const double Gs = p.snorm64[(int64_t)tile * 32 + rho];
+        double R[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = (double)c[k][v];
+        // a frame collapsed onto its centroid has R = 0 and lambda = 0
+        const double r2 =
+            (Gs > 0.0 && Gq > 0.0) ? rmsd2_from_corr64(R, Gq, Gs, A, kPairSolveTol) : (Gq + Gs) / A;
+        out[(4 * (rho >> 3) + (rho & 3)) * 64 + ((rho >> 2) & 1) * 32] = (float)r2;
+    }
+    }   // tiles
 }
 
 template <typename TI, int DP, int PM, int NW>
@@ -252,10 +319,6 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     double* mself = reinterpret_cast<double*>(smem_raw + sizeof(float) * (size_t)NH * C * 32);   // [C]
     double* msegabs = mself + C;                                                             // [C]
     int32_t* off = reinterpret_cast<int32_t*>(msegabs + C);                                 // [C+1]
-    // RMSD: the group's query frames in the B-operand layout
-    const int nsteps = RM ? a.ks.n_atoms / 2 : 0;
-    float* xs = reinterpret_cast<float*>(smem_raw + ((sizeof(float) * (size_t)NH * C * 32 + sizeof(double) * 2 * C +
-                                                      sizeof(int32_t) * (C + 1) + 15) & ~size_t(15)));
     __shared__ float Ew[4][32];
     __shared__ float Eg[4][32];
     __shared__ double Bw1[4][32], Bw2[4][32];
@@ -278,25 +341,24 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     const float snmax = *a.sup.snorm_max;
     __syncthreads();
 
-    // groups of 32 samples, grid-stride
-    const int64_t ngroups = (a.q.n + 31) / 32;
-    for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    // groups of 32 samples, grid-stride (RMSD: the groups of the pair pass's chunk)
+    const int64_t g_begin = RM ? a.grp0 : 0;
+    const int64_t g_end = RM ? a.grp0 + a.grp_n : (a.q.n + 31) / 32;
+    const int64_t r2_tiles = (a.n_support + 31) / 32;
+    for (int64_t grp = g_begin + blockIdx.x; grp < g_end; grp += gridDim.x) {
     const int64_t q = grp * 32 + col;
     const bool active = q < a.q.n;
 
-    // the sample's half of the dimensions, its squared norm, and its bf16 split (RMSD: the group's
-    // frames staged in LDS and G_x of the lane's frame)
+    // the sample's half of the dimensions, its squared norm, and its bf16 split (RMSD: G_x of the
+    // lane's frame, left by the pair pass, which also flagged non-finite frames)
     const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
     float xq[H];
     bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
     bool ok;
-    double Gq = 0.0;
     float qn;
     if constexpr (RM) {
-        stage_rmsd_queries(a, grp, nsteps, xs);
-        __syncthreads();
-        Gq = rmsd_query_norm(xs, lane, nsteps, ok);
-        qn = (float)Gq;
+        qn = (float)a.r2gq[(grp - g_begin) * 32 + col];
+        ok = true;
     } else {
         qn = load_query<TI, DP, PM>(xr, a.q.d, (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0, h, xq, bh, bl, ok);
     }
@@ -323,11 +385,10 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
         // tile (64 consecutive vectors per step group)
         const int64_t tile = r0 >> 5;
         floatx16 acc;
-        if constexpr (RM) {
-            float r2[16];
-            rmsd_tile(a.sup, tile, lane, nsteps, xs, Gq, a.ks.n_atoms, r2);
+        if constexpr (RM) {   // the squared RMSDs of the tile, from the pair pass
+            const float* rb = a.r2buf + ((grp - g_begin) * r2_tiles + tile) * 1024 + lane;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc[i] = r2[i];
+            for (int i = 0; i < 16; ++i) acc[i] = rb[64 * i];
         } else {
             acc = mfma_tile<DP, PM>(a.sup, tile, lane, xq, bh, bl);
         }
@@ -556,14 +617,10 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
     const float snmax = *a.sup.snorm_max;
     const float dot_rel = BF3 ? kUbf3 + (3.0f * DP + 2.0f) * kU32 : BF ? kUbf1 + (DP + 3.0f) * kU32 : (DP + 2.0f) * kU32;
     const bool vec_ok = (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0;
-    // RMSD: each wavefront stages its own 32 frames (one B-operand block per wavefront)
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nsteps = RM ? a.ks.n_atoms / 2 : 0;
-    float* xs = reinterpret_cast<float*>(smem_raw) + (size_t)wave * 192 * nsteps;
-    const int64_t ngroups = (a.q.n + 31) / 32;
-    // (every wavefront of the workgroup runs the same number of group iterations: the RMSD staging
-    // is per wavefront, so no workgroup barrier is needed)
-    for (int64_t grp = (int64_t)blockIdx.x * 4 + wave; grp < ngroups; grp += (int64_t)gridDim.x * 4) {
+    // (RMSD: the groups of the pair pass's chunk, whose squared RMSDs it reads)
+    const int64_t g_begin = RM ? a.grp0 : 0;
+    const int64_t g_end = RM ? a.grp0 + a.grp_n : (a.q.n + 31) / 32;
+    for (int64_t grp = g_begin + (int64_t)blockIdx.x * 4 + wave; grp < g_end; grp += (int64_t)gridDim.x * 4) {
         const int64_t q = grp * 32 + col;
         const bool active = q < a.q.n;
         const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
@@ -571,19 +628,9 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
         bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
         bool ok;
         float qn;
-        double Gq = 0.0;
-        if constexpr (RM) {
-            const float* X = static_cast<const float*>(a.q.X);
-            wave_sync_lds();   // the previous group's reads of xs are done
-            for (int e = lane; e < nsteps * 192; e += 64) {
-                const int l = e & 63, tp = e >> 6;
-                const int t = tp / 3, p = tp - 3 * t;
-                const int64_t qq = grp * 32 + (l & 31);
-                xs[e] = qq < a.q.n ? X[(a.q.base + qq * a.q.stride) * a.q.d + 3 * (2 * t + (l >> 5)) + p] : 0.0f;
-            }
-            wave_sync_lds();
-            Gq = rmsd_query_norm(xs, lane, nsteps, ok);
-            qn = (float)Gq;
+        if constexpr (RM) {   // (G of the frame from the pair pass, which flagged non-finite frames)
+            qn = (float)a.r2gq[(grp - g_begin) * 32 + col];
+            ok = true;
         } else {
             qn = load_query<TI, DP, PM>(xr, a.q.d, vec_ok, h, xq, bh, bl, ok);
         }
@@ -593,10 +640,9 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
         for (int t = 0; t < ntiles; ++t) {
             floatx16 acc;
             if constexpr (RM) {
-                float r2[16];
-                rmsd_tile(a.sup, t, lane, nsteps, xs, Gq, a.ks.n_atoms, r2);
+                const float* rb = a.r2buf + ((grp - g_begin) * ((a.n_support + 31) / 32) + t) * 1024 + lane;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) acc[i] = r2[i];
+                for (int i = 0; i < 16; ++i) acc[i] = rb[64 * i];
             } else {
                 acc = mfma_tile<DP, PM>(a.sup, t, lane, xq, bh, bl);
             }
@@ -678,9 +724,8 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
     }
 }
 
-size_t mfma_lds_dynamic(size_t C, int nw, int rmsd_steps = 0) {
-    const size_t base = sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
-    return rmsd_steps ? ((base + 15) & ~size_t(15)) + sizeof(float) * 192 * (size_t)rmsd_steps : base;
+size_t mfma_lds_dynamic(size_t C, int nw) {
+    return sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
 }
 size_t mfma_lds_static(int nw) {
     return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 + 64;
@@ -688,14 +733,16 @@ size_t mfma_lds_static(int nw) {
 
 template <typename TI, int PM, int NW>
 kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsigned blocks) {
-    const size_t lds = mfma_lds_dynamic((size_t)a.sup.C, NW, PM == kPmRmsd ? a.ks.n_atoms / 2 : 0);
+    const size_t lds = mfma_lds_dynamic((size_t)a.sup.C, NW);
     auto go = [&](auto fn) -> kkm_status {
         KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
         hipLaunchKernelGGL(fn, dim3(blocks), dim3(NW * 64), lds, s, a);
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     };
-    if constexpr (PM == kPmRmsd) return go(mfma_dist_kernel<TI, 16, PM, NW>);
+    if constexpr (PM == kPmRmsd) {
+        return go(mfma_dist_kernel<TI, 16, PM, NW>);
+    } else {
     switch (a.sup.dpad) {
         case 4: if constexpr (PM == kPmF32) return go(mfma_dist_kernel<TI, 4, PM, NW>); break;
         case 8: if constexpr (PM == kPmF32) return go(mfma_dist_kernel<TI, 8, PM, NW>); break;
@@ -706,21 +753,71 @@ kkm_status launch_mfma_nw(const DistArgs& a, hipStream_t s, int64_t groups, unsi
         default: break;
     }
     return fail(KKM_ERR_UNSUPPORTED, "matrix-core distance pass: unsupported padded dimension");
+    }
+}
+
+// The RMSD pair pass over query groups [g0, g0 + ng) (chunk buffers of a).
+kkm_status launch_rmsd_pairs(const DistArgs& a, int64_t g0, int64_t ng, hipStream_t s) {
+    RmsdPairsArgs p{};
+    p.q = a.q;
+    p.pan = a.sup.pan;
+    p.snorm64 = a.sup.snorm64;
+    p.A = a.ks.n_atoms;
+    p.g0 = g0;
+    p.ntiles = (int32_t)std::max<int64_t>(1, (a.n_support + 31) / 32);
+    // tiles per workgroup: the staging of a group's frames is shared by several tiles while the grid
+    // still holds about 2048 workgroups
+    p.tiles_per_block = (int32_t)std::max<int64_t>(1, std::min<int64_t>(p.ntiles, ng * p.ntiles / 2048));
+    p.r2 = a.r2buf;
+    p.gq = a.r2gq;
+    p.nonfinite = a.nonfinite;
+    const dim3 grid((unsigned)ng, (unsigned)((p.ntiles + p.tiles_per_block - 1) / p.tiles_per_block));
+    const size_t lds = sizeof(float) * 384 * (size_t)((p.A + 3) / 4);
+    KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(rmsd_pairs_kernel), lds));
+    hipLaunchKernelGGL(rmsd_pairs_kernel, grid, dim3(256), lds, s, p);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+// Every chunk of query groups: the pair pass, then the reduction f(a, g0, ng).
+template <typename F>
+kkm_status rmsd_chunks(const DistArgs& a, hipStream_t s, F&& f) {
+    if (!a.r2buf || !a.r2gq || a.rmsd_chunk < 1 || !a.sup.pan)
+        return fail(KKM_ERR_INTERNAL, "RMSD pair pass without its buffers");
+    const int64_t groups = (a.q.n + 31) / 32;
+    for (int64_t g0 = 0; g0 < groups; g0 += a.rmsd_chunk) {
+        const int64_t ng = std::min<int64_t>(a.rmsd_chunk, groups - g0);
+        KKM_TRY(launch_rmsd_pairs(a, g0, ng, s));
+        DistArgs b = a;
+        b.grp0 = g0;
+        b.grp_n = ng;
+        KKM_TRY(f(b, ng));
+    }
+    return KKM_OK;
 }
 
 template <typename TI, int PM>
 kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     const size_t C = (size_t)a.sup.C;
-    const int rs = PM == kPmRmsd ? a.ks.n_atoms / 2 : 0;
-    if (mfma_lds_dynamic(C, 4, rs) + mfma_lds_static(4) > dev.max_lds_per_block)
+    if (mfma_lds_dynamic(C, 4) + mfma_lds_static(4) > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
     // 32 samples per group; a bounded grid of workgroups, each looping over groups
     const int64_t groups = (a.q.n + 31) / 32;
+    if constexpr (PM == kPmRmsd) {
+        // the tiles are read back from the pair pass: four wavefronts per workgroup, a grid per chunk
+        if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
+        KKM_TRY(rmsd_chunks(a, s, [&](const DistArgs& b, int64_t ng) {
+            const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ng, 8 * (int64_t)dev.num_cus));
+            return launch_mfma_nw<TI, PM, 4>(b, s, ng, blocks);
+        }));
+        if (a.colmin && a.colpart_blocks) *a.colpart_blocks = groups;
+        return KKM_OK;
+    }
     // Eight wavefronts per workgroup when four would leave the SIMDs under two wavefronts each
     // (few groups: the pass is bound by each wavefront's chain of tiles), where their LDS fits;
     // otherwise four, which duplicate less per-group work.
     const bool eight = groups < 2 * (int64_t)dev.num_cus &&
-                       mfma_lds_dynamic(C, 8, rs) + mfma_lds_static(8) <= dev.max_lds_per_block;
+                       mfma_lds_dynamic(C, 8) + mfma_lds_static(8) <= dev.max_lds_per_block;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
     if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
     const kkm_status st = eight ? launch_mfma_nw<TI, PM, 8>(a, s, groups, blocks)
@@ -751,15 +848,22 @@ bool mfma_dist_applies(const DistArgs& a) {
 template <int PM>
 kkm_status launch_assign1(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     const int64_t groups = (a.q.n + 31) / 32;
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((groups + 3) / 4, 16 * (int64_t)dev.num_cus));
-    const size_t lds = PM == kPmRmsd ? sizeof(float) * 4 * 192 * (size_t)(a.ks.n_atoms / 2) : 0;
+    auto blocks_for = [&](int64_t g) {
+        return (unsigned)std::max<int64_t>(1, std::min<int64_t>((g + 3) / 4, 16 * (int64_t)dev.num_cus));
+    };
+    if constexpr (PM == kPmRmsd) {
+        return rmsd_chunks(a, s, [&](const DistArgs& b, int64_t ng) -> kkm_status {
+            hipLaunchKernelGGL((mfma_assign1_kernel<float, 16, PM>), dim3(blocks_for(ng)), dim3(256), 0, s, b);
+            KKM_HIP(hipGetLastError());
+            return KKM_OK;
+        });
+    } else {
+    const unsigned blocks = blocks_for(groups);
     auto go = [&](auto fn) -> kkm_status {
-        KKM_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(fn), lds));
-        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(fn, dim3(blocks), dim3(256), 0, s, a);
         KKM_HIP(hipGetLastError());
         return KKM_OK;
     };
-    if constexpr (PM == kPmRmsd) return go(mfma_assign1_kernel<float, 16, PM>);
     switch (a.sup.dpad) {
         case 4: if constexpr (PM == kPmF32) return go(mfma_assign1_kernel<float, 4, PM>); break;
         case 8: if constexpr (PM == kPmF32) return go(mfma_assign1_kernel<float, 8, PM>); break;
@@ -770,6 +874,7 @@ kkm_status launch_assign1(const DistArgs& a, const DeviceInfo& dev, hipStream_t 
         default: break;
     }
     return fail(KKM_ERR_UNSUPPORTED, "matrix-core assign: unsupported padded dimension");
+    }
 }
 
 kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {

@@ -78,7 +78,7 @@ __host__ __device__ inline int64_t rmsd_panel_index(int64_t r, int atom, int q, 
     return (((r >> 5) * nsteps + (atom >> 1)) * 3 + q) * 64 + (atom & 1) * 32 + (int)(r & 31);
 }
 // RMSD frames take the matrix-core path for float frames with an even atom count up to this many.
-constexpr int kRmsdMfmaMaxAtoms = 64;   // (the assign kernel stages 4 x 96 A floats of LDS)
+constexpr int kRmsdMfmaMaxAtoms = 64;   // (the pair pass stages 384 A bytes of LDS per workgroup)
 inline bool rmsd_mfma_ok(int n_atoms, int dtype) {
     return dtype == KKM_F32 && n_atoms >= 2 && n_atoms % 2 == 0 && n_atoms <= kRmsdMfmaMaxAtoms;
 }
@@ -275,7 +275,7 @@ __device__ __forceinline__ void horn_key(const T R[9], T N[4][4]) {
 // "Matrix Computations", Sec. 8.5): each rotation zeroes one off-diagonal pair; sweeps repeat until
 // the off-diagonal mass is negligible against the diagonal.  Backward stable, so the eigenvalue is
 // accurate to a few units of roundoff of ||N|| whatever the multiplicity.  N is overwritten.
-static __device__ __attribute__((noinline)) double sym4_max_eig_jacobi(double N[4][4]) {
+__device__ __forceinline__ double sym4_max_eig_jacobi(double (&N)[4][4]) {
     for (int sweep = 0; sweep < 16; ++sweep) {
         double off = 0.0, diag = 0.0;
         for (int i = 0; i < 4; ++i) {
@@ -307,52 +307,137 @@ static __device__ __attribute__((noinline)) double sym4_max_eig_jacobi(double N[
     return fmax(fmax(N[0][0], N[1][1]), fmax(N[2][2], N[3][3]));
 }
 
-// Iterations after which Newton's method counts as slow: from the upper bound a simple largest root
-// is reached in about ten; more means a (near) multiple root, where the iteration converges only
-// linearly and the polynomial's rounding limits the root to about the square root of the unit
-// roundoff.  Such pairs are solved again by Jacobi rotations of the key matrix.
-constexpr int kNewtonSlow = 20;
-
-// Largest eigenvalue of the key matrix by Newton's method on its characteristic polynomial
-// lambda^4 + c2 lambda^2 + c1 lambda + c0 (c2 = -tr(N^2)/2, c1 = -tr(N^3)/3, c0 = det N),
-// started from the upper bound (Ga + Gb)/2; the polynomial is convex above its largest root, so
-// the iterates decrease monotonically onto it.  A slow iteration (kNewtonSlow) falls back to
-// Jacobi rotations.  Returns RMSD^2 = max(0, (Ga + Gb - 2 lambda) / A).
-__device__ inline double rmsd2_from_corr64(const double R[9], double Ga, double Gb, int A) {
+// The Jacobi solve of the key matrix of R, out of line (it is rare) and with R passed by value, so
+// that no array of the caller has its address taken and the caller's solve stays in registers.
+static __device__ __attribute__((noinline)) double key_max_eig_jacobi(double r0, double r1, double r2, double r3,
+                                                                       double r4, double r5, double r6, double r7,
+                                                                       double r8) {
+    const double R[9] = {r0, r1, r2, r3, r4, r5, r6, r7, r8};
     double N[4][4];
     horn_key(R, N);
-    double N2[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-            double t = 0.0;
-            for (int k = 0; k < 4; ++k) t = fma(N[i][k], N[k][j], t);
-            N2[i][j] = t;
-        }
-    double tr2 = 0.0, tr3 = 0.0;
-    for (int i = 0; i < 4; ++i) {
-        tr2 += N2[i][i];
-        for (int k = 0; k < 4; ++k) tr3 = fma(N2[i][k], N[k][i], tr3);
+    return sym4_max_eig_jacobi(N);
+}
+
+// Iterations after which the root iteration gives up: from the upper bound a simple largest root is
+// reached in about five.
+constexpr int kRootSteps = 20;
+
+// Largest eigenvalue of the key matrix from its characteristic polynomial
+// P(lambda) = lambda^4 + c2 lambda^2 + c1 lambda + c0.  For Horn's matrix tr(N^2) = 4 ||R||_F^2 and
+// tr(N^3) = 24 det R, so c2 = -tr(N^2)/2 = -2 ||R||_F^2, c1 = -tr(N^3)/3 = -8 det R and c0 = det N.
+// P has only real roots (N is symmetric), so Laguerre's iteration for degree n = 4,
+//   lambda <- lambda - n P / (P' + sqrt((n - 1) ((n - 1) P'^2 - n P P''))),
+// started from the upper bound (Ga + Gb)/2 decreases monotonically onto the largest root and
+// converges cubically at a simple root (Press et al., "Numerical Recipes", Sec. 9.5; the method is
+// globally convergent for real-rooted polynomials); it needs about half of Newton's steps from the
+// same start.
+//
+// Near a multiple root the iteration converges only linearly and P's rounding can stop it away from
+// the root, so the root is accepted only with an a-posteriori check: eta(lambda) bounds the error of
+// P as computed (the coefficients' rounding -- relative 10 u for the sum of squares, 5 u of the
+// absolute cofactor terms m1 of det R and 10 u of the absolute minor products M0 of det N -- and the
+// evaluation's, 4 u of each term), so the exact root lies within about (|P| + eta) / P'(lambda) of
+// the computed one; it is kept when that is at most tol (Ga + Gb) / 2, and otherwise (or when the
+// iteration does not settle within kRootSteps steps) the pair is solved by Jacobi rotations of the
+// key matrix.  Returns RMSD^2 = max(0, (Ga + Gb - 2 lambda) / A), within tol (Ga + Gb) / A plus
+// roundoff.  (FP64 callers keep tol = 1e-13; a caller whose R carries FP32 rounding may pass a larger
+// tol, well under that rounding, and so rarely needs the rotations.)
+// Coefficients of the key matrix's characteristic polynomial, P(l) = l^4 + c2 l^2 + c1 l + c0, and
+// the terms of the bound on its rounding: |P computed - P| <= u (((4 l^2 + e2) l + e1) l + e0).
+struct KeyPoly {
+    double c2, c1, c0;
+    double e2, e1, e0;
+};
+
+__device__ __forceinline__ KeyPoly key_poly(const double R[9]) {
+    double f2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) f2 = fma(R[k], R[k], f2);
+    const double p48 = R[4] * R[8], p57 = R[5] * R[7], p38 = R[3] * R[8], p56 = R[5] * R[6];
+    const double p37 = R[3] * R[7], p46 = R[4] * R[6];
+    const double detR = R[0] * (p48 - p57) - R[1] * (p38 - p56) + R[2] * (p37 - p46);
+    const double m1 = fabs(R[0]) * (fabs(p48) + fabs(p57)) + fabs(R[1]) * (fabs(p38) + fabs(p56)) +
+                      fabs(R[2]) * (fabs(p37) + fabs(p46));
+    double N[4][4];
+    horn_key(R, N);
+    // det N over the 2x2 minors of rows (0,1) and (2,3), with the sum of their absolute products
+    double c0 = 0.0, M0 = 0.0;
+    constexpr int ja[6] = {0, 0, 0, 1, 1, 2}, jb[6] = {1, 2, 3, 2, 3, 3};
+    constexpr double sg[6] = {1.0, -1.0, 1.0, 1.0, -1.0, 1.0};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int a0 = ja[k], b0 = jb[k], a1 = ja[5 - k], b1 = jb[5 - k];
+        const double s1 = N[0][a0] * N[1][b0], s2 = N[1][a0] * N[0][b0];
+        const double t1 = N[2][a1] * N[3][b1], t2 = N[3][a1] * N[2][b1];
+        c0 = fma(sg[k] * (s1 - s2), t1 - t2, c0);
+        M0 = fma(fabs(s1) + fabs(s2), fabs(t1) + fabs(t2), M0);
     }
-    const double c2 = -0.5 * tr2, c1 = -tr3 / 3.0, c0 = det4(N);
-    const double E0 = 0.5 * (Ga + Gb);
+    KeyPoly k;
+    k.c2 = -2.0 * f2;
+    k.c1 = -8.0 * detR;
+    k.c0 = c0;
+    k.e2 = 14.0 * fabs(k.c2);
+    k.e1 = 4.0 * fabs(k.c1) + 48.0 * m1;
+    k.e0 = 4.0 * fabs(c0) + 10.0 * M0;
+    return k;
+}
+
+// One Laguerre step on P from lam (above the largest root).  good: the step is defined (else it is
+// not taken); conv: the step was below stop or P(lam) within its rounding bound.
+__device__ __forceinline__ void key_root_step(const KeyPoly& k, double& lam, double stop, bool& good, bool& conv) {
+    constexpr double u = 0x1p-53;
+    const double l2 = lam * lam;
+    const double p = (l2 + k.c2) * l2 + k.c1 * lam + k.c0;
+    const double dp = (4.0 * l2 + 2.0 * k.c2) * lam + k.c1;
+    const double ddp = 12.0 * l2 + 2.0 * k.c2;
+    const double eta = u * (((4.0 * l2 + k.e2) * lam + k.e1) * lam + k.e0);
+    const double H = 3.0 * (3.0 * dp * dp - 4.0 * p * ddp);   // >= 0 for real roots (rounding: clamped)
+    // (the square root and the quotient from the hardware approximations with one Newton-Raphson
+    // correction each: the iteration corrects any small error of a step, and both the stopping
+    // test on P and the acceptance below evaluate P exactly)
+    // (branch-free: H <= 0 gives an infinite or NaN reciprocal root, replaced by a zero root)
+    const double y = __builtin_amdgcn_rsq(H);
+    double sh = H * y;
+    sh = fma(0.5 * sh, fma(-sh, y, 1.0), sh);
+    sh = H > 0.0 ? sh : 0.0;
+    const double den = dp + sh;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const double step = 4.0 * p * r;
+    good = den > 0.0;
+    conv = good & ((fabs(step) <= stop) | (fabs(p) <= eta));
+    lam = good ? lam - step : lam;
+}
+
+// The a-posteriori check of a settled root: the exact root within tol E0 of lam.
+__device__ __forceinline__ bool key_root_ok(const KeyPoly& k, double lam, double E0, double tol) {
+    constexpr double u = 0x1p-53;
+    const double l2 = lam * lam;
+    const double p = (l2 + k.c2) * l2 + k.c1 * lam + k.c0;
+    const double dp = (4.0 * l2 + 2.0 * k.c2) * lam + k.c1;
+    const double eta = u * (((4.0 * l2 + k.e2) * lam + k.e1) * lam + k.e0);
+    return dp > 0.0 && fabs(p) + eta <= tol * E0 * dp;
+}
+
+// The stopping step for a tolerance: with cubic convergence, after a step of 1e-3 tol the error is
+// far below tol.
+__device__ __forceinline__ double key_stop(double E0, double tol) { return fmax(1e-15, 1e-3 * tol) * E0; }
+
+__device__ inline double rmsd2_from_corr64(const double R[9], double Ga, double Gb, int A, double tol = 1e-13) {
+    const KeyPoly k = key_poly(R);
+    const double E0 = 0.5 * (Ga + Gb), stop = key_stop(E0, tol);
     double lam = E0;
-    bool converged = false;
-    for (int it = 0; it < kNewtonSlow; ++it) {
-        const double l2 = lam * lam;
-        const double p = (l2 + c2) * l2 + c1 * lam + c0;
-        const double dp = (4.0 * l2 + 2.0 * c2) * lam + c1;
-        if (!(dp > 0.0)) break;
-        const double step = p / dp;
-        lam -= step;
-        if (fabs(step) <= 1e-15 * E0) {
-            converged = true;
+    bool settled = false;
+    for (int it = 0; it < kRootSteps; ++it) {
+        bool good, conv;
+        key_root_step(k, lam, stop, good, conv);
+        if (!good | conv) {
+            settled = conv;
             break;
         }
     }
-    if (!converged) {
-        horn_key(R, N);
-        lam = sym4_max_eig_jacobi(N);
-    }
+    if (!(settled && key_root_ok(k, lam, E0, tol)))
+        lam = key_max_eig_jacobi(R[0], R[1], R[2], R[3], R[4], R[5], R[6], R[7], R[8]);
     const double r2 = (Ga + Gb - 2.0 * lam) / A;
     return r2 > 0.0 ? r2 : 0.0;
 }

@@ -121,7 +121,22 @@ struct DistArgs {
     int64_t colpart_cap;
     int64_t* colpart_blocks;// host out (with colmin): workgroups of the pass
     int64_t n_support;      // rows of sup (offsets[C])
+    // RMSD on the matrix cores: a pair pass leaves the squared RMSD of every (query, support) pair of
+    // a chunk of query groups (32 frames each), which the distance pass then reads back
+    float* r2buf;           // [rmsd_chunk][ceil(n_support / 32)][1024]
+    double* r2gq;           // [rmsd_chunk * 32] G = sum of squared coordinates of each query frame
+    int64_t rmsd_chunk;     // query groups per chunk
+    int64_t grp0, grp_n;    // the chunk being reduced (set by the launcher)
 };
+// Query groups per chunk of the RMSD pair pass: its buffer of squared RMSDs stays under cap_bytes.
+inline int64_t rmsd_chunk_groups(int64_t n, int64_t n_support, size_t cap_bytes) {
+    const int64_t tiles = std::max<int64_t>(1, (n_support + 31) / 32);
+    const int64_t groups = std::max<int64_t>(1, (n + 31) / 32);
+    return std::min<int64_t>(groups, std::max<int64_t>(1, (int64_t)(cap_bytes / ((size_t)tiles * 4096))));
+}
+// Pair-pass buffers of a fit's batch pass and of an assign call.
+constexpr size_t kRmsdFitChunkBytes = size_t(64) << 20;
+constexpr size_t kRmsdAssignChunkBytes = size_t(16) << 20;
 kkm_status launch_dist(const DistArgs& a, const DeviceInfo& dev, hipStream_t s);
 // Matrix-core distance pass (k_mfma.hip): linear / RBF, float samples, FP32, BF16 or BF16x3.
 bool mfma_dist_applies(const DistArgs& a);
