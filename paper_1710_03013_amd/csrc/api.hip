@@ -220,6 +220,8 @@ struct FitWs {
     int32_t* flags;        // [2] nonfinite, medoid candidates
     int32_t* bmed;
     int32_t* mpart_c;
+    double* tpan;          // merge targets [C][2][dpad] and their norms [C][2]
+    double* tnorm;
     double* gpart_v;
     int32_t* gpart_i;
     int32_t* updates;      // [B]
@@ -300,6 +302,8 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.psum = c.take<double>(1024);
     w.bmed = c.take<int32_t>(C);
     w.mpart_c = c.take<int32_t>((size_t)C * P.nchunk);
+    w.tpan = c.take<double>((size_t)C * 2 * P.dpad);
+    w.tnorm = c.take<double>((size_t)C * 2);
     w.gpart_v = c.take<double>((size_t)C * merge_chunks(P.nmax));
     w.gpart_i = c.take<int32_t>((size_t)C * merge_chunks(P.nmax));
     w.barrier = c.take<unsigned>(1);
@@ -802,6 +806,8 @@ kkm_status fit_enqueue(const FitPlan& P, FitWs& w, const void* X, hipStream_t s,
         sa.cand_v = w.cand_v;
         sa.cand_count = w.counts_b + C;
         sa.cand_cap = (int32_t)P.cand_cap;
+        sa.tpan = w.tpan;
+        sa.tnorm = w.tnorm;
         sa.gpart_v = w.gpart_v;
         sa.gpart_i = w.gpart_i;
 

@@ -529,12 +529,61 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
 }
 
 // Large merge grids: the clusters are settled once, a block per kMergeTJ clusters, instead of by
-// every row chunk (whose repeated reads of the candidate list would dominate the merge).
+// every row chunk (whose repeated reads of the candidate list would dominate the merge).  With
+// TARGETS (linear / RBF: the matrix-core merge) the block also writes its clusters' targets -- target
+// 2 jj the batch medoid m_j^i, 2 jj + 1 the global medoid m_j, zero when the merge does not use it --
+// in FP64 to tpan[j][2][Mpad], and their squared norms (summed in order) to tnorm[j][2].
+template <typename TI, int DP, bool TARGETS>
 __global__ __launch_bounds__(256) void merge_settle_kernel(SelectArgs a) {
     __shared__ unsigned long long cmin[kMergeTJ];
     __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
     __shared__ double calpha[kMergeTJ];
-    merge_settle(a, blockIdx.x * kMergeTJ, true, cmin, cpos, cmem, cmed, calpha);
+    const int j0 = blockIdx.x * kMergeTJ;
+    merge_settle(a, j0, true, cmin, cpos, cmem, cmed, calpha);
+    if constexpr (TARGETS && DP > 0) {
+        // value p of the block is dimension k = p % DP of target tt = p / DP; the loads are issued
+        // together (clamped, masked afterwards), the panel written from registers, and the norms
+        // summed over eight strided parts, then the parts in order
+        constexpr int NT = 2 * kMergeTJ, TPER = (DP * NT + 255) / 256;
+        __shared__ double part[8][NT];
+        const int d = a.b.d, t = threadIdx.x;
+        const int last = min(2 * a.C - 2 * j0, NT) - 1;
+        double tv[TPER];
+#pragma unroll
+        for (int u = 0; u < TPER; ++u) {
+            const int p = min(t + 256 * u, DP * NT - 1), tt = min(p / DP, last), k = p % DP;
+            const int jj = tt / 2, j = j0 + jj;
+            const bool med = (tt & 1) == 0;
+            const TI* src = med ? brow<TI>(a.b, max(cmed[jj], 0)) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+            const double alpha = calpha[jj];
+            const bool on = k < d && (med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0));
+            tv[u] = on ? (double)src[min(k, d - 1)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < TPER; ++u) {
+            const int p = t + 256 * u, tt = p / DP, k = p % DP;
+            if (p < DP * NT && tt <= last) a.tpan[((int64_t)j0 * 2 + tt) * a.Mpad + k] = tv[u];
+        }
+        __shared__ double tl[NT][DP + 1];
+#pragma unroll
+        for (int u = 0; u < TPER; ++u) {
+            const int p = t + 256 * u;
+            if (p < DP * NT) tl[p / DP][p % DP] = tv[u];
+        }
+        __syncthreads();
+        {
+            const int tt = t & (NT - 1), pt = t / NT;   // eight parts of 32 targets
+            double s2 = 0.0;
+            for (int k = pt; k < DP; k += 8) s2 = fma(tl[tt][k], tl[tt][k], s2);
+            part[pt][tt] = s2;
+        }
+        __syncthreads();
+        if (t < NT && t <= last) {
+            double v = 0.0;
+            for (int q = 0; q < 8; ++q) v += part[q][t];
+            a.tnorm[(int64_t)j0 * 2 + t] = v;
+        }
+    }
 }
 
 // SETTLED: the clusters were settled by merge_settle_kernel (read back from counts / bmed).
@@ -673,6 +722,189 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
             a.gpart_v[at] = bv;
             a.gpart_i[at] = bi == INT64_MAX ? -1 : (int32_t)bi;
         }
+    }
+}
+
+// The same merge on the FP64 matrix cores (linear / RBF): the dot products of the block's 64 rows
+// with its 32 targets run on v_mfma_f64_16x16x4f64, four dimensions a step (the A operand a target,
+// the B operand a row), and each score follows from them in FP64: d(x, t) = ||x||^2 + ||t||^2 - 2 x.t
+// (at least 0), K = exp(-d / (2 sigma^2)) for RBF or x.t for the linear kernel.  This is the FP64
+// value of the merge formula up to the order of its roundings (a few units of 2^-53 of ||x||^2 +
+// ||t||^2 in d), so the argmin is the FP64 one except between candidates equal to that order, and
+// no re-evaluation follows.  Wavefront w takes rows 16w .. 16w + 15 of the block and both 16-target
+// halves.  The FP64 product leaves output row 4v + l/16 of column l%16 in register v of lane l, so
+// A-operand row i carries target 4(i%4) + i/4 of the half: lane l then holds targets 4(l/16) + v
+// for row 16w + l%16, i.e. both targets (m_j^i, m_j) of two clusters per half.  Norms are summed in a fixed order (strided parts, then the
+// parts in order), so the result does not depend on scheduling.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename TI, int DP, bool SETTLED>
+__global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
+    constexpr int NT = 2 * kMergeTJ;                 // 32 targets
+    constexpr int XS = kMergeRows + 4;               // LDS row stride of the staged rows
+    __shared__ double Ts[DP][NT + 2];
+    __shared__ TI Xs[DP][XS];
+    __shared__ double part[4][kMergeRows];
+    __shared__ double xn[kMergeRows], tn[NT];
+    __shared__ double wv[4][kMergeTJ];
+    __shared__ int32_t wi[4][kMergeTJ];
+    __shared__ unsigned long long cmin[kMergeTJ];
+    __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
+    __shared__ double calpha[kMergeTJ];
+    const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
+    const int d = a.b.d;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t row0 = (int64_t)chunk * kMergeRows;
+    const int nrows = (int)min<int64_t>(kMergeRows, a.b.n - row0);
+    // the block's rows, dimension-major (rows and dimensions past the end: zero).  Every load is issued
+    // unconditionally (row and dimension clamped into range, the value masked afterwards), so that
+    // all of a thread's loads are in flight together.
+    constexpr int XPER = kMergeRows * DP / 256;
+    static_assert(XPER * 256 == kMergeRows * DP, "row staging covers the block exactly");
+    TI xv[XPER];
+#pragma unroll
+    for (int u = 0; u < XPER; ++u) {
+        const int p = t + 256 * u, r = p / DP, k = p - r * DP;
+        xv[u] = brow<TI>(a.b, row0 + min(r, nrows - 1))[min(k, d - 1)];
+    }
+    if constexpr (SETTLED) {
+        if (t < kMergeTJ && j0 + t < a.C) {
+            const int j = j0 + t;
+            const int32_t med = a.bmed[j];
+            const double alpha = merge_alpha(a.counts[j], a.wcount[j]);
+            cmed[t] = med;
+            calpha[t] = alpha > 0.0 && med >= 0 ? alpha : 0.0;
+        } else if (t < kMergeTJ) {   // past the last cluster: no medoid, no merge step
+            cmed[t] = -1;
+            calpha[t] = 0.0;
+        }
+        __syncthreads();
+    } else {
+        merge_settle(a, j0, chunk == 0, cmin, cpos, cmem, cmed, calpha);
+    }
+    // targets, dimension-major: target 2 jj is m_j^i, 2 jj + 1 is m_j (zero when unused); with the
+    // clusters settled beforehand, read from the settle pass's FP64 panel (coalesced) with their norms
+    if constexpr (SETTLED) {
+        constexpr int TPER = (DP * NT + 255) / 256;
+        const int last = min(2 * a.C - 2 * j0, NT) - 1;   // the block's last target (clusters past C: zero)
+        double tv[TPER];
+#pragma unroll
+        for (int u = 0; u < TPER; ++u) {
+            const int p = min(t + 256 * u, DP * NT - 1), tt = p / DP, k = p - tt * DP;
+            tv[u] = a.tpan[((int64_t)j0 * 2 + min(tt, last)) * a.Mpad + k];
+        }
+#pragma unroll
+        for (int u = 0; u < TPER; ++u) {
+            const int p = t + 256 * u, tt = p / DP, k = p - tt * DP;
+            if (p < DP * NT) Ts[k][tt] = tt <= last ? tv[u] : 0.0;
+        }
+        if (t < NT) tn[t] = t <= last ? a.tnorm[(int64_t)j0 * 2 + t] : 0.0;
+    } else {
+        for (int p = t; p < DP * NT; p += 256) {
+            const int k = p / NT, tt = p - k * NT;
+            const int jj = tt / 2, j = min(j0 + jj, a.C - 1);
+            const double alpha = calpha[jj];
+            const bool med = (tt & 1) == 0;
+            const int mrow = j0 + jj < a.C ? max(cmed[jj], 0) : 0;
+            const TI* src = med ? brow<TI>(a.b, mrow) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+            const bool on = j0 + jj < a.C && k < d && (med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0));
+            Ts[k][tt] = on ? (double)src[k] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < XPER; ++u) {
+        const int p = t + 256 * u, r = p / DP, k = p - r * DP;
+        Xs[k][r] = (r < nrows && k < d) ? xv[u] : TI(0);
+    }
+    __syncthreads();
+    // squared norms in a fixed order: rows in four parts, (unsettled) targets summed in order
+    {
+        const int r = t & 63, pr = t >> 6;
+        double sx = 0.0;
+        for (int k = pr; k < DP; k += 4) {
+            const double v = Xs[k][r];
+            sx = fma(v, v, sx);
+        }
+        part[pr][r] = sx;
+        if constexpr (!SETTLED) {
+            if (t < NT) {
+                double st = 0.0;
+                for (int k = 0; k < d; ++k) st = fma(Ts[k][t], Ts[k][t], st);
+                tn[t] = st;
+            }
+        }
+        __syncthreads();
+        if (t < kMergeRows) xn[t] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+        __syncthreads();
+    }
+    // the products: wave w, rows 16w + l%16; target halves h = 0, 1
+    doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const int q4 = lane >> 4, c16 = lane & 15;
+    const int ta = 4 * (c16 & 3) + (c16 >> 2);   // the target of A-operand row c16
+#pragma unroll 4
+    for (int s = 0; s < DP / 4; ++s) {
+        const int k = 4 * s + q4;
+        const double xv = (double)Xs[k][16 * wave + c16];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[k][ta], xv, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[k][16 + ta], xv, acc1, 0, 0, 0);
+    }
+    // scores of the lane's four clusters for its row, then the wavefront's minimum per cluster over
+    // its 16 rows (lanes of one quarter), lowest position on equal scores
+    const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
+    const int r = 16 * wave + c16;
+    const double xx = xn[r];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const doublex4 acc = h == 0 ? acc0 : acc1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int jj = 8 * h + 2 * q4 + c;              // cluster of targets 2jj, 2jj + 1
+            const int t1 = 2 * jj;
+            const double alpha = calpha[jj];
+            double bv = kInf;
+            int32_t bi = INT32_MAX;
+            if (alpha > 0.0 && r < nrows) {
+                double k1, k2 = 0.0;
+                if (lin) {
+                    k1 = acc[2 * c];
+                    k2 = acc[2 * c + 1];
+                } else {
+                    k1 = ::exp(-fmax(xx + tn[t1] - 2.0 * acc[2 * c], 0.0) * a.ks.inv2s2);
+                    if (alpha < 1.0) k2 = ::exp(-fmax(xx + tn[t1 + 1] - 2.0 * acc[2 * c + 1], 0.0) * a.ks.inv2s2);
+                }
+                double sc = (lin ? xx : 1.0) - 2.0 * alpha * k1;
+                if (alpha < 1.0) sc = sc - 2.0 * (1.0 - alpha) * k2;
+                bv = sc;
+                bi = r;
+            }
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) {
+                const double v2 = __shfl_xor(bv, o, 64);
+                const int32_t i2 = __shfl_xor(bi, o, 64);
+                if (v2 < bv || (v2 == bv && i2 < bi)) {
+                    bv = v2;
+                    bi = i2;
+                }
+            }
+            if (c16 == 0) {
+                wv[wave][jj] = bv;
+                wi[wave][jj] = bi;
+            }
+        }
+    }
+    __syncthreads();
+    // the block's minimum per cluster over the four wavefronts (rows ascending)
+    if (t < kMergeTJ && j0 + t < a.C) {
+        double bv = wv[0][t];
+        int32_t bi = wi[0][t];
+        for (int w = 1; w < 4; ++w)
+            if (wv[w][t] < bv || (wv[w][t] == bv && wi[w][t] < bi)) {
+                bv = wv[w][t];
+                bi = wi[w][t];
+            }
+        const int64_t at = (int64_t)(j0 + t) * a.mchunk + chunk;
+        a.gpart_v[at] = bv;
+        a.gpart_i[at] = bi == INT32_MAX ? -1 : (int32_t)(row0 + bi);
     }
 }
 
@@ -970,6 +1202,16 @@ kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, in
     return KKM_OK;
 }
 
+// KKM_MERGE_VALU=1 in the environment: the merge scores on the VALU (explicit differences) instead of
+// the FP64 matrix cores.
+bool merge_on_mfma() {
+    static const bool valu = [] {
+        const char* e = std::getenv("KKM_MERGE_VALU");
+        return e && e[0] == '1';
+    }();
+    return !valu;
+}
+
 int select_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kRowsPerBlock - 1) / kRowsPerBlock); }
 int merge_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kMergeRows - 1) / kMergeRows); }
 
@@ -996,9 +1238,17 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
             hipLaunchKernelGGL((merge_partial_kernel<TI, DP>), grid, dim3(256), 0, s, a);
         } else {
             // (more than 1024 tile blocks: settle the clusters once first)
-            if ((int64_t)tgrid.x * tgrid.y > 1024) {
-                hipLaunchKernelGGL(merge_settle_kernel, dim3(tgrid.y), dim3(256), 0, s, a);
+            const bool settle_first = (int64_t)tgrid.x * tgrid.y > 1024;
+            if (settle_first) {
+                if (merge_on_mfma() && a.tpan && a.tnorm)
+                    hipLaunchKernelGGL((merge_settle_kernel<TI, DP, true>), dim3(tgrid.y), dim3(256), 0, s, a);
+                else hipLaunchKernelGGL((merge_settle_kernel<TI, DP, false>), dim3(tgrid.y), dim3(256), 0, s, a);
                 KKM_HIP(hipGetLastError());
+            }
+            if (merge_on_mfma() && (!settle_first || (a.tpan && a.tnorm))) {
+                if (settle_first) hipLaunchKernelGGL((merge_mfma_kernel<TI, DP, true>), tgrid, dim3(256), 0, s, a);
+                else hipLaunchKernelGGL((merge_mfma_kernel<TI, DP, false>), tgrid, dim3(256), 0, s, a);
+            } else if (settle_first) {
                 hipLaunchKernelGGL((merge_tile_kernel<TI, DP, true>), tgrid, dim3(256), 0, s, a);
             } else {
                 hipLaunchKernelGGL((merge_tile_kernel<TI, DP, false>), tgrid, dim3(256), 0, s, a);

@@ -197,6 +197,8 @@ struct SelectArgs {
     int32_t* cand_count;    // [1] (cleared before the batch)
     int32_t cand_cap;
     int32_t* cand_total;    // [1] accumulates cand_count over batches, or null
+    double* tpan;           // [C][2][Mpad] merge targets (m_j^i, m_j) in FP64, written by the settle pass
+    double* tnorm;          // [C][2] their squared norms
     double* gpart_v;        // [C][mchunk] merge partials (set by launch_select)
     int32_t* gpart_i;
     int32_t mchunk;
