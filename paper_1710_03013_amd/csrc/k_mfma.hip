@@ -32,6 +32,8 @@
 // outside these relative bounds.
 #include <cstdlib>
 
+#include <type_traits>
+
 #include "kkm_internal.hpp"
 #include "kkm_launch.hpp"
 
@@ -646,26 +648,31 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
             } else {
                 acc = mfma_tile<DP, PM>(a.sup, t, lane, xq, bh, bl);
             }
+            // best and second best of the lane's rows (branch-free; a NaN changes neither), the rows
+            // past the last cluster masked only in the last, partial tile
+            auto take = [&](float e, int j) {
+                const bool lt = e < e1;
+                e2 = lt ? e1 : fminf(e2, e);
+                j1 = lt ? j : j1;
+                e1 = lt ? e : e1;
+            };
+            auto epilogue = [&](auto masked) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int rb = 32 * t + 8 * b + 4 * h;
-                const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
-                const float sn[4] = {sn4.x, sn4.y, sn4.z, sn4.w};
+                for (int b = 0; b < 4; ++b) {
+                    const int rb = 32 * t + 8 * b + 4 * h;
+                    const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
+                    const float sn[4] = {sn4.x, sn4.y, sn4.z, sn4.w};
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int j = rb + c;
-                    // RBF / linear: e = ||m||^2 - 2 x.m; RMSD: e = r^2 (d = 2 - 2 exp(-r^2 / (2 sigma^2)))
-                    const float ev = RM ? acc[4 * b + c] : fmaf(-2.0f, acc[4 * b + c], sn[c]);
-                    const float e = j < C ? ev : __builtin_huge_valf();
-                    if (e < e1) {
-                        e2 = e1;
-                        e1 = e;
-                        j1 = j;
-                    } else if (e < e2) {
-                        e2 = e;
+                    for (int c = 0; c < 4; ++c) {
+                        const int j = rb + c;
+                        // RBF / linear: e = ||m||^2 - 2 x.m; RMSD: e = r^2 (d = 2 - 2 exp(-r^2 / (2 sigma^2)))
+                        const float ev = RM ? acc[4 * b + c] : fmaf(-2.0f, acc[4 * b + c], sn[c]);
+                        take(decltype(masked)::value && j >= C ? __builtin_huge_valf() : ev, j);
                     }
                 }
-            }
+            };
+            if (32 * t + 32 <= C) epilogue(std::false_type{});
+            else epilogue(std::true_type{});
         }
         {   // the partner lane holds the interleaved rows of every tile
             const float o1 = __shfl_xor(e1, 32, 64), o2 = __shfl_xor(e2, 32, 64);
@@ -796,6 +803,17 @@ kkm_status rmsd_chunks(const DistArgs& a, hipStream_t s, F&& f) {
     return KKM_OK;
 }
 
+// Eight wavefronts per distance workgroup below this many 32-sample groups per CU (KKM_DIST_EIGHT
+// overrides it).
+static int dist_eight_groups_per_cu() {
+    static const int v = [] {
+        const char* e = std::getenv("KKM_DIST_EIGHT");
+        const int x = e ? std::atoi(e) : 0;
+        return x > 0 ? x : 2;
+    }();
+    return v;
+}
+
 template <typename TI, int PM>
 kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s) {
     const size_t C = (size_t)a.sup.C;
@@ -816,7 +834,7 @@ kkm_status launch_mfma_t(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
     // Eight wavefronts per workgroup when four would leave the SIMDs under two wavefronts each
     // (few groups: the pass is bound by each wavefront's chain of tiles), where their LDS fits;
     // otherwise four, which duplicate less per-group work.
-    const bool eight = groups < 2 * (int64_t)dev.num_cus &&
+    const bool eight = groups < (int64_t)dist_eight_groups_per_cu() * dev.num_cus &&
                        mfma_lds_dynamic(C, 8) + mfma_lds_static(8) <= dev.max_lds_per_block;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(groups, 8 * (int64_t)dev.num_cus));
     if (a.colmin && groups > a.colpart_cap) return fail(KKM_ERR_INTERNAL, "column partials too small");
