@@ -50,8 +50,11 @@ PEAK_BF16_MATRIX = 2.5e15     # published MI355X dense BF16 matrix-core FLOP/s
 # calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
 # and its SHA-1 prefix at measurement time: a changed kernel source reports null.
 TRAFFIC_MEASURED = {
-    ("landmark_phase_kernel", "mixture16"): (10.579e6, "k_landmark.hip", "12c51db228ac"),
-    ("mfma_dist_kernel", "mixture16"): (2.890e6, "k_mfma.hip", "8f0dd5a930b6"),
+    ("mfma_dist_kernel", "mixture64"): (16.367e6, "k_mfma.hip", "bb19a507df0d"),
+    ("landmark_phase_kernel", "mixture64"): (2.948e6, "k_landmark.hip", "808051d9fa5e"),
+    ("mfma_assign1_kernel", "mixture64"): (260.19e6, "k_mfma.hip", "bb19a507df0d"),
+    ("rmsd_pairs_kernel+mfma_dist_kernel", "md"): (105.12e6, "k_mfma.hip", "bb19a507df0d"),
+    ("rmsd_pairs_kernel+mfma_assign1_kernel", "md"): (231.14e6, "k_mfma.hip", "bb19a507df0d"),
 }
 
 
@@ -83,9 +86,16 @@ def dist_flops_per_eval(kind: str, d: int) -> float:
         return 2 * d + 2
     if kind == "rbf":
         return 2 * d + 7
-    # RMSD: 9 correlation sums over A atoms (18 A), key-matrix polynomial and Newton (~150)
+    # RMSD: 9 correlation sums over A atoms (18 A) and the key-matrix solve
     A = d // 3
-    return 18 * A + 150
+    return 18 * A + KEY_SOLVE_FLOPS
+
+
+# FP64 flops of one key-matrix solve as the library's code performs it: coefficients with their
+# rounding terms ~142 (det N over 2x2 minors 72, the key matrix 20, ||R||^2 18, det R and its
+# absolute terms 16, the rest 16), ~37 per Laguerre step at the 4.7 steps a pair of MD frames takes
+# on average from (Ga + Gb) / 2, the acceptance test 17 and r^2 3.
+KEY_SOLVE_FLOPS = 142 + 37 * 4.7 + 17 + 3
 
 
 def landmark_flops_per_launch(ell: int, updates: int, C: int) -> float:
@@ -561,10 +571,22 @@ def step_bench(args) -> int:
             "landmark_phase_kernel": (ms["landmark_loop"], B, lm_flops, PEAK_FP64_VECTOR, "alu"),
             dist_name: (ms["dist"], B, dist_flops, peak, "mfma" if mfma else "alu"),
         }
-        if r["assign_pass_ms"]:
+        if cfg["kernel"] == "rmsd" and mfma:
+            # the RMSD distance pass is the pair pass (FP32 cross-covariance on the matrix cores, then the
+            # FP64 key-matrix solve on the VALU, which bounds it) and the segment reduction: priced as
+            # FP64 ALU work on the solve's flops
+            pairs = float(np.mean([batch_n[i] * ells[i] for i in range(B)]))
+            cands = {"landmark_phase_kernel": cands["landmark_phase_kernel"],
+                     "rmsd_pairs_kernel+mfma_dist_kernel": (ms["dist"], B, pairs * KEY_SOLVE_FLOPS,
+                                                            PEAK_FP64_VECTOR, "alu")}
+        if r["assign_pass_ms"] and cfg["kernel"] != "rmsd":
             # the assign pass's contraction: N x C dot products of length d
             cands[assign_name + " (assign pass)"] = (r["assign_pass_ms"], 1, 2.0 * N * C * d, peak,
                                                      "mfma" if mfma else "alu")
+        elif r["assign_pass_ms"]:
+            cands["rmsd_pairs_kernel+mfma_assign1_kernel (assign pass)"] = (r["assign_pass_ms"], 1,
+                                                                          float(N) * C * KEY_SOLVE_FLOPS,
+                                                                          PEAK_FP64_VECTOR, "alu")
         for name, (tot_ms, launches, flops, pk, bound) in cands.items():
             dur = tot_ms / launches * 1e-3
             achieved = flops / dur if dur > 0 else 0.0
