@@ -387,7 +387,7 @@ def main() -> int:
                     help="instead: accuracy and time against (B, s) on the 16-d mixture, and the (B, s) procedure")
     ap.add_argument("--sweep-b", default="2,4,8,16")
     ap.add_argument("--sweep-s", default="0.025,0.05,0.1,0.2,0.4,0.7,1.0")
-    ap.add_argument("--sweep-time-budget", type=float, default=0.004, help="seconds, for the (B, s) procedure")
+    ap.add_argument("--sweep-time-budget", type=float, default=0.01, help="seconds, for the (B, s) procedure")
     ap.add_argument("--sweep-memory-gb", type=float, default=0.5, help="workspace budget of the (B, s) procedure")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="arrival window per load")
     ap.add_argument("--serving-budget-gb", type=float, default=200.0, help="HBM admission budget")
