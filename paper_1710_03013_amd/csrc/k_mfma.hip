@@ -112,11 +112,9 @@ __device__ __forceinline__ floatx16 mfma_tile(const SupportView& sup, int64_t ti
     return acc;
 }
 
-// The lane half's dimensions of sample row xr (zero past d), with the squared norm over both halves,
-// the finiteness of the lane's part, and the bfloat16 split for the BF16 forms.
-template <typename TI, int DP, int PM>
-__device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok, int h, float* xq, bf16x8* bh,
-                                            bf16x8* bl, bool& ok) {
+// The lane half's dimensions of sample row xr (zero past d).
+template <typename TI, int DP>
+__device__ __forceinline__ void load_query_rows(const TI* xr, int64_t d, bool vec_ok, int h, float* xq) {
     constexpr int H = DP / 2;
     const bool xvec = H % 4 == 0 && d == DP && vec_ok;
     if (xvec) {
@@ -136,6 +134,13 @@ __device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok
             xq[s] = dim < d ? (float)xr[dim] : 0.0f;
         }
     }
+}
+
+// The squared norm of the sample over both lane halves, the finiteness of the lane's part, and the
+// bfloat16 split for the BF16 forms.
+template <int DP, int PM>
+__device__ __forceinline__ float finish_query(const float* xq, bf16x8* bh, bf16x8* bl, bool& ok) {
+    constexpr int H = DP / 2;
     float qn = 0.0f;
     ok = true;
 #pragma unroll
@@ -156,6 +161,13 @@ __device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok
             }
     }
     return qn;
+}
+
+template <typename TI, int DP, int PM>
+__device__ __forceinline__ float load_query(const TI* xr, int64_t d, bool vec_ok, int h, float* xq, bf16x8* bh,
+                                            bf16x8* bl, bool& ok) {
+    load_query_rows<TI, DP>(xr, d, vec_ok, h, xq);
+    return finish_query<DP, PM>(xq, bh, bl, ok);
 }
 
 // ----------------------------------------------------------------------------- RMSD frames
@@ -325,6 +337,7 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     __shared__ float Eg[4][32];
     __shared__ double Bw1[4][32], Bw2[4][32];
     __shared__ int Iw[4][32];
+    __shared__ float Es[32];
     __shared__ float Pt[NW][32 * 33];
     __shared__ int jb[5];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -332,16 +345,7 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     const int type = a.ks.type;
     const float inv2s2 = (float)a.ks.inv2s2;
 
-    if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
-    for (int j = threadIdx.x; j <= C; j += blockDim.x) {
-        off[j] = a.sup.offsets[j];
-        if (j < C) {
-            mself[j] = a.sup.self[j];
-            msegabs[j] = a.sup.segabs[j];
-        }
-    }
-    const float snmax = *a.sup.snorm_max;
-    __syncthreads();
+    float snmax = 0.0f;
 
     // groups of 32 samples, grid-stride (RMSD: the groups of the pair pass's chunk)
     const int64_t g_begin = RM ? a.grp0 : 0;
@@ -350,6 +354,7 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     for (int64_t grp = g_begin + blockIdx.x; grp < g_end; grp += gridDim.x) {
     const int64_t q = grp * 32 + col;
     const bool active = q < a.q.n;
+    const bool first = grp == g_begin + (int64_t)blockIdx.x;
 
     // the sample's half of the dimensions, its squared norm, and its bf16 split (RMSD: G_x of the
     // lane's frame, left by the pair pass, which also flagged non-finite frames)
@@ -362,8 +367,23 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
         qn = (float)a.r2gq[(grp - g_begin) * 32 + col];
         ok = true;
     } else {
-        qn = load_query<TI, DP, PM>(xr, a.q.d, (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0, h, xq, bh, bl, ok);
+        load_query_rows<TI, DP>(xr, a.q.d, (reinterpret_cast<uintptr_t>(a.q.X) & 15) == 0, h, xq);
     }
+    if (first) {
+        // segment metadata of the support, read once per workgroup while the first group's rows
+        // are in flight: offsets, self terms, |a| sums
+        if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
+        for (int j = threadIdx.x; j <= C; j += blockDim.x) {
+            off[j] = a.sup.offsets[j];
+            if (j < C) {
+                mself[j] = a.sup.self[j];
+                msegabs[j] = a.sup.segabs[j];
+            }
+        }
+        snmax = *a.sup.snorm_max;
+        __syncthreads();
+    }
+    if constexpr (!RM) qn = finish_query<DP, PM>(xq, bh, bl, ok);
     if (active && !ok) atomicOr(a.nonfinite, 1);   // either half may hold the bad value
     const float kqq = type == KKM_KERNEL_LINEAR ? qn : 1.0f;
     const int quarter = wave & 3, half = wave >> 2;
@@ -438,21 +458,44 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
             if (nseg > 0) jc += __builtin_amdgcn_readlane(o1, nseg - 1) > tile_end ? nseg - 1 : nseg;
         } else {
             // short segments: the tile through LDS; lane half h takes every other segment, lane col
-            // its sample, each adding its rows in row order
+            // its sample, each adding its rows in row order.  Each step takes two segments per lane
+            // (k0 + h and k0 + 2 + h) and reads their first four rows without a branch (rows past a
+            // segment's end count as zeros, which leaves the ordered sums unchanged); longer segments
+            // continue four rows at a time.  A lane past the last segment adds its zero into Es, which
+            // is free until the decision.
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) P[(8 * b + 4 * h + c) * 33 + col] = v[4 * b + c];
             wave_sync_lds();
+            auto rows4 = [&](int r, int hi, float part) {
+                float x[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x[e] = P[(max(min(r + e, hi - 1), r0) - r0) * 33 + col];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) part += r + e < hi ? x[e] : 0.0f;
+                return part;
+            };
             for (;;) {
-                for (int k0 = 0; k0 < nseg; k0 += 2) {
-                    const int k = k0 + h;
-                    const int lo_k = __shfl(o0, k, 64), hi_k = __shfl(o1, k, 64);
-                    if (k < nseg) {
-                        const int lo = max(lo_k, r0), hi = min(hi_k, tile_end);
-                        float part = 0.0f;
-                        for (int r = lo; r < hi; ++r) part += P[(r - r0) * 33 + col];
-                        if (hi > lo) Dw[(jc + k) * 32 + col] += part;
+                for (int k0 = 0; k0 < nseg; k0 += 4) {
+                    int lo[2], hi[2];
+                    float part[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int k = k0 + 2 * u + h, kc = min(k, nseg - 1);
+                        const int a0 = off[jc + kc], a1 = off[jc + kc + 1];
+                        lo[u] = max(a0, r0);
+                        hi[u] = k < nseg ? min(a1, tile_end) : lo[u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) part[u] = rows4(lo[u], hi[u], 0.0f);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        for (int r = lo[u] + 4; r < hi[u]; r += 4) part[u] = rows4(r, hi[u], part[u]);
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int k = k0 + 2 * u + h;
+                        *(k < nseg ? &Dw[(jc + k) * 32 + col] : &Es[col]) += part[u];
                     }
                 }
                 // the last counted segment may continue in the next tile
@@ -486,45 +529,64 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     const float dot_rel = BF3 ? kUbf3 + (3.0f * DP + 2.0f) * kU32
                         : BF ? kUbf1 + (DP + 3.0f) * kU32 : (DP + 2.0f) * kU32;
     const float kmax = sqrtf(qn * snmax) * 1.0001f;
-    for (int jj = j0 + h; half == 0 && jj < j1; jj += 2) {
-        const int lo = off[jj], hi = off[jj + 1];
-        const double g = mself[jj];
-        float accf = Dl[jj * 32 + col];
-        if constexpr (NH > 1) accf += Dl[(size_t)C * 32 + jj * 32 + col];
-        double D64 = kInf;
-        float D = __builtin_huge_valf();
-        if (hi > lo && g < kInf) {
-            D64 = (double)kqq + g - 2.0 * (double)accf;
-            D = (float)D64;
-            const float len = (float)(hi - lo), segabs = (float)msegabs[jj];
+    // (branch-free, so that the unrolled iterations' LDS reads are issued together; one copy of the
+    // loop per kernel form)
+    const bool nonneg = a.sup.nonneg != 0;
+    float rho;   // relative error of each kernel value
+    if constexpr (RM) {
+        // K = exp(-r^2 / (2 sigma^2)): the r^2 bound times 1 / (2 sigma^2), the float rounding of the
+        // exponent's argument and a few ulps of the exponential
+        rho = rmsd_r2_bound(qn, snmax, a.ks.n_atoms) * inv2s2 +
+              (inv2s2 * (qn + snmax) / (float)a.ks.n_atoms + 4.0f) * kU32;
+    } else {
+        // RBF: exp's relative error is rho (from the squared-distance error) plus a few ulps, so the
+        // sum's error scales with the sum of |a_l| K: the sum itself when no a_l is negative
+        rho = (2.0f * dot_rel * kmax + (DP + 6.0f) * kU32 * (qn + snmax)) * inv2s2;
+    }
+    // (the pairs of clusters are walked with a trip count common to the wavefront; a lane whose
+    // cluster is past the quarter's end reads a valid one, discards the result and stores it into its
+    // wavefront's free tile buffer)
+    const int jend = half == 0 ? j1 : j0;
+    auto decide = [&](auto lin_c) {
+        constexpr bool LIN = decltype(lin_c)::value;
+        const float elin = LIN ? (DP + 2.0f) * kU32 * qn : 0.0f;
+#pragma unroll 4
+        for (int jp = j0; jp < jend; jp += 2) {
+            const int jj = jp + h;
+            const bool in = jj < j1;
+            const int jr = in ? jj : jp;
+            const int lo = off[jr], hi = off[jr + 1];
+            const double g = mself[jr];
+            const float segabs = (float)msegabs[jr];
+            float accf = Dl[jr * 32 + col];
+            if constexpr (NH > 1) accf += Dl[(size_t)C * 32 + jr * 32 + col];
+            const bool live = in && hi > lo && g < kInf;
+            const double Dc = (double)kqq + g - 2.0 * (double)accf;
+            const float len = (float)(hi - lo);
             float ef;
-            if (RM) {
-                // relative error of K = exp(-r^2 / (2 sigma^2)): the r^2 bound times 1 / (2 sigma^2), the
-                // float rounding of the exponent's argument and a few ulps of the exponential
-                const float rho = rmsd_r2_bound(qn, snmax, a.ks.n_atoms) * inv2s2 +
-                                  (inv2s2 * (qn + snmax) / (float)a.ks.n_atoms + 4.0f) * kU32;
-                const float mass = a.sup.nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
-                ef = (rho + (len + 8.0f) * kU32) * mass;
-            } else if (type == KKM_KERNEL_LINEAR) {
+            if constexpr (LIN) {
                 ef = (dot_rel * kmax + (len + 2.0f) * kU32 * kmax) * segabs;
             } else {
-                // exp's relative error is rho (from the squared-distance error) plus a few ulps, so the
-                // sum's error scales with the sum of |a_l| K: the sum itself when no a_l is negative
-                const float rho = (2.0f * dot_rel * kmax + (DP + 6.0f) * kU32 * (qn + snmax)) * inv2s2;
-                const float mass = a.sup.nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
+                const float mass = nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
                 ef = (rho + (len + 8.0f) * kU32) * mass;
             }
             // (plus the FP64 rounding of D and of the self term, 4 units of 2^-53 of the magnitudes)
-            egap = fmaxf(egap, 2.0f * ef * 1.0001f +
-                                   (float)(4.5e-16 * (fabs((double)kqq) + fabs(g) + 2.0 * fabs((double)accf))));
-            const float e = 2.0f * ef + 2.0f * kU32 * fabsf(D) +
-                            (type == KKM_KERNEL_LINEAR ? (DP + 2.0f) * kU32 * qn : 0.0f);
-            ecol = fmaxf(ecol, 2.0f * e);
+            const float eg =
+                2.0f * ef * 1.0001f + (float)(4.5e-16 * (fabs((double)kqq) + fabs(g) + 2.0 * fabs((double)accf)));
+            const float Df = (float)Dc;
+            const float e = 2.0f * ef + 2.0f * kU32 * fabsf(Df) + elin;
+            egap = live ? fmaxf(egap, eg) : egap;
+            ecol = live ? fmaxf(ecol, 2.0f * e) : ecol;
+            const double D64 = live ? Dc : kInf;
+            *(in ? &Dl[jj * 32 + col] : &P[col]) = live ? Df : __builtin_huge_valf();
+            const bool lt1 = D64 < b1, lt2 = D64 < b2;
+            b2 = lt1 ? b1 : (lt2 ? D64 : b2);
+            b1 = lt1 ? D64 : b1;
+            i1 = lt1 ? jj : i1;
         }
-        Dl[jj * 32 + col] = D;
-        if (D64 < b1) { b2 = b1; b1 = D64; i1 = jj; }
-        else if (D64 < b2) { b2 = D64; }
-    }
+    };
+    if (!RM && type == KKM_KERNEL_LINEAR) decide(std::true_type{});
+    else decide(std::false_type{});
     {   // merge the two lane halves
         const double c1 = __shfl_xor(b1, 32, 64), c2 = __shfl_xor(b2, 32, 64);
         const int k1 = __shfl_xor(i1, 32, 64);
@@ -576,15 +638,27 @@ __global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
     }
     if (wave == 0) append_rows(need, q, a.refine_count, a.refine_list);
     if (a.Dt) {
+        // the D tile through LDS: consecutive threads store consecutive samples of one cluster, and
+        // thread j takes the column minimum of cluster j over the group's samples (each thread starting
+        // at sample j mod 32, so that a wavefront's reads fall in distinct banks)
+        // (E of a sample slot past the last row is +inf, which removes it from the minima)
+        if (wave == 0 && h == 0) Es[col] = active ? E : __builtin_huge_valf();
+        __syncthreads();
         float* Dt = a.Dt;
-        for (int jj = wave; jj < C; jj += NW) {
-            const float D = Dl[jj * 32 + col];
-            if (active && h == 0) Dt[(int64_t)jj * a.ldD + q] = D;
-            if (a.colmin) {
-                double vv = (active && h == 0) ? (double)D + (double)E : kInf;
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) vv = fmin(vv, __shfl_xor(vv, o, kWave));
-                if (lane == 0) a.colpart[(int64_t)jj * a.colpart_cap + grp] = vv;
+        const int64_t q0 = grp * 32;
+        for (int p = threadIdx.x; p < C * 32; p += NW * 64) {
+            const int c = p & 31;
+            if (q0 + c < a.q.n) Dt[(int64_t)(p >> 5) * a.ldD + q0 + c] = Dl[p];
+        }
+        if (a.colmin) {
+            for (int jj = threadIdx.x; jj < C; jj += NW * 64) {
+                double vv = kInf;
+#pragma unroll 8
+                for (int k = 0; k < 32; ++k) {
+                    const int c = (k + jj) & 31;
+                    vv = fmin(vv, (double)Dl[jj * 32 + c] + (double)Es[c]);
+                }
+                a.colpart[(int64_t)jj * a.colpart_cap + grp] = vv;
             }
         }
     }
@@ -735,7 +809,8 @@ size_t mfma_lds_dynamic(size_t C, int nw) {
     return sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
 }
 size_t mfma_lds_static(int nw) {
-    return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 + 64;
+    return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2 + 32) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 +
+           64;
 }
 
 template <typename TI, int PM, int NW>

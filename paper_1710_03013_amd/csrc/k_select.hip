@@ -1231,7 +1231,10 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
             if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP, false>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP, false>), grid, dim3(256), 0, s, a);
             KKM_HIP(hipGetLastError());
-            hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3((unsigned)std::max(1, 4 * dev.num_cus)), dim3(256), 0, s, a);
+            // (candidates are typically a few per cluster: a wavefront each, far fewer workgroups than
+            // the candidate scan)
+            hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3((unsigned)std::max(1, dev.num_cus / 2)), dim3(256), 0, s,
+                               a);
         }
         KKM_HIP(hipGetLastError());
         if constexpr (DP == 0) {
