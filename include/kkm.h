@@ -69,7 +69,8 @@ enum kkm_precision {
     KKM_PREC_FP64 = 0,
     KKM_PREC_FP32 = 1,
     KKM_PREC_BF16 = 2,          /* x.y from one bfloat16 product hi*hi' (FP32 accumulation) on MFMA: the
-                                   cheap gating pass, rows under its (wider) bound go to FP64; kkm_cost
+                                   cheap gating pass; the rows under its (wider) bound are decided again
+                                   with the BF16X3 products, and those still undecided in FP64; kkm_cost
                                    then takes each row's distance to its cluster in FP64.  In kkm_fit the
                                    batch pass feeds the medoid candidates, whose bound needs the
                                    compensated products: a fit asked for BF16 runs BF16X3 there */
@@ -257,7 +258,7 @@ kkm_status kkm_assign(const kkm_model* model, const void* X, int64_t n, int32_t 
 /* kkm_assign without a workspace, for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same labels and margins as
  * kkm_assign, with the scratch taken from a fixed 48 MiB device array that the library holds on every
- * GPU it runs on until the process ends.  Allocates nothing.  Rows of n * (16 bytes + for RMSD one
+ * GPU it runs on until the process ends.  Allocates nothing.  Rows of n * (16.125 bytes + for RMSD one
  * centred frame and its squared RMSDs to the support) plus fixed parts must fit that array (about
  * 3 million rows of d = 64, 55 000 frames of 50 atoms against 50 medoids): a larger n returns
  * KKM_ERR_UNSUPPORTED and enqueues nothing.  All calls on one GPU share

@@ -167,6 +167,7 @@ struct AssignWs {
     double* partials;
     double* cost;
     int32_t* labels_tmp;   // labels when the caller wants only the cost
+    uint32_t* gate;        // [ceil(n / 32)] rows the plain BF16 pass leaves undecided
 };
 
 struct FitWs {
@@ -511,6 +512,7 @@ size_t carve_assign(Carver& c, const kkm_model* m, int64_t n, AssignWs& w) {
     w.partials = c.take<double>(1024);
     w.cost = c.take<double>(1);
     w.labels_tmp = c.take<int32_t>(nn);
+    w.gate = c.take<uint32_t>((size_t)(nn + 31) / 32);
     return c.off;
 }
 
@@ -580,6 +582,7 @@ kkm_status assign_launch(const kkm_model* m, const void* X, int64_t n, int32_t d
     da.r2buf = w.r2buf;
     da.r2gq = w.r2gq;
     da.rmsd_chunk = w.rmsd_chunk;
+    da.gate = w.gate;
     if (da.sup.C * 64 * (dist_is_fp64(da) ? 8u : 4u) > dev.max_lds_per_block)
         return fail(KKM_ERR_UNSUPPORTED, "too many clusters for the distance tile");
     KKM_TRY(launch_dist(da, dev, s));

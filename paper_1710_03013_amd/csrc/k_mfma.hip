@@ -697,9 +697,13 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
     const int64_t g_begin = RM ? a.grp0 : 0;
     const int64_t g_end = RM ? a.grp0 + a.grp_n : (a.q.n + 31) / 32;
     for (int64_t grp = g_begin + (int64_t)blockIdx.x * 4 + wave; grp < g_end; grp += (int64_t)gridDim.x * 4) {
+        // (re-decision pass of the plain BF16 cascade: only the groups with marked rows, and in them
+        // only the marked rows are written)
+        const uint32_t gmask = a.gate_mode == 2 ? a.gate[grp] : 0xffffffffu;
+        if (gmask == 0u) continue;
         const int64_t q = grp * 32 + col;
-        const bool active = q < a.q.n;
-        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (active ? q : 0) * a.q.stride) * a.q.d;
+        const bool active = q < a.q.n && ((gmask >> col) & 1u);
+        const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + (q < a.q.n ? q : 0) * a.q.stride) * a.q.d;
         float xq[H];
         bf16x8 bh[BF ? H / 8 : 1], bl[BF3 ? H / 8 : 1];
         bool ok;
@@ -801,7 +805,12 @@ __global__ __launch_bounds__(256) void mfma_assign1_kernel(DistArgs a) {
                 need = !(ub < (float)kTieMargin);
             }
         }
-        append_rows(need, q, a.refine_count, a.refine_list);
+        if (a.gate_mode == 1) {   // BF16 pass of the cascade: mark, do not list
+            const uint32_t mk = (uint32_t)(__ballot(need) & 0xffffffffull);
+            if (lane == 0) a.gate[grp] = mk;
+        } else {
+            append_rows(need, q, a.refine_count, a.refine_list);
+        }
     }
 }
 
@@ -978,7 +987,16 @@ kkm_status launch_dist_mfma(const DistArgs& a, const DeviceInfo& dev, hipStream_
     }
     if (a.sup.medoid_form && !a.Dt && !a.colmin && !a.Erow) {
         if (a.precision == KKM_PREC_BF16X3) return launch_assign1<kPmBf16x3>(a, dev, s);
-        if (a.precision == KKM_PREC_BF16) return launch_assign1<kPmBf16>(a, dev, s);
+        if (a.precision == KKM_PREC_BF16) {
+            if (!a.gate || !a.sup.lo) return launch_assign1<kPmBf16>(a, dev, s);
+            // the cascade: BF16 marks its undecided rows, BF16x3 re-decides them and lists for FP64
+            // the rows it cannot decide either
+            DistArgs b = a;
+            b.gate_mode = 1;
+            KKM_TRY(launch_assign1<kPmBf16>(b, dev, s));
+            b.gate_mode = 2;
+            return launch_assign1<kPmBf16x3>(b, dev, s);
+        }
         return launch_assign1<kPmF32>(a, dev, s);
     }
     if (a.precision == KKM_PREC_BF16X3) return launch_mfma_t<float, kPmBf16x3>(a, dev, s);

@@ -127,6 +127,11 @@ struct DistArgs {
     double* r2gq;           // [rmsd_chunk * 32] G = sum of squared coordinates of each query frame
     int64_t rmsd_chunk;     // query groups per chunk
     int64_t grp0, grp_n;    // the chunk being reduced (set by the launcher)
+    // Plain BF16 assign against a medoid model: the BF16 pass marks the rows it cannot decide in one
+    // 32-bit word per group of 32 rows (no list, no atomics), BF16x3 re-decides the marked rows and
+    // lists for FP64 those it cannot decide either
+    uint32_t* gate;         // [ceil(n / 32)], or null (BF16 rows straight to FP64)
+    int32_t gate_mode;      // 0 none, 1 write the marks (BF16 pass), 2 read them (BF16x3 pass)
 };
 // Query groups per chunk of the RMSD pair pass: its buffer of squared RMSDs stays under cap_bytes.
 inline int64_t rmsd_chunk_groups(int64_t n, int64_t n_support, size_t cap_bytes) {

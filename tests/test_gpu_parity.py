@@ -91,6 +91,35 @@ def test_assign_medoid_model(kind, sigma, d, C, n, prec, dtype):
     assert abs(cost - want) <= COST_TOL[prec] * max(1.0, abs(want))
 
 
+def test_assign_bf16_cascade_near_duplicate_medoids():
+    """Plain BF16 against medoids in near-duplicate pairs: the one-product pass cannot tell a pair apart,
+    so it marks most rows (every group, the last one ragged) and the compensated products decide them
+    again; the labels must still be the oracle's wherever its margin exceeds the tie bar."""
+    kk = _kk()
+    _say("assign bf16 cascade near-duplicate medoids")
+    d, P, n = 64, 20, 3000 + 13
+    X, _ = ki.datasets.gaussian_mixture(n + P, d, P, seed=321, sigma=1.0, dtype=np.float32)
+    base, Y = X[:P].astype(np.float64), X[P:]
+    rng = np.random.default_rng(7)
+    twin = base + 0.02 * rng.standard_normal(base.shape)
+    rows = np.empty((2 * P, d), dtype=np.float32)
+    rows[0::2], rows[1::2] = base, twin
+    kern = Kernel("rbf", 8.0)
+    m = _medoid_model_from_rows(kk, kern, rows, "f32")
+    Yd = torch.from_numpy(np.ascontiguousarray(Y)).cuda()
+    model = okkm.SparseModel(rows.astype(np.float64), np.arange(2 * P + 1), np.ones(2 * P))
+    rl, rg, _ = okkm.assign(kern, Y, model)
+    # (the oracle's margins: most rows sit between the two medoids of a pair, far inside the BF16 bound)
+    assert np.median(rg) < 1e-2, np.median(rg)
+    for prec in ("bf16", "bf16x3", "fp32"):
+        lab = kk.kkm_assign(m, Yd, precision=prec)
+        torch.cuda.synchronize()
+        _labels_match(lab.cpu().numpy(), rl, rg, f"assign {prec}")
+    cost = kk.kkm_cost(m, Yd, precision="bf16")
+    want = okkm.cost(kern, Y, model)
+    assert abs(cost - want) <= COST_TOL["bf16"] * max(1.0, abs(want))
+
+
 def test_assign_sparse_centroids():
     """General sparse centroids: several support rows per cluster, unequal coefficients, an empty cluster."""
     kk = _kk()
