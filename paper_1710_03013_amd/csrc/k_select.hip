@@ -841,7 +841,8 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
     doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
     const int q4 = lane >> 4, c16 = lane & 15;
     const int ta = 4 * (c16 & 3) + (c16 >> 2);   // the target of A-operand row c16
-#pragma unroll 4
+    // (fully unrolled: a loop would move the accumulators between register files every iteration)
+#pragma unroll
     for (int s = 0; s < DP / 4; ++s) {
         const int k = 4 * s + q4;
         const double xv = (double)Xs[k][16 * wave + c16];
