@@ -170,20 +170,24 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
         }
         __syncthreads();
     }
-    // otherwise one distinct label at a time
+    // otherwise every lane compares its label with the chunk's 64 labels (read one at a time from the
+    // lanes): the equal ones below it are its rank, all equal ones the label's count, which the
+    // label's first lane stores (a fixed 64 steps, where a loop over the distinct labels took up
+    // to 64 dependent ballot rounds)
     for (int ch = wave; C > 64 && ch < nchunks; ch += nwaves) {
         const int m = ch * 64 + lane;
         const bool valid = m < ell;
         const int lab = valid ? L.lbl[m] : -1;
-        uint64_t remaining = __ballot(valid);
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        while (remaining) {
-            const int leader = __ffsll((unsigned long long)remaining) - 1;
-            const int cur = __builtin_amdgcn_readlane(lab, leader);
-            const uint64_t mask = __ballot(valid && lab == cur);
-            if (valid && lab == cur) L.rank[m] = (uint8_t)__popcll(mask & below);
-            if (lane == 0) L.chunk[ch * C + cur] = (uint16_t)__popcll(mask);
-            remaining &= ~mask;
+        int rk = 0, ct = 0;
+#pragma unroll 16
+        for (int k = 0; k < 64; ++k) {
+            const int eq = __builtin_amdgcn_readlane(lab, k) == lab;
+            ct += eq;
+            rk += eq & (k < lane);
+        }
+        if (valid) {
+            L.rank[m] = (uint8_t)rk;
+            if (rk == 0) L.chunk[ch * C + lab] = (uint16_t)ct;
         }
     }
     __syncthreads();

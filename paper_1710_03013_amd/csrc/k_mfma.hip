@@ -319,8 +319,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }   // tiles
 }
 
+// (eight wavefronts per workgroup run on small grids: two such workgroups per CU need four wavefronts
+// per SIMD, i.e. at most 128 registers)
 template <typename TI, int DP, int PM, int NW>
-__global__ __launch_bounds__(NW * 64) void mfma_dist_kernel(DistArgs a) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 && DP <= 64 ? 4 : 1)))
+void mfma_dist_kernel(DistArgs a) {
     constexpr bool RM = PM == kPmRmsd;        // RMSD frames
     constexpr bool BF = PM == kPmBf16 || PM == kPmBf16x3;   // bfloat16 operands
     constexpr bool BF3 = PM == kPmBf16x3;     // with the remainder products
