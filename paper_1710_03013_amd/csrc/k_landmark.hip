@@ -721,12 +721,22 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         stamp(a, ns);
         grid_barrier(a, target);
         stamp(a, ns);
-        // nsub interleaved sub-sums per cluster, then in order
+        // nsub interleaved sub-sums per cluster, then in order (each sub-sum's loads, up to eight at a
+        // time, are issued before they are added in workgroup order)
         for (int p = tid; p < nsub * C; p += nt) {
             const int j = p % C, sub = p / C;
             double acc = 0.0;
-#pragma unroll 4
-            for (int g = sub; g < G; g += nsub) acc += xget(a.partial + (int64_t)g * C + j);
+            for (int g0 = sub; g0 < G; g0 += 8 * nsub) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int g = g0 + u * nsub;
+                    v[u] = g < G ? xget(a.partial + (int64_t)g * C + j) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (g0 + u * nsub < G) acc += v[u];
+            }
             L.red[p] = acc;
         }
         __syncthreads();
