@@ -143,51 +143,27 @@ __device__ __forceinline__ void csr_sort(const LdsLayout& L, int ell, int C) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
     const int nchunks = (ell + 63) / 64;
-    if (C > 64) {
-        for (int i = tid; i < nchunks * C; i += nt) L.chunk[i] = 0;
-        __syncthreads();
-    }
-    // ranks inside each 64-landmark chunk
-    if (C <= 64) {
-        // few clusters: every label in turn over the wave's chunk (one ballot per label); the rank
-        // is selected in a register and lane j keeps the count of label j, so the label loop has no
-        // branches; both are stored once
-        for (int ch = wave; ch < nchunks; ch += nwaves) {
-            const int m = ch * 64 + lane;
-            const int lab = m < ell ? L.lbl[m] : -1;
-            int rk = 0, ct = 0;
-            for (int j = 0; j < C; ++j) {
-                const bool hit = lab == j;
-                const uint64_t mask = __ballot(hit);
-                // lanes below this one with label j
-                const int rb = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                rk = hit ? rb : rk;
-                ct = lane == j ? (int)__popcll(mask) : ct;
-            }
-            if (m < ell) L.rank[m] = (uint8_t)rk;
-            if (lane < C) L.chunk[ch * C + lane] = (uint16_t)ct;
-        }
-        __syncthreads();
-    }
-    // otherwise every lane compares its label with the chunk's 64 labels (read one at a time from the
-    // lanes): the equal ones below it are its rank, all equal ones the label's count, which the
-    // label's first lane stores (a fixed 64 steps, where a loop over the distinct labels took up
-    // to 64 dependent ballot rounds)
-    for (int ch = wave; C > 64 && ch < nchunks; ch += nwaves) {
+    for (int i = tid; i < nchunks * C; i += nt) L.chunk[i] = 0;
+    __syncthreads();
+    // ranks inside each 64-landmark chunk: the lanes holding the same label are the AND, over the
+    // label's bits, of the ballot of that bit (or of its complement); the equal lanes below a lane
+    // are its rank, all of them the label's count in the chunk, which the label's first lane stores
+    const int nbits = C > 1 ? 32 - __builtin_clz((unsigned)(C - 1)) : 1;
+    for (int ch = wave; ch < nchunks; ch += nwaves) {
         const int m = ch * 64 + lane;
         const bool valid = m < ell;
-        const int lab = valid ? L.lbl[m] : -1;
-        int rk = 0, ct = 0;
-#pragma unroll 16
-        for (int k = 0; k < 64; ++k) {
-            const int eq = __builtin_amdgcn_readlane(lab, k) == lab;
-            ct += eq;
-            rk += eq & (k < lane);
+        const int lab = valid ? L.lbl[m] : 0;
+        uint64_t eq = __ballot(valid);
+        for (int bt = 0; bt < nbits; ++bt) {
+            const bool on = (lab >> bt) & 1;
+            const uint64_t bb = __ballot(valid && on);
+            eq &= on ? bb : ~bb;
         }
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const int rk = (int)__popcll(eq & below);
         if (valid) {
             L.rank[m] = (uint8_t)rk;
-            if (rk == 0) L.chunk[ch * C + lab] = (uint16_t)ct;
+            if (rk == 0) L.chunk[ch * C + lab] = (uint16_t)__popcll(eq);
         }
     }
     __syncthreads();
