@@ -979,15 +979,19 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
             a.ghat[j] = cnt > 0 ? L.gh[j] : kInf;
             a.segabs[j] = cnt > 0 ? 1.0 : 0.0;
         }
-        if (tid < 5) {
-            // contiguous cluster runs holding about a quarter of the support each (distance pass)
-            int j = 0;
-            if (tid == 4) j = C;
-            else if (tid > 0) {
-                const int want = (ell * tid + 3) / 4;
-                while (j < C && L.off[j] < want) ++j;
+        // contiguous cluster runs holding about a quarter of the support each (distance pass): split
+        // q (q = 1, 2, 3) is the first cluster j <= C with off[j] >= ceil(ell q / 4), found by the one
+        // thread j where the offsets cross it (they ascend)
+        if (tid == 0) {
+            a.split[0] = 0;
+            a.split[4] = C;
+        }
+        for (int j = tid; j <= C; j += nt) {
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                const int want = (ell * q + 3) / 4;
+                if ((j == C || L.off[j] >= want) && (j == 0 || L.off[j - 1] < want)) a.split[q] = j;
             }
-            a.split[tid] = j;
         }
         if (tid == 0) *a.updates_out = it;
         for (int m = tid; m < ell; m += nt) a.lab[ell + m] = L.lbl[m];   // final landmark labels
