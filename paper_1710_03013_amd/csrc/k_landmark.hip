@@ -876,12 +876,25 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 }
             }
             __syncthreads();
+            // (branch-free, eight changes per step with their reads issued first; a change that does
+            // not touch cluster j adds and subtracts exact zeros, so the sum is the one in change order)
             for (int j = tid; j < C; j += nt) {
                 double dt = 0.0;
-                for (int t = 0; t < nch; ++t) {
-                    const int ab = L.pab[t];
-                    if ((ab >> 16) == j) dt += 2.0 * L.psb[t] + L.pwb[t];
-                    if ((ab & 0xffff) == j) dt -= 2.0 * L.psa[t] + L.pwa[t];
+                for (int t0 = 0; t0 < nch; t0 += 8) {
+                    int ab[8];
+                    double vb[8], va[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int t = min(t0 + u, nch - 1);
+                        ab[u] = t0 + u < nch ? L.pab[t] : -1;
+                        vb[u] = 2.0 * L.psb[t] + L.pwb[t];
+                        va[u] = 2.0 * L.psa[t] + L.pwa[t];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        dt += (ab[u] >= 0 && (ab[u] >> 16) == j) ? vb[u] : 0.0;
+                        dt -= (ab[u] >= 0 && (ab[u] & 0xffff) == j) ? va[u] : 0.0;
+                    }
                 }
                 L.dT[j] = dt;
             }
