@@ -50,11 +50,11 @@ PEAK_BF16_MATRIX = 2.5e15     # published MI355X dense BF16 matrix-core FLOP/s
 # calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
 # and its SHA-1 prefix at measurement time: a changed kernel source reports null.
 TRAFFIC_MEASURED = {
-    ("mfma_dist_kernel", "mixture64"): (16.43e6, "k_mfma.hip", "20ae83a35e81"),
-    ("landmark_phase_kernel", "mixture64"): (2.95e6, "k_landmark.hip", "808051d9fa5e"),
-    ("mfma_assign1_kernel", "mixture64"): (260.20e6, "k_mfma.hip", "20ae83a35e81"),
-    ("rmsd_pairs_kernel+mfma_dist_kernel", "md"): (104.67e6, "k_mfma.hip", "20ae83a35e81"),
-    ("rmsd_pairs_kernel+mfma_assign1_kernel", "md"): (231.15e6, "k_mfma.hip", "20ae83a35e81"),
+    ("mfma_dist_kernel", "mixture64"): (16.41e6, "k_mfma.hip", "8b69f3b831be"),
+    ("landmark_phase_kernel", "mixture64"): (2.94e6, "k_landmark.hip", "e27c4726638a"),
+    ("mfma_assign1_kernel", "mixture64"): (260.20e6, "k_mfma.hip", "8b69f3b831be"),
+    ("rmsd_pairs_kernel+mfma_dist_kernel", "md"): (104.67e6, "k_mfma.hip", "8b69f3b831be"),
+    ("rmsd_pairs_kernel+mfma_assign1_kernel", "md"): (231.15e6, "k_mfma.hip", "8b69f3b831be"),
 }
 
 
