@@ -397,6 +397,121 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
     const int64_t ns = off[C];
     const TI* rows = static_cast<const TI*>(a.sup.rows);
     const int count = *a.refine_count;
+    auto merge = [](double& x1, double& x2, int& y1, double c1, double c2, int j1) {
+        if (c1 < x1 || (c1 == x1 && j1 < y1)) {
+            x2 = fmin(x1, c2);
+            x1 = c1;
+            y1 = j1;
+        } else {
+            x2 = fmin(x2, c1);
+        }
+    };
+    if constexpr (DP > 0 && DP * sizeof(TI) <= 256) {
+        // One pass holds the whole support (a support row per thread, a cluster per thread): the
+        // thread's support row, its coefficient and its cluster's segment bounds and self term are
+        // requested together with the listed row's index, before the listed row itself can be read.
+        // The sums are those of the general pass below, term for term.
+        if (ns <= kRefineThreads && C <= kRefineThreads) {
+            if ((int)blockIdx.x >= count) return;   // (uniform over the block)
+            const bool has = t < ns;
+            const int64_t ls = min<int64_t>(t, max<int64_t>(ns - 1, 0));
+            const TI* srow = rows + ls * a.sup.dpad;
+            const int d = (int)a.ks.d;
+            const int jc = min(t, C - 1);
+            const int nwc = (C + 63) / 64;   // wavefronts holding clusters
+            for (int i = blockIdx.x; i < count; i += gridDim.x) {
+                // (the listed row's index first: the wait for it then covers no other load)
+                const int64_t q = a.refine_list[i];
+                // (only the threads that own a support row load one: the block's loads pass
+                // through one CU, whose load bandwidth the whole support already takes)
+                TI y[DP];
+                if (has) {
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) y[k] = srow[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) y[k] = TI(0);
+                }
+                const double cf = a.sup.coef64[ls];
+                const int32_t olo = off[jc], ohi = off[jc + 1];
+                const double gself = a.sup.self[jc];
+                const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
+                if (t < DP) xs[t] = t < a.q.d ? (double)xr[t] : 0.0;
+                // dimensions past d: zero here and in the staged listed row, so that they add
+                // fma(0, 0, acc) = acc, as the masked terms of the general pass do
+                if (d < DP) {
+#pragma unroll
+                    for (int k = 0; k < DP; ++k) y[k] = k < d ? y[k] : TI(0);
+                }
+                __syncthreads();
+                if (has) {
+                    // (8 dimensions at a time: the compiler is kept from converting or reading ahead
+                    // the next part, so that the FP64 values do not crowd out the support row)
+                    constexpr int CH = DP < 8 ? DP : 8;
+                    double acc = 0.0;
+                    if (a.ks.type == KKM_KERNEL_LINEAR) {
+#pragma unroll
+                        for (int c0 = 0; c0 < DP; c0 += CH) {
+#pragma unroll
+                            for (int k = c0; k < c0 + CH; ++k) asm volatile("" : "+v"(y[k]) :: "memory");
+#pragma unroll
+                            for (int k = c0; k < c0 + CH; ++k) acc = fma(xs[k], (double)y[k], acc);
+                        }
+                    } else {
+#pragma unroll
+                        for (int c0 = 0; c0 < DP; c0 += CH) {
+#pragma unroll
+                            for (int k = c0; k < c0 + CH; ++k) asm volatile("" : "+v"(y[k]) :: "memory");
+#pragma unroll
+                            for (int k = c0; k < c0 + CH; ++k) {
+                                const double df = xs[k] - (double)y[k];
+                                acc = fma(df, df, acc);
+                            }
+                        }
+                        acc = ::exp(-acc * a.ks.inv2s2);
+                    }
+                    Kv[t] = cf * acc;
+                }
+                __syncthreads();
+                if (wave < nwc) {
+                    const double kqq = kself64(a.ks, xr);
+                    double b1 = kInf, b2 = kInf;
+                    int i1 = C;
+                    if (t < C) {
+                        double sj = 0.0;
+                        for (int l = olo; l < ohi; ++l) sj += Kv[l];
+                        const double D = (ohi > olo && gself < kInf) ? kqq - 2.0 * sj + gself : kInf;
+                        if (D < b1) {
+                            b1 = D;
+                            i1 = t;
+                        }
+                    }
+                    for (int o = 32; o >= 1; o >>= 1)
+                        merge(b1, b2, i1, __shfl_xor(b1, o, 64), __shfl_xor(b2, o, 64), __shfl_xor(i1, o, 64));
+                    if (lane == 0) {
+                        rb1[wave] = b1;
+                        rb2[wave] = b2;
+                        ri1[wave] = i1;
+                    }
+                }
+                __syncthreads();
+                if (t == 0) {
+                    const double kqq = kself64(a.ks, xr);
+                    double v1 = rb1[0], v2 = rb2[0];
+                    int j1 = ri1[0];
+                    for (int w = 1; w < nwc; ++w) merge(v1, v2, j1, rb1[w], rb2[w], ri1[w]);
+                    a.labels[q] = j1 < C ? j1 : 0;
+                    if (a.best) a.best[q] = v1;
+                    if (a.gap) {
+                        const double scale = fmax(fmax(fabs(v1), fabs(v2)), fabs(kqq));
+                        a.gap[q] = v2 < kInf ? (float)((v2 - v1) / (scale > 0 ? scale : 1.0)) : __builtin_huge_valf();
+                    }
+                }
+                __syncthreads();
+            }
+            return;
+        }
+    }
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         const int64_t q = a.refine_list[i];
         const TI* xr = static_cast<const TI*>(a.q.X) + (a.q.base + q * a.q.stride) * a.q.d;
@@ -434,15 +549,6 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
             if (D < b1) { b2 = b1; b1 = D; i1 = j; }
             else if (D < b2) { b2 = D; }
         }
-        auto merge = [](double& x1, double& x2, int& y1, double c1, double c2, int j1) {
-            if (c1 < x1 || (c1 == x1 && j1 < y1)) {
-                x2 = fmin(x1, c2);
-                x1 = c1;
-                y1 = j1;
-            } else {
-                x2 = fmin(x2, c1);
-            }
-        };
         for (int o = 32; o >= 1; o >>= 1)
             merge(b1, b2, i1, __shfl_xor(b1, o, 64), __shfl_xor(b2, o, 64), __shfl_xor(i1, o, 64));
         if (lane == 0) {

@@ -736,13 +736,20 @@ __global__ __launch_bounds__(256) void merge_tile_kernel(SelectArgs a) {
 // A-operand row i carries target 4(i%4) + i/4 of the half: lane l then holds targets 4(l/16) + v
 // for row 16w + l%16, i.e. both targets (m_j^i, m_j) of two clusters per half.  Norms are summed in a fixed order (strided parts, then the
 // parts in order), so the result does not depend on scheduling.
+//
+// The grid is one-dimensional, one workgroup per (row chunk, cluster group) tile, numbered chunk-major.
+// Consecutive workgroups are dealt to the eight XCDs in turn, so workgroup b takes tile
+// (b % 8) * per + b / 8 (per = tiles / 8, rounded up): the cluster groups of one row chunk then run on
+// one XCD and read the chunk's rows through one L2.  Targets are staged in LDS at the data's
+// precision (they are rows of X), which keeps a workgroup's LDS small enough for five per CU.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename TI, int DP, bool SETTLED>
 __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
     constexpr int NT = 2 * kMergeTJ;                 // 32 targets
     constexpr int XS = kMergeRows + 4;               // LDS row stride of the staged rows
-    __shared__ double Ts[DP][NT + 2];
+    static_assert(256 % DP == 0, "a thread's staged values share one dimension");
+    __shared__ TI Ts[DP][NT + 2];
     __shared__ TI Xs[DP][XS];
     __shared__ double part[4][kMergeRows];
     __shared__ double xn[kMergeRows], tn[NT];
@@ -751,21 +758,32 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
     __shared__ unsigned long long cmin[kMergeTJ];
     __shared__ int32_t cpos[kMergeTJ], cmem[kMergeTJ], cmed[kMergeTJ];
     __shared__ double calpha[kMergeTJ];
-    const int j0 = blockIdx.y * kMergeTJ, chunk = blockIdx.x;
+    const int ngrp = (a.C + kMergeTJ - 1) / kMergeTJ, ntile = a.mchunk * ngrp;
+    const int tile = (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3);
+    if (tile >= ntile) return;   // (padding of the grid to a multiple of eight)
+    const int chunk = tile / ngrp, j0 = (tile - chunk * ngrp) * kMergeTJ;
     const int d = a.b.d;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t row0 = (int64_t)chunk * kMergeRows;
     const int nrows = (int)min<int64_t>(kMergeRows, a.b.n - row0);
     // the block's rows, dimension-major (rows and dimensions past the end: zero).  Every load is issued
     // unconditionally (row and dimension clamped into range, the value masked afterwards), so that
-    // all of a thread's loads are in flight together.
-    constexpr int XPER = kMergeRows * DP / 256;
+    // all of a thread's loads are in flight together.  Value u of thread t is dimension t % DP of row
+    // t / DP + u * (256 / DP); the row addresses step by a uniform amount.
+    constexpr int XPER = kMergeRows * DP / 256, RPU = 256 / DP;
     static_assert(XPER * 256 == kMergeRows * DP, "row staging covers the block exactly");
     TI xv[XPER];
+    {
+        const int64_t rs = a.b.stride * a.b.d;   // elements between consecutive batch rows
+        const TI* xb = static_cast<const TI*>(a.b.X) + (a.b.base + row0 * a.b.stride) * a.b.d + min(t % DP, d - 1);
+        if (nrows == kMergeRows) {
+            const TI* xp = xb + (t / DP) * rs;
 #pragma unroll
-    for (int u = 0; u < XPER; ++u) {
-        const int p = t + 256 * u, r = p / DP, k = p - r * DP;
-        xv[u] = brow<TI>(a.b, row0 + min(r, nrows - 1))[min(k, d - 1)];
+            for (int u = 0; u < XPER; ++u) xv[u] = xp[(int64_t)(u * RPU) * rs];
+        } else {
+#pragma unroll
+            for (int u = 0; u < XPER; ++u) xv[u] = xb[(int64_t)min(t / DP + u * RPU, nrows - 1) * rs];
+        }
     }
     if constexpr (SETTLED) {
         if (t < kMergeTJ && j0 + t < a.C) {
@@ -788,15 +806,27 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
         constexpr int TPER = (DP * NT + 255) / 256;
         const int last = min(2 * a.C - 2 * j0, NT) - 1;   // the block's last target (clusters past C: zero)
         double tv[TPER];
+        if constexpr (DP * NT >= 256) {   // value u of thread t: dimension t % DP of target t / DP + u * (256 / DP)
+            const double* tb = a.tpan + ((int64_t)j0 * 2) * a.Mpad + t % DP;
+            if (last == NT - 1) {
+                const double* tp = tb + (t / DP) * a.Mpad;
 #pragma unroll
-        for (int u = 0; u < TPER; ++u) {
-            const int p = min(t + 256 * u, DP * NT - 1), tt = p / DP, k = p - tt * DP;
-            tv[u] = a.tpan[((int64_t)j0 * 2 + min(tt, last)) * a.Mpad + k];
+                for (int u = 0; u < TPER; ++u) tv[u] = tp[(int64_t)(u * RPU) * a.Mpad];
+            } else {
+#pragma unroll
+                for (int u = 0; u < TPER; ++u) tv[u] = tb[(int64_t)min(t / DP + u * RPU, last) * a.Mpad];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < TPER; ++u) {
+                const int p = min(t + 256 * u, DP * NT - 1), tt = p / DP, k = p - tt * DP;
+                tv[u] = a.tpan[((int64_t)j0 * 2 + min(tt, last)) * a.Mpad + k];
+            }
         }
 #pragma unroll
         for (int u = 0; u < TPER; ++u) {
             const int p = t + 256 * u, tt = p / DP, k = p - tt * DP;
-            if (p < DP * NT) Ts[k][tt] = tt <= last ? tv[u] : 0.0;
+            if (p < DP * NT) Ts[k][tt] = tt <= last ? (TI)tv[u] : TI(0);   // (exact: values of X)
         }
         if (t < NT) tn[t] = t <= last ? a.tnorm[(int64_t)j0 * 2 + t] : 0.0;
     } else {
@@ -808,7 +838,7 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
             const int mrow = j0 + jj < a.C ? max(cmed[jj], 0) : 0;
             const TI* src = med ? brow<TI>(a.b, mrow) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
             const bool on = j0 + jj < a.C && k < d && (med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0));
-            Ts[k][tt] = on ? (double)src[k] : 0.0;
+            Ts[k][tt] = on ? src[k] : TI(0);
         }
     }
 #pragma unroll
@@ -829,7 +859,7 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
         if constexpr (!SETTLED) {
             if (t < NT) {
                 double st = 0.0;
-                for (int k = 0; k < d; ++k) st = fma(Ts[k][t], Ts[k][t], st);
+                for (int k = 0; k < d; ++k) st = fma((double)Ts[k][t], (double)Ts[k][t], st);
                 tn[t] = st;
             }
         }
@@ -846,11 +876,12 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
     for (int s = 0; s < DP / 4; ++s) {
         const int k = 4 * s + q4;
         const double xv = (double)Xs[k][16 * wave + c16];
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[k][ta], xv, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[k][16 + ta], xv, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Ts[k][ta], xv, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)Ts[k][16 + ta], xv, acc1, 0, 0, 0);
     }
     // scores of the lane's four clusters for its row, then the wavefront's minimum per cluster over
-    // its 16 rows (lanes of one quarter), lowest position on equal scores
+    // its 16 rows (lanes of one quarter): the minimum value by a butterfly, then the lowest row
+    // holding it from a ballot of the lanes equal to it
     const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
     const int r = 16 * wave + c16;
     const double xx = xn[r];
@@ -863,7 +894,6 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
             const int t1 = 2 * jj;
             const double alpha = calpha[jj];
             double bv = kInf;
-            int32_t bi = INT32_MAX;
             if (alpha > 0.0 && r < nrows) {
                 double k1, k2 = 0.0;
                 if (lin) {
@@ -876,17 +906,14 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
                 double sc = (lin ? xx : 1.0) - 2.0 * alpha * k1;
                 if (alpha < 1.0) sc = sc - 2.0 * (1.0 - alpha) * k2;
                 bv = sc;
-                bi = r;
             }
+            double mv = bv;
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                const double v2 = __shfl_xor(bv, o, 64);
-                const int32_t i2 = __shfl_xor(bi, o, 64);
-                if (v2 < bv || (v2 == bv && i2 < bi)) {
-                    bv = v2;
-                    bi = i2;
-                }
-            }
+            for (int o = 1; o < 16; o <<= 1) mv = fmin(mv, __shfl_xor(mv, o, 64));
+            // (a NaN score never equals the minimum; a quarter without finite scores has no row)
+            const uint32_t eq = (uint32_t)(__ballot(bv == mv && mv < kInf) >> (16 * q4)) & 0xffffu;
+            const int32_t bi = eq ? 16 * wave + __builtin_ctz(eq) : INT32_MAX;
+            bv = mv;
             if (c16 == 0) {
                 wv[wave][jj] = bv;
                 wi[wave][jj] = bi;
@@ -1216,6 +1243,13 @@ bool merge_on_mfma() {
 int select_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kRowsPerBlock - 1) / kRowsPerBlock); }
 int merge_chunks(int64_t n) { return (int)std::max<int64_t>(1, (n + kMergeRows - 1) / kMergeRows); }
 
+// The matrix-core merge's one-dimensional grid: its (row chunk, cluster group) tiles, padded to a
+// multiple of the eight XCDs.
+static unsigned merge_mfma_blocks(int64_t n, int C) {
+    const int64_t tiles = (int64_t)merge_chunks(n) * ((C + kMergeTJ - 1) / kMergeTJ);
+    return (unsigned)(8 * ((tiles + 7) / 8));
+}
+
 kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& dev, hipStream_t s) {
     const dim3 grid(a0.nchunk, a0.C);
     SelectArgs a = a0;
@@ -1250,8 +1284,9 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
                 KKM_HIP(hipGetLastError());
             }
             if (merge_on_mfma() && (!settle_first || (a.tpan && a.tnorm))) {
-                if (settle_first) hipLaunchKernelGGL((merge_mfma_kernel<TI, DP, true>), tgrid, dim3(256), 0, s, a);
-                else hipLaunchKernelGGL((merge_mfma_kernel<TI, DP, false>), tgrid, dim3(256), 0, s, a);
+                const dim3 mgrid(merge_mfma_blocks(a.b.n, a.C));
+                if (settle_first) hipLaunchKernelGGL((merge_mfma_kernel<TI, DP, true>), mgrid, dim3(256), 0, s, a);
+                else hipLaunchKernelGGL((merge_mfma_kernel<TI, DP, false>), mgrid, dim3(256), 0, s, a);
             } else if (settle_first) {
                 hipLaunchKernelGGL((merge_tile_kernel<TI, DP, true>), tgrid, dim3(256), 0, s, a);
             } else {
