@@ -290,13 +290,13 @@ constexpr int kRowsPerBlock = 256;
 
 // Grid (row chunks) x (clusters): member counts per chunk, label scatter, and the candidates of the
 // block: rows with D - E <= U_j, where U_j is the minimum of the distance pass's per-block column
-// minima (every block reduces them itself; the minimum is exact in any order).  With EVAL the block
-// then evaluates its candidates in FP64,
+// minima (every block reduces them itself; the minimum is exact in any order).  The block then
+// evaluates its candidates in FP64,
 //   d(x, j) = K(x,x) - 2 sum_l a_l K(x, s_l) + self_j,
 // a group of lanes per candidate over the segment's support rows, and appends (row, cluster, value)
-// to the candidate list; without it (large grids, where the evaluation's registers would cost
-// occupancy) it appends (row, cluster) and candidate_eval_kernel follows.
-template <typename TD, typename TI, int DP, bool EVAL>
+// to the candidate list.  (Large grids, where the evaluation's registers would cost occupancy, take
+// medoid_candidates_multi_kernel and candidate_eval_kernel instead.)
+template <typename TD, typename TI, int DP>
 __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
     const int j = blockIdx.y, chunk = blockIdx.x;
     const int64_t q = (int64_t)chunk * kRowsPerBlock + threadIdx.x;
@@ -341,14 +341,6 @@ __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
         base = ncand ? atomicAdd(a.cand_count, ncand) : 0;
     }
     __syncthreads();
-    if constexpr (!EVAL) {
-        for (int c = threadIdx.x; c < ncand; c += blockDim.x)
-            if (base + c < a.cand_cap) {
-                a.cand_q[base + c] = cq[c];
-                a.cand_j[base + c] = j;
-            }
-        return;
-    }
     // groups of L lanes per candidate, L the power of two (<= 64) covering the segment, so that
     // short segments put several candidates on one wavefront
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -372,6 +364,80 @@ __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
             a.cand_v[base + c] = kself64(a.ks, x) - 2.0 * f + a.sup.self[j];
         }
     }
+}
+
+// The large-grid form of the candidate scan: a block takes JPB clusters of its row chunk, so that the
+// rows' labels and bounds are read once for all of them and the grid is JPB times smaller; per
+// cluster the same member counts, label scatter and candidates as above, appended as (row, cluster)
+// for candidate_eval_kernel.
+template <typename TD, int JPB>
+__global__ __launch_bounds__(256) void medoid_candidates_multi_kernel(SelectArgs a) {
+    static_assert(kRowsPerBlock == 256, "a row per thread");
+    const int jb = blockIdx.y * JPB, chunk = blockIdx.x;
+    const int64_t q = (int64_t)chunk * kRowsPerBlock + threadIdx.x;
+    const bool active = q < a.b.n;
+    __shared__ int cnt[JPB], ncand, base;
+    __shared__ int32_t cq[JPB * kRowsPerBlock], cj[JPB * kRowsPerBlock];
+    __shared__ double umin[JPB][kRowsPerBlock / 64];
+    if (threadIdx.x < JPB) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) ncand = 0;
+    // the row's label, bound and distances are loaded first: their loads overlap the column minima
+    const int64_t qa = active ? q : 0;
+    const TD* Dt = static_cast<const TD*>(static_cast<const void*>(a.Dt));
+    const int lab = a.labels[qa];
+    const double Eq = (double)a.Erow[qa];
+    double D[JPB], U[JPB];
+#pragma unroll
+    for (int jj = 0; jj < JPB; ++jj) D[jj] = (double)Dt[(int64_t)min(jb + jj, a.C - 1) * a.ldD + qa];
+    if (a.colpart_blocks > 0) {
+        double v[JPB];
+#pragma unroll
+        for (int jj = 0; jj < JPB; ++jj) v[jj] = kInf;
+        for (int64_t b = threadIdx.x; b < a.colpart_blocks; b += blockDim.x)
+#pragma unroll
+            for (int jj = 0; jj < JPB; ++jj) v[jj] = fmin(v[jj], a.colpart[(int64_t)min(jb + jj, a.C - 1) * a.colpart_ld + b]);
+#pragma unroll
+        for (int jj = 0; jj < JPB; ++jj) {
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v[jj] = fmin(v[jj], __shfl_xor(v[jj], o, 64));
+            if ((threadIdx.x & 63) == 0) umin[jj][threadIdx.x >> 6] = v[jj];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < JPB; ++jj) {
+            double w = umin[jj][0];
+            for (int i = 1; i < (int)(blockDim.x >> 6); ++i) w = fmin(w, umin[jj][i]);
+            U[jj] = w < kInf ? w : ord_dec(~0ull);
+        }
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < JPB; ++jj) U[jj] = ord_dec(a.colmin[min(jb + jj, a.C - 1)]);
+    }
+    if (active) {
+        if (jb == 0 && a.label_out) a.label_out[a.b.base + q * a.b.stride] = lab;
+#pragma unroll
+        for (int jj = 0; jj < JPB; ++jj) {
+            const int j = jb + jj;
+            if (j < a.C) {
+                if (lab == j) atomicAdd(&cnt[jj], 1);
+                if (D[jj] < kInf && D[jj] - Eq <= U[jj]) {
+                    const int c = atomicAdd(&ncand, 1);
+                    cq[c] = (int32_t)q;
+                    cj[c] = j;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < JPB && jb + (int)threadIdx.x < a.C) a.mpart_c[(int64_t)(jb + threadIdx.x) * a.nchunk + chunk] = cnt[threadIdx.x];
+    if (threadIdx.x == 0) base = ncand ? atomicAdd(a.cand_count, ncand) : 0;
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncand; c += blockDim.x)
+        if (base + c < a.cand_cap) {
+            a.cand_q[base + c] = cq[c];
+            a.cand_j[base + c] = cj[c];
+        }
 }
 
 // One wavefront per listed candidate (the large-grid path): d(x, j) as above.
@@ -476,6 +542,21 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
         cpos[threadIdx.x] = INT32_MAX;
         cmem[threadIdx.x] = 0;
     }
+    // member counts: the 16 threads of cluster jj = t / 16 sum its chunk partials k = t % 16, t % 16
+    // + 16, ... (integers: exact in any order), then across the 16 threads.  The first four
+    // partials of each thread are requested before the candidate count, so that the reads overlap.
+    static_assert(kMergeTJ * 16 == 256, "16 threads per cluster");
+    const int mjj = (int)threadIdx.x >> 4, msub = (int)threadIdx.x & 15;
+    const bool mon = j0 + mjj < a.C;
+    const int32_t* mp = a.mpart_c + (int64_t)min(j0 + mjj, a.C - 1) * a.nchunk;
+    int32_t msum = 0;
+    {
+        int32_t c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = mp[min(msub + 16 * u, a.nchunk - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) msum += (mon && msub + 16 * u < a.nchunk) ? c[u] : 0;
+    }
     __syncthreads();
     const int count = min(*a.cand_count, a.cand_cap);
     for (int i = threadIdx.x; i < count; i += blockDim.x) {
@@ -483,24 +564,16 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
         const double v = a.cand_v[i];
         if (jj >= 0 && jj < kMergeTJ && !isnan(v)) atomicMin(&cmin[jj], ord_enc(v + 0.0));   // -0 counts as +0
     }
-    // member-count partials, four per thread at a time (indices clamped, values masked), so
-    // their loads are in flight together
-    const int npart = kMergeTJ * a.nchunk;
-    for (int p0 = threadIdx.x; p0 < npart; p0 += 4 * (int)blockDim.x) {
+    for (int k0 = msub + 64; k0 < a.nchunk; k0 += 64) {
         int32_t c[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int p = min(p0 + u * (int)blockDim.x, npart - 1);
-            const int jj = p / a.nchunk, k = p - jj * a.nchunk;
-            c[u] = a.mpart_c[(int64_t)min(j0 + jj, a.C - 1) * a.nchunk + k];
-        }
+        for (int u = 0; u < 4; ++u) c[u] = mp[min(k0 + 16 * u, a.nchunk - 1)];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int p = p0 + u * (int)blockDim.x;
-            const int jj = p / a.nchunk;
-            if (p < npart && j0 + jj < a.C && c[u]) atomicAdd(&cmem[jj], c[u]);
-        }
+        for (int u = 0; u < 4; ++u) msum += (mon && k0 + 16 * u < a.nchunk) ? c[u] : 0;
     }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) msum += __shfl_xor(msum, o, 64);
+    if (msub == 0) cmem[mjj] = msum;
     __syncthreads();
     for (int i = threadIdx.x; i < count; i += blockDim.x) {
         const int jj = a.cand_j[i] - j0;
@@ -546,23 +619,36 @@ __global__ __launch_bounds__(256) void merge_settle_kernel(SelectArgs a) {
         // summed over eight strided parts, then the parts in order
         constexpr int NT = 2 * kMergeTJ, TPER = (DP * NT + 255) / 256;
         __shared__ double part[8][NT];
+        __shared__ const TI* tsrc[NT];   // the targets' rows (nullptr: the target is not used)
         const int d = a.b.d, t = threadIdx.x;
         const int last = min(2 * a.C - 2 * j0, NT) - 1;
+        if (t < NT) {
+            const int tt = min(t, last), jj = tt / 2, j = j0 + jj;
+            const bool med = (tt & 1) == 0;
+            const double alpha = calpha[jj];
+            const bool on = med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0);
+            tsrc[t] = !on ? nullptr : med ? brow<TI>(a.b, max(cmed[jj], 0)) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+        }
+        __syncthreads();
         double tv[TPER];
 #pragma unroll
         for (int u = 0; u < TPER; ++u) {
             const int p = min(t + 256 * u, DP * NT - 1), tt = min(p / DP, last), k = p % DP;
-            const int jj = tt / 2, j = j0 + jj;
-            const bool med = (tt & 1) == 0;
-            const TI* src = med ? brow<TI>(a.b, max(cmed[jj], 0)) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
-            const double alpha = calpha[jj];
-            const bool on = k < d && (med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0));
-            tv[u] = on ? (double)src[min(k, d - 1)] : 0.0;
+            const TI* src = tsrc[tt];
+            tv[u] = src && k < d ? (double)src[min(k, d - 1)] : 0.0;
         }
+        // (value u of thread t is dimension t % DP of target t / DP + u * (256 / DP) when the block
+        // covers 256 values at a time: the panel address steps by a uniform amount)
+        double* tp = a.tpan + ((int64_t)j0 * 2) * a.Mpad;
 #pragma unroll
         for (int u = 0; u < TPER; ++u) {
             const int p = t + 256 * u, tt = p / DP, k = p % DP;
-            if (p < DP * NT && tt <= last) a.tpan[((int64_t)j0 * 2 + tt) * a.Mpad + k] = tv[u];
+            if constexpr (DP * NT >= 256) {
+                if (tt <= last) tp[(t / DP) * a.Mpad + k] = tv[u];
+                tp += (256 / DP) * a.Mpad;
+            } else {
+                if (p < DP * NT && tt <= last) a.tpan[((int64_t)j0 * 2 + tt) * a.Mpad + k] = tv[u];
+            }
         }
         __shared__ double tl[NT][DP + 1];
 #pragma unroll
@@ -769,20 +855,20 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
     // the block's rows, dimension-major (rows and dimensions past the end: zero).  Every load is issued
     // unconditionally (row and dimension clamped into range, the value masked afterwards), so that
     // all of a thread's loads are in flight together.  Value u of thread t is dimension t % DP of row
-    // t / DP + u * (256 / DP); the row addresses step by a uniform amount.
+    // t / DP + u * (256 / DP): the address steps by a uniform amount (rows past the end read the last
+    // row), with no multiplication per load.
     constexpr int XPER = kMergeRows * DP / 256, RPU = 256 / DP;
     static_assert(XPER * 256 == kMergeRows * DP, "row staging covers the block exactly");
     TI xv[XPER];
     {
         const int64_t rs = a.b.stride * a.b.d;   // elements between consecutive batch rows
         const TI* xb = static_cast<const TI*>(a.b.X) + (a.b.base + row0 * a.b.stride) * a.b.d + min(t % DP, d - 1);
-        if (nrows == kMergeRows) {
-            const TI* xp = xb + (t / DP) * rs;
+        const TI* xlast = xb + (int64_t)(nrows - 1) * rs;
+        const TI* xp = xb + (int64_t)(t / DP) * rs;
 #pragma unroll
-            for (int u = 0; u < XPER; ++u) xv[u] = xp[(int64_t)(u * RPU) * rs];
-        } else {
-#pragma unroll
-            for (int u = 0; u < XPER; ++u) xv[u] = xb[(int64_t)min(t / DP + u * RPU, nrows - 1) * rs];
+        for (int u = 0; u < XPER; ++u) {
+            xv[u] = *(t / DP + u * RPU < nrows ? xp : xlast);
+            xp += RPU * rs;
         }
     }
     if constexpr (SETTLED) {
@@ -808,13 +894,12 @@ __global__ __launch_bounds__(256) void merge_mfma_kernel(SelectArgs a) {
         double tv[TPER];
         if constexpr (DP * NT >= 256) {   // value u of thread t: dimension t % DP of target t / DP + u * (256 / DP)
             const double* tb = a.tpan + ((int64_t)j0 * 2) * a.Mpad + t % DP;
-            if (last == NT - 1) {
-                const double* tp = tb + (t / DP) * a.Mpad;
+            const double* tlast = tb + (int64_t)last * a.Mpad;
+            const double* tp = tb + (int64_t)(t / DP) * a.Mpad;
 #pragma unroll
-                for (int u = 0; u < TPER; ++u) tv[u] = tp[(int64_t)(u * RPU) * a.Mpad];
-            } else {
-#pragma unroll
-                for (int u = 0; u < TPER; ++u) tv[u] = tb[(int64_t)min(t / DP + u * RPU, last) * a.Mpad];
+            for (int u = 0; u < TPER; ++u) {
+                tv[u] = *(t / DP + u * RPU <= last ? tp : tlast);
+                tp += RPU * a.Mpad;
             }
         } else {
 #pragma unroll
@@ -947,9 +1032,10 @@ __global__ __launch_bounds__(64) void merge_final_kernel(SelectArgs a) {
     if (alpha > 0.0 && med >= 0) {
         double bv = kInf;
         int64_t bi = INT64_MAX;
-        for (int c = lane; c < a.mchunk; c += 64) {
+        for (int c = lane; c < a.mchunk; c += 64) {   // (index and value loaded together)
             const int32_t i = a.gpart_i[(int64_t)j * a.mchunk + c];
-            if (i >= 0) vmin(bv, bi, a.gpart_v[(int64_t)j * a.mchunk + c], i);
+            const double v = a.gpart_v[(int64_t)j * a.mchunk + c];
+            if (i >= 0) vmin(bv, bi, v, i);
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -1260,11 +1346,13 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
         // for a separate pass (the evaluation's registers would halve the large grid's occupancy)
         const bool fused = (int64_t)grid.x * grid.y <= 2048;
         if (fused) {
-            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP, true>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP, true>), grid, dim3(256), 0, s, a);
+            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP>), grid, dim3(256), 0, s, a);
         } else {
-            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP, false>), grid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP, false>), grid, dim3(256), 0, s, a);
+            constexpr int JPB = 4;
+            const dim3 mgrid(a.nchunk, (a.C + JPB - 1) / JPB);
+            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_multi_kernel<double, JPB>), mgrid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((medoid_candidates_multi_kernel<float, JPB>), mgrid, dim3(256), 0, s, a);
             KKM_HIP(hipGetLastError());
             // (candidates are typically a few per cluster: a wavefront each, far fewer workgroups than
             // the candidate scan)
