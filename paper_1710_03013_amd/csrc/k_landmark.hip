@@ -479,15 +479,27 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
         ma[u] = rowok[0][rr];
         mb[u] = rowok[1][rr];
     }
-    for (int k0 = 0; k0 < DP; k0 += CH) {
+    // every stage's values are requested before the first is used (kept at the data's precision
+    // until their stage), so that the stages wait for one round of loads instead of one each
+    constexpr int NS = DP / CH;
+    TI ra[NS][PER], rb[NS][PER];
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int dc = min(st * CH + kk[u], d - 1);
+            ra[st][u] = pa[u][dc];
+            rb[st][u] = pb[u][dc];
+        }
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+        const int k0 = st * CH;
         double va[PER], vb[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int dim = k0 + kk[u];
-            const int dc = min(dim, d - 1);
-            const double in = dim < d ? 1.0 : 0.0;
-            va[u] = (double)pa[u][dc] * (ma[u] * in);
-            vb[u] = (double)pb[u][dc] * (mb[u] * in);
+            const double in = k0 + kk[u] < d ? 1.0 : 0.0;
+            va[u] = (double)ra[st][u] * (ma[u] * in);
+            vb[u] = (double)rb[st][u] * (mb[u] * in);
         }
         __syncthreads();
 #pragma unroll

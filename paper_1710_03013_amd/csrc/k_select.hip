@@ -440,7 +440,11 @@ __global__ __launch_bounds__(256) void medoid_candidates_multi_kernel(SelectArgs
         }
 }
 
-// One wavefront per listed candidate (the large-grid path): d(x, j) as above.
+// One wavefront per listed candidate (the large-grid path): d(x, j) as above.  Linear / RBF: each
+// support row of the segment is split over DP / 4 lanes, four dimensions each (one load of the
+// candidate's row and one of the support row per lane), the lane parts added by a butterfly in a
+// fixed order, and the rows' terms a_l K(x, s_l) added across the pass's rows by a butterfly and
+// pass after pass: FP64 up to the order of the roundings.  RMSD: a support row per lane.
 template <typename TI, int DP>
 __global__ __launch_bounds__(256) void candidate_eval_kernel(SelectArgs a) {
     const int lane = threadIdx.x & 63;
@@ -452,10 +456,55 @@ __global__ __launch_bounds__(256) void candidate_eval_kernel(SelectArgs a) {
         const int j = a.cand_j[i];
         const TI* x = brow<TI>(a.b, q);
         const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
-        double f = 0.0;
-        for (int l = lo + lane; l < hi; l += 64) f += a.sup.coef64[l] * k64p<DP>(a.ks, x, rows + (int64_t)l * a.sup.dpad);
-        f = wave_sum(f);
-        if (lane == 0) a.cand_v[i] = kself64(a.ks, x) - 2.0 * f + a.sup.self[j];
+        const double sj = a.sup.self[j];
+        if constexpr (DP == 0) {
+            double f = 0.0;
+            for (int l = lo + lane; l < hi; l += 64) f += a.sup.coef64[l] * k64p<DP>(a.ks, x, rows + (int64_t)l * a.sup.dpad);
+            f = wave_sum(f);
+            if (lane == 0) a.cand_v[i] = kself64(a.ks, x) - 2.0 * f + sj;
+        } else {
+            constexpr int LPR = DP >= 4 ? DP / 4 : 1;   // lanes per support row
+            constexpr int RPP = 64 / LPR;               // support rows per pass
+            const int d = (int)a.ks.d;
+            const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
+            const int sub = lane % LPR, rr = lane / LPR, k0 = 4 * sub;
+            // the lane's four dimensions of the candidate (zero past d)
+            double xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xv[k] = k0 + k < d ? (double)x[min(k0 + k, d - 1)] : 0.0;
+            double xx = 0.0;   // linear: K(x, x) from the same lane parts
+            if (lin) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) xx = fma(xv[k], xv[k], xx);
+#pragma unroll
+                for (int o = 1; o < LPR; o <<= 1) xx += __shfl_xor(xx, o, 64);
+            }
+            double f = 0.0;
+            for (int l0 = lo; l0 < hi; l0 += RPP) {
+                const int l = l0 + rr;
+                const bool on = l < hi;
+                const TI* sr = rows + (int64_t)(on ? l : lo) * a.sup.dpad;
+                double p = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double y = k0 + k < d ? (double)sr[min(k0 + k, DP - 1)] : 0.0;
+                    if (lin) {
+                        p = fma(xv[k], y, p);
+                    } else {
+                        const double t = xv[k] - y;
+                        p = fma(t, t, p);
+                    }
+                }
+#pragma unroll
+                for (int o = 1; o < LPR; o <<= 1) p += __shfl_xor(p, o, 64);
+                const double kv = lin ? p : ::exp(-p * a.ks.inv2s2);
+                double term = on ? a.sup.coef64[on ? l : lo] * kv : 0.0;
+#pragma unroll
+                for (int o = LPR; o < 64; o <<= 1) term += __shfl_xor(term, o, 64);
+                f += term;
+            }
+            if (lane == 0) a.cand_v[i] = (lin ? xx : 1.0) - 2.0 * f + sj;
+        }
     }
 }
 
@@ -606,6 +655,7 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
 // TARGETS (linear / RBF: the matrix-core merge) the block also writes its clusters' targets -- target
 // 2 jj the batch medoid m_j^i, 2 jj + 1 the global medoid m_j, zero when the merge does not use it --
 // in FP64 to tpan[j][2][Mpad], and their squared norms (summed in order) to tnorm[j][2].
+
 template <typename TI, int DP, bool TARGETS>
 __global__ __launch_bounds__(256) void merge_settle_kernel(SelectArgs a) {
     __shared__ unsigned long long cmin[kMergeTJ];
@@ -1340,10 +1390,12 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
     const dim3 grid(a0.nchunk, a0.C);
     SelectArgs a = a0;
     const dim3 tgrid(merge_chunks(a.b.n), (a.C + kMergeTJ - 1) / kMergeTJ);
+    // (more than 1024 tile blocks: the merge settles the clusters once first)
+    const bool settle_first = (int64_t)tgrid.x * tgrid.y > 1024;
     auto run = [&]<typename TI, int DP>() -> kkm_status {
         a.mchunk = DP == 0 ? a.nchunk : merge_chunks(a.b.n);
         // candidates evaluated by the blocks that find them when the grid is small; otherwise listed
-        // for a separate pass (the evaluation's registers would halve the large grid's occupancy)
+        // for a later pass (the evaluation's registers would halve the large grid's occupancy)
         const bool fused = (int64_t)grid.x * grid.y <= 2048;
         if (fused) {
             if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP>), grid, dim3(256), 0, s, a);
@@ -1363,8 +1415,6 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
         if constexpr (DP == 0) {
             hipLaunchKernelGGL((merge_partial_kernel<TI, DP>), grid, dim3(256), 0, s, a);
         } else {
-            // (more than 1024 tile blocks: settle the clusters once first)
-            const bool settle_first = (int64_t)tgrid.x * tgrid.y > 1024;
             if (settle_first) {
                 if (merge_on_mfma() && a.tpan && a.tnorm)
                     hipLaunchKernelGGL((merge_settle_kernel<TI, DP, true>), dim3(tgrid.y), dim3(256), 0, s, a);

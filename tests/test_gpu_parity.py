@@ -304,6 +304,21 @@ def test_fit_gaussian_mixture(N, prec):
     np.testing.assert_allclose(info["partial_cost"], okkm.partial_costs(ref), rtol=COST_TOL[prec])
 
 
+def test_fit_listed_candidates_with_small_merge_grid():
+    """Selection forms by grid size: 5120 rows per batch and 150 clusters give a candidate scan of
+    20 row chunks x 150 clusters (beyond the form that evaluates its candidates in place, so they are
+    listed and evaluated by their own pass) but a merge of 80 x 10 tiles (small enough for every tile
+    to settle its clusters itself, without the separate settle pass)."""
+    kk = _kk()
+    _say("fit C=150, 5120 rows per batch")
+    X, _ = ki.datasets.gaussian_mixture(15360, 16, 150, seed=1501, sigma=1.0)
+    kern = Kernel("rbf", 4.0)
+    T = 20
+    model, labels, info, ref = _fit_both(kk, X, kern, 150, 3, 0.05, T, "kmeans++", 1502, "fp32")
+    _check_fit(kk, model, labels, info, ref, kern, X, T)   # oracle margins all above 1e-6 (5e-5 at least)
+    np.testing.assert_allclose(info["partial_cost"], okkm.partial_costs(ref), rtol=COST_TOL["fp32"])
+
+
 def _check_displacement(info, ref, kern, X, C, B, seed):
     """Medoid displacement per batch (Sec. 4.1 observable) against the oracle's definition, the
     medoids before batch 0 being the k-means++ picks of the same draws."""
