@@ -261,7 +261,7 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.uniforms = c.take<double>(C);
     w.chosen = c.take<int32_t>(C);
     w.D2 = c.take<double>(2 * P.nmax);
-    w.kpp_part = c.take<double>(2 * 256);
+    w.kpp_part = c.take<double>(3 * 256);
     w.M = c.take<char>((size_t)C * P.dpad * es);
     w.Mself = c.take<double>(C);
     w.Midx = c.take<int64_t>(C);
@@ -645,8 +645,8 @@ kkm_status fit_enqueue(const FitPlan& P, FitWs& w, const void* X, hipStream_t s,
     // batch-0 initialisation of the global medoids
     KKM_TRY(tm.begin(kPhInit));
     if (P.p.init == KKM_INIT_KMEANSPP) {
-        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.barrier,
-                                w.lm_error, dev, s, (P.p.flags & KKM_FIT_COOPERATIVE) != 0));
+        KKM_TRY(launch_kmeanspp(view(0), dtype, ks, C, w.uniforms, w.chosen, w.D2, w.kpp_part, w.lm_error, dev, s,
+                                (P.p.flags & KKM_FIT_COOPERATIVE) != 0));
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));
     } else if (P.p.init == KKM_INIT_MEDOIDS) {
         KKM_TRY(launch_set_medoids(view(0), dtype, ks, C, w.chosen, w.M, P.dpad, w.Mself, w.Midx, w.wcount, s));

@@ -455,13 +455,17 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     // to a real row and dimensions past d to the last one, the values scaled by a 0 / 1 mask -- so
     // the loads of a stage are in flight together instead of one branch and one wait each.  (Scaling
     // by 1 keeps every value bit for bit; masked entries add exact zeros.)
-    __shared__ const TI* rowp[2][T];
+    // (held as element offsets from X or M, not as pointers: a pointer read back from LDS would
+    // turn the element loads into flat ones)
+    __shared__ int64_t rowo[2][T];
+    __shared__ int rowm[2][T];
     __shared__ float rowok[2][T];
     if (threadIdx.x < 2 * T) {
         const int side = threadIdx.x / T, t = threadIdx.x - side * T;
         const int g = (side == 0 ? r0 : c0) + t;
         const bool cm = side == 1 && g >= mc0 && g < ncol;
-        rowp[side][t] = cm ? M + (int64_t)(g - mc0) * a.Mpad : X + (int64_t)a.lm[min(g, ell - 1)] * rs;
+        rowo[side][t] = cm ? (int64_t)(g - mc0) * a.Mpad : (int64_t)a.lm[min(g, ell - 1)] * rs;
+        rowm[side][t] = cm ? 1 : 0;
         rowok[side][t] = (g < ell || cm) ? 1.0f : 0.0f;
     }
     __syncthreads();
@@ -474,8 +478,8 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
         const int p = threadIdx.x + 256 * u;
         const int rr = p / CH;
         kk[u] = p - rr * CH;
-        pa[u] = rowp[0][rr];
-        pb[u] = rowp[1][rr];
+        pa[u] = X + rowo[0][rr];
+        pb[u] = (rowm[1][rr] ? M : X) + rowo[1][rr];
         ma[u] = rowok[0][rr];
         mb[u] = rowok[1][rr];
     }

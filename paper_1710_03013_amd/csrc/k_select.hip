@@ -55,11 +55,20 @@ __device__ void block_vmin(double& v, int64_t& i) {
 // ----------------------------------------------------------------------------- k-means++
 // Kernel k-means++ (Sec. 3.1) as one kernel whose workgroups are all resident: workgroup g owns the
 // contiguous rows [g R, (g + 1) R).  Pick k >= 1: every workgroup folds medoid k - 1 into its rows of
-// D^2 (D2 buffers alternate between picks), publishes its row sum, and after one grid barrier every
-// workgroup derives the same pick -- the owner chunk from the prefix of the G sums (in workgroup
-// order), then the row inside it by an ordered scan of that chunk.  The picked index is the first
-// row whose running sum exceeds u_k times the total (rows in index order; a pick with no mass falls
-// back to floor(u_k n)).
+// D^2 (D2 buffers alternate between picks), publishes its row sum, and once every sum of the pick is
+// there, every workgroup derives the same pick -- the owner chunk from the prefix of the G sums (in
+// workgroup order), then the row inside it by an ordered scan of that chunk.  The picked index is the
+// first row whose running sum exceeds u_k times the total (rows in index order; a pick with no mass
+// falls back to floor(u_k n)).
+//
+// The sums are their own signal: pick k uses buffer k % 3 of part, filled with -1 (sums are >= 0)
+// before the launch, and the readers wait until every slot of it holds a sum.  Workgroup g clears its
+// slot of buffer (k + 1) % 3 at the start of pick k, before publishing its pick-k sum: that buffer
+// was last read in pick k - 2, which every workgroup has finished once all pick k - 1 sums exist --
+// and g saw them all before starting pick k; a reader of pick k + 1 in turn waits for g's pick-k sum
+// first, so it cannot find the old value.  Only the owner workgroup searches its own rows for the
+// pick (its D^2 values are its own) and publishes it as chosen[k], filled with -1 before the launch;
+// the others wait for it.
 struct KppArgs {
     BatchView b;
     KSpec ks;
@@ -67,9 +76,8 @@ struct KppArgs {
     const double* uniforms;   // [C]
     int32_t* chosen;          // [C] out
     double* D2;               // [2][n]
-    double* part;             // [2][G]
-    unsigned* barrier;        // cleared before the launch
-    int32_t* error;           // set when a barrier wait exceeded its cap
+    double* part;             // [3][G], filled with -1 before the launch
+    int32_t* error;           // set when a wait exceeded its cap
     int32_t lds_rows;         // own rows staged in LDS (linear / RBF, when they fit)
 };
 
@@ -77,8 +85,8 @@ constexpr unsigned kKppSpinCap = 1u << 26;
 constexpr int kKppMaxGrid = 256;  // <= 256: one partial per thread in the owner search
 
 // The values exchanged between the workgroups (D^2 rows, per-workgroup sums) are written and read as
-// relaxed device-scope atomics, which pass the per-XCD L2 caches; the barrier then only waits for
-// every thread's stores to complete before one thread arrives (no L2 write-back or invalidation).
+// relaxed device-scope atomics, which pass the per-XCD L2 caches; a workgroup's sum is then published
+// only after every thread's stores have completed (no L2 write-back or invalidation).
 template <typename T>
 __device__ __forceinline__ void kput(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 template <typename T>
@@ -86,24 +94,34 @@ __device__ __forceinline__ T kget(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void kpp_barrier(const KppArgs& a, unsigned& target) {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);   // this thread's stores (the exchange stores among them) are done
-    __syncthreads();
-    target += gridDim.x;
+// Publishes the workgroup's sum of pick k (thread 0, which cleared the workgroup's slot for pick
+// k + 1 at the start of the pick: that store is complete first).
+__device__ __forceinline__ void kpp_publish(const KppArgs& a, int k, double gsum) {
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned polls = 0;
-        while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++polls > kKppSpinCap) {
-                atomicOr(a.error, 1);
-                break;
-            }
-        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        kput(a.part + (int64_t)(k % 3) * gridDim.x + blockIdx.x, gsum);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
-    __syncthreads();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Thread t < G: workgroup t's sum of pick k, once it is there (bounded wait; a wait past the cap
+// reports the error and goes on with what it read, never a hang).
+__device__ __forceinline__ double kpp_wait_sum(const KppArgs& a, int k) {
+    const int G = gridDim.x, t = threadIdx.x;
+    if (t >= G) return 0.0;
+    const double* p = a.part + (int64_t)(k % 3) * G + t;
+    double v = kget(p);
+    unsigned polls = 0;
+    while (v < 0.0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++polls > kKppSpinCap) {
+            atomicOr(a.error, 1);
+            break;
+        }
+        v = kget(p);
+    }
+    return v;
 }
 
 // Inclusive scan of one value per thread over the workgroup in a fixed order: within each wavefront
@@ -178,7 +196,6 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
         }
         __syncthreads();
     }
-    unsigned target = 0;
     int32_t prev = (int32_t)min<int64_t>((int64_t)floor(a.uniforms[0] * (double)n), n - 1);
     if (g == 0 && t == 0) a.chosen[0] = prev;
     for (int k = 1; k < a.C; ++k) {
@@ -186,21 +203,23 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
         double* D2 = a.D2 + (int64_t)cur * n;
         const double* D2o = a.D2 + (int64_t)old * n;
         // fold medoid k - 1 into the own rows; row sums in order (thread slice, then threads)
+        if (t == 0 && k + 1 < a.C) kput(a.part + (int64_t)((k + 1) % 3) * G + g, -1.0);   // (see above)
         const TI* m = row(prev);
-        if (lds_rows) {   // the medoid row, read once per pick into LDS (after the row of the own rows)
-            TI* ms = xs + R * XS;
+        // the medoid row, read once per pick into LDS (after the own rows); the evaluation below
+        // names it through the LDS array itself, so that its reads stay LDS reads
+        TI* const ms = xs + R * XS;
+        if (lds_rows) {
             for (int c = t; c < DP; c += nt) ms[c] = c < a.b.d ? m[c] : TI(0);
             __syncthreads();
-            m = ms;
         }
-        const double kmm = kself64(a.ks, m);
+        const double kmm = lds_rows ? kself64(a.ks, (const TI*)ms) : kself64(a.ks, m);
         double ts = 0.0;
         for (int64_t q = tlo; q < thi; ++q) {
             double v;
             if (lds_rows) {
                 if constexpr (DP > 0) {
                     const TI* x = xs + (q - lo) * XS;
-                    v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, m)) + kmm;
+                    v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, (const TI*)ms)) + kmm;
                 }
                 v = v > 0.0 ? v : 0.0;
                 if (k > 1) v = fmin(d2own[q - lo], v);
@@ -209,19 +228,18 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
                 const TI* x = row(q);
                 v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, m)) + kmm;
                 v = v > 0.0 ? v : 0.0;
-                if (k > 1) v = fmin(kget(D2o + q), v);
+                if (k > 1) v = fmin(D2o[q], v);
+                D2[q] = v;
             }
-            kput(D2 + q, v);
             ts += v;
         }
+        if (!lds_rows) __builtin_amdgcn_s_waitcnt(0);   // (the owner search below reads other threads' D^2)
         double e0, i0;
         const double gsum = block_scan(ts, sh, &e0, &i0);
-        if (t == 0) kput(a.part + (int64_t)cur * G + g, gsum);
-        kpp_barrier(a, target);
+        kpp_publish(a, k, gsum);
         // every workgroup derives the same pick: owner chunk from the partials, then the row
-        const double* P = a.part + (int64_t)cur * G;
         double pe, pi;
-        const double total = block_scan(t < G ? kget(P + t) : 0.0, sh, &pe, &pi);   // G <= 256
+        const double total = block_scan(kpp_wait_sum(a, k), sh, &pe, &pi);   // G <= 256
         const double u = a.uniforms[k];
         if (t == 0) {
             pick_sh = (int32_t)min<int64_t>((int64_t)floor(u * (double)n), n - 1);   // no mass: fallback
@@ -235,20 +253,18 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
         }
         __syncthreads();
         const int owner = owner_sh;
-        if (owner >= 0) {
-            int64_t olo, ohi, qlo, qhi;
-            chunk(owner, &olo, &ohi);
-            slice(olo, ohi, &qlo, &qhi);
+        if (owner == g) {   // the pick lies in this workgroup's rows: find it (rows in order) and publish it
+            auto d2 = [&](int64_t q) { return lds_rows ? d2own[q - lo] : (double)D2[q]; };
             double cs = 0.0;
-            for (int64_t q = qlo; q < qhi; ++q) cs += kget(D2 + q);
+            for (int64_t q = tlo; q < thi; ++q) cs += d2(q);
             double ce, ci;
             (void)block_scan(cs, sh, &ce, &ci);
             const double base = base_sh;
             if (base + ci > thr && base + ce <= thr) {   // at most one thread
                 double loc = base + ce;
-                int64_t pk = qhi - 1;
-                for (int64_t q = qlo; q < qhi; ++q) {
-                    loc += kget(D2 + q);
+                int64_t pk = thi - 1;
+                for (int64_t q = tlo; q < thi; ++q) {
+                    loc += d2(q);
                     if (loc > thr) {
                         pk = q;
                         break;
@@ -257,9 +273,27 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
                 pick_sh = (int32_t)pk;
             }
             __syncthreads();
+            if (t == 0) kput(a.chosen + k, pick_sh);   // (the fallback when rounding left no row)
+        } else if (owner >= 0) {   // wait for the owner's pick (bounded; past the cap: error reported)
+            if (t == 0) {
+                int32_t v = kget(a.chosen + k);
+                unsigned polls = 0;
+                while (v < 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++polls > kKppSpinCap) {
+                        atomicOr(a.error, 1);
+                        v = pick_sh;
+                        break;
+                    }
+                    v = kget(a.chosen + k);
+                }
+                pick_sh = v;
+            }
+            __syncthreads();
+        } else if (g == 0 && t == 0) {
+            kput(a.chosen + k, pick_sh);   // no mass: the fallback pick
         }
         prev = pick_sh;
-        if (g == 0 && t == 0) a.chosen[k] = prev;
         __syncthreads();
     }
 }
@@ -669,7 +703,9 @@ __global__ __launch_bounds__(256) void merge_settle_kernel(SelectArgs a) {
         // summed over eight strided parts, then the parts in order
         constexpr int NT = 2 * kMergeTJ, TPER = (DP * NT + 255) / 256;
         __shared__ double part[8][NT];
-        __shared__ const TI* tsrc[NT];   // the targets' rows (nullptr: the target is not used)
+        // the targets' rows as element offsets from X (m_j^i) or M (m_j), -1 when the target is not
+        // used (offsets rather than pointers: a pointer read back from LDS makes flat loads)
+        __shared__ int64_t toff[NT];
         const int d = a.b.d, t = threadIdx.x;
         const int last = min(2 * a.C - 2 * j0, NT) - 1;
         if (t < NT) {
@@ -677,15 +713,18 @@ __global__ __launch_bounds__(256) void merge_settle_kernel(SelectArgs a) {
             const bool med = (tt & 1) == 0;
             const double alpha = calpha[jj];
             const bool on = med ? alpha > 0.0 : (alpha > 0.0 && alpha < 1.0);
-            tsrc[t] = !on ? nullptr : med ? brow<TI>(a.b, max(cmed[jj], 0)) : static_cast<const TI*>(a.M) + (int64_t)j * a.Mpad;
+            toff[t] = !on ? -1 : med ? (a.b.base + (int64_t)max(cmed[jj], 0) * a.b.stride) * a.b.d : (int64_t)j * a.Mpad;
         }
         __syncthreads();
+        const TI* Xb = static_cast<const TI*>(a.b.X);
+        const TI* Mb = static_cast<const TI*>(a.M);
         double tv[TPER];
 #pragma unroll
         for (int u = 0; u < TPER; ++u) {
             const int p = min(t + 256 * u, DP * NT - 1), tt = min(p / DP, last), k = p % DP;
-            const TI* src = tsrc[tt];
-            tv[u] = src && k < d ? (double)src[min(k, d - 1)] : 0.0;
+            const int64_t o = toff[tt];
+            const TI* src = ((tt & 1) == 0 ? Xb : Mb) + (o < 0 ? 0 : o);
+            tv[u] = o >= 0 && k < d ? (double)src[min(k, d - 1)] : 0.0;
         }
         // (value u of thread t is dimension t % DP of target t / DP + u * (256 / DP) when the block
         // covers 256 values at a time: the panel address steps by a uniform amount)
@@ -1310,8 +1349,8 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
 }  // namespace
 
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
-                           int32_t* chosen, double* D2, double* part, unsigned* barrier, int32_t* error,
-                           const DeviceInfo& dev, hipStream_t s, bool cooperative) {
+                           int32_t* chosen, double* D2, double* part, int32_t* error, const DeviceInfo& dev,
+                           hipStream_t s, bool cooperative) {
     if (b.n <= 0) return fail(KKM_ERR_INVALID_ARG, "k-means++ on an empty batch");
     // workgroups: at least KKM_KPP_WGS (default 128) when the rows allow, more when that lets every
     // workgroup keep its rows in LDS; at most kKppMaxGrid and the CUs
@@ -1338,8 +1377,10 @@ kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C
             }
     }
     const size_t lds = lds_rows ? lds_for(G) : 0;
-    KppArgs a{b, ks, C, uniforms, chosen, D2, part, barrier, error, lds_rows ? 1 : 0};
-    KKM_TRY(launch_zero_i32(reinterpret_cast<int32_t*>(barrier), 1, s));
+    KppArgs a{b, ks, C, uniforms, chosen, D2, part, error, lds_rows ? 1 : 0};
+    // (the sums' buffers and the picks start empty: -1)
+    KKM_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(part), 3 * (int64_t)G, 0xBFF0000000000000ull, s));
+    KKM_TRY(launch_fill_i32(chosen, C, -1, s));
     return dispatch_dp(dp, [&]<int DP>() -> kkm_status {
         const void* fn = dtype == KKM_F64 ? reinterpret_cast<const void*>(&kmeanspp_kernel<double, DP>)
                                           : reinterpret_cast<const void*>(&kmeanspp_kernel<float, DP>);
@@ -1495,6 +1536,10 @@ kkm_status launch_add_i32(int32_t* dst, const int32_t* src, hipStream_t s) {
     return KKM_OK;
 }
 
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long long v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -1502,6 +1547,13 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 kkm_status launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
     if (n <= 0) return KKM_OK;
     hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)std::min<int64_t>(1024, nblocks(n, 256))), dim3(256), 0, s, p, n, v);
+    KKM_HIP(hipGetLastError());
+    return KKM_OK;
+}
+
+kkm_status launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return KKM_OK;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)std::min<int64_t>(1024, nblocks(n, 256))), dim3(256), 0, s, p, n, v);
     KKM_HIP(hipGetLastError());
     return KKM_OK;
 }

@@ -220,11 +220,11 @@ int merge_chunks(int64_t n);
 // tile_f64: the distance tile Dt holds doubles (FP64 precision) rather than floats.
 kkm_status launch_select(const SelectArgs& a, bool tile_f64, const DeviceInfo& dev, hipStream_t s);
 
-// k-means++ on a batch: uniforms[C] device, chosen[C] device out, D2 [2n] and part [512] scratch,
-// barrier / error as for the landmark loop (barrier cleared here).
+// k-means++ on a batch: uniforms[C] device, chosen[C] device out, D2 [2n] and part [768] scratch,
+// error as for the landmark loop.
 kkm_status launch_kmeanspp(const BatchView& b, int dtype, const KSpec& ks, int C, const double* uniforms,
-                           int32_t* chosen, double* D2, double* part, unsigned* barrier, int32_t* error,
-                           const DeviceInfo& dev, hipStream_t s, bool cooperative = false);
+                           int32_t* chosen, double* D2, double* part, int32_t* error, const DeviceInfo& dev,
+                           hipStream_t s, bool cooperative = false);
 // Global medoids <- batch rows `chosen` (valid, counts 0), or all unset when chosen == null.
 kkm_status launch_set_medoids(const BatchView& b, int dtype, const KSpec& ks, int C, const int32_t* chosen,
                               void* M, int64_t Mpad, double* Mself, int64_t* Midx, int64_t* wcount, hipStream_t s);
@@ -241,5 +241,6 @@ kkm_status launch_zero_i32(int32_t* p, int64_t n, hipStream_t s);
 kkm_status launch_add_i32(int32_t* dst, const int32_t* src, hipStream_t s);
 // Set n 64-bit words to v (a kernel, for the same reason).
 kkm_status launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+kkm_status launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 }  // namespace kkm
