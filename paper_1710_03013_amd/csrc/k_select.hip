@@ -400,11 +400,74 @@ __global__ __launch_bounds__(256) void medoid_candidates_kernel(SelectArgs a) {
     }
 }
 
+// d(x_q, j) as above by one wavefront (all 64 lanes take part; every lane returns the value).  Linear
+// / RBF: each support row of the segment is split over DP / 4 lanes, four dimensions each (one load of
+// the candidate's row and one of the support row per lane), the lane parts added by a butterfly in a
+// fixed order, and the rows' terms a_l K(x, s_l) added across the pass's rows by a butterfly and pass
+// after pass: FP64 up to the order of the roundings.  RMSD: a support row per lane.
+template <typename TI, int DP>
+__device__ __forceinline__ double eval_candidate_wave(const SelectArgs& a, int64_t q, int j) {
+    const int lane = threadIdx.x & 63;
+    const TI* rows = static_cast<const TI*>(a.sup.rows);
+    const TI* x = brow<TI>(a.b, q);
+    const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
+    const double sj = a.sup.self[j];
+    if constexpr (DP == 0) {
+        double f = 0.0;
+        for (int l = lo + lane; l < hi; l += 64) f += a.sup.coef64[l] * k64p<DP>(a.ks, x, rows + (int64_t)l * a.sup.dpad);
+        f = wave_sum(f);
+        return kself64(a.ks, x) - 2.0 * f + sj;
+    } else {
+        constexpr int LPR = DP >= 4 ? DP / 4 : 1;   // lanes per support row
+        constexpr int RPP = 64 / LPR;               // support rows per pass
+        const int d = (int)a.ks.d;
+        const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
+        const int sub = lane % LPR, rr = lane / LPR, k0 = 4 * sub;
+        // the lane's four dimensions of the candidate (zero past d)
+        double xv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) xv[k] = k0 + k < d ? (double)x[min(k0 + k, d - 1)] : 0.0;
+        double xx = 0.0;   // linear: K(x, x) from the same lane parts
+        if (lin) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) xx = fma(xv[k], xv[k], xx);
+#pragma unroll
+            for (int o = 1; o < LPR; o <<= 1) xx += __shfl_xor(xx, o, 64);
+        }
+        double f = 0.0;
+        for (int l0 = lo; l0 < hi; l0 += RPP) {
+            const int l = l0 + rr;
+            const bool on = l < hi;
+            const TI* sr = rows + (int64_t)(on ? l : lo) * a.sup.dpad;
+            double p = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double y = k0 + k < d ? (double)sr[min(k0 + k, DP - 1)] : 0.0;
+                if (lin) {
+                    p = fma(xv[k], y, p);
+                } else {
+                    const double t = xv[k] - y;
+                    p = fma(t, t, p);
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < LPR; o <<= 1) p += __shfl_xor(p, o, 64);
+            const double kv = lin ? p : ::exp(-p * a.ks.inv2s2);
+            double term = on ? a.sup.coef64[on ? l : lo] * kv : 0.0;
+#pragma unroll
+            for (int o = LPR; o < 64; o <<= 1) term += __shfl_xor(term, o, 64);
+            f += term;
+        }
+        return (lin ? xx : 1.0) - 2.0 * f + sj;
+    }
+}
+
 // The large-grid form of the candidate scan: a block takes JPB clusters of its row chunk, so that the
 // rows' labels and bounds are read once for all of them and the grid is JPB times smaller; per
 // cluster the same member counts, label scatter and candidates as above, appended as (row, cluster)
-// for candidate_eval_kernel.
-template <typename TD, int JPB>
+// and, for linear / RBF, evaluated by the block (a wavefront per candidate, eval_candidate_wave);
+// RMSD candidates are evaluated by candidate_eval_kernel.
+template <typename TD, typename TI, int DP, int JPB>
 __global__ __launch_bounds__(256) void medoid_candidates_multi_kernel(SelectArgs a) {
     static_assert(kRowsPerBlock == 256, "a row per thread");
     const int jb = blockIdx.y * JPB, chunk = blockIdx.x;
@@ -472,73 +535,24 @@ __global__ __launch_bounds__(256) void medoid_candidates_multi_kernel(SelectArgs
             a.cand_q[base + c] = cq[c];
             a.cand_j[base + c] = cj[c];
         }
+    if constexpr (DP > 0) {
+        const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+        for (int c = wave; c < ncand; c += nwaves) {   // (uniform over the wavefront)
+            if (base + c >= a.cand_cap) break;          // (beyond the capacity: the list is full)
+            const double v = eval_candidate_wave<TI, DP>(a, cq[c], cj[c]);
+            if ((threadIdx.x & 63) == 0) a.cand_v[base + c] = v;
+        }
+    }
 }
 
-// One wavefront per listed candidate (the large-grid path): d(x, j) as above.  Linear / RBF: each
-// support row of the segment is split over DP / 4 lanes, four dimensions each (one load of the
-// candidate's row and one of the support row per lane), the lane parts added by a butterfly in a
-// fixed order, and the rows' terms a_l K(x, s_l) added across the pass's rows by a butterfly and
-// pass after pass: FP64 up to the order of the roundings.  RMSD: a support row per lane.
+// One wavefront per listed candidate (the large-grid path, RMSD).
 template <typename TI, int DP>
 __global__ __launch_bounds__(256) void candidate_eval_kernel(SelectArgs a) {
-    const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * 4 + (threadIdx.x >> 6), nw = gridDim.x * 4;
     const int count = min(*a.cand_count, a.cand_cap);
-    const TI* rows = static_cast<const TI*>(a.sup.rows);
     for (int i = gw; i < count; i += nw) {
-        const int64_t q = a.cand_q[i];
-        const int j = a.cand_j[i];
-        const TI* x = brow<TI>(a.b, q);
-        const int lo = a.sup.offsets[j], hi = a.sup.offsets[j + 1];
-        const double sj = a.sup.self[j];
-        if constexpr (DP == 0) {
-            double f = 0.0;
-            for (int l = lo + lane; l < hi; l += 64) f += a.sup.coef64[l] * k64p<DP>(a.ks, x, rows + (int64_t)l * a.sup.dpad);
-            f = wave_sum(f);
-            if (lane == 0) a.cand_v[i] = kself64(a.ks, x) - 2.0 * f + sj;
-        } else {
-            constexpr int LPR = DP >= 4 ? DP / 4 : 1;   // lanes per support row
-            constexpr int RPP = 64 / LPR;               // support rows per pass
-            const int d = (int)a.ks.d;
-            const bool lin = a.ks.type == KKM_KERNEL_LINEAR;
-            const int sub = lane % LPR, rr = lane / LPR, k0 = 4 * sub;
-            // the lane's four dimensions of the candidate (zero past d)
-            double xv[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) xv[k] = k0 + k < d ? (double)x[min(k0 + k, d - 1)] : 0.0;
-            double xx = 0.0;   // linear: K(x, x) from the same lane parts
-            if (lin) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) xx = fma(xv[k], xv[k], xx);
-#pragma unroll
-                for (int o = 1; o < LPR; o <<= 1) xx += __shfl_xor(xx, o, 64);
-            }
-            double f = 0.0;
-            for (int l0 = lo; l0 < hi; l0 += RPP) {
-                const int l = l0 + rr;
-                const bool on = l < hi;
-                const TI* sr = rows + (int64_t)(on ? l : lo) * a.sup.dpad;
-                double p = 0.0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double y = k0 + k < d ? (double)sr[min(k0 + k, DP - 1)] : 0.0;
-                    if (lin) {
-                        p = fma(xv[k], y, p);
-                    } else {
-                        const double t = xv[k] - y;
-                        p = fma(t, t, p);
-                    }
-                }
-#pragma unroll
-                for (int o = 1; o < LPR; o <<= 1) p += __shfl_xor(p, o, 64);
-                const double kv = lin ? p : ::exp(-p * a.ks.inv2s2);
-                double term = on ? a.sup.coef64[on ? l : lo] * kv : 0.0;
-#pragma unroll
-                for (int o = LPR; o < 64; o <<= 1) term += __shfl_xor(term, o, 64);
-                f += term;
-            }
-            if (lane == 0) a.cand_v[i] = (lin ? xx : 1.0) - 2.0 * f + sj;
-        }
+        const double v = eval_candidate_wave<TI, DP>(a, a.cand_q[i], a.cand_j[i]);
+        if ((threadIdx.x & 63) == 0) a.cand_v[i] = v;
     }
 }
 
@@ -1442,15 +1456,17 @@ kkm_status launch_select(const SelectArgs& a0, bool tile_f64, const DeviceInfo& 
             if (tile_f64) hipLaunchKernelGGL((medoid_candidates_kernel<double, TI, DP>), grid, dim3(256), 0, s, a);
             else hipLaunchKernelGGL((medoid_candidates_kernel<float, TI, DP>), grid, dim3(256), 0, s, a);
         } else {
-            constexpr int JPB = 4;
+            // (five clusters a workgroup: with the evaluation's registers, seven workgroups per CU still
+            // hold the mixture64 grid of 79 x 20 at once)
+            constexpr int JPB = 5;
             const dim3 mgrid(a.nchunk, (a.C + JPB - 1) / JPB);
-            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_multi_kernel<double, JPB>), mgrid, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((medoid_candidates_multi_kernel<float, JPB>), mgrid, dim3(256), 0, s, a);
-            KKM_HIP(hipGetLastError());
-            // (candidates are typically a few per cluster: a wavefront each, far fewer workgroups than
-            // the candidate scan)
-            hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3((unsigned)std::max(1, dev.num_cus / 2)), dim3(256), 0, s,
-                               a);
+            if (tile_f64) hipLaunchKernelGGL((medoid_candidates_multi_kernel<double, TI, DP, JPB>), mgrid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((medoid_candidates_multi_kernel<float, TI, DP, JPB>), mgrid, dim3(256), 0, s, a);
+            if constexpr (DP == 0) {   // (RMSD candidates: a wavefront each, far fewer workgroups than the scan)
+                KKM_HIP(hipGetLastError());
+                hipLaunchKernelGGL((candidate_eval_kernel<TI, DP>), dim3((unsigned)std::max(1, dev.num_cus / 2)), dim3(256), 0,
+                                   s, a);
+            }
         }
         KKM_HIP(hipGetLastError());
         if constexpr (DP == 0) {
