@@ -218,8 +218,23 @@ __global__ __launch_bounds__(256) void kmeanspp_kernel(KppArgs a) {
             double v;
             if (lds_rows) {
                 if constexpr (DP > 0) {
+                    // both rows are zero past d in LDS, so the sum runs over DP dimensions with no
+                    // clamp or mask (the padded terms add fma(0, 0, acc) = acc, as the masked terms of
+                    // the general evaluator do), all reads in flight together
                     const TI* x = xs + (q - lo) * XS;
-                    v = (kself64(a.ks, x) - 2.0 * k64p<DP>(a.ks, x, (const TI*)ms)) + kmm;
+                    double acc = 0.0;
+                    if (a.ks.type == KKM_KERNEL_LINEAR) {
+#pragma unroll
+                        for (int k = 0; k < DP; ++k) acc = fma((double)x[k], (double)ms[k], acc);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < DP; ++k) {
+                            const double df = (double)x[k] - (double)ms[k];
+                            acc = fma(df, df, acc);
+                        }
+                        acc = ::exp(-acc * a.ks.inv2s2);
+                    }
+                    v = (kself64(a.ks, x) - 2.0 * acc) + kmm;
                 }
                 v = v > 0.0 ? v : 0.0;
                 if (k > 1) v = fmin(d2own[q - lo], v);
