@@ -341,8 +341,9 @@ __global__ __launch_bounds__(256) void refine_kernel(DistArgs a) {
     }
 }
 
-// A whole block per listed row (supports of hundreds of rows and more): 1024 threads, one support
-// row each per pass of up to kRefineChunk rows, so that every row's loads and exponential are in
+// A whole block per listed row (supports of hundreds of rows and more): 1024 threads (512 when the
+// support and the clusters number at most 512), one support row each per pass of up to kRefineChunk
+// rows, so that every row's loads and exponential are in
 // flight at once; then per-cluster sums in row order and a reduction of best / second best
 // (lowest cluster on ties).  For linear / RBF the listed row is staged once in LDS as doubles,
 // zero past d; support rows are read over their padded length DP (the stored row stride) with the
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
         // thread's support row, its coefficient and its cluster's segment bounds and self term are
         // requested together with the listed row's index, before the listed row itself can be read.
         // The sums are those of the general pass below, term for term.
-        if (ns <= kRefineThreads && C <= kRefineThreads) {
+        if (ns <= (int64_t)blockDim.x && C <= (int)blockDim.x) {
             if ((int)blockIdx.x >= count) return;   // (uniform over the block)
             const bool has = t < ns;
             const int64_t ls = min<int64_t>(t, max<int64_t>(ns - 1, 0));
@@ -518,11 +519,11 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
         if constexpr (DP > 0) {
             if (t < DP) xs[t] = t < a.q.d ? (double)xr[t] : 0.0;
         }
-        for (int j = t; j < C; j += kRefineThreads) facc[j] = 0.0;
+        for (int j = t; j < C; j += blockDim.x) facc[j] = 0.0;
         for (int64_t base = 0; base < ns; base += kRefineChunk) {
             const int lim = (int)min<int64_t>(kRefineChunk, ns - base);
             __syncthreads();
-            for (int l = t; l < lim; l += kRefineThreads) {
+            for (int l = t; l < lim; l += blockDim.x) {
                 const TI* s = rows + (base + l) * a.sup.dpad;
                 const double cf = a.sup.coef64[base + l];   // loaded with the row
                 double v;
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
                 Kv[l] = cf * v;
             }
             __syncthreads();
-            for (int j = t; j < C; j += kRefineThreads) {
+            for (int j = t; j < C; j += blockDim.x) {
                 const int64_t lo = max<int64_t>(off[j], base), hi = min<int64_t>(off[j + 1], base + lim);
                 double sj = facc[j];
 #pragma unroll 8
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
         const double kqq = kself64(a.ks, xr);
         double b1 = kInf, b2 = kInf;
         int i1 = C;
-        for (int j = t; j < C; j += kRefineThreads) {
+        for (int j = t; j < C; j += blockDim.x) {
             const double g = a.sup.self[j];
             const double D = (off[j + 1] > off[j] && g < kInf) ? kqq - 2.0 * facc[j] + g : kInf;
             if (D < b1) { b2 = b1; b1 = D; i1 = j; }
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(kRefineThreads) void refine_block_kernel(DistArgs a
         if (t == 0) {
             double v1 = rb1[0], v2 = rb2[0];
             int j1 = ri1[0];
-            for (int w = 1; w < NW; ++w) merge(v1, v2, j1, rb1[w], rb2[w], ri1[w]);
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) merge(v1, v2, j1, rb1[w], rb2[w], ri1[w]);
             a.labels[q] = j1 < C ? j1 : 0;
             if (a.best) a.best[q] = v1;
             if (a.gap) {
@@ -712,15 +713,19 @@ kkm_status launch_refine(const DistArgs& a, const DeviceInfo& dev, hipStream_t s
     const bool per_block = n_support > 256;   // large supports: a whole block per listed row
     const size_t lds = per_block ? sizeof(double) * (kRefineChunk + (size_t)a.sup.C)
                                  : sizeof(double) * 4 * (256 + (size_t)a.sup.C);
-    // (the listed rows are usually few: one workgroup per CU, each taking rows in turn)
-    const unsigned blocks = per_block ? (unsigned)std::min<int64_t>(a.q.n, (int64_t)dev.num_cus)
+    // (the listed rows are usually few: one workgroup per CU, each taking rows in turn; supports and
+    // cluster counts up to 512 take half-size workgroups, two per CU, so that twice the rows run at
+    // once; workgroups without a row leave at once)
+    const bool half = per_block && n_support <= kRefineThreads / 2 && a.sup.C <= kRefineThreads / 2;
+    const unsigned threads = half ? kRefineThreads / 2 : kRefineThreads;
+    const unsigned blocks = per_block ? (unsigned)std::min<int64_t>(a.q.n, (half ? 2 : 1) * (int64_t)dev.num_cus)
                                       : (unsigned)std::min<int64_t>((a.q.n + 3) / 4, 2 * (int64_t)dev.num_cus);
     return dispatch_dp(eval_dp(a.ks.type, a.ks.d), [&]<int DP>() -> kkm_status {
         if (per_block) {
             if (a.dtype == KKM_F64)
-                hipLaunchKernelGGL((refine_block_kernel<double, DP>), dim3(blocks), dim3(kRefineThreads), lds, s, a);
+                hipLaunchKernelGGL((refine_block_kernel<double, DP>), dim3(blocks), dim3(threads), lds, s, a);
             else
-                hipLaunchKernelGGL((refine_block_kernel<float, DP>), dim3(blocks), dim3(kRefineThreads), lds, s, a);
+                hipLaunchKernelGGL((refine_block_kernel<float, DP>), dim3(blocks), dim3(threads), lds, s, a);
         } else {
             if (a.dtype == KKM_F64)
                 hipLaunchKernelGGL((refine_kernel<double, DP>), dim3(blocks), dim3(256), lds, s, a);
