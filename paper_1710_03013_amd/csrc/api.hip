@@ -683,6 +683,7 @@ kkm_status fit_enqueue(const FitPlan& P, FitWs& w, const void* X, hipStream_t s,
         la.ldk = landmark_ldk(ell);
         la.Kmed = w.Kmed;
         la.lab = w.lab;
+        la.init_parts = landmark_init_parts(la);
         la.nlab_x = w.nlab_x;
         la.sx = w.sx;
         la.partial = w.partial;

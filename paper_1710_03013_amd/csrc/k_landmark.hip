@@ -4,8 +4,9 @@
 //      K(x_l, m_j) for the global medoids (landmark_k_kernel, 32 x 32 tiles; RMSD frames:
 //      landmark_block_kernel, 32 x 32 tiles);
 //   2. the initial landmark labels: given, or the nearest global medoid (Eq. 8, with K(m,m)) --
-//      taken by landmark_k_kernel itself when the medoid columns fit one tile, else by
-//      landmark_init_from_k_kernel (one wavefront per landmark; RMSD: landmark_init_kernel);
+//      taken by landmark_k_kernel itself when the medoid columns fit one tile; else each medoid
+//      tile leaves the minimum over its columns per row, and the loop kernel combines them (RMSD:
+//      landmark_init_kernel);
 //   3. one kernel for the landmark loop, all workgroups resident (Eq. 14-17 restricted to the
 //      landmarks):
 //        counting sort of the landmarks by label  -> CSR segments L_j, c_j = |L_j|
@@ -428,6 +429,7 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
     const int mc0 = (ell + T - 1) / T * T;
     const int ncol = a.init_mode ? mc0 + C : ell;
     const bool init_here = a.init_mode && C <= T;
+    const int parts = a.init_parts;   // > 0: this tile's minimum per row, combined by the loop kernel
     const int r0 = blockIdx.y * T, c0 = blockIdx.x * T;
     if (blockIdx.x == 0 && blockIdx.y == 0) reset_batch_state(a);
     if (blockIdx.x == 0 && !a.init_mode)   // given initial labels
@@ -537,8 +539,10 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
                 }
         }
     }
-    if (init_here && c0 == mc0) {
-        // Eq. 8 for rows r0 + ty + 16 i: the 16 lanes of a row (tx) hold its medoid columns
+    if ((init_here && c0 == mc0) || (parts > 0 && c0 >= mc0)) {
+        // Eq. 8 for rows r0 + ty + 16 i over the tile's medoid columns (all of them when they fit
+        // one tile): the 16 lanes of a row (tx) hold them; the lowest cluster among equal minima
+        const int mb = c0 - mc0;   // the tile's first medoid
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
             const int r = r0 + ty + 16 * i;
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
             int bj = C;
 #pragma unroll
             for (int j = 0; j < NI; ++j) {
-                const int m = tx + 16 * j;
+                const int m = mb + tx + 16 * j;
                 if (m < C) {
                     const double ms = a.Mself[m];
                     if (ms < kInf) {
@@ -563,7 +567,15 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
                 const int j2 = __shfl_xor(bj, o, 64);
                 if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
             }
-            if (tx == 0 && r < ell) a.lab[r] = bj < C ? bj : 0;
+            if (tx == 0 && r < ell) {
+                if (parts > 0) {
+                    double* pp = a.Kmed + ((int64_t)r * parts + mb / T) * 2;
+                    pp[0] = bv;
+                    pp[1] = (double)bj;   // (C when the tile has no medoid set)
+                } else {
+                    a.lab[r] = bj < C ? bj : 0;
+                }
+            }
         }
         return;
     }
@@ -574,39 +586,9 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
             const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
             if (r < ell && c < ncol) {
                 const double v = lin ? acc[i][j] : ::exp(-acc[i][j] * a.inv2s2);
-                if (c < ell) a.Kbuf[(int64_t)r * a.ldk + c] = v;
-                else if (c >= mc0) a.Kmed[(int64_t)r * C + (c - mc0)] = v;   // (columns in between: none)
+                if (c < ell) a.Kbuf[(int64_t)r * a.ldk + c] = v;   // (medoid columns: taken above)
             }
         }
-}
-
-// 2'. Initial labels from K(x_l, m_j) (Eq. 8): one wavefront per landmark, lowest j among equal
-//     minima over the clusters that have a medoid (0 when none has); or the given labels.
-__global__ __launch_bounds__(256) void landmark_init_from_k_kernel(LandmarkArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (l >= a.ell) return;   // uniform over the wavefront
-    const int C = a.C;
-    if (a.init_mode == 0) {
-        if (lane == 0) a.lab[l] = a.lab_init[l];
-        return;
-    }
-    const double kxx = a.Kbuf[(int64_t)l * a.ldk + l];
-    double bv = kInf;
-    int bj = C;
-    for (int j = lane; j < C; j += 64) {
-        const double ms = a.Mself[j];
-        if (!(ms < kInf)) continue;
-        const double v = kxx - 2.0 * a.Kmed[(int64_t)l * C + j] + ms;
-        if (bj == C || v < bv) { bv = v; bj = j; }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const double v2 = __shfl_xor(bv, o, 64);
-        const int j2 = __shfl_xor(bj, o, 64);
-        if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) { bv = v2; bj = j2; }
-    }
-    if (lane == 0) a.lab[l] = bj < C ? bj : 0;
 }
 
 // 3-4. The landmark loop and the centroid support (grid <= device CUs, all workgroups resident).
@@ -656,7 +638,24 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
         if (i < n2) kv[u] = ksrc[i];
     }
     for (int m = tid; m < ell; m += nt) {
-        L.lbl[m] = a.lab[m];
+        int lb;
+        if (a.init_parts > 0) {   // Eq. 8: the medoid tiles' minima in tile (= cluster) order
+            const double* pp = a.Kmed + (int64_t)m * a.init_parts * 2;
+            double bv = kInf;
+            int bj = C;
+            for (int p = 0; p < a.init_parts; ++p) {
+                const double v2 = pp[2 * p];
+                const int j2 = (int)pp[2 * p + 1];
+                if (j2 < C && (bj == C || v2 < bv || (v2 == bv && j2 < bj))) {
+                    bv = v2;
+                    bj = j2;
+                }
+            }
+            lb = bj < C ? bj : 0;
+        } else {
+            lb = a.lab[m];
+        }
+        L.lbl[m] = lb;
         L.lmv[m] = a.lm[m];
     }
     for (int r = tid; r < nr; r += nt) L.kself[r] = a.Kbuf[(int64_t)(r0 + r) * ldk + r0 + r];
@@ -1161,6 +1160,13 @@ static kkm_status check_landmark_args(const LandmarkArgs& args, const DeviceInfo
     return KKM_OK;
 }
 
+int landmark_init_parts(const LandmarkArgs& a) {
+    const int dp = eval_dp(a.ktype, a.d);
+    if (dp == 0 || !a.init_mode) return 0;   // (RMSD: landmark_init_kernel; given labels)
+    const int T = dp >= 8 ? 32 : 64;         // the block kernel's tile (launch_landmark_block)
+    return a.C > T ? (a.C + T - 1) / T : 0;
+}
+
 kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const DeviceInfo& dev, hipStream_t stream) {
     size_t lds = 0;
     KKM_TRY(check_landmark_args(args, dev, &lds));
@@ -1182,10 +1188,9 @@ kkm_status launch_landmark_block(const LandmarkArgs& args, int dtype, const Devi
                 if (lin) hipLaunchKernelGGL((landmark_k_kernel<float, DP, true, T>), kgrid, dim3(256), 0, stream, args);
                 else hipLaunchKernelGGL((landmark_k_kernel<float, DP, false, T>), kgrid, dim3(256), 0, stream, args);
             }
-            KKM_HIP(hipGetLastError());
-            // the block kernel took the initial labels itself unless the medoids span several tiles
-            if (args.init_mode && args.C > T)
-                hipLaunchKernelGGL(landmark_init_from_k_kernel, dim3((unsigned)((args.ell + 3) / 4)), dim3(256), 0, stream, args);
+            // (the block kernel takes the initial labels itself, or leaves per-tile minima for the loop)
+            if (args.init_mode && args.C > T && args.init_parts != (args.C + T - 1) / T)
+                return fail(KKM_ERR_INTERNAL, "Eq. 8 tile minima: init_parts does not match the tiles");
         } else {
             const int tiles = (args.ell + 31) / 32;
             const dim3 bgrid((unsigned)tiles, (unsigned)tiles);

@@ -23,13 +23,16 @@ struct LandmarkArgs {
     int32_t ktype, n_atoms;
     double inv2s2;
     int32_t init_mode;      // 0: lab_init, 1: nearest valid global medoid (Eq. 8)
+    int32_t init_parts;     // > 0: Eq. 8 minima of the medoid column tiles, (value, cluster) pairs as
+                            // doubles in Kmed ([ell][init_parts][2]), combined by the loop kernel;
+                            // 0: the initial labels are in lab (landmark_init_parts sets it)
     const int32_t* lab_init;// [ell]
     const void* M;          // [C][Mpad] global medoid rows (dtype of the fit)
     int64_t Mpad;
     const double* Mself;    // [C] K(m,m), +inf where the medoid is unset
     double* Kbuf;           // [ell][ldk] scratch: K_LL
     int64_t ldk;            // row stride of Kbuf (ell rounded up to even)
-    double* Kmed;           // [ell][C] scratch: K(x_l, m_j) for the Eq. 8 initialisation
+    double* Kmed;           // [ell][C] scratch: the Eq. 8 minima of the medoid tiles (init_parts)
     int32_t* lab;           // [2][ell] scratch: initial labels, then final labels
     int32_t* nlab_x;        // [2][ell] scratch: labels after an update, exchanged between workgroups
                             // (two halves used by alternate updates)
@@ -74,6 +77,8 @@ size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds);
 inline int64_t landmark_ldk(int64_t ell) { return (ell + 15) & ~int64_t(15); }
 // K_LL (+ K(x_l, m_j)) and the initial landmark labels; then the landmark loop and the support.
 kkm_status launch_landmark_block(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
+// The init_parts value for these arguments (the medoid column tiles of the landmark block kernel).
+int landmark_init_parts(const LandmarkArgs& a);
 kkm_status launch_landmark_loop(const LandmarkArgs& a, int dtype, const DeviceInfo& dev, hipStream_t s);
 
 // ---------------------------------------------------------------- sparse-centroid distances (k_dist.hip)
