@@ -505,9 +505,22 @@ __global__ __launch_bounds__(256) void medoid_candidates_multi_kernel(SelectArgs
         double v[JPB];
 #pragma unroll
         for (int jj = 0; jj < JPB; ++jj) v[jj] = kInf;
-        for (int64_t b = threadIdx.x; b < a.colpart_blocks; b += blockDim.x)
+        // two strides of partials at a time, their loads issued together (index clamped, value
+        // masked; the minimum is exact in any order)
+        for (int64_t b0 = threadIdx.x; b0 < a.colpart_blocks; b0 += 2 * (int64_t)blockDim.x) {
+            double c[2][JPB];
 #pragma unroll
-            for (int jj = 0; jj < JPB; ++jj) v[jj] = fmin(v[jj], a.colpart[(int64_t)min(jb + jj, a.C - 1) * a.colpart_ld + b]);
+            for (int u = 0; u < 2; ++u) {
+                const int64_t b = min<int64_t>(b0 + u * (int64_t)blockDim.x, a.colpart_blocks - 1);
+#pragma unroll
+                for (int jj = 0; jj < JPB; ++jj) c[u][jj] = a.colpart[(int64_t)min(jb + jj, a.C - 1) * a.colpart_ld + b];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (b0 + u * (int64_t)blockDim.x < a.colpart_blocks)
+#pragma unroll
+                    for (int jj = 0; jj < JPB; ++jj) v[jj] = fmin(v[jj], c[u][jj]);
+        }
 #pragma unroll
         for (int jj = 0; jj < JPB; ++jj) {
 #pragma unroll
@@ -1145,15 +1158,37 @@ template <typename TI>
 __global__ __launch_bounds__(64) void merge_final_kernel(SelectArgs a) {
     const int j = blockIdx.x, lane = threadIdx.x;
     if (j == 0 && lane == 0 && a.cand_total) *a.cand_total += *a.cand_count;
+    // the chunk partials, eight per lane at a time, every index and value requested before any is
+    // used -- the first eight together with the cluster's counts (clamped, masked by selects: an
+    // absent partial is (+inf, INT64_MAX), which never wins)
+    constexpr int PU = 8;
+    int32_t ii[PU];
+    double vv[PU];
+    auto load8 = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const int64_t at = (int64_t)j * a.mchunk + min(c0 + 64 * u, a.mchunk - 1);
+            ii[u] = a.gpart_i[at];
+            vv[u] = a.gpart_v[at];
+        }
+    };
     const int32_t mem = a.counts[j], med = a.bmed[j];
-    const double alpha = merge_alpha(mem, a.wcount[j]);
+    const int64_t wc = a.wcount[j];
+    load8(lane);
+    // (all of them issued here, before any is waited for, rather than the partials after the test)
+#pragma unroll
+    for (int u = 0; u < PU; ++u) asm volatile("" :: "v"(ii[u]), "v"(vv[u]), "v"(mem), "v"(med), "v"(wc));
+    const double alpha = merge_alpha(mem, wc);
     if (alpha > 0.0 && med >= 0) {
         double bv = kInf;
         int64_t bi = INT64_MAX;
-        for (int c = lane; c < a.mchunk; c += 64) {   // (index and value loaded together)
-            const int32_t i = a.gpart_i[(int64_t)j * a.mchunk + c];
-            const double v = a.gpart_v[(int64_t)j * a.mchunk + c];
-            if (i >= 0) vmin(bv, bi, v, i);
+        for (int c0 = lane; c0 < a.mchunk; c0 += 64 * PU) {
+            if (c0 != lane) load8(c0);
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const bool ok = c0 + 64 * u < a.mchunk && ii[u] >= 0;
+                vmin(bv, bi, ok ? vv[u] : kInf, ok ? (int64_t)ii[u] : INT64_MAX);
+            }
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
