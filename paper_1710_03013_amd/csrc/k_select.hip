@@ -668,50 +668,56 @@ __device__ void merge_settle(const SelectArgs& a, int j0, bool record, unsigned 
         cmem[threadIdx.x] = 0;
     }
     // member counts: the 16 threads of cluster jj = t / 16 sum its chunk partials k = t % 16, t % 16
-    // + 16, ... (integers: exact in any order), then across the 16 threads.  The first four
-    // partials of each thread are requested before the candidate count, so that the reads overlap.
+    // + 16, ... (integers: exact in any order), then across the 16 threads.  The first eight
+    // partials of each thread and the thread's own entry of the candidate list are requested before
+    // the candidate count is known (the entry is masked by the count afterwards), so that the reads
+    // overlap; the entry stays in registers for the second pass.
     static_assert(kMergeTJ * 16 == 256, "16 threads per cluster");
+    constexpr int MU = 8;
     const int mjj = (int)threadIdx.x >> 4, msub = (int)threadIdx.x & 15;
     const bool mon = j0 + mjj < a.C;
     const int32_t* mp = a.mpart_c + (int64_t)min(j0 + mjj, a.C - 1) * a.nchunk;
-    int32_t msum = 0;
-    {
-        int32_t c[4];
+    int32_t cpart[MU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = mp[min(msub + 16 * u, a.nchunk - 1)];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) msum += (mon && msub + 16 * u < a.nchunk) ? c[u] : 0;
-    }
+    for (int u = 0; u < MU; ++u) cpart[u] = mp[min(msub + 16 * u, a.nchunk - 1)];
+    const int i0 = threadIdx.x, ic = min(i0, a.cand_cap - 1);
+    const int32_t cj0 = a.cand_j[ic], cq0 = a.cand_q[ic];
+    const double cv0 = a.cand_v[ic];
+    const int64_t wc0 = a.wcount[min(j0 + (int)threadIdx.x, a.C - 1)];   // (|w_j| of thread t < 16's cluster)
     __syncthreads();
     const int count = min(*a.cand_count, a.cand_cap);
-    for (int i = threadIdx.x; i < count; i += blockDim.x) {
-        const int jj = a.cand_j[i] - j0;
-        const double v = a.cand_v[i];
+    auto note_min = [&](int32_t cj, double v) {
+        const int jj = cj - j0;
         if (jj >= 0 && jj < kMergeTJ && !isnan(v)) atomicMin(&cmin[jj], ord_enc(v + 0.0));   // -0 counts as +0
-    }
-    for (int k0 = msub + 64; k0 < a.nchunk; k0 += 64) {
-        int32_t c[4];
+    };
+    if (i0 < count) note_min(cj0, cv0);
+    for (int i = i0 + (int)blockDim.x; i < count; i += blockDim.x) note_min(a.cand_j[i], a.cand_v[i]);
+    int32_t msum = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = mp[min(k0 + 16 * u, a.nchunk - 1)];
+    for (int u = 0; u < MU; ++u) msum += (mon && msub + 16 * u < a.nchunk) ? cpart[u] : 0;
+    for (int k0 = msub + 16 * MU; k0 < a.nchunk; k0 += 16 * MU) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) msum += (mon && k0 + 16 * u < a.nchunk) ? c[u] : 0;
+        for (int u = 0; u < MU; ++u) cpart[u] = mp[min(k0 + 16 * u, a.nchunk - 1)];
+#pragma unroll
+        for (int u = 0; u < MU; ++u) msum += (mon && k0 + 16 * u < a.nchunk) ? cpart[u] : 0;
     }
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) msum += __shfl_xor(msum, o, 64);
     if (msub == 0) cmem[mjj] = msum;
     __syncthreads();
-    for (int i = threadIdx.x; i < count; i += blockDim.x) {
-        const int jj = a.cand_j[i] - j0;
-        const double v = a.cand_v[i];
-        if (jj >= 0 && jj < kMergeTJ && !isnan(v) && ord_enc(v + 0.0) == cmin[jj]) atomicMin(&cpos[jj], a.cand_q[i]);
-    }
+    auto note_pos = [&](int32_t cj, double v, int32_t q) {
+        const int jj = cj - j0;
+        if (jj >= 0 && jj < kMergeTJ && !isnan(v) && ord_enc(v + 0.0) == cmin[jj]) atomicMin(&cpos[jj], q);
+    };
+    if (i0 < count) note_pos(cj0, cv0, cq0);
+    for (int i = i0 + (int)blockDim.x; i < count; i += blockDim.x) note_pos(a.cand_j[i], a.cand_v[i], a.cand_q[i]);
     __syncthreads();
     if (threadIdx.x < kMergeTJ && j0 + (int)threadIdx.x < a.C) {
         const int j = j0 + threadIdx.x;
         const int32_t mem = cmem[threadIdx.x];
         // no candidate only when every distance is +inf or NaN (non-finite input, reported separately)
         const int32_t med = mem == 0 ? -1 : (cpos[threadIdx.x] == INT32_MAX ? 0 : cpos[threadIdx.x]);
-        const double alpha = merge_alpha(mem, a.wcount[j]);
+        const double alpha = merge_alpha(mem, wc0);
         const bool on = alpha > 0.0 && med >= 0;
         cmed[threadIdx.x] = med;
         calpha[threadIdx.x] = on ? alpha : 0.0;
