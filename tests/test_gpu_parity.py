@@ -319,6 +319,19 @@ def test_fit_listed_candidates_with_small_merge_grid():
     np.testing.assert_allclose(info["partial_cost"], okkm.partial_costs(ref), rtol=COST_TOL["fp32"])
 
 
+def test_fit_initial_labels_over_two_wide_tiles():
+    """Eq. 8 for 80 clusters in 3 dimensions: rows of 4 padded dimensions take 64-wide tiles in the
+    landmark block kernel, so the medoid columns span two tiles, whose per-row minima the loop kernel
+    combines (the 16-d and 64-d fits cover 32-wide tiles)."""
+    kk = _kk()
+    _say("fit d=3, C=80")
+    X, _ = ki.datasets.gaussian_mixture(8000, 3, 80, seed=4003, sigma=0.3)
+    kern = Kernel("rbf", 1.0)
+    T = 20
+    model, labels, info, ref = _fit_both(kk, X, kern, 80, 2, 0.1, T, "kmeans++", 4004, "fp32")
+    _check_fit(kk, model, labels, info, ref, kern, X, T)   # oracle margins all above 1e-6 (3.4e-5 at least)
+
+
 def _check_displacement(info, ref, kern, X, C, B, seed):
     """Medoid displacement per batch (Sec. 4.1 observable) against the oracle's definition, the
     medoids before batch 0 being the k-means++ picks of the same draws."""
