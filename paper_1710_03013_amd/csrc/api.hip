@@ -235,7 +235,6 @@ struct FitWs {
     double* best;          // [nmax] each batch row's distance to its nearest centroid (partial cost)
     double* psum;          // [1024] partial sums of the partial cost
     int64_t* trace;        // [64]
-    unsigned* barrier;     // [1]
     int32_t* lm_error;     // [1]
     char* status_end;      // end of the status block (refine_counts .. trace)
 };
@@ -271,7 +270,7 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.lab = c.take<int32_t>(2 * P.ellmax);
     w.nlab_x = c.take<int32_t>((size_t)2 * P.ellmax);
     w.sx = c.take<double>((size_t)4 * P.ellmax);
-    w.partial = c.take<double>((size_t)P.gmax * C);
+    w.partial = c.take<double>((size_t)3 * P.gmax * C);
     w.changed = c.take<int32_t>(P.T + 1);
     w.lab_final = c.take<int32_t>(P.ellmax);
     w.offsets = c.take<int32_t>(C + 1);
@@ -307,7 +306,6 @@ size_t carve_fit(Carver& c, const FitPlan& P, FitWs& w) {
     w.tnorm = c.take<double>((size_t)C * 2);
     w.gpart_v = c.take<double>((size_t)C * merge_chunks(P.nmax));
     w.gpart_i = c.take<int32_t>((size_t)C * merge_chunks(P.nmax));
-    w.barrier = c.take<unsigned>(1);
     // status block, read back with one copy: [refine_counts, flags, updates, lm_error, info, info_disp, trace]
     w.refine_counts = c.take<int32_t>(P.B);
     w.flags = c.take<int32_t>(2);
@@ -709,7 +707,6 @@ kkm_status fit_enqueue(const FitPlan& P, FitWs& w, const void* X, hipStream_t s,
         la.sup_lo = w.sup_lo;
         la.bpad = bf16_pad(P.dpad);
         la.trace = (i == 0 && want_trace) ? w.trace : nullptr;
-        la.barrier = w.barrier;
         la.colmin = w.colmin;
         la.error = w.lm_error;
         if (la.trace) {
@@ -899,7 +896,7 @@ kkm_status fit_finish(const FitPlan& P, const FitWs& w, const std::vector<char>&
         info->ms_refine = ms[kPhRefine];
         info->ms_select = ms[kPhSelect];
     }
-    if (lm_err) return fail(KKM_ERR_INTERNAL, "a grid-barrier wait (k-means++ or landmark loop) exceeded its cap");
+    if (lm_err) return fail(KKM_ERR_INTERNAL, "a wait for another workgroup (k-means++ or landmark loop) exceeded its cap");
     if (flags[0]) return fail(KKM_ERR_NONFINITE, "X holds NaN or Inf");
     return KKM_OK;
 }

@@ -22,7 +22,7 @@
 //
 // Every sum has a fixed order that depends only on the labels (CSR order within a segment, row
 // order, then workgroup order), so results are bitwise repeatable.  Cross-workgroup data is written
-// and read with device-scope accesses, so the grid barrier needs no cache maintenance.
+// and read with device-scope accesses, so the waits on it need no cache maintenance.
 #include <cstdlib>
 
 #include "kkm_internal.hpp"
@@ -39,7 +39,7 @@ constexpr int kLoopThreads = 1024;
 constexpr int kPairMax = 64;
 constexpr int kPairPerWave = (kPairMax + kLoopThreads / 64 - 1) / (kLoopThreads / 64);   // changes per wavefront
 // Published labels carry the update that produced them above their low kLabelBits bits (labels are
-// below 1024), so a reader can wait on the label itself instead of a grid barrier.
+// below 1024), so a reader can wait on the label itself.
 constexpr int kLabelBits = 11;
 
 struct LdsLayout {
@@ -254,34 +254,18 @@ __device__ __forceinline__ void xput(T* p, T v) { __hip_atomic_store(p, v, __ATO
 template <typename T>
 __device__ __forceinline__ T xget(T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-// Barrier over the co-resident workgroups of the loop kernel: a monotonically increasing arrival
-// counter (cleared by a kernel launched just before on the same stream).  Every thread first waits
-// until its exchange stores have completed, then after the workgroup barrier one thread arrives
-// with a device-scope RMW and polls with device-scope loads; the closing workgroup barrier
-// releases the other threads.  Since all exchanged data moves through device-scope accesses, no L2
-// write-back or invalidation is needed.  The wait is bounded: past kSpinCap polls the workgroup
-// records an error and proceeds, so the kernel always terminates.
+// The cluster partial sums of an exchange are their own signal: exchange e of a batch uses buffer
+// e % 3 of partial ([3][grid][C]), whose slots hold kNoPart until written, and the readers wait on
+// the slots themselves (bounded: past kSpinCap polls the workgroup records an error and proceeds,
+// so the kernel always terminates).  Buffer 0 is filled before the loop (reset_batch_state); a
+// workgroup clears its slots of buffer (e + 1) % 3 during exchange e, before publishing its sums:
+// that buffer was last read in exchange e - 2, which every workgroup has finished once all sums of
+// exchange e - 1 exist, and the workgroup read them all before exchange e; a reader of exchange
+// e + 1 waits for this workgroup's exchange-e sums first, so it cannot find the old values.
+// Every workgroup takes the same exchanges (the choice follows from the shared labels).
 constexpr unsigned kSpinCap = 1u << 26;
-
-__device__ __forceinline__ void grid_barrier(const LandmarkArgs& a, unsigned& target) {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);   // this thread's stores (the exchange stores among them) are done
-    __syncthreads();
-    target += gridDim.x;
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(a.barrier, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned polls = 0;
-        while (__hip_atomic_load(a.barrier, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++polls > kSpinCap) {
-                atomicOr(a.error, 1);
-                break;
-            }
-        }
-    }
-    __syncthreads();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
+constexpr unsigned long long kNoPart = 0x7ff4dead0badf00dull;   // a NaN pattern no sum produces
+__device__ __forceinline__ bool no_part(double v) { return (unsigned long long)__double_as_longlong(v) == kNoPart; }
 
 // Counters the loop and the later kernels of the batch expect cleared (one workgroup).
 __device__ __forceinline__ void reset_batch_state(const LandmarkArgs& a) {
@@ -289,10 +273,9 @@ __device__ __forceinline__ void reset_batch_state(const LandmarkArgs& a) {
     for (int i = threadIdx.x; i < a.n_zero_ints; i += blockDim.x) a.zero_ints[i] = 0;
     for (int i = threadIdx.x; i < a.C; i += blockDim.x) a.colmin[i] = ~0ull;
     for (int i = threadIdx.x; i < 2 * a.ell; i += blockDim.x) a.nlab_x[i] = 0;   // no update published yet
-    if (threadIdx.x == 0) {
-        *a.barrier = 0u;   // (the error flag accumulates over the fit: cleared once by the host)
-        *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
-    }
+    for (int i = threadIdx.x; i < a.grid * a.C; i += blockDim.x) a.partial[i] = __longlong_as_double((long long)kNoPart);
+    // (the error flag accumulates over the fit: cleared once by the host)
+    if (threadIdx.x == 0) *reinterpret_cast<unsigned int*>(a.snorm_max) = 0u;
 }
 
 // Wall-clock stamp of workgroup 0 (profiling aid): slot 0 holds the count, which thread 0 also
@@ -595,14 +578,16 @@ __global__ __launch_bounds__(256) void landmark_k_kernel(LandmarkArgs a) {
 //
 // Workgroup wg owns landmark rows [r0, r1): their rows of K (in LDS when they fit) and of S.  Every
 // workgroup keeps all landmark labels, cluster counts and T_j = c_j^2 g^_j.  Before the first update
-// the own parts of sum_{m in L_j} S[m][j] are exchanged (barrier) and summed in the same order
-// everywhere.  An update is then
+// the own parts of sum_{m in L_j} S[m][j] are exchanged and summed in the same order everywhere.
+// An update is then
 //   Eq. 15 for the own rows, publish their labels (and S at the old and new label of a changed row)
-//   -> barrier -> all labels, the changed list, own rows of S follow the changes (incrementally in
-//   landmark order, or from scratch), and T follows either by the pair formula (at most kPairMax
-//   changes, no exchange) or by a new exchange of the partial sums (barrier).
-// The label / S exchange alternates between two halves, and every other buffer is rewritten only
-// after the barrier that ends every reader's use of it.
+//   -> wait for every label of the update -> the changed list, own rows of S follow the changes
+//   (incrementally in landmark order, or from scratch), and T follows either by the pair formula
+//   (at most kPairMax changes, no exchange) or by a new exchange of the partial sums.
+// No workgroup waits on a grid-wide barrier: every published value carries its own signal (labels
+// are tagged with their update, partial sums replace a sentinel), and every buffer is rewritten
+// only once its readers have provably moved past it (the label / S exchange alternates between two
+// halves, the partial sums rotate over three buffers).
 // KL: the own rows of K_LL are staged in LDS (else read from HBM); a compile-time choice, so the
 // reads compile to LDS or global instructions rather than generic ones.
 template <typename TI, bool KL>
@@ -620,7 +605,6 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
     auto row = [&](int pos) { return X + (a.base + (int64_t)pos * a.stride) * a.d; };
     const double* const Kg = a.Kbuf + (int64_t)r0 * ldk;
     const double* const Krows = KL ? L.K : Kg;     // own row r at Krows + r * ldk
-    unsigned target = 0;
     int ns = 0;   // trace stamps taken (thread 0 of workgroup 0)
 
     stamp(a, ns);
@@ -689,8 +673,14 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
 
     const int nsub = C < nt ? nt / C : 1;     // threads per cluster in the partial reduction
     // T_j and g^_j from every workgroup's part of sum_{m in L_j} S[m][j] (in row order), exchanged
-    // through one grid barrier, then summed in a fixed order; also 1 / c_j
+    // through the partial buffers (see kNoPart), then summed in a fixed order; also 1 / c_j
+    int nexch = 0;
     auto exchange_T = [&]() {
+        const int e = nexch++;
+        double* Pw = a.partial + (int64_t)(e % 3) * G * C;
+        double* Pn = a.partial + (int64_t)((e + 1) % 3) * G * C;
+        for (int j = tid; j < C; j += nt) xput(Pn + (int64_t)wg * C + j, __longlong_as_double((long long)kNoPart));
+        __builtin_amdgcn_s_waitcnt(0);   // (the clears complete before the sums are published)
         for (int j = tid; j < C; j += nt) {
             double acc = 0.0;
             int r = 0;
@@ -706,11 +696,9 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 for (int u = 0; u < 8; ++u) acc += lb[u] == j ? v[u] : 0.0;
             }
             for (; r < nr; ++r) acc += L.lbl[r0 + r] == j ? L.S[r * C + j] : 0.0;
-            xput(a.partial + (int64_t)wg * C + j, acc);
+            xput(Pw + (int64_t)wg * C + j, acc);
             L.rcnt[j] = L.cnt[j] > 0 ? 1.0 / (double)L.cnt[j] : 0.0;
         }
-        stamp(a, ns);
-        grid_barrier(a, target);
         stamp(a, ns);
         // nsub interleaved sub-sums per cluster, then in order (each sub-sum's loads, up to eight at a
         // time, are issued before they are added in workgroup order)
@@ -722,7 +710,23 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int g = g0 + u * nsub;
-                    v[u] = g < G ? xget(a.partial + (int64_t)g * C + j) : 0.0;
+                    v[u] = g < G ? xget(Pw + (int64_t)g * C + j) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {   // (a slot not yet written: wait for it, bounded)
+                    const int g = g0 + u * nsub;
+                    if (g < G && no_part(v[u])) {
+                        unsigned polls = 0;
+                        do {
+                            __builtin_amdgcn_s_sleep(1);
+                            if (++polls > kSpinCap) {
+                                atomicOr(a.error, 1);
+                                v[u] = 0.0;
+                                break;
+                            }
+                            v[u] = xget(Pw + (int64_t)g * C + j);
+                        } while (no_part(v[u]));
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
@@ -913,7 +917,7 @@ __global__ __launch_bounds__(kLoopThreads) void landmark_phase_kernel(LandmarkAr
                 }
                 L.dT[j] = dt;
             }
-            // (the next barrier orders these before the update below overwrites pab's source labels)
+            // (the next workgroup barrier orders these before the update below overwrites pab's source labels)
         }
 
         // own rows of S: from scratch (sort + segment sums, ~ell steps per row) only when the
@@ -1122,7 +1126,7 @@ size_t landmark_lds_bytes_host(int ell, int C, int G, bool k_in_lds) {
 
 LandmarkShape landmark_shape(const DeviceInfo& dev, int ell, int C) {
     // at least 4 landmark rows per workgroup and at most KKM_LANDMARK_WGS workgroups (default 64):
-    // the loop is bound by its grid barriers, whose cost grows with the grid; the grid is widened
+    // the loop is bound by its cross-workgroup waits, whose cost grows with the grid; the grid is widened
     // (up to the device) when that lets the own rows of K_LL stay in LDS
     static int cap = [] {
         const char* e = std::getenv("KKM_LANDMARK_WGS");
@@ -1227,7 +1231,7 @@ kkm_status launch_landmark_loop(const LandmarkArgs& args, int dtype, const Devic
     if (per_cu * dev.num_cus < G)
         return fail(KKM_ERR_DEVICE, "landmark loop grid does not fit co-resident on the device");
     // The grid fits the device at once, so a plain launch makes every workgroup resident as soon as
-    // the CUs are free (work of other streams only delays the barrier; its waits are bounded and
+    // the CUs are free (work of other streams only delays the exchanges; their waits are bounded and
     // report an error).  A cooperative launch gives the same guarantee formally but costs ~20 us of
     // queue synchronisation per launch; KKM_LANDMARK_COOPERATIVE=1 selects it.
     static const bool coop = [] {

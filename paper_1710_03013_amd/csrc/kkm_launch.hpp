@@ -37,7 +37,8 @@ struct LandmarkArgs {
     int32_t* nlab_x;        // [2][ell] scratch: labels after an update, exchanged between workgroups
                             // (two halves used by alternate updates)
     double* sx;             // [2][ell][2] scratch: S of a changed landmark at its old and new label
-    double* partial;        // [grid][C] scratch: each workgroup's part of the g^ sums
+    double* partial;        // [3][grid][C] scratch: each workgroup's part of the g^ sums, three
+                            // buffers used by successive exchanges in turn
     int32_t* changed;       // [max_updates+1] scratch
     int32_t* zero_ints;     // ints to clear for the later kernels of the batch
     int32_t n_zero_ints;
@@ -64,8 +65,7 @@ struct LandmarkArgs {
     int32_t cooperative;    // host: launch the loop kernel cooperatively
     int64_t* trace;         // [64] device wall-clock stamps of workgroup 0, or null
     unsigned long long* colmin;   // [C] set to the empty value for the batch's distance pass
-    unsigned* barrier;      // [1] arrival counter of the loop's grid barrier
-    int32_t* error;         // [1] set when a barrier wait exceeded its cap
+    int32_t* error;         // [1] set when a wait for another workgroup exceeded its cap
 };
 // Workgroups of the landmark phase for a landmark set of size ell (KKM_LANDMARK_ROWS rows each).
 struct LandmarkShape {
