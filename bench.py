@@ -51,7 +51,7 @@ PEAK_BF16_MATRIX = 2.5e15     # published MI355X dense BF16 matrix-core FLOP/s
 # and its SHA-1 prefix at measurement time: a changed kernel source reports null.
 TRAFFIC_MEASURED = {
     ("mfma_dist_kernel", "mixture64"): (16.41e6, "k_mfma.hip", "8b69f3b831be"),
-    ("landmark_phase_kernel", "mixture64"): (3.17e6, "k_landmark.hip", "79969c7d4c26"),
+    ("landmark_phase_kernel", "mixture64"): (3.62e6, "k_landmark.hip", "15eb76f94bb8"),
     ("mfma_assign1_kernel", "mixture64"): (260.35e6, "k_mfma.hip", "8b69f3b831be"),
     ("rmsd_pairs_kernel+mfma_dist_kernel", "md"): (104.67e6, "k_mfma.hip", "8b69f3b831be"),
     ("rmsd_pairs_kernel+mfma_assign1_kernel", "md"): (231.15e6, "k_mfma.hip", "8b69f3b831be"),
