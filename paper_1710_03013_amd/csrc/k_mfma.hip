@@ -341,7 +341,7 @@ void mfma_dist_kernel(DistArgs a) {
     __shared__ double Bw1[4][32], Bw2[4][32];
     __shared__ int Iw[4][32];
     __shared__ float Es[32];
-    __shared__ float Pt[NW][32 * 33];
+    __shared__ float Pt[NW][36 * 33];
     __shared__ int jb[5];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = lane >> 5, col = lane & 31;
@@ -393,7 +393,7 @@ void mfma_dist_kernel(DistArgs a) {
     const int j0 = jb[quarter], j1 = jb[quarter + 1];
     const int start = off[j0], end = off[j1];
     float* Dw = Dl + (size_t)half * C * 32;     // this wavefront's per-cluster sums
-    float* P = Pt[wave];                         // [32 rows][33]: one tile of a_l K(x, s_l)
+    float* P = Pt[wave];                         // [36 rows][33]: one tile of a_l K(x, s_l), 4 rows of slack
     for (int p = lane; p < (j1 - j0) * 32; p += 64) Dw[j0 * 32 + p] = 0.0f;
     // the wavefront's tiles: all of the quarter's, or the first (half 0) or second half of them
     const int t0 = start & ~31;
@@ -471,10 +471,13 @@ void mfma_dist_kernel(DistArgs a) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) P[(8 * b + 4 * h + c) * 33 + col] = v[4 * b + c];
             wave_sync_lds();
+            // (r <= r0 + 31, so the four rows read lie within the buffer's 36; rows at or past hi,
+            // the slack rows among them, are read but replaced by zeros)
             auto rows4 = [&](int r, int hi, float part) {
+                const float* pr = P + (r - r0) * 33 + col;
                 float x[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) x[e] = P[(max(min(r + e, hi - 1), r0) - r0) * 33 + col];
+                for (int e = 0; e < 4; ++e) x[e] = pr[e * 33];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) part += r + e < hi ? x[e] : 0.0f;
                 return part;
@@ -821,7 +824,7 @@ size_t mfma_lds_dynamic(size_t C, int nw) {
     return sizeof(float) * (size_t)(nw / 4) * C * 32 + sizeof(double) * 2 * C + sizeof(int32_t) * (C + 1);
 }
 size_t mfma_lds_static(int nw) {
-    return sizeof(float) * ((size_t)nw * 32 * 33 + 4 * 32 * 2 + 32) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 +
+    return sizeof(float) * ((size_t)nw * 36 * 33 + 4 * 32 * 2 + 32) + sizeof(double) * 4 * 32 * 2 + sizeof(int) * 4 * 32 +
            64;
 }
 
