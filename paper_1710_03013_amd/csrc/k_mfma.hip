@@ -334,8 +334,8 @@ void mfma_dist_kernel(DistArgs a) {
     float* Dl = reinterpret_cast<float*>(smem_raw);   // [NH][C][32]; copy 0 ends up holding D
     // segment metadata of the support, read once per workgroup: offsets, self terms, |a| sums
     double* mself = reinterpret_cast<double*>(smem_raw + sizeof(float) * (size_t)NH * C * 32);   // [C]
-    double* msegabs = mself + C;                                                             // [C]
-    int32_t* off = reinterpret_cast<int32_t*>(msegabs + C);                                 // [C+1]
+    float2* mseg = reinterpret_cast<float2*>(mself + C);   // [C]: the |a| sum and the summation term
+    int32_t* off = reinterpret_cast<int32_t*>(mseg + C);                                    // [C+1]
     __shared__ float Ew[4][32];
     __shared__ float Eg[4][32];
     __shared__ double Bw1[4][32], Bw2[4][32];
@@ -374,13 +374,17 @@ void mfma_dist_kernel(DistArgs a) {
     }
     if (first) {
         // segment metadata of the support, read once per workgroup while the first group's rows
-        // are in flight: offsets, self terms, |a| sums
+        // are in flight: offsets; per cluster its self term (+inf for an empty segment, which no
+        // row decision counts), its |a| sum and the (length + c) u32 term of its sum's error bound
         if (threadIdx.x < 5) jb[threadIdx.x] = a.sup.split[threadIdx.x];
+        const float lc = !RM && type == KKM_KERNEL_LINEAR ? 2.0f : 8.0f;
         for (int j = threadIdx.x; j <= C; j += blockDim.x) {
-            off[j] = a.sup.offsets[j];
+            const int o = a.sup.offsets[j];
+            off[j] = o;
             if (j < C) {
-                mself[j] = a.sup.self[j];
-                msegabs[j] = a.sup.segabs[j];
+                const int o1 = a.sup.offsets[j + 1];
+                mself[j] = o1 > o ? a.sup.self[j] : kInf;
+                mseg[j] = make_float2((float)a.sup.segabs[j], ((float)(o1 - o) + lc) * kU32);
             }
         }
         snmax = *a.sup.snorm_max;
@@ -561,20 +565,19 @@ void mfma_dist_kernel(DistArgs a) {
             const int jj = jp + h;
             const bool in = jj < j1;
             const int jr = in ? jj : jp;
-            const int lo = off[jr], hi = off[jr + 1];
             const double g = mself[jr];
-            const float segabs = (float)msegabs[jr];
+            const float2 sg = mseg[jr];
+            const float segabs = sg.x, lterm = sg.y;
             float accf = Dl[jr * 32 + col];
             if constexpr (NH > 1) accf += Dl[(size_t)C * 32 + jr * 32 + col];
-            const bool live = in && hi > lo && g < kInf;
+            const bool live = in && g < kInf;
             const double Dc = (double)kqq + g - 2.0 * (double)accf;
-            const float len = (float)(hi - lo);
             float ef;
             if constexpr (LIN) {
-                ef = (dot_rel * kmax + (len + 2.0f) * kU32 * kmax) * segabs;
+                ef = (dot_rel * kmax + lterm * kmax) * segabs;
             } else {
                 const float mass = nonneg ? fabsf(accf) * 1.0001f + 1e-30f : segabs;
-                ef = (rho + (len + 8.0f) * kU32) * mass;
+                ef = (rho + lterm) * mass;
             }
             // (plus the FP64 rounding of D and of the self term, 4 units of 2^-53 of the magnitudes)
             const float eg =
