@@ -51,11 +51,13 @@ constexpr float kUbf3 = 4.6134e-5f;       // BF16x3: 3 u^2 (1 + 2^-7) = 3 * 2^-1
 // precision modes of the pass (kPmRmsd: RMSD frames, FP32 cross-covariance and FP64 eigenvalue)
 constexpr int kPmF32 = 0, kPmBf16 = 1, kPmBf16x3 = 3, kPmRmsd = 4;
 
-__device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float sn, float inv2s2) {
+// (e2s = log2(e) / (2 sigma^2) rounded to float, so the exponent takes one product: its two roundings,
+// the constant's and the product's, are those of d2 / (2 sigma^2) times log2(e))
+__device__ __forceinline__ float rbf_or_dot(int type, float dot, float qn, float sn, float e2s) {
     if (type == KKM_KERNEL_LINEAR) return dot;
     float d2 = qn + sn - 2.0f * dot;
     d2 = d2 > 0.0f ? d2 : 0.0f;
-    return __builtin_amdgcn_exp2f(-d2 * inv2s2 * 1.4426950408889634f);
+    return __builtin_amdgcn_exp2f(-d2 * e2s);
 }
 
 // x.s for the 32 support rows of panel tile `tile` and the wavefront's 32 samples: lane l ends up with
@@ -347,6 +349,7 @@ void mfma_dist_kernel(DistArgs a) {
     const int h = lane >> 5, col = lane & 31;
     const int type = a.ks.type;
     const float inv2s2 = (float)a.ks.inv2s2;
+    const float e2s = inv2s2 * 1.4426950408889634f;   // exponent scale of the tile's kernel values
 
     float snmax = 0.0f;
 
@@ -434,15 +437,15 @@ void mfma_dist_kernel(DistArgs a) {
             const float4 sn4 = *reinterpret_cast<const float4*>(a.sup.snorm32 + rb);
             const float4 cf4 = *reinterpret_cast<const float4*>(a.sup.coef32 + rb);
             if constexpr (RM) {   // acc holds the squared RMSD
-                v[4 * b + 0] = cf4.x * exp_neg(acc[4 * b + 0] * inv2s2);
-                v[4 * b + 1] = cf4.y * exp_neg(acc[4 * b + 1] * inv2s2);
-                v[4 * b + 2] = cf4.z * exp_neg(acc[4 * b + 2] * inv2s2);
-                v[4 * b + 3] = cf4.w * exp_neg(acc[4 * b + 3] * inv2s2);
+                v[4 * b + 0] = cf4.x * __builtin_amdgcn_exp2f(-acc[4 * b + 0] * e2s);
+                v[4 * b + 1] = cf4.y * __builtin_amdgcn_exp2f(-acc[4 * b + 1] * e2s);
+                v[4 * b + 2] = cf4.z * __builtin_amdgcn_exp2f(-acc[4 * b + 2] * e2s);
+                v[4 * b + 3] = cf4.w * __builtin_amdgcn_exp2f(-acc[4 * b + 3] * e2s);
             } else {
-                v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, inv2s2);
-                v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, inv2s2);
-                v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, inv2s2);
-                v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, inv2s2);
+                v[4 * b + 0] = cf4.x * rbf_or_dot(type, acc[4 * b + 0], qn, sn4.x, e2s);
+                v[4 * b + 1] = cf4.y * rbf_or_dot(type, acc[4 * b + 1], qn, sn4.y, e2s);
+                v[4 * b + 2] = cf4.z * rbf_or_dot(type, acc[4 * b + 2], qn, sn4.z, e2s);
+                v[4 * b + 3] = cf4.w * rbf_or_dot(type, acc[4 * b + 3], qn, sn4.w, e2s);
             }
         }
         // (the register path is compiled for short rows only, where it costs no occupancy)
