@@ -50,11 +50,11 @@ PEAK_BF16_MATRIX = 2.5e15     # published MI355X dense BF16 matrix-core FLOP/s
 # calibration: FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), keyed by (kernel, workload), with the source file
 # and its SHA-1 prefix at measurement time: a changed kernel source reports null.
 TRAFFIC_MEASURED = {
-    ("mfma_dist_kernel", "mixture64"): (16.40e6, "k_mfma.hip", "6ddd1a4fdb91"),
+    ("mfma_dist_kernel", "mixture64"): (16.42e6, "k_mfma.hip", "233890992b32"),
     ("landmark_phase_kernel", "mixture64"): (3.63e6, "k_landmark.hip", "15eb76f94bb8"),
-    ("mfma_assign1_kernel", "mixture64"): (260.34e6, "k_mfma.hip", "6ddd1a4fdb91"),
-    ("rmsd_pairs_kernel+mfma_dist_kernel", "md"): (102.45e6, "k_mfma.hip", "6ddd1a4fdb91"),
-    ("rmsd_pairs_kernel+mfma_assign1_kernel", "md"): (231.17e6, "k_mfma.hip", "6ddd1a4fdb91"),
+    ("mfma_assign1_kernel", "mixture64"): (260.34e6, "k_mfma.hip", "233890992b32"),
+    ("rmsd_pairs_kernel+mfma_dist_kernel", "md"): (102.45e6, "k_mfma.hip", "233890992b32"),
+    ("rmsd_pairs_kernel+mfma_assign1_kernel", "md"): (231.14e6, "k_mfma.hip", "233890992b32"),
 }
 
 
